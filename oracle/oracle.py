@@ -1,0 +1,272 @@
+"""ctypes front of the CPU oracle (liboracle.so).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+CPU-baseline leg of the benchmark, never by the product package.
+
+Arrays are numpy float64 patch arrays of shape (nf, nz+6, ny+6, nx+6).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+WAVE, MHD, CCZ4 = 0, 1, 2
+RK4, SSPRK3 = 0, 1
+NFIELDS = {WAVE: 2, MHD: 8, CCZ4: 25}
+
+
+class Params(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in (
+        "sigma", "gamma_ad", "weno_eps", "weno_q", "kappa_z", "kappa_c",
+        "bm_f0", "bm_f1", "gd_g", "gd_eta", "upwind")]
+
+
+def params(**kw) -> Params:
+    d = dict(sigma=0.1, gamma_ad=5.0 / 3.0, weno_eps=-1.0, weno_q=2.0,
+             kappa_z=0.1, kappa_c=0.1, bm_f0=0.0, bm_f1=2.0, gd_g=0.75,
+             gd_eta=2.0, upwind=1.0)
+    d.update(kw)
+    return Params(**d)
+
+
+def build(force: bool = False) -> str:
+    """Compile liboracle.so with the oracle's Makefile (gcc)."""
+    if force or not os.path.exists(_LIB_PATH):
+        subprocess.run(["make", "-B" if force else "-s", "-C", _HERE, "liboracle.so"],
+                       check=True, capture_output=True)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        i = ctypes.c_int
+        d = ctypes.c_double
+        lng = ctypes.c_long
+        P = ctypes.POINTER(Params)
+        vp = ctypes.c_void_p
+        for name in ("orc_d1", "orc_d2"):
+            getattr(L, name).argtypes = [dp, lng, d]
+            getattr(L, name).restype = d
+        L.orc_adv.argtypes = [dp, lng, d, d]
+        L.orc_adv.restype = d
+        L.orc_ko.argtypes = [dp, lng, d, d]
+        L.orc_ko.restype = d
+        L.orc_dmix.argtypes = [dp, lng, d, lng, d]
+        L.orc_dmix.restype = d
+        L.orc_fill_periodic.argtypes = [dp, i, i, i, i]
+        L.orc_rhs.argtypes = [i, dp, dp, i, i, i, dp, P]
+        for name in ("orc_weno5z_left", "orc_weno5z_right"):
+            getattr(L, name).argtypes = [dp, d, d]
+            getattr(L, name).restype = d
+        L.orc_weno5js_left.argtypes = [dp, d]
+        L.orc_weno5js_left.restype = d
+        L.orc_rk_run.argtypes = [i, i, dp, i, i, i, dp, d, i, P]
+        L.orc_rk_scalar.argtypes = [i, d, d, dp, dp]
+        L.orc_dense_rk4.argtypes = [i, i, d]
+        L.orc_dense_rk4.restype = d
+        L.orc_bor_rk4.argtypes = [i, i, i, d, dp, ctypes.POINTER(dp), dp, lng]
+        L.orc_lagrange6.argtypes = [d, dp]
+        L.orc_hier_create.argtypes = [i, i, ctypes.POINTER(i), ctypes.POINTER(i), dp, d,
+                                      ctypes.POINTER(i), ctypes.POINTER(i)]
+        L.orc_hier_create.restype = vp
+        L.orc_hier_destroy.argtypes = [vp]
+        L.orc_hier_set.argtypes = [vp, i, i, dp]
+        L.orc_hier_get.argtypes = [vp, i, i, dp]
+        L.orc_hier_fill_same.argtypes = [vp, i]
+        L.orc_hier_step.argtypes = [vp, d, P]
+        L.orc_hier_set_parent_data.argtypes = [vp, i, i, dp, dp, dp, dp, dp]
+        L.orc_hier_prolong.argtypes = [vp, i, i, i, d]
+        L.orc_hier_restrict.argtypes = [vp, i]
+        L.orc_wave_rhs_adjoint.argtypes = [dp, dp, i, i, i, dp, P]
+        L.orc_fill_periodic_adjoint.argtypes = [dp, i, i, i, i]
+        L.orc_wave_adjoint_run.argtypes = [dp, i, i, i, dp, dp, d, i, d, P]
+        L.orc_sphere_integral.argtypes = [dp, i, i, i, i, dp, dp, d, d]
+        L.orc_sphere_integral.restype = d
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _h3(h):
+    h = np.broadcast_to(np.asarray(h, dtype=np.float64), (3,)).copy()
+    return h
+
+
+def dims(U: np.ndarray):
+    nf, NZ, NY, NX = U.shape
+    return nf, NX - 6, NY - 6, NZ - 6
+
+
+def fill_periodic(U: np.ndarray) -> None:
+    nf, nx, ny, nz = dims(U)
+    lib().orc_fill_periodic(_p(U), nf, nx, ny, nz)
+
+
+def rhs(system: int, U: np.ndarray, h, prm: Params | None = None) -> np.ndarray:
+    prm = prm or params()
+    nf, nx, ny, nz = dims(U)
+    R = np.zeros_like(U)
+    hh = _h3(h)
+    lib().orc_rhs(system, _p(U), _p(R), nx, ny, nz, _p(hh), ctypes.byref(prm))
+    return R
+
+
+def rk_run(system: int, scheme: int, U: np.ndarray, h, dt: float, nsteps: int,
+           prm: Params | None = None) -> None:
+    prm = prm or params()
+    nf, nx, ny, nz = dims(U)
+    hh = _h3(h)
+    lib().orc_rk_run(system, scheme, _p(U), nx, ny, nz, _p(hh), dt, nsteps, ctypes.byref(prm))
+
+
+def rk_scalar(scheme: int, z: complex) -> complex:
+    a = ctypes.c_double()
+    b = ctypes.c_double()
+    lib().orc_rk_scalar(scheme, z.real, z.imag, ctypes.byref(a), ctypes.byref(b))
+    return complex(a.value, b.value)
+
+
+def stencil(name: str, u: np.ndarray, center: int, stride: int, h: float, *extra) -> float:
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    ptr = ctypes.cast(u.ctypes.data + 8 * center, ctypes.POINTER(ctypes.c_double))
+    return getattr(lib(), "orc_" + name)(ptr, stride, h, *extra)
+
+
+def dmix(u: np.ndarray, center: int, sa: int, ha: float, sb: int, hb: float) -> float:
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    ptr = ctypes.cast(u.ctypes.data + 8 * center, ctypes.POINTER(ctypes.c_double))
+    return lib().orc_dmix(ptr, sa, ha, sb, hb)
+
+
+def weno(kind: str, u5: np.ndarray, eps: float, q: float = 2.0) -> float:
+    u = np.ascontiguousarray(u5, dtype=np.float64)
+    ptr = ctypes.cast(u.ctypes.data + 16, ctypes.POINTER(ctypes.c_double))
+    if kind == "zL":
+        return lib().orc_weno5z_left(ptr, eps, q)
+    if kind == "zR":
+        return lib().orc_weno5z_right(ptr, eps, q)
+    return lib().orc_weno5js_left(ptr, eps)
+
+
+def dense_rk4(j: int, m: int, theta: float) -> float:
+    return lib().orc_dense_rk4(j, m, theta)
+
+
+def bor_rk4(R: int, r: int, s: int, dt: float, Un: np.ndarray, k) -> np.ndarray:
+    Un = np.ascontiguousarray(Un, dtype=np.float64)
+    ks = [np.ascontiguousarray(x, dtype=np.float64) for x in k]
+    arr = (ctypes.POINTER(ctypes.c_double) * 4)(*[_p(x) for x in ks])
+    out = np.empty_like(Un)
+    lib().orc_bor_rk4(R, r, s, dt, _p(Un), arr, _p(out), Un.size)
+    return out
+
+
+def lagrange6(xi: float) -> np.ndarray:
+    w = np.zeros(6)
+    lib().orc_lagrange6(xi, _p(w))
+    return w
+
+
+def wave_rhs_adjoint(lam: np.ndarray, h, prm: Params | None = None) -> np.ndarray:
+    prm = prm or params()
+    nf, nx, ny, nz = dims(lam)
+    out = np.zeros_like(lam)
+    lib().orc_wave_rhs_adjoint(_p(np.ascontiguousarray(lam)), _p(out), nx, ny, nz,
+                               _p(_h3(h)), ctypes.byref(prm))
+    return out
+
+
+def fill_periodic_adjoint(A: np.ndarray) -> None:
+    nf, nx, ny, nz = dims(A)
+    lib().orc_fill_periodic_adjoint(_p(A), nf, nx, ny, nz)
+
+
+def wave_adjoint_run(n, h, xlo, dt, nsteps, rad, prm: Params | None = None) -> np.ndarray:
+    prm = prm or params()
+    nx, ny, nz = n
+    lam = np.zeros((2, nz + 6, ny + 6, nx + 6))
+    lib().orc_wave_adjoint_run(_p(lam), nx, ny, nz, _p(_h3(h)),
+                               _p(np.asarray(xlo, dtype=np.float64).copy()), dt, nsteps, rad,
+                               ctypes.byref(prm))
+    return lam
+
+
+def sphere_integral(U: np.ndarray, field: int, xlo, h, rad: float, shift: float = 0.0) -> float:
+    nf, nx, ny, nz = dims(U)
+    return lib().orc_sphere_integral(_p(U), field, nx, ny, nz,
+                                     _p(np.asarray(xlo, dtype=np.float64).copy()),
+                                     _p(_h3(h)), rad, shift)
+
+
+class Hierarchy:
+    """Oracle AMR hierarchy: levels of boxes (inclusive lo/hi, level index space)."""
+
+    def __init__(self, system: int, N0, xlo, dx0: float, levels):
+        """levels: list of (ratio, [(lo3, hi3), ...]); ratio of level 0 ignored."""
+        L = lib()
+        self.system = system
+        self.nf = NFIELDS[system]
+        self.levels = levels
+        ratio = (ctypes.c_int * len(levels))(*[lv[0] for lv in levels])
+        npatch = (ctypes.c_int * len(levels))(*[len(lv[1]) for lv in levels])
+        flat = []
+        for _, boxes in levels:
+            for lo, hi in boxes:
+                flat += list(lo) + list(hi)
+        barr = (ctypes.c_int * len(flat))(*flat)
+        n0 = (ctypes.c_int * 3)(*N0)
+        xl = np.asarray(xlo, dtype=np.float64).copy()
+        self._h = L.orc_hier_create(system, len(levels), ratio, n0, _p(xl), dx0, npatch, barr)
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().orc_hier_destroy(self._h)
+            self._h = None
+
+    def shape(self, l: int, p: int):
+        lo, hi = self.levels[l][1][p]
+        return (self.nf, hi[2] - lo[2] + 7, hi[1] - lo[1] + 7, hi[0] - lo[0] + 7)
+
+    def set(self, l: int, p: int, U: np.ndarray) -> None:
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        assert U.shape == self.shape(l, p)
+        lib().orc_hier_set(self._h, l, p, _p(U))
+
+    def get(self, l: int, p: int) -> np.ndarray:
+        out = np.empty(self.shape(l, p))
+        lib().orc_hier_get(self._h, l, p, _p(out))
+        return out
+
+    def fill_same(self, l: int) -> None:
+        lib().orc_hier_fill_same(self._h, l)
+
+    def step(self, dt0: float, prm: Params | None = None) -> None:
+        prm = prm or params()
+        lib().orc_hier_step(self._h, dt0, ctypes.byref(prm))
+
+    def set_parent_data(self, l: int, p: int, Un, k) -> None:
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in [Un] + list(k)]
+        lib().orc_hier_set_parent_data(self._h, l, p, *[_p(a) for a in arrs])
+
+    def prolong(self, l: int, r: int, s: int, dt_parent: float) -> None:
+        lib().orc_hier_prolong(self._h, l, r, s, dt_parent)
+
+    def restrict(self, l: int) -> None:
+        lib().orc_hier_restrict(self._h, l)

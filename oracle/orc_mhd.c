@@ -1,0 +1,185 @@
+/*
+ * Oracle: Newtonian ideal MHD right-hand side (Sec. IV.B) with the
+ * conservative finite-difference form (eq. conservative_discretization),
+ * WENO5-Z reconstruction of the evolved fields (Sec. II.B.2, App. B) and the
+ * local Lax-Friedrichs flux (eq. LLF).  TEST INFRASTRUCTURE ONLY.
+ *
+ * Conserved fields, in this order: rho, S_x, S_y, S_z, E, B^x, B^y, B^z
+ * (the eight-field ideal core: the cleaning scalar psi is identically zero).
+ *
+ * Readings (the paper leaves these open):
+ *  - the reconstruction acts on the evolved (conserved) fields, as the text
+ *    states for its tests; the flux is then evaluated on U^L and U^R;
+ *  - S in the LLF formula is max over the L and R states of |v_d| + c_f, with
+ *    the fast magnetosonic speed c_f^2 = ((a^2+b^2) + sqrt((a^2+b^2)^2 - 4 a^2 b_d^2))/2,
+ *    a^2 = Gamma p / rho, b^2 = B^2/rho, b_d^2 = B_d^2/rho (units where the
+ *    magnetic pressure is B^2/2, as in the paper's energy density);
+ *  - S is taken per interface.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "oracle.h"
+
+/* Table of c_{r,j} for k = 3 (Sec. II.B.2), rows r = -1, 0, 1, 2. */
+static const double C3[4][3] = {
+    {11.0 / 6.0, -7.0 / 6.0, 1.0 / 3.0},
+    {1.0 / 3.0, 5.0 / 6.0, -1.0 / 6.0},
+    {-1.0 / 6.0, 5.0 / 6.0, 1.0 / 3.0},
+    {1.0 / 3.0, -7.0 / 6.0, 11.0 / 6.0},
+};
+static const double D3[3] = {3.0 / 10.0, 6.0 / 10.0, 1.0 / 10.0};
+
+static double sq(double x) { return x * x; }
+
+/* Smoothness indicators of App. B for the left state at i+1/2; u points at U_i. */
+static void beta_left(const double* u, double b[3])
+{
+    b[0] = 13.0 / 12.0 * sq(u[0] - 2.0 * u[1] + u[2]) + 0.25 * sq(3.0 * u[0] - 4.0 * u[1] + u[2]);
+    b[1] = 13.0 / 12.0 * sq(u[-1] - 2.0 * u[0] + u[1]) + 0.25 * sq(u[-1] - u[1]);
+    b[2] = 13.0 / 12.0 * sq(u[-2] - 2.0 * u[-1] + u[0]) + 0.25 * sq(u[-2] - 4.0 * u[-1] + 3.0 * u[0]);
+}
+
+/* Smoothness indicators of App. B for the right state at i-1/2; u points at U_i. */
+static void beta_right(const double* u, double b[3])
+{
+    b[0] = 13.0 / 12.0 * sq(u[2] - 2.0 * u[1] + u[0]) + 0.25 * sq(u[2] - 4.0 * u[1] + 3.0 * u[0]);
+    b[1] = 13.0 / 12.0 * sq(u[1] - 2.0 * u[0] + u[-1]) + 0.25 * sq(u[1] - u[-1]);
+    b[2] = 13.0 / 12.0 * sq(u[0] - 2.0 * u[-1] + u[-2]) + 0.25 * sq(3.0 * u[0] - 4.0 * u[-1] + u[-2]);
+}
+
+static double powq(double x, double q)
+{
+    return q == 2.0 ? x * x : pow(x, q);
+}
+
+/* Candidate values: ^L U^(r)_{i+1/2} = sum_j c_{r,j} U_{i-r+j};
+ *                   ^R U^(r)_{i-1/2} = sum_j c_{r-1,j} U_{i-r+j}. */
+static void cand_left(const double* u, double v[3])
+{
+    for (int r = 0; r < 3; ++r) {
+        v[r] = 0.0;
+        for (int j = 0; j < 3; ++j) v[r] += C3[r + 1][j] * u[-r + j];
+    }
+}
+
+static void cand_right(const double* u, double v[3])
+{
+    for (int r = 0; r < 3; ++r) {
+        v[r] = 0.0;
+        for (int j = 0; j < 3; ++j) v[r] += C3[r][j] * u[-r + j];
+    }
+}
+
+/* WENO-Z weights (App. B): alpha_r = d_r (1 + [tau/(eps + beta_r)]^q),
+ * tau = |beta_0 - beta_2|, omega_r = alpha_r / sum_s alpha_s. */
+static double combine_z(const double v[3], const double b[3], const double d[3],
+                        double eps, double q)
+{
+    double tau = fabs(b[0] - b[2]);
+    double a[3], sum = 0.0;
+    for (int r = 0; r < 3; ++r) {
+        a[r] = d[r] * (1.0 + powq(tau / (eps + b[r]), q));
+        sum += a[r];
+    }
+    double out = 0.0;
+    for (int r = 0; r < 3; ++r) out += (a[r] / sum) * v[r];
+    return out;
+}
+
+double orc_weno5z_left(const double* u, double eps, double q)
+{
+    double v[3], b[3];
+    cand_left(u, v);
+    beta_left(u, b);
+    return combine_z(v, b, D3, eps, q);
+}
+
+double orc_weno5z_right(const double* u, double eps, double q)
+{
+    double v[3], b[3];
+    double dt[3] = {D3[2], D3[1], D3[0]}; /* tilde d_r = d_{k-1-r} */
+    cand_right(u, v);
+    beta_right(u, b);
+    return combine_z(v, b, dt, eps, q);
+}
+
+/* Classic (JS) weights of Sec. II.B.2: alpha_r = d_r / (eps + beta_r)^2. */
+double orc_weno5js_left(const double* u, double eps)
+{
+    double v[3], b[3], a[3], sum = 0.0, out = 0.0;
+    cand_left(u, v);
+    beta_left(u, b);
+    for (int r = 0; r < 3; ++r) { a[r] = D3[r] / sq(eps + b[r]); sum += a[r]; }
+    for (int r = 0; r < 3; ++r) out += (a[r] / sum) * v[r];
+    return out;
+}
+
+/* Physical flux along direction d and the largest signal speed |v_d| + c_f. */
+static void mhd_flux(const double U[8], int d, double gam, double F[8], double* speed)
+{
+    double rho = U[0];
+    double v[3] = {U[1] / rho, U[2] / rho, U[3] / rho};
+    double E = U[4];
+    double B[3] = {U[5], U[6], U[7]};
+    double B2 = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
+    double S2 = U[1] * U[1] + U[2] * U[2] + U[3] * U[3];
+    double p = (gam - 1.0) * (E - 0.5 * S2 / rho - 0.5 * B2);
+    double vB = v[0] * B[0] + v[1] * B[1] + v[2] * B[2];
+    double ptot = p + 0.5 * B2;
+    F[0] = rho * v[d];
+    for (int i = 0; i < 3; ++i)
+        F[1 + i] = rho * v[d] * v[i] + (i == d ? ptot : 0.0) - B[d] * B[i];
+    F[4] = (E + ptot) * v[d] - vB * B[d];
+    for (int i = 0; i < 3; ++i) F[5 + i] = v[d] * B[i] - v[i] * B[d];
+    double a2 = gam * p / rho, b2 = B2 / rho, bd2 = B[d] * B[d] / rho;
+    double s = a2 + b2;
+    double cf2 = 0.5 * (s + sqrt(s * s - 4.0 * a2 * bd2));
+    *speed = fabs(v[d]) + sqrt(cf2);
+}
+
+void orc_mhd_rhs(const double* U, double* R, int nx, int ny, int nz,
+                 const double h[3], const orc_params* p)
+{
+    long NX = nx + 2 * ORC_G, NY = ny + 2 * ORC_G, NZ = nz + 2 * ORC_G;
+    long vol = NX * NY * NZ;
+    long st[3] = {1, NX, NX * NY};
+    int n[3] = {nx, ny, nz};
+    for (int k = ORC_G; k < nz + ORC_G; ++k)
+        for (int j = ORC_G; j < ny + ORC_G; ++j)
+            for (int i = ORC_G; i < nx + ORC_G; ++i)
+                for (int f = 0; f < 8; ++f) R[f * vol + (k * NY + j) * NX + i] = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        double eps = p->weno_eps > 0.0 ? p->weno_eps : h[d] * h[d] * h[d] * h[d];
+        /* every interface i+1/2 with i = -1 .. n_d - 1 along d (interior coords) */
+        int lo[3] = {ORC_G, ORC_G, ORC_G}, hi[3] = {nx + ORC_G, ny + ORC_G, nz + ORC_G};
+        lo[d] = ORC_G - 1;
+        (void)n;
+        for (int k = lo[2]; k < hi[2]; ++k)
+            for (int j = lo[1]; j < hi[1]; ++j)
+                for (int i = lo[0]; i < hi[0]; ++i) {
+                    long c = (k * NY + j) * NX + i;
+                    double UL[8], UR[8], FL[8], FR[8], sL, sR;
+                    for (int f = 0; f < 8; ++f) {
+                        double line[6];
+                        for (int m = 0; m < 6; ++m) line[m] = U[f * vol + c + (m - 2) * st[d]];
+                        /* line[2] is U_i; left state from cells i-2..i+2, right
+                         * state at i+1/2 is the right state at (i+1)-1/2 */
+                        UL[f] = orc_weno5z_left(line + 2, eps, p->weno_q);
+                        UR[f] = orc_weno5z_right(line + 3, eps, p->weno_q);
+                    }
+                    mhd_flux(UL, d, p->gamma_ad, FL, &sL);
+                    mhd_flux(UR, d, p->gamma_ad, FR, &sR);
+                    double S = sL > sR ? sL : sR;
+                    for (int f = 0; f < 8; ++f) {
+                        double Fh = 0.5 * (FL[f] + FR[f] - S * (UR[f] - UL[f]));
+                        /* interface i+1/2 closes cell i (if interior) on the right
+                         * and opens cell i+1 (if interior) on the left */
+                        int ii[3] = {i, j, k};
+                        if (ii[d] >= ORC_G) R[f * vol + c] -= Fh / h[d];
+                        if (ii[d] + 1 < n[d] + ORC_G) R[f * vol + c + st[d]] += Fh / h[d];
+                    }
+                }
+    }
+}
