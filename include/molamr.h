@@ -1,0 +1,233 @@
+/*
+ * molamr — method-of-lines hot path on SAMRAI-style patches for gfx950.
+ *
+ * C ABI of the HIP library libmolamr.so.  The operations follow Palenzuela
+ * et al., "A Simflowny-based finite-difference code for high-performance
+ * computing in Relativity" (arXiv:1806.04182); each entry point names the
+ * section or equation that defines it.
+ *
+ * Conventions (all entry points):
+ *  - Ownership.  A patchset owns its host metadata and its device tables
+ *    (allocated in mol_create_patchset, freed in mol_destroy_patchset).  The
+ *    caller owns every field buffer: device memory holding float64 values in
+ *    the layout reported by mol_level_layout.  Input buffers are not written.
+ *  - Streams.  Every call that takes a `stream` (a hipStream_t; NULL is the
+ *    default stream) only enqueues work on it: no call synchronises, and none
+ *    allocates device memory after mol_create_patchset, so sequences of calls
+ *    can be captured in a HIP graph.
+ *  - Errors.  Every int-returning call returns 0 on success or a negative
+ *    code; mol_last_error() returns a message for the calling thread's last
+ *    failure.  Argument errors are detected on the host before any work is
+ *    enqueued.  Faults inside kernels surface at the caller's next
+ *    synchronisation.  No C++ exception crosses this interface.
+ *  - Threading.  Calls on different patchsets are independent; concurrent
+ *    calls that write the same buffers race.
+ *
+ * Geometry (Sec. III).  Grids are vertex centred: level l has spacing
+ * dx0 / (R_1 ... R_l), and fine point R*i coincides with coarse point i for
+ * any integer ratio R (which makes injection a copy for R = 2 and R = 3).
+ * The domain is periodic with N0 level-0 points per axis (N0 R_1 ... R_l on
+ * level l).  Boxes are inclusive (lo, hi) index ranges in level index space.
+ * Every patch carries a ghost layer of 3 points (MOL_GHOST).
+ *
+ * Field layout of a level buffer: patch p occupies the block starting at
+ * patch_offsets[p]; inside it, field f starts at f * fstride_p, and point
+ * (i, j, k) of the ghosted box (0 <= i < nx+6, ...) is at
+ * (k * (ny+6) + j) * (nx+6) + i.  fstride_p = (nx+6)(ny+6)(nz+6) rounded up
+ * to a multiple of 32 doubles; patch blocks start on 256-byte boundaries.
+ */
+#ifndef MOLAMR_H
+#define MOLAMR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MOL_GHOST 3
+#define MOL_MAX_LEVELS 8
+
+/* error codes */
+#define MOL_OK 0
+#define MOL_EINVAL (-1)
+#define MOL_ENOMEM (-2)
+#define MOL_EHIP (-3)
+#define MOL_EUNSUPPORTED (-4)
+#define MOL_ESTATE (-5)
+
+/* systems */
+#define MOL_WAVE 0 /* scalar wave, Sec. IV.A: fields phi, Pi */
+#define MOL_MHD 1  /* Newtonian ideal MHD, Sec. IV.B: rho, S_x, S_y, S_z, E, B^x, B^y, B^z */
+#define MOL_CCZ4 2 /* CCZ4, Sec. V: chi, gt_ij(6), trKhat, At_ij(6), Ghat^i(3), Theta,
+                      alpha, beta^i(3), B^i(3); symmetric pairs ordered xx xy xz yy yz zz */
+
+/* time integrators */
+#define MOL_RK4 0    /* Table RK44 */
+#define MOL_SSPRK3 1 /* SSP-RK(3,3) of App. D (stage 3 = U^n + k1/4 + k2/4, weights (1,1,4)/6) */
+
+typedef struct {
+    int nlevels;          /* 1 .. MOL_MAX_LEVELS */
+    int N0[3];            /* level-0 points per axis (periodic domain) */
+    double xlo[3];        /* coordinate of index 0 on every level */
+    double dx0;           /* level-0 spacing */
+    const int* ratio;     /* [nlevels]; ratio[l] = dx_{l-1}/dx_l in {2,3,4}; ratio[0] ignored */
+    const int* npatch;    /* [nlevels] */
+    const int* boxes;     /* 6 ints per patch (lo x y z, hi x y z), levels concatenated */
+} mol_hierarchy_desc;
+
+typedef struct {
+    int system;           /* MOL_WAVE, MOL_MHD or MOL_CCZ4 */
+    int upwind;           /* CCZ4: 1 = lop-sided advection stencils (Sec. II.B.1), 0 = centred */
+    double sigma;         /* Kreiss-Oliger strength (Sec. II.B.1); wave and CCZ4 */
+    double gamma_ad;      /* MHD ideal-gas index (Sec. IV.B) */
+    double weno_eps;      /* MHD WENO epsilon; <= 0 means dx^4 of the sweep axis (App. B) */
+    double weno_q;        /* MHD WENO-Z exponent q (App. B); 2 */
+    double kappa_z;       /* CCZ4 damping (Sec. V) */
+    double kappa_c;
+    double bm_f0;         /* CCZ4 Bona-Masso f = bm_f0 + bm_f1 / alpha (1+log: 0, 2) */
+    double bm_f1;
+    double gd_g;          /* CCZ4 Gamma-driver g and eta */
+    double gd_eta;
+} mol_system_desc;
+
+typedef struct mol_patchset mol_patchset;
+
+/* Build a patchset: validates the hierarchy (boxes inside the level's
+ * periodic domain and non-overlapping, each fine level's region inside its
+ * parent level with a margin of 6 parent points so that prolongation stencils
+ * stay on parent data, interiors of at least 1 point per axis) and builds the
+ * device tables: same-level/periodic ghost lists, coarse-fine ghost lists
+ * (Sec. III.A), injection lists and per-level tile work lists.
+ * Returns MOL_EINVAL on a bad description, MOL_EHIP/MOL_ENOMEM on device
+ * failure. */
+int mol_create_patchset(const mol_hierarchy_desc* h, const mol_system_desc* s,
+                        mol_patchset** out);
+void mol_destroy_patchset(mol_patchset* ps);
+const char* mol_last_error(void);
+
+/* Number of fields of the patchset's system. */
+int mol_nfields(const mol_patchset* ps);
+
+/* Layout of a level buffer (pure host query).  nelems receives the number of
+ * doubles of one level buffer (all fields); patch_offsets[np] (nullable) the
+ * start of each patch block; patch_dims[3*np] (nullable) the interior size of
+ * each patch; fstrides[np] (nullable) the field stride of each patch. */
+int mol_level_layout(const mol_patchset* ps, int level, int64_t* nelems,
+                     int64_t* patch_offsets, int32_t* patch_dims, int64_t* fstrides);
+int mol_level_npatch(const mol_patchset* ps, int level);
+
+/* Ghost fill of level `level`, same-level and periodic sources only (the
+ * "level synchronization" of the Sec. III skeleton): every ghost point that
+ * the stencils read (faces to depth 3, edges to depth 2) and that lies in the
+ * interior of a patch of the same level, modulo the period, takes that value.
+ * nf fields of U are filled (nf = 0 means all fields of the system). */
+int mol_fill_ghosts(mol_patchset* ps, int level, double* U, int nf, void* stream);
+
+/* Right-hand side L(U) + Q_d(U) (eq. semidiscrete) on the interior of every
+ * patch of the level: wave Sec. IV.A; MHD eq. conservative_discretization
+ * with WENO5-Z reconstruction of the evolved fields (App. B) and the LLF flux
+ * (eq. LLF); CCZ4 eqs. syseq1 .. syseq2 with the gauge of Sec. V.  U must
+ * have filled ghosts.  dUdt ghosts are not written. */
+int mol_rhs(mol_patchset* ps, int level, const double* U, double* dUdt, void* stream);
+
+/* One Runge-Kutta stage (eq. eRK) fused with the right-hand side:
+ * k = dt (L + Q_d)(Us) on the interior, then
+ *  RK4 (Table RK44), stage s = 1..4:
+ *    s = 1: Acc = k/6,  Uout = Un + k/2     s = 2: Acc += k/3, Uout = Un + k/2
+ *    s = 3: Acc += k/3, Uout = Un + k       s = 4: Uout = Un + (Acc + k/6)
+ *  SSP-RK3, stage s = 1..3 (Acc unused, may be NULL):
+ *    s = 1: Uout = Un + k;  s = 2: Uout = 3/4 Un + 1/4 (Us + k);
+ *    s = 3: Uout = 1/3 Un + 2/3 (Us + k)
+ * k_store (nullable) receives k on the interior.  Us must have filled
+ * ghosts and must not alias Uout; Un may alias Us; Uout may alias Un only for
+ * the last stage.  Ghosts of Uout are not written. */
+int mol_rk_stage(mol_patchset* ps, int level, int scheme, int stage, double dt,
+                 const double* Un, const double* Us, double* Acc, double* Uout,
+                 double* k_store, void* stream);
+
+/* Coarse-fine ghost fill of fine level `fine_level` (>= 1) with Berger-Oliger
+ * without order reduction (App. D, RK4) and quintic Lagrange interpolation
+ * (Sec. III.A): for fine step r (0 <= r < R) inside the parent step and fine
+ * stage s (1..4), every stencil-read ghost point of the level that has no
+ * same-level source takes
+ *   sum_{a,b,c} L_a(xi_x) L_b(xi_y) L_c(xi_z) [Un_c + sum_j w_j(R,r,s) k_c[j]]
+ * over the parent nodes around it (6 per axis, or the coincident node when
+ * the fine index is a multiple of R), with w_j from the RK4 dense output and
+ * the App. D fine increments.  Un_c and the k_c[4] are parent-level buffers
+ * whose ghosts have been filled with mol_fill_ghosts. */
+int mol_prolong(mol_patchset* ps, int fine_level, int r, int stage,
+                const double* Un_c, const double* const* k_c, double* U_f, void* stream);
+
+/* BOR weights w_1..w_4 used by mol_prolong (host query). */
+int mol_bor_weights(int R, int r, int stage, double w[4]);
+
+/* Injection (Sec. III.A): every interior point of the parent level that
+ * coincides with an interior point of `fine_level` takes the fine value. */
+int mol_restrict(mol_patchset* ps, int fine_level, const double* U_f, double* U_c,
+                 void* stream);
+
+/* Vector-Jacobian product of the right-hand side (project addition, wave
+ * system only): lamU = (d(L + Q_d)/dU)^T lam over the ghosted box of every
+ * patch, with lam read on interior points only (its ghost values are
+ * ignored).  Ghost entries of lamU receive the contributions of the stencil
+ * reads; fold them back with mol_fill_ghosts_adjoint.  MOL_EUNSUPPORTED for
+ * other systems. */
+int mol_rhs_adjoint(mol_patchset* ps, int level, const double* U, const double* lam,
+                    double* lamU, void* stream);
+/* Transpose of mol_fill_ghosts: every source point adds the ghost entries
+ * that copy it, then those ghost entries are zeroed (owner gather, no atomics). */
+int mol_fill_ghosts_adjoint(mol_patchset* ps, int level, double* lamU, void* stream);
+/* Reverse of one RK4 step (Table RK44) of the wave system on one periodic
+ * level: lam <- (dU^{n+1}/dU^n)^T lam.  w0, w1, w2 are work buffers of the
+ * level's size.  lam ghosts are zero on return. */
+int mol_rk4_adjoint_step(mol_patchset* ps, int level, double dt, double* lam,
+                         double* w0, double* w1, double* w2, void* stream);
+
+/* Reductions over the interior of every patch of the level, for
+ * v = U[field] - shift: out_dev[0] = sum |v| dV, [1] = sum v^2 dV,
+ * [2] = max |v|, [3] = sum over points with |x| < radius of v dV,
+ * [4] = number of non-finite values.  out_dev is device memory (5 doubles).
+ * The summation order is fixed (deterministic). */
+int mol_norms(mol_patchset* ps, int level, const double* U, int field, double shift,
+              double radius, double* out_dev, void* stream);
+
+/* Wave initial data phi = A exp(-|x-c|^2/w^2) (minimum image), Pi = 0, with
+ * prm = {A, w, cx, cy, cz}; and its vector-Jacobian product
+ * grad_dev[i] = sum_points lam_phi d phi / d prm_i (interior points). */
+int mol_wave_gaussian(mol_patchset* ps, int level, const double prm[5], double* U,
+                      void* stream);
+int mol_wave_gaussian_vjp(mol_patchset* ps, int level, const double prm[5],
+                          const double* lam, double* grad_dev, void* stream);
+
+/* ---- sub-cycled driver (Sec. III skeleton, BOR sub-cycling) ---- */
+typedef struct {
+    double* U;    /* state; holds U^n on entry and U^{n+1} on return (ghosts filled) */
+    double* S0;   /* stage-state work buffers */
+    double* S1;
+    double* acc;  /* RK4 accumulator */
+    double* k[4]; /* stage increments; required on levels that have a finer level */
+} mol_level_state;
+
+#define MOL_BATCHED 0 /* one launch per level and operation (work list over all patches) */
+#define MOL_PLAIN 1   /* one launch per patch and operation */
+
+/* One RK4 step of size dt0 on level 0 with sub-cycling of the finer levels
+ * (each level steps with dt / R of its parent), BOR prolongation and
+ * injection; states[nlevels]. */
+int mol_advance(mol_patchset* ps, const mol_level_state* states, double dt0, int mode,
+                void* stream);
+
+typedef struct mol_graph mol_graph;
+/* Capture mol_advance(ps, states, dt0, MOL_BATCHED) into a HIP graph and
+ * instantiate it (the states' buffers are baked in). */
+int mol_graph_create(mol_patchset* ps, const mol_level_state* states, double dt0,
+                     mol_graph** out);
+int mol_graph_launch(mol_graph* g, void* stream);
+void mol_graph_destroy(mol_graph* g);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

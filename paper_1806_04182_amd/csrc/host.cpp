@@ -1,0 +1,939 @@
+// Host runtime of libmolamr: patchset construction (layout, ghost / prolong /
+// restrict schedules, tile work lists), argument validation, the C ABI entry
+// points, the sub-cycled driver and its HIP-graph capture.
+//
+// The AMR skeleton follows Sec. III of Palenzuela et al. (arXiv:1806.04182);
+// BOR sub-cycling follows App. D; the spatial interpolation is the quintic
+// Lagrange polynomial of Sec. III.A.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "molamr_int.h"
+
+using namespace mol;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    return fail(MOL_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+struct Box {
+    int lo[3], hi[3];
+    int n(int d) const { return hi[d] - lo[d] + 1; }
+};
+
+int wrapi(int a, int n)
+{
+    int m = a % n;
+    return m < 0 ? m + n : m;
+}
+
+int64_t round_up(int64_t a, int64_t m) { return (a + m - 1) / m * m; }
+
+// device array helper: owns one hipMalloc'd block
+template <class T>
+struct DevArr {
+    T* p = nullptr;
+    int64_t n = 0;
+    int upload(const std::vector<T>& v)
+    {
+        n = (int64_t)v.size();
+        if (n == 0) return MOL_OK;
+        hipError_t e = hipMalloc(&p, sizeof(T) * n);
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+        e = hipMemcpy(p, v.data(), sizeof(T) * n, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+        return MOL_OK;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+};
+
+struct TileList {
+    int tdim[3] = {1, 1, 1};
+    DevArr<Tile> dev;
+    std::vector<int> by_patch;  // np + 1 offsets
+};
+
+}  // namespace
+
+struct mol_patchset {
+    SysParams sp{};
+    int nlev = 0;
+    int N0[3] = {0, 0, 0};
+    double xlo[3] = {0, 0, 0};
+    double dx0 = 0;
+    struct Level {
+        int ratio = 1;
+        int period[3] = {0, 0, 0};
+        double h = 0;
+        std::vector<Box> boxes;
+        std::vector<PatchDev> pd;
+        int64_t nelems = 0;
+        DevArr<PatchDev> d_pd;
+        // same-level ghost copies, grouped by destination patch
+        DevArr<GhostCopy> fill;
+        std::vector<int64_t> fill_by_patch;
+        DevArr<GhostSource> fill_src;
+        DevArr<GhostImage> fill_img;
+        // coarse-fine ghost points (this level is the fine one), by dst patch
+        DevArr<ProlongPt> pro;
+        std::vector<int64_t> pro_by_patch;
+        DevArr<double> lagw;  // Lagrange weights [R][6]
+        // injection into the parent level, grouped by fine patch
+        DevArr<RestrictPt> rst;
+        std::vector<int64_t> rst_by_patch;
+        TileList tiles;   // interior tiles for the stage kernels
+        TileList gtiles;  // ghosted-box tiles for the adjoint
+        TileList ntiles;  // interior tiles for reductions / initial data
+    };
+    Level L[MOL_MAX_LEVELS];
+    double* scratch = nullptr;  // reduction partials
+    int red_blocks = 256;
+    hipStream_t capture_stream = nullptr;
+
+    ~mol_patchset()
+    {
+        for (auto& l : L) {
+            l.d_pd.release();
+            l.fill.release();
+            l.fill_src.release();
+            l.fill_img.release();
+            l.pro.release();
+            l.lagw.release();
+            l.rst.release();
+            l.tiles.dev.release();
+            l.gtiles.dev.release();
+            l.ntiles.dev.release();
+        }
+        if (scratch) (void)hipFree(scratch);
+        if (capture_stream) (void)hipStreamDestroy(capture_stream);
+    }
+};
+
+struct mol_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+using Level = mol_patchset::Level;
+
+int64_t local_index(const PatchDev& p, int i, int j, int k)  // ghosted local coords
+{
+    return (int64_t)k * p.pitch_z + (int64_t)j * p.pitch_y + i;
+}
+
+// patch of `lev` whose interior holds global index g (wrapped by the period);
+// candidates restrict the search.  Returns -1 when none.
+int find_owner(const Level& lev, const int g0[3], const std::vector<int>& cand, int gw[3])
+{
+    for (int d = 0; d < 3; ++d) gw[d] = wrapi(g0[d], lev.period[d]);
+    for (int q : cand) {
+        const Box& b = lev.boxes[q];
+        if (gw[0] >= b.lo[0] && gw[0] <= b.hi[0] && gw[1] >= b.lo[1] && gw[1] <= b.hi[1] &&
+            gw[2] >= b.lo[2] && gw[2] <= b.hi[2])
+            return q;
+    }
+    return -1;
+}
+
+// do the periodic images of boxes a (grown by `grow`) and b intersect?
+bool periodic_touch(const Box& a, int grow, const Box& b, const int per[3])
+{
+    for (int d = 0; d < 3; ++d) {
+        bool any = false;
+        for (int s = -1; s <= 1 && !any; ++s) {
+            int lo = b.lo[d] + s * per[d], hi = b.hi[d] + s * per[d];
+            if (hi >= a.lo[d] - grow && lo <= a.hi[d] + grow) any = true;
+        }
+        if (!any) return false;
+    }
+    return true;
+}
+
+std::vector<std::vector<int>> candidates(const Level& a, int grow, const Level& b, int scale)
+{
+    // scale: a's coordinates are b's coordinates times `scale` (a finer)
+    std::vector<std::vector<int>> out(a.boxes.size());
+    for (size_t p = 0; p < a.boxes.size(); ++p) {
+        Box ab = a.boxes[p];
+        for (int d = 0; d < 3; ++d) {
+            ab.lo[d] = (int)std::floor((double)(ab.lo[d] - grow) / scale);
+            ab.hi[d] = (int)std::floor((double)(ab.hi[d] + grow) / scale);
+        }
+        for (size_t q = 0; q < b.boxes.size(); ++q)
+            if (periodic_touch(ab, 4, b.boxes[q], b.period)) out[p].push_back((int)q);
+    }
+    return out;
+}
+
+void build_tiles(const Level& lev, const int td[3], int margin, TileList& tl)
+{
+    tl.tdim[0] = td[0];
+    tl.tdim[1] = td[1];
+    tl.tdim[2] = td[2];
+    std::vector<Tile> v;
+    tl.by_patch.assign(lev.pd.size() + 1, 0);
+    for (size_t p = 0; p < lev.pd.size(); ++p) {
+        const PatchDev& pd = lev.pd[p];
+        tl.by_patch[p] = (int)v.size();
+        for (int k = -margin; k < pd.n[2] + margin; k += td[2])
+            for (int j = -margin; j < pd.n[1] + margin; j += td[1])
+                for (int i = -margin; i < pd.n[0] + margin; i += td[0])
+                    v.push_back(Tile{(int)p, {i, j, k}});
+    }
+    tl.by_patch[lev.pd.size()] = (int)v.size();
+    tl.dev.upload(v);
+}
+
+void default_tile(int system, int td[3])
+{
+    switch (system) {
+    case MOL_WAVE: td[0] = 32; td[1] = 4; td[2] = 2; break;
+    case MOL_MHD: td[0] = 16; td[1] = 4; td[2] = 4; break;
+    default: td[0] = 16; td[1] = 4; td[2] = 2; break;
+    }
+}
+
+bool overlap(const Box& a, const Box& b)
+{
+    for (int d = 0; d < 3; ++d)
+        if (a.hi[d] < b.lo[d] || b.hi[d] < a.lo[d]) return false;
+    return true;
+}
+
+int build(mol_patchset* ps, const mol_hierarchy_desc* h)
+{
+    const int* bx = h->boxes;
+    for (int l = 0; l < ps->nlev; ++l) {
+        Level& lev = ps->L[l];
+        lev.ratio = l == 0 ? 1 : h->ratio[l];
+        if (l > 0 && (lev.ratio < 2 || lev.ratio > 4))
+            return fail(MOL_EINVAL, "level %d: ratio %d not in {2,3,4}", l, lev.ratio);
+        for (int d = 0; d < 3; ++d)
+            lev.period[d] = l == 0 ? ps->N0[d] : ps->L[l - 1].period[d] * lev.ratio;
+        lev.h = l == 0 ? ps->dx0 : ps->L[l - 1].h / lev.ratio;
+        int np = h->npatch[l];
+        if (np < 1) return fail(MOL_EINVAL, "level %d has no patch", l);
+        int64_t vol = 0, off = 0;
+        for (int p = 0; p < np; ++p, bx += 6) {
+            Box b;
+            for (int d = 0; d < 3; ++d) {
+                b.lo[d] = bx[d];
+                b.hi[d] = bx[3 + d];
+                if (b.hi[d] < b.lo[d] || b.lo[d] < 0 || b.hi[d] >= lev.period[d])
+                    return fail(MOL_EINVAL, "level %d patch %d: box outside [0, %d) on axis %d",
+                                l, p, lev.period[d], d);
+            }
+            for (const Box& o : lev.boxes)
+                if (overlap(o, b)) return fail(MOL_EINVAL, "level %d patch %d overlaps another", l, p);
+            lev.boxes.push_back(b);
+            vol += (int64_t)b.n(0) * b.n(1) * b.n(2);
+            PatchDev pd{};
+            for (int d = 0; d < 3; ++d) {
+                pd.n[d] = b.n(d);
+                pd.lo[d] = b.lo[d];
+            }
+            pd.pitch_y = pd.n[0] + 2 * G;
+            pd.pitch_z = pd.pitch_y * (pd.n[1] + 2 * G);
+            pd.fs = round_up((int64_t)pd.pitch_z * (pd.n[2] + 2 * G), 32);
+            pd.off = off;
+            off += round_up(pd.fs * ps->sp.nf, 32);
+            lev.pd.push_back(pd);
+        }
+        lev.nelems = off;
+        if (l == 0 && vol != (int64_t)ps->N0[0] * ps->N0[1] * ps->N0[2])
+            return fail(MOL_EINVAL, "level 0 boxes must tile the periodic domain exactly");
+    }
+
+    for (int l = 0; l < ps->nlev; ++l) {
+        Level& lev = ps->L[l];
+        int rc = lev.d_pd.upload(lev.pd);
+        if (rc) return rc;
+        // ---- same-level ghost copies and coarse-fine points ----
+        auto cand = candidates(lev, G, lev, 1);
+        std::vector<GhostCopy> fill;
+        std::vector<ProlongPt> pro;
+        lev.fill_by_patch.assign(lev.pd.size() + 1, 0);
+        lev.pro_by_patch.assign(lev.pd.size() + 1, 0);
+        const Level* par = l > 0 ? &ps->L[l - 1] : nullptr;
+        std::vector<std::vector<int>> pcand;
+        std::vector<int> allpar;
+        if (par) {
+            pcand = candidates(lev, G, *par, lev.ratio);
+            for (size_t q = 0; q < par->boxes.size(); ++q) allpar.push_back((int)q);
+        }
+        const int R = lev.ratio;
+        for (size_t p = 0; p < lev.pd.size(); ++p) {
+            lev.fill_by_patch[p] = (int64_t)fill.size();
+            lev.pro_by_patch[p] = (int64_t)pro.size();
+            const PatchDev& pd = lev.pd[p];
+            for (int k = -G; k < pd.n[2] + G; ++k)
+                for (int j = -G; j < pd.n[1] + G; ++j)
+                    for (int i = -G; i < pd.n[0] + G; ++i) {
+                        if (i >= 0 && i < pd.n[0] && j >= 0 && j < pd.n[1] && k >= 0 && k < pd.n[2])
+                            continue;
+                        int g[3] = {pd.lo[0] + i, pd.lo[1] + j, pd.lo[2] + k}, gw[3];
+                        int64_t dst = pd.off + local_index(pd, i + G, j + G, k + G);
+                        int q = find_owner(lev, g, cand[p], gw);
+                        if (q >= 0) {
+                            const PatchDev& qd = lev.pd[q];
+                            int64_t src = qd.off + local_index(qd, gw[0] - qd.lo[0] + G,
+                                                               gw[1] - qd.lo[1] + G, gw[2] - qd.lo[2] + G);
+                            fill.push_back(GhostCopy{dst, src, pd.fs, qd.fs});
+                            continue;
+                        }
+                        if (!par) return fail(MOL_EINVAL, "level 0 ghost point without a source");
+                        // coarse position g/R = i0 + m/R per axis
+                        int i0[3], m[3], c0[3], cw[3];
+                        for (int d = 0; d < 3; ++d) {
+                            gw[d] = wrapi(g[d], lev.period[d]);
+                            m[d] = gw[d] % R;
+                            i0[d] = gw[d] / R;
+                        }
+                        int q0 = find_owner(*par, i0, pcand[p], cw);
+                        if (q0 < 0) q0 = find_owner(*par, i0, allpar, cw);
+                        if (q0 < 0)
+                            return fail(MOL_EINVAL, "level %d patch %zu: ghost point has no parent data", l, p);
+                        // every stencil node must be interior data of the parent level
+                        for (int c = (m[2] ? -2 : 0); c <= (m[2] ? 3 : 0); ++c)
+                            for (int b = (m[1] ? -2 : 0); b <= (m[1] ? 3 : 0); ++b)
+                                for (int a = (m[0] ? -2 : 0); a <= (m[0] ? 3 : 0); ++a) {
+                                    int nd[3] = {i0[0] + a, i0[1] + b, i0[2] + c}, tmp[3];
+                                    if (find_owner(*par, nd, pcand[p], tmp) < 0 &&
+                                        find_owner(*par, nd, allpar, tmp) < 0)
+                                        return fail(MOL_EINVAL,
+                                                    "level %d patch %zu: prolongation stencil leaves the "
+                                                    "parent level (nest fine levels at least 6 parent points "
+                                                    "inside it)", l, p);
+                                }
+                        const PatchDev& qd = par->pd[q0];
+                        for (int d = 0; d < 3; ++d) c0[d] = cw[d] - qd.lo[d] + G - (m[d] ? 2 : 0);
+                        ProlongPt e{};
+                        e.dst = dst;
+                        e.cbase = qd.off + local_index(qd, c0[0], c0[1], c0[2]);
+                        e.dfs = pd.fs;
+                        e.cfs = qd.fs;
+                        e.cpy = qd.pitch_y;
+                        e.cpz = qd.pitch_z;
+                        for (int d = 0; d < 3; ++d) e.m[d] = (int8_t)m[d];
+                        pro.push_back(e);
+                    }
+        }
+        lev.fill_by_patch[lev.pd.size()] = (int64_t)fill.size();
+        lev.pro_by_patch[lev.pd.size()] = (int64_t)pro.size();
+        if ((rc = lev.fill.upload(fill))) return rc;
+        if ((rc = lev.pro.upload(pro))) return rc;
+        // owner-gather form of the fill (for the adjoint)
+        {
+            std::vector<size_t> idx(fill.size());
+            for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
+            std::stable_sort(idx.begin(), idx.end(),
+                             [&](size_t a, size_t b) { return fill[a].src < fill[b].src; });
+            std::vector<GhostSource> srcs;
+            std::vector<GhostImage> imgs;
+            for (size_t t = 0; t < idx.size(); ++t) {
+                const GhostCopy& e = fill[idx[t]];
+                if (srcs.empty() || srcs.back().src != e.src)
+                    srcs.push_back(GhostSource{e.src, e.sfs, (int32_t)imgs.size(), (int32_t)imgs.size()});
+                imgs.push_back(GhostImage{e.dst, e.dfs});
+                srcs.back().end = (int32_t)imgs.size();
+            }
+            if ((rc = lev.fill_src.upload(srcs))) return rc;
+            if ((rc = lev.fill_img.upload(imgs))) return rc;
+        }
+        if (par) {
+            // Lagrange weights at xi = m/R through nodes -2..3 (Sec. III.A);
+            // row m = 0 is the coincident copy
+            std::vector<double> lw(R * 6, 0.0);
+            lw[0] = 1.0;
+            for (int m = 1; m < R; ++m) {
+                double xi = (double)m / R;
+                for (int j = 0; j < 6; ++j) {
+                    double num = 1.0, den = 1.0;
+                    for (int q = 0; q < 6; ++q) {
+                        if (q == j) continue;
+                        num *= xi - (q - 2);
+                        den *= (double)(j - q);
+                    }
+                    lw[m * 6 + j] = num / den;
+                }
+            }
+            if ((rc = lev.lagw.upload(lw))) return rc;
+            // injection: coarse interior points that coincide with fine interior points
+            std::vector<RestrictPt> rst;
+            lev.rst_by_patch.assign(lev.pd.size() + 1, 0);
+            std::vector<std::vector<RestrictPt>> per(lev.pd.size());
+            std::vector<int> allfine;
+            for (size_t q = 0; q < lev.boxes.size(); ++q) allfine.push_back((int)q);
+            for (size_t q = 0; q < par->pd.size(); ++q) {
+                const PatchDev& qd = par->pd[q];
+                for (int k = 0; k < qd.n[2]; ++k)
+                    for (int j = 0; j < qd.n[1]; ++j)
+                        for (int i = 0; i < qd.n[0]; ++i) {
+                            int gf[3] = {R * (qd.lo[0] + i), R * (qd.lo[1] + j), R * (qd.lo[2] + k)}, fw[3];
+                            int p = find_owner(lev, gf, allfine, fw);
+                            if (p < 0) continue;
+                            const PatchDev& fd = lev.pd[p];
+                            per[p].push_back(RestrictPt{
+                                fd.off + local_index(fd, fw[0] - fd.lo[0] + G, fw[1] - fd.lo[1] + G,
+                                                     fw[2] - fd.lo[2] + G),
+                                qd.off + local_index(qd, i + G, j + G, k + G), fd.fs, qd.fs});
+                        }
+            }
+            for (size_t p = 0; p < lev.pd.size(); ++p) {
+                lev.rst_by_patch[p] = (int64_t)rst.size();
+                rst.insert(rst.end(), per[p].begin(), per[p].end());
+            }
+            lev.rst_by_patch[lev.pd.size()] = (int64_t)rst.size();
+            if ((rc = lev.rst.upload(rst))) return rc;
+        }
+        int td[3];
+        default_tile(ps->sp.system, td);
+        build_tiles(lev, td, 0, lev.tiles);
+        int tg[3] = {16, 4, 4};
+        build_tiles(lev, tg, G, lev.gtiles);
+        int tn[3] = {32, 4, 2};
+        build_tiles(lev, tn, 0, lev.ntiles);
+    }
+    hipError_t e = hipMalloc(&ps->scratch, sizeof(double) * 8 * ps->red_blocks);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+    return MOL_OK;
+}
+
+int check_level(const mol_patchset* ps, int level)
+{
+    if (!ps) return fail(MOL_EINVAL, "null patchset");
+    if (level < 0 || level >= ps->nlev) return fail(MOL_EINVAL, "level %d out of range", level);
+    return MOL_OK;
+}
+
+SysParams level_params(const mol_patchset* ps, int level)
+{
+    SysParams sp = ps->sp;
+    sp.h = ps->L[level].h;
+    return sp;
+}
+
+// BOR weights (App. D, RK4): with theta = r/R and e = 1/R, the fine increments
+// in units of the coarse k_j are
+//   k1F = e b'(theta), k2F = k1F + e^2 b''/2 + e^3 (b''' - F)/8,
+//   k3F = k1F + e^2 b''/2 + e^3 (b''' + F)/8,  F = 4 (delta_j3 - delta_j2),
+// and the fine stage states are b(theta) + (0, k1F/2, k2F/2, k3F).
+// b_4 = -theta^2/2 + 2 theta^3/3 (the sign for which b(1) = (1,2,2,1)/6).
+void bor_weights(int R, int r, int s, double w[4])
+{
+    const double t = (double)r / R, e = 1.0 / R;
+    const double c1[4] = {1.0, 0.0, 0.0, 0.0};
+    const double c2[4] = {-1.5, 1.0, 1.0, -0.5};
+    const double c3[4] = {2.0 / 3.0, -2.0 / 3.0, -2.0 / 3.0, 2.0 / 3.0};
+    for (int j = 0; j < 4; ++j) {
+        double b0 = c1[j] * t + c2[j] * t * t + c3[j] * t * t * t;
+        double b1 = c1[j] + 2.0 * c2[j] * t + 3.0 * c3[j] * t * t;
+        double b2 = 2.0 * c2[j] + 6.0 * c3[j] * t;
+        double b3 = 6.0 * c3[j];
+        double F = j == 2 ? 4.0 : (j == 1 ? -4.0 : 0.0);
+        double k1 = e * b1;
+        double k2 = k1 + 0.5 * e * e * b2 + 0.125 * e * e * e * (b3 - F);
+        double k3 = k1 + 0.5 * e * e * b2 + 0.125 * e * e * e * (b3 + F);
+        w[j] = s == 1 ? b0 : s == 2 ? b0 + 0.5 * k1 : s == 3 ? b0 + 0.5 * k2 : b0 + k3;
+    }
+}
+
+hipStream_t S(void* s) { return (hipStream_t)s; }
+
+int stage_impl(mol_patchset* ps, int level, int mode, int stage, double dt, const double* Un,
+               const double* Us, double* acc, double* out, double* kst, hipStream_t st, int plain)
+{
+    Level& lev = ps->L[level];
+    SysParams sp = level_params(ps, level);
+    StageArgs a{};
+    a.patches = lev.d_pd.p;
+    a.mode = mode;
+    a.stage = stage;
+    a.dt = dt;
+    a.Un = Un;
+    a.Us = Us;
+    a.acc = acc;
+    a.out = out;
+    a.kst = kst;
+    if (!plain) {
+        a.tiles = lev.tiles.dev.p;
+        a.ntiles = (int)lev.tiles.dev.n;
+        hipError_t e = launch_stage(sp, a, lev.tiles.tdim, st);
+        return e == hipSuccess ? MOL_OK : hip_fail(e, "stage launch");
+    }
+    for (size_t p = 0; p < lev.pd.size(); ++p) {
+        a.tiles = lev.tiles.dev.p + lev.tiles.by_patch[p];
+        a.ntiles = lev.tiles.by_patch[p + 1] - lev.tiles.by_patch[p];
+        hipError_t e = launch_stage(sp, a, lev.tiles.tdim, st);
+        if (e != hipSuccess) return hip_fail(e, "stage launch");
+    }
+    return MOL_OK;
+}
+
+int fill_impl(mol_patchset* ps, int level, double* U, int nf, hipStream_t st, int plain)
+{
+    Level& lev = ps->L[level];
+    if (nf <= 0) nf = ps->sp.nf;
+    if (!plain) {
+        hipError_t e = launch_fill(lev.fill.p, lev.fill.n, nf, U, st);
+        return e == hipSuccess ? MOL_OK : hip_fail(e, "fill launch");
+    }
+    for (size_t p = 0; p < lev.pd.size(); ++p) {
+        int64_t b = lev.fill_by_patch[p], n = lev.fill_by_patch[p + 1] - b;
+        hipError_t e = launch_fill(lev.fill.p + b, n, nf, U, st);
+        if (e != hipSuccess) return hip_fail(e, "fill launch");
+    }
+    return MOL_OK;
+}
+
+int prolong_impl(mol_patchset* ps, int fl, int r, int stage, const double* Unc,
+                 const double* const* kc, double* Uf, hipStream_t st, int plain)
+{
+    Level& lev = ps->L[fl];
+    double w[4];
+    bor_weights(lev.ratio, r, stage, w);
+    if (!plain) {
+        hipError_t e = launch_prolong(lev.pro.p, lev.pro.n, ps->sp.nf, lev.ratio, lev.lagw.p, w,
+                                      Unc, kc[0], kc[1], kc[2], kc[3], Uf, st);
+        return e == hipSuccess ? MOL_OK : hip_fail(e, "prolong launch");
+    }
+    for (size_t p = 0; p < lev.pd.size(); ++p) {
+        int64_t b = lev.pro_by_patch[p], n = lev.pro_by_patch[p + 1] - b;
+        hipError_t e = launch_prolong(lev.pro.p + b, n, ps->sp.nf, lev.ratio, lev.lagw.p, w, Unc,
+                                      kc[0], kc[1], kc[2], kc[3], Uf, st);
+        if (e != hipSuccess) return hip_fail(e, "prolong launch");
+    }
+    return MOL_OK;
+}
+
+int restrict_impl(mol_patchset* ps, int fl, const double* Uf, double* Uc, hipStream_t st, int plain)
+{
+    Level& lev = ps->L[fl];
+    if (!plain) {
+        hipError_t e = launch_restrict(lev.rst.p, lev.rst.n, ps->sp.nf, Uf, Uc, st);
+        return e == hipSuccess ? MOL_OK : hip_fail(e, "restrict launch");
+    }
+    for (size_t p = 0; p < lev.pd.size(); ++p) {
+        int64_t b = lev.rst_by_patch[p], n = lev.rst_by_patch[p + 1] - b;
+        hipError_t e = launch_restrict(lev.rst.p + b, n, ps->sp.nf, Uf, Uc, st);
+        if (e != hipSuccess) return hip_fail(e, "restrict launch");
+    }
+    return MOL_OK;
+}
+
+// Sec. III skeleton with BOR sub-cycling: level l takes one RK4 step of size
+// dt; its finer level then takes R steps of dt/R whose coarse-fine ghosts
+// come from this step's U^n and k_1..k_4; the fine result is injected.
+int advance_level(mol_patchset* ps, const mol_level_state* st, int l, int r, double dt,
+                  hipStream_t s, int plain)
+{
+    const mol_level_state& X = st[l];
+    const bool kids = l + 1 < ps->nlev;
+    const int nf = ps->sp.nf;
+    double* stage_in[4] = {X.U, X.S0, X.S1, X.S0};
+    double* stage_out[4] = {X.S0, X.S1, X.S0, kids ? X.S1 : X.U};
+    int rc;
+    for (int sidx = 0; sidx < 4; ++sidx) {
+        double* Us = stage_in[sidx];
+        if ((rc = fill_impl(ps, l, Us, nf, s, plain))) return rc;
+        if (l > 0) {
+            const mol_level_state& P = st[l - 1];
+            const double* kc[4] = {P.k[0], P.k[1], P.k[2], P.k[3]};
+            if ((rc = prolong_impl(ps, l, r, sidx + 1, P.U, kc, Us, s, plain))) return rc;
+        }
+        if ((rc = stage_impl(ps, l, ST_RK4, sidx + 1, dt, X.U, Us, X.acc, stage_out[sidx],
+                             kids ? X.k[sidx] : nullptr, s, plain)))
+            return rc;
+    }
+    if (kids) {
+        for (int j = 0; j < 4; ++j)
+            if ((rc = fill_impl(ps, l, X.k[j], nf, s, plain))) return rc;
+        const int R = ps->L[l + 1].ratio;
+        for (int rr = 0; rr < R; ++rr)
+            if ((rc = advance_level(ps, st, l + 1, rr, dt / R, s, plain))) return rc;
+        if ((rc = restrict_impl(ps, l + 1, st[l + 1].U, X.S1, s, plain))) return rc;
+        hipError_t e = hipMemcpyAsync(X.U, X.S1, sizeof(double) * ps->L[l].nelems,
+                                      hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    }
+    return fill_impl(ps, l, X.U, nf, s, plain);
+}
+
+int check_states(const mol_patchset* ps, const mol_level_state* st)
+{
+    if (!st) return fail(MOL_EINVAL, "null level states");
+    for (int l = 0; l < ps->nlev; ++l) {
+        const mol_level_state& X = st[l];
+        if (!X.U || !X.S0 || !X.S1 || !X.acc) return fail(MOL_EINVAL, "level %d: null buffer", l);
+        if (X.U == X.S0 || X.U == X.S1 || X.S0 == X.S1)
+            return fail(MOL_EINVAL, "level %d: state buffers must be distinct", l);
+        if (l + 1 < ps->nlev)
+            for (int j = 0; j < 4; ++j)
+                if (!X.k[j]) return fail(MOL_EINVAL, "level %d: k buffers required (has a finer level)", l);
+    }
+    return MOL_OK;
+}
+
+}  // namespace
+
+// ============================================================== C ABI
+
+extern "C" {
+
+const char* mol_last_error(void) { return g_err.c_str(); }
+
+int mol_create_patchset(const mol_hierarchy_desc* h, const mol_system_desc* s, mol_patchset** out)
+{
+    if (!h || !s || !out) return fail(MOL_EINVAL, "null argument");
+    *out = nullptr;
+    if (h->nlevels < 1 || h->nlevels > MOL_MAX_LEVELS)
+        return fail(MOL_EINVAL, "nlevels %d not in [1, %d]", h->nlevels, MOL_MAX_LEVELS);
+    if (!h->npatch || !h->boxes || (h->nlevels > 1 && !h->ratio))
+        return fail(MOL_EINVAL, "null hierarchy arrays");
+    if (!(h->dx0 > 0.0)) return fail(MOL_EINVAL, "dx0 must be positive");
+    for (int d = 0; d < 3; ++d)
+        if (h->N0[d] < 1) return fail(MOL_EINVAL, "N0[%d] must be >= 1", d);
+    if (s->system != MOL_WAVE && s->system != MOL_MHD && s->system != MOL_CCZ4)
+        return fail(MOL_EINVAL, "unknown system %d", s->system);
+    mol_patchset* ps = new (std::nothrow) mol_patchset();
+    if (!ps) return fail(MOL_ENOMEM, "host allocation failed");
+    ps->sp.system = s->system;
+    ps->sp.nf = s->system == MOL_WAVE ? 2 : s->system == MOL_MHD ? 8 : 25;
+    ps->sp.upwind = s->upwind;
+    ps->sp.sigma = s->sigma;
+    ps->sp.gamma_ad = s->gamma_ad;
+    ps->sp.weno_eps = s->weno_eps;
+    ps->sp.weno_q = s->weno_q;
+    ps->sp.kappa_z = s->kappa_z;
+    ps->sp.kappa_c = s->kappa_c;
+    ps->sp.bm_f0 = s->bm_f0;
+    ps->sp.bm_f1 = s->bm_f1;
+    ps->sp.gd_g = s->gd_g;
+    ps->sp.gd_eta = s->gd_eta;
+    if (s->system == MOL_MHD && !(s->gamma_ad > 1.0)) {
+        delete ps;
+        return fail(MOL_EINVAL, "gamma_ad must exceed 1");
+    }
+    ps->nlev = h->nlevels;
+    for (int d = 0; d < 3; ++d) {
+        ps->N0[d] = h->N0[d];
+        ps->xlo[d] = h->xlo[d];
+    }
+    ps->dx0 = h->dx0;
+    int rc = build(ps, h);
+    if (rc) {
+        delete ps;
+        return rc;
+    }
+    *out = ps;
+    return MOL_OK;
+}
+
+void mol_destroy_patchset(mol_patchset* ps) { delete ps; }
+
+int mol_nfields(const mol_patchset* ps) { return ps ? ps->sp.nf : fail(MOL_EINVAL, "null patchset"); }
+
+int mol_level_npatch(const mol_patchset* ps, int level)
+{
+    int rc = check_level(ps, level);
+    return rc ? rc : (int)ps->L[level].pd.size();
+}
+
+int mol_level_layout(const mol_patchset* ps, int level, int64_t* nelems, int64_t* offs,
+                     int32_t* dims, int64_t* fstrides)
+{
+    int rc = check_level(ps, level);
+    if (rc) return rc;
+    const Level& lev = ps->L[level];
+    if (nelems) *nelems = lev.nelems;
+    for (size_t p = 0; p < lev.pd.size(); ++p) {
+        if (offs) offs[p] = lev.pd[p].off;
+        if (dims)
+            for (int d = 0; d < 3; ++d) dims[3 * p + d] = lev.pd[p].n[d];
+        if (fstrides) fstrides[p] = lev.pd[p].fs;
+    }
+    return MOL_OK;
+}
+
+int mol_fill_ghosts(mol_patchset* ps, int level, double* U, int nf, void* stream)
+{
+    int rc = check_level(ps, level);
+    if (rc) return rc;
+    if (!U) return fail(MOL_EINVAL, "null buffer");
+    if (nf > ps->sp.nf) return fail(MOL_EINVAL, "nf %d exceeds the system's %d fields", nf, ps->sp.nf);
+    return fill_impl(ps, level, U, nf, S(stream), 0);
+}
+
+int mol_rhs(mol_patchset* ps, int level, const double* U, double* dUdt, void* stream)
+{
+    int rc = check_level(ps, level);
+    if (rc) return rc;
+    if (!U || !dUdt) return fail(MOL_EINVAL, "null buffer");
+    if (U == dUdt) return fail(MOL_EINVAL, "U and dUdt must not alias");
+    return stage_impl(ps, level, ST_RHS, 0, 1.0, U, U, nullptr, dUdt, nullptr, S(stream), 0);
+}
+
+int mol_rk_stage(mol_patchset* ps, int level, int scheme, int stage, double dt, const double* Un,
+                 const double* Us, double* Acc, double* Uout, double* k_store, void* stream)
+{
+    int rc = check_level(ps, level);
+    if (rc) return rc;
+    if (!Un || !Us || !Uout) return fail(MOL_EINVAL, "null buffer");
+    if (!std::isfinite(dt) || dt <= 0.0) return fail(MOL_EINVAL, "dt must be positive and finite");
+    if ((const double*)Uout == Us) return fail(MOL_EINVAL, "Uout must not alias Us");
+    if (scheme == MOL_RK4) {
+        if (stage < 1 || stage > 4) return fail(MOL_EINVAL, "RK4 stage %d not in 1..4", stage);
+        if (!Acc) return fail(MOL_EINVAL, "RK4 needs the accumulator");
+        if ((const double*)Uout == Un && stage != 4)
+            return fail(MOL_EINVAL, "Uout may alias Un only at the last stage");
+        return stage_impl(ps, level, ST_RK4, stage, dt, Un, Us, Acc, Uout, k_store, S(stream), 0);
+    }
+    if (scheme == MOL_SSPRK3) {
+        if (stage < 1 || stage > 3) return fail(MOL_EINVAL, "SSP-RK3 stage %d not in 1..3", stage);
+        if ((const double*)Uout == Un && stage != 3)
+            return fail(MOL_EINVAL, "Uout may alias Un only at the last stage");
+        return stage_impl(ps, level, ST_SSP3, stage, dt, Un, Us, Acc, Uout, k_store, S(stream), 0);
+    }
+    return fail(MOL_EINVAL, "unknown scheme %d", scheme);
+}
+
+int mol_bor_weights(int R, int r, int stage, double w[4])
+{
+    if (R < 1 || r < 0 || r >= R || stage < 1 || stage > 4 || !w)
+        return fail(MOL_EINVAL, "bad BOR arguments");
+    bor_weights(R, r, stage, w);
+    return MOL_OK;
+}
+
+int mol_prolong(mol_patchset* ps, int fine_level, int r, int stage, const double* Un_c,
+                const double* const* k_c, double* U_f, void* stream)
+{
+    int rc = check_level(ps, fine_level);
+    if (rc) return rc;
+    if (fine_level < 1) return fail(MOL_EINVAL, "level 0 has no parent");
+    const int R = ps->L[fine_level].ratio;
+    if (r < 0 || r >= R) return fail(MOL_EINVAL, "fine step %d not in [0, %d)", r, R);
+    if (stage < 1 || stage > 4) return fail(MOL_EINVAL, "stage %d not in 1..4", stage);
+    if (!Un_c || !k_c || !U_f) return fail(MOL_EINVAL, "null buffer");
+    for (int j = 0; j < 4; ++j)
+        if (!k_c[j]) return fail(MOL_EINVAL, "null k buffer");
+    return prolong_impl(ps, fine_level, r, stage, Un_c, k_c, U_f, S(stream), 0);
+}
+
+int mol_restrict(mol_patchset* ps, int fine_level, const double* U_f, double* U_c, void* stream)
+{
+    int rc = check_level(ps, fine_level);
+    if (rc) return rc;
+    if (fine_level < 1) return fail(MOL_EINVAL, "level 0 has no parent");
+    if (!U_f || !U_c) return fail(MOL_EINVAL, "null buffer");
+    return restrict_impl(ps, fine_level, U_f, U_c, S(stream), 0);
+}
+
+int mol_rhs_adjoint(mol_patchset* ps, int level, const double* U, const double* lam, double* lamU,
+                    void* stream)
+{
+    int rc = check_level(ps, level);
+    if (rc) return rc;
+    if (ps->sp.system != MOL_WAVE)
+        return fail(MOL_EUNSUPPORTED, "the right-hand-side adjoint exists for the wave system only");
+    if (!lam || !lamU) return fail(MOL_EINVAL, "null buffer");
+    if (lam == lamU) return fail(MOL_EINVAL, "lam and lamU must not alias");
+    (void)U;  // the wave operator is linear: its transpose does not depend on U
+    Level& lev = ps->L[level];
+    SysParams sp = level_params(ps, level);
+    hipError_t e = launch_wave_adjoint(sp, lev.d_pd.p, lev.gtiles.dev.p, (int)lev.gtiles.dev.n,
+                                       lev.gtiles.tdim, lam, lamU, S(stream));
+    return e == hipSuccess ? MOL_OK : hip_fail(e, "adjoint launch");
+}
+
+int mol_fill_ghosts_adjoint(mol_patchset* ps, int level, double* lamU, void* stream)
+{
+    int rc = check_level(ps, level);
+    if (rc) return rc;
+    if (!lamU) return fail(MOL_EINVAL, "null buffer");
+    Level& lev = ps->L[level];
+    hipError_t e = launch_fill_adjoint(lev.fill_src.p, lev.fill_src.n, lev.fill_img.p, ps->sp.nf,
+                                       lamU, S(stream));
+    return e == hipSuccess ? MOL_OK : hip_fail(e, "fill adjoint launch");
+}
+
+int mol_rk4_adjoint_step(mol_patchset* ps, int level, double dt, double* lam, double* w0,
+                         double* w1, double* w2, void* stream)
+{
+    int rc = check_level(ps, level);
+    if (rc) return rc;
+    if (ps->sp.system != MOL_WAVE)
+        return fail(MOL_EUNSUPPORTED, "the RK4 adjoint exists for the wave system only");
+    if (!lam || !w0 || !w1 || !w2) return fail(MOL_EINVAL, "null buffer");
+    if (ps->nlev != 1) return fail(MOL_EUNSUPPORTED, "the RK4 adjoint handles one periodic level");
+    if (!std::isfinite(dt) || dt <= 0.0) return fail(MOL_EINVAL, "dt must be positive and finite");
+    const int64_t n = ps->L[level].nelems;
+    hipStream_t s = S(stream);
+    // Reverse of U' = U + sum_s c_s k_s, k_s = dt L(U + b_s k_{s-1}):
+    //   lk_s = c_s lam + b_{s+1} m_{s+1};  m_s = fill^T(dt L^T lk_s);
+    //   lam  <- lam + m_1 + m_2 + m_3 + m_4.
+    // w0 = lk, w1 = m (current), w2 = running sum of the m's.
+    static const double cw[4] = {1.0 / 6.0, 2.0 / 6.0, 2.0 / 6.0, 1.0 / 6.0};
+    static const double bsub[4] = {0.0, 0.5, 0.5, 1.0};
+    hipError_t e = hipSuccess;
+    for (int st = 3; st >= 0; --st) {
+        if (st == 3)
+            e = launch_axpby(n, cw[3], lam, 0.0, lam, w0, s);
+        else
+            e = launch_axpby(n, cw[st], lam, bsub[st + 1], w1, w0, s);
+        if (e != hipSuccess) return hip_fail(e, "axpby");
+        if ((rc = mol_rhs_adjoint(ps, level, nullptr, w0, w1, stream))) return rc;
+        if ((rc = mol_fill_ghosts_adjoint(ps, level, w1, stream))) return rc;
+        e = launch_axpby(n, dt, w1, 0.0, w1, w1, s);
+        if (e != hipSuccess) return hip_fail(e, "axpby");
+        e = st == 3 ? launch_axpby(n, 1.0, w1, 0.0, w1, w2, s) : launch_axpby(n, 1.0, w2, 1.0, w1, w2, s);
+        if (e != hipSuccess) return hip_fail(e, "axpby");
+    }
+    e = launch_axpby(n, 1.0, lam, 1.0, w2, lam, s);
+    return e == hipSuccess ? MOL_OK : hip_fail(e, "axpby");
+}
+
+int mol_norms(mol_patchset* ps, int level, const double* U, int field, double shift, double radius,
+              double* out_dev, void* stream)
+{
+    int rc = check_level(ps, level);
+    if (rc) return rc;
+    if (!U || !out_dev) return fail(MOL_EINVAL, "null buffer");
+    if (field < 0 || field >= ps->sp.nf) return fail(MOL_EINVAL, "field %d out of range", field);
+    Level& lev = ps->L[level];
+    hipError_t e = launch_norms(lev.d_pd.p, lev.ntiles.dev.p, (int)lev.ntiles.dev.n, lev.ntiles.tdim, U,
+                                field, shift, radius, lev.h, ps->xlo, ps->scratch, ps->red_blocks,
+                                out_dev, S(stream));
+    return e == hipSuccess ? MOL_OK : hip_fail(e, "norms launch");
+}
+
+int mol_wave_gaussian(mol_patchset* ps, int level, const double prm[5], double* U, void* stream)
+{
+    int rc = check_level(ps, level);
+    if (rc) return rc;
+    if (ps->sp.system != MOL_WAVE) return fail(MOL_EUNSUPPORTED, "wave system only");
+    if (!prm || !U) return fail(MOL_EINVAL, "null argument");
+    if (!(prm[1] > 0.0)) return fail(MOL_EINVAL, "width must be positive");
+    Level& lev = ps->L[level];
+    double per[3];
+    for (int d = 0; d < 3; ++d) per[d] = lev.period[d] * lev.h;
+    hipError_t e = launch_gaussian(lev.d_pd.p, lev.ntiles.dev.p, (int)lev.ntiles.dev.n, lev.ntiles.tdim, prm,
+                                   lev.h, ps->xlo, per, U, nullptr, nullptr, 0, nullptr, S(stream));
+    return e == hipSuccess ? MOL_OK : hip_fail(e, "gaussian launch");
+}
+
+int mol_wave_gaussian_vjp(mol_patchset* ps, int level, const double prm[5], const double* lam,
+                          double* grad_dev, void* stream)
+{
+    int rc = check_level(ps, level);
+    if (rc) return rc;
+    if (ps->sp.system != MOL_WAVE) return fail(MOL_EUNSUPPORTED, "wave system only");
+    if (!prm || !lam || !grad_dev) return fail(MOL_EINVAL, "null argument");
+    if (!(prm[1] > 0.0)) return fail(MOL_EINVAL, "width must be positive");
+    Level& lev = ps->L[level];
+    double per[3];
+    for (int d = 0; d < 3; ++d) per[d] = lev.period[d] * lev.h;
+    hipError_t e = launch_gaussian(lev.d_pd.p, lev.ntiles.dev.p, (int)lev.ntiles.dev.n, lev.ntiles.tdim, prm,
+                                   lev.h, ps->xlo, per, nullptr, lam, ps->scratch, ps->red_blocks,
+                                   grad_dev, S(stream));
+    return e == hipSuccess ? MOL_OK : hip_fail(e, "gaussian vjp launch");
+}
+
+int mol_advance(mol_patchset* ps, const mol_level_state* states, double dt0, int mode, void* stream)
+{
+    if (!ps) return fail(MOL_EINVAL, "null patchset");
+    if (ps->sp.system != MOL_WAVE && ps->sp.system != MOL_CCZ4 && ps->sp.system != MOL_MHD)
+        return fail(MOL_EINVAL, "unknown system");
+    if (!std::isfinite(dt0) || dt0 <= 0.0) return fail(MOL_EINVAL, "dt must be positive and finite");
+    if (mode != MOL_BATCHED && mode != MOL_PLAIN) return fail(MOL_EINVAL, "unknown mode %d", mode);
+    int rc = check_states(ps, states);
+    if (rc) return rc;
+    return advance_level(ps, states, 0, 0, dt0, S(stream), mode == MOL_PLAIN);
+}
+
+int mol_graph_create(mol_patchset* ps, const mol_level_state* states, double dt0, mol_graph** out)
+{
+    if (!ps || !out) return fail(MOL_EINVAL, "null argument");
+    *out = nullptr;
+    if (!std::isfinite(dt0) || dt0 <= 0.0) return fail(MOL_EINVAL, "dt must be positive and finite");
+    int rc = check_states(ps, states);
+    if (rc) return rc;
+    hipError_t e;
+    if (!ps->capture_stream) {
+        e = hipStreamCreateWithFlags(&ps->capture_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+    }
+    mol_graph* g = new (std::nothrow) mol_graph();
+    if (!g) return fail(MOL_ENOMEM, "host allocation failed");
+    e = hipStreamBeginCapture(ps->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        delete g;
+        return hip_fail(e, "hipStreamBeginCapture");
+    }
+    rc = advance_level(ps, states, 0, 0, dt0, ps->capture_stream, 0);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(ps->capture_stream, &graph);
+    if (rc || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        delete g;
+        return rc ? rc : hip_fail(e, "hipStreamEndCapture");
+    }
+    g->graph = graph;
+    e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        delete g;
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    *out = g;
+    return MOL_OK;
+}
+
+int mol_graph_launch(mol_graph* g, void* stream)
+{
+    if (!g || !g->exec) return fail(MOL_EINVAL, "null graph");
+    hipError_t e = hipGraphLaunch(g->exec, S(stream));
+    return e == hipSuccess ? MOL_OK : hip_fail(e, "hipGraphLaunch");
+}
+
+void mol_graph_destroy(mol_graph* g)
+{
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+}
+
+}  // extern "C"

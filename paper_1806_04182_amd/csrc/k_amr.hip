@@ -1,0 +1,155 @@
+// Ghost fill, its transpose, coarse-fine prolongation and injection kernels
+// (the data movement of the Sec. III skeleton), plus a vector update used
+// by the RK4 adjoint.
+#include "molamr_int.h"
+
+namespace mol {
+
+namespace {
+
+constexpr int BLK = 256;
+
+int grid_for(int64_t n)
+{
+    int64_t b = (n + BLK - 1) / BLK;
+    return (int)(b < 1 ? 1 : (b > 65535 * 8 ? 65535 * 8 : b));
+}
+
+// same-level / periodic copy: ghost <- interior point of the owning patch
+__global__ __launch_bounds__(BLK) void fill_kernel(const GhostCopy* __restrict__ e, int64_t n, int nf,
+                                                   double* __restrict__ U)
+{
+    for (int64_t t = blockIdx.x * (int64_t)BLK + threadIdx.x; t < n; t += (int64_t)gridDim.x * BLK) {
+        const GhostCopy c = e[t];
+        for (int f = 0; f < nf; ++f) U[c.dst + f * c.dfs] = U[c.src + f * c.sfs];
+    }
+}
+
+// transpose of the copy: source += its images, images <- 0
+__global__ __launch_bounds__(BLK) void fill_adjoint_kernel(const GhostSource* __restrict__ src, int64_t n,
+                                                           const GhostImage* __restrict__ img, int nf,
+                                                           double* __restrict__ A)
+{
+    for (int64_t t = blockIdx.x * (int64_t)BLK + threadIdx.x; t < n; t += (int64_t)gridDim.x * BLK) {
+        const GhostSource s = src[t];
+        for (int f = 0; f < nf; ++f) {
+            double acc = A[s.src + f * s.sfs];
+            for (int q = s.beg; q < s.end; ++q) {
+                const int64_t d = img[q].dst + f * img[q].dfs;
+                acc += A[d];
+                A[d] = 0.0;
+            }
+            A[s.src + f * s.sfs] = acc;
+        }
+    }
+}
+
+struct BorW {
+    double w[4];
+};
+
+// coarse-fine ghost point: tensor-product Lagrange interpolation (Sec. III.A)
+// of the parent's BOR stage state U^n + sum_j w_j k_j (App. D)
+__global__ __launch_bounds__(BLK) void prolong_kernel(const ProlongPt* __restrict__ e, int64_t n, int nf,
+                                                      const double* __restrict__ lw, BorW W,
+                                                      const double* __restrict__ Un,
+                                                      const double* __restrict__ k0,
+                                                      const double* __restrict__ k1,
+                                                      const double* __restrict__ k2,
+                                                      const double* __restrict__ k3,
+                                                      double* __restrict__ U)
+{
+    for (int64_t t = blockIdx.x * (int64_t)BLK + threadIdx.x; t < n; t += (int64_t)gridDim.x * BLK) {
+        const ProlongPt p = e[t];
+        const int cx = p.m[0] ? 6 : 1, cy = p.m[1] ? 6 : 1, cz = p.m[2] ? 6 : 1;
+        double wx[6], wy[6], wz[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            wx[q] = lw[p.m[0] * 6 + q];
+            wy[q] = lw[p.m[1] * 6 + q];
+            wz[q] = lw[p.m[2] * 6 + q];
+        }
+        for (int f = 0; f < nf; ++f) {
+            const int64_t base = p.cbase + f * p.cfs;
+            double sz = 0.0;
+            for (int c = 0; c < cz; ++c) {
+                double sy = 0.0;
+                for (int b = 0; b < cy; ++b) {
+                    const int64_t row = base + (int64_t)c * p.cpz + (int64_t)b * p.cpy;
+                    double sx = 0.0;
+                    for (int a = 0; a < cx; ++a) {
+                        const int64_t q = row + a;
+                        const double T = Un[q] + W.w[0] * k0[q] + W.w[1] * k1[q] + W.w[2] * k2[q] +
+                                         W.w[3] * k3[q];
+                        sx += wx[a] * T;
+                    }
+                    sy += wy[b] * sx;
+                }
+                sz += wz[c] * sy;
+            }
+            U[p.dst + f * p.dfs] = sz;
+        }
+    }
+}
+
+__global__ __launch_bounds__(BLK) void restrict_kernel(const RestrictPt* __restrict__ e, int64_t n, int nf,
+                                                       const double* __restrict__ Uf, double* __restrict__ Uc)
+{
+    for (int64_t t = blockIdx.x * (int64_t)BLK + threadIdx.x; t < n; t += (int64_t)gridDim.x * BLK) {
+        const RestrictPt r = e[t];
+        for (int f = 0; f < nf; ++f) Uc[r.c + f * r.cfs] = Uf[r.f + f * r.ffs];
+    }
+}
+
+__global__ __launch_bounds__(BLK) void axpby_kernel(int64_t n, double a, const double* x,
+                                                    double b, const double* y, double* z)
+{
+    for (int64_t t = blockIdx.x * (int64_t)BLK + threadIdx.x; t < n; t += (int64_t)gridDim.x * BLK)
+        z[t] = a * x[t] + b * y[t];
+}
+
+}  // namespace
+
+hipError_t launch_fill(const GhostCopy* e, int64_t n, int nf, double* U, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    fill_kernel<<<grid_for(n), BLK, 0, s>>>(e, n, nf, U);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_adjoint(const GhostSource* src, int64_t n, const GhostImage* img, int nf, double* A,
+                               hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    fill_adjoint_kernel<<<grid_for(n), BLK, 0, s>>>(src, n, img, nf, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_prolong(const ProlongPt* e, int64_t n, int nf, int R, const double* lw, const double w[4],
+                          const double* Un, const double* k0, const double* k1, const double* k2,
+                          const double* k3, double* U, hipStream_t s)
+{
+    (void)R;
+    if (n <= 0) return hipSuccess;
+    BorW W;
+    for (int j = 0; j < 4; ++j) W.w[j] = w[j];
+    prolong_kernel<<<grid_for(n), BLK, 0, s>>>(e, n, nf, lw, W, Un, k0, k1, k2, k3, U);
+    return hipGetLastError();
+}
+
+hipError_t launch_restrict(const RestrictPt* e, int64_t n, int nf, const double* Uf, double* Uc, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    restrict_kernel<<<grid_for(n), BLK, 0, s>>>(e, n, nf, Uf, Uc);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpby(int64_t n, double a, const double* x, double b, const double* y, double* z,
+                        hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    axpby_kernel<<<grid_for(n), BLK, 0, s>>>(n, a, x, b, y, z);
+    return hipGetLastError();
+}
+
+}  // namespace mol

@@ -1,0 +1,159 @@
+// Deterministic reductions over the interior of a level (norms, the sphere
+// integral objective, the Gaussian initial data and its vector-Jacobian
+// product).  Order of summation is fixed: each thread walks a fixed set of
+// tiles, blocks reduce with a fixed tree in LDS, and one final block reduces
+// the per-block partials with the same tree.
+#include "molamr_int.h"
+
+namespace mol {
+
+namespace {
+
+constexpr int RB = 256;  // threads per reduction block (one tile of 32 x 4 x 2)
+constexpr int NQ = 5;    // reduced quantities per launch
+
+struct Red {
+    double v[NQ];
+};
+
+// q < 2, 3: sums; q == 2: max
+__device__ __forceinline__ void block_reduce(Red& r, double* sh, int nmaxq)
+{
+    const int t = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+    for (int q = 0; q < NQ; ++q) sh[q * RB + t] = r.v[q];
+    __syncthreads();
+    for (int w = RB / 2; w > 0; w >>= 1) {
+        if (t < w)
+            for (int q = 0; q < NQ; ++q) {
+                const double a = sh[q * RB + t], b = sh[q * RB + t + w];
+                sh[q * RB + t] = q == nmaxq ? fmax(a, b) : a + b;
+            }
+        __syncthreads();
+    }
+    for (int q = 0; q < NQ; ++q) r.v[q] = sh[q * RB];
+}
+
+__global__ __launch_bounds__(RB) void norms_kernel(const PatchDev* __restrict__ patches,
+                                                   const Tile* __restrict__ tiles, int ntiles,
+                                                   const double* __restrict__ U, int field, double shift,
+                                                   double r2max, double h, double x0, double y0, double z0,
+                                                   double* __restrict__ partial)
+{
+    __shared__ double sh[NQ * RB];
+    Red r;
+    for (int q = 0; q < NQ; ++q) r.v[q] = 0.0;
+    const double dV = h * h * h;
+    for (int tt = blockIdx.x; tt < ntiles; tt += gridDim.x) {
+        const Tile t = tiles[tt];
+        const PatchDev P = patches[t.patch];
+        const int i = t.o[0] + threadIdx.x, j = t.o[1] + threadIdx.y, k = t.o[2] + threadIdx.z;
+        if (i >= P.n[0] || j >= P.n[1] || k >= P.n[2]) continue;
+        const double v =
+            U[P.off + (int64_t)field * P.fs + (int64_t)(k + G) * P.pitch_z + (int64_t)(j + G) * P.pitch_y + i + G] -
+            shift;
+        if (!isfinite(v)) {
+            r.v[4] += 1.0;
+            continue;
+        }
+        r.v[0] += fabs(v) * dV;
+        r.v[1] += v * v * dV;
+        r.v[2] = fmax(r.v[2], fabs(v));
+        const double x = x0 + (P.lo[0] + i) * h, y = y0 + (P.lo[1] + j) * h, z = z0 + (P.lo[2] + k) * h;
+        if (x * x + y * y + z * z < r2max) r.v[3] += v * dV;
+    }
+    block_reduce(r, sh, 2);
+    if (threadIdx.x == 0 && threadIdx.y == 0 && threadIdx.z == 0)
+        for (int q = 0; q < NQ; ++q) partial[blockIdx.x * NQ + q] = r.v[q];
+}
+
+__global__ __launch_bounds__(RB) void final_kernel(const double* __restrict__ partial, int nb, int nmaxq,
+                                                   double* __restrict__ out)
+{
+    __shared__ double sh[NQ * RB];
+    Red r;
+    for (int q = 0; q < NQ; ++q) r.v[q] = 0.0;
+    const int t = threadIdx.x;
+    for (int b = t; b < nb; b += RB)
+        for (int q = 0; q < NQ; ++q) {
+            const double a = partial[b * NQ + q];
+            r.v[q] = q == nmaxq ? fmax(r.v[q], a) : r.v[q] + a;
+        }
+    block_reduce(r, sh, nmaxq);
+    if (t == 0)
+        for (int q = 0; q < NQ; ++q) out[q] = r.v[q];
+}
+
+// phi = A exp(-|d|^2 / w^2), d the minimum-image displacement from c
+__global__ __launch_bounds__(RB) void gaussian_kernel(const PatchDev* __restrict__ patches,
+                                                      const Tile* __restrict__ tiles, int ntiles, Red prm,
+                                                      double h, double x0, double y0, double z0, double Lx,
+                                                      double Ly, double Lz, double* __restrict__ U,
+                                                      const double* __restrict__ lam,
+                                                      double* __restrict__ partial)
+{
+    __shared__ double sh[NQ * RB];
+    Red r;
+    for (int q = 0; q < NQ; ++q) r.v[q] = 0.0;
+    const double A = prm.v[0], w = prm.v[1];
+    for (int tt = blockIdx.x; tt < ntiles; tt += gridDim.x) {
+        const Tile t = tiles[tt];
+        const PatchDev P = patches[t.patch];
+        const int i = t.o[0] + threadIdx.x, j = t.o[1] + threadIdx.y, k = t.o[2] + threadIdx.z;
+        if (i >= P.n[0] || j >= P.n[1] || k >= P.n[2]) continue;
+        double d[3] = {x0 + (P.lo[0] + i) * h - prm.v[2], y0 + (P.lo[1] + j) * h - prm.v[3],
+                       z0 + (P.lo[2] + k) * h - prm.v[4]};
+        const double L[3] = {Lx, Ly, Lz};
+        for (int a = 0; a < 3; ++a) d[a] -= L[a] * rint(d[a] / L[a]);
+        const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        const double E = exp(-r2 / (w * w));
+        const int64_t c = P.off + (int64_t)(k + G) * P.pitch_z + (int64_t)(j + G) * P.pitch_y + i + G;
+        if (U) {
+            U[c] = A * E;
+            U[c + P.fs] = 0.0;
+        }
+        if (lam) {
+            const double l = lam[c];
+            r.v[0] += l * E;
+            r.v[1] += l * A * E * 2.0 * r2 / (w * w * w);
+            for (int a = 0; a < 3; ++a) r.v[2 + a] += l * A * E * 2.0 * d[a] / (w * w);
+        }
+    }
+    if (!lam) return;
+    block_reduce(r, sh, -1);
+    if (threadIdx.x == 0 && threadIdx.y == 0 && threadIdx.z == 0)
+        for (int q = 0; q < NQ; ++q) partial[blockIdx.x * NQ + q] = r.v[q];
+}
+
+}  // namespace
+
+hipError_t launch_norms(const PatchDev* patches, const Tile* tiles, int ntiles, const int td[3], const double* U,
+                        int field, double shift, double radius, double h, const double xlo[3], double* partial,
+                        int nblocks, double* out, hipStream_t s)
+{
+    if (td[0] * td[1] * td[2] != RB) return hipErrorInvalidValue;
+    norms_kernel<<<nblocks, dim3(td[0], td[1], td[2]), 0, s>>>(patches, tiles, ntiles, U, field, shift,
+                                                               radius * radius, h, xlo[0], xlo[1], xlo[2],
+                                                               partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    final_kernel<<<1, RB, 0, s>>>(partial, nblocks, 2, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gaussian(const PatchDev* patches, const Tile* tiles, int ntiles, const int td[3],
+                           const double prm5[5], double h, const double xlo[3], const double per[3], double* U,
+                           const double* lam, double* partial, int nblocks, double* grad, hipStream_t s)
+{
+    if (td[0] * td[1] * td[2] != RB) return hipErrorInvalidValue;
+    Red prm;
+    for (int q = 0; q < NQ; ++q) prm.v[q] = prm5[q];
+    const int nb = lam ? nblocks : (ntiles < 1 ? 1 : ntiles);
+    gaussian_kernel<<<nb, dim3(td[0], td[1], td[2]), 0, s>>>(patches, tiles, ntiles, prm, h, xlo[0], xlo[1],
+                                                             xlo[2], per[0], per[1], per[2], U, lam, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !lam) return e;
+    final_kernel<<<1, RB, 0, s>>>(partial, nblocks, -1, grad);
+    return hipGetLastError();
+}
+
+}  // namespace mol

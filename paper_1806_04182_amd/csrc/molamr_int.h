@@ -1,0 +1,137 @@
+// Internal declarations shared by the host runtime and the HIP kernels of
+// libmolamr.  Not part of the public ABI (include/molamr.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "molamr.h"
+
+namespace mol {
+
+constexpr int G = MOL_GHOST;
+
+// One patch of a level, as the kernels see it.
+struct PatchDev {
+    int64_t off;   // start of the patch block in the level buffer (doubles)
+    int64_t fs;    // field stride (doubles)
+    int n[3];      // interior size
+    int pitch_y;   // (nx + 6)
+    int pitch_z;   // (nx + 6) * (ny + 6)
+    int lo[3];     // global index of the first interior point
+    int pad;
+};
+
+// A tile of a patch's interior (or of its ghosted box for the adjoint):
+// origin in interior coordinates (may be negative for ghosted-box tiles).
+struct Tile {
+    int patch;
+    int o[3];
+};
+
+// Same-level ghost copy: destination and source offsets of field 0 in the
+// level buffer and the field strides of both patches.
+struct GhostCopy {
+    int64_t dst;
+    int64_t src;
+    int64_t dfs;
+    int64_t sfs;
+};
+
+// Owner-gather adjoint of the ghost copies: one record per source point with
+// the range [beg, end) of its images in a list of (dst, dfs) pairs.
+struct GhostSource {
+    int64_t src;
+    int64_t sfs;
+    int32_t beg;
+    int32_t end;
+};
+struct GhostImage {
+    int64_t dst;
+    int64_t dfs;
+};
+
+// Coarse-fine ghost point: destination (fine level), base of its parent
+// stencil (parent level, field 0, lowest corner), field strides, parent
+// pitches and the fine index modulo R per axis.
+struct ProlongPt {
+    int64_t dst;
+    int64_t cbase;
+    int64_t dfs;
+    int64_t cfs;
+    int32_t cpy;
+    int32_t cpz;
+    int8_t m[3];
+    int8_t pad[5];
+};
+
+// Injection: fine offset, coarse offset (field 0) and field strides.
+struct RestrictPt {
+    int64_t f;
+    int64_t c;
+    int64_t ffs;
+    int64_t cfs;
+};
+
+struct SysParams {
+    int system;
+    int nf;
+    int upwind;
+    double h;  // grid spacing of the level (isotropic)
+    double sigma, gamma_ad, weno_eps, weno_q, kappa_z, kappa_c, bm_f0, bm_f1, gd_g, gd_eta;
+};
+
+// What the fused stage kernels do after evaluating k = dt * rhs.
+enum StageMode { ST_RHS = 0, ST_RK4 = 1, ST_SSP3 = 2 };
+
+struct StageArgs {
+    const PatchDev* patches;
+    const Tile* tiles;
+    int ntiles;
+    int mode;
+    int stage;
+    double dt;
+    const double* Un;
+    const double* Us;
+    double* acc;
+    double* out;
+    double* kst;
+};
+
+// kernel launchers (each returns hipGetLastError() of its launch)
+hipError_t launch_stage_wave(const SysParams& sp, const StageArgs& a, const int tdim[3], hipStream_t s);
+hipError_t launch_stage_mhd(const SysParams& sp, const StageArgs& a, const int tdim[3], hipStream_t s);
+hipError_t launch_stage_ccz4(const SysParams& sp, const StageArgs& a, const int tdim[3], hipStream_t s);
+inline hipError_t launch_stage(const SysParams& sp, const StageArgs& a, const int tdim[3], hipStream_t s)
+{
+    switch (sp.system) {
+    case MOL_WAVE: return launch_stage_wave(sp, a, tdim, s);
+    case MOL_MHD: return launch_stage_mhd(sp, a, tdim, s);
+    default: return launch_stage_ccz4(sp, a, tdim, s);
+    }
+}
+hipError_t launch_fill(const GhostCopy* e, int64_t n, int nf, double* U, hipStream_t s);
+hipError_t launch_fill_adjoint(const GhostSource* src, int64_t nsrc, const GhostImage* img,
+                               int nf, double* A, hipStream_t s);
+hipError_t launch_prolong(const ProlongPt* e, int64_t n, int nf, int R, const double* lw,
+                          const double w[4], const double* Un, const double* k0,
+                          const double* k1, const double* k2, const double* k3, double* U,
+                          hipStream_t s);
+hipError_t launch_restrict(const RestrictPt* e, int64_t n, int nf, const double* Uf, double* Uc,
+                           hipStream_t s);
+hipError_t launch_wave_adjoint(const SysParams& sp, const PatchDev* patches, const Tile* tiles,
+                               int ntiles, const int tdim[3], const double* lam, double* lamU,
+                               hipStream_t s);
+hipError_t launch_axpby(int64_t n, double a, const double* x, double b, const double* y,
+                        double* z, hipStream_t s);
+hipError_t launch_norms(const PatchDev* patches, const Tile* tiles, int ntiles, const int tdim[3],
+                        const double* U, int field, double shift, double radius, double h,
+                        const double xlo[3], double* partial, int nblocks, double* out,
+                        hipStream_t s);
+hipError_t launch_gaussian(const PatchDev* patches, const Tile* tiles, int ntiles, const int tdim[3],
+                           const double prm[5], double h, const double xlo[3], const double per[3],
+                           double* U, const double* lam, double* partial, int nblocks, double* grad,
+                           hipStream_t s);
+
+}  // namespace mol

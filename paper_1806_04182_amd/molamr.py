@@ -1,0 +1,310 @@
+"""Python binding of libmolamr (include/molamr.h).
+
+Argument marshalling only: every operation runs in the HIP library.  Device
+buffers are torch float64 tensors on the GPU (passed by pointer), streams are
+torch streams.  The library must be built (``paper_1806_04182_amd.build``);
+importing this module on a machine without it raises instead of falling back.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmolamr.so")
+
+MOL_WAVE, MOL_MHD, MOL_CCZ4 = 0, 1, 2
+MOL_RK4, MOL_SSPRK3 = 0, 1
+MOL_BATCHED, MOL_PLAIN = 0, 1
+GHOST = 3
+NFIELDS = {MOL_WAVE: 2, MOL_MHD: 8, MOL_CCZ4: 25}
+
+
+class MolError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"molamr error {code}: {msg}")
+        self.code = code
+
+
+class _Hier(ctypes.Structure):
+    _fields_ = [("nlevels", ctypes.c_int), ("N0", ctypes.c_int * 3), ("xlo", ctypes.c_double * 3),
+                ("dx0", ctypes.c_double), ("ratio", ctypes.POINTER(ctypes.c_int)),
+                ("npatch", ctypes.POINTER(ctypes.c_int)), ("boxes", ctypes.POINTER(ctypes.c_int))]
+
+
+class _Sys(ctypes.Structure):
+    _fields_ = [("system", ctypes.c_int), ("upwind", ctypes.c_int)] + [
+        (n, ctypes.c_double) for n in ("sigma", "gamma_ad", "weno_eps", "weno_q", "kappa_z", "kappa_c",
+                                       "bm_f0", "bm_f1", "gd_g", "gd_eta")]
+
+
+class _LevelState(ctypes.Structure):
+    _fields_ = [("U", ctypes.c_void_p), ("S0", ctypes.c_void_p), ("S1", ctypes.c_void_p),
+                ("acc", ctypes.c_void_p), ("k", ctypes.c_void_p * 4)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmolamr.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_1806_04182_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        dp = ctypes.POINTER(ctypes.c_double)
+        sig = {
+            "mol_create_patchset": ([ctypes.POINTER(_Hier), ctypes.POINTER(_Sys), ctypes.POINTER(vp)], i),
+            "mol_destroy_patchset": ([vp], None),
+            "mol_last_error": ([], ctypes.c_char_p),
+            "mol_nfields": ([vp], i),
+            "mol_level_layout": ([vp, i, i64p, i64p, i32p, i64p], i),
+            "mol_level_npatch": ([vp, i], i),
+            "mol_fill_ghosts": ([vp, i, vp, i, vp], i),
+            "mol_rhs": ([vp, i, vp, vp, vp], i),
+            "mol_rk_stage": ([vp, i, i, i, d, vp, vp, vp, vp, vp, vp], i),
+            "mol_prolong": ([vp, i, i, i, vp, ctypes.POINTER(vp), vp, vp], i),
+            "mol_bor_weights": ([i, i, i, dp], i),
+            "mol_restrict": ([vp, i, vp, vp, vp], i),
+            "mol_rhs_adjoint": ([vp, i, vp, vp, vp, vp], i),
+            "mol_fill_ghosts_adjoint": ([vp, i, vp, vp], i),
+            "mol_rk4_adjoint_step": ([vp, i, d, vp, vp, vp, vp, vp], i),
+            "mol_norms": ([vp, i, vp, i, d, d, vp, vp], i),
+            "mol_wave_gaussian": ([vp, i, dp, vp, vp], i),
+            "mol_wave_gaussian_vjp": ([vp, i, dp, vp, vp, vp], i),
+            "mol_advance": ([vp, ctypes.POINTER(_LevelState), d, i, vp], i),
+            "mol_graph_create": ([vp, ctypes.POINTER(_LevelState), d, ctypes.POINTER(vp)], i),
+            "mol_graph_launch": ([vp, vp], i),
+            "mol_graph_destroy": ([vp], None),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def exported_symbols() -> list[str]:
+    return [n for n in dir(lib()) if n.startswith("mol_")]
+
+
+def _check(rc: int) -> None:
+    if rc != 0:
+        raise MolError(rc, lib().mol_last_error().decode())
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return stream if isinstance(stream, int) else stream.cuda_stream
+
+
+@dataclass
+class System:
+    system: int
+    sigma: float = 0.1
+    gamma_ad: float = 5.0 / 3.0
+    weno_eps: float = -1.0
+    weno_q: float = 2.0
+    kappa_z: float = 0.1
+    kappa_c: float = 0.1
+    bm_f0: float = 0.0
+    bm_f1: float = 2.0
+    gd_g: float = 0.75
+    gd_eta: float = 2.0
+    upwind: int = 1
+
+    def _c(self) -> _Sys:
+        return _Sys(self.system, int(self.upwind), self.sigma, self.gamma_ad, self.weno_eps, self.weno_q,
+                    self.kappa_z, self.kappa_c, self.bm_f0, self.bm_f1, self.gd_g, self.gd_eta)
+
+
+@dataclass
+class Hierarchy:
+    N0: tuple
+    xlo: tuple
+    dx0: float
+    levels: list  # [(ratio, [((lo), (hi)), ...]), ...]
+
+    def _c(self):
+        ratio = (ctypes.c_int * len(self.levels))(*[lv[0] for lv in self.levels])
+        npatch = (ctypes.c_int * len(self.levels))(*[len(lv[1]) for lv in self.levels])
+        flat = [v for _, boxes in self.levels for lo, hi in boxes for v in (*lo, *hi)]
+        boxes = (ctypes.c_int * len(flat))(*flat)
+        h = _Hier(len(self.levels), (ctypes.c_int * 3)(*self.N0), (ctypes.c_double * 3)(*self.xlo),
+                  self.dx0, ratio, npatch, boxes)
+        return h, (ratio, npatch, boxes)
+
+
+class Patchset:
+    """A hierarchy of patches with its device schedules (mol_create_patchset)."""
+
+    def __init__(self, hier: Hierarchy, system: System):
+        h, keep = hier._c()
+        s = system._c()
+        out = ctypes.c_void_p()
+        _check(lib().mol_create_patchset(ctypes.byref(h), ctypes.byref(s), ctypes.byref(out)))
+        self._h = out
+        self.hier = hier
+        self.system = system
+        self.nf = lib().mol_nfields(self._h)
+        self.nlev = len(hier.levels)
+        self.layouts = [self.level_layout(l) for l in range(self.nlev)]
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().mol_destroy_patchset(self._h)
+            self._h = None
+
+    # ---- layout -------------------------------------------------------
+    def level_layout(self, level: int):
+        np_ = lib().mol_level_npatch(self._h, level)
+        if np_ < 0:
+            _check(np_)
+        n = ctypes.c_int64()
+        offs = (ctypes.c_int64 * np_)()
+        dims = (ctypes.c_int32 * (3 * np_))()
+        fss = (ctypes.c_int64 * np_)()
+        _check(lib().mol_level_layout(self._h, level, ctypes.byref(n), offs, dims, fss))
+        return dict(nelems=n.value, offsets=list(offs), dims=[tuple(dims[3 * p:3 * p + 3]) for p in range(np_)],
+                    fstrides=list(fss))
+
+    def alloc(self, level: int, device="cuda"):
+        import torch
+        return torch.zeros(self.layouts[level]["nelems"], dtype=torch.float64, device=device)
+
+    def pack(self, level: int, patches: Sequence[np.ndarray]) -> np.ndarray:
+        """Patch arrays (nf, nz+6, ny+6, nx+6) -> one host level buffer."""
+        L = self.layouts[level]
+        buf = np.zeros(L["nelems"])
+        for p, a in enumerate(patches):
+            nx, ny, nz = L["dims"][p]
+            vol = (nx + 6) * (ny + 6) * (nz + 6)
+            nf = a.shape[0]
+            blk = buf[L["offsets"][p]:L["offsets"][p] + nf * L["fstrides"][p]].reshape(nf, L["fstrides"][p])
+            blk[:, :vol] = a.reshape(nf, vol)
+        return buf
+
+    def unpack(self, level: int, buf, nf: int | None = None) -> list[np.ndarray]:
+        if not isinstance(buf, np.ndarray):
+            buf = buf.detach().cpu().numpy()
+        L = self.layouts[level]
+        nf = nf or self.nf
+        out = []
+        for p in range(len(L["dims"])):
+            nx, ny, nz = L["dims"][p]
+            vol = (nx + 6) * (ny + 6) * (nz + 6)
+            blk = buf[L["offsets"][p]:L["offsets"][p] + nf * L["fstrides"][p]].reshape(nf, L["fstrides"][p])
+            out.append(blk[:, :vol].reshape(nf, nz + 6, ny + 6, nx + 6).copy())
+        return out
+
+    # ---- operations (same names as the C ABI) ---------------------------
+    def fill_ghosts(self, level, U, nf=0, stream=None):
+        _check(lib().mol_fill_ghosts(self._h, level, _ptr(U), nf, _stream(stream)))
+
+    def rhs(self, level, U, dUdt, stream=None):
+        _check(lib().mol_rhs(self._h, level, _ptr(U), _ptr(dUdt), _stream(stream)))
+
+    def rk_stage(self, level, scheme, stage, dt, Un, Us, Acc, Uout, k_store=None, stream=None):
+        _check(lib().mol_rk_stage(self._h, level, scheme, stage, dt, _ptr(Un), _ptr(Us), _ptr(Acc),
+                                  _ptr(Uout), _ptr(k_store), _stream(stream)))
+
+    def prolong(self, fine_level, r, stage, Un_c, k_c, U_f, stream=None):
+        arr = (ctypes.c_void_p * 4)(*[_ptr(k) for k in k_c])
+        _check(lib().mol_prolong(self._h, fine_level, r, stage, _ptr(Un_c), arr, _ptr(U_f), _stream(stream)))
+
+    def restrict(self, fine_level, U_f, U_c, stream=None):
+        _check(lib().mol_restrict(self._h, fine_level, _ptr(U_f), _ptr(U_c), _stream(stream)))
+
+    def rhs_adjoint(self, level, U, lam, lamU, stream=None):
+        _check(lib().mol_rhs_adjoint(self._h, level, _ptr(U), _ptr(lam), _ptr(lamU), _stream(stream)))
+
+    def fill_ghosts_adjoint(self, level, lamU, stream=None):
+        _check(lib().mol_fill_ghosts_adjoint(self._h, level, _ptr(lamU), _stream(stream)))
+
+    def rk4_adjoint_step(self, level, dt, lam, w0, w1, w2, stream=None):
+        _check(lib().mol_rk4_adjoint_step(self._h, level, dt, _ptr(lam), _ptr(w0), _ptr(w1), _ptr(w2),
+                                          _stream(stream)))
+
+    def norms(self, level, U, field, shift, radius, out_dev, stream=None):
+        _check(lib().mol_norms(self._h, level, _ptr(U), field, shift, radius, _ptr(out_dev), _stream(stream)))
+
+    def wave_gaussian(self, level, prm, U, stream=None):
+        p = (ctypes.c_double * 5)(*prm)
+        _check(lib().mol_wave_gaussian(self._h, level, p, _ptr(U), _stream(stream)))
+
+    def wave_gaussian_vjp(self, level, prm, lam, grad_dev, stream=None):
+        p = (ctypes.c_double * 5)(*prm)
+        _check(lib().mol_wave_gaussian_vjp(self._h, level, p, _ptr(lam), _ptr(grad_dev), _stream(stream)))
+
+    def _states(self, states):
+        arr = (_LevelState * self.nlev)()
+        for l, st in enumerate(states):
+            arr[l].U = _ptr(st["U"])
+            arr[l].S0 = _ptr(st["S0"])
+            arr[l].S1 = _ptr(st["S1"])
+            arr[l].acc = _ptr(st["acc"])
+            ks = st.get("k") or [None] * 4
+            for j in range(4):
+                arr[l].k[j] = _ptr(ks[j])
+        return arr
+
+    def advance(self, states, dt0, mode=MOL_BATCHED, stream=None):
+        _check(lib().mol_advance(self._h, self._states(states), dt0, mode, _stream(stream)))
+
+    def graph_create(self, states, dt0):
+        g = ctypes.c_void_p()
+        _check(lib().mol_graph_create(self._h, self._states(states), dt0, ctypes.byref(g)))
+        return Graph(g)
+
+    def alloc_states(self, device="cuda"):
+        """Device buffers for mol_advance: U, S0, S1, acc and (when a finer
+        level exists) k[4] per level."""
+        out = []
+        for l in range(self.nlev):
+            st = {n: self.alloc(l, device) for n in ("U", "S0", "S1", "acc")}
+            st["k"] = [self.alloc(l, device) for _ in range(4)] if l + 1 < self.nlev else None
+            out.append(st)
+        return out
+
+
+class Graph:
+    def __init__(self, handle):
+        self._g = handle
+
+    def launch(self, stream=None):
+        _check(lib().mol_graph_launch(self._g, _stream(stream)))
+
+    def __del__(self):
+        if getattr(self, "_g", None):
+            lib().mol_graph_destroy(self._g)
+            self._g = None
+
+
+def bor_weights(R: int, r: int, stage: int) -> np.ndarray:
+    w = (ctypes.c_double * 4)()
+    _check(lib().mol_bor_weights(R, r, stage, w))
+    return np.array(list(w))
+
+
+def single_patch(n, xlo, dx) -> Hierarchy:
+    """One periodic patch covering an n[0] x n[1] x n[2] domain."""
+    return Hierarchy(tuple(n), tuple(xlo), dx, [(1, [((0, 0, 0), tuple(x - 1 for x in n))])])

@@ -1,0 +1,70 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point declared in include/molamr.h, validates arguments before
+touching the device, and its BOR weights reproduce the oracle's App. D steps."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1806_04182_amd import molamr as M
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "molamr.h")).read()
+    return sorted(set(re.findall(r"\b(mol_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = M.lib()
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def _hier(boxes0, N0=(8, 8, 8)):
+    return M.Hierarchy(N0, (0, 0, 0), 0.125, [(1, boxes0)])
+
+
+@pytest.mark.parametrize("boxes, msg", [
+    ([((0, 0, 0), (7, 7, 6))], "tile the periodic domain"),
+    ([((0, 0, 0), (7, 7, 7)), ((0, 0, 0), (1, 1, 1))], "overlaps"),
+    ([((0, 0, 0), (8, 7, 7))], "outside"),
+])
+def test_create_rejects_bad_hierarchies(boxes, msg):
+    with pytest.raises(M.MolError) as e:
+        M.Patchset(_hier(boxes), M.System(M.MOL_WAVE))
+    assert e.value.code == -1 and msg in str(e.value)
+
+
+def test_create_rejects_bad_ratio():
+    h = M.Hierarchy((8, 8, 8), (0, 0, 0), 0.125, [(1, [((0, 0, 0), (7, 7, 7))]), (5, [((8, 8, 8), (15, 15, 15))])])
+    with pytest.raises(M.MolError) as e:
+        M.Patchset(h, M.System(M.MOL_WAVE))
+    assert "ratio" in str(e.value)
+
+
+@pytest.mark.parametrize("R", [1, 2, 3, 4])
+def test_bor_weights_match_oracle_steps(R):
+    """The library's closed-form weights w_j(R, r, s) against the oracle's
+    literal App. D steps applied to unit increments."""
+    rng = np.random.default_rng(R)
+    Un = rng.standard_normal(7)
+    k = [rng.standard_normal(7) for _ in range(4)]
+    for r in range(R):
+        for s in range(1, 5):
+            w = M.bor_weights(R, r, s)
+            ref = O.bor_rk4(R, r, s, 0.37, Un, k)
+            got = Un + sum(w[j] * k[j] for j in range(4))
+            assert np.max(np.abs(got - ref)) < 1e-14
+
+
+def test_bor_weights_table_ratio2():
+    # fine step 0 of a ratio-2 step, stage 3: (3/32, 1/8, 1/16, -1/32)
+    assert np.allclose(M.bor_weights(2, 0, 3), [3 / 32, 1 / 8, 1 / 16, -1 / 32], atol=1e-16)
+    with pytest.raises(M.MolError):
+        M.bor_weights(2, 2, 1)
