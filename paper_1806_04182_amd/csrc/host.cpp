@@ -221,7 +221,7 @@ void default_tile(int system, int td[3])
     switch (system) {
     case MOL_WAVE: td[0] = 32; td[1] = 4; td[2] = 2; break;
     case MOL_MHD: td[0] = 16; td[1] = 4; td[2] = 4; break;
-    default: td[0] = 16; td[1] = 4; td[2] = 2; break;
+    default: td[0] = 8; td[1] = 8; td[2] = 4; break;
     }
 }
 

@@ -3,12 +3,22 @@
 // printed below them), Bona-Masso slicing and Gamma-driver shift, with
 // 4th-order centred derivatives, lop-sided advection and Kreiss-Oliger
 // dissipation on every field (Sec. II.B.1), fused with the Runge-Kutta stage
-// update.  One thread evaluates one grid point.
+// update.
 //
 // Conventions: symmetric pairs are packed xx xy xz yy yz zz; Z^i =
 // chi (Ghat^i - Gt^i)/2; R + 2 nabla Z and nabla^i nabla_i alpha are traces
 // with the physical inverse metric chi gt^{ij}; [.]^TF is taken with gt;
 // ln det gt = log1p(det(I + h) - 1) expanded in h = gt - I.
+//
+// Kernel organisation (gfx950): one workgroup of 256 threads owns a tile of
+// TX x TY x TZ points.  The 25 fields are streamed through LDS one at a time
+// (tile plus a 3-point halo, double buffered: the next field's global loads
+// are in flight while the current one is differentiated).  Each field's
+// derivatives are consumed as soon as they arrive (Christoffel symbols after
+// the six metric components, Ricci terms after Ghat and chi, the lapse
+// Hessian after alpha, ...), so only the partial sums stay live.  Advection
+// and dissipation of every field are parked in LDS until the algebra that
+// needs all fields is done; then the RK stage update writes the results.
 #include "k_common.h"
 
 namespace mol {
@@ -28,33 +38,67 @@ struct CczConst {
     double i144h2;  // 1 / (144 h^2)
     double ko;      // sigma / (64 h)
     double kz, kc, f0, f1, g, eta;
-    int upwind;
 };
 
-template <bool UPWIND>
-__global__ __launch_bounds__(128) void ccz4_stage_kernel(StageArgs a, CczConst C)
-{
-    PointRef pr;
-    int pi, pj, pk, pp;
-    if (!tile_point(a, blockIdx.x, pr, pi, pj, pk, pp)) return;
-    const double* __restrict__ u = a.Us + pr.c;
-    const int64_t fs = pr.fs;
-    const int s[3] = {1, pr.sy, pr.sz};
-#define FLD(f) (u + (int64_t)(f) * fs)
+// order in which the fields pass through LDS
+__device__ constexpr int ORDER[NF] = {GT + 0, GT + 1, GT + 2, GT + 3, GT + 4, GT + 5, GH + 0, GH + 1, GH + 2,
+                                      CHI,    ALP,    BETA + 0, BETA + 1, BETA + 2, KH, TH,
+                                      AT + 0, AT + 1, AT + 2, AT + 3, AT + 4, AT + 5, BB + 0, BB + 1, BB + 2};
 
-    // ---- point values and the inverse conformal metric ----
-    const double chi = FLD(CHI)[0], Kh = FLD(KH)[0], Th = FLD(TH)[0], alp = FLD(ALP)[0];
-    double g[6], A[6], Gh[3], be[3], Bv[3];
+template <int TX, int TY, int TZ, bool UPWIND>
+__global__ __launch_bounds__(TX * TY * TZ) void ccz4_stage_kernel(StageArgs a, CczConst C)
+{
+    constexpr int HX = TX + 2 * G, HY = TY + 2 * G, HZ = TZ + 2 * G;
+    constexpr int HV = HX * HY * HZ, NT = TX * TY * TZ, NR = (HV + NT - 1) / NT;
+    __shared__ double buf[2][HV];
+    __shared__ double akx[NF][NT];  // advection + dissipation of every field
+
+    const Tile tile = a.tiles[blockIdx.x];
+    const PatchDev P = a.patches[tile.patch];
+    const int tx = threadIdx.x, ty = threadIdx.y, tz = threadIdx.z;
+    const int tid = tx + TX * (ty + TY * tz);
+    const bool valid = tile.o[0] + tx < P.n[0] && tile.o[1] + ty < P.n[1] && tile.o[2] + tz < P.n[2];
+    // halo tile origin = tile origin - 3 in interior coordinates = tile origin in ghosted coordinates
+    const int64_t hbase = P.off + (int64_t)tile.o[2] * P.pitch_z + (int64_t)tile.o[1] * P.pitch_y + tile.o[0];
+    const int64_t c = hbase + (int64_t)(tz + G) * P.pitch_z + (int64_t)(ty + G) * P.pitch_y + (tx + G);
+    const int64_t fs = P.fs;
+
+    // this thread's share of the halo-tile loads: offsets and in-box flags
+    int goff[NR];
+    bool gok[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int e = tid + r * NT;
+        const int hx = e % HX, hy = (e / HX) % HY, hz = e / (HX * HY);
+        gok[r] = e < HV && tile.o[0] + hx < P.n[0] + 2 * G && tile.o[1] + hy < P.n[1] + 2 * G &&
+                 tile.o[2] + hz < P.n[2] + 2 * G;
+        goff[r] = hz * P.pitch_z + hy * P.pitch_y + hx;
+    }
+    double stg[NR];
+    auto gload = [&](int f) {
+        const double* src = a.Us + hbase + (int64_t)f * fs;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) stg[r] = gok[r] ? src[goff[r]] : 0.0;
+    };
+    auto lstore = [&](int b) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+            if (tid + r * NT < HV) buf[b][tid + r * NT] = stg[r];
+    };
+
+    // ---- point values and the inverse conformal metric (global loads) ----
+    const double* __restrict__ u = a.Us + c;
+    const double chi = u[CHI * fs], Kh = u[KH * fs], Th = u[TH * fs], alp = u[ALP * fs];
+    double g[6], A[6], Gh[3], be[3];
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
-        g[q] = FLD(GT + q)[0];
-        A[q] = FLD(AT + q)[0];
+        g[q] = u[(GT + q) * fs];
+        A[q] = u[(AT + q) * fs];
     }
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        Gh[i] = FLD(GH + i)[0];
-        be[i] = FLD(BETA + i)[0];
-        Bv[i] = FLD(BB + i)[0];
+        Gh[i] = u[(GH + i) * fs];
+        be[i] = u[(BETA + i) * fs];
     }
     double gu[6], lndet;
     {
@@ -72,171 +116,7 @@ __global__ __launch_bounds__(128) void ccz4_stage_kernel(StageArgs a, CczConst C
         gu[4] = (g[2] * g[1] - g[0] * g[4]) * idet;
         gu[5] = (g[0] * g[3] - g[1] * g[1]) * idet;
     }
-
-    // ---- first derivatives ----
-    double dchi[3], dalp[3], dK[3], dTh[3], db[3][3], dG[3][3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        dchi[k] = C.i12h * fd1(FLD(CHI), s[k]);
-        dalp[k] = C.i12h * fd1(FLD(ALP), s[k]);
-        dK[k] = C.i12h * fd1(FLD(KH), s[k]);
-        dTh[k] = C.i12h * fd1(FLD(TH), s[k]);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            db[k][i] = C.i12h * fd1(FLD(BETA + i), s[k]);
-            dG[k][i] = C.i12h * fd1(FLD(GH + i), s[k]);
-        }
-    }
-    // Christoffel symbols of gt: Gl[i][jk] = (d_j g_ik + d_k g_ij - d_i g_jk)/2,
-    // Gu[i][jk] = gt^{il} Gl[l][jk], contracted Gc^i = gt^{jk} Gu[i][jk]
-    double Gl[3][6], Gu[3][6], Gc[3];
-    {
-        double dg[3][6];
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-            for (int q = 0; q < 6; ++q) dg[k][q] = C.i12h * fd1(FLD(GT + q), s[k]);
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j)
-#pragma unroll
-                for (int k = j; k < 3; ++k)
-                    Gl[i][SI(j, k)] = 0.5 * (dg[j][SI(i, k)] + dg[k][SI(i, j)] - dg[i][SI(j, k)]);
-    }
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int q = 0; q < 6; ++q)
-            Gu[i][q] = gu[SI(i, 0)] * Gl[0][q] + gu[SI(i, 1)] * Gl[1][q] + gu[SI(i, 2)] * Gl[2][q];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-        Gc[i] = gu[0] * Gu[i][0] + gu[3] * Gu[i][3] + gu[5] * Gu[i][5] +
-                2.0 * (gu[1] * Gu[i][1] + gu[2] * Gu[i][2] + gu[4] * Gu[i][4]);
-    double Z[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) Z[i] = 0.5 * chi * (Gh[i] - Gc[i]);
-
-    // ---- second derivatives, contracted as soon as possible ----
-    double ddchi[6], ddalp[6], lapg[6], gddb[3], gdiv[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-        for (int l = k; l < 3; ++l) {
-            if (k == l) {
-                ddchi[SI(k, k)] = C.i12h2 * fd2(FLD(CHI), s[k]);
-                ddalp[SI(k, k)] = C.i12h2 * fd2(FLD(ALP), s[k]);
-            } else {
-                ddchi[SI(k, l)] = C.i144h2 * fmix(FLD(CHI), s[k], s[l]);
-                ddalp[SI(k, l)] = C.i144h2 * fmix(FLD(ALP), s[k], s[l]);
-            }
-        }
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        const double* w = FLD(GT + q);
-        double acc = 0.0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-            for (int l = k; l < 3; ++l) {
-                const double dd = k == l ? C.i12h2 * fd2(w, s[k]) : C.i144h2 * fmix(w, s[k], s[l]);
-                acc += (k == l ? 1.0 : 2.0) * gu[SI(k, l)] * dd;
-            }
-        lapg[q] = acc;
-    }
-#pragma unroll
-    for (int i = 0; i < 3; ++i) gdiv[i] = 0.0;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        const double* w = FLD(BETA + i);
-        double acc = 0.0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-            for (int l = k; l < 3; ++l) {
-                const double dd = k == l ? C.i12h2 * fd2(w, s[k]) : C.i144h2 * fmix(w, s[k], s[l]);
-                acc += (k == l ? 1.0 : 2.0) * gu[SI(k, l)] * dd;
-                // sum_k d_j d_k beta^k: beta^i contributes d_j d_i beta^i to row j
-                if (k == i) gdiv[l] += dd;
-                if (l == i && k != l) gdiv[k] += dd;
-            }
-        gddb[i] = acc;
-    }
-
-    // ---- Ricci tensor pieces ----
-    double Ric[6];
-    {
-        // H[k][i][n] = sum_m gt^{nm} Gt^k_{mi}
-        double H[3][3][3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int n = 0; n < 3; ++n)
-                    H[k][i][n] = gu[SI(n, 0)] * Gu[k][SI(0, i)] + gu[SI(n, 1)] * Gu[k][SI(1, i)] +
-                                 gu[SI(n, 2)] * Gu[k][SI(2, i)];
-        double trdd = 0.0, Ghd = 0.0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            Ghd += Gh[k] * dchi[k];
-#pragma unroll
-            for (int m = 0; m < 3; ++m)
-                trdd += gu[SI(k, m)] * (ddchi[SI(k, m)] - 1.5 / chi * dchi[k] * dchi[m]);
-        }
-        const double ic = 1.0 / chi;
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = i; j < 3; ++j) {
-                const int q = SI(i, j);
-                // Rhat_ij
-                double r = -0.5 * lapg[q];
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    r += 0.5 * (g[SI(k, i)] * dG[j][k] + g[SI(k, j)] * dG[i][k]);
-                    r += Gh[k] * 0.5 * (Gl[i][SI(j, k)] + Gl[j][SI(i, k)]);
-#pragma unroll
-                    for (int n = 0; n < 3; ++n)
-                        r += H[k][i][n] * Gl[j][SI(k, n)] + H[k][j][n] * Gl[i][SI(k, n)] +
-                             H[k][i][n] * Gl[k][SI(n, j)];
-                }
-                // Rhat^chi_ij
-                double Gd = 0.0, zs = 0.0;
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    Gd += Gu[k][q] * dchi[k];
-                    zs += Z[k] * 0.5 * (g[SI(k, i)] * dchi[j] + g[SI(k, j)] * dchi[i]);
-                }
-                r += 0.5 * ic * ddchi[q] - 0.5 * ic * Gd - 0.25 * ic * ic * dchi[i] * dchi[j] +
-                     2.0 * ic * ic * zs + 0.5 * ic * g[q] * (trdd - Ghd);
-                Ric[q] = r;
-            }
-    }
-    // nabla_i nabla_j alpha
-    double DDa[6];
-    {
-        double cr = 0.0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-            for (int m = 0; m < 3; ++m) cr += gu[SI(k, m)] * dalp[k] * dchi[m];
-        const double hic = 0.5 / chi;
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = i; j < 3; ++j) {
-                const int q = SI(i, j);
-                DDa[q] = ddalp[q] - (Gu[0][q] * dalp[0] + Gu[1][q] * dalp[1] + Gu[2][q] * dalp[2]) +
-                         hic * (dalp[i] * dchi[j] + dalp[j] * dchi[i] - g[q] * cr);
-            }
-    }
-    auto tr = [&](const double* T) {  // gt^{ij} T_ij
-        return gu[0] * T[0] + gu[3] * T[3] + gu[5] * T[5] + 2.0 * (gu[1] * T[1] + gu[2] * T[2] + gu[4] * T[4]);
-    };
-    const double trRic = chi * tr(Ric);
-    const double lapa = chi * tr(DDa);
-    // raised At
+    // raised traceless curvature At^i_j and At^{ij}
     double Am[3][3], Au[6];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -248,6 +128,209 @@ __global__ __launch_bounds__(128) void ccz4_stage_kernel(StageArgs a, CczConst C
 #pragma unroll
         for (int j = i; j < 3; ++j)
             Au[SI(i, j)] = Am[i][0] * gu[SI(0, j)] + Am[i][1] * gu[SI(1, j)] + Am[i][2] * gu[SI(2, j)];
+
+    // ---- quantities built while the fields stream through LDS ----
+    double dg[3][6], lapg[6];           // metric derivatives (until the Christoffels are formed)
+    double Gu[3][6], Z[3], GtAu[3];     // Gt^i_jk, Z^i, Gt^i_jk At^jk
+    double Ric[6];                      // R_ij + 2 nabla_(i Z_j), accumulated
+    double dchi[3], dalp[3], DDa[6];    // chi and alpha gradients, nabla_i nabla_j alpha
+    double db[3][3], gddb[3], gdiv[3];  // d_k beta^i, gt^jk d_j d_k beta^i, d_i (d_k beta^k)
+    double rG[3];                       // Ghat^i terms with d Khat and d Theta
+    const int S[3] = {1, HX, HX * HY};
+
+    gload(ORDER[0]);
+    lstore(0);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NF; ++q) {
+        const int f = ORDER[q];
+        if (q + 1 < NF) gload(ORDER[q + 1]);
+        if (valid) {
+            const double* t = &buf[q & 1][(tz + G) * HX * HY + (ty + G) * HX + tx + G];
+            // advection beta^k d_k and KO dissipation of every field
+            double adv = 0.0, ko = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                adv += be[k] * (UPWIND ? fadv(t, S[k], be[k]) : fd1(t, S[k]));
+                ko += fko(t, S[k]);
+            }
+            akx[f][tid] = C.i12h * adv + C.ko * ko;
+
+            auto d1 = [&](int k) { return C.i12h * fd1(t, S[k]); };
+            auto dd = [&](int k, int l) {
+                return k == l ? C.i12h2 * fd2(t, S[k]) : C.i144h2 * fmix(t, S[k], S[l]);
+            };
+            // gt^{kl} d_k d_l of the field in LDS
+            auto trdd = [&]() {
+                double s = 0.0;
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+#pragma unroll
+                    for (int l = k; l < 3; ++l) s += (k == l ? 1.0 : 2.0) * gu[SI(k, l)] * dd(k, l);
+                return s;
+            };
+
+            if (f >= GT && f < GT + 6) {
+                const int qq = f - GT;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) dg[k][qq] = d1(k);
+                lapg[qq] = trdd();
+                if (qq == 5) {
+                    // Christoffels: Gl[i][jk] = (d_j g_ik + d_k g_ij - d_i g_jk)/2, Gu = gt^-1 Gl
+                    double Gl[3][6];
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+#pragma unroll
+                        for (int j = 0; j < 3; ++j)
+#pragma unroll
+                            for (int k = j; k < 3; ++k)
+                                Gl[i][SI(j, k)] = 0.5 * (dg[j][SI(i, k)] + dg[k][SI(i, j)] - dg[i][SI(j, k)]);
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+#pragma unroll
+                        for (int m = 0; m < 6; ++m)
+                            Gu[i][m] = gu[SI(i, 0)] * Gl[0][m] + gu[SI(i, 1)] * Gl[1][m] + gu[SI(i, 2)] * Gl[2][m];
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        const double Gc = gu[0] * Gu[i][0] + gu[3] * Gu[i][3] + gu[5] * Gu[i][5] +
+                                          2.0 * (gu[1] * Gu[i][1] + gu[2] * Gu[i][2] + gu[4] * Gu[i][4]);
+                        Z[i] = 0.5 * chi * (Gh[i] - Gc);
+                        GtAu[i] = Gu[i][0] * Au[0] + Gu[i][3] * Au[3] + Gu[i][5] * Au[5] +
+                                  2.0 * (Gu[i][1] * Au[1] + Gu[i][2] * Au[2] + Gu[i][4] * Au[4]);
+                    }
+                    // Rhat_ij without the d Ghat term:
+                    //  -gt^mn d_m d_n gt_ij / 2 + Ghat^k Gt_(ij)k
+                    //  + gt^mn (Gt^k_mi Gt_jkn + Gt^k_mj Gt_ikn + Gt^k_mi Gt_knj)
+                    double H[3][3][3];  // H[k][i][n] = gt^{nm} Gt^k_{mi}
+#pragma unroll
+                    for (int k = 0; k < 3; ++k)
+#pragma unroll
+                        for (int i = 0; i < 3; ++i)
+#pragma unroll
+                            for (int n = 0; n < 3; ++n)
+                                H[k][i][n] = gu[SI(n, 0)] * Gu[k][SI(0, i)] + gu[SI(n, 1)] * Gu[k][SI(1, i)] +
+                                             gu[SI(n, 2)] * Gu[k][SI(2, i)];
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+#pragma unroll
+                        for (int j = i; j < 3; ++j) {
+                            double r = -0.5 * lapg[SI(i, j)];
+#pragma unroll
+                            for (int k = 0; k < 3; ++k) {
+                                r += Gh[k] * 0.5 * (Gl[i][SI(j, k)] + Gl[j][SI(i, k)]);
+#pragma unroll
+                                for (int n = 0; n < 3; ++n)
+                                    r += H[k][i][n] * Gl[j][SI(k, n)] + H[k][j][n] * Gl[i][SI(k, n)] +
+                                         H[k][i][n] * Gl[k][SI(n, j)];
+                            }
+                            Ric[SI(i, j)] = r;
+                        }
+                }
+            } else if (f >= GH && f < GH + 3) {
+                // gt_k(i d_j) Ghat^k for k = f - GH
+                const int kk = f - GH;
+                double dG[3];
+#pragma unroll
+                for (int j = 0; j < 3; ++j) dG[j] = d1(j);
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = i; j < 3; ++j)
+                        Ric[SI(i, j)] += 0.5 * (g[SI(kk, i)] * dG[j] + g[SI(kk, j)] * dG[i]);
+            } else if (f == CHI) {
+                double ddc[6];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) dchi[k] = d1(k);
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+#pragma unroll
+                    for (int l = k; l < 3; ++l) ddc[SI(k, l)] = dd(k, l);
+                const double ic = 1.0 / chi;
+                double tr = 0.0, Ghd = 0.0;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    Ghd += Gh[k] * dchi[k];
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) tr += gu[SI(k, m)] * (ddc[SI(k, m)] - 1.5 * ic * dchi[k] * dchi[m]);
+                }
+                // Rhat^chi_ij
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = i; j < 3; ++j) {
+                        const int m = SI(i, j);
+                        double Gd = 0.0, zs = 0.0;
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) {
+                            Gd += Gu[k][m] * dchi[k];
+                            zs += Z[k] * 0.5 * (g[SI(k, i)] * dchi[j] + g[SI(k, j)] * dchi[i]);
+                        }
+                        Ric[m] += 0.5 * ic * ddc[m] - 0.5 * ic * Gd - 0.25 * ic * ic * dchi[i] * dchi[j] +
+                                  2.0 * ic * ic * zs + 0.5 * ic * g[m] * (tr - Ghd);
+                    }
+            } else if (f == ALP) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) dalp[k] = d1(k);
+                double cr = 0.0;
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) cr += gu[SI(k, m)] * dalp[k] * dchi[m];
+                const double hic = 0.5 / chi;
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = i; j < 3; ++j) {
+                        const int m = SI(i, j);
+                        DDa[m] = dd(i, j) - (Gu[0][m] * dalp[0] + Gu[1][m] * dalp[1] + Gu[2][m] * dalp[2]) +
+                                 hic * (dalp[i] * dchi[j] + dalp[j] * dchi[i] - g[m] * cr);
+                    }
+            } else if (f >= BETA && f < BETA + 3) {
+                const int i = f - BETA;
+                if (i == 0) gdiv[0] = gdiv[1] = gdiv[2] = 0.0;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) db[k][i] = d1(k);
+                double s = 0.0;
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+#pragma unroll
+                    for (int l = k; l < 3; ++l) {
+                        const double v = dd(k, l);
+                        s += (k == l ? 1.0 : 2.0) * gu[SI(k, l)] * v;
+                        // d_j d_i beta^i goes to row j
+                        if (k == i) gdiv[l] += v;
+                        if (l == i && k != l) gdiv[k] += v;
+                    }
+                gddb[i] = s;
+            } else if (f == KH) {
+                double d[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) d[k] = d1(k);
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+                    rG[i] = -(2.0 / 3.0) * (gu[SI(i, 0)] * d[0] + gu[SI(i, 1)] * d[1] + gu[SI(i, 2)] * d[2]);
+            } else if (f == TH) {
+                double d[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) d[k] = d1(k);
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j)
+                        rG[i] += -gu[SI(i, j)] * ((1.0 / 3.0) * d[j] + Th / alp * dalp[j]);
+            }
+        }
+        if (q + 1 < NF) lstore((q + 1) & 1);
+        __syncthreads();
+    }
+    if (!valid) return;
+
+    // ---- algebra with all fields available ----
+    auto tr = [&](const double* T) {  // gt^{ij} T_ij
+        return gu[0] * T[0] + gu[3] * T[3] + gu[5] * T[5] + 2.0 * (gu[1] * T[1] + gu[2] * T[2] + gu[4] * T[4]);
+    };
+    const double trRic = chi * tr(Ric);
+    const double lapa = chi * tr(DDa);
     const double trA = Am[0][0] + Am[1][1] + Am[2][2];
     double AA = 0.0;
 #pragma unroll
@@ -257,78 +340,62 @@ __global__ __launch_bounds__(128) void ccz4_stage_kernel(StageArgs a, CczConst C
     const double divb = db[0][0] + db[1][1] + db[2][2];
     const double Zda = Z[0] * dalp[0] + Z[1] * dalp[1] + Z[2] * dalp[2];
     const double Kt = Kh + 2.0 * Th;
+    auto out = [&](int f, double phys) { stage_store(a, c + (int64_t)f * fs, phys + akx[f][tid]); };
 
-    double rhs[NF];
     // d_t gt_ij
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = i; j < 3; ++j) {
-            const int q = SI(i, j);
+            const int m = SI(i, j);
             double r = 0.0;
 #pragma unroll
             for (int k = 0; k < 3; ++k) r += g[SI(i, k)] * db[j][k] + g[SI(k, j)] * db[i][k];
-            rhs[GT + q] = r - (2.0 / 3.0) * g[q] * divb - 2.0 * alp * (A[q] - (1.0 / 3.0) * g[q] * trA) -
-                          (C.kc / 3.0) * alp * g[q] * lndet;
+            out(GT + m, r - (2.0 / 3.0) * g[m] * divb - 2.0 * alp * (A[m] - (1.0 / 3.0) * g[m] * trA) -
+                            (C.kc / 3.0) * alp * g[m] * lndet);
         }
     // d_t At_ij
     {
         double X[6];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) X[q] = alp * Ric[q] - DDa[q];
+        for (int m = 0; m < 6; ++m) X[m] = alp * Ric[m] - DDa[m];
         const double trX = tr(X);
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
             for (int j = i; j < 3; ++j) {
-                const int q = SI(i, j);
+                const int m = SI(i, j);
                 double r = 0.0, aa = 0.0;
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
                     r += A[SI(i, k)] * db[j][k] + A[SI(k, j)] * db[i][k];
                     aa += A[SI(i, k)] * Am[k][j];
                 }
-                rhs[AT + q] = r - (2.0 / 3.0) * A[q] * divb - (C.kc / 3.0) * alp * g[q] * trA +
-                              chi * (X[q] - (1.0 / 3.0) * g[q] * trX) + alp * (Kh * A[q] - 2.0 * aa);
+                out(AT + m, r - (2.0 / 3.0) * A[m] * divb - (C.kc / 3.0) * alp * g[m] * trA +
+                                chi * (X[m] - (1.0 / 3.0) * g[m] * trX) + alp * (Kh * A[m] - 2.0 * aa));
             }
     }
-    rhs[CHI] = (2.0 / 3.0) * chi * (alp * Kt - divb);
-    rhs[KH] = -lapa + alp * ((1.0 / 3.0) * Kt * Kt + AA + C.kz * Th) + 2.0 * Zda;
-    rhs[TH] = 0.5 * alp * (trRic + (2.0 / 3.0) * Kh * Kh + (2.0 / 3.0) * Th * (Kh - 2.0 * Th) - AA) - Zda -
-              alp * (2.0 * C.kz * Th);
+    out(CHI, (2.0 / 3.0) * chi * (alp * Kt - divb));
+    out(KH, -lapa + alp * ((1.0 / 3.0) * Kt * Kt + AA + C.kz * Th) + 2.0 * Zda);
+    out(TH, 0.5 * alp * (trRic + (2.0 / 3.0) * Kh * Kh + (2.0 / 3.0) * Th * (Kh - 2.0 * Th) - AA) - Zda -
+                alp * (2.0 * C.kz * Th));
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         double r = (2.0 / 3.0) * Gh[i] * divb + gddb[i];
-        double b1 = 0.0, b2 = 0.0;
+        double b1 = GtAu[i];
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             r += -Gh[j] * db[j][i] + (1.0 / 3.0) * gu[SI(i, j)] * gdiv[j] - 2.0 * Au[SI(i, j)] * dalp[j];
-            b1 += -1.5 / chi * Au[SI(i, j)] * dchi[j] - (2.0 / 3.0) * gu[SI(i, j)] * dK[j];
-            b2 += -gu[SI(i, j)] * ((1.0 / 3.0) * dTh[j] + Th / alp * dalp[j]);
+            b1 += -1.5 / chi * Au[SI(i, j)] * dchi[j];
         }
-#pragma unroll
-        for (int q = 0; q < 6; ++q) b1 += (q == 0 || q == 3 || q == 5 ? 1.0 : 2.0) * Gu[i][q] * Au[q];
-        b2 += -Z[i] / chi * (C.kz + (2.0 / 3.0) * Kt);
-        r += 2.0 * alp * b1 + 2.0 * alp * b2;
-        rhs[GH + i] = r;
-        rhs[BB + i] = -C.eta * Bv[i] + r;  // d_t Ghat^i without its advection term
-        rhs[BETA + i] = C.g * Bv[i];
+        const double b2 = -Z[i] / chi * (C.kz + (2.0 / 3.0) * Kt);
+        r += 2.0 * alp * (b1 + rG[i] + b2);
+        const double Bv = u[(BB + i) * fs];
+        out(GH + i, r);
+        out(BB + i, -C.eta * Bv + r);  // d_t Ghat^i without its advection term
+        out(BETA + i, C.g * Bv);
     }
-    rhs[ALP] = -alp * alp * (C.f0 + C.f1 / alp) * Kh;
-
-    // ---- advection (every field) and KO dissipation, then the RK update ----
-#pragma unroll 1
-    for (int f = 0; f < NF; ++f) {
-        const double* w = FLD(f);
-        double adv = 0.0, ko = 0.0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            adv += be[k] * (UPWIND ? fadv(w, s[k], be[k]) : fd1(w, s[k]));
-            ko += fko(w, s[k]);
-        }
-        stage_store(a, pr.c + (int64_t)f * fs, (rhs[f] + C.i12h * adv) + C.ko * ko);
-    }
-#undef FLD
+    out(ALP, -alp * alp * (C.f0 + C.f1 / alp) * Kh);
 }
 
 }  // namespace
@@ -336,6 +403,7 @@ __global__ __launch_bounds__(128) void ccz4_stage_kernel(StageArgs a, CczConst C
 hipError_t launch_stage_ccz4(const SysParams& sp, const StageArgs& a, const int td[3], hipStream_t s)
 {
     if (a.ntiles <= 0) return hipSuccess;
+    if (td[0] != 8 || td[1] != 8 || td[2] != 4) return hipErrorInvalidConfiguration;
     CczConst C;
     C.i12h = 1.0 / (12.0 * sp.h);
     C.i12h2 = 1.0 / (12.0 * sp.h * sp.h);
@@ -347,12 +415,11 @@ hipError_t launch_stage_ccz4(const SysParams& sp, const StageArgs& a, const int 
     C.f1 = sp.bm_f1;
     C.g = sp.gd_g;
     C.eta = sp.gd_eta;
-    C.upwind = sp.upwind;
-    dim3 blk(td[0], td[1], td[2]);
+    dim3 blk(8, 8, 4);
     if (sp.upwind)
-        ccz4_stage_kernel<true><<<a.ntiles, blk, 0, s>>>(a, C);
+        ccz4_stage_kernel<8, 8, 4, true><<<a.ntiles, blk, 0, s>>>(a, C);
     else
-        ccz4_stage_kernel<false><<<a.ntiles, blk, 0, s>>>(a, C);
+        ccz4_stage_kernel<8, 8, 4, false><<<a.ntiles, blk, 0, s>>>(a, C);
     return hipGetLastError();
 }
 
