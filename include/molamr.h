@@ -94,9 +94,10 @@ typedef struct {
 typedef struct mol_patchset mol_patchset;
 
 /* Build a patchset: validates the hierarchy (boxes inside the level's
- * periodic domain and non-overlapping, each fine level's region inside its
- * parent level with a margin of 6 parent points so that prolongation stencils
- * stay on parent data, interiors of at least 1 point per axis) and builds the
+ * periodic domain and non-overlapping, level 0 tiling the domain, every
+ * prolongation stencil node inside the interior of a parent patch -- a margin
+ * of 6 parent points between a fine level's region and the boundary of its
+ * parent level's region suffices) and builds the
  * device tables: same-level/periodic ghost lists, coarse-fine ghost lists
  * (Sec. III.A), injection lists and per-level tile work lists.
  * Returns MOL_EINVAL on a bad description, MOL_EHIP/MOL_ENOMEM on device
@@ -118,10 +119,10 @@ int mol_level_layout(const mol_patchset* ps, int level, int64_t* nelems,
 int mol_level_npatch(const mol_patchset* ps, int level);
 
 /* Ghost fill of level `level`, same-level and periodic sources only (the
- * "level synchronization" of the Sec. III skeleton): every ghost point that
- * the stencils read (faces to depth 3, edges to depth 2) and that lies in the
- * interior of a patch of the same level, modulo the period, takes that value.
- * nf fields of U are filled (nf = 0 means all fields of the system). */
+ * "level synchronization" of the Sec. III skeleton): every ghost point
+ * (faces, edges and corners of the 3-point layer) that lies in the interior
+ * of a patch of the same level, modulo the period, takes that value.  nf
+ * fields of U are filled (nf = 0 means all fields of the system). */
 int mol_fill_ghosts(mol_patchset* ps, int level, double* U, int nf, void* stream);
 
 /* Right-hand side L(U) + Q_d(U) (eq. semidiscrete) on the interior of every
@@ -149,8 +150,8 @@ int mol_rk_stage(mol_patchset* ps, int level, int scheme, int stage, double dt,
 /* Coarse-fine ghost fill of fine level `fine_level` (>= 1) with Berger-Oliger
  * without order reduction (App. D, RK4) and quintic Lagrange interpolation
  * (Sec. III.A): for fine step r (0 <= r < R) inside the parent step and fine
- * stage s (1..4), every stencil-read ghost point of the level that has no
- * same-level source takes
+ * stage s (1..4), every ghost point of the level that has no same-level
+ * source takes
  *   sum_{a,b,c} L_a(xi_x) L_b(xi_y) L_c(xi_z) [Un_c + sum_j w_j(R,r,s) k_c[j]]
  * over the parent nodes around it (6 per axis, or the coincident node when
  * the fine index is a multiple of R), with w_j from the RK4 dense output and
@@ -179,8 +180,9 @@ int mol_rhs_adjoint(mol_patchset* ps, int level, const double* U, const double* 
  * that copy it, then those ghost entries are zeroed (owner gather, no atomics). */
 int mol_fill_ghosts_adjoint(mol_patchset* ps, int level, double* lamU, void* stream);
 /* Reverse of one RK4 step (Table RK44) of the wave system on one periodic
- * level: lam <- (dU^{n+1}/dU^n)^T lam.  w0, w1, w2 are work buffers of the
- * level's size.  lam ghosts are zero on return. */
+ * level: lam <- (dU^{n+1}/dU^n)^T lam on interior points.  w0, w1, w2 are
+ * work buffers of the level's size.  Ghost entries of lam are ignored and
+ * left unchanged. */
 int mol_rk4_adjoint_step(mol_patchset* ps, int level, double dt, double* lam,
                          double* w0, double* w1, double* w2, void* stream);
 
@@ -191,6 +193,13 @@ int mol_rk4_adjoint_step(mol_patchset* ps, int level, double dt, double* lam,
  * The summation order is fixed (deterministic). */
 int mol_norms(mol_patchset* ps, int level, const double* U, int field, double shift,
               double radius, double* out_dev, void* stream);
+
+/* Transpose of the sphere integral of mol_norms (out_dev[3]): lam[field] =
+ * scale * dV at interior points with |x| < radius, 0 at the other interior
+ * points; the other fields are set to 0 on interior points; ghost entries
+ * are not written. */
+int mol_sphere_adjoint(mol_patchset* ps, int level, int field, double radius, double scale,
+                       double* lam, void* stream);
 
 /* Wave initial data phi = A exp(-|x-c|^2/w^2) (minimum image), Pi = 0, with
  * prm = {A, w, cx, cy, cz}; and its vector-Jacobian product

@@ -1,0 +1,56 @@
+"""Gradient of a sphere-integral objective of the periodic scalar wave with
+respect to its Gaussian initial-data parameters, as a torch.autograd.Function.
+
+Forward: phi_0 = A exp(-|x - c|^2 / w^2), Pi_0 = 0 (mol_wave_gaussian); nsteps
+RK4 steps (mol_advance, one periodic level); J = sum_{|x| < R} phi dV
+(mol_norms).  Checkpoints of the state are kept every `every` steps.
+Backward: lam_T = dJ/dU_T (mol_sphere_adjoint), then the reverse RK4 sweep
+(mol_rk4_adjoint_step) segment by segment from the last checkpoint to the
+first, and dJ/dp = <lam_0, dU_0/dp> (mol_wave_gaussian_vjp).  The wave operator
+is linear, so its transpose does not depend on the forward states: the
+segments are not recomputed.  All arithmetic runs in libmolamr.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import molamr as M
+
+
+class WaveSphereObjective(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, prm: torch.Tensor, ps: M.Patchset, nsteps: int, dt: float, radius: float, every: int = 20):
+        p = [float(v) for v in prm.detach().cpu()]
+        st = ps.alloc_states()
+        ps.wave_gaussian(0, p, st[0]["U"])
+        ps.fill_ghosts(0, st[0]["U"])
+        ckpts = [st[0]["U"].clone()]
+        for s in range(nsteps):
+            ps.advance(st, dt)
+            if (s + 1) % every == 0 and s + 1 < nsteps:
+                ckpts.append(st[0]["U"].clone())
+        out = torch.zeros(5, dtype=torch.float64, device=st[0]["U"].device)
+        ps.norms(0, st[0]["U"], 0, 0.0, radius, out)
+        ctx.ps, ctx.p, ctx.nsteps, ctx.dt, ctx.radius, ctx.every = ps, p, nsteps, dt, radius, every
+        ctx.ckpts = ckpts
+        return out[3].detach().cpu().reshape(())
+
+    @staticmethod
+    def backward(ctx, gJ):
+        ps = ctx.ps
+        lam = ps.alloc(0)
+        w0, w1, w2 = ps.alloc(0), ps.alloc(0), ps.alloc(0)
+        ps.sphere_adjoint(0, 0, ctx.radius, float(gJ), lam)
+        # segments [k*every, (k+1)*every) in reverse order
+        nseg = (ctx.nsteps + ctx.every - 1) // ctx.every
+        for k in reversed(range(nseg)):
+            steps = min(ctx.every, ctx.nsteps - k * ctx.every)
+            for _ in range(steps):
+                ps.rk4_adjoint_step(0, ctx.dt, lam, w0, w1, w2)
+        g = torch.zeros(5, dtype=torch.float64, device=lam.device)
+        ps.wave_gaussian_vjp(0, ctx.p, lam, g)
+        return g.cpu(), None, None, None, None, None
+
+
+def sphere_objective(prm, ps, nsteps, dt, radius, every=20):
+    return WaveSphereObjective.apply(prm, ps, nsteps, dt, radius, every)

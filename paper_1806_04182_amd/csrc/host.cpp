@@ -221,7 +221,7 @@ void default_tile(int system, int td[3])
     switch (system) {
     case MOL_WAVE: td[0] = 32; td[1] = 4; td[2] = 2; break;
     case MOL_MHD: td[0] = 16; td[1] = 4; td[2] = 4; break;
-    default: td[0] = 8; td[1] = 8; td[2] = 4; break;
+    default: td[0] = MOL_CCZ4_TX; td[1] = MOL_CCZ4_TY; td[2] = MOL_CCZ4_TZ; break;
     }
 }
 
@@ -837,6 +837,19 @@ int mol_norms(mol_patchset* ps, int level, const double* U, int field, double sh
                                 field, shift, radius, lev.h, ps->xlo, ps->scratch, ps->red_blocks,
                                 out_dev, S(stream));
     return e == hipSuccess ? MOL_OK : hip_fail(e, "norms launch");
+}
+
+int mol_sphere_adjoint(mol_patchset* ps, int level, int field, double radius, double scale, double* lam,
+                       void* stream)
+{
+    int rc = check_level(ps, level);
+    if (rc) return rc;
+    if (!lam) return fail(MOL_EINVAL, "null buffer");
+    if (field < 0 || field >= ps->sp.nf) return fail(MOL_EINVAL, "field %d out of range", field);
+    Level& lev = ps->L[level];
+    hipError_t e = launch_sphere_adjoint(lev.d_pd.p, lev.ntiles.dev.p, (int)lev.ntiles.dev.n, lev.ntiles.tdim,
+                                         ps->sp.nf, field, radius, scale, lev.h, ps->xlo, lam, S(stream));
+    return e == hipSuccess ? MOL_OK : hip_fail(e, "sphere adjoint launch");
 }
 
 int mol_wave_gaussian(mol_patchset* ps, int level, const double prm[5], double* U, void* stream)

@@ -74,16 +74,18 @@ __global__ __launch_bounds__(TX * TY * TZ) void ccz4_stage_kernel(StageArgs a, C
                  tile.o[2] + hz < P.n[2] + 2 * G;
         goff[r] = hz * P.pitch_z + hy * P.pitch_y + hx;
     }
-    double stg[NR];
-    auto gload = [&](int f) {
+    // two register stages: the loads of field q+2 are issued while field q is
+    // differentiated and field q+1 (loaded one iteration earlier) is moved to LDS
+    double stg[2][NR];
+    auto gload = [&](int f, int slot) {
         const double* src = a.Us + hbase + (int64_t)f * fs;
 #pragma unroll
-        for (int r = 0; r < NR; ++r) stg[r] = gok[r] ? src[goff[r]] : 0.0;
+        for (int r = 0; r < NR; ++r) stg[slot][r] = gok[r] ? src[goff[r]] : 0.0;
     };
-    auto lstore = [&](int b) {
+    auto lstore = [&](int b, int slot) {
 #pragma unroll
         for (int r = 0; r < NR; ++r)
-            if (tid + r * NT < HV) buf[b][tid + r * NT] = stg[r];
+            if (tid + r * NT < HV) buf[b][tid + r * NT] = stg[slot][r];
     };
 
     // ---- point values and the inverse conformal metric (global loads) ----
@@ -138,13 +140,14 @@ __global__ __launch_bounds__(TX * TY * TZ) void ccz4_stage_kernel(StageArgs a, C
     double rG[3];                       // Ghat^i terms with d Khat and d Theta
     const int S[3] = {1, HX, HX * HY};
 
-    gload(ORDER[0]);
-    lstore(0);
+    gload(ORDER[0], 0);
+    lstore(0, 0);
+    gload(ORDER[1], 1);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < NF; ++q) {
         const int f = ORDER[q];
-        if (q + 1 < NF) gload(ORDER[q + 1]);
+        if (q + 2 < NF) gload(ORDER[q + 2], q & 1);
         if (valid) {
             const double* t = &buf[q & 1][(tz + G) * HX * HY + (ty + G) * HX + tx + G];
             // advection beta^k d_k and KO dissipation of every field
@@ -320,7 +323,7 @@ __global__ __launch_bounds__(TX * TY * TZ) void ccz4_stage_kernel(StageArgs a, C
                         rG[i] += -gu[SI(i, j)] * ((1.0 / 3.0) * d[j] + Th / alp * dalp[j]);
             }
         }
-        if (q + 1 < NF) lstore((q + 1) & 1);
+        if (q + 1 < NF) lstore((q + 1) & 1, (q + 1) & 1);
         __syncthreads();
     }
     if (!valid) return;
@@ -403,7 +406,7 @@ __global__ __launch_bounds__(TX * TY * TZ) void ccz4_stage_kernel(StageArgs a, C
 hipError_t launch_stage_ccz4(const SysParams& sp, const StageArgs& a, const int td[3], hipStream_t s)
 {
     if (a.ntiles <= 0) return hipSuccess;
-    if (td[0] != 8 || td[1] != 8 || td[2] != 4) return hipErrorInvalidConfiguration;
+    if (td[0] != MOL_CCZ4_TX || td[1] != MOL_CCZ4_TY || td[2] != MOL_CCZ4_TZ) return hipErrorInvalidConfiguration;
     CczConst C;
     C.i12h = 1.0 / (12.0 * sp.h);
     C.i12h2 = 1.0 / (12.0 * sp.h * sp.h);
@@ -415,11 +418,11 @@ hipError_t launch_stage_ccz4(const SysParams& sp, const StageArgs& a, const int 
     C.f1 = sp.bm_f1;
     C.g = sp.gd_g;
     C.eta = sp.gd_eta;
-    dim3 blk(8, 8, 4);
+    dim3 blk(MOL_CCZ4_TX, MOL_CCZ4_TY, MOL_CCZ4_TZ);
     if (sp.upwind)
-        ccz4_stage_kernel<8, 8, 4, true><<<a.ntiles, blk, 0, s>>>(a, C);
+        ccz4_stage_kernel<MOL_CCZ4_TX, MOL_CCZ4_TY, MOL_CCZ4_TZ, true><<<a.ntiles, blk, 0, s>>>(a, C);
     else
-        ccz4_stage_kernel<8, 8, 4, false><<<a.ntiles, blk, 0, s>>>(a, C);
+        ccz4_stage_kernel<MOL_CCZ4_TX, MOL_CCZ4_TY, MOL_CCZ4_TZ, false><<<a.ntiles, blk, 0, s>>>(a, C);
     return hipGetLastError();
 }
 

@@ -124,7 +124,33 @@ __global__ __launch_bounds__(RB) void gaussian_kernel(const PatchDev* __restrict
         for (int q = 0; q < NQ; ++q) partial[blockIdx.x * NQ + q] = r.v[q];
 }
 
+__global__ __launch_bounds__(RB) void sphere_adjoint_kernel(const PatchDev* __restrict__ patches,
+                                                            const Tile* __restrict__ tiles, int nf, int field,
+                                                            double r2max, double w, double h, double x0,
+                                                            double y0, double z0, double* __restrict__ lam)
+{
+    const Tile t = tiles[blockIdx.x];
+    const PatchDev P = patches[t.patch];
+    const int i = t.o[0] + threadIdx.x, j = t.o[1] + threadIdx.y, k = t.o[2] + threadIdx.z;
+    if (i >= P.n[0] || j >= P.n[1] || k >= P.n[2]) return;
+    const int64_t c = P.off + (int64_t)(k + G) * P.pitch_z + (int64_t)(j + G) * P.pitch_y + i + G;
+    const double x = x0 + (P.lo[0] + i) * h, y = y0 + (P.lo[1] + j) * h, z = z0 + (P.lo[2] + k) * h;
+    const double v = x * x + y * y + z * z < r2max ? w : 0.0;
+    for (int f = 0; f < nf; ++f) lam[c + f * P.fs] = f == field ? v : 0.0;
+}
+
 }  // namespace
+
+hipError_t launch_sphere_adjoint(const PatchDev* patches, const Tile* tiles, int ntiles, const int td[3], int nf,
+                                 int field, double radius, double scale, double h, const double xlo[3], double* lam,
+                                 hipStream_t s)
+{
+    if (ntiles <= 0) return hipSuccess;
+    sphere_adjoint_kernel<<<ntiles, dim3(td[0], td[1], td[2]), 0, s>>>(patches, tiles, nf, field, radius * radius,
+                                                                       scale * h * h * h, h, xlo[0], xlo[1],
+                                                                       xlo[2], lam);
+    return hipGetLastError();
+}
 
 hipError_t launch_norms(const PatchDev* patches, const Tile* tiles, int ntiles, const int td[3], const double* U,
                         int field, double shift, double radius, double h, const double xlo[3], double* partial,

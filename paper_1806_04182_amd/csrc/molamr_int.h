@@ -12,6 +12,13 @@ namespace mol {
 
 constexpr int G = MOL_GHOST;
 
+// tile of the CCZ4 stage kernel (threads per workgroup = product)
+#ifndef MOL_CCZ4_TX
+#define MOL_CCZ4_TX 8
+#define MOL_CCZ4_TY 8
+#define MOL_CCZ4_TZ 4
+#endif
+
 // One patch of a level, as the kernels see it.
 struct PatchDev {
     int64_t off;   // start of the patch block in the level buffer (doubles)
@@ -129,6 +136,9 @@ hipError_t launch_norms(const PatchDev* patches, const Tile* tiles, int ntiles, 
                         const double* U, int field, double shift, double radius, double h,
                         const double xlo[3], double* partial, int nblocks, double* out,
                         hipStream_t s);
+hipError_t launch_sphere_adjoint(const PatchDev* patches, const Tile* tiles, int ntiles, const int tdim[3],
+                                int nf, int field, double radius, double scale, double h, const double xlo[3],
+                                double* lam, hipStream_t s);
 hipError_t launch_gaussian(const PatchDev* patches, const Tile* tiles, int ntiles, const int tdim[3],
                            const double prm[5], double h, const double xlo[3], const double per[3],
                            double* U, const double* lam, double* partial, int nblocks, double* grad,

@@ -15,7 +15,7 @@ from typing import Sequence
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmolamr.so")
+LIB_PATH = os.environ.get("MOLAMR_LIB", os.path.join(HERE, "libmolamr.so"))
 
 MOL_WAVE, MOL_MHD, MOL_CCZ4 = 0, 1, 2
 MOL_RK4, MOL_SSPRK3 = 0, 1
@@ -78,6 +78,7 @@ def lib():
             "mol_fill_ghosts_adjoint": ([vp, i, vp, vp], i),
             "mol_rk4_adjoint_step": ([vp, i, d, vp, vp, vp, vp, vp], i),
             "mol_norms": ([vp, i, vp, i, d, d, vp, vp], i),
+            "mol_sphere_adjoint": ([vp, i, i, d, d, vp, vp], i),
             "mol_wave_gaussian": ([vp, i, dp, vp, vp], i),
             "mol_wave_gaussian_vjp": ([vp, i, dp, vp, vp, vp], i),
             "mol_advance": ([vp, ctypes.POINTER(_LevelState), d, i, vp], i),
@@ -246,6 +247,9 @@ class Patchset:
 
     def norms(self, level, U, field, shift, radius, out_dev, stream=None):
         _check(lib().mol_norms(self._h, level, _ptr(U), field, shift, radius, _ptr(out_dev), _stream(stream)))
+
+    def sphere_adjoint(self, level, field, radius, scale, lam, stream=None):
+        _check(lib().mol_sphere_adjoint(self._h, level, field, radius, scale, _ptr(lam), _stream(stream)))
 
     def wave_gaussian(self, level, prm, U, stream=None):
         p = (ctypes.c_double * 5)(*prm)
