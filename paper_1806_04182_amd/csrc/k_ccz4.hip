@@ -19,6 +19,8 @@
 // Hessian after alpha, ...), so only the partial sums stay live.  Advection
 // and dissipation of every field are parked in LDS until the algebra that
 // needs all fields is done; then the RK stage update writes the results.
+#include <utility>
+
 #include "k_common.h"
 
 namespace mol {
@@ -27,9 +29,12 @@ namespace {
 
 enum { CHI = 0, GT = 1, KH = 7, AT = 8, GH = 14, TH = 17, ALP = 18, BETA = 19, BB = 22, NF = 25 };
 
+// packed index of the symmetric pair (i, j); written without recursion so
+// that it folds to a constant wherever i and j are constants
 __device__ constexpr int SI(int i, int j)
 {
-    return i > j ? SI(j, i) : (i == 0 ? j : (i == 1 ? 2 + j : 5));
+    const int a = i < j ? i : j, b = i < j ? j : i;
+    return a == 0 ? b : (a == 1 ? 2 + b : 5);
 }
 
 struct CczConst {
@@ -41,16 +46,17 @@ struct CczConst {
 };
 
 // order in which the fields pass through LDS
-__device__ constexpr int ORDER[NF] = {GT + 0, GT + 1, GT + 2, GT + 3, GT + 4, GT + 5, GH + 0, GH + 1, GH + 2,
+constexpr int ORDER[NF] = {GT + 0, GT + 1, GT + 2, GT + 3, GT + 4, GT + 5, GH + 0, GH + 1, GH + 2,
                                       CHI,    ALP,    BETA + 0, BETA + 1, BETA + 2, KH, TH,
                                       AT + 0, AT + 1, AT + 2, AT + 3, AT + 4, AT + 5, BB + 0, BB + 1, BB + 2};
 
 template <int TX, int TY, int TZ, bool UPWIND>
-__global__ __launch_bounds__(TX * TY * TZ) void ccz4_stage_kernel(StageArgs a, CczConst C)
+__global__ __launch_bounds__(TX * TY * TZ, MOL_CCZ4_WAVES) void ccz4_stage_kernel(StageArgs a, CczConst C)
 {
     constexpr int HX = TX + 2 * G, HY = TY + 2 * G, HZ = TZ + 2 * G;
     constexpr int HV = HX * HY * HZ, NT = TX * TY * TZ, NR = (HV + NT - 1) / NT;
-    __shared__ double buf[2][HV];
+    constexpr int NB = MOL_CCZ4_NBUF;  // LDS halo buffers (1 or 2)
+    __shared__ double buf[NB][HV];
     __shared__ double akx[NF][NT];  // advection + dissipation of every field
 
     const Tile tile = a.tiles[blockIdx.x];
@@ -74,15 +80,17 @@ __global__ __launch_bounds__(TX * TY * TZ) void ccz4_stage_kernel(StageArgs a, C
                  tile.o[2] + hz < P.n[2] + 2 * G;
         goff[r] = hz * P.pitch_z + hy * P.pitch_y + hx;
     }
-    // two register stages: the loads of field q+2 are issued while field q is
-    // differentiated and field q+1 (loaded one iteration earlier) is moved to LDS
-    double stg[2][NR];
-    auto gload = [&](int f, int slot) {
+    // register stages of the halo loads.  Two LDS buffers: the loads of field
+    // q+2 are issued while field q is differentiated and field q+1 (loaded one
+    // iteration earlier) is moved to LDS.  One LDS buffer: the loads of field
+    // q+1 are in flight while field q is differentiated.
+    double stg[NB][NR];
+    auto gload = [&](int f, int slot) __attribute__((always_inline)) {
         const double* src = a.Us + hbase + (int64_t)f * fs;
 #pragma unroll
         for (int r = 0; r < NR; ++r) stg[slot][r] = gok[r] ? src[goff[r]] : 0.0;
     };
-    auto lstore = [&](int b, int slot) {
+    auto lstore = [&](int b, int slot) __attribute__((always_inline)) {
 #pragma unroll
         for (int r = 0; r < NR; ++r)
             if (tid + r * NT < HV) buf[b][tid + r * NT] = stg[slot][r];
@@ -142,14 +150,17 @@ __global__ __launch_bounds__(TX * TY * TZ) void ccz4_stage_kernel(StageArgs a, C
 
     gload(ORDER[0], 0);
     lstore(0, 0);
-    gload(ORDER[1], 1);
+    if constexpr (NB == 2) gload(ORDER[1], 1);
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < NF; ++q) {
-        const int f = ORDER[q];
-        if (q + 2 < NF) gload(ORDER[q + 2], q & 1);
+    // one pass per field, expanded at compile time so that every branch and
+    // array index below is a constant
+    auto pass = [&](auto qc) __attribute__((always_inline)) {
+        constexpr int q = decltype(qc)::value;
+        constexpr int f = ORDER[q];
+        if constexpr (NB == 2 && q + 2 < NF) gload(ORDER[q + 2], q & 1);
+        if constexpr (NB == 1 && q + 1 < NF) gload(ORDER[q + 1], 0);
         if (valid) {
-            const double* t = &buf[q & 1][(tz + G) * HX * HY + (ty + G) * HX + tx + G];
+            const double* t = &buf[NB == 2 ? (q & 1) : 0][(tz + G) * HX * HY + (ty + G) * HX + tx + G];
             // advection beta^k d_k and KO dissipation of every field
             double adv = 0.0, ko = 0.0;
 #pragma unroll
@@ -159,12 +170,12 @@ __global__ __launch_bounds__(TX * TY * TZ) void ccz4_stage_kernel(StageArgs a, C
             }
             akx[f][tid] = C.i12h * adv + C.ko * ko;
 
-            auto d1 = [&](int k) { return C.i12h * fd1(t, S[k]); };
-            auto dd = [&](int k, int l) {
+            auto d1 = [&](int k) __attribute__((always_inline)) { return C.i12h * fd1(t, S[k]); };
+            auto dd = [&](int k, int l) __attribute__((always_inline)) {
                 return k == l ? C.i12h2 * fd2(t, S[k]) : C.i144h2 * fmix(t, S[k], S[l]);
             };
             // gt^{kl} d_k d_l of the field in LDS
-            auto trdd = [&]() {
+            auto trdd = [&]() __attribute__((always_inline)) {
                 double s = 0.0;
 #pragma unroll
                 for (int k = 0; k < 3; ++k)
@@ -173,12 +184,12 @@ __global__ __launch_bounds__(TX * TY * TZ) void ccz4_stage_kernel(StageArgs a, C
                 return s;
             };
 
-            if (f >= GT && f < GT + 6) {
-                const int qq = f - GT;
+            if constexpr (f >= GT && f < GT + 6) {
+                constexpr int qq = f - GT;
 #pragma unroll
                 for (int k = 0; k < 3; ++k) dg[k][qq] = d1(k);
                 lapg[qq] = trdd();
-                if (qq == 5) {
+                if constexpr (qq == 5) {
                     // Christoffels: Gl[i][jk] = (d_j g_ik + d_k g_ij - d_i g_jk)/2, Gu = gt^-1 Gl
                     double Gl[3][6];
 #pragma unroll
@@ -229,9 +240,9 @@ __global__ __launch_bounds__(TX * TY * TZ) void ccz4_stage_kernel(StageArgs a, C
                             Ric[SI(i, j)] = r;
                         }
                 }
-            } else if (f >= GH && f < GH + 3) {
+            } else if constexpr (f >= GH && f < GH + 3) {
                 // gt_k(i d_j) Ghat^k for k = f - GH
-                const int kk = f - GH;
+                constexpr int kk = f - GH;
                 double dG[3];
 #pragma unroll
                 for (int j = 0; j < 3; ++j) dG[j] = d1(j);
@@ -240,7 +251,7 @@ __global__ __launch_bounds__(TX * TY * TZ) void ccz4_stage_kernel(StageArgs a, C
 #pragma unroll
                     for (int j = i; j < 3; ++j)
                         Ric[SI(i, j)] += 0.5 * (g[SI(kk, i)] * dG[j] + g[SI(kk, j)] * dG[i]);
-            } else if (f == CHI) {
+            } else if constexpr (f == CHI) {
                 double ddc[6];
 #pragma unroll
                 for (int k = 0; k < 3; ++k) dchi[k] = d1(k);
@@ -271,7 +282,7 @@ __global__ __launch_bounds__(TX * TY * TZ) void ccz4_stage_kernel(StageArgs a, C
                         Ric[m] += 0.5 * ic * ddc[m] - 0.5 * ic * Gd - 0.25 * ic * ic * dchi[i] * dchi[j] +
                                   2.0 * ic * ic * zs + 0.5 * ic * g[m] * (tr - Ghd);
                     }
-            } else if (f == ALP) {
+            } else if constexpr (f == ALP) {
 #pragma unroll
                 for (int k = 0; k < 3; ++k) dalp[k] = d1(k);
                 double cr = 0.0;
@@ -288,9 +299,9 @@ __global__ __launch_bounds__(TX * TY * TZ) void ccz4_stage_kernel(StageArgs a, C
                         DDa[m] = dd(i, j) - (Gu[0][m] * dalp[0] + Gu[1][m] * dalp[1] + Gu[2][m] * dalp[2]) +
                                  hic * (dalp[i] * dchi[j] + dalp[j] * dchi[i] - g[m] * cr);
                     }
-            } else if (f >= BETA && f < BETA + 3) {
-                const int i = f - BETA;
-                if (i == 0) gdiv[0] = gdiv[1] = gdiv[2] = 0.0;
+            } else if constexpr (f >= BETA && f < BETA + 3) {
+                constexpr int i = f - BETA;
+                if constexpr (i == 0) gdiv[0] = gdiv[1] = gdiv[2] = 0.0;
 #pragma unroll
                 for (int k = 0; k < 3; ++k) db[k][i] = d1(k);
                 double s = 0.0;
@@ -305,14 +316,14 @@ __global__ __launch_bounds__(TX * TY * TZ) void ccz4_stage_kernel(StageArgs a, C
                         if (l == i && k != l) gdiv[k] += v;
                     }
                 gddb[i] = s;
-            } else if (f == KH) {
+            } else if constexpr (f == KH) {
                 double d[3];
 #pragma unroll
                 for (int k = 0; k < 3; ++k) d[k] = d1(k);
 #pragma unroll
                 for (int i = 0; i < 3; ++i)
                     rG[i] = -(2.0 / 3.0) * (gu[SI(i, 0)] * d[0] + gu[SI(i, 1)] * d[1] + gu[SI(i, 2)] * d[2]);
-            } else if (f == TH) {
+            } else if constexpr (f == TH) {
                 double d[3];
 #pragma unroll
                 for (int k = 0; k < 3; ++k) d[k] = d1(k);
@@ -323,13 +334,21 @@ __global__ __launch_bounds__(TX * TY * TZ) void ccz4_stage_kernel(StageArgs a, C
                         rG[i] += -gu[SI(i, j)] * ((1.0 / 3.0) * d[j] + Th / alp * dalp[j]);
             }
         }
-        if (q + 1 < NF) lstore((q + 1) & 1, (q + 1) & 1);
+        if constexpr (NB == 2) {
+            if constexpr (q + 1 < NF) lstore((q + 1) & 1, (q + 1) & 1);
+        } else {
+            __syncthreads();
+            if constexpr (q + 1 < NF) lstore(0, 0);
+        }
         __syncthreads();
-    }
+    };
+    [&]<int... Q>(std::integer_sequence<int, Q...>) {
+        (pass(std::integral_constant<int, Q>{}), ...);
+    }(std::make_integer_sequence<int, NF>{});
     if (!valid) return;
 
     // ---- algebra with all fields available ----
-    auto tr = [&](const double* T) {  // gt^{ij} T_ij
+    auto tr = [&](const double* T) __attribute__((always_inline)) {  // gt^{ij} T_ij
         return gu[0] * T[0] + gu[3] * T[3] + gu[5] * T[5] + 2.0 * (gu[1] * T[1] + gu[2] * T[2] + gu[4] * T[4]);
     };
     const double trRic = chi * tr(Ric);
@@ -343,7 +362,7 @@ __global__ __launch_bounds__(TX * TY * TZ) void ccz4_stage_kernel(StageArgs a, C
     const double divb = db[0][0] + db[1][1] + db[2][2];
     const double Zda = Z[0] * dalp[0] + Z[1] * dalp[1] + Z[2] * dalp[2];
     const double Kt = Kh + 2.0 * Th;
-    auto out = [&](int f, double phys) { stage_store(a, c + (int64_t)f * fs, phys + akx[f][tid]); };
+    auto out = [&](int f, double phys) __attribute__((always_inline)) { stage_store(a, c + (int64_t)f * fs, phys + akx[f][tid]); };
 
     // d_t gt_ij
 #pragma unroll

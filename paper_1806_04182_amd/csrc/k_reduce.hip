@@ -5,6 +5,12 @@
 // the per-block partials with the same tree.
 #include "molamr_int.h"
 
+// Sphere membership |x| < R decides which points enter the objective: the
+// coordinates and x^2 + y^2 + z^2 are evaluated without FMA contraction so
+// that points on the sphere are classified exactly as by a plain C evaluation
+// of the same expressions.
+#pragma clang fp contract(off)
+
 namespace mol {
 
 namespace {

@@ -18,6 +18,13 @@ constexpr int G = MOL_GHOST;
 #define MOL_CCZ4_TY 8
 #define MOL_CCZ4_TZ 4
 #endif
+// LDS halo buffers of the CCZ4 kernel and its minimum waves per SIMD
+#ifndef MOL_CCZ4_NBUF
+#define MOL_CCZ4_NBUF 1
+#endif
+#ifndef MOL_CCZ4_WAVES
+#define MOL_CCZ4_WAVES 2
+#endif
 
 // One patch of a level, as the kernels see it.
 struct PatchDev {

@@ -171,8 +171,8 @@ class Patchset:
         self.layouts = [self.level_layout(l) for l in range(self.nlev)]
 
     def __del__(self):
-        if getattr(self, "_h", None):
-            lib().mol_destroy_patchset(self._h)
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.mol_destroy_patchset(self._h)
             self._h = None
 
     # ---- layout -------------------------------------------------------
@@ -298,8 +298,8 @@ class Graph:
         _check(lib().mol_graph_launch(self._g, _stream(stream)))
 
     def __del__(self):
-        if getattr(self, "_g", None):
-            lib().mol_graph_destroy(self._g)
+        if getattr(self, "_g", None) and _lib is not None:
+            _lib.mol_graph_destroy(self._g)
             self._g = None
 
 
