@@ -53,13 +53,18 @@ constexpr int ORDER[NF] = {GT + 0, GT + 1, GT + 2, GT + 3, GT + 4, GT + 5, GH + 
 template <int TX, int TY, int TZ, bool UPWIND>
 __global__ __launch_bounds__(TX * TY * TZ, MOL_CCZ4_WAVES) void ccz4_stage_kernel(StageArgs a, CczConst C)
 {
+    // halo tile in LDS: rows padded to a pitch of PX doubles.  A wave reads
+    // 8 rows of 8 doubles; with PX = 24 (= 8 mod 16 doubles) every group of
+    // rows served in one LDS cycle starts on distinct banks
     constexpr int HX = TX + 2 * G, HY = TY + 2 * G, HZ = TZ + 2 * G;
+    constexpr int PX = TX == 8 ? 24 : HX;
     constexpr int HV = HX * HY * HZ, NT = TX * TY * TZ, NR = (HV + NT - 1) / NT;
+    constexpr int LV = PX * HY * HZ;
     constexpr int NB = MOL_CCZ4_NBUF;  // LDS halo buffers (1 or 2)
-    __shared__ double buf[NB][HV];
+    __shared__ double buf[NB][LV];
     __shared__ double akx[NF][NT];  // advection + dissipation of every field
 
-    const Tile tile = a.tiles[blockIdx.x];
+    const Tile tile = a.tiles[xcd_tile(blockIdx.x, gridDim.x)];
     const PatchDev P = a.patches[tile.patch];
     const int tx = threadIdx.x, ty = threadIdx.y, tz = threadIdx.z;
     const int tid = tx + TX * (ty + TY * tz);
@@ -70,7 +75,7 @@ __global__ __launch_bounds__(TX * TY * TZ, MOL_CCZ4_WAVES) void ccz4_stage_kerne
     const int64_t fs = P.fs;
 
     // this thread's share of the halo-tile loads: offsets and in-box flags
-    int goff[NR];
+    int goff[NR], loff[NR];
     bool gok[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -79,6 +84,7 @@ __global__ __launch_bounds__(TX * TY * TZ, MOL_CCZ4_WAVES) void ccz4_stage_kerne
         gok[r] = e < HV && tile.o[0] + hx < P.n[0] + 2 * G && tile.o[1] + hy < P.n[1] + 2 * G &&
                  tile.o[2] + hz < P.n[2] + 2 * G;
         goff[r] = hz * P.pitch_z + hy * P.pitch_y + hx;
+        loff[r] = (hz * HY + hy) * PX + hx;
     }
     // register stages of the halo loads.  Two LDS buffers: the loads of field
     // q+2 are issued while field q is differentiated and field q+1 (loaded one
@@ -93,7 +99,7 @@ __global__ __launch_bounds__(TX * TY * TZ, MOL_CCZ4_WAVES) void ccz4_stage_kerne
     auto lstore = [&](int b, int slot) __attribute__((always_inline)) {
 #pragma unroll
         for (int r = 0; r < NR; ++r)
-            if (tid + r * NT < HV) buf[b][tid + r * NT] = stg[slot][r];
+            if (tid + r * NT < HV) buf[b][loff[r]] = stg[slot][r];
     };
 
     // ---- point values and the inverse conformal metric (global loads) ----
@@ -146,7 +152,7 @@ __global__ __launch_bounds__(TX * TY * TZ, MOL_CCZ4_WAVES) void ccz4_stage_kerne
     double dchi[3], dalp[3], DDa[6];    // chi and alpha gradients, nabla_i nabla_j alpha
     double db[3][3], gddb[3], gdiv[3];  // d_k beta^i, gt^jk d_j d_k beta^i, d_i (d_k beta^k)
     double rG[3];                       // Ghat^i terms with d Khat and d Theta
-    const int S[3] = {1, HX, HX * HY};
+    const int S[3] = {1, PX, PX * HY};
 
     gload(ORDER[0], 0);
     lstore(0, 0);
@@ -160,7 +166,7 @@ __global__ __launch_bounds__(TX * TY * TZ, MOL_CCZ4_WAVES) void ccz4_stage_kerne
         if constexpr (NB == 2 && q + 2 < NF) gload(ORDER[q + 2], q & 1);
         if constexpr (NB == 1 && q + 1 < NF) gload(ORDER[q + 1], 0);
         if (valid) {
-            const double* t = &buf[NB == 2 ? (q & 1) : 0][(tz + G) * HX * HY + (ty + G) * HX + tx + G];
+            const double* t = &buf[NB == 2 ? (q & 1) : 0][((tz + G) * HY + ty + G) * PX + tx + G];
             // advection beta^k d_k and KO dissipation of every field
             double adv = 0.0, ko = 0.0;
 #pragma unroll

@@ -6,8 +6,20 @@
 
 namespace mol {
 
-// Interior point handled by this thread inside tile blockIdx.x (or tile t);
-// returns false for the ragged tail.
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2): workgroup b runs on XCD b % 8.  Giving every XCD a contiguous range of
+// the tile list keeps spatially neighbouring tiles, whose halos overlap, in the
+// same L2.  Bijection of [0, n).
+__device__ __forceinline__ int xcd_tile(int b, int n)
+{
+    constexpr int NXCD = 8;
+    const int per = n / NXCD, rem = n % NXCD;
+    const int x = b % NXCD, slot = b / NXCD;
+    return x * per + (x < rem ? x : rem) + slot;
+}
+
+// Interior point handled by this thread inside tile `tile`; returns false for
+// the ragged tail.
 struct PointRef {
     int64_t c;     // level-buffer index of field 0 at the point
     int64_t fs;    // field stride

@@ -103,7 +103,7 @@ __global__ __launch_bounds__(256) void mhd_stage_kernel(StageArgs a, MhdConst C)
 {
     PointRef pr;
     int i, j, k, p;
-    if (!tile_point(a, blockIdx.x, pr, i, j, k, p)) return;
+    if (!tile_point(a, xcd_tile(blockIdx.x, gridDim.x), pr, i, j, k, p)) return;
     const double* u = a.Us + pr.c;
     const int s[3] = {1, pr.sy, pr.sz};
     double rhs[8];

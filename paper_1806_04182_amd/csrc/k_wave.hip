@@ -13,7 +13,7 @@ __global__ __launch_bounds__(256) void wave_stage_kernel(StageArgs a, double ih2
 {
     PointRef pr;
     int i, j, k, p;
-    if (!tile_point(a, blockIdx.x, pr, i, j, k, p)) return;
+    if (!tile_point(a, xcd_tile(blockIdx.x, gridDim.x), pr, i, j, k, p)) return;
     const double* phi = a.Us + pr.c;
     const double* pi = phi + pr.fs;
     const int s[3] = {1, pr.sy, pr.sz};
