@@ -31,20 +31,107 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(n=24, seconds_hint=20.0):
+def cpu_baseline(n=96, steps=2):
     """The oracle (single-threaded C) on a bounded sample of the same workload:
-    one RK4 step of an n^3 periodic patch with the same data recipe."""
-    import numpy as np
+    `steps` RK4 steps of the n^3 periodic patch with the same data recipe."""
     from oracle import oracle as O
     from paper_1806_04182_amd import synth
     dx = 2.0 / 96
     U = synth.embed(synth.ccz4_minkowski_noise((n, n, n), amp=1e-10, seed=0))
     t0 = time.perf_counter()
-    O.rk_run(O.CCZ4, O.RK4, U, dx, 0.25 * dx, 1, O.params())
+    O.rk_run(O.CCZ4, O.RK4, U, dx, 0.25 * dx, steps, O.params())
     dt = time.perf_counter() - t0
-    return {"value": n ** 3 * 4 / dt, "unit": "pt-stage/s", "cores": 1, "kind": "oracle",
-            "sample": f"one RK4 step (4 stages) of a {n}^3 periodic CCZ4 patch, same data recipe, "
-                      f"{dt:.1f} s wall on one host core"}
+    return {"value": n ** 3 * 4 * steps / dt, "unit": "pt-stage/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} RK4 steps ({4 * steps} stages) of the {n}^3 periodic CCZ4 patch, same data "
+                      f"recipe, {dt:.1f} s wall on one host core"}
+
+
+def fill_minkowski_noise(ps, level, U, seed):
+    """Minkowski plus 1e-10 uniform noise on every field of a level buffer
+    (device-side seeded generator; ghosts are filled by the first stage)."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    from paper_1806_04182_amd import synth
+    L = ps.layouts[level]
+    U.zero_()
+    for p, off in enumerate(L["offsets"]):
+        fs = L["fstrides"][p]
+        for f in range(25):
+            blk = U[off + f * fs: off + (f + 1) * fs]
+            blk.uniform_(-1e-10, 1e-10, generator=g)
+            blk.add_(float(synth.CCZ4_FLAT[f]))
+
+
+def amr_bench(M, steps=2):
+    """Three levels (R = 2, 3), 200 patches, BOR sub-cycling: one coarse step
+    as a captured HIP graph (batched: one launch per level and operation) vs
+    the same step with one launch per patch and operation, no graph."""
+    import torch
+    from paper_1806_04182_amd import synth
+    levels, N0, dx0 = synth.amr_three_levels(0)
+    t0 = time.perf_counter()
+    ps = M.Patchset(M.Hierarchy(N0, (-1, -1, -1), dx0, levels), M.System(M.MOL_CCZ4))
+    tbuild = time.perf_counter() - t0
+    log(f"bench: AMR patchset built in {tbuild:.1f} s")
+    st = ps.alloc_states()
+    for l in range(len(levels)):
+        fill_minkowski_noise(ps, l, st[l]["U"], 100 + l)
+    pts = [sum((hi[0] - lo[0] + 1) * (hi[1] - lo[1] + 1) * (hi[2] - lo[2] + 1) for lo, hi in b) for _, b in levels]
+    stages = 4 * pts[0] + 8 * pts[1] + 24 * pts[2]
+    dt0 = 0.25 * dx0
+    res = {}
+    g = ps.graph_create(st, dt0)
+    stream = torch.cuda.current_stream()
+    for mode in ("batched", "plain"):
+        run = (lambda: g.launch(stream)) if mode == "batched" else (lambda: ps.advance(st, dt0, M.MOL_PLAIN, stream))
+        run()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(steps):
+            run()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        res[mode] = {"ms_per_coarse_step": ms, "pt_stage_per_s": stages / (ms * 1e-3),
+                     "wall_ms_per_coarse_step": (time.perf_counter() - t0) * 1e3 / steps}
+        log(f"bench: AMR {mode}: {ms:.1f} ms per coarse step")
+    out = torch.zeros(5, dtype=torch.float64, device="cuda")
+    ps.norms(0, st[0]["U"], 18, 1.0, 0.6, out)
+    torch.cuda.synchronize()
+    res["batched_over_plain"] = res["plain"]["ms_per_coarse_step"] / res["batched"]["ms_per_coarse_step"]
+    res["config"] = {"levels": 3, "ratios": [2, 3], "patches": sum(len(b) for _, b in levels),
+                     "points_per_level": pts, "pt_stages_per_coarse_step": stages,
+                     "patch_interior_range": [16, 48], "host_schedule_build_s": tbuild,
+                     "nonfinite_after_run": int(out[4].item())}
+    del g
+    return res
+
+
+def adjoint_bench(M, n=64, nsteps=200, every=20):
+    """Wave 64^3, 200 RK4 steps, checkpoints every 20: forward (with the
+    objective) and backward (reverse sweep + initial-data VJP) times."""
+    import torch
+    from paper_1806_04182_amd.adjoint import sphere_objective
+    dx = 2.0 / n
+    ps = M.Patchset(M.single_patch((n, n, n), (-1, -1, -1), dx), M.System(M.MOL_WAVE, sigma=0.1))
+    p = torch.tensor([1.0, 0.2, 0.1, -0.05, 0.02], dtype=torch.float64, requires_grad=True)
+    sphere_objective(p, ps, 4, 0.25 * dx, 0.6, every)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = sphere_objective(p, ps, nsteps, 0.25 * dx, 0.6, every)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    J.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    fwd, bwd = t1 - t0, t2 - t1
+    return {"workload": f"wave_{n}^3_rk4_{nsteps}_steps_checkpoint_{every}", "fwd_s": fwd, "bwd_s": bwd,
+            "bwd_over_fwd": bwd / fwd, "fwd_plus_bwd_over_fwd": (fwd + bwd) / fwd,
+            "dJ_dA_minus_J": float(p.grad[0]) - float(J.detach()), "ccz4": None}
 
 
 def main():
@@ -54,7 +141,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=96)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=24)
+    ap.add_argument("--cpu-n", type=int, default=96)
+    ap.add_argument("--no-extras", action="store_true", help="skip the AMR and adjoint measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -141,12 +229,36 @@ def main():
                      "kernel": "ccz4_stage_kernel", "kernel_ms": kms,
                      "bytes_per_pt_stage": CCZ4_BYTES_PER_PT_STAGE},
     }
+    res["roofline"]["traffic"] = traffic_from_profile(pts)
+    if not args.no_extras:
+        log("bench: batched AMR hierarchy")
+        res["amr_plain_vs_batched"] = amr_bench(M)
+        log("bench: adjoint")
+        res["adjoint"] = adjoint_bench(M)
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle sample")
         res["cpu_baseline"] = cpu_baseline(args.cpu_n)
         res["cpu_baseline"]["host_cpu"] = _cpu_name()
         res["cpu_baseline"]["nproc"] = os.cpu_count()
     print(json.dumps(res), flush=True)
+
+
+def traffic_from_profile(pts):
+    """HBM bytes per stage launch of the CCZ4 kernel from the committed
+    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy
+    of known size), or None when the kernel source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "ccz4_stage_96cube_traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in ("k_ccz4.hip", "k_common.h", "molamr_int.h"):
+        h.update(open(os.path.join(ROOT, "paper_1806_04182_amd", "csrc", f), "rb").read())
+    if rec.get("source_sha256") != h.hexdigest() or rec.get("points") != pts:
+        return None
+    return rec["hbm_bytes_per_launch"]
 
 
 def _cpu_name():

@@ -156,7 +156,9 @@ int mol_rk_stage(mol_patchset* ps, int level, int scheme, int stage, double dt,
  * over the parent nodes around it (6 per axis, or the coincident node when
  * the fine index is a multiple of R), with w_j from the RK4 dense output and
  * the App. D fine increments.  Un_c and the k_c[4] are parent-level buffers
- * whose ghosts have been filled with mol_fill_ghosts. */
+ * whose ghosts have been filled with mol_fill_ghosts.  The parent stage state
+ * is staged in a band buffer owned by the patchset: mol_prolong calls on one
+ * patchset must not overlap in time. */
 int mol_prolong(mol_patchset* ps, int fine_level, int r, int stage,
                 const double* Un_c, const double* const* k_c, double* U_f, void* stream);
 

@@ -108,6 +108,10 @@ struct mol_patchset {
         DevArr<ProlongPt> pro;
         std::vector<int64_t> pro_by_patch;
         DevArr<double> lagw;  // Lagrange weights [R][6]
+        // parent points read by the prolongation stencils of this level
+        // (parent-level offset of field 0 and field stride)
+        DevArr<GhostImage> band;
+        std::vector<int64_t> band_by_patch;
         // injection into the parent level, grouped by fine patch
         DevArr<RestrictPt> rst;
         std::vector<int64_t> rst_by_patch;
@@ -117,6 +121,7 @@ struct mol_patchset {
     };
     Level L[MOL_MAX_LEVELS];
     double* scratch = nullptr;  // reduction partials
+    double* tband = nullptr;    // parent-level BOR stage state used by the prolongation
     int red_blocks = 256;
     hipStream_t capture_stream = nullptr;
 
@@ -129,12 +134,14 @@ struct mol_patchset {
             l.fill_img.release();
             l.pro.release();
             l.lagw.release();
+            l.band.release();
             l.rst.release();
             l.tiles.dev.release();
             l.gtiles.dev.release();
             l.ntiles.dev.release();
         }
         if (scratch) (void)hipFree(scratch);
+        if (tband) (void)hipFree(tband);
         if (capture_stream) (void)hipStreamDestroy(capture_stream);
     }
 };
@@ -354,6 +361,31 @@ int build(mol_patchset* ps, const mol_hierarchy_desc* h)
         lev.pro_by_patch[lev.pd.size()] = (int64_t)pro.size();
         if ((rc = lev.fill.upload(fill))) return rc;
         if ((rc = lev.pro.upload(pro))) return rc;
+        if (par) {
+            // every parent point that some stencil reads, once, grouped by the
+            // fine patch that first needs it (so per-patch launches cover it)
+            std::vector<uint8_t> mark((size_t)par->nelems, 0);
+            std::vector<GhostImage> band;
+            lev.band_by_patch.assign(lev.pd.size() + 1, 0);
+            std::vector<int64_t> fs_of(par->pd.size());
+            for (size_t p = 0; p < lev.pd.size(); ++p) {
+                lev.band_by_patch[p] = (int64_t)band.size();
+                for (int64_t t = lev.pro_by_patch[p]; t < (int64_t)(p + 1 < lev.pd.size() ? lev.pro_by_patch[p + 1] : pro.size()); ++t) {
+                    const ProlongPt& e = pro[t];
+                    for (int c = 0; c < (e.m[2] ? 6 : 1); ++c)
+                        for (int b = 0; b < (e.m[1] ? 6 : 1); ++b)
+                            for (int a = 0; a < (e.m[0] ? 6 : 1); ++a) {
+                                const int64_t o = e.cbase + (int64_t)c * e.cpz + (int64_t)b * e.cpy + a;
+                                if (!mark[o]) {
+                                    mark[o] = 1;
+                                    band.push_back(GhostImage{o, e.cfs});
+                                }
+                            }
+                }
+            }
+            lev.band_by_patch[lev.pd.size()] = (int64_t)band.size();
+            if ((rc = lev.band.upload(band))) return rc;
+        }
         // owner-gather form of the fill (for the adjoint)
         {
             std::vector<size_t> idx(fill.size());
@@ -428,6 +460,12 @@ int build(mol_patchset* ps, const mol_hierarchy_desc* h)
     }
     hipError_t e = hipMalloc(&ps->scratch, sizeof(double) * 8 * ps->red_blocks);
     if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+    int64_t tmax = 0;
+    for (int l = 0; l + 1 < ps->nlev; ++l) tmax = std::max(tmax, ps->L[l].nelems);
+    if (tmax > 0) {
+        e = hipMalloc(&ps->tband, sizeof(double) * tmax);
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+    }
     return MOL_OK;
 }
 
@@ -524,15 +562,20 @@ int prolong_impl(mol_patchset* ps, int fl, int r, int stage, const double* Unc,
     Level& lev = ps->L[fl];
     double w[4];
     bor_weights(lev.ratio, r, stage, w);
-    if (!plain) {
-        hipError_t e = launch_prolong(lev.pro.p, lev.pro.n, ps->sp.nf, lev.ratio, lev.lagw.p, w,
-                                      Unc, kc[0], kc[1], kc[2], kc[3], Uf, st);
-        return e == hipSuccess ? MOL_OK : hip_fail(e, "prolong launch");
+    const int nf = ps->sp.nf;
+    // BOR stage state on the parent band, then Lagrange interpolation from it
+    const int nl = plain ? (int)lev.pd.size() : 1;
+    for (int p = 0; p < nl; ++p) {
+        const int64_t b0 = plain ? lev.band_by_patch[p] : 0;
+        const int64_t bn = plain ? lev.band_by_patch[p + 1] - b0 : lev.band.n;
+        hipError_t e = launch_bor_band(lev.band.p + b0, bn, nf, w, Unc, kc[0], kc[1], kc[2], kc[3],
+                                       ps->tband, st);
+        if (e != hipSuccess) return hip_fail(e, "BOR band launch");
     }
-    for (size_t p = 0; p < lev.pd.size(); ++p) {
-        int64_t b = lev.pro_by_patch[p], n = lev.pro_by_patch[p + 1] - b;
-        hipError_t e = launch_prolong(lev.pro.p + b, n, ps->sp.nf, lev.ratio, lev.lagw.p, w, Unc,
-                                      kc[0], kc[1], kc[2], kc[3], Uf, st);
+    for (int p = 0; p < nl; ++p) {
+        const int64_t b0 = plain ? lev.pro_by_patch[p] : 0;
+        const int64_t bn = plain ? lev.pro_by_patch[p + 1] - b0 : lev.pro.n;
+        hipError_t e = launch_prolong(lev.pro.p + b0, bn, nf, lev.lagw.p, ps->tband, Uf, st);
         if (e != hipSuccess) return hip_fail(e, "prolong launch");
     }
     return MOL_OK;

@@ -48,47 +48,51 @@ struct BorW {
     double w[4];
 };
 
-// coarse-fine ghost point: tensor-product Lagrange interpolation (Sec. III.A)
-// of the parent's BOR stage state U^n + sum_j w_j k_j (App. D)
-__global__ __launch_bounds__(BLK) void prolong_kernel(const ProlongPt* __restrict__ e, int64_t n, int nf,
-                                                      const double* __restrict__ lw, BorW W,
-                                                      const double* __restrict__ Un,
-                                                      const double* __restrict__ k0,
-                                                      const double* __restrict__ k1,
-                                                      const double* __restrict__ k2,
-                                                      const double* __restrict__ k3,
-                                                      double* __restrict__ U)
+// parent BOR stage state (App. D) T = U^n + sum_j w_j k_j on the band of
+// parent points that the prolongation stencils read; one thread per (point, field)
+__global__ __launch_bounds__(BLK) void bor_band_kernel(const GhostImage* __restrict__ band, int64_t n, int nf,
+                                                       BorW W, const double* __restrict__ Un,
+                                                       const double* __restrict__ k0,
+                                                       const double* __restrict__ k1,
+                                                       const double* __restrict__ k2,
+                                                       const double* __restrict__ k3, double* __restrict__ T)
 {
-    for (int64_t t = blockIdx.x * (int64_t)BLK + threadIdx.x; t < n; t += (int64_t)gridDim.x * BLK) {
-        const ProlongPt p = e[t];
+    const int64_t tot = n * nf;
+    for (int64_t t = blockIdx.x * (int64_t)BLK + threadIdx.x; t < tot; t += (int64_t)gridDim.x * BLK) {
+        const int f = (int)(t / n);
+        const GhostImage b = band[t - (int64_t)f * n];
+        const int64_t q = b.dst + f * b.dfs;
+        T[q] = Un[q] + W.w[0] * k0[q] + W.w[1] * k1[q] + W.w[2] * k2[q] + W.w[3] * k3[q];
+    }
+}
+
+// coarse-fine ghost point: tensor-product Lagrange interpolation (Sec. III.A)
+// of the parent's BOR stage state; one thread per (ghost point, field)
+__global__ __launch_bounds__(BLK) void prolong_kernel(const ProlongPt* __restrict__ e, int64_t n, int nf,
+                                                      const double* __restrict__ lw,
+                                                      const double* __restrict__ T, double* __restrict__ U)
+{
+    const int64_t tot = n * nf;
+    for (int64_t t = blockIdx.x * (int64_t)BLK + threadIdx.x; t < tot; t += (int64_t)gridDim.x * BLK) {
+        const int f = (int)(t / n);
+        const ProlongPt p = e[t - (int64_t)f * n];
         const int cx = p.m[0] ? 6 : 1, cy = p.m[1] ? 6 : 1, cz = p.m[2] ? 6 : 1;
-        double wx[6], wy[6], wz[6];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            wx[q] = lw[p.m[0] * 6 + q];
-            wy[q] = lw[p.m[1] * 6 + q];
-            wz[q] = lw[p.m[2] * 6 + q];
-        }
-        for (int f = 0; f < nf; ++f) {
-            const int64_t base = p.cbase + f * p.cfs;
-            double sz = 0.0;
-            for (int c = 0; c < cz; ++c) {
-                double sy = 0.0;
-                for (int b = 0; b < cy; ++b) {
-                    const int64_t row = base + (int64_t)c * p.cpz + (int64_t)b * p.cpy;
-                    double sx = 0.0;
-                    for (int a = 0; a < cx; ++a) {
-                        const int64_t q = row + a;
-                        const double T = Un[q] + W.w[0] * k0[q] + W.w[1] * k1[q] + W.w[2] * k2[q] +
-                                         W.w[3] * k3[q];
-                        sx += wx[a] * T;
-                    }
-                    sy += wy[b] * sx;
-                }
-                sz += wz[c] * sy;
+        const double* wx = lw + p.m[0] * 6;
+        const double* wy = lw + p.m[1] * 6;
+        const double* wz = lw + p.m[2] * 6;
+        const int64_t base = p.cbase + f * p.cfs;
+        double sz = 0.0;
+        for (int c = 0; c < cz; ++c) {
+            double sy = 0.0;
+            for (int b = 0; b < cy; ++b) {
+                const double* row = T + base + (int64_t)c * p.cpz + (int64_t)b * p.cpy;
+                double sx = 0.0;
+                for (int a = 0; a < cx; ++a) sx += wx[a] * row[a];
+                sy += wy[b] * sx;
             }
-            U[p.dst + f * p.dfs] = sz;
+            sz += wz[c] * sy;
         }
+        U[p.dst + f * p.dfs] = sz;
     }
 }
 
@@ -125,15 +129,22 @@ hipError_t launch_fill_adjoint(const GhostSource* src, int64_t n, const GhostIma
     return hipGetLastError();
 }
 
-hipError_t launch_prolong(const ProlongPt* e, int64_t n, int nf, int R, const double* lw, const double w[4],
-                          const double* Un, const double* k0, const double* k1, const double* k2,
-                          const double* k3, double* U, hipStream_t s)
+hipError_t launch_bor_band(const GhostImage* band, int64_t n, int nf, const double w[4], const double* Un,
+                           const double* k0, const double* k1, const double* k2, const double* k3, double* T,
+                           hipStream_t s)
 {
-    (void)R;
     if (n <= 0) return hipSuccess;
     BorW W;
     for (int j = 0; j < 4; ++j) W.w[j] = w[j];
-    prolong_kernel<<<grid_for(n), BLK, 0, s>>>(e, n, nf, lw, W, Un, k0, k1, k2, k3, U);
+    bor_band_kernel<<<grid_for(n * nf), BLK, 0, s>>>(band, n, nf, W, Un, k0, k1, k2, k3, T);
+    return hipGetLastError();
+}
+
+hipError_t launch_prolong(const ProlongPt* e, int64_t n, int nf, const double* lw, const double* T, double* U,
+                          hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    prolong_kernel<<<grid_for(n * nf), BLK, 0, s>>>(e, n, nf, lw, T, U);
     return hipGetLastError();
 }
 

@@ -171,3 +171,54 @@ def ccz4_lapse_pulse(n, xlo, dx, amp=0.1, width=0.2, centre=(0.0, 0.0, 0.0), lo=
         out[f] = CCZ4_FLAT[f]
     out[18] = 1.0 + amp * np.broadcast_to(np.exp(-r2 / width ** 2), shape)
     return out
+
+
+# ------------------------------------------------------------ hierarchies
+
+def composition(total: int, parts: int, lo: int, hi: int, rng) -> list[int]:
+    """Random composition of `total` into `parts` integers in [lo, hi]."""
+    assert parts * lo <= total <= parts * hi
+    out = [total // parts] * parts
+    for i in range(total % parts):
+        out[i] += 1
+    for _ in range(8 * parts):
+        i, j = rng.integers(0, parts, 2)
+        d = int(rng.integers(1, 9))
+        if i != j and out[i] - d >= lo and out[j] + d <= hi:
+            out[i] -= d
+            out[j] += d
+    return out
+
+
+def tiled_boxes(start, sizes_per_axis):
+    """Boxes tiling the region that starts at `start` with the given segment
+    lengths per axis (x fastest)."""
+    edges = []
+    for d in range(3):
+        e = [start[d]]
+        for s in sizes_per_axis[d]:
+            e.append(e[-1] + s)
+        edges.append(e)
+    boxes = []
+    for k in range(len(sizes_per_axis[2])):
+        for j in range(len(sizes_per_axis[1])):
+            for i in range(len(sizes_per_axis[0])):
+                lo = (edges[0][i], edges[1][j], edges[2][k])
+                hi = (edges[0][i + 1] - 1, edges[1][j + 1] - 1, edges[2][k + 1] - 1)
+                boxes.append((lo, hi))
+    return boxes
+
+
+def amr_three_levels(seed: int = 0):
+    """Three-level hierarchy on [-1, 1)^3: level 0 = 128^3 tiled 4x4x4; level 1
+    (ratio 2) = 128^3 fine points centred, tiled 4x4x4; level 2 (ratio 3) =
+    192 x 132 x 96 fine points centred, tiled 6x4x3.  Segment lengths per
+    axis are seeded random compositions with parts in [16, 48]; 200 patches."""
+    rng = np.random.default_rng(seed)
+    l0 = tiled_boxes((0, 0, 0), [composition(128, 4, 16, 48, rng) for _ in range(3)])
+    l1 = tiled_boxes((64, 64, 64), [composition(128, 4, 16, 48, rng) for _ in range(3)])
+    ext2 = (192, 132, 96)
+    start2 = tuple((768 - e) // 2 for e in ext2)
+    l2 = tiled_boxes(start2, [composition(ext2[0], 6, 16, 48, rng), composition(ext2[1], 4, 16, 48, rng),
+                              composition(ext2[2], 3, 16, 48, rng)])
+    return [(1, l0), (2, l1), (3, l2)], (128, 128, 128), 2.0 / 128
