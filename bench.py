@@ -134,6 +134,73 @@ def adjoint_bench(M, n=64, nsteps=200, every=20):
             "dJ_dA_minus_J": float(p.grad[0]) - float(J.detach()), "ccz4": None}
 
 
+def stage_kernel_time(ps, M, st, scheme, dt, reps=10):
+    """Average duration of the fused stage kernel alone (HIP events on the
+    launch stream), cycling through the scheme's stages."""
+    import torch
+    stream = torch.cuda.current_stream()
+    U, a, b, acc = st[0]["U"], st[0]["S0"], st[0]["S1"], st[0]["acc"]
+    ps.fill_ghosts(0, U, stream=stream)
+    seq = ([(1, U, a), (2, a, b), (3, b, a), (4, a, b)] if scheme == M.MOL_RK4
+           else [(1, U, a), (2, a, b), (3, b, a)])
+    def run(n):
+        for _ in range(n):
+            for s, Us, Uo in seq:
+                ps.rk_stage(0, scheme, s, dt, U, Us, acc, Uo, stream=stream)
+    run(1)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    run(reps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / (reps * len(seq))
+
+
+def wave_mhd_bench(M):
+    """Secondary paths: the scalar wave (32^3, 20 steps; and 256^3, where the
+    state is far larger than the caches) and MHD (128^3, SSP-RK3)."""
+    import torch
+    from paper_1806_04182_amd import synth
+    out = {}
+    for n in (32, 256):
+        dx = 2.0 / n
+        ps = M.Patchset(M.single_patch((n, n, n), (-1, -1, -1), dx), M.System(M.MOL_WAVE, sigma=0.1))
+        st = ps.alloc_states()
+        ps.wave_gaussian(0, [1.0, 0.2, *synth.wave_centre(0)], st[0]["U"])
+        g = ps.graph_create(st, 0.25 * dx)
+        stream = torch.cuda.current_stream()
+        g.launch(stream)
+        torch.cuda.synchronize()
+        steps = 20
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            g.launch(stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        kms = stage_kernel_time(ps, M, st, M.MOL_RK4, 0.25 * dx)
+        gbs = 68.0 * n ** 3 / (kms * 1e-3) / 1e9
+        out[f"wave_{n}^3"] = {"pt_stage_per_s": n ** 3 * 4 / (ms * 1e-3), "ms_per_step": ms,
+                               "stage_kernel_ms": kms, "stage_kernel_GBs_algorithmic": gbs,
+                               "hbm_frac": gbs / HBM_PEAK_GBS, "bytes_per_pt_stage": 68.0}
+        del g
+    n = 128
+    dx = 1.0 / n
+    ps = M.Patchset(M.single_patch((n, n, n), (0, 0, 0), dx), M.System(M.MOL_MHD, sigma=0.0))
+    st = ps.alloc_states()
+    st[0]["U"].copy_(torch.from_numpy(ps.pack(0, [synth.embed(synth.mhd_ot_like((n, n, n), seed=0))])))
+    kms = stage_kernel_time(ps, M, st, M.MOL_SSPRK3, 0.2 * dx)
+    gbs = 171.0 * n ** 3 / (kms * 1e-3) / 1e9
+    out["mhd_128^3"] = {"pt_stage_per_s": n ** 3 / (kms * 1e-3), "stage_kernel_ms": kms,
+                        "stage_kernel_GBs_algorithmic": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+                        "bytes_per_pt_stage": 171.0}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -235,6 +302,8 @@ def main():
         res["amr_plain_vs_batched"] = amr_bench(M)
         log("bench: adjoint")
         res["adjoint"] = adjoint_bench(M)
+        log("bench: wave and MHD paths")
+        res["other_paths"] = wave_mhd_bench(M)
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle sample")
         res["cpu_baseline"] = cpu_baseline(args.cpu_n)

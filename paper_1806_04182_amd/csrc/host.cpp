@@ -223,11 +223,24 @@ void build_tiles(const Level& lev, const int td[3], int margin, TileList& tl)
     tl.dev.upload(v);
 }
 
-void default_tile(int system, int td[3])
+// Tile of the stage kernels.  Wave: levels of at least 2^21 points march
+// along z (64 x 4 columns, chunk length chosen so that the launch still has
+// about 2048 workgroups); smaller levels use one thread per point.
+void default_tile(int system, int64_t level_points, int td[3])
 {
     switch (system) {
-    case MOL_WAVE: td[0] = 32; td[1] = 4; td[2] = 2; break;
-    case MOL_MHD: td[0] = 16; td[1] = 4; td[2] = 4; break;
+    case MOL_WAVE:
+        if (level_points >= (int64_t(1) << 21)) {
+            td[0] = 64;
+            td[1] = 4;
+            td[2] = (int)std::max<int64_t>(4, std::min<int64_t>(32, level_points / (64 * 4 * 2048)));
+        } else {
+            td[0] = 32;
+            td[1] = 4;
+            td[2] = 2;
+        }
+        break;
+    case MOL_MHD: td[0] = 15; td[1] = 15; td[2] = 8; break;  // 15 x 15 columns, 8 planes (z-marching)
     default: td[0] = MOL_CCZ4_TX; td[1] = MOL_CCZ4_TY; td[2] = MOL_CCZ4_TZ; break;
     }
 }
@@ -451,7 +464,9 @@ int build(mol_patchset* ps, const mol_hierarchy_desc* h)
             if ((rc = lev.rst.upload(rst))) return rc;
         }
         int td[3];
-        default_tile(ps->sp.system, td);
+        int64_t npts = 0;
+        for (const PatchDev& pd : lev.pd) npts += (int64_t)pd.n[0] * pd.n[1] * pd.n[2];
+        default_tile(ps->sp.system, npts, td);
         build_tiles(lev, td, 0, lev.tiles);
         int tg[3] = {16, 4, 4};
         build_tiles(lev, tg, G, lev.gtiles);

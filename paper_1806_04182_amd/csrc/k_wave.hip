@@ -28,6 +28,70 @@ __global__ __launch_bounds__(256) void wave_stage_kernel(StageArgs a, double ih2
     stage_store(a, pr.c + pr.fs, -ih2 * lap + ko * qpi);
 }
 
+// Large levels: a workgroup of WX x WY threads owns WX x WY columns and marches
+// along z over zc planes.  z-neighbours come from a 7-value register queue per
+// field (each value is read from memory once per column); x/y neighbours from
+// the current plane staged in LDS, whose interior part is written from the
+// queues and whose 3-point halo is loaded from memory.
+constexpr int WX = 64, WY = 4, WHX = WX + 6, WHY = WY + 6, WPX = WHX + 2;
+
+__global__ __launch_bounds__(WX * WY) void wave_zmarch_kernel(StageArgs a, double ih2, double ko, int zc)
+{
+    __shared__ double pl[2][WHY][WPX];
+    const Tile tile = a.tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    const PatchDev P = a.patches[tile.patch];
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + WX * ty;
+    const int x0 = tile.o[0], y0 = tile.o[1], z0 = tile.o[2];
+    const int z1 = min(z0 + zc, P.n[2]);
+    const int sz = P.pitch_z;
+    const bool col = x0 + tx < P.n[0] && y0 + ty < P.n[1];
+    const int64_t cb = P.off + (int64_t)(y0 + ty + G) * P.pitch_y + (x0 + tx + G);
+    const double* __restrict__ U = a.Us;
+    double qp[7], qq[7];  // phi and Pi at z = k-3 .. k+3
+    if (col)
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+            qp[m] = U[cb + (int64_t)(z0 - 3 + m + G) * sz];
+            qq[m] = U[cb + P.fs + (int64_t)(z0 - 3 + m + G) * sz];
+        }
+    for (int k = z0; k < z1; ++k) {
+        const int64_t pc = (int64_t)(k + G) * sz;
+        if (col) {
+            qp[6] = U[cb + pc + 3 * (int64_t)sz];
+            qq[6] = U[cb + P.fs + pc + 3 * (int64_t)sz];
+            pl[0][ty + G][tx + G] = qp[3];
+            pl[1][ty + G][tx + G] = qq[3];
+        }
+        // the rest of the plane: the 3-point halo, and the cells of the block
+        // that lie beyond the patch interior (ragged tail: ghosts or unused)
+        const int64_t hb = P.off + pc + (int64_t)y0 * P.pitch_y + x0;
+        for (int e = tid; e < WHX * WHY; e += WX * WY) {
+            const int hy = e / WHX, hx = e - hy * WHX;
+            if (hx >= G && hx < G + WX && hy >= G && hy < G + WY && x0 + hx - G < P.n[0] && y0 + hy - G < P.n[1])
+                continue;
+            const bool ok = x0 + hx < P.n[0] + 2 * G && y0 + hy < P.n[1] + 2 * G;
+            pl[0][hy][hx] = ok ? U[hb + (int64_t)hy * P.pitch_y + hx] : 0.0;
+            pl[1][hy][hx] = ok ? U[hb + P.fs + (int64_t)hy * P.pitch_y + hx] : 0.0;
+        }
+        __syncthreads();
+        if (col) {
+            const double* p = &pl[0][ty + G][tx + G];
+            const double* q = &pl[1][ty + G][tx + G];
+            double lap = fd2(p, 1) + fd2(p, WPX) + fd2(qp + 3, 1);
+            double qphi = fko(p, 1) + fko(p, WPX) + fko(qp + 3, 1);
+            double qpi = fko(q, 1) + fko(q, WPX) + fko(qq + 3, 1);
+            stage_store(a, cb + pc, -q[0] + ko * qphi);
+            stage_store(a, cb + pc + P.fs, -ih2 * lap + ko * qpi);
+#pragma unroll
+            for (int m = 0; m < 6; ++m) {
+                qp[m] = qp[m + 1];
+                qq[m] = qq[m + 1];
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // lamU(p) = sum_c lam(c) dR(c)/dU(p): the stencils are symmetric, so the
 // transpose reads lam at the same offsets, restricted to interior points.
 __global__ __launch_bounds__(256) void wave_adjoint_kernel(const PatchDev* __restrict__ patches,
@@ -90,7 +154,10 @@ hipError_t launch_stage_wave(const SysParams& sp, const StageArgs& a, const int 
     if (a.ntiles <= 0) return hipSuccess;
     const double ih2 = 1.0 / (12.0 * sp.h * sp.h);
     const double ko = sp.sigma / (64.0 * sp.h);
-    wave_stage_kernel<<<a.ntiles, dim3(td[0], td[1], td[2]), 0, s>>>(a, ih2, ko);
+    if (td[0] == WX && td[1] == WY && td[2] > 1)
+        wave_zmarch_kernel<<<a.ntiles, dim3(WX, WY, 1), 0, s>>>(a, ih2, ko, td[2]);
+    else
+        wave_stage_kernel<<<a.ntiles, dim3(td[0], td[1], td[2]), 0, s>>>(a, ih2, ko);
     return hipGetLastError();
 }
 
