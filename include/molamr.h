@@ -155,8 +155,9 @@ int mol_rk_stage(mol_patchset* ps, int level, int scheme, int stage, double dt,
  *   sum_{a,b,c} L_a(xi_x) L_b(xi_y) L_c(xi_z) [Un_c + sum_j w_j(R,r,s) k_c[j]]
  * over the parent nodes around it (6 per axis, or the coincident node when
  * the fine index is a multiple of R), with w_j from the RK4 dense output and
- * the App. D fine increments.  Un_c and the k_c[4] are parent-level buffers
- * whose ghosts have been filled with mol_fill_ghosts.  The parent stage state
+ * the App. D fine increments.  Un_c and the k_c[4] are parent-level buffers;
+ * only their interior values are read (each parent node is taken from the
+ * patch whose interior owns it).  The parent stage state
  * is staged in a band buffer owned by the patchset: mol_prolong calls on one
  * patchset must not overlap in time. */
 int mol_prolong(mol_patchset* ps, int fine_level, int r, int stage,

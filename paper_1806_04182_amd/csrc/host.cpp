@@ -107,10 +107,11 @@ struct mol_patchset {
         // coarse-fine ghost points (this level is the fine one), by dst patch
         DevArr<ProlongPt> pro;
         std::vector<int64_t> pro_by_patch;
-        DevArr<double> lagw;  // Lagrange weights [R][6]
-        // parent points read by the prolongation stencils of this level
-        // (parent-level offset of field 0 and field stride)
-        DevArr<GhostImage> band;
+        std::vector<double> lagw;  // Lagrange weights [R][6]
+        // parent points read by the prolongation stencils of this level: the
+        // position in a parent patch's ghosted box (dst) and the interior
+        // point that owns it (src)
+        DevArr<GhostCopy> band;
         std::vector<int64_t> band_by_patch;
         // injection into the parent level, grouped by fine patch
         DevArr<RestrictPt> rst;
@@ -133,7 +134,6 @@ struct mol_patchset {
             l.fill_src.release();
             l.fill_img.release();
             l.pro.release();
-            l.lagw.release();
             l.band.release();
             l.rst.release();
             l.tiles.dev.release();
@@ -378,7 +378,12 @@ int build(mol_patchset* ps, const mol_hierarchy_desc* h)
             // every parent point that some stencil reads, once, grouped by the
             // fine patch that first needs it (so per-patch launches cover it)
             std::vector<uint8_t> mark((size_t)par->nelems, 0);
-            std::vector<GhostImage> band;
+            std::vector<GhostCopy> band;
+            // parent patch of each band position: patch blocks are contiguous and ordered
+            std::vector<int64_t> pstart(par->pd.size());
+            for (size_t q = 0; q < par->pd.size(); ++q) pstart[q] = par->pd[q].off;
+            std::vector<int> allpar2;
+            for (size_t q = 0; q < par->boxes.size(); ++q) allpar2.push_back((int)q);
             lev.band_by_patch.assign(lev.pd.size() + 1, 0);
             std::vector<int64_t> fs_of(par->pd.size());
             for (size_t p = 0; p < lev.pd.size(); ++p) {
@@ -391,7 +396,22 @@ int build(mol_patchset* ps, const mol_hierarchy_desc* h)
                                 const int64_t o = e.cbase + (int64_t)c * e.cpz + (int64_t)b * e.cpy + a;
                                 if (!mark[o]) {
                                     mark[o] = 1;
-                                    band.push_back(GhostImage{o, e.cfs});
+                                    // global index of this ghosted-box position, and its owner
+                                    const size_t q = (size_t)(std::upper_bound(pstart.begin(), pstart.end(), o) -
+                                                              pstart.begin()) - 1;
+                                    const PatchDev& qd = par->pd[q];
+                                    const int64_t loc = o - qd.off;
+                                    const int lz = (int)(loc / qd.pitch_z), ly = (int)((loc % qd.pitch_z) / qd.pitch_y),
+                                              lx = (int)(loc % qd.pitch_y);
+                                    int g[3] = {qd.lo[0] + lx - G, qd.lo[1] + ly - G, qd.lo[2] + lz - G}, gw[3];
+                                    const int own = find_owner(*par, g, allpar2, gw);
+                                    if (own < 0)
+                                        return fail(MOL_EINVAL, "level %d: prolongation stencil leaves the parent level", l);
+                                    const PatchDev& od = par->pd[own];
+                                    band.push_back(GhostCopy{o,
+                                                             od.off + local_index(od, gw[0] - od.lo[0] + G,
+                                                                                  gw[1] - od.lo[1] + G, gw[2] - od.lo[2] + G),
+                                                             qd.fs, od.fs});
                                 }
                             }
                 }
@@ -434,7 +454,7 @@ int build(mol_patchset* ps, const mol_hierarchy_desc* h)
                     lw[m * 6 + j] = num / den;
                 }
             }
-            if ((rc = lev.lagw.upload(lw))) return rc;
+            lev.lagw = lw;
             // injection: coarse interior points that coincide with fine interior points
             std::vector<RestrictPt> rst;
             lev.rst_by_patch.assign(lev.pd.size() + 1, 0);
@@ -590,7 +610,7 @@ int prolong_impl(mol_patchset* ps, int fl, int r, int stage, const double* Unc,
     for (int p = 0; p < nl; ++p) {
         const int64_t b0 = plain ? lev.pro_by_patch[p] : 0;
         const int64_t bn = plain ? lev.pro_by_patch[p + 1] - b0 : lev.pro.n;
-        hipError_t e = launch_prolong(lev.pro.p + b0, bn, nf, lev.lagw.p, ps->tband, Uf, st);
+        hipError_t e = launch_prolong(lev.pro.p + b0, bn, nf, lev.ratio, lev.lagw.data(), ps->tband, Uf, st);
         if (e != hipSuccess) return hip_fail(e, "prolong launch");
     }
     return MOL_OK;
@@ -636,8 +656,6 @@ int advance_level(mol_patchset* ps, const mol_level_state* st, int l, int r, dou
             return rc;
     }
     if (kids) {
-        for (int j = 0; j < 4; ++j)
-            if ((rc = fill_impl(ps, l, X.k[j], nf, s, plain))) return rc;
         const int R = ps->L[l + 1].ratio;
         for (int rr = 0; rr < R; ++rr)
             if ((rc = advance_level(ps, st, l + 1, rr, dt / R, s, plain))) return rc;

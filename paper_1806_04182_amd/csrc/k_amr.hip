@@ -49,8 +49,11 @@ struct BorW {
 };
 
 // parent BOR stage state (App. D) T = U^n + sum_j w_j k_j on the band of
-// parent points that the prolongation stencils read; one thread per (point, field)
-__global__ __launch_bounds__(BLK) void bor_band_kernel(const GhostImage* __restrict__ band, int64_t n, int nf,
+// parent points that the prolongation stencils read.  A band entry writes T at
+// its position in some parent patch's ghosted box (dst) from the interior
+// point that owns it (src), so the parent's k arrays need no ghost fill.
+// One thread per (point, field).
+__global__ __launch_bounds__(BLK) void bor_band_kernel(const GhostCopy* __restrict__ band, int64_t n, int nf,
                                                        BorW W, const double* __restrict__ Un,
                                                        const double* __restrict__ k0,
                                                        const double* __restrict__ k1,
@@ -60,16 +63,20 @@ __global__ __launch_bounds__(BLK) void bor_band_kernel(const GhostImage* __restr
     const int64_t tot = n * nf;
     for (int64_t t = blockIdx.x * (int64_t)BLK + threadIdx.x; t < tot; t += (int64_t)gridDim.x * BLK) {
         const int f = (int)(t / n);
-        const GhostImage b = band[t - (int64_t)f * n];
-        const int64_t q = b.dst + f * b.dfs;
-        T[q] = Un[q] + W.w[0] * k0[q] + W.w[1] * k1[q] + W.w[2] * k2[q] + W.w[3] * k3[q];
+        const GhostCopy b = band[t - (int64_t)f * n];
+        const int64_t q = b.src + f * b.sfs;
+        T[b.dst + f * b.dfs] = Un[q] + W.w[0] * k0[q] + W.w[1] * k1[q] + W.w[2] * k2[q] + W.w[3] * k3[q];
     }
 }
 
+// Lagrange weights at xi = m / R, m = 0 .. R-1 (row 0: the coincident copy)
+struct LagW {
+    double w[4][6];
+};
+
 // coarse-fine ghost point: tensor-product Lagrange interpolation (Sec. III.A)
 // of the parent's BOR stage state; one thread per (ghost point, field)
-__global__ __launch_bounds__(BLK) void prolong_kernel(const ProlongPt* __restrict__ e, int64_t n, int nf,
-                                                      const double* __restrict__ lw,
+__global__ __launch_bounds__(BLK) void prolong_kernel(const ProlongPt* __restrict__ e, int64_t n, int nf, LagW L,
                                                       const double* __restrict__ T, double* __restrict__ U)
 {
     const int64_t tot = n * nf;
@@ -77,9 +84,9 @@ __global__ __launch_bounds__(BLK) void prolong_kernel(const ProlongPt* __restric
         const int f = (int)(t / n);
         const ProlongPt p = e[t - (int64_t)f * n];
         const int cx = p.m[0] ? 6 : 1, cy = p.m[1] ? 6 : 1, cz = p.m[2] ? 6 : 1;
-        const double* wx = lw + p.m[0] * 6;
-        const double* wy = lw + p.m[1] * 6;
-        const double* wz = lw + p.m[2] * 6;
+        const double* wx = L.w[p.m[0]];
+        const double* wy = L.w[p.m[1]];
+        const double* wz = L.w[p.m[2]];
         const int64_t base = p.cbase + f * p.cfs;
         double sz = 0.0;
         for (int c = 0; c < cz; ++c) {
@@ -87,7 +94,12 @@ __global__ __launch_bounds__(BLK) void prolong_kernel(const ProlongPt* __restric
             for (int b = 0; b < cy; ++b) {
                 const double* row = T + base + (int64_t)c * p.cpz + (int64_t)b * p.cpy;
                 double sx = 0.0;
-                for (int a = 0; a < cx; ++a) sx += wx[a] * row[a];
+                if (cx == 6) {
+#pragma unroll
+                    for (int a = 0; a < 6; ++a) sx += wx[a] * row[a];
+                } else {
+                    sx = row[0];
+                }
                 sy += wy[b] * sx;
             }
             sz += wz[c] * sy;
@@ -129,7 +141,7 @@ hipError_t launch_fill_adjoint(const GhostSource* src, int64_t n, const GhostIma
     return hipGetLastError();
 }
 
-hipError_t launch_bor_band(const GhostImage* band, int64_t n, int nf, const double w[4], const double* Un,
+hipError_t launch_bor_band(const GhostCopy* band, int64_t n, int nf, const double w[4], const double* Un,
                            const double* k0, const double* k1, const double* k2, const double* k3, double* T,
                            hipStream_t s)
 {
@@ -140,11 +152,15 @@ hipError_t launch_bor_band(const GhostImage* band, int64_t n, int nf, const doub
     return hipGetLastError();
 }
 
-hipError_t launch_prolong(const ProlongPt* e, int64_t n, int nf, const double* lw, const double* T, double* U,
-                          hipStream_t s)
+hipError_t launch_prolong(const ProlongPt* e, int64_t n, int nf, int R, const double* lw_host, const double* T,
+                          double* U, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    prolong_kernel<<<grid_for(n * nf), BLK, 0, s>>>(e, n, nf, lw, T, U);
+    if (R < 1 || R > 4) return hipErrorInvalidValue;
+    LagW L{};
+    for (int m = 0; m < R; ++m)
+        for (int j = 0; j < 6; ++j) L.w[m][j] = lw_host[m * 6 + j];
+    prolong_kernel<<<grid_for(n * nf), BLK, 0, s>>>(e, n, nf, L, T, U);
     return hipGetLastError();
 }
 

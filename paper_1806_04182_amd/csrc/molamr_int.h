@@ -128,11 +128,11 @@ inline hipError_t launch_stage(const SysParams& sp, const StageArgs& a, const in
 hipError_t launch_fill(const GhostCopy* e, int64_t n, int nf, double* U, hipStream_t s);
 hipError_t launch_fill_adjoint(const GhostSource* src, int64_t nsrc, const GhostImage* img,
                                int nf, double* A, hipStream_t s);
-hipError_t launch_bor_band(const GhostImage* band, int64_t n, int nf, const double w[4], const double* Un,
+hipError_t launch_bor_band(const GhostCopy* band, int64_t n, int nf, const double w[4], const double* Un,
                            const double* k0, const double* k1, const double* k2, const double* k3, double* T,
                            hipStream_t s);
-hipError_t launch_prolong(const ProlongPt* e, int64_t n, int nf, const double* lw, const double* T, double* U,
-                          hipStream_t s);
+hipError_t launch_prolong(const ProlongPt* e, int64_t n, int nf, int R, const double* lw_host, const double* T,
+                          double* U, hipStream_t s);
 hipError_t launch_restrict(const RestrictPt* e, int64_t n, int nf, const double* Uf, double* Uc,
                            hipStream_t s);
 hipError_t launch_wave_adjoint(const SysParams& sp, const PatchDev* patches, const Tile* tiles,
