@@ -12,13 +12,15 @@
 //
 // Kernel organisation (gfx950): one workgroup of 256 threads owns a tile of
 // TX x TY x TZ points.  The 25 fields are streamed through LDS one at a time
-// (tile plus a 3-point halo, double buffered: the next field's global loads
-// are in flight while the current one is differentiated).  Each field's
-// derivatives are consumed as soon as they arrive (Christoffel symbols after
-// the six metric components, Ricci terms after Ghat and chi, the lapse
-// Hessian after alpha, ...), so only the partial sums stay live.  Advection
-// and dissipation of every field are parked in LDS until the algebra that
-// needs all fields is done; then the RK stage update writes the results.
+// (tile plus a 3-point halo; the next field's global loads are in flight
+// while the current one is differentiated).  Each field's derivatives are
+// consumed as soon as they arrive (Christoffel symbols after the six metric
+// components, Ricci terms after chi and Ghat, the lapse Hessian after alpha,
+// ...), and point values that are needed only late are taken from LDS when
+// their field passes, so that only partial sums stay live and the kernel
+// fits 256 registers per lane without spilling.  Advection and dissipation of
+// every field are parked in LDS until the algebra that needs all fields is
+// done; then the RK stage update writes the results.
 #include <utility>
 
 #include "k_common.h"
@@ -46,9 +48,9 @@ struct CczConst {
 };
 
 // order in which the fields pass through LDS
-constexpr int ORDER[NF] = {GT + 0, GT + 1, GT + 2, GT + 3, GT + 4, GT + 5, GH + 0, GH + 1, GH + 2,
-                                      CHI,    ALP,    BETA + 0, BETA + 1, BETA + 2, KH, TH,
-                                      AT + 0, AT + 1, AT + 2, AT + 3, AT + 4, AT + 5, BB + 0, BB + 1, BB + 2};
+constexpr int ORDER[NF] = {GT + 0, GT + 1, GT + 2,   GT + 3,   GT + 4,   GT + 5, CHI,    ALP, AT + 0,
+                           AT + 1, AT + 2, AT + 3,   AT + 4,   AT + 5,   GH + 0, GH + 1, GH + 2,
+                           BETA + 0, BETA + 1, BETA + 2, KH,     TH,     BB + 0, BB + 1, BB + 2};
 
 template <int TX, int TY, int TZ, bool UPWIND>
 __global__ __launch_bounds__(TX * TY * TZ, MOL_CCZ4_WAVES) void ccz4_stage_kernel(StageArgs a, CczConst C)
@@ -58,10 +60,13 @@ __global__ __launch_bounds__(TX * TY * TZ, MOL_CCZ4_WAVES) void ccz4_stage_kerne
     // rows served in one LDS cycle starts on distinct banks
     constexpr int HX = TX + 2 * G, HY = TY + 2 * G, HZ = TZ + 2 * G;
     constexpr int PX = TX == 8 ? 24 : HX;
-    constexpr int HV = HX * HY * HZ, NT = TX * TY * TZ, NR = (HV + NT - 1) / NT;
+    constexpr int NT = TX * TY * TZ;
+    // halo loads: 16 lanes per row (x), NT / 16 rows per pass covering PP
+    // whole planes, NR passes; the offset between passes is a constant
+    constexpr int LW = 16, PP = (NT / LW) / HY, NR = (HZ + PP - 1) / PP;
+    static_assert(HX <= LW && PP >= 1, "halo row wider than 16 or tile plane too large");
     constexpr int LV = PX * HY * HZ;
-    constexpr int NB = MOL_CCZ4_NBUF;  // LDS halo buffers (1 or 2)
-    __shared__ double buf[NB][LV];
+    __shared__ double buf[LV];
     __shared__ double akx[NF][NT];  // advection + dissipation of every field
 
     const Tile tile = a.tiles[xcd_tile(blockIdx.x, gridDim.x)];
@@ -74,43 +79,33 @@ __global__ __launch_bounds__(TX * TY * TZ, MOL_CCZ4_WAVES) void ccz4_stage_kerne
     const int64_t c = hbase + (int64_t)(tz + G) * P.pitch_z + (int64_t)(ty + G) * P.pitch_y + (tx + G);
     const int64_t fs = P.fs;
 
-    // this thread's share of the halo-tile loads: offsets and in-box flags
-    int goff[NR], loff[NR];
-    bool gok[NR];
+    // this thread's halo element in the first pass; pass r adds PP planes
+    const int lx = tid % LW, ly = tid / LW, hy = ly % HY, hz0 = ly / HY;
+    const bool lane = lx < HX && ly < PP * HY && tile.o[0] + lx < P.n[0] + 2 * G && tile.o[1] + hy < P.n[1] + 2 * G;
+    const int gl = hz0 * P.pitch_z + hy * P.pitch_y + lx;
+    const int ll = (hz0 * HY + hy) * PX + lx;
+    const int hzmax = P.n[2] + 2 * G - tile.o[2];  // halo planes inside the ghosted box
+    double stg[NR];
+    auto gload = [&](int f) __attribute__((always_inline)) {
+        const double* src = a.Us + hbase + (int64_t)f * fs + gl;
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        const int e = tid + r * NT;
-        const int hx = e % HX, hy = (e / HX) % HY, hz = e / (HX * HY);
-        gok[r] = e < HV && tile.o[0] + hx < P.n[0] + 2 * G && tile.o[1] + hy < P.n[1] + 2 * G &&
-                 tile.o[2] + hz < P.n[2] + 2 * G;
-        goff[r] = hz * P.pitch_z + hy * P.pitch_y + hx;
-        loff[r] = (hz * HY + hy) * PX + hx;
-    }
-    // register stages of the halo loads.  Two LDS buffers: the loads of field
-    // q+2 are issued while field q is differentiated and field q+1 (loaded one
-    // iteration earlier) is moved to LDS.  One LDS buffer: the loads of field
-    // q+1 are in flight while field q is differentiated.
-    double stg[NB][NR];
-    auto gload = [&](int f, int slot) __attribute__((always_inline)) {
-        const double* src = a.Us + hbase + (int64_t)f * fs;
-#pragma unroll
-        for (int r = 0; r < NR; ++r) stg[slot][r] = gok[r] ? src[goff[r]] : 0.0;
+        for (int r = 0; r < NR; ++r) {
+            const int hz = hz0 + r * PP;
+            stg[r] = lane && hz < HZ && hz < hzmax ? src[(int64_t)r * PP * P.pitch_z] : 0.0;
+        }
     };
-    auto lstore = [&](int b, int slot) __attribute__((always_inline)) {
+    auto lstore = [&]() __attribute__((always_inline)) {
 #pragma unroll
         for (int r = 0; r < NR; ++r)
-            if (tid + r * NT < HV) buf[b][loff[r]] = stg[slot][r];
+            if (lx < HX && ly < PP * HY && hz0 + r * PP < HZ) buf[ll + r * PP * HY * PX] = stg[r];
     };
 
-    // ---- point values and the inverse conformal metric (global loads) ----
+    // ---- point values needed from the first pass on (global loads) ----
     const double* __restrict__ u = a.Us + c;
-    const double chi = u[CHI * fs], Kh = u[KH * fs], Th = u[TH * fs], alp = u[ALP * fs];
-    double g[6], A[6], Gh[3], be[3];
+    const double chi = u[CHI * fs];
+    double g[6], Gh[3], be[3];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        g[q] = u[(GT + q) * fs];
-        A[q] = u[(AT + q) * fs];
-    }
+    for (int q = 0; q < 6; ++q) g[q] = u[(GT + q) * fs];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         Gh[i] = u[(GH + i) * fs];
@@ -132,41 +127,28 @@ __global__ __launch_bounds__(TX * TY * TZ, MOL_CCZ4_WAVES) void ccz4_stage_kerne
         gu[4] = (g[2] * g[1] - g[0] * g[4]) * idet;
         gu[5] = (g[0] * g[3] - g[1] * g[1]) * idet;
     }
-    // raised traceless curvature At^i_j and At^{ij}
-    double Am[3][3], Au[6];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-            Am[i][j] = gu[SI(i, 0)] * A[SI(0, j)] + gu[SI(i, 1)] * A[SI(1, j)] + gu[SI(i, 2)] * A[SI(2, j)];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = i; j < 3; ++j)
-            Au[SI(i, j)] = Am[i][0] * gu[SI(0, j)] + Am[i][1] * gu[SI(1, j)] + Am[i][2] * gu[SI(2, j)];
 
     // ---- quantities built while the fields stream through LDS ----
     double dg[3][6], lapg[6];           // metric derivatives (until the Christoffels are formed)
-    double Gu[3][6], Z[3], GtAu[3];     // Gt^i_jk, Z^i, Gt^i_jk At^jk
+    double Gu[3][6], Z[3], GtAu[3];     // Gt^i_jk (until At^jk is known), Z^i, Gt^i_jk At^jk
     double Ric[6];                      // R_ij + 2 nabla_(i Z_j), accumulated
     double dchi[3], dalp[3], DDa[6];    // chi and alpha gradients, nabla_i nabla_j alpha
     double db[3][3], gddb[3], gdiv[3];  // d_k beta^i, gt^jk d_j d_k beta^i, d_i (d_k beta^k)
     double rG[3];                       // Ghat^i terms with d Khat and d Theta
+    double alp, A[6], Au[6], Kh, Th, Bv[3];  // point values taken from LDS, At^{ij}
     const int S[3] = {1, PX, PX * HY};
 
-    gload(ORDER[0], 0);
-    lstore(0, 0);
-    if constexpr (NB == 2) gload(ORDER[1], 1);
+    gload(ORDER[0]);
+    lstore();
     __syncthreads();
     // one pass per field, expanded at compile time so that every branch and
     // array index below is a constant
     auto pass = [&](auto qc) __attribute__((always_inline)) {
         constexpr int q = decltype(qc)::value;
         constexpr int f = ORDER[q];
-        if constexpr (NB == 2 && q + 2 < NF) gload(ORDER[q + 2], q & 1);
-        if constexpr (NB == 1 && q + 1 < NF) gload(ORDER[q + 1], 0);
+        if constexpr (q + 1 < NF) gload(ORDER[q + 1]);
         if (valid) {
-            const double* t = &buf[NB == 2 ? (q & 1) : 0][((tz + G) * HY + ty + G) * PX + tx + G];
+            const double* t = &buf[((tz + G) * HY + ty + G) * PX + tx + G];
             // advection beta^k d_k and KO dissipation of every field
             double adv = 0.0, ko = 0.0;
 #pragma unroll
@@ -215,36 +197,45 @@ __global__ __launch_bounds__(TX * TY * TZ, MOL_CCZ4_WAVES) void ccz4_stage_kerne
                         const double Gc = gu[0] * Gu[i][0] + gu[3] * Gu[i][3] + gu[5] * Gu[i][5] +
                                           2.0 * (gu[1] * Gu[i][1] + gu[2] * Gu[i][2] + gu[4] * Gu[i][4]);
                         Z[i] = 0.5 * chi * (Gh[i] - Gc);
-                        GtAu[i] = Gu[i][0] * Au[0] + Gu[i][3] * Au[3] + Gu[i][5] * Au[5] +
-                                  2.0 * (Gu[i][1] * Au[1] + Gu[i][2] * Au[2] + Gu[i][4] * Au[4]);
                     }
                     // Rhat_ij without the d Ghat term:
                     //  -gt^mn d_m d_n gt_ij / 2 + Ghat^k Gt_(ij)k
                     //  + gt^mn (Gt^k_mi Gt_jkn + Gt^k_mj Gt_ikn + Gt^k_mi Gt_knj)
-                    double H[3][3][3];  // H[k][i][n] = gt^{nm} Gt^k_{mi}
-#pragma unroll
-                    for (int k = 0; k < 3; ++k)
-#pragma unroll
-                        for (int i = 0; i < 3; ++i)
-#pragma unroll
-                            for (int n = 0; n < 3; ++n)
-                                H[k][i][n] = gu[SI(n, 0)] * Gu[k][SI(0, i)] + gu[SI(n, 1)] * Gu[k][SI(1, i)] +
-                                             gu[SI(n, 2)] * Gu[k][SI(2, i)];
+                    // built row by row: with H_i[k][n] = gt^{nm} Gt^k_{mi},
+                    // P_ij = H_i[k][n] Gt_jkn and Q_ij = H_i[k][n] Gt_knj, the
+                    // quadratic part of entry (i, j) is P_ij + P_ji + Q_ij
 #pragma unroll
                     for (int i = 0; i < 3; ++i)
 #pragma unroll
                         for (int j = i; j < 3; ++j) {
                             double r = -0.5 * lapg[SI(i, j)];
 #pragma unroll
-                            for (int k = 0; k < 3; ++k) {
-                                r += Gh[k] * 0.5 * (Gl[i][SI(j, k)] + Gl[j][SI(i, k)]);
-#pragma unroll
-                                for (int n = 0; n < 3; ++n)
-                                    r += H[k][i][n] * Gl[j][SI(k, n)] + H[k][j][n] * Gl[i][SI(k, n)] +
-                                         H[k][i][n] * Gl[k][SI(n, j)];
-                            }
+                            for (int k = 0; k < 3; ++k) r += Gh[k] * 0.5 * (Gl[i][SI(j, k)] + Gl[j][SI(i, k)]);
                             Ric[SI(i, j)] = r;
                         }
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        double H[3][3];
+#pragma unroll
+                        for (int k = 0; k < 3; ++k)
+#pragma unroll
+                            for (int n = 0; n < 3; ++n)
+                                H[k][n] = gu[SI(n, 0)] * Gu[k][SI(0, i)] + gu[SI(n, 1)] * Gu[k][SI(1, i)] +
+                                          gu[SI(n, 2)] * Gu[k][SI(2, i)];
+#pragma unroll
+                        for (int j = 0; j < 3; ++j) {
+                            double p = 0.0, qv = 0.0;
+#pragma unroll
+                            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                                for (int n = 0; n < 3; ++n) {
+                                    p += H[k][n] * Gl[j][SI(k, n)];
+                                    if (j >= i) qv += H[k][n] * Gl[k][SI(n, j)];
+                                }
+                            if (j >= i) Ric[SI(i, j)] += p + qv;
+                            if (j <= i) Ric[SI(j, i)] += p;
+                        }
+                    }
                 }
             } else if constexpr (f >= GH && f < GH + 3) {
                 // gt_k(i d_j) Ghat^k for k = f - GH
@@ -289,6 +280,7 @@ __global__ __launch_bounds__(TX * TY * TZ, MOL_CCZ4_WAVES) void ccz4_stage_kerne
                                   2.0 * ic * ic * zs + 0.5 * ic * g[m] * (tr - Ghd);
                     }
             } else if constexpr (f == ALP) {
+                alp = t[0];
 #pragma unroll
                 for (int k = 0; k < 3; ++k) dalp[k] = d1(k);
                 double cr = 0.0;
@@ -305,6 +297,27 @@ __global__ __launch_bounds__(TX * TY * TZ, MOL_CCZ4_WAVES) void ccz4_stage_kerne
                         DDa[m] = dd(i, j) - (Gu[0][m] * dalp[0] + Gu[1][m] * dalp[1] + Gu[2][m] * dalp[2]) +
                                  hic * (dalp[i] * dchi[j] + dalp[j] * dchi[i] - g[m] * cr);
                     }
+            } else if constexpr (f >= AT && f < AT + 6) {
+                A[f - AT] = t[0];
+                if constexpr (f == AT + 5) {
+                    // At^{ij} and Gt^i_jk At^jk; the Christoffels are not needed after this
+                    double Am[3][3];
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+#pragma unroll
+                        for (int j = 0; j < 3; ++j)
+                            Am[i][j] = gu[SI(i, 0)] * A[SI(0, j)] + gu[SI(i, 1)] * A[SI(1, j)] +
+                                       gu[SI(i, 2)] * A[SI(2, j)];
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+#pragma unroll
+                        for (int j = i; j < 3; ++j)
+                            Au[SI(i, j)] = Am[i][0] * gu[SI(0, j)] + Am[i][1] * gu[SI(1, j)] + Am[i][2] * gu[SI(2, j)];
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+                        GtAu[i] = Gu[i][0] * Au[0] + Gu[i][3] * Au[3] + Gu[i][5] * Au[5] +
+                                  2.0 * (Gu[i][1] * Au[1] + Gu[i][2] * Au[2] + Gu[i][4] * Au[4]);
+                }
             } else if constexpr (f >= BETA && f < BETA + 3) {
                 constexpr int i = f - BETA;
                 if constexpr (i == 0) gdiv[0] = gdiv[1] = gdiv[2] = 0.0;
@@ -323,6 +336,7 @@ __global__ __launch_bounds__(TX * TY * TZ, MOL_CCZ4_WAVES) void ccz4_stage_kerne
                     }
                 gddb[i] = s;
             } else if constexpr (f == KH) {
+                Kh = t[0];
                 double d[3];
 #pragma unroll
                 for (int k = 0; k < 3; ++k) d[k] = d1(k);
@@ -330,6 +344,7 @@ __global__ __launch_bounds__(TX * TY * TZ, MOL_CCZ4_WAVES) void ccz4_stage_kerne
                 for (int i = 0; i < 3; ++i)
                     rG[i] = -(2.0 / 3.0) * (gu[SI(i, 0)] * d[0] + gu[SI(i, 1)] * d[1] + gu[SI(i, 2)] * d[2]);
             } else if constexpr (f == TH) {
+                Th = t[0];
                 double d[3];
 #pragma unroll
                 for (int k = 0; k < 3; ++k) d[k] = d1(k);
@@ -338,15 +353,15 @@ __global__ __launch_bounds__(TX * TY * TZ, MOL_CCZ4_WAVES) void ccz4_stage_kerne
 #pragma unroll
                     for (int j = 0; j < 3; ++j)
                         rG[i] += -gu[SI(i, j)] * ((1.0 / 3.0) * d[j] + Th / alp * dalp[j]);
+            } else if constexpr (f >= BB && f < BB + 3) {
+                Bv[f - BB] = t[0];
             }
         }
-        if constexpr (NB == 2) {
-            if constexpr (q + 1 < NF) lstore((q + 1) & 1, (q + 1) & 1);
-        } else {
-            __syncthreads();
-            if constexpr (q + 1 < NF) lstore(0, 0);
-        }
         __syncthreads();
+        if constexpr (q + 1 < NF) {
+            lstore();
+            __syncthreads();
+        }
     };
     [&]<int... Q>(std::integer_sequence<int, Q...>) {
         (pass(std::integral_constant<int, Q>{}), ...);
@@ -357,6 +372,13 @@ __global__ __launch_bounds__(TX * TY * TZ, MOL_CCZ4_WAVES) void ccz4_stage_kerne
     auto tr = [&](const double* T) __attribute__((always_inline)) {  // gt^{ij} T_ij
         return gu[0] * T[0] + gu[3] * T[3] + gu[5] * T[5] + 2.0 * (gu[1] * T[1] + gu[2] * T[2] + gu[4] * T[4]);
     };
+    // raised traceless curvature At^i_j
+    double Am[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            Am[i][j] = gu[SI(i, 0)] * A[SI(0, j)] + gu[SI(i, 1)] * A[SI(1, j)] + gu[SI(i, 2)] * A[SI(2, j)];
     const double trRic = chi * tr(Ric);
     const double lapa = chi * tr(DDa);
     const double trA = Am[0][0] + Am[1][1] + Am[2][2];
@@ -418,10 +440,9 @@ __global__ __launch_bounds__(TX * TY * TZ, MOL_CCZ4_WAVES) void ccz4_stage_kerne
         }
         const double b2 = -Z[i] / chi * (C.kz + (2.0 / 3.0) * Kt);
         r += 2.0 * alp * (b1 + rG[i] + b2);
-        const double Bv = u[(BB + i) * fs];
         out(GH + i, r);
-        out(BB + i, -C.eta * Bv + r);  // d_t Ghat^i without its advection term
-        out(BETA + i, C.g * Bv);
+        out(BB + i, -C.eta * Bv[i] + r);  // d_t Ghat^i without its advection term
+        out(BETA + i, C.g * Bv[i]);
     }
     out(ALP, -alp * alp * (C.f0 + C.f1 / alp) * Kh);
 }

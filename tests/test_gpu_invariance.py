@@ -1,0 +1,100 @@
+"""Properties of the GPU path that need no second implementation:
+decomposition invariance (one periodic patch vs the same level cut into
+ragged patches), run-to-run determinism, and error reporting."""
+import numpy as np
+import pytest
+
+from paper_1806_04182_amd import molamr as M
+from paper_1806_04182_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU test needs a GPU"
+    return torch
+
+
+def _boxes_split(n, cuts):
+    """Tile the box [0, n) with cuts per axis (lists of split points)."""
+    edges = [[0] + list(c) + [n[d]] for d, c in enumerate(cuts)]
+    boxes = []
+    for k in range(len(edges[2]) - 1):
+        for j in range(len(edges[1]) - 1):
+            for i in range(len(edges[0]) - 1):
+                boxes.append(((edges[0][i], edges[1][j], edges[2][k]),
+                              (edges[0][i + 1] - 1, edges[1][j + 1] - 1, edges[2][k + 1] - 1)))
+    return boxes
+
+
+def _run(system, n, boxes, state, steps, dt, dx):
+    torch = _torch()
+    ps = M.Patchset(M.Hierarchy(n, (-1, -1, -1), dx, [(1, boxes)]), M.System(system))
+    arrs = []
+    for lo, hi in boxes:
+        sub = state[:, lo[2]:hi[2] + 1, lo[1]:hi[1] + 1, lo[0]:hi[0] + 1]
+        arrs.append(synth.embed(np.ascontiguousarray(sub)))
+    st = ps.alloc_states()
+    st[0]["U"].copy_(torch.from_numpy(ps.pack(0, arrs)))
+    for _ in range(steps):
+        ps.advance(st, dt)
+    torch.cuda.synchronize()
+    out = np.zeros_like(state)
+    for (lo, hi), a in zip(boxes, ps.unpack(0, st[0]["U"])):
+        out[:, lo[2]:hi[2] + 1, lo[1]:hi[1] + 1, lo[0]:hi[0] + 1] = synth.interior(a)
+    return out
+
+
+@pytest.mark.parametrize("system", [M.MOL_WAVE, M.MOL_CCZ4, M.MOL_MHD])
+def test_decomposition_invariance_bitwise(system):
+    n = (24, 20, 17)
+    dx = 2.0 / 24
+    if system == M.MOL_WAVE:
+        state = synth.wave_gaussian(n, (-1, -1, -1), dx, width=0.4)
+    elif system == M.MOL_CCZ4:
+        state = synth.ccz4_lapse_pulse(n, (-1, -1, -1), dx, amp=0.1, width=0.4) + \
+            synth.ccz4_minkowski_noise(n, amp=1e-3) - synth.CCZ4_FLAT[:, None, None, None]
+    else:
+        state = synth.mhd_ot_like(n, seed=2, N=(24, 24, 24))
+    one = _run(system, n, [((0, 0, 0), tuple(x - 1 for x in n))], state, 2, 0.2 * dx, dx)
+    many = _run(system, n, _boxes_split(n, [[7, 19], [11], [5, 9]]), state, 2, 0.2 * dx, dx)
+    assert np.array_equal(one, many)
+    again = _run(system, n, _boxes_split(n, [[7, 19], [11], [5, 9]]), state, 2, 0.2 * dx, dx)
+    assert np.array_equal(many, again)  # run to run
+
+
+def test_norms_flag_non_finite_values():
+    torch = _torch()
+    n = (10, 9, 8)
+    ps = M.Patchset(M.single_patch(n, (0, 0, 0), 0.1), M.System(M.MOL_WAVE))
+    a = synth.embed(np.ones((2, 8, 9, 10)))
+    a[0, 5, 5, 5] = np.nan
+    a[0, 4, 4, 4] = np.inf
+    U = torch.from_numpy(ps.pack(0, [a])).cuda()
+    out = torch.zeros(5, dtype=torch.float64, device="cuda")
+    ps.norms(0, U, 0, 0.0, 100.0, out)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    assert o[4] == 2.0 and o[2] == 1.0
+    assert abs(o[0] - (10 * 9 * 8 - 2) * 1e-3) < 1e-12
+
+
+def test_argument_errors_are_reported_before_launch():
+    torch = _torch()
+    n = (8, 8, 8)
+    ps = M.Patchset(M.single_patch(n, (0, 0, 0), 0.1), M.System(M.MOL_WAVE))
+    U, V, acc = ps.alloc(0), ps.alloc(0), ps.alloc(0)
+    with pytest.raises(M.MolError, match="dt must be positive"):
+        ps.rk_stage(0, M.MOL_RK4, 1, 0.0, U, U, acc, V)
+    with pytest.raises(M.MolError, match="stage 5"):
+        ps.rk_stage(0, M.MOL_RK4, 5, 0.1, U, U, acc, V)
+    with pytest.raises(M.MolError, match="must not alias"):
+        ps.rk_stage(0, M.MOL_RK4, 2, 0.1, U, V, acc, V)
+    with pytest.raises(M.MolError, match="level 3 out of range"):
+        ps.fill_ghosts(3, U)
+    with pytest.raises(M.MolError, match="level 0 has no parent"):
+        ps.restrict(0, U, V)
+    with pytest.raises(M.MolError, match="wave system only|EUNSUPPORTED|only"):
+        M.Patchset(M.single_patch(n, (0, 0, 0), 0.1), M.System(M.MOL_CCZ4)).rhs_adjoint(0, U, U, V)
+    torch.cuda.synchronize()
