@@ -30,11 +30,14 @@
  * level l).  Boxes are inclusive (lo, hi) index ranges in level index space.
  * Every patch carries a ghost layer of 3 points (MOL_GHOST).
  *
- * Field layout of a level buffer: patch p occupies the block starting at
- * patch_offsets[p]; inside it, field f starts at f * fstride_p, and point
- * (i, j, k) of the ghosted box (0 <= i < nx+6, ...) is at
- * (k * (ny+6) + j) * (nx+6) + i.  fstride_p = (nx+6)(ny+6)(nz+6) rounded up
- * to a multiple of 32 doubles; patch blocks start on 256-byte boundaries.
+ * Field layout of a level buffer: patch p starts at patch_offsets[p]; from
+ * there, field f starts at f * fstride_p, and point (i, j, k) of the ghosted
+ * box (0 <= i < nx+6, ...) is at (k * (ny+6) + j) * px_p + i, where the row
+ * pitch px_p = nx+6 rounded up to a multiple of 8 doubles and fstride_p =
+ * px_p (ny+6)(nz+6) rounded up to a multiple of 32 doubles.  Patch offsets
+ * are 5 more than a multiple of 32 doubles, so that every interior row
+ * (i = 3) starts on a 64-byte boundary; the doubles between rows are padding
+ * that no call reads as data.
  */
 #ifndef MOLAMR_H
 #define MOLAMR_H
@@ -112,10 +115,12 @@ int mol_nfields(const mol_patchset* ps);
 
 /* Layout of a level buffer (pure host query).  nelems receives the number of
  * doubles of one level buffer (all fields); patch_offsets[np] (nullable) the
- * start of each patch block; patch_dims[3*np] (nullable) the interior size of
- * each patch; fstrides[np] (nullable) the field stride of each patch. */
+ * start of each patch; patch_dims[3*np] (nullable) the interior size of each
+ * patch; fstrides[np] (nullable) the field stride of each patch; row_pitch[np]
+ * (nullable) the row pitch px of each patch. */
 int mol_level_layout(const mol_patchset* ps, int level, int64_t* nelems,
-                     int64_t* patch_offsets, int32_t* patch_dims, int64_t* fstrides);
+                     int64_t* patch_offsets, int32_t* patch_dims, int64_t* fstrides,
+                     int32_t* row_pitch);
 int mol_level_npatch(const mol_patchset* ps, int level);
 
 /* Ghost fill of level `level`, same-level and periodic sources only (the

@@ -284,11 +284,13 @@ int build(mol_patchset* ps, const mol_hierarchy_desc* h)
                 pd.n[d] = b.n(d);
                 pd.lo[d] = b.lo[d];
             }
-            pd.pitch_y = pd.n[0] + 2 * G;
+            // rows padded to 8 doubles and the patch start shifted by
+            // 8 - G doubles: interior rows start on 64-byte boundaries
+            pd.pitch_y = (int)round_up(pd.n[0] + 2 * G, 8);
             pd.pitch_z = pd.pitch_y * (pd.n[1] + 2 * G);
             pd.fs = round_up((int64_t)pd.pitch_z * (pd.n[2] + 2 * G), 32);
-            pd.off = off;
-            off += round_up(pd.fs * ps->sp.nf, 32);
+            pd.off = off + (8 - G);
+            off += round_up((8 - G) + pd.fs * ps->sp.nf, 32);
             lev.pd.push_back(pd);
         }
         lev.nelems = off;
@@ -748,7 +750,7 @@ int mol_level_npatch(const mol_patchset* ps, int level)
 }
 
 int mol_level_layout(const mol_patchset* ps, int level, int64_t* nelems, int64_t* offs,
-                     int32_t* dims, int64_t* fstrides)
+                     int32_t* dims, int64_t* fstrides, int32_t* row_pitch)
 {
     int rc = check_level(ps, level);
     if (rc) return rc;
@@ -759,6 +761,7 @@ int mol_level_layout(const mol_patchset* ps, int level, int64_t* nelems, int64_t
         if (dims)
             for (int d = 0; d < 3; ++d) dims[3 * p + d] = lev.pd[p].n[d];
         if (fstrides) fstrides[p] = lev.pd[p].fs;
+        if (row_pitch) row_pitch[p] = lev.pd[p].pitch_y;
     }
     return MOL_OK;
 }

@@ -17,8 +17,8 @@
 // consumed as soon as they arrive (Christoffel symbols after the six metric
 // components, Ricci terms after chi and Ghat, the lapse Hessian after alpha,
 // ...), and point values that are needed only late are taken from LDS when
-// their field passes, so that only partial sums stay live and the kernel
-// fits 256 registers per lane without spilling.  Advection and dissipation of
+// their field passes, so that only partial sums stay live (the kernel keeps
+// to 256 registers per lane, two waves per SIMD).  Advection and dissipation of
 // every field are parked in LDS until the algebra that needs all fields is
 // done; then the RK stage update writes the results.
 #include <utility>
@@ -37,6 +37,29 @@ __device__ constexpr int SI(int i, int j)
 {
     const int a = i < j ? i : j, b = i < j ? j : i;
     return a == 0 ? b : (a == 1 ? 2 + b : 5);
+}
+
+// Neighbour combinations along stride s: e_m = (u_m - u_0) + (u_-m - u_0),
+// o_m = u_m - u_-m (m = 1, 2, 3).  In these, 12 h D1 = 8 o1 - o2,
+// 12 h^2 D2 = 16 e1 - e2, the sixth-order dissipation stencil is
+// e3 - 6 e2 + 15 e1, and b times the lop-sided derivative (the b >= 0
+// stencil reading i-1 .. i+3, its mirror for b < 0) is
+// b (o3/2 - 3 o2 + 21 o1/2) + |b| (e3/2 - 3 e2 + 15 e1/2), which needs no
+// branch on the sign of b.
+struct Axis {
+    double e1, e2, e3, o1, o2, o3;
+};
+__device__ __forceinline__ Axis axis(const double* __restrict__ u, int s)
+{
+    const double c = u[0];
+    Axis a;
+    a.e1 = (u[s] - c) + (u[-s] - c);
+    a.e2 = (u[2 * s] - c) + (u[-2 * s] - c);
+    a.e3 = (u[3 * s] - c) + (u[-3 * s] - c);
+    a.o1 = u[s] - u[-s];
+    a.o2 = u[2 * s] - u[-2 * s];
+    a.o3 = u[3 * s] - u[-3 * s];
+    return a;
 }
 
 struct CczConst {
@@ -64,7 +87,7 @@ __global__ __launch_bounds__(TX * TY * TZ, MOL_CCZ4_WAVES) void ccz4_stage_kerne
     // halo loads: 16 lanes per row (x), NT / 16 rows per pass covering PP
     // whole planes, NR passes; the offset between passes is a constant
     constexpr int LW = 16, PP = (NT / LW) / HY, NR = (HZ + PP - 1) / PP;
-    static_assert(HX <= LW && PP >= 1, "halo row wider than 16 or tile plane too large");
+    static_assert(HX <= LW && PP >= 1 && HZ % PP == 0, "halo tile does not fit the load pattern");
     constexpr int LV = PX * HY * HZ;
     __shared__ double buf[LV];
     __shared__ double akx[NF][NT];  // advection + dissipation of every field
@@ -79,25 +102,29 @@ __global__ __launch_bounds__(TX * TY * TZ, MOL_CCZ4_WAVES) void ccz4_stage_kerne
     const int64_t c = hbase + (int64_t)(tz + G) * P.pitch_z + (int64_t)(ty + G) * P.pitch_y + (tx + G);
     const int64_t fs = P.fs;
 
-    // this thread's halo element in the first pass; pass r adds PP planes
+    // this thread's halo element in the first pass; pass r adds PP planes.
+    // Lanes outside the ghosted box load from the tile origin instead (no
+    // branch around the load; such halo values are read only by threads
+    // outside the patch, which compute nothing).
     const int lx = tid % LW, ly = tid / LW, hy = ly % HY, hz0 = ly / HY;
-    const bool lane = lx < HX && ly < PP * HY && tile.o[0] + lx < P.n[0] + 2 * G && tile.o[1] + hy < P.n[1] + 2 * G;
+    const bool lane = lx < HX && ly < PP * HY;
+    const bool inxy = lane && tile.o[0] + lx < P.n[0] + 2 * G && tile.o[1] + hy < P.n[1] + 2 * G;
     const int gl = hz0 * P.pitch_z + hy * P.pitch_y + lx;
     const int ll = (hz0 * HY + hy) * PX + lx;
     const int hzmax = P.n[2] + 2 * G - tile.o[2];  // halo planes inside the ghosted box
     double stg[NR];
     auto gload = [&](int f) __attribute__((always_inline)) {
-        const double* src = a.Us + hbase + (int64_t)f * fs + gl;
+        const double* src = a.Us + hbase + (int64_t)f * fs;
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            const int hz = hz0 + r * PP;
-            stg[r] = lane && hz < HZ && hz < hzmax ? src[(int64_t)r * PP * P.pitch_z] : 0.0;
+            const bool ok = inxy && hz0 + r * PP < hzmax;
+            stg[r] = src[ok ? gl + r * PP * P.pitch_z : 0];
         }
     };
     auto lstore = [&]() __attribute__((always_inline)) {
 #pragma unroll
         for (int r = 0; r < NR; ++r)
-            if (lx < HX && ly < PP * HY && hz0 + r * PP < HZ) buf[ll + r * PP * HY * PX] = stg[r];
+            if (lane) buf[ll + r * PP * HY * PX] = stg[r];
     };
 
     // ---- point values needed from the first pass on (global loads) ----
@@ -149,18 +176,27 @@ __global__ __launch_bounds__(TX * TY * TZ, MOL_CCZ4_WAVES) void ccz4_stage_kerne
         if constexpr (q + 1 < NF) gload(ORDER[q + 1]);
         if (valid) {
             const double* t = &buf[((tz + G) * HY + ty + G) * PX + tx + G];
-            // advection beta^k d_k and KO dissipation of every field
-            double adv = 0.0, ko = 0.0;
+            // advection beta^k d_k and KO dissipation of every field; first
+            // and pure second derivatives from the same combinations
+            constexpr bool second = (f >= GT && f < GT + 6) || f == CHI || f == ALP || (f >= BETA && f < BETA + 3);
+            double adv = 0.0, ko = 0.0, d1v[3], d2v[3];
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                adv += be[k] * (UPWIND ? fadv(t, S[k], be[k]) : fd1(t, S[k]));
-                ko += fko(t, S[k]);
+                const Axis x = axis(t, S[k]);
+                ko += (x.e3 - 6.0 * x.e2) + 15.0 * x.e1;
+                d1v[k] = 8.0 * x.o1 - x.o2;
+                if (UPWIND)
+                    adv += be[k] * ((0.5 * x.o3 - 3.0 * x.o2) + 10.5 * x.o1) +
+                           fabs(be[k]) * ((0.5 * x.e3 - 3.0 * x.e2) + 7.5 * x.e1);
+                else
+                    adv += be[k] * d1v[k];
+                if constexpr (second) d2v[k] = 16.0 * x.e1 - x.e2;
             }
             akx[f][tid] = C.i12h * adv + C.ko * ko;
 
-            auto d1 = [&](int k) __attribute__((always_inline)) { return C.i12h * fd1(t, S[k]); };
+            auto d1 = [&](int k) __attribute__((always_inline)) { return C.i12h * d1v[k]; };
             auto dd = [&](int k, int l) __attribute__((always_inline)) {
-                return k == l ? C.i12h2 * fd2(t, S[k]) : C.i144h2 * fmix(t, S[k], S[l]);
+                return k == l ? C.i12h2 * d2v[k] : C.i144h2 * fmix(t, S[k], S[l]);
             };
             // gt^{kl} d_k d_l of the field in LDS
             auto trdd = [&]() __attribute__((always_inline)) {

@@ -31,8 +31,8 @@ struct PatchDev {
     int64_t off;   // start of the patch block in the level buffer (doubles)
     int64_t fs;    // field stride (doubles)
     int n[3];      // interior size
-    int pitch_y;   // (nx + 6)
-    int pitch_z;   // (nx + 6) * (ny + 6)
+    int pitch_y;   // row pitch: nx + 6 rounded up to 8
+    int pitch_z;   // pitch_y * (ny + 6)
     int lo[3];     // global index of the first interior point
     int pad;
 };

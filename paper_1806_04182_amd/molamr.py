@@ -66,7 +66,7 @@ def lib():
             "mol_destroy_patchset": ([vp], None),
             "mol_last_error": ([], ctypes.c_char_p),
             "mol_nfields": ([vp], i),
-            "mol_level_layout": ([vp, i, i64p, i64p, i32p, i64p], i),
+            "mol_level_layout": ([vp, i, i64p, i64p, i32p, i64p, i32p], i),
             "mol_level_npatch": ([vp, i], i),
             "mol_fill_ghosts": ([vp, i, vp, i, vp], i),
             "mol_rhs": ([vp, i, vp, vp, vp], i),
@@ -184,9 +184,18 @@ class Patchset:
         offs = (ctypes.c_int64 * np_)()
         dims = (ctypes.c_int32 * (3 * np_))()
         fss = (ctypes.c_int64 * np_)()
-        _check(lib().mol_level_layout(self._h, level, ctypes.byref(n), offs, dims, fss))
+        pxs = (ctypes.c_int32 * np_)()
+        _check(lib().mol_level_layout(self._h, level, ctypes.byref(n), offs, dims, fss, pxs))
         return dict(nelems=n.value, offsets=list(offs), dims=[tuple(dims[3 * p:3 * p + 3]) for p in range(np_)],
-                    fstrides=list(fss))
+                    fstrides=list(fss), pitches=list(pxs))
+
+    def _view(self, level: int, buf, p: int, nf: int):
+        """(nf, nz+6, ny+6, nx+6) view of patch p inside a level buffer."""
+        L = self.layouts[level]
+        nx, ny, nz = L["dims"][p]
+        px, fs, off = L["pitches"][p], L["fstrides"][p], L["offsets"][p]
+        blk = buf[off:off + nf * fs].reshape(nf, fs)
+        return blk[:, :px * (ny + 6) * (nz + 6)].reshape(nf, nz + 6, ny + 6, px)[..., :nx + 6]
 
     def alloc(self, level: int, device="cuda"):
         import torch
@@ -194,28 +203,16 @@ class Patchset:
 
     def pack(self, level: int, patches: Sequence[np.ndarray]) -> np.ndarray:
         """Patch arrays (nf, nz+6, ny+6, nx+6) -> one host level buffer."""
-        L = self.layouts[level]
-        buf = np.zeros(L["nelems"])
+        buf = np.zeros(self.layouts[level]["nelems"])
         for p, a in enumerate(patches):
-            nx, ny, nz = L["dims"][p]
-            vol = (nx + 6) * (ny + 6) * (nz + 6)
-            nf = a.shape[0]
-            blk = buf[L["offsets"][p]:L["offsets"][p] + nf * L["fstrides"][p]].reshape(nf, L["fstrides"][p])
-            blk[:, :vol] = a.reshape(nf, vol)
+            self._view(level, buf, p, a.shape[0])[...] = a
         return buf
 
     def unpack(self, level: int, buf, nf: int | None = None) -> list[np.ndarray]:
         if not isinstance(buf, np.ndarray):
             buf = buf.detach().cpu().numpy()
-        L = self.layouts[level]
         nf = nf or self.nf
-        out = []
-        for p in range(len(L["dims"])):
-            nx, ny, nz = L["dims"][p]
-            vol = (nx + 6) * (ny + 6) * (nz + 6)
-            blk = buf[L["offsets"][p]:L["offsets"][p] + nf * L["fstrides"][p]].reshape(nf, L["fstrides"][p])
-            out.append(blk[:, :vol].reshape(nf, nz + 6, ny + 6, nx + 6).copy())
-        return out
+        return [self._view(level, buf, p, nf).copy() for p in range(len(self.layouts[level]["dims"]))]
 
     # ---- operations (same names as the C ABI) ---------------------------
     def fill_ghosts(self, level, U, nf=0, stream=None):
