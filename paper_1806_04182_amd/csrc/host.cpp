@@ -224,16 +224,17 @@ void build_tiles(const Level& lev, const int td[3], int margin, TileList& tl)
 }
 
 // Tile of the stage kernels.  Wave: levels of at least 2^21 points march
-// along z (64 x 4 columns, chunk length chosen so that the launch still has
+// along z (64 x 8 columns, chunk length chosen so that the launch still has
 // about 2048 workgroups); smaller levels use one thread per point.
 void default_tile(int system, int64_t level_points, int td[3])
 {
     switch (system) {
     case MOL_WAVE:
         if (level_points >= (int64_t(1) << 21)) {
-            td[0] = 64;
-            td[1] = 4;
-            td[2] = (int)std::max<int64_t>(4, std::min<int64_t>(32, level_points / (64 * 4 * 2048)));
+            td[0] = MOL_WAVE_WX;
+            td[1] = MOL_WAVE_WY;
+            td[2] = (int)std::max<int64_t>(
+                4, std::min<int64_t>(MOL_WAVE_ZMAX, level_points / (MOL_WAVE_WX * MOL_WAVE_WY * 2048)));
         } else {
             td[0] = 32;
             td[1] = 4;

@@ -43,9 +43,28 @@ __device__ __forceinline__ bool tile_point(const StageArgs& a, int tile, PointRe
     return true;
 }
 
+// Values the stage update reads at a point besides the right-hand side
+// (loaded separately so that kernels can fetch them ahead of use).
+struct StageIn {
+    double un, ac, us;
+};
+__device__ __forceinline__ StageIn stage_load(const StageArgs& a, int64_t idx)
+{
+    StageIn v{0.0, 0.0, 0.0};
+    if (a.mode == ST_RHS) return v;
+    v.un = a.Un[idx];
+    if (a.stage >= 2) {
+        if (a.mode == ST_RK4)
+            v.ac = a.acc[idx];
+        else
+            v.us = a.Us[idx];
+    }
+    return v;
+}
+
 // k = dt * rhs, then the RK4 (Table RK44, accumulator form) or SSP-RK3
 // (Shu-Osher form of the App. D scheme) stage update, or plain rhs output.
-__device__ __forceinline__ void stage_store(const StageArgs& a, int64_t idx, double rhs)
+__device__ __forceinline__ void stage_apply(const StageArgs& a, int64_t idx, double rhs, const StageIn& v)
 {
     if (a.mode == ST_RHS) {
         a.out[idx] = rhs;
@@ -53,7 +72,7 @@ __device__ __forceinline__ void stage_store(const StageArgs& a, int64_t idx, dou
     }
     const double k = a.dt * rhs;
     if (a.kst) a.kst[idx] = k;
-    const double un = a.Un[idx];
+    const double un = v.un;
     if (a.mode == ST_RK4) {
         switch (a.stage) {
         case 1:
@@ -61,25 +80,29 @@ __device__ __forceinline__ void stage_store(const StageArgs& a, int64_t idx, dou
             a.out[idx] = un + 0.5 * k;
             break;
         case 2:
-            a.acc[idx] = a.acc[idx] + k * (1.0 / 3.0);
+            a.acc[idx] = v.ac + k * (1.0 / 3.0);
             a.out[idx] = un + 0.5 * k;
             break;
         case 3:
-            a.acc[idx] = a.acc[idx] + k * (1.0 / 3.0);
+            a.acc[idx] = v.ac + k * (1.0 / 3.0);
             a.out[idx] = un + k;
             break;
         default:
-            a.out[idx] = un + (a.acc[idx] + k * (1.0 / 6.0));
+            a.out[idx] = un + (v.ac + k * (1.0 / 6.0));
             break;
         }
     } else {
-        const double us = a.Us[idx];
         switch (a.stage) {
         case 1: a.out[idx] = un + k; break;
-        case 2: a.out[idx] = 0.75 * un + 0.25 * (us + k); break;
-        default: a.out[idx] = (1.0 / 3.0) * un + (2.0 / 3.0) * (us + k); break;
+        case 2: a.out[idx] = 0.75 * un + 0.25 * (v.us + k); break;
+        default: a.out[idx] = (1.0 / 3.0) * un + (2.0 / 3.0) * (v.us + k); break;
         }
     }
+}
+
+__device__ __forceinline__ void stage_store(const StageArgs& a, int64_t idx, double rhs)
+{
+    stage_apply(a, idx, rhs, stage_load(a, idx));
 }
 
 // ---- 4th-order finite differences, evaluated as differences of symmetric

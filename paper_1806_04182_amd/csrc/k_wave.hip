@@ -32,10 +32,15 @@ __global__ __launch_bounds__(256) void wave_stage_kernel(StageArgs a, double ih2
 // along z over zc planes.  z-neighbours come from a 7-value register queue per
 // field (each value is read from memory once per column); x/y neighbours from
 // the current plane staged in LDS, whose interior part is written from the
-// queues and whose 3-point halo is loaded from memory.
-constexpr int WX = 64, WY = 4, WHX = WX + 6, WHY = WY + 6, WPX = WHX + 2;
+// queues and whose 3-point halo is loaded from memory.  The halo cells of a
+// plane are dealt out to the threads once (NH cells each, fixed offsets), so
+// the per-plane loop has no index arithmetic; columns beyond the patch
+// interior (ragged tail) load their own cell like a halo cell.
+constexpr int WX = MOL_WAVE_WX, WY = MOL_WAVE_WY, WHX = WX + 6, WHY = WY + 6, WPX = WHX + 2;
+constexpr int WNH = 6 * WHX + 6 * WY;                   // halo cells per plane
+constexpr int WT = WX * WY, NH = (WNH + WT - 1) / WT;  // halo cells per thread
 
-__global__ __launch_bounds__(WX * WY) void wave_zmarch_kernel(StageArgs a, double ih2, double ko, int zc)
+__global__ __launch_bounds__(WT) void wave_zmarch_kernel(StageArgs a, double ih2, double ko, int zc)
 {
     __shared__ double pl[2][WHY][WPX];
     const Tile tile = a.tiles[xcd_tile(blockIdx.x, gridDim.x)];
@@ -45,8 +50,30 @@ __global__ __launch_bounds__(WX * WY) void wave_zmarch_kernel(StageArgs a, doubl
     const int z1 = min(z0 + zc, P.n[2]);
     const int sz = P.pitch_z;
     const bool col = x0 + tx < P.n[0] && y0 + ty < P.n[1];
+    // own cell in the ghosted box (ragged-tail columns may lie beyond it)
+    const bool cin = x0 + tx < P.n[0] + G && y0 + ty < P.n[1] + G;
     const int64_t cb = P.off + (int64_t)(y0 + ty + G) * P.pitch_y + (x0 + tx + G);
     const double* __restrict__ U = a.Us;
+    // this thread's halo cells: LDS slot (-1: none) and offset in the plane
+    // (-1: outside the ghosted box)
+    int hl[NH], hg[NH];
+#pragma unroll
+    for (int r = 0; r < NH; ++r) {
+        const int e = tid + r * WT;
+        int hx = 0, hy = 0;
+        if (e < 6 * WHX) {  // three rows below and three above the columns
+            hy = e / WHX;
+            hx = e - hy * WHX;
+            if (hy >= 3) hy += WY;
+        } else {            // three cells left and right of every column row
+            const int q = e - 6 * WHX, row = q / 6, c = q - row * 6;
+            hy = G + row;
+            hx = c < 3 ? c : WX + c;
+        }
+        const bool ok = e < WNH && x0 + hx < P.n[0] + 2 * G && y0 + hy < P.n[1] + 2 * G;
+        hl[r] = e < WNH ? hy * WPX + hx : -1;
+        hg[r] = ok ? hy * P.pitch_y + hx : -1;
+    }
     double qp[7], qq[7];  // phi and Pi at z = k-3 .. k+3
     if (col)
 #pragma unroll
@@ -54,6 +81,24 @@ __global__ __launch_bounds__(WX * WY) void wave_zmarch_kernel(StageArgs a, doubl
             qp[m] = U[cb + (int64_t)(z0 - 3 + m + G) * sz];
             qq[m] = U[cb + P.fs + (int64_t)(z0 - 3 + m + G) * sz];
         }
+    // halo cells and stage-update inputs are fetched one plane ahead
+    double hp[NH], hq[NH];
+    StageIn sp, sq;
+    auto fetch = [&](int k, double* np, double* nq, StageIn& s0, StageIn& s1) __attribute__((always_inline)) {
+        const int64_t hb = P.off + (int64_t)(k + G) * sz + (int64_t)y0 * P.pitch_y + x0;
+#pragma unroll
+        for (int r = 0; r < NH; ++r) {
+            const bool ok = hg[r] >= 0;
+            np[r] = ok ? U[hb + hg[r]] : 0.0;
+            nq[r] = ok ? U[hb + P.fs + hg[r]] : 0.0;
+        }
+        if (col) {
+            const int64_t c = cb + (int64_t)(k + G) * sz;
+            s0 = stage_load(a, c);
+            s1 = stage_load(a, c + P.fs);
+        }
+    };
+    if (z0 < z1) fetch(z0, hp, hq, sp, sq);
     for (int k = z0; k < z1; ++k) {
         const int64_t pc = (int64_t)(k + G) * sz;
         if (col) {
@@ -61,18 +106,18 @@ __global__ __launch_bounds__(WX * WY) void wave_zmarch_kernel(StageArgs a, doubl
             qq[6] = U[cb + P.fs + pc + 3 * (int64_t)sz];
             pl[0][ty + G][tx + G] = qp[3];
             pl[1][ty + G][tx + G] = qq[3];
+        } else {
+            pl[0][ty + G][tx + G] = cin ? U[cb + pc] : 0.0;
+            pl[1][ty + G][tx + G] = cin ? U[cb + P.fs + pc] : 0.0;
         }
-        // the rest of the plane: the 3-point halo, and the cells of the block
-        // that lie beyond the patch interior (ragged tail: ghosts or unused)
-        const int64_t hb = P.off + pc + (int64_t)y0 * P.pitch_y + x0;
-        for (int e = tid; e < WHX * WHY; e += WX * WY) {
-            const int hy = e / WHX, hx = e - hy * WHX;
-            if (hx >= G && hx < G + WX && hy >= G && hy < G + WY && x0 + hx - G < P.n[0] && y0 + hy - G < P.n[1])
-                continue;
-            const bool ok = x0 + hx < P.n[0] + 2 * G && y0 + hy < P.n[1] + 2 * G;
-            pl[0][hy][hx] = ok ? U[hb + (int64_t)hy * P.pitch_y + hx] : 0.0;
-            pl[1][hy][hx] = ok ? U[hb + P.fs + (int64_t)hy * P.pitch_y + hx] : 0.0;
-        }
+#pragma unroll
+        for (int r = 0; r < NH; ++r)
+            if (hl[r] >= 0) {
+                (&pl[0][0][0])[hl[r]] = hp[r];
+                (&pl[1][0][0])[hl[r]] = hq[r];
+            }
+        const StageIn cp = sp, cq = sq;
+        if (k + 1 < z1) fetch(k + 1, hp, hq, sp, sq);
         __syncthreads();
         if (col) {
             const double* p = &pl[0][ty + G][tx + G];
@@ -80,8 +125,8 @@ __global__ __launch_bounds__(WX * WY) void wave_zmarch_kernel(StageArgs a, doubl
             double lap = fd2(p, 1) + fd2(p, WPX) + fd2(qp + 3, 1);
             double qphi = fko(p, 1) + fko(p, WPX) + fko(qp + 3, 1);
             double qpi = fko(q, 1) + fko(q, WPX) + fko(qq + 3, 1);
-            stage_store(a, cb + pc, -q[0] + ko * qphi);
-            stage_store(a, cb + pc + P.fs, -ih2 * lap + ko * qpi);
+            stage_apply(a, cb + pc, -q[0] + ko * qphi, cp);
+            stage_apply(a, cb + pc + P.fs, -ih2 * lap + ko * qpi, cq);
 #pragma unroll
             for (int m = 0; m < 6; ++m) {
                 qp[m] = qp[m + 1];

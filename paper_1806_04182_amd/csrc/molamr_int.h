@@ -12,6 +12,14 @@ namespace mol {
 
 constexpr int G = MOL_GHOST;
 
+// columns per workgroup of the z-marching wave kernel and the longest z chunk
+#ifndef MOL_WAVE_WX
+#define MOL_WAVE_WX 64
+#define MOL_WAVE_WY 8
+#endif
+#ifndef MOL_WAVE_ZMAX
+#define MOL_WAVE_ZMAX 32
+#endif
 // tile of the CCZ4 stage kernel (threads per workgroup = product)
 #ifndef MOL_CCZ4_TX
 #define MOL_CCZ4_TX 8
