@@ -165,6 +165,7 @@ def wave_mhd_bench(M):
     from paper_1806_04182_amd import synth
     out = {}
     for n in (32, 256):
+        log(f"bench: wave {n}^3")
         dx = 2.0 / n
         ps = M.Patchset(M.single_patch((n, n, n), (-1, -1, -1), dx), M.System(M.MOL_WAVE, sigma=0.1))
         st = ps.alloc_states()
@@ -189,6 +190,7 @@ def wave_mhd_bench(M):
                                "hbm_frac": gbs / HBM_PEAK_GBS, "bytes_per_pt_stage": 68.0}
         del g
     n = 128
+    log(f"bench: MHD {n}^3")
     dx = 1.0 / n
     ps = M.Patchset(M.single_patch((n, n, n), (0, 0, 0), dx), M.System(M.MOL_MHD, sigma=0.0))
     st = ps.alloc_states()
@@ -210,6 +212,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=96)
     ap.add_argument("--no-extras", action="store_true", help="skip the AMR and adjoint measurements")
+    ap.add_argument("--paths-only", action="store_true",
+                    help="measure only the wave and MHD paths and print their JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -223,6 +227,9 @@ def main():
     from paper_1806_04182_amd import synth
 
     assert torch.cuda.is_available(), "no GPU"
+    if args.paths_only:
+        print(json.dumps(wave_mhd_bench(M)), flush=True)
+        return
     n = args.n
     dx = 2.0 / n
     dt = 0.25 * dx
@@ -296,7 +303,15 @@ def main():
                      "kernel": "ccz4_stage_kernel", "kernel_ms": kms,
                      "bytes_per_pt_stage": CCZ4_BYTES_PER_PT_STAGE},
     }
-    res["roofline"]["traffic"] = traffic_from_profile(pts)
+    rec = ccz4_profile_record(pts)
+    if rec is not None:
+        res["roofline"]["traffic"] = rec["hbm_bytes_per_launch"]
+        # the same kernel against the FP64 vector peak, with the executed FP64
+        # FLOP per point-stage from the counter record
+        tf = rec["fp64_flop_per_pt_stage"] * pts / (kms * 1e-3) / 1e12
+        res["roofline_fp64"] = {"bound": "alu", "achieved": tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                "frac": tf / FP64_PEAK_TFLOPS, "flop_per_pt_stage": rec["fp64_flop_per_pt_stage"],
+                                "flop_count": "executed (SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes)"}
     if not args.no_extras:
         log("bench: batched AMR hierarchy")
         res["amr_plain_vs_batched"] = amr_bench(M)
@@ -312,22 +327,19 @@ def main():
     print(json.dumps(res), flush=True)
 
 
-def traffic_from_profile(pts):
-    """HBM bytes per stage launch of the CCZ4 kernel from the committed
-    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy
-    of known size), or None when the kernel source changed since."""
-    import hashlib
+def ccz4_profile_record(pts):
+    """The committed rocprofv3 counter record of the CCZ4 stage kernel (HBM
+    bytes per launch, FP64 FLOP per point-stage), or None when the kernel
+    sources changed since it was taken or the workload differs."""
+    from paper_1806_04182_amd import profsum
     path = os.path.join(ROOT, "profiles", "ccz4_stage_96cube_traffic.json")
     try:
         rec = json.load(open(path))
     except (OSError, ValueError):
         return None
-    h = hashlib.sha256()
-    for f in ("k_ccz4.hip", "k_common.h", "molamr_int.h"):
-        h.update(open(os.path.join(ROOT, "paper_1806_04182_amd", "csrc", f), "rb").read())
-    if rec.get("source_sha256") != h.hexdigest() or rec.get("points") != pts:
+    if rec.get("source_sha256") != profsum.ccz4_source_hash() or rec.get("points") != pts:
         return None
-    return rec["hbm_bytes_per_launch"]
+    return rec
 
 
 def _cpu_name():

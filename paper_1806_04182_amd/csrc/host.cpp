@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <array>
+#include <map>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -104,9 +105,10 @@ struct mol_patchset {
         std::vector<int64_t> fill_by_patch;
         DevArr<GhostSource> fill_src;
         DevArr<GhostImage> fill_img;
-        // coarse-fine ghost points (this level is the fine one), by dst patch
-        DevArr<ProlongPt> pro;
-        std::vector<int64_t> pro_by_patch;
+        // coarse-fine ghost points (this level is the fine one) grouped by
+        // parent cell, by dst patch
+        DevArr<ProlongCell> pcell;
+        std::vector<int64_t> pcell_by_patch;
         std::vector<double> lagw;  // Lagrange weights [R][6]
         // parent points read by the prolongation stencils of this level: the
         // position in a parent patch's ghosted box (dst) and the interior
@@ -133,7 +135,7 @@ struct mol_patchset {
             l.fill.release();
             l.fill_src.release();
             l.fill_img.release();
-            l.pro.release();
+            l.pcell.release();
             l.band.release();
             l.rst.release();
             l.tiles.dev.release();
@@ -203,6 +205,21 @@ std::vector<std::vector<int>> candidates(const Level& a, int grow, const Level& 
     }
     return out;
 }
+
+// Coarse-fine ghost point (host side, used to build the band and the cells):
+// destination (fine level), base of its parent stencil (parent level, field 0,
+// lowest corner), field strides, parent pitches and the fine index modulo R.
+struct ProlongPt {
+    int64_t dst;
+    int64_t cbase;
+    int64_t dfs;
+    int64_t cfs;
+    int32_t cpy;
+    int32_t cpz;
+    int8_t m[3];
+};
+
+int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 
 void build_tiles(const Level& lev, const int td[3], int margin, TileList& tl)
 {
@@ -307,8 +324,10 @@ int build(mol_patchset* ps, const mol_hierarchy_desc* h)
         auto cand = candidates(lev, G, lev, 1);
         std::vector<GhostCopy> fill;
         std::vector<ProlongPt> pro;
+        std::vector<int64_t> pro_by_patch(lev.pd.size() + 1, 0);
+        std::vector<ProlongCell> cells;
         lev.fill_by_patch.assign(lev.pd.size() + 1, 0);
-        lev.pro_by_patch.assign(lev.pd.size() + 1, 0);
+        lev.pcell_by_patch.assign(lev.pd.size() + 1, 0);
         const Level* par = l > 0 ? &ps->L[l - 1] : nullptr;
         std::vector<std::vector<int>> pcand;
         std::vector<int> allpar;
@@ -319,8 +338,18 @@ int build(mol_patchset* ps, const mol_hierarchy_desc* h)
         const int R = lev.ratio;
         for (size_t p = 0; p < lev.pd.size(); ++p) {
             lev.fill_by_patch[p] = (int64_t)fill.size();
-            lev.pro_by_patch[p] = (int64_t)pro.size();
+            pro_by_patch[p] = (int64_t)pro.size();
+            lev.pcell_by_patch[p] = (int64_t)cells.size();
             const PatchDev& pd = lev.pd[p];
+            // parent cells of this patch's coarse-fine ghost points: cell
+            // coordinates floor(g / R), owner patch and owned position of i0
+            struct CellTmp {
+                int key[3], q0, cw[3];
+                uint64_t mask;
+                int frac;
+            };
+            std::vector<CellTmp> ct;
+            std::map<std::array<int, 3>, size_t> cidx;
             for (int k = -G; k < pd.n[2] + G; ++k)
                 for (int j = -G; j < pd.n[1] + G; ++j)
                     for (int i = -G; i < pd.n[0] + G; ++i) {
@@ -371,12 +400,43 @@ int build(mol_patchset* ps, const mol_hierarchy_desc* h)
                         e.cpz = qd.pitch_z;
                         for (int d = 0; d < 3; ++d) e.m[d] = (int8_t)m[d];
                         pro.push_back(e);
+                        const std::array<int, 3> key = {floor_div(g[0], R), floor_div(g[1], R), floor_div(g[2], R)};
+                        auto it = cidx.find(key);
+                        if (it == cidx.end()) {
+                            it = cidx.emplace(key, ct.size()).first;
+                            ct.push_back(CellTmp{{key[0], key[1], key[2]}, q0, {cw[0], cw[1], cw[2]}, 0, 0});
+                        }
+                        CellTmp& c = ct[it->second];
+                        c.mask |= uint64_t(1) << ((m[2] * R + m[1]) * R + m[0]);
+                        for (int d = 0; d < 3; ++d)
+                            if (m[d]) c.frac |= 1 << d;
                     }
+            // cells ordered by their fractional axes (uniform work within a wave)
+            std::stable_sort(ct.begin(), ct.end(), [](const CellTmp& a, const CellTmp& b) { return a.frac < b.frac; });
+            for (const CellTmp& c : ct) {
+                const PatchDev& qd = par->pd[c.q0];
+                int c0[3];
+                for (int d = 0; d < 3; ++d) c0[d] = c.cw[d] - qd.lo[d] + G - ((c.frac >> d & 1) ? 2 : 0);
+                ProlongCell e{};
+                e.dbase = pd.off + local_index(pd, R * c.key[0] - pd.lo[0] + G, R * c.key[1] - pd.lo[1] + G,
+                                               R * c.key[2] - pd.lo[2] + G);
+                e.cbase = qd.off + local_index(qd, c0[0], c0[1], c0[2]);
+                e.dfs = pd.fs;
+                e.cfs = qd.fs;
+                e.dpy = pd.pitch_y;
+                e.dpz = pd.pitch_z;
+                e.cpy = qd.pitch_y;
+                e.cpz = qd.pitch_z;
+                e.mask = c.mask;
+                e.frac = c.frac;
+                cells.push_back(e);
+            }
         }
         lev.fill_by_patch[lev.pd.size()] = (int64_t)fill.size();
-        lev.pro_by_patch[lev.pd.size()] = (int64_t)pro.size();
+        pro_by_patch[lev.pd.size()] = (int64_t)pro.size();
+        lev.pcell_by_patch[lev.pd.size()] = (int64_t)cells.size();
         if ((rc = lev.fill.upload(fill))) return rc;
-        if ((rc = lev.pro.upload(pro))) return rc;
+        if ((rc = lev.pcell.upload(cells))) return rc;
         if (par) {
             // every parent point that some stencil reads, once, grouped by the
             // fine patch that first needs it (so per-patch launches cover it)
@@ -391,7 +451,7 @@ int build(mol_patchset* ps, const mol_hierarchy_desc* h)
             std::vector<int64_t> fs_of(par->pd.size());
             for (size_t p = 0; p < lev.pd.size(); ++p) {
                 lev.band_by_patch[p] = (int64_t)band.size();
-                for (int64_t t = lev.pro_by_patch[p]; t < (int64_t)(p + 1 < lev.pd.size() ? lev.pro_by_patch[p + 1] : pro.size()); ++t) {
+                for (int64_t t = pro_by_patch[p]; t < pro_by_patch[p + 1]; ++t) {
                     const ProlongPt& e = pro[t];
                     for (int c = 0; c < (e.m[2] ? 6 : 1); ++c)
                         for (int b = 0; b < (e.m[1] ? 6 : 1); ++b)
@@ -441,11 +501,10 @@ int build(mol_patchset* ps, const mol_hierarchy_desc* h)
             if ((rc = lev.fill_img.upload(imgs))) return rc;
         }
         if (par) {
-            // Lagrange weights at xi = m/R through nodes -2..3 (Sec. III.A);
-            // row m = 0 is the coincident copy
+            // Lagrange weights at xi = m/R through nodes -2..3 (Sec. III.A)
+            // (row m = 0 is (0, 0, 1, 0, 0, 0); the kernel takes that node as is)
             std::vector<double> lw(R * 6, 0.0);
-            lw[0] = 1.0;
-            for (int m = 1; m < R; ++m) {
+            for (int m = 0; m < R; ++m) {
                 double xi = (double)m / R;
                 for (int j = 0; j < 6; ++j) {
                     double num = 1.0, den = 1.0;
@@ -611,9 +670,9 @@ int prolong_impl(mol_patchset* ps, int fl, int r, int stage, const double* Unc,
         if (e != hipSuccess) return hip_fail(e, "BOR band launch");
     }
     for (int p = 0; p < nl; ++p) {
-        const int64_t b0 = plain ? lev.pro_by_patch[p] : 0;
-        const int64_t bn = plain ? lev.pro_by_patch[p + 1] - b0 : lev.pro.n;
-        hipError_t e = launch_prolong(lev.pro.p + b0, bn, nf, lev.ratio, lev.lagw.data(), ps->tband, Uf, st);
+        const int64_t b0 = plain ? lev.pcell_by_patch[p] : 0;
+        const int64_t bn = plain ? lev.pcell_by_patch[p + 1] - b0 : lev.pcell.n;
+        hipError_t e = launch_prolong(lev.pcell.p + b0, bn, nf, lev.ratio, lev.lagw.data(), ps->tband, Uf, st);
         if (e != hipSuccess) return hip_fail(e, "prolong launch");
     }
     return MOL_OK;

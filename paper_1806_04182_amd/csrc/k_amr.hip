@@ -69,42 +69,90 @@ __global__ __launch_bounds__(BLK) void bor_band_kernel(const GhostCopy* __restri
     }
 }
 
-// Lagrange weights at xi = m / R, m = 0 .. R-1 (row 0: the coincident copy)
+// Lagrange weights at xi = m / R, m = 0 .. R-1
 struct LagW {
     double w[4][6];
 };
 
-// coarse-fine ghost point: tensor-product Lagrange interpolation (Sec. III.A)
-// of the parent's BOR stage state; one thread per (ghost point, field)
-__global__ __launch_bounds__(BLK) void prolong_kernel(const ProlongPt* __restrict__ e, int64_t n, int nf, LagW L,
+// Coarse-fine ghost points: tensor-product quintic Lagrange interpolation
+// (Sec. III.A) of the parent's BOR stage state.  One thread per (parent cell,
+// field) loads the cell's stencil once and forms every present fine point of
+// the cell, axis by axis (x, then y, then z).  On a fractional axis a point
+// with m = 0 takes the node i0 itself (selected, not weighted), so only the
+// nodes of its own stencil enter its value.
+template <int R>
+__global__ __launch_bounds__(BLK) void prolong_kernel(const ProlongCell* __restrict__ e, int64_t n, int nf, LagW L,
                                                       const double* __restrict__ T, double* __restrict__ U)
 {
     const int64_t tot = n * nf;
     for (int64_t t = blockIdx.x * (int64_t)BLK + threadIdx.x; t < tot; t += (int64_t)gridDim.x * BLK) {
         const int f = (int)(t / n);
-        const ProlongPt p = e[t - (int64_t)f * n];
-        const int cx = p.m[0] ? 6 : 1, cy = p.m[1] ? 6 : 1, cz = p.m[2] ? 6 : 1;
-        const double* wx = L.w[p.m[0]];
-        const double* wy = L.w[p.m[1]];
-        const double* wz = L.w[p.m[2]];
-        const int64_t base = p.cbase + f * p.cfs;
-        double sz = 0.0;
-        for (int c = 0; c < cz; ++c) {
-            double sy = 0.0;
-            for (int b = 0; b < cy; ++b) {
-                const double* row = T + base + (int64_t)c * p.cpz + (int64_t)b * p.cpy;
-                double sx = 0.0;
-                if (cx == 6) {
+        const ProlongCell c = e[t - (int64_t)f * n];
+        const bool fx = c.frac & 1, fy = c.frac & 2, fz = c.frac & 4;
+        const double* __restrict__ base = T + c.cbase + f * c.cfs;
+        double out[R][R][R];  // [mz][my][mx]
 #pragma unroll
-                    for (int a = 0; a < 6; ++a) sx += wx[a] * row[a];
+        for (int kc = 0; kc < 6; ++kc) {
+            if (kc > 0 && !fz) break;
+            double Y[R][R];  // [my][mx] at this z node
+#pragma unroll
+            for (int kb = 0; kb < 6; ++kb) {
+                if (kb > 0 && !fy) break;
+                const double* row = base + kc * c.cpz + kb * c.cpy;
+                double X[R];
+                if (fx) {
+                    double r[6];
+#pragma unroll
+                    for (int a = 0; a < 6; ++a) r[a] = row[a];
+                    X[0] = r[2];
+#pragma unroll
+                    for (int mx = 1; mx < R; ++mx) {
+                        double sx = 0.0;
+#pragma unroll
+                        for (int a = 0; a < 6; ++a) sx += L.w[mx][a] * r[a];
+                        X[mx] = sx;
+                    }
                 } else {
-                    sx = row[0];
+#pragma unroll
+                    for (int mx = 0; mx < R; ++mx) X[mx] = row[0];
                 }
-                sy += wy[b] * sx;
+#pragma unroll
+                for (int my = 0; my < R; ++my)
+#pragma unroll
+                    for (int mx = 0; mx < R; ++mx) {
+                        if (!fy) {
+                            Y[my][mx] = X[mx];
+                        } else if (my == 0) {
+                            if (kb == 2) Y[0][mx] = X[mx];
+                        } else {
+                            Y[my][mx] = (kb == 0 ? 0.0 : Y[my][mx]) + L.w[my][kb] * X[mx];
+                        }
+                    }
             }
-            sz += wz[c] * sy;
+#pragma unroll
+            for (int mz = 0; mz < R; ++mz)
+#pragma unroll
+                for (int my = 0; my < R; ++my)
+#pragma unroll
+                    for (int mx = 0; mx < R; ++mx) {
+                        if (!fz) {
+                            out[mz][my][mx] = Y[my][mx];
+                        } else if (mz == 0) {
+                            if (kc == 2) out[0][my][mx] = Y[my][mx];
+                        } else {
+                            out[mz][my][mx] = (kc == 0 ? 0.0 : out[mz][my][mx]) + L.w[mz][kc] * Y[my][mx];
+                        }
+                    }
         }
-        U[p.dst + f * p.dfs] = sz;
+        double* __restrict__ d = U + c.dbase + f * c.dfs;
+#pragma unroll
+        for (int mz = 0; mz < R; ++mz)
+#pragma unroll
+            for (int my = 0; my < R; ++my)
+#pragma unroll
+                for (int mx = 0; mx < R; ++mx)
+                    if (c.mask >> ((mz * R + my) * R + mx) & 1)
+                        d[(int64_t)mz * c.dpz + (int64_t)my * c.dpy + mx] = out[mz][my][mx];
     }
 }
 
@@ -152,15 +200,19 @@ hipError_t launch_bor_band(const GhostCopy* band, int64_t n, int nf, const doubl
     return hipGetLastError();
 }
 
-hipError_t launch_prolong(const ProlongPt* e, int64_t n, int nf, int R, const double* lw_host, const double* T,
+hipError_t launch_prolong(const ProlongCell* e, int64_t n, int nf, int R, const double* lw_host, const double* T,
                           double* U, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    if (R < 1 || R > 4) return hipErrorInvalidValue;
     LagW L{};
+    if (R < 2 || R > 4) return hipErrorInvalidValue;
     for (int m = 0; m < R; ++m)
         for (int j = 0; j < 6; ++j) L.w[m][j] = lw_host[m * 6 + j];
-    prolong_kernel<<<grid_for(n * nf), BLK, 0, s>>>(e, n, nf, L, T, U);
+    switch (R) {
+    case 2: prolong_kernel<2><<<grid_for(n * nf), BLK, 0, s>>>(e, n, nf, L, T, U); break;
+    case 3: prolong_kernel<3><<<grid_for(n * nf), BLK, 0, s>>>(e, n, nf, L, T, U); break;
+    default: prolong_kernel<4><<<grid_for(n * nf), BLK, 0, s>>>(e, n, nf, L, T, U); break;
+    }
     return hipGetLastError();
 }
 

@@ -74,18 +74,22 @@ struct GhostImage {
     int64_t dfs;
 };
 
-// Coarse-fine ghost point: destination (fine level), base of its parent
-// stencil (parent level, field 0, lowest corner), field strides, parent
-// pitches and the fine index modulo R per axis.
-struct ProlongPt {
-    int64_t dst;
+// Coarse-fine ghost points of one fine patch grouped by parent cell: the
+// fine points R i0 + m (m in [0, R)^3) of parent cell i0.  Bit
+// (mz R + my) R + mx of mask marks the points present.  Axis d is fractional
+// (bit d of frac) when some present point has m_d != 0; the stencil then
+// spans parent nodes i0-2 .. i0+3 on that axis, otherwise only i0; cbase is
+// the stencil corner.  dbase is the fine-level index of the point m = 0,
+// which may lie outside the fine patch's ghosted box.
+struct ProlongCell {
+    int64_t dbase;
     int64_t cbase;
-    int64_t dfs;
-    int64_t cfs;
-    int32_t cpy;
-    int32_t cpz;
-    int8_t m[3];
-    int8_t pad[5];
+    int64_t dfs, cfs;  // field strides (fine, parent)
+    int32_t dpy, dpz;  // fine pitches
+    int32_t cpy, cpz;  // parent pitches
+    uint64_t mask;
+    int32_t frac;
+    int32_t pad;
 };
 
 // Injection: fine offset, coarse offset (field 0) and field strides.
@@ -139,7 +143,7 @@ hipError_t launch_fill_adjoint(const GhostSource* src, int64_t nsrc, const Ghost
 hipError_t launch_bor_band(const GhostCopy* band, int64_t n, int nf, const double w[4], const double* Un,
                            const double* k0, const double* k1, const double* k2, const double* k3, double* T,
                            hipStream_t s);
-hipError_t launch_prolong(const ProlongPt* e, int64_t n, int nf, int R, const double* lw_host, const double* T,
+hipError_t launch_prolong(const ProlongCell* e, int64_t n, int nf, int R, const double* lw_host, const double* T,
                           double* U, hipStream_t s);
 hipError_t launch_restrict(const RestrictPt* e, int64_t n, int nf, const double* Uf, double* Uc,
                            hipStream_t s);
