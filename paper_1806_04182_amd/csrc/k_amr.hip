@@ -15,13 +15,30 @@ int grid_for(int64_t n)
     return (int)(b < 1 ? 1 : (b > 65535 * 8 ? 65535 * 8 : b));
 }
 
+// Copies of nf fields between two points: the loads of up to FC fields are
+// issued together before their stores.
+constexpr int FC = 8;
+__device__ __forceinline__ void copy_fields(const double* __restrict__ src, int64_t sfs, double* __restrict__ dst,
+                                            int64_t dfs, int nf)
+{
+    for (int f0 = 0; f0 < nf; f0 += FC) {
+        double v[FC];
+#pragma unroll
+        for (int j = 0; j < FC; ++j)
+            if (f0 + j < nf) v[j] = src[(f0 + j) * sfs];
+#pragma unroll
+        for (int j = 0; j < FC; ++j)
+            if (f0 + j < nf) dst[(f0 + j) * dfs] = v[j];
+    }
+}
+
 // same-level / periodic copy: ghost <- interior point of the owning patch
 __global__ __launch_bounds__(BLK) void fill_kernel(const GhostCopy* __restrict__ e, int64_t n, int nf,
                                                    double* __restrict__ U)
 {
     for (int64_t t = blockIdx.x * (int64_t)BLK + threadIdx.x; t < n; t += (int64_t)gridDim.x * BLK) {
         const GhostCopy c = e[t];
-        for (int f = 0; f < nf; ++f) U[c.dst + f * c.dfs] = U[c.src + f * c.sfs];
+        copy_fields(U + c.src, c.sfs, U + c.dst, c.dfs, nf);
     }
 }
 
@@ -161,7 +178,7 @@ __global__ __launch_bounds__(BLK) void restrict_kernel(const RestrictPt* __restr
 {
     for (int64_t t = blockIdx.x * (int64_t)BLK + threadIdx.x; t < n; t += (int64_t)gridDim.x * BLK) {
         const RestrictPt r = e[t];
-        for (int f = 0; f < nf; ++f) Uc[r.c + f * r.cfs] = Uf[r.f + f * r.ffs];
+        copy_fields(Uf + r.f, r.ffs, Uc + r.c, r.cfs, nf);
     }
 }
 
