@@ -182,3 +182,65 @@ def test_ccz4_axis_permutation():
     R1rot = rot_fields(R1i[:, None, None, :])[:, 0, 0, :]
     scale = np.max(np.abs(R1i))
     assert np.max(np.abs(R1rot - R2i)) < 1e-12 * scale
+
+
+def _lapse_pulse_2d(N, A=0.1, w=0.5):
+    """Flat space (gt = I, chi = 1, K = 0, Ghat = 0) with a smooth periodic
+    lapse alpha = 1 + A exp(-(sin^2(pi x / 2) + sin^2(pi y / 2)) / w^2) on an
+    N x N x 1 grid of [-1, 1)^2: pure gauge, so the constraints are zero in
+    the continuum and the discrete violations are truncation errors."""
+    x = -1.0 + 2.0 * np.arange(N) / N
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    s = (np.sin(np.pi * X / 2) ** 2 + np.sin(np.pi * Y / 2) ** 2) / w ** 2
+    out = np.empty((25, 1, N, N))
+    out[:] = synth.CCZ4_FLAT[:, None, None, None]
+    out[ALP, 0] = 1 + A * np.exp(-s)
+    return out
+
+
+def _constraint_norms(U):
+    """rms of Theta, ln det gt and tr At = gt^{ij} At_ij over the interior."""
+    I = synth.interior(U)
+    g = I[GT:GT + 6]
+    det = g[0] * (g[3] * g[5] - g[4] ** 2) - g[1] * (g[1] * g[5] - g[4] * g[2]) + g[2] * (g[1] * g[4] - g[3] * g[2])
+    cof = [g[3] * g[5] - g[4] ** 2, g[2] * g[4] - g[1] * g[5], g[1] * g[4] - g[2] * g[3],
+           g[0] * g[5] - g[2] ** 2, g[2] * g[1] - g[0] * g[4], g[0] * g[3] - g[1] ** 2]
+    A = I[AT:AT + 6]
+    trA = (cof[0] * A[0] + cof[3] * A[3] + cof[5] * A[5] + 2 * (cof[1] * A[1] + cof[2] * A[2] + cof[4] * A[4])) / det
+    rms = lambda a: float(np.sqrt(np.mean(a ** 2)))
+    return np.array([rms(I[TH]), rms(np.log(det)), rms(trA)])
+
+
+def test_lapse_pulse_constraints_converge_order4():
+    """The constraint quantities of a pure-gauge evolution self-converge to zero
+    at 4th order (Sec. II.B.1 stencils, RK4; dissipation is 5th order)."""
+    T = 0.5
+    norms = []
+    for N in (32, 64):
+        dx = 2.0 / N
+        U = synth.embed(_lapse_pulse_2d(N))
+        nsteps = int(round(T / (0.25 * dx)))
+        O.rk_run(O.CCZ4, O.RK4, U, (dx, dx, dx), T / nsteps, nsteps, O.params())
+        norms.append(_constraint_norms(U))
+    order = np.log2(norms[0] / norms[1])
+    assert np.all(norms[1] > 0)
+    assert np.all((order > 3.5) & (order < 5.2)), order
+
+
+def test_noisy_minkowski_stays_bounded():
+    """Robust stability: Minkowski plus 1e-10 noise on every field.  The first
+    steps amplify the grid-scale noise by a bounded factor (second differences
+    of white noise, about 40x at 16^3, growing with the resolution); after
+    that the deviation from flat space must not grow (no exponential mode),
+    over 50 RK4 steps."""
+    n = (16, 16, 16)
+    dx = 2.0 / 16
+    U = synth.embed(synth.ccz4_minkowski_noise(n, amp=1e-10, seed=3))
+    flat = synth.CCZ4_FLAT[:, None, None, None]
+    dev0 = np.max(np.abs(synth.interior(U) - flat))
+    devs = []
+    for _ in range(10):
+        O.rk_run(O.CCZ4, O.RK4, U, (dx, dx, dx), 0.25 * dx, 5, O.params())
+        devs.append(np.max(np.abs(synth.interior(U) - flat)))
+    assert max(devs) <= 1e4 * dev0, (dev0, devs)
+    assert max(devs[5:]) <= max(devs[:5]), devs
