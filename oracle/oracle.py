@@ -95,6 +95,7 @@ def lib():
         L.orc_wave_adjoint_run.argtypes = [dp, i, i, i, dp, dp, d, i, d, P]
         L.orc_sphere_integral.argtypes = [dp, i, i, i, i, dp, dp, d, d]
         L.orc_sphere_integral.restype = d
+        L.orc_ccz4_rhs_jvp.argtypes = [dp, dp, dp, dp, i, i, i, dp, P]
         _lib = L
     return _lib
 
@@ -270,3 +271,39 @@ class Hierarchy:
 
     def restrict(self, l: int) -> None:
         lib().orc_hier_restrict(self._h, l)
+
+
+def ccz4_rhs_jvp(U: np.ndarray, V: np.ndarray, h, prm: Params | None = None):
+    """(R(U), R'(U) V) of the CCZ4 right-hand side on a ghosted patch array,
+    the derivative exact up to rounding (dual-number build of the oracle)."""
+    prm = prm or params()
+    nf, nx, ny, nz = dims(U)
+    assert nf == 25 and V.shape == U.shape
+    R = np.zeros_like(U)
+    RV = np.zeros_like(U)
+    lib().orc_ccz4_rhs_jvp(_p(U), _p(np.ascontiguousarray(V)), _p(R), _p(RV), nx, ny, nz, _p(_h3(h)),
+                           ctypes.byref(prm))
+    return R, RV
+
+
+def ccz4_rhs_vjp_periodic(U: np.ndarray, lam: np.ndarray, h, prm: Params | None = None) -> np.ndarray:
+    """Transpose of the CCZ4 right-hand side of a periodic patch applied to lam:
+    (lamU)_{f,p} = sum over interior points c of lam(c) . d R(c) / d U_f(p),
+    where U's ghosts are the periodic images of its interior.  Assembled
+    column by column from exact JVPs (one per interior value): small patches
+    only.  U is a ghosted array with filled ghosts; lam and the result are
+    interior arrays (25, nz, ny, nx)."""
+    nf, nx, ny, nz = dims(U)
+    out = np.zeros((nf, nz, ny, nx))
+    V = np.zeros_like(U)
+    for f in range(nf):
+        for k in range(nz):
+            for j in range(ny):
+                for i in range(nx):
+                    V[:] = 0.0
+                    V[f, k + 3, j + 3, i + 3] = 1.0
+                    fill_periodic(V)
+                    _, RV = ccz4_rhs_jvp(U, V, h, prm)
+                    out[f, k, j, i] = np.sum(lam * RV[:, 3:-3, 3:-3, 3:-3])
+    return out
+

@@ -244,3 +244,30 @@ def test_noisy_minkowski_stays_bounded():
         devs.append(np.max(np.abs(synth.interior(U) - flat)))
     assert max(devs) <= 1e4 * dev0, (dev0, devs)
     assert max(devs[5:]) <= max(devs[:5]), devs
+
+
+def _nonflat_state(n, dx, seed):
+    st = synth.ccz4_lapse_pulse(n, (-1, -1, -1), dx, amp=0.2, width=0.4)
+    st = st + synth.ccz4_minkowski_noise(n, amp=1e-2, seed=seed) - synth.CCZ4_FLAT[:, None, None, None]
+    U = synth.embed(st)
+    O.fill_periodic(U)
+    return U
+
+
+def test_jvp_build_repeats_the_rhs_and_matches_central_differences():
+    """The dual-number build of the oracle: its value part is the right-hand
+    side bit for bit, and its derivative part is the limit of central
+    difference quotients (error falling as eps^2)."""
+    n, dx = (5, 4, 4), 0.15
+    U = _nonflat_state(n, dx, 2)
+    rng = np.random.default_rng(0)
+    V = synth.embed(rng.standard_normal((25,) + tuple(reversed(n))))
+    O.fill_periodic(V)
+    R, RV = O.ccz4_rhs_jvp(U, V, dx)
+    I = (slice(None), slice(3, -3), slice(3, -3), slice(3, -3))
+    assert np.array_equal(R[I], O.rhs(O.CCZ4, U, dx)[I])
+    errs = []
+    for eps in (1e-5, 1e-6):
+        fd = (O.rhs(O.CCZ4, U + eps * V, dx) - O.rhs(O.CCZ4, U - eps * V, dx)) / (2 * eps)
+        errs.append(np.max(np.abs(fd[I] - RV[I])) / np.max(np.abs(RV[I])))
+    assert errs[1] < 1e-9 and errs[1] < errs[0], errs
