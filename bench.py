@@ -111,27 +111,44 @@ def amr_bench(M, steps=2):
     return res
 
 
-def adjoint_bench(M, n=64, nsteps=200, every=20):
-    """Wave 64^3, 200 RK4 steps, checkpoints every 20: forward (with the
-    objective) and backward (reverse sweep + initial-data VJP) times."""
+def _time_objective(fn, p, *args):
     import torch
-    from paper_1806_04182_amd.adjoint import sphere_objective
-    dx = 2.0 / n
-    ps = M.Patchset(M.single_patch((n, n, n), (-1, -1, -1), dx), M.System(M.MOL_WAVE, sigma=0.1))
-    p = torch.tensor([1.0, 0.2, 0.1, -0.05, 0.02], dtype=torch.float64, requires_grad=True)
-    sphere_objective(p, ps, 4, 0.25 * dx, 0.6, every)  # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    J = sphere_objective(p, ps, nsteps, 0.25 * dx, 0.6, every)
+    J = fn(p, *args)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     J.backward()
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    fwd, bwd = t1 - t0, t2 - t1
-    return {"workload": f"wave_{n}^3_rk4_{nsteps}_steps_checkpoint_{every}", "fwd_s": fwd, "bwd_s": bwd,
-            "bwd_over_fwd": bwd / fwd, "fwd_plus_bwd_over_fwd": (fwd + bwd) / fwd,
-            "dJ_dA_minus_J": float(p.grad[0]) - float(J.detach()), "ccz4": None}
+    return J, t1 - t0, t2 - t1
+
+
+def adjoint_bench(M, n=64, nsteps=200, every=20, n_ccz4=48):
+    """Wave 64^3 and CCZ4 48^3 (lapse pulse), 200 RK4 steps, checkpoints every
+    20: forward (with the objective) and backward (reverse sweep, recomputed
+    segments for CCZ4, initial-data VJP) wall times."""
+    import torch
+    from paper_1806_04182_amd.adjoint import ccz4_lapse_objective, sphere_objective
+    dx = 2.0 / n
+    ps = M.Patchset(M.single_patch((n, n, n), (-1, -1, -1), dx), M.System(M.MOL_WAVE, sigma=0.1))
+    p = torch.tensor([1.0, 0.2, 0.1, -0.05, 0.02], dtype=torch.float64, requires_grad=True)
+    sphere_objective(p, ps, 4, 0.25 * dx, 0.6, every)  # warm-up
+    J, fwd, bwd = _time_objective(sphere_objective, p, ps, nsteps, 0.25 * dx, 0.6, every)
+    res = {"workload": f"wave_{n}^3_rk4_{nsteps}_steps_checkpoint_{every}", "fwd_s": fwd, "bwd_s": bwd,
+           "bwd_over_fwd": bwd / fwd, "fwd_plus_bwd_over_fwd": (fwd + bwd) / fwd,
+           "dJ_dA_minus_J": float(p.grad[0]) - float(J.detach())}
+    log(f"bench: CCZ4 adjoint {n_ccz4}^3")
+    dx = 2.0 / n_ccz4
+    ps = M.Patchset(M.single_patch((n_ccz4,) * 3, (-1, -1, -1), dx), M.System(M.MOL_CCZ4))
+    p = torch.tensor([0.1, 0.4, 0.05, -0.1, 0.02], dtype=torch.float64, requires_grad=True)
+    p0 = torch.tensor([0.1, 0.4, 0.05, -0.1, 0.02], dtype=torch.float64, requires_grad=True)
+    ccz4_lapse_objective(p0, ps, 4, 0.25 * dx, 0.6, every).backward()  # warm-up
+    J, fwd, bwd = _time_objective(ccz4_lapse_objective, p, ps, nsteps, 0.25 * dx, 0.6, every)
+    res["ccz4"] = {"workload": f"ccz4_{n_ccz4}^3_lapse_pulse_rk4_{nsteps}_steps_checkpoint_{every}", "fwd_s": fwd,
+                   "bwd_s": bwd, "bwd_over_fwd": bwd / fwd, "fwd_plus_bwd_over_fwd": (fwd + bwd) / fwd,
+                   "J": float(J.detach()), "dJ_dA": float(p.grad[0])}
+    return res
 
 
 def stage_kernel_time(ps, M, st, scheme, dt, reps=10):

@@ -176,23 +176,33 @@ int mol_bor_weights(int R, int r, int stage, double w[4]);
 int mol_restrict(mol_patchset* ps, int fine_level, const double* U_f, double* U_c,
                  void* stream);
 
-/* Vector-Jacobian product of the right-hand side (project addition, wave
- * system only): lamU = (d(L + Q_d)/dU)^T lam over the ghosted box of every
- * patch, with lam read on interior points only (its ghost values are
- * ignored).  Ghost entries of lamU receive the contributions of the stencil
- * reads; fold them back with mol_fill_ghosts_adjoint.  MOL_EUNSUPPORTED for
- * other systems. */
+/* Vector-Jacobian product of the right-hand side (project addition; wave
+ * and CCZ4 systems): lamU = (d(L + Q_d)/dU)^T lam at the state U, over the
+ * ghosted box of every patch, with lam read on interior points only (its
+ * ghost values are ignored).  Ghost entries of lamU receive the
+ * contributions of the stencil reads; fold them back with
+ * mol_fill_ghosts_adjoint.  U (ghosts filled) is read by the CCZ4 system;
+ * the wave operator is linear and ignores it.  work: device memory of
+ * mol_adjoint_workspace(ps, level) doubles (NULL when that is 0), overwritten.
+ * The sign branch of the lop-sided advection stencils is taken at U.
+ * MOL_EUNSUPPORTED for MHD. */
 int mol_rhs_adjoint(mol_patchset* ps, int level, const double* U, const double* lam,
-                    double* lamU, void* stream);
+                    double* lamU, double* work, void* stream);
+/* Doubles of workspace mol_rhs_adjoint needs on `level` (0 for the wave;
+ * CCZ4: 139 per point of the padded ghosted boxes); negative on error. */
+int64_t mol_adjoint_workspace(const mol_patchset* ps, int level);
 /* Transpose of mol_fill_ghosts: every source point adds the ghost entries
  * that copy it, then those ghost entries are zeroed (owner gather, no atomics). */
 int mol_fill_ghosts_adjoint(mol_patchset* ps, int level, double* lamU, void* stream);
-/* Reverse of one RK4 step (Table RK44) of the wave system on one periodic
- * level: lam <- (dU^{n+1}/dU^n)^T lam on interior points.  w0, w1, w2 are
- * work buffers of the level's size.  Ghost entries of lam are ignored and
- * left unchanged. */
-int mol_rk4_adjoint_step(mol_patchset* ps, int level, double dt, double* lam,
-                         double* w0, double* w1, double* w2, void* stream);
+/* Reverse of one RK4 step (Table RK44) on one periodic level:
+ * lam <- (dU^{n+1}/dU^n)^T lam on interior points, where U^n is the state at
+ * the start of the step (ghosts filled; read by the CCZ4 system, which
+ * recomputes the stage states from it with the forward stage kernel; NULL
+ * allowed for the wave).  w[0..5]: work buffers of the level's size (the wave
+ * uses w[0..2] only); work: as for mol_rhs_adjoint.  Ghost entries of lam are
+ * ignored and left unchanged. */
+int mol_rk4_adjoint_step(mol_patchset* ps, int level, double dt, const double* Un, double* lam,
+                         double* const w[6], double* work, void* stream);
 
 /* Reductions over the interior of every patch of the level, for
  * v = U[field] - shift: out_dev[0] = sum |v| dV, [1] = sum v^2 dV,
@@ -216,6 +226,15 @@ int mol_wave_gaussian(mol_patchset* ps, int level, const double prm[5], double* 
                       void* stream);
 int mol_wave_gaussian_vjp(mol_patchset* ps, int level, const double prm[5],
                           const double* lam, double* grad_dev, void* stream);
+/* CCZ4 lapse pulse (a pure-gauge perturbation of flat space, Sec. V
+ * variables): chi = 1, gt_ij = delta_ij, alpha = 1 + A exp(-|x-c|^2/w^2)
+ * (minimum image), every other field 0, with prm = {A, w, cx, cy, cz}; and
+ * its vector-Jacobian product grad_dev[i] = sum_points lam_alpha
+ * d alpha / d prm_i (interior points). */
+int mol_ccz4_lapse_pulse(mol_patchset* ps, int level, const double prm[5], double* U,
+                         void* stream);
+int mol_ccz4_lapse_pulse_vjp(mol_patchset* ps, int level, const double prm[5],
+                             const double* lam, double* grad_dev, void* stream);
 
 /* ---- sub-cycled driver (Sec. III skeleton, BOR sub-cycling) ---- */
 typedef struct {

@@ -1,5 +1,8 @@
-"""Gradient of a sphere-integral objective of the periodic scalar wave with
-respect to its Gaussian initial-data parameters, as a torch.autograd.Function.
+"""Gradients of sphere-integral objectives with respect to Gaussian
+initial-data parameters, as torch.autograd.Functions: the periodic scalar
+wave, and CCZ4 with a lapse pulse.
+
+Wave.
 
 Forward: phi_0 = A exp(-|x - c|^2 / w^2), Pi_0 = 0 (mol_wave_gaussian); nsteps
 RK4 steps (mol_advance, one periodic level); J = sum_{|x| < R} phi dV
@@ -8,7 +11,15 @@ Backward: lam_T = dJ/dU_T (mol_sphere_adjoint), then the reverse RK4 sweep
 (mol_rk4_adjoint_step) segment by segment from the last checkpoint to the
 first, and dJ/dp = <lam_0, dU_0/dp> (mol_wave_gaussian_vjp).  The wave operator
 is linear, so its transpose does not depend on the forward states: the
-segments are not recomputed.  All arithmetic runs in libmolamr.
+segments are not recomputed.
+
+CCZ4.  Forward: flat data with alpha = 1 + A exp(-|x - c|^2 / w^2)
+(mol_ccz4_lapse_pulse); nsteps RK4 steps; J = sum_{|x| < R} (alpha - 1) dV.
+Backward: the operator is nonlinear, so each segment is recomputed forward
+from its checkpoint (its states kept), then the reverse RK4 steps
+(mol_rk4_adjoint_step with the state at the start of each step) run from the
+last state of the segment back to its checkpoint; dJ/dp through
+mol_ccz4_lapse_pulse_vjp.  All arithmetic runs in libmolamr.
 """
 from __future__ import annotations
 
@@ -39,14 +50,14 @@ class WaveSphereObjective(torch.autograd.Function):
     def backward(ctx, gJ):
         ps = ctx.ps
         lam = ps.alloc(0)
-        w0, w1, w2 = ps.alloc(0), ps.alloc(0), ps.alloc(0)
+        w = [ps.alloc(0) for _ in range(3)]
         ps.sphere_adjoint(0, 0, ctx.radius, float(gJ), lam)
         # segments [k*every, (k+1)*every) in reverse order
         nseg = (ctx.nsteps + ctx.every - 1) // ctx.every
         for k in reversed(range(nseg)):
             steps = min(ctx.every, ctx.nsteps - k * ctx.every)
             for _ in range(steps):
-                ps.rk4_adjoint_step(0, ctx.dt, lam, w0, w1, w2)
+                ps.rk4_adjoint_step(0, ctx.dt, lam, w)
         g = torch.zeros(5, dtype=torch.float64, device=lam.device)
         ps.wave_gaussian_vjp(0, ctx.p, lam, g)
         return g.cpu(), None, None, None, None, None
@@ -54,3 +65,53 @@ class WaveSphereObjective(torch.autograd.Function):
 
 def sphere_objective(prm, ps, nsteps, dt, radius, every=20):
     return WaveSphereObjective.apply(prm, ps, nsteps, dt, radius, every)
+
+
+ALPHA = 18  # lapse: field index of the CCZ4 state
+
+
+class Ccz4LapseObjective(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, prm: torch.Tensor, ps: M.Patchset, nsteps: int, dt: float, radius: float, every: int = 20):
+        p = [float(v) for v in prm.detach().cpu()]
+        st = ps.alloc_states()
+        ps.ccz4_lapse_pulse(0, p, st[0]["U"])
+        ps.fill_ghosts(0, st[0]["U"])
+        ckpts = [st[0]["U"].clone()]
+        for s_ in range(nsteps):
+            ps.advance(st, dt)
+            if (s_ + 1) % every == 0 and s_ + 1 < nsteps:
+                ckpts.append(st[0]["U"].clone())
+        out = torch.zeros(5, dtype=torch.float64, device=st[0]["U"].device)
+        ps.norms(0, st[0]["U"], ALPHA, 1.0, radius, out)
+        ctx.ps, ctx.p, ctx.nsteps, ctx.dt, ctx.radius, ctx.every = ps, p, nsteps, dt, radius, every
+        ctx.ckpts = ckpts
+        return out[3].detach().cpu().reshape(())
+
+    @staticmethod
+    def backward(ctx, gJ):
+        ps = ctx.ps
+        lam = ps.alloc(0)
+        w = [ps.alloc(0) for _ in range(6)]
+        work = ps.alloc_work(0)
+        ps.sphere_adjoint(0, ALPHA, ctx.radius, float(gJ), lam)
+        st = ps.alloc_states()
+        nseg = (ctx.nsteps + ctx.every - 1) // ctx.every
+        for k in reversed(range(nseg)):
+            steps = min(ctx.every, ctx.nsteps - k * ctx.every)
+            # states at the start of each step of the segment
+            st[0]["U"].copy_(ctx.ckpts[k])
+            states = []
+            for _ in range(steps):
+                states.append(st[0]["U"].clone())
+                ps.advance(st, ctx.dt)
+            for Un in reversed(states):
+                ps.rk4_adjoint_step(0, ctx.dt, lam, w, Un=Un, work=work)
+        g = torch.zeros(5, dtype=torch.float64, device=lam.device)
+        ps.ccz4_lapse_pulse_vjp(0, ctx.p, lam, g)
+        return g.cpu(), None, None, None, None, None
+
+
+def ccz4_lapse_objective(prm, ps, nsteps, dt, radius, every=20):
+    return Ccz4LapseObjective.apply(prm, ps, nsteps, dt, radius, every)
+

@@ -121,6 +121,9 @@ struct mol_patchset {
         TileList tiles;   // interior tiles for the stage kernels
         TileList gtiles;  // ghosted-box tiles for the adjoint
         TileList ntiles;  // interior tiles for reductions / initial data
+        // CCZ4 adjoint workspace: start of each patch's block (slots x fs)
+        DevArr<int64_t> wofs;
+        int64_t wsize = 0;
     };
     Level L[MOL_MAX_LEVELS];
     double* scratch = nullptr;  // reduction partials
@@ -140,6 +143,7 @@ struct mol_patchset {
             l.rst.release();
             l.tiles.dev.release();
             l.gtiles.dev.release();
+            l.wofs.release();
             l.ntiles.dev.release();
         }
         if (scratch) (void)hipFree(scratch);
@@ -552,6 +556,16 @@ int build(mol_patchset* ps, const mol_hierarchy_desc* h)
         build_tiles(lev, td, 0, lev.tiles);
         int tg[3] = {16, 4, 4};
         build_tiles(lev, tg, G, lev.gtiles);
+        if (ps->sp.system == MOL_CCZ4) {
+            std::vector<int64_t> wo(lev.pd.size());
+            int64_t w = 0;
+            for (size_t p = 0; p < lev.pd.size(); ++p) {
+                wo[p] = w;
+                w += (int64_t)ccz4_adjoint_slots() * lev.pd[p].fs;
+            }
+            lev.wsize = w;
+            if ((rc = lev.wofs.upload(wo))) return rc;
+        }
         int tn[3] = {32, 4, 2};
         build_tiles(lev, tn, 0, lev.ntiles);
     }
@@ -901,20 +915,37 @@ int mol_restrict(mol_patchset* ps, int fine_level, const double* U_f, double* U_
 }
 
 int mol_rhs_adjoint(mol_patchset* ps, int level, const double* U, const double* lam, double* lamU,
-                    void* stream)
+                    double* work, void* stream)
 {
     int rc = check_level(ps, level);
     if (rc) return rc;
-    if (ps->sp.system != MOL_WAVE)
-        return fail(MOL_EUNSUPPORTED, "the right-hand-side adjoint exists for the wave system only");
+    if (ps->sp.system != MOL_WAVE && ps->sp.system != MOL_CCZ4)
+        return fail(MOL_EUNSUPPORTED, "the right-hand-side adjoint exists for the wave and CCZ4 systems");
     if (!lam || !lamU) return fail(MOL_EINVAL, "null buffer");
     if (lam == lamU) return fail(MOL_EINVAL, "lam and lamU must not alias");
-    (void)U;  // the wave operator is linear: its transpose does not depend on U
     Level& lev = ps->L[level];
     SysParams sp = level_params(ps, level);
-    hipError_t e = launch_wave_adjoint(sp, lev.d_pd.p, lev.gtiles.dev.p, (int)lev.gtiles.dev.n,
-                                       lev.gtiles.tdim, lam, lamU, S(stream));
+    hipError_t e;
+    if (ps->sp.system == MOL_WAVE) {
+        // the wave operator is linear: its transpose does not depend on U
+        e = launch_wave_adjoint(sp, lev.d_pd.p, lev.gtiles.dev.p, (int)lev.gtiles.dev.n, lev.gtiles.tdim, lam, lamU,
+                                S(stream));
+    } else {
+        if (!U || !work) return fail(MOL_EINVAL, "the CCZ4 adjoint needs U and the workspace");
+        if (U == lamU || work == lamU || work == U || work == lam)
+            return fail(MOL_EINVAL, "U, lamU and work must not alias");
+        e = launch_ccz4_adjoint(sp, lev.d_pd.p, lev.tiles.dev.p, (int)lev.tiles.dev.n, lev.tiles.tdim,
+                                lev.gtiles.dev.p, (int)lev.gtiles.dev.n, lev.gtiles.tdim, U, lam, work, lev.wofs.p,
+                                lamU, S(stream));
+    }
     return e == hipSuccess ? MOL_OK : hip_fail(e, "adjoint launch");
+}
+
+int64_t mol_adjoint_workspace(const mol_patchset* ps, int level)
+{
+    if (!ps) return fail(MOL_EINVAL, "null patchset");
+    if (level < 0 || level >= ps->nlev) return fail(MOL_EINVAL, "level %d out of range", level);
+    return ps->L[level].wsize;
 }
 
 int mol_fill_ghosts_adjoint(mol_patchset* ps, int level, double* lamU, void* stream)
@@ -928,39 +959,53 @@ int mol_fill_ghosts_adjoint(mol_patchset* ps, int level, double* lamU, void* str
     return e == hipSuccess ? MOL_OK : hip_fail(e, "fill adjoint launch");
 }
 
-int mol_rk4_adjoint_step(mol_patchset* ps, int level, double dt, double* lam, double* w0,
-                         double* w1, double* w2, void* stream)
+int mol_rk4_adjoint_step(mol_patchset* ps, int level, double dt, const double* Un, double* lam,
+                         double* const w[6], double* work, void* stream)
 {
     int rc = check_level(ps, level);
     if (rc) return rc;
-    if (ps->sp.system != MOL_WAVE)
-        return fail(MOL_EUNSUPPORTED, "the RK4 adjoint exists for the wave system only");
-    if (!lam || !w0 || !w1 || !w2) return fail(MOL_EINVAL, "null buffer");
+    const bool nl = ps->sp.system == MOL_CCZ4;
+    if (ps->sp.system != MOL_WAVE && !nl)
+        return fail(MOL_EUNSUPPORTED, "the RK4 adjoint exists for the wave and CCZ4 systems");
+    if (!lam || !w || !w[0] || !w[1] || !w[2]) return fail(MOL_EINVAL, "null buffer");
+    if (nl && (!Un || !w[3] || !w[4] || !w[5] || !work))
+        return fail(MOL_EINVAL, "the CCZ4 RK4 adjoint needs U^n, six work buffers and the workspace");
     if (ps->nlev != 1) return fail(MOL_EUNSUPPORTED, "the RK4 adjoint handles one periodic level");
     if (!std::isfinite(dt) || dt <= 0.0) return fail(MOL_EINVAL, "dt must be positive and finite");
     const int64_t n = ps->L[level].nelems;
     hipStream_t s = S(stream);
-    // Reverse of U' = U + sum_s c_s k_s, k_s = dt L(U + b_s k_{s-1}):
-    //   lk_s = c_s lam + b_{s+1} m_{s+1};  m_s = fill^T(dt L^T lk_s);
+    // Reverse of U' = U + sum_s c_s k_s, k_s = dt L(U_s), U_s = U + b_s k_{s-1}:
+    //   lk_s = c_s lam + b_{s+1} m_{s+1};  m_s = fill^T(dt L'(U_s)^T lk_s);
     //   lam  <- lam + m_1 + m_2 + m_3 + m_4.
-    // w0 = lk, w1 = m (current), w2 = running sum of the m's.
+    // w0 = lk, w1 = m (current), w2 = running sum of the m's; for a
+    // nonlinear system w3..w5 hold the stage states U_2..U_4, recomputed from
+    // U^n with the forward stage kernel (w2 serves as its accumulator).
     static const double cw[4] = {1.0 / 6.0, 2.0 / 6.0, 2.0 / 6.0, 1.0 / 6.0};
     static const double bsub[4] = {0.0, 0.5, 0.5, 1.0};
+    const double* Ust[4] = {Un, nullptr, nullptr, nullptr};
+    if (nl) {
+        const double* in[3] = {Un, w[3], w[4]};
+        for (int st = 0; st < 3; ++st) {
+            if ((rc = stage_impl(ps, level, ST_RK4, st + 1, dt, Un, in[st], w[2], w[3 + st], nullptr, s, 0))) return rc;
+            if ((rc = fill_impl(ps, level, w[3 + st], ps->sp.nf, s, 0))) return rc;
+            Ust[st + 1] = w[3 + st];
+        }
+    }
     hipError_t e = hipSuccess;
     for (int st = 3; st >= 0; --st) {
         if (st == 3)
-            e = launch_axpby(n, cw[3], lam, 0.0, lam, w0, s);
+            e = launch_axpby(n, cw[3], lam, 0.0, lam, w[0], s);
         else
-            e = launch_axpby(n, cw[st], lam, bsub[st + 1], w1, w0, s);
+            e = launch_axpby(n, cw[st], lam, bsub[st + 1], w[1], w[0], s);
         if (e != hipSuccess) return hip_fail(e, "axpby");
-        if ((rc = mol_rhs_adjoint(ps, level, nullptr, w0, w1, stream))) return rc;
-        if ((rc = mol_fill_ghosts_adjoint(ps, level, w1, stream))) return rc;
-        e = launch_axpby(n, dt, w1, 0.0, w1, w1, s);
+        if ((rc = mol_rhs_adjoint(ps, level, Ust[st], w[0], w[1], work, stream))) return rc;
+        if ((rc = mol_fill_ghosts_adjoint(ps, level, w[1], stream))) return rc;
+        e = launch_axpby(n, dt, w[1], 0.0, w[1], w[1], s);
         if (e != hipSuccess) return hip_fail(e, "axpby");
-        e = st == 3 ? launch_axpby(n, 1.0, w1, 0.0, w1, w2, s) : launch_axpby(n, 1.0, w2, 1.0, w1, w2, s);
+        e = st == 3 ? launch_axpby(n, 1.0, w[1], 0.0, w[1], w[2], s) : launch_axpby(n, 1.0, w[2], 1.0, w[1], w[2], s);
         if (e != hipSuccess) return hip_fail(e, "axpby");
     }
-    e = launch_axpby(n, 1.0, lam, 1.0, w2, lam, s);
+    e = launch_axpby(n, 1.0, lam, 1.0, w[2], lam, s);
     return e == hipSuccess ? MOL_OK : hip_fail(e, "axpby");
 }
 
@@ -991,36 +1036,55 @@ int mol_sphere_adjoint(mol_patchset* ps, int level, int field, double radius, do
     return e == hipSuccess ? MOL_OK : hip_fail(e, "sphere adjoint launch");
 }
 
-int mol_wave_gaussian(mol_patchset* ps, int level, const double prm[5], double* U, void* stream)
+namespace {
+// Gaussian initial data of the system: the wave's phi (Pi = 0), or the CCZ4
+// lapse pulse on flat data (chi = 1, gt = identity, alpha = 1 + pulse, the
+// rest 0); U written when lam is null, else the VJP into grad_dev
+int gaussian_impl(mol_patchset* ps, int level, int system, const double prm[5], double* U, const double* lam,
+                  double* grad_dev, void* stream)
 {
     int rc = check_level(ps, level);
     if (rc) return rc;
-    if (ps->sp.system != MOL_WAVE) return fail(MOL_EUNSUPPORTED, "wave system only");
-    if (!prm || !U) return fail(MOL_EINVAL, "null argument");
+    if (ps->sp.system != system)
+        return fail(MOL_EUNSUPPORTED, system == MOL_WAVE ? "wave system only" : "CCZ4 system only");
+    if (!prm || (!U && !lam) || (lam && !grad_dev)) return fail(MOL_EINVAL, "null argument");
     if (!(prm[1] > 0.0)) return fail(MOL_EINVAL, "width must be positive");
     Level& lev = ps->L[level];
     double per[3];
     for (int d = 0; d < 3; ++d) per[d] = lev.period[d] * lev.h;
-    hipError_t e = launch_gaussian(lev.d_pd.p, lev.ntiles.dev.p, (int)lev.ntiles.dev.n, lev.ntiles.tdim, prm,
-                                   lev.h, ps->xlo, per, U, nullptr, nullptr, 0, nullptr, S(stream));
+    const int fg = system == MOL_WAVE ? 0 : 18;  // phi, or alpha
+    const unsigned ones = system == MOL_WAVE ? 0u : (1u << 0 | 1u << 1 | 1u << 4 | 1u << 6 | 1u << 18);
+    hipError_t e = launch_gaussian(lev.d_pd.p, lev.ntiles.dev.p, (int)lev.ntiles.dev.n, lev.ntiles.tdim, prm, lev.h,
+                                   ps->xlo, per, ps->sp.nf, fg, ones, U, lam, lam ? ps->scratch : nullptr,
+                                   lam ? ps->red_blocks : 0, grad_dev, S(stream));
     return e == hipSuccess ? MOL_OK : hip_fail(e, "gaussian launch");
+}
+}  // namespace
+
+int mol_wave_gaussian(mol_patchset* ps, int level, const double prm[5], double* U, void* stream)
+{
+    if (!U) return fail(MOL_EINVAL, "null argument");
+    return gaussian_impl(ps, level, MOL_WAVE, prm, U, nullptr, nullptr, stream);
 }
 
 int mol_wave_gaussian_vjp(mol_patchset* ps, int level, const double prm[5], const double* lam,
                           double* grad_dev, void* stream)
 {
-    int rc = check_level(ps, level);
-    if (rc) return rc;
-    if (ps->sp.system != MOL_WAVE) return fail(MOL_EUNSUPPORTED, "wave system only");
-    if (!prm || !lam || !grad_dev) return fail(MOL_EINVAL, "null argument");
-    if (!(prm[1] > 0.0)) return fail(MOL_EINVAL, "width must be positive");
-    Level& lev = ps->L[level];
-    double per[3];
-    for (int d = 0; d < 3; ++d) per[d] = lev.period[d] * lev.h;
-    hipError_t e = launch_gaussian(lev.d_pd.p, lev.ntiles.dev.p, (int)lev.ntiles.dev.n, lev.ntiles.tdim, prm,
-                                   lev.h, ps->xlo, per, nullptr, lam, ps->scratch, ps->red_blocks,
-                                   grad_dev, S(stream));
-    return e == hipSuccess ? MOL_OK : hip_fail(e, "gaussian vjp launch");
+    if (!lam) return fail(MOL_EINVAL, "null argument");
+    return gaussian_impl(ps, level, MOL_WAVE, prm, nullptr, lam, grad_dev, stream);
+}
+
+int mol_ccz4_lapse_pulse(mol_patchset* ps, int level, const double prm[5], double* U, void* stream)
+{
+    if (!U) return fail(MOL_EINVAL, "null argument");
+    return gaussian_impl(ps, level, MOL_CCZ4, prm, U, nullptr, nullptr, stream);
+}
+
+int mol_ccz4_lapse_pulse_vjp(mol_patchset* ps, int level, const double prm[5], const double* lam,
+                             double* grad_dev, void* stream)
+{
+    if (!lam) return fail(MOL_EINVAL, "null argument");
+    return gaussian_impl(ps, level, MOL_CCZ4, prm, nullptr, lam, grad_dev, stream);
 }
 
 int mol_advance(mol_patchset* ps, const mol_level_state* states, double dt0, int mode, void* stream)

@@ -89,12 +89,15 @@ __global__ __launch_bounds__(RB) void final_kernel(const double* __restrict__ pa
         for (int q = 0; q < NQ; ++q) out[q] = r.v[q];
 }
 
-// phi = A exp(-|d|^2 / w^2), d the minimum-image displacement from c
+// Gaussian initial data: field fg = base + A exp(-|d|^2 / w^2), d the
+// minimum-image displacement from c; the other nf - 1 fields are constants
+// (field f is 1 where bit f of `ones` is set, else 0, as is the base of fg).
+// With lam: the vector-Jacobian product sum_points lam[fg] d(A exp(..))/dprm.
 __global__ __launch_bounds__(RB) void gaussian_kernel(const PatchDev* __restrict__ patches,
                                                       const Tile* __restrict__ tiles, int ntiles, Red prm,
                                                       double h, double x0, double y0, double z0, double Lx,
-                                                      double Ly, double Lz, double* __restrict__ U,
-                                                      const double* __restrict__ lam,
+                                                      double Ly, double Lz, int nf, int fg, unsigned ones,
+                                                      double* __restrict__ U, const double* __restrict__ lam,
                                                       double* __restrict__ partial)
 {
     __shared__ double sh[NQ * RB];
@@ -113,12 +116,13 @@ __global__ __launch_bounds__(RB) void gaussian_kernel(const PatchDev* __restrict
         const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
         const double E = exp(-r2 / (w * w));
         const int64_t c = P.off + (int64_t)(k + G) * P.pitch_z + (int64_t)(j + G) * P.pitch_y + i + G;
-        if (U) {
-            U[c] = A * E;
-            U[c + P.fs] = 0.0;
-        }
+        if (U)
+            for (int f = 0; f < nf; ++f) {
+                const double base = (ones >> f & 1u) ? 1.0 : 0.0;
+                U[c + (int64_t)f * P.fs] = f == fg ? base + A * E : base;
+            }
         if (lam) {
-            const double l = lam[c];
+            const double l = lam[c + (int64_t)fg * P.fs];
             r.v[0] += l * E;
             r.v[1] += l * A * E * 2.0 * r2 / (w * w * w);
             for (int a = 0; a < 3; ++a) r.v[2 + a] += l * A * E * 2.0 * d[a] / (w * w);
@@ -173,15 +177,17 @@ hipError_t launch_norms(const PatchDev* patches, const Tile* tiles, int ntiles, 
 }
 
 hipError_t launch_gaussian(const PatchDev* patches, const Tile* tiles, int ntiles, const int td[3],
-                           const double prm5[5], double h, const double xlo[3], const double per[3], double* U,
-                           const double* lam, double* partial, int nblocks, double* grad, hipStream_t s)
+                           const double prm5[5], double h, const double xlo[3], const double per[3], int nf, int fg,
+                           unsigned ones, double* U, const double* lam, double* partial, int nblocks, double* grad,
+                           hipStream_t s)
 {
     if (td[0] * td[1] * td[2] != RB) return hipErrorInvalidValue;
     Red prm;
     for (int q = 0; q < NQ; ++q) prm.v[q] = prm5[q];
     const int nb = lam ? nblocks : (ntiles < 1 ? 1 : ntiles);
     gaussian_kernel<<<nb, dim3(td[0], td[1], td[2]), 0, s>>>(patches, tiles, ntiles, prm, h, xlo[0], xlo[1],
-                                                             xlo[2], per[0], per[1], per[2], U, lam, partial);
+                                                             xlo[2], per[0], per[1], per[2], nf, fg, ones, U, lam,
+                                                             partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !lam) return e;
     final_kernel<<<1, RB, 0, s>>>(partial, nblocks, -1, grad);

@@ -147,6 +147,11 @@ hipError_t launch_prolong(const ProlongCell* e, int64_t n, int nf, int R, const 
                           double* U, hipStream_t s);
 hipError_t launch_restrict(const RestrictPt* e, int64_t n, int nf, const double* Uf, double* Uc,
                            hipStream_t s);
+int ccz4_adjoint_slots();
+hipError_t launch_ccz4_adjoint(const SysParams& sp, const PatchDev* patches, const Tile* tiles, int ntiles,
+                               const int td[3], const Tile* gtiles, int ngtiles, const int gtd[3],
+                               const double* U, const double* lam, double* W, const int64_t* wofs, double* lamU,
+                               hipStream_t s);
 hipError_t launch_wave_adjoint(const SysParams& sp, const PatchDev* patches, const Tile* tiles,
                                int ntiles, const int tdim[3], const double* lam, double* lamU,
                                hipStream_t s);
@@ -159,9 +164,9 @@ hipError_t launch_norms(const PatchDev* patches, const Tile* tiles, int ntiles, 
 hipError_t launch_sphere_adjoint(const PatchDev* patches, const Tile* tiles, int ntiles, const int tdim[3],
                                 int nf, int field, double radius, double scale, double h, const double xlo[3],
                                 double* lam, hipStream_t s);
-hipError_t launch_gaussian(const PatchDev* patches, const Tile* tiles, int ntiles, const int tdim[3],
-                           const double prm[5], double h, const double xlo[3], const double per[3],
-                           double* U, const double* lam, double* partial, int nblocks, double* grad,
+hipError_t launch_gaussian(const PatchDev* patches, const Tile* tiles, int ntiles, const int td[3],
+                           const double prm5[5], double h, const double xlo[3], const double per[3], int nf, int fg,
+                           unsigned ones, double* U, const double* lam, double* partial, int nblocks, double* grad,
                            hipStream_t s);
 
 }  // namespace mol

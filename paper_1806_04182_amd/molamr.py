@@ -56,6 +56,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with paper_1806_04182_amd.build")
+        # torch brings its own HIP runtime; the library must bind to the same
+        # one, so torch is loaded first (a runtime loaded by the library first
+        # would leave torch without a usable device)
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
         i64p = ctypes.POINTER(ctypes.c_int64)
@@ -74,13 +78,16 @@ def lib():
             "mol_prolong": ([vp, i, i, i, vp, ctypes.POINTER(vp), vp, vp], i),
             "mol_bor_weights": ([i, i, i, dp], i),
             "mol_restrict": ([vp, i, vp, vp, vp], i),
-            "mol_rhs_adjoint": ([vp, i, vp, vp, vp, vp], i),
+            "mol_rhs_adjoint": ([vp, i, vp, vp, vp, vp, vp], i),
+            "mol_adjoint_workspace": ([vp, i], ctypes.c_int64),
             "mol_fill_ghosts_adjoint": ([vp, i, vp, vp], i),
-            "mol_rk4_adjoint_step": ([vp, i, d, vp, vp, vp, vp, vp], i),
+            "mol_rk4_adjoint_step": ([vp, i, d, vp, vp, ctypes.POINTER(vp), vp, vp], i),
             "mol_norms": ([vp, i, vp, i, d, d, vp, vp], i),
             "mol_sphere_adjoint": ([vp, i, i, d, d, vp, vp], i),
             "mol_wave_gaussian": ([vp, i, dp, vp, vp], i),
             "mol_wave_gaussian_vjp": ([vp, i, dp, vp, vp, vp], i),
+            "mol_ccz4_lapse_pulse": ([vp, i, dp, vp, vp], i),
+            "mol_ccz4_lapse_pulse_vjp": ([vp, i, dp, vp, vp, vp], i),
             "mol_advance": ([vp, ctypes.POINTER(_LevelState), d, i, vp], i),
             "mol_graph_create": ([vp, ctypes.POINTER(_LevelState), d, ctypes.POINTER(vp)], i),
             "mol_graph_launch": ([vp, vp], i),
@@ -232,15 +239,29 @@ class Patchset:
     def restrict(self, fine_level, U_f, U_c, stream=None):
         _check(lib().mol_restrict(self._h, fine_level, _ptr(U_f), _ptr(U_c), _stream(stream)))
 
-    def rhs_adjoint(self, level, U, lam, lamU, stream=None):
-        _check(lib().mol_rhs_adjoint(self._h, level, _ptr(U), _ptr(lam), _ptr(lamU), _stream(stream)))
+    def rhs_adjoint(self, level, U, lam, lamU, work=None, stream=None):
+        _check(lib().mol_rhs_adjoint(self._h, level, _ptr(U), _ptr(lam), _ptr(lamU), _ptr(work), _stream(stream)))
+
+    def adjoint_workspace(self, level) -> int:
+        n = lib().mol_adjoint_workspace(self._h, level)
+        if n < 0:
+            _check(int(n))
+        return int(n)
+
+    def alloc_work(self, level, device="cuda"):
+        """Workspace for rhs_adjoint / rk4_adjoint_step (None when none is needed)."""
+        import torch
+        n = self.adjoint_workspace(level)
+        return torch.empty(n, dtype=torch.float64, device=device) if n > 0 else None
 
     def fill_ghosts_adjoint(self, level, lamU, stream=None):
         _check(lib().mol_fill_ghosts_adjoint(self._h, level, _ptr(lamU), _stream(stream)))
 
-    def rk4_adjoint_step(self, level, dt, lam, w0, w1, w2, stream=None):
-        _check(lib().mol_rk4_adjoint_step(self._h, level, dt, _ptr(lam), _ptr(w0), _ptr(w1), _ptr(w2),
-                                          _stream(stream)))
+    def rk4_adjoint_step(self, level, dt, lam, w, Un=None, work=None, stream=None):
+        """w: 3 (wave) or 6 (CCZ4) level-size work buffers."""
+        ws = list(w) + [None] * (6 - len(w))
+        arr = (ctypes.c_void_p * 6)(*[_ptr(x) for x in ws])
+        _check(lib().mol_rk4_adjoint_step(self._h, level, dt, _ptr(Un), _ptr(lam), arr, _ptr(work), _stream(stream)))
 
     def norms(self, level, U, field, shift, radius, out_dev, stream=None):
         _check(lib().mol_norms(self._h, level, _ptr(U), field, shift, radius, _ptr(out_dev), _stream(stream)))
@@ -255,6 +276,14 @@ class Patchset:
     def wave_gaussian_vjp(self, level, prm, lam, grad_dev, stream=None):
         p = (ctypes.c_double * 5)(*prm)
         _check(lib().mol_wave_gaussian_vjp(self._h, level, p, _ptr(lam), _ptr(grad_dev), _stream(stream)))
+
+    def ccz4_lapse_pulse(self, level, prm, U, stream=None):
+        p = (ctypes.c_double * 5)(*prm)
+        _check(lib().mol_ccz4_lapse_pulse(self._h, level, p, _ptr(U), _stream(stream)))
+
+    def ccz4_lapse_pulse_vjp(self, level, prm, lam, grad_dev, stream=None):
+        p = (ctypes.c_double * 5)(*prm)
+        _check(lib().mol_ccz4_lapse_pulse_vjp(self._h, level, p, _ptr(lam), _ptr(grad_dev), _stream(stream)))
 
     def _states(self, states):
         arr = (_LevelState * self.nlev)()

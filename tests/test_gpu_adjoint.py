@@ -54,7 +54,7 @@ def test_rk4_adjoint_sweep_matches_oracle():
     ps.sphere_adjoint(0, 0, 0.6, 1.0, lam)
     nsteps, dt = 9, 0.25 * dx
     for _ in range(nsteps):
-        ps.rk4_adjoint_step(0, dt, lam, *w)
+        ps.rk4_adjoint_step(0, dt, lam, w)
     torch.cuda.synchronize()
     got = ps.unpack(0, lam)[0]
     ref = O.wave_adjoint_run(n, (dx, dx, dx), xlo, dt, nsteps, 0.6, O.params(sigma=0.1))

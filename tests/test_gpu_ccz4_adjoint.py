@@ -1,0 +1,136 @@
+"""GPU adjoint of the CCZ4 right-hand side and of the RK4 step, against the
+oracle's exact derivative (its right-hand side compiled with dual numbers):
+element by element on a small periodic patch, and through dot-product
+identities on ragged multi-tile patches; plus the gradient of the lapse-pulse
+objective against central differences."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1806_04182_amd import molamr as M
+from paper_1806_04182_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU test needs a GPU"
+    return torch
+
+
+def _state(n, dx, seed):
+    """Strongly non-flat CCZ4 state (lapse pulse + 1e-2 noise on every field),
+    ghosts filled periodically."""
+    st = synth.ccz4_lapse_pulse(n, (-1, -1, -1), dx, amp=0.2, width=0.4)
+    st = st + synth.ccz4_minkowski_noise(n, amp=1e-2, seed=seed) - synth.CCZ4_FLAT[:, None, None, None]
+    U = synth.embed(st)
+    O.fill_periodic(U)
+    return U
+
+
+def _gpu_vjp(ps, U, lam_int):
+    """(dR/dU)^T lam with the ghost contributions folded into their owners."""
+    torch = _torch()
+    Ud = torch.from_numpy(ps.pack(0, [U])).cuda()
+    Ld = torch.from_numpy(ps.pack(0, [synth.embed(lam_int)])).cuda()
+    out = ps.alloc(0)
+    work = ps.alloc_work(0)
+    ps.rhs_adjoint(0, Ud, Ld, out, work)
+    ps.fill_ghosts_adjoint(0, out)
+    torch.cuda.synchronize()
+    return synth.interior(ps.unpack(0, out)[0])
+
+
+@pytest.mark.parametrize("upwind", [1, 0])
+def test_rhs_adjoint_matches_oracle_elementwise(upwind):
+    n, dx = (5, 4, 4), 0.15
+    U = _state(n, dx, 7)
+    lam = np.random.default_rng(1).standard_normal((25,) + tuple(reversed(n)))
+    ps = M.Patchset(M.single_patch(n, (-1, -1, -1), dx), M.System(M.MOL_CCZ4, upwind=upwind))
+    got = _gpu_vjp(ps, U, lam)
+    ref = O.ccz4_rhs_vjp_periodic(U, lam, dx, O.params(upwind=float(upwind)))
+    sc = np.maximum(np.max(np.abs(ref), axis=(1, 2, 3)), 1.0)
+    err = np.max(np.abs(got - ref), axis=(1, 2, 3)) / sc
+    assert np.all(err < 1e-12), err
+
+
+@pytest.mark.parametrize("n", [(19, 13, 9), (8, 8, 8)])
+def test_rhs_adjoint_dot_product_with_oracle_jvp(n):
+    """<(dR/dU)^T lam, v> = <lam, (dR/dU) P v> for random v; P the periodic fill."""
+    dx = 2.0 / max(n)
+    U = _state(n, dx, 3)
+    rng = np.random.default_rng(2)
+    shape = (25,) + tuple(reversed(n))
+    lam, v = rng.standard_normal(shape), rng.standard_normal(shape)
+    ps = M.Patchset(M.single_patch(n, (-1, -1, -1), dx), M.System(M.MOL_CCZ4))
+    got = _gpu_vjp(ps, U, lam)
+    V = synth.embed(v)
+    O.fill_periodic(V)
+    _, JV = O.ccz4_rhs_jvp(U, V, dx)
+    a, b = np.sum(got * v), np.sum(lam * synth.interior(JV))
+    assert abs(a - b) <= 1e-12 * np.sum(np.abs(got * v)), (a, b)
+
+
+def test_rk4_adjoint_step_dot_product_with_oracle_jvp():
+    """One reverse RK4 step against the tangent of one forward step built from
+    the oracle's right-hand side and its exact JVP, stage by stage."""
+    torch = _torch()
+    n = (10, 8, 6)
+    dx = 2.0 / 10
+    dt = 0.25 * dx
+    U = _state(n, dx, 5)
+    rng = np.random.default_rng(4)
+    shape = (25,) + tuple(reversed(n))
+    lam, v = rng.standard_normal(shape), rng.standard_normal(shape)
+    # oracle: stage states and the tangent of U' = U + (k1 + 2 k2 + 2 k3 + k4)/6
+    I = (slice(None), slice(3, -3), slice(3, -3), slice(3, -3))
+    V = synth.embed(v)
+    O.fill_periodic(V)
+    Us, Vs, tan = U.copy(), V.copy(), v.copy()
+    for b, c in ((0.5, 1 / 6), (0.5, 1 / 3), (1.0, 1 / 3), (None, 1 / 6)):
+        R, RV = O.ccz4_rhs_jvp(Us, Vs, dx)
+        tan = tan + c * dt * RV[I]
+        if b is None:
+            break
+        Us = U.copy()
+        Us[I] = U[I] + b * dt * R[I]
+        O.fill_periodic(Us)
+        Vs = V.copy()
+        Vs[I] = V[I] + b * dt * RV[I]
+        O.fill_periodic(Vs)
+    ref = np.sum(lam * tan)
+    # GPU reverse step
+    ps = M.Patchset(M.single_patch(n, (-1, -1, -1), dx), M.System(M.MOL_CCZ4))
+    Un = torch.from_numpy(ps.pack(0, [U])).cuda()
+    L = torch.from_numpy(ps.pack(0, [synth.embed(lam)])).cuda()
+    w = [ps.alloc(0) for _ in range(6)]
+    ps.rk4_adjoint_step(0, dt, L, w, Un=Un, work=ps.alloc_work(0))
+    torch.cuda.synchronize()
+    got = np.sum(synth.interior(ps.unpack(0, L)[0]) * v)
+    assert abs(got - ref) <= 1e-12 * abs(ref), (got, ref)
+
+
+def test_lapse_objective_gradient_matches_central_differences():
+    torch = _torch()
+    from paper_1806_04182_amd.adjoint import ccz4_lapse_objective
+    n = (16, 16, 16)
+    dx = 2.0 / 16
+    ps = M.Patchset(M.single_patch(n, (-1, -1, -1), dx), M.System(M.MOL_CCZ4))
+    p0 = np.array([0.1, 0.4, 0.05, -0.1, 0.02])
+    nsteps, dt, R = 8, 0.25 * dx, 0.6
+    prm = torch.tensor(p0, dtype=torch.float64, requires_grad=True)
+    J = ccz4_lapse_objective(prm, ps, nsteps, dt, R, 3)
+    J.backward()
+    g = prm.grad.numpy()
+    h = 1e-6
+    fd = np.zeros(5)
+    for i in range(5):
+        pp, pm = p0.copy(), p0.copy()
+        pp[i] += h
+        pm[i] -= h
+        Jp = float(ccz4_lapse_objective(torch.tensor(pp), ps, nsteps, dt, R, 3))
+        Jm = float(ccz4_lapse_objective(torch.tensor(pm), ps, nsteps, dt, R, 3))
+        fd[i] = (Jp - Jm) / (2 * h)
+    err = np.abs(g - fd) / np.maximum(np.abs(fd), 1e-3 * np.max(np.abs(fd)))
+    assert np.all(err < 1e-6), (g, fd, err)

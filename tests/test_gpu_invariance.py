@@ -95,7 +95,9 @@ def test_argument_errors_are_reported_before_launch():
         ps.fill_ghosts(3, U)
     with pytest.raises(M.MolError, match="level 0 has no parent"):
         ps.restrict(0, U, V)
-    with pytest.raises(M.MolError, match="wave system only|EUNSUPPORTED|only"):
+    with pytest.raises(M.MolError, match="wave and CCZ4 systems"):
+        M.Patchset(M.single_patch(n, (0, 0, 0), 0.1), M.System(M.MOL_MHD)).rhs_adjoint(0, U, U, V)
+    with pytest.raises(M.MolError, match="workspace"):
         M.Patchset(M.single_patch(n, (0, 0, 0), 0.1), M.System(M.MOL_CCZ4)).rhs_adjoint(0, U, U, V)
     torch.cuda.synchronize()
 
