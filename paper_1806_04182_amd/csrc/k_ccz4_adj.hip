@@ -149,9 +149,17 @@ __global__ __launch_bounds__(256) void ccz4_adj_point_kernel(const PatchDev* __r
         Ghd += Gh[k] * dchi[k];
         for (int m = 0; m < 3; ++m) trc += gu[k][m] * (ddc[k][m] - 1.5 * ic * dchi[k] * dchi[m]);
     }
+    // gt^{mn} d_m d_n gt_q, once per packed component q
+    double lapg[6];
+    for (int q = 0; q < 6; ++q) {
+        double t = 0.0;
+        for (int m = 0; m < 3; ++m)
+            for (int n = m; n < 3; ++n) t += (m == n ? 1.0 : 2.0) * gu[m][n] * dd(GT + q, m, n);
+        lapg[q] = t;
+    }
     double Ric[3][3], Gd[3][3], zs[3][3];
     for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
+        for (int j = i; j < 3; ++j) {
             double gd = 0.0, z = 0.0;
             for (int k = 0; k < 3; ++k) {
                 gd += Gu[k][i][j] * dchi[k];
@@ -161,8 +169,7 @@ __global__ __launch_bounds__(256) void ccz4_adj_point_kernel(const PatchDev* __r
             zs[i][j] = z;
             double r = 0.5 * ic * ddc[i][j] - 0.5 * ic * gd - 0.25 * ic * ic * dchi[i] * dchi[j] + 2.0 * ic * ic * z +
                        0.5 * ic * g[i][j] * (trc - Ghd);
-            for (int m = 0; m < 3; ++m)
-                for (int n = 0; n < 3; ++n) r += -0.5 * gu[m][n] * dd(GT + SI(i, j), m, n);
+            r += -0.5 * lapg[SI(i, j)];
             for (int k = 0; k < 3; ++k) {
                 r += 0.5 * (g[k][i] * dGh[j][k] + g[k][j] * dGh[i][k]);
                 r += Gh[k] * 0.5 * (Gl[i][j][k] + Gl[j][i][k]);
@@ -171,7 +178,9 @@ __global__ __launch_bounds__(256) void ccz4_adj_point_kernel(const PatchDev* __r
                 for (int n = 0; n < 3; ++n)
                     for (int k = 0; k < 3; ++k)
                         r += gu[m][n] * (Gu[k][m][i] * Gl[j][k][n] + Gu[k][m][j] * Gl[i][k][n] + Gu[k][m][i] * Gl[k][n][j]);
-            Ric[i][j] = r;
+            Ric[i][j] = Ric[j][i] = r;
+            Gd[j][i] = gd;
+            zs[j][i] = z;
         }
     double cr = 0.0;
     for (int k = 0; k < 3; ++k)
@@ -231,7 +240,7 @@ __global__ __launch_bounds__(256) void ccz4_adj_point_kernel(const PatchDev* __r
     double a_g[3][3] = {}, a_A[3][3] = {}, a_gu[3][3] = {}, a_Gl[3][3][3] = {}, a_Gu[3][3][3] = {};
     double a_Ric[3][3] = {}, a_DDa[3][3] = {}, a_Am[3][3] = {}, a_Au[3][3] = {}, a_X[3][3] = {};
     double a_dg[3][3][3] = {}, a_dGh[3][3] = {}, a_db[3][3] = {}, a_ddc[3][3] = {}, a_dda[3][3] = {}, a_ddb[3][3][3] = {};
-    double a_ddg[6][3][3] = {};  // [packed field of gt][m][n]
+    double a_lapg[6] = {};
     double a_chi = 0.0, a_Kh = 0.0, a_Th = 0.0, a_alp = 0.0, a_ic = 0.0, a_lndet = 0.0, a_trA = 0.0, a_AA = 0.0;
     double a_divb = 0.0, a_Zda = 0.0, a_Kt = 0.0, a_trX = 0.0, a_trRic = 0.0, a_lapa = 0.0;
     double a_Gh[3] = {}, a_Bv[3] = {}, a_Z[3] = {}, a_dchi[3] = {}, a_dalp[3] = {}, a_dKh[3] = {}, a_dTh[3] = {};
@@ -424,12 +433,12 @@ __global__ __launch_bounds__(256) void ccz4_adj_point_kernel(const PatchDev* __r
             }
         a_ic += 0.5 * a_hic;
     }
-    // Ric = Rh + Rchi
+    // Ric = Rh + Rchi (computed once per pair i <= j)
     {
         double a_trc = 0.0, a_Ghd = 0.0;
         for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) {
-                const double a = a_Ric[i][j];
+            for (int j = i; j < 3; ++j) {
+                const double a = i == j ? a_Ric[i][i] : a_Ric[i][j] + a_Ric[j][i];
                 // Rchi
                 a_ic += (0.5 * ddc[i][j] - 0.5 * Gd[i][j] - 0.5 * ic * dchi[i] * dchi[j] + 4.0 * ic * zs[i][j] +
                          0.5 * g[i][j] * (trc - Ghd)) * a;
@@ -450,11 +459,7 @@ __global__ __launch_bounds__(256) void ccz4_adj_point_kernel(const PatchDev* __r
                     a_dchi[i] += 0.5 * Z[k] * g[k][j] * azs;
                 }
                 // Rh
-                for (int m = 0; m < 3; ++m)
-                    for (int n = 0; n < 3; ++n) {
-                        a_gu[m][n] += -0.5 * dd(GT + SI(i, j), m, n) * a;
-                        a_ddg[SI(i, j)][m][n] += -0.5 * gu[m][n] * a;
-                    }
+                a_lapg[SI(i, j)] += -0.5 * a;
                 for (int k = 0; k < 3; ++k) {
                     a_g[k][i] += 0.5 * dGh[j][k] * a;
                     a_dGh[j][k] += 0.5 * g[k][i] * a;
@@ -475,6 +480,16 @@ __global__ __launch_bounds__(256) void ccz4_adj_point_kernel(const PatchDev* __r
                             a_Gl[k][n][j] += gu[m][n] * Gu[k][m][i] * a;
                         }
             }
+        // lapg[q] = gt^{mn} d_m d_n gt_q: the second derivatives go to the
+        // workspace now (packed pairs), gt^{mn} collects the rest
+        for (int q = 0; q < 6; ++q)
+            for (int m = 0; m < 3; ++m)
+                for (int n = m; n < 3; ++n) {
+                    const double v = dd(GT + q, m, n);
+                    a_gu[m][n] += v * a_lapg[q];
+                    if (m != n) a_gu[n][m] += v * a_lapg[q];
+                    w[(int64_t)(W_D2 + 6 * d2_slot(GT + q) + SI(m, n)) * fs] = (m == n ? 1.0 : 2.0) * gu[m][n] * a_lapg[q];
+                }
         for (int k = 0; k < 3; ++k)
             for (int m = 0; m < 3; ++m) {
                 a_gu[k][m] += (ddc[k][m] - 1.5 * ic * dchi[k] * dchi[m]) * a_trc;
@@ -565,7 +580,6 @@ __global__ __launch_bounds__(256) void ccz4_adj_point_kernel(const PatchDev* __r
     for (int k = 0; k < 3; ++k)
         for (int l = k; l < 3; ++l) {
             const int m = SI(k, l);
-            for (int q = 0; q < 6; ++q) put(W_D2 + 6 * d2_slot(GT + q) + m, sym(a_ddg[q], k, l));
             put(W_D2 + 6 * d2_slot(CHI) + m, sym(a_ddc, k, l));
             put(W_D2 + 6 * d2_slot(ALP) + m, sym(a_dda, k, l));
             for (int i = 0; i < 3; ++i) put(W_D2 + 6 * d2_slot(BETA + i) + m, sym(a_ddb[i], k, l));
@@ -604,35 +618,43 @@ __global__ __launch_bounds__(256) void ccz4_adj_gather_kernel(const PatchDev* __
     const double wko[7] = {1.0, -6.0, 15.0, -20.0, 15.0, -6.0, 1.0};
     const double wlp[7] = {0.0, 0.0, -3.0, -10.0, 18.0, -6.0, 1.0};  // beta >= 0: o = -3..3
     const double wlm[7] = {-1.0, 6.0, -18.0, 10.0, 3.0, 0.0, 0.0};   // beta < 0
-    for (int f = 0; f < NF; ++f) {
-        double acc = self ? wp[(int64_t)(W_U + f) * fs] : 0.0;
-        const double* lf = lp + (int64_t)f * fs;
-        const int s1 = d1_slot(f), s2 = d2_slot(f);
-        for (int k = 0; k < 3; ++k) {
-            // u(p) enters the stencil at c = p - o e_k with the coefficient of offset o
-            for (int o = -3; o <= 3; ++o) {
-                if (!inside(k, -o)) continue;
-                const int64_t cof = -(int64_t)o * S[k];
-                // KO and advection of lam
-                acc += C.ko * wko[o + 3] * lf[cof];
-                const double bk = bp[(int64_t)k * fs + cof];
-                const double wa = C.upwind ? (bk >= 0.0 ? wlp[o + 3] : wlm[o + 3]) : (o >= -2 && o <= 2 ? w1[o + 2] : 0.0);
-                acc += C.i12h * wa * bk * lf[cof];
-                if (o < -2 || o > 2) continue;
-                if (s1 >= 0) acc += C.i12h * w1[o + 2] * wp[(int64_t)(W_D1 + 3 * s1 + k) * fs + cof];
-                if (s2 >= 0) acc += C.i12h2 * w2[o + 2] * wp[(int64_t)(W_D2 + 6 * s2 + SI(k, k)) * fs + cof];
+    double acc[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) acc[f] = self ? wp[(int64_t)(W_U + f) * fs] : 0.0;
+    // u(p) enters the stencils of the interior points c = p - o e_k
+    for (int k = 0; k < 3; ++k)
+        for (int o = -3; o <= 3; ++o) {
+            if (!inside(k, -o)) continue;
+            const int64_t cof = -(int64_t)o * S[k];
+            const double bk = bp[(int64_t)k * fs + cof];
+            const double wa = C.upwind ? (bk >= 0.0 ? wlp[o + 3] : wlm[o + 3]) : (o >= -2 && o <= 2 ? w1[o + 2] : 0.0);
+            // KO and advection act on lam of every field
+            const double wl = C.ko * wko[o + 3] + C.i12h * wa * bk;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) acc[f] += wl * lp[(int64_t)f * fs + cof];
+            if (o < -2 || o > 2) continue;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                const int s1 = d1_slot(f), s2 = d2_slot(f);
+                if (s1 >= 0) acc[f] += C.i12h * w1[o + 2] * wp[(int64_t)(W_D1 + 3 * s1 + k) * fs + cof];
+                if (s2 >= 0) acc[f] += C.i12h2 * w2[o + 2] * wp[(int64_t)(W_D2 + 6 * s2 + SI(k, k)) * fs + cof];
             }
-            if (s2 >= 0)
-                for (int l = k + 1; l < 3; ++l)
-                    for (int a = -2; a <= 2; ++a)
-                        for (int b = -2; b <= 2; ++b) {
-                            if (a == 0 || b == 0 || !inside(k, -a, l, -b)) continue;
-                            const int64_t cof = -(int64_t)a * S[k] - (int64_t)b * S[l];
-                            acc += C.i144h2 * w1[a + 2] * w1[b + 2] * wp[(int64_t)(W_D2 + 6 * s2 + SI(k, l)) * fs + cof];
-                        }
         }
-        lamU[P.off + loc + (int64_t)f * fs] = acc;
-    }
+    for (int k = 0; k < 3; ++k)
+        for (int l = k + 1; l < 3; ++l)
+            for (int a = -2; a <= 2; ++a)
+                for (int b = -2; b <= 2; ++b) {
+                    if (a == 0 || b == 0 || !inside(k, -a, l, -b)) continue;
+                    const int64_t cof = -(int64_t)a * S[k] - (int64_t)b * S[l];
+                    const double wm = C.i144h2 * w1[a + 2] * w1[b + 2];
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) {
+                        const int s2 = d2_slot(f);
+                        if (s2 >= 0) acc[f] += wm * wp[(int64_t)(W_D2 + 6 * s2 + SI(k, l)) * fs + cof];
+                    }
+                }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) lamU[P.off + loc + (int64_t)f * fs] = acc[f];
 }
 
 }  // namespace
