@@ -114,6 +114,11 @@ void orc_hier_get(const orc_hier* H, int l, int p, double* dst);
 void orc_hier_fill_same(orc_hier* H, int l);
 /* one sub-cycled RK4 coarse step with BOR prolongation and injection */
 void orc_hier_step(orc_hier* H, double dt0, const orc_params* p);
+/* time refinement of the sub-cycled step (Sec. III.B); BOR by default */
+enum { ORC_TIME_BOR = 0, ORC_TIME_BO = 1, ORC_TIME_BO1 = 2, ORC_TIME_NOSUB = 3 };
+void orc_hier_set_time_mode(orc_hier* H, int mode);
+void orc_time_state(int mode, int R, int r, int s, double dt, const double* Un,
+                    const double* const* k, double* out, long n);
 /* the pieces, for the unit checks: prolong into level l (>0) at fine step r,
  * stage s, from the parent's saved U^n and k's (set with orc_hier_set_parent) */
 void orc_hier_set_parent_data(orc_hier* H, int l, int p, const double* Un,

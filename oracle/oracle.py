@@ -27,6 +27,10 @@ class Params(ctypes.Structure):
         "bm_f0", "bm_f1", "gd_g", "gd_eta", "upwind")]
 
 
+# time refinement of the sub-cycled step (Sec. III.B)
+TIME_BOR, TIME_BO, TIME_BO1, TIME_NOSUB = 0, 1, 2, 3
+
+
 def params(**kw) -> Params:
     d = dict(sigma=0.1, gamma_ad=5.0 / 3.0, weno_eps=-1.0, weno_q=2.0,
              kappa_z=0.1, kappa_c=0.1, bm_f0=0.0, bm_f1=2.0, gd_g=0.75,
@@ -87,6 +91,8 @@ def lib():
         L.orc_hier_get.argtypes = [vp, i, i, dp]
         L.orc_hier_fill_same.argtypes = [vp, i]
         L.orc_hier_step.argtypes = [vp, d, P]
+        L.orc_hier_set_time_mode.argtypes = [vp, i]
+        L.orc_time_state.argtypes = [i, i, i, i, d, dp, ctypes.POINTER(dp), dp, lng]
         L.orc_hier_set_parent_data.argtypes = [vp, i, i, dp, dp, dp, dp, dp]
         L.orc_hier_prolong.argtypes = [vp, i, i, i, d]
         L.orc_hier_restrict.argtypes = [vp, i]
@@ -262,6 +268,9 @@ class Hierarchy:
         prm = prm or params()
         lib().orc_hier_step(self._h, dt0, ctypes.byref(prm))
 
+    def set_time_mode(self, mode: int) -> None:
+        lib().orc_hier_set_time_mode(self._h, mode)
+
     def set_parent_data(self, l: int, p: int, Un, k) -> None:
         arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in [Un] + list(k)]
         lib().orc_hier_set_parent_data(self._h, l, p, *[_p(a) for a in arrs])
@@ -305,5 +314,13 @@ def ccz4_rhs_vjp_periodic(U: np.ndarray, lam: np.ndarray, h, prm: Params | None 
                     fill_periodic(V)
                     _, RV = ccz4_rhs_jvp(U, V, h, prm)
                     out[f, k, j, i] = np.sum(lam * RV[:, 3:-3, 3:-3, 3:-3])
+    return out
+
+
+def time_state(mode: int, R: int, r: int, s: int, dt: float, Un: np.ndarray, k) -> np.ndarray:
+    """Parent state feeding fine step r, stage s for a time-refinement mode."""
+    out = np.zeros_like(Un)
+    arr = (ctypes.POINTER(ctypes.c_double) * 4)(*[_p(np.ascontiguousarray(kk)) for kk in k])
+    lib().orc_time_state(mode, R, r, s, dt, _p(Un), arr, _p(out), Un.size)
     return out
 

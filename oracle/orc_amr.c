@@ -83,6 +83,47 @@ void orc_bor_rk4(int R, int r, int s, double dt, const double* Un,
     }
 }
 
+/* Sec. III.B: the parent's state that feeds the ghost points of fine step r,
+ * stage s, for each time-refinement strategy (the parent stepped from U^n
+ * with increments k_1..k_4 over dt; the fine stage s of step r sits at
+ * theta = (r + c_s)/R, c = (0, 1/2, 1/2, 1)):
+ *  - BOR: App. D (orc_bor_rk4);
+ *  - BO, dense output: U^n + sum_j b_j(theta) k_j (App. C), the parent's
+ *    solution at the stage time;
+ *  - BO1: linear in time between U^n and U^{n+1} = U^n + sum_j c_j k_j,
+ *    c = (1, 2, 2, 1)/6;
+ *  - no sub-cycling (the fine level takes the parent's dt, R = 1 in time):
+ *    the parent's own stage states U^n, U^n + k_1/2, U^n + k_2/2, U^n + k_3. */
+void orc_time_state(int mode, int R, int r, int s, double dt, const double* Un,
+                    const double* const* k, double* out, long n)
+{
+    static const double cs[4] = {0.0, 0.5, 0.5, 1.0};
+    static const double cw[4] = {1.0 / 6.0, 2.0 / 6.0, 2.0 / 6.0, 1.0 / 6.0};
+    if (mode == ORC_TIME_BOR) {
+        orc_bor_rk4(R, r, s, dt, Un, k, out, n);
+        return;
+    }
+    const double th = (r + cs[s - 1]) / (double)R;
+    for (long i = 0; i < n; ++i) {
+        double u = Un[i];
+        switch (mode) {
+        case ORC_TIME_BO:
+            for (int j = 0; j < 4; ++j) u += orc_dense_rk4(j, 0, th) * k[j][i];
+            break;
+        case ORC_TIME_BO1: {
+            double inc = 0.0;
+            for (int j = 0; j < 4; ++j) inc += cw[j] * k[j][i];
+            u += th * inc;
+            break;
+        }
+        default: /* ORC_TIME_NOSUB */
+            if (s > 1) u += (s == 4 ? 1.0 : 0.5) * k[s - 2][i];
+            break;
+        }
+        out[i] = u;
+    }
+}
+
 /* Sec. III.A: l_j(x) = prod_{m != j} (x - x_m)/(x_j - x_m), nodes x_m = -2..3. */
 void orc_lagrange6(double xi, double w[6])
 {
@@ -115,6 +156,7 @@ typedef struct {
 
 struct orc_hier {
     int system, nf, nlev;
+    int tmode;  /* time refinement (ORC_TIME_*) */
     int N0[3];
     double xlo[3], dx0;
     olevel L[MAXLEV];
@@ -304,7 +346,7 @@ static double parent_state(orc_hier* H, int lp, pro_ctx* c, const int gc[3], int
     if (!c->D[q][off]) {
         const double* kk[4] = {P->k[0][q] + off, P->k[1][q] + off, P->k[2][q] + off,
                                P->k[3][q] + off};
-        orc_bor_rk4(c->R, c->r, c->s, c->dtp, P->Un[q] + off, kk, c->T[q] + off, 1);
+        orc_time_state(H->tmode, c->R, c->r, c->s, c->dtp, P->Un[q] + off, kk, c->T[q] + off, 1);
         c->D[q][off] = 1;
     }
     return c->T[q][off];
@@ -349,7 +391,7 @@ static void prolong_set(orc_hier* H, int l, double** A, int r, int s, double dtp
     olevel* P = &H->L[l - 1];
     pro_ctx c;
     c.A = A;
-    c.R = H->L[l].ratio;
+    c.R = H->tmode == ORC_TIME_NOSUB ? 1 : H->L[l].ratio;
     c.r = r;
     c.s = s;
     c.dtp = dtp;
@@ -423,8 +465,8 @@ static void advance(orc_hier* H, int l, double dt, const orc_params* prm)
         }
         fill_same_set(H, l, L->Us);
         if (l > 0) {
-            double dtp = dt * L->ratio;
-            prolong_set(H, l, L->Us, L->step_r, s + 1, dtp);
+            const int Rt = H->tmode == ORC_TIME_NOSUB ? 1 : L->ratio;
+            prolong_set(H, l, L->Us, L->step_r, s + 1, dt * Rt);
         }
         for (int p = 0; p < L->np; ++p) {
             const int* b = L->box + 6 * p;
@@ -443,7 +485,8 @@ static void advance(orc_hier* H, int l, double dt, const orc_params* prm)
         }
     }
     if (l + 1 < H->nlev) {
-        int R = H->L[l + 1].ratio;
+        /* sub-cycling: R fine steps of dt/R; without it, one of dt */
+        int R = H->tmode == ORC_TIME_NOSUB ? 1 : H->L[l + 1].ratio;
         for (int r = 0; r < R; ++r) {
             H->L[l + 1].step_r = r;
             advance(H, l + 1, dt / R, prm);
@@ -452,6 +495,8 @@ static void advance(orc_hier* H, int l, double dt, const orc_params* prm)
     }
     fill_same_set(H, l, L->U);
 }
+
+void orc_hier_set_time_mode(orc_hier* H, int mode) { H->tmode = mode; }
 
 void orc_hier_step(orc_hier* H, double dt0, const orc_params* p)
 {

@@ -76,15 +76,19 @@ def test_bor_fine_stages_are_consistent(R):
     assert 3.5 < np.log2(errs[0] / errs[1]) < 5.0
 
 
-def _fmr_wave_run(N_unit, R, T=2.5, L=6.0, width=0.25):
-    """1D wave (Sec. IV.A set-up, shortened): periodic x in [-2, 4), pulse at
-    x = 0, one refined level over [1, 2] with ratio R, sub-cycled RK4 + BOR."""
+def _fmr_wave_run(N_unit, R, T=2.5, L=6.0, width=0.25, mode=O.TIME_BOR, window=None):
+    """1D wave (Sec. IV.A set-up, shortened): periodic x in [-2, -2 + L), pulse
+    at x = 0, one refined level over [1, 2] with ratio R, RK4 with the given
+    time refinement (BOR by default).  Returns the L1 error at T, or with
+    window = (t0, t1) the largest reflection integral Q = int_{-2}^{-1} |phi|
+    dx over steps in that time window."""
     N0 = int(L * N_unit)
     dx0 = 1.0 / N_unit
     lo_c, hi_c = int(3 * N_unit), int(4 * N_unit)
     levels = [(1, [((0, 0, 0), (N0 - 1, 0, 0))]),
               (R, [((R * lo_c, 0, 0), (R * hi_c, R - 1, R - 1))])]
     H = O.Hierarchy(O.WAVE, (N0, 1, 1), (-2.0, 0.0, 0.0), dx0, levels)
+    H.set_time_mode(mode)
 
     def exact(x, t):
         g = lambda s: np.exp(-(s ** 2) / width ** 2)
@@ -96,8 +100,16 @@ def _fmr_wave_run(N_unit, R, T=2.5, L=6.0, width=0.25):
     f0 = np.broadcast_to(exact(xf, 0.0), (R, R, xf.size))
     H.set(1, 0, synth.embed(np.stack([f0, 0 * f0])))
     dt0 = 0.25 * dx0
-    nsteps = int(round(T / dt0))
     prm = O.params(sigma=0.1)
+    if window is not None:
+        inside, q, t = (x0 >= -2.0) & (x0 <= -1.0), 0.0, 0.0
+        while t < window[1] - 1e-12:
+            H.step(dt0, prm)
+            t += dt0
+            if t >= window[0]:
+                q = max(q, np.sum(np.abs(synth.interior(H.get(0, 0))[0, 0, 0][inside])) * dx0)
+        return q
+    nsteps = int(round(T / dt0))
     for _ in range(nsteps):
         H.step(dt0, prm)
     got = synth.interior(H.get(0, 0))[0, 0, 0]
@@ -109,6 +121,44 @@ def test_fmr_wave_bor_converges_order4(R):
     errs = [_fmr_wave_run(n, R, width=0.3) for n in (12, 24, 48)]
     orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert 3.5 < orders[-1] < 4.8, (errs, orders)
+
+
+@pytest.mark.parametrize("mode,lo,hi", [(O.TIME_BO, 3.5, 4.8), (O.TIME_NOSUB, 3.5, 4.8), (O.TIME_BO1, 0.7, 1.6)])
+def test_fmr_wave_time_refinement_orders(mode, lo, hi):
+    """Sec. III.B / IV.A: without sub-cycling and with Berger-Oliger using the
+    dense output the global error converges at 4th order; the linear
+    Berger-Oliger (BO1) only at 1st order."""
+    errs = [_fmr_wave_run(n, 2, width=0.3, mode=mode) for n in (12, 24, 48)]
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert lo < orders[-1] < hi, (errs, orders)
+
+
+@pytest.mark.parametrize("mode,lo,hi", [(O.TIME_BOR, 3.5, 5.5), (O.TIME_BO1, 0.7, 1.6)])
+def test_fmr_wave_reflections(mode, lo, hi):
+    """The reflection integral Q over [-2, -1] while only the reflection of
+    the pulse entering the refined region crosses it (domain length 10, the
+    exact Q is below 1e-11 there): BOR reflections vanish at 4th order, BO1
+    ones at 1st order (Sec. IV.A)."""
+    qs = [_fmr_wave_run(n, 2, L=10.0, width=0.25, mode=mode, window=(3.2, 4.2)) for n in (12, 24, 48)]
+    orders = np.log2(np.array(qs[:-1]) / np.array(qs[1:]))
+    assert lo < orders[-1] < hi, (qs, orders)
+
+
+def test_time_refinement_states_reduce_to_known_values():
+    """At the start of a parent step every strategy gives U^n for stage 1 of
+    fine step 0; without sub-cycling the states are the parent's RK4 stages;
+    BO1 at theta = 1 and BO at theta = 1 are U^{n+1}."""
+    rng = np.random.default_rng(0)
+    Un = rng.standard_normal(7)
+    k = [rng.standard_normal(7) for _ in range(4)]
+    un1 = Un + (k[0] + 2 * k[1] + 2 * k[2] + k[3]) / 6
+    for mode in (O.TIME_BOR, O.TIME_BO, O.TIME_BO1, O.TIME_NOSUB):
+        assert np.array_equal(O.time_state(mode, 2, 0, 1, 0.1, Un, k), Un)
+    for s, ref in ((2, Un + 0.5 * k[0]), (3, Un + 0.5 * k[1]), (4, Un + k[2])):
+        assert np.allclose(O.time_state(O.TIME_NOSUB, 1, 0, s, 0.1, Un, k), ref, rtol=0, atol=1e-15)
+    # fine step r = R - 1, stage 4 sits at theta = 1
+    for mode in (O.TIME_BO, O.TIME_BO1):
+        assert np.allclose(O.time_state(mode, 3, 2, 4, 0.1, Un, k), un1, rtol=0, atol=1e-14)
 
 
 def test_restriction_is_injection_and_fill_same_is_copy():
