@@ -99,6 +99,24 @@ def amr_bench(M, steps=2):
         res[mode] = {"ms_per_coarse_step": ms, "pt_stage_per_s": stages / (ms * 1e-3),
                      "wall_ms_per_coarse_step": (time.perf_counter() - t0) * 1e3 / steps}
         log(f"bench: AMR {mode}: {ms:.1f} ms per coarse step")
+    # time-refinement strategies (batched launches, no graph): the cost of
+    # advancing the hierarchy by dt0; without sub-cycling every level takes
+    # the finest level's step, dt0 / 6
+    strat = {}
+    for name, tm, calls in (("BOR", M.MOL_TIME_BOR, 1), ("BO", M.MOL_TIME_BO, 1), ("BO1", M.MOL_TIME_BO1, 1),
+                            ("NOSUB", M.MOL_TIME_NOSUB, 6)):
+        ps.advance(st, dt0 / calls, M.MOL_BATCHED | tm, stream)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(calls):
+            ps.advance(st, dt0 / calls, M.MOL_BATCHED | tm, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        strat[name] = {"ms_per_dt0": e0.elapsed_time(e1), "calls_per_dt0": calls}
+        log(f"bench: AMR {name}: {strat[name]['ms_per_dt0']:.1f} ms per dt0")
+    res["time_strategies"] = strat
     out = torch.zeros(5, dtype=torch.float64, device="cuda")
     ps.norms(0, st[0]["U"], 18, 1.0, 0.6, out)
     torch.cuda.synchronize()
@@ -108,6 +126,26 @@ def amr_bench(M, steps=2):
                      "patch_interior_range": [16, 48], "host_schedule_build_s": tbuild,
                      "nonfinite_after_run": int(out[4].item())}
     del g
+    return res
+
+
+def fmr_bench(M):
+    """The FMR wave experiment (Sec. IV.A) on the GPU driver: the largest
+    reflection integral Q while the reflection of the pulse entering the
+    refined region crosses [-2, -1], at coarse dx = 1/40, 1/80, 1/160, per
+    time-refinement strategy, and ratio 4 against ratio 2/2 (BOR)."""
+    import numpy as np
+    from paper_1806_04182_amd import fmr
+    res = {"resolutions": [40, 80, 160], "window": [3.2, 4.2]}
+    t0 = time.perf_counter()
+    for name, tm in (("BOR", M.MOL_TIME_BOR), ("BO", M.MOL_TIME_BO), ("BO1", M.MOL_TIME_BO1),
+                     ("NOSUB", M.MOL_TIME_NOSUB)):
+        q = [fmr.reflection_q(n, tm) for n in (40, 80, 160)]
+        res[name] = {"Q": q, "orders": [float(np.log2(q[i] / q[i + 1])) for i in range(2)]}
+        log(f"bench: FMR {name}: Q {q}, orders {res[name]['orders']}")
+    res["ratio4_vs_2x2_BOR_dx1_80"] = {"ratio4": fmr.reflection_q(80, M.MOL_TIME_BOR, ratios=(4,)),
+                                      "ratio2x2": fmr.reflection_q(80, M.MOL_TIME_BOR, ratios=(2, 2))}
+    res["wall_s"] = time.perf_counter() - t0
     return res
 
 
@@ -229,6 +267,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=96)
     ap.add_argument("--no-extras", action="store_true", help="skip the AMR and adjoint measurements")
+    ap.add_argument("--no-fmr", action="store_true",
+                    help="skip the FMR reflection runs (many small launches; kept out of kernel traces)")
     ap.add_argument("--paths-only", action="store_true",
                     help="measure only the wave and MHD paths and print their JSON (for profiling)")
     args = ap.parse_args()
@@ -332,6 +372,9 @@ def main():
     if not args.no_extras:
         log("bench: batched AMR hierarchy")
         res["amr_plain_vs_batched"] = amr_bench(M)
+        if not args.no_fmr:
+            log("bench: FMR reflections")
+            res["fmr_reflections"] = fmr_bench(M)
         log("bench: adjoint")
         res["adjoint"] = adjoint_bench(M)
         log("bench: wave and MHD paths")

@@ -171,6 +171,25 @@ int mol_prolong(mol_patchset* ps, int fine_level, int r, int stage,
 /* BOR weights w_1..w_4 used by mol_prolong (host query). */
 int mol_bor_weights(int R, int r, int stage, double w[4]);
 
+/* Time-refinement strategies of the sub-cycled step (Sec. III.B), or-ed into
+ * the mode of mol_advance.  Each fixes the parent state U^n + sum_j w_j k_j
+ * that is prolonged into the ghosts of fine step r (0 <= r < R), stage s:
+ *   MOL_TIME_BOR    App. D fine increments (mol_bor_weights), order 4;
+ *   MOL_TIME_BO     Berger-Oliger with the RK4 dense output b_j(theta) at
+ *                   the stage time theta = (r + c_s)/R, c = (0, 1/2, 1/2, 1);
+ *   MOL_TIME_BO1    linear Berger-Oliger, theta (1, 2, 2, 1)/6;
+ *   MOL_TIME_NOSUB  no sub-cycling: every level steps with the parent's dt
+ *                   (R = 1 in time) and stage s reads the parent's own stage
+ *                   state, w = 0, (1/2,0,0,0), (0,1/2,0,0), (0,0,1,0). */
+#define MOL_TIME_BOR 0
+#define MOL_TIME_BO 16
+#define MOL_TIME_BO1 32
+#define MOL_TIME_NOSUB 48
+
+/* Weights w_1..w_4 of strategy `tmode` (one of MOL_TIME_*), host query; for
+ * MOL_TIME_NOSUB only R = 1 is valid.  MOL_EINVAL on bad arguments. */
+int mol_time_weights(int tmode, int R, int r, int stage, double w[4]);
+
 /* Injection (Sec. III.A): every interior point of the parent level that
  * coincides with an interior point of `fine_level` takes the fine value. */
 int mol_restrict(mol_patchset* ps, int fine_level, const double* U_f, double* U_c,
@@ -212,6 +231,15 @@ int mol_rk4_adjoint_step(mol_patchset* ps, int level, double dt, const double* U
 int mol_norms(mol_patchset* ps, int level, const double* U, int field, double shift,
               double radius, double* out_dev, void* stream);
 
+/* The same reductions restricted to the interior points whose coordinates lie
+ * in the closed box lo[d] <= x_d <= hi[d] (infinite bounds allowed), with
+ * out_dev[3] = sum over the box of v dV.  For a channel one point thick in y
+ * and z, out_dev[0] / dx^2 is the line integral of |v| over [lo[0], hi[0]],
+ * the reflection integral Q of the FMR wave test (Sec. IV.A).  MOL_EINVAL for
+ * a NaN bound. */
+int mol_box_norms(mol_patchset* ps, int level, const double* U, int field, double shift,
+                  const double lo[3], const double hi[3], double* out_dev, void* stream);
+
 /* Transpose of the sphere integral of mol_norms (out_dev[3]): lam[field] =
  * scale * dV at interior points with |x| < radius, 0 at the other interior
  * points; the other fields are set to 0 on interior points; ghost entries
@@ -249,8 +277,10 @@ typedef struct {
 #define MOL_PLAIN 1   /* one launch per patch and operation */
 
 /* One RK4 step of size dt0 on level 0 with sub-cycling of the finer levels
- * (each level steps with dt / R of its parent), BOR prolongation and
- * injection; states[nlevels]. */
+ * (each level steps with dt / R of its parent), prolongation of the parent
+ * state into the fine ghosts at every stage and injection; states[nlevels].
+ * mode = MOL_BATCHED or MOL_PLAIN, or-ed with one MOL_TIME_* strategy
+ * (MOL_TIME_BOR when none is given).  MOL_EINVAL on an unknown mode. */
 int mol_advance(mol_patchset* ps, const mol_level_state* states, double dt0, int mode,
                 void* stream);
 

@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <array>
+#include <limits>
 #include <map>
 #include <cmath>
 #include <cstdarg>
@@ -619,6 +620,31 @@ void bor_weights(int R, int r, int s, double w[4])
     }
 }
 
+// Weights w_j of the parent state U^n + sum_j w_j k_j that feeds fine step r,
+// stage s, per time-refinement strategy (Sec. III.B): BOR (App. D, above);
+// Berger-Oliger with the dense output, b_j(theta) at the stage time
+// theta = (r + c_s)/R, c = (0, 1/2, 1/2, 1) (App. C); linear Berger-Oliger,
+// theta (1, 2, 2, 1)/6; no sub-cycling (R = 1 in time), the parent's own
+// stage states.
+void time_weights(int tmode, int R, int r, int s, double w[4])
+{
+    static const double cs[4] = {0.0, 0.5, 0.5, 1.0};
+    static const double cw[4] = {1.0 / 6.0, 2.0 / 6.0, 2.0 / 6.0, 1.0 / 6.0};
+    static const double c1[4] = {1.0, 0.0, 0.0, 0.0};
+    static const double c2[4] = {-1.5, 1.0, 1.0, -0.5};
+    static const double c3[4] = {2.0 / 3.0, -2.0 / 3.0, -2.0 / 3.0, 2.0 / 3.0};
+    const double th = (r + cs[s - 1]) / R;
+    for (int j = 0; j < 4; ++j) {
+        switch (tmode) {
+        case MOL_TIME_BO: w[j] = c1[j] * th + c2[j] * th * th + c3[j] * th * th * th; break;
+        case MOL_TIME_BO1: w[j] = th * cw[j]; break;
+        case MOL_TIME_NOSUB: w[j] = (s > 1 && j == s - 2) ? (s == 4 ? 1.0 : 0.5) : 0.0; break;
+        default: break;
+        }
+    }
+    if (tmode == MOL_TIME_BOR) bor_weights(R, r, s, w);
+}
+
 hipStream_t S(void* s) { return (hipStream_t)s; }
 
 int stage_impl(mol_patchset* ps, int level, int mode, int stage, double dt, const double* Un,
@@ -668,11 +694,11 @@ int fill_impl(mol_patchset* ps, int level, double* U, int nf, hipStream_t st, in
 }
 
 int prolong_impl(mol_patchset* ps, int fl, int r, int stage, const double* Unc,
-                 const double* const* kc, double* Uf, hipStream_t st, int plain)
+                 const double* const* kc, double* Uf, hipStream_t st, int plain, int tmode = MOL_TIME_BOR)
 {
     Level& lev = ps->L[fl];
     double w[4];
-    bor_weights(lev.ratio, r, stage, w);
+    time_weights(tmode, tmode == MOL_TIME_NOSUB ? 1 : lev.ratio, r, stage, w);
     const int nf = ps->sp.nf;
     // BOR stage state on the parent band, then Lagrange interpolation from it
     const int nl = plain ? (int)lev.pd.size() : 1;
@@ -711,7 +737,7 @@ int restrict_impl(mol_patchset* ps, int fl, const double* Uf, double* Uc, hipStr
 // dt; its finer level then takes R steps of dt/R whose coarse-fine ghosts
 // come from this step's U^n and k_1..k_4; the fine result is injected.
 int advance_level(mol_patchset* ps, const mol_level_state* st, int l, int r, double dt,
-                  hipStream_t s, int plain)
+                  hipStream_t s, int plain, int tmode)
 {
     const mol_level_state& X = st[l];
     const bool kids = l + 1 < ps->nlev;
@@ -725,16 +751,17 @@ int advance_level(mol_patchset* ps, const mol_level_state* st, int l, int r, dou
         if (l > 0) {
             const mol_level_state& P = st[l - 1];
             const double* kc[4] = {P.k[0], P.k[1], P.k[2], P.k[3]};
-            if ((rc = prolong_impl(ps, l, r, sidx + 1, P.U, kc, Us, s, plain))) return rc;
+            if ((rc = prolong_impl(ps, l, r, sidx + 1, P.U, kc, Us, s, plain, tmode))) return rc;
         }
         if ((rc = stage_impl(ps, l, ST_RK4, sidx + 1, dt, X.U, Us, X.acc, stage_out[sidx],
                              kids ? X.k[sidx] : nullptr, s, plain)))
             return rc;
     }
     if (kids) {
-        const int R = ps->L[l + 1].ratio;
+        // sub-cycling: R fine steps of dt/R; without it, one step of dt
+        const int R = tmode == MOL_TIME_NOSUB ? 1 : ps->L[l + 1].ratio;
         for (int rr = 0; rr < R; ++rr)
-            if ((rc = advance_level(ps, st, l + 1, rr, dt / R, s, plain))) return rc;
+            if ((rc = advance_level(ps, st, l + 1, rr, dt / R, s, plain, tmode))) return rc;
         if ((rc = restrict_impl(ps, l + 1, st[l + 1].U, X.S1, s, plain))) return rc;
         hipError_t e = hipMemcpyAsync(X.U, X.S1, sizeof(double) * ps->L[l].nelems,
                                       hipMemcpyDeviceToDevice, s);
@@ -890,6 +917,16 @@ int mol_bor_weights(int R, int r, int stage, double w[4])
     return MOL_OK;
 }
 
+int mol_time_weights(int tmode, int R, int r, int stage, double w[4])
+{
+    if (tmode != MOL_TIME_BOR && tmode != MOL_TIME_BO && tmode != MOL_TIME_BO1 && tmode != MOL_TIME_NOSUB)
+        return fail(MOL_EINVAL, "unknown time-refinement strategy %d", tmode);
+    if (R < 1 || r < 0 || r >= R || stage < 1 || stage > 4 || !w || (tmode == MOL_TIME_NOSUB && R != 1))
+        return fail(MOL_EINVAL, "bad time-weight arguments");
+    time_weights(tmode, R, r, stage, w);
+    return MOL_OK;
+}
+
 int mol_prolong(mol_patchset* ps, int fine_level, int r, int stage, const double* Un_c,
                 const double* const* k_c, double* U_f, void* stream)
 {
@@ -1009,8 +1046,9 @@ int mol_rk4_adjoint_step(mol_patchset* ps, int level, double dt, const double* U
     return e == hipSuccess ? MOL_OK : hip_fail(e, "axpby");
 }
 
-int mol_norms(mol_patchset* ps, int level, const double* U, int field, double shift, double radius,
-              double* out_dev, void* stream)
+namespace {
+int norms_impl(mol_patchset* ps, int level, const double* U, int field, double shift, double radius,
+               const CoordBox& box, double* out_dev, void* stream)
 {
     int rc = check_level(ps, level);
     if (rc) return rc;
@@ -1018,9 +1056,32 @@ int mol_norms(mol_patchset* ps, int level, const double* U, int field, double sh
     if (field < 0 || field >= ps->sp.nf) return fail(MOL_EINVAL, "field %d out of range", field);
     Level& lev = ps->L[level];
     hipError_t e = launch_norms(lev.d_pd.p, lev.ntiles.dev.p, (int)lev.ntiles.dev.n, lev.ntiles.tdim, U,
-                                field, shift, radius, lev.h, ps->xlo, ps->scratch, ps->red_blocks,
+                                field, shift, radius, lev.h, ps->xlo, box, ps->scratch, ps->red_blocks,
                                 out_dev, S(stream));
     return e == hipSuccess ? MOL_OK : hip_fail(e, "norms launch");
+}
+}  // namespace
+
+int mol_norms(mol_patchset* ps, int level, const double* U, int field, double shift, double radius,
+              double* out_dev, void* stream)
+{
+    const double inf = std::numeric_limits<double>::infinity();
+    const CoordBox all = {{-inf, -inf, -inf}, {inf, inf, inf}};
+    return norms_impl(ps, level, U, field, shift, radius, all, out_dev, stream);
+}
+
+int mol_box_norms(mol_patchset* ps, int level, const double* U, int field, double shift, const double lo[3],
+                  const double hi[3], double* out_dev, void* stream)
+{
+    if (!lo || !hi) return fail(MOL_EINVAL, "null box");
+    CoordBox b;
+    for (int d = 0; d < 3; ++d) {
+        if (std::isnan(lo[d]) || std::isnan(hi[d])) return fail(MOL_EINVAL, "box bound is NaN");
+        b.lo[d] = lo[d];
+        b.hi[d] = hi[d];
+    }
+    const double inf = std::numeric_limits<double>::infinity();
+    return norms_impl(ps, level, U, field, shift, inf, b, out_dev, stream);
 }
 
 int mol_sphere_adjoint(mol_patchset* ps, int level, int field, double radius, double scale, double* lam,
@@ -1093,10 +1154,13 @@ int mol_advance(mol_patchset* ps, const mol_level_state* states, double dt0, int
     if (ps->sp.system != MOL_WAVE && ps->sp.system != MOL_CCZ4 && ps->sp.system != MOL_MHD)
         return fail(MOL_EINVAL, "unknown system");
     if (!std::isfinite(dt0) || dt0 <= 0.0) return fail(MOL_EINVAL, "dt must be positive and finite");
-    if (mode != MOL_BATCHED && mode != MOL_PLAIN) return fail(MOL_EINVAL, "unknown mode %d", mode);
+    const int launch = mode & 15, tmode = mode & ~15;
+    if ((launch != MOL_BATCHED && launch != MOL_PLAIN) ||
+        (tmode != MOL_TIME_BOR && tmode != MOL_TIME_BO && tmode != MOL_TIME_BO1 && tmode != MOL_TIME_NOSUB))
+        return fail(MOL_EINVAL, "unknown mode %d", mode);
     int rc = check_states(ps, states);
     if (rc) return rc;
-    return advance_level(ps, states, 0, 0, dt0, S(stream), mode == MOL_PLAIN);
+    return advance_level(ps, states, 0, 0, dt0, S(stream), launch == MOL_PLAIN, tmode);
 }
 
 int mol_graph_create(mol_patchset* ps, const mol_level_state* states, double dt0, mol_graph** out)
@@ -1118,7 +1182,7 @@ int mol_graph_create(mol_patchset* ps, const mol_level_state* states, double dt0
         delete g;
         return hip_fail(e, "hipStreamBeginCapture");
     }
-    rc = advance_level(ps, states, 0, 0, dt0, ps->capture_stream, 0);
+    rc = advance_level(ps, states, 0, 0, dt0, ps->capture_stream, 0, MOL_TIME_BOR);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(ps->capture_stream, &graph);
     if (rc || e != hipSuccess) {

@@ -43,7 +43,7 @@ __global__ __launch_bounds__(RB) void norms_kernel(const PatchDev* __restrict__ 
                                                    const Tile* __restrict__ tiles, int ntiles,
                                                    const double* __restrict__ U, int field, double shift,
                                                    double r2max, double h, double x0, double y0, double z0,
-                                                   double* __restrict__ partial)
+                                                   CoordBox box, double* __restrict__ partial)
 {
     __shared__ double sh[NQ * RB];
     Red r;
@@ -54,6 +54,10 @@ __global__ __launch_bounds__(RB) void norms_kernel(const PatchDev* __restrict__ 
         const PatchDev P = patches[t.patch];
         const int i = t.o[0] + threadIdx.x, j = t.o[1] + threadIdx.y, k = t.o[2] + threadIdx.z;
         if (i >= P.n[0] || j >= P.n[1] || k >= P.n[2]) continue;
+        const double x = x0 + (P.lo[0] + i) * h, y = y0 + (P.lo[1] + j) * h, z = z0 + (P.lo[2] + k) * h;
+        if (!(x >= box.lo[0] && x <= box.hi[0] && y >= box.lo[1] && y <= box.hi[1] && z >= box.lo[2] &&
+              z <= box.hi[2]))
+            continue;
         const double v =
             U[P.off + (int64_t)field * P.fs + (int64_t)(k + G) * P.pitch_z + (int64_t)(j + G) * P.pitch_y + i + G] -
             shift;
@@ -64,7 +68,6 @@ __global__ __launch_bounds__(RB) void norms_kernel(const PatchDev* __restrict__ 
         r.v[0] += fabs(v) * dV;
         r.v[1] += v * v * dV;
         r.v[2] = fmax(r.v[2], fabs(v));
-        const double x = x0 + (P.lo[0] + i) * h, y = y0 + (P.lo[1] + j) * h, z = z0 + (P.lo[2] + k) * h;
         if (x * x + y * y + z * z < r2max) r.v[3] += v * dV;
     }
     block_reduce(r, sh, 2);
@@ -163,12 +166,12 @@ hipError_t launch_sphere_adjoint(const PatchDev* patches, const Tile* tiles, int
 }
 
 hipError_t launch_norms(const PatchDev* patches, const Tile* tiles, int ntiles, const int td[3], const double* U,
-                        int field, double shift, double radius, double h, const double xlo[3], double* partial,
-                        int nblocks, double* out, hipStream_t s)
+                        int field, double shift, double radius, double h, const double xlo[3], const CoordBox& box,
+                        double* partial, int nblocks, double* out, hipStream_t s)
 {
     if (td[0] * td[1] * td[2] != RB) return hipErrorInvalidValue;
     norms_kernel<<<nblocks, dim3(td[0], td[1], td[2]), 0, s>>>(patches, tiles, ntiles, U, field, shift,
-                                                               radius * radius, h, xlo[0], xlo[1], xlo[2],
+                                                               radius * radius, h, xlo[0], xlo[1], xlo[2], box,
                                                                partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

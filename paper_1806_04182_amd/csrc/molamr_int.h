@@ -157,9 +157,13 @@ hipError_t launch_wave_adjoint(const SysParams& sp, const PatchDev* patches, con
                                hipStream_t s);
 hipError_t launch_axpby(int64_t n, double a, const double* x, double b, const double* y,
                         double* z, hipStream_t s);
+// Closed coordinate box lo <= x <= hi per axis (infinite bounds: no restriction).
+struct CoordBox {
+    double lo[3], hi[3];
+};
 hipError_t launch_norms(const PatchDev* patches, const Tile* tiles, int ntiles, const int tdim[3],
                         const double* U, int field, double shift, double radius, double h,
-                        const double xlo[3], double* partial, int nblocks, double* out,
+                        const double xlo[3], const CoordBox& box, double* partial, int nblocks, double* out,
                         hipStream_t s);
 hipError_t launch_sphere_adjoint(const PatchDev* patches, const Tile* tiles, int ntiles, const int tdim[3],
                                 int nf, int field, double radius, double scale, double h, const double xlo[3],

@@ -20,6 +20,8 @@ LIB_PATH = os.environ.get("MOLAMR_LIB", os.path.join(HERE, "libmolamr.so"))
 MOL_WAVE, MOL_MHD, MOL_CCZ4 = 0, 1, 2
 MOL_RK4, MOL_SSPRK3 = 0, 1
 MOL_BATCHED, MOL_PLAIN = 0, 1
+# time-refinement strategies (Sec. III.B), or-ed into the mode of advance()
+MOL_TIME_BOR, MOL_TIME_BO, MOL_TIME_BO1, MOL_TIME_NOSUB = 0, 16, 32, 48
 GHOST = 3
 NFIELDS = {MOL_WAVE: 2, MOL_MHD: 8, MOL_CCZ4: 25}
 
@@ -77,12 +79,14 @@ def lib():
             "mol_rk_stage": ([vp, i, i, i, d, vp, vp, vp, vp, vp, vp], i),
             "mol_prolong": ([vp, i, i, i, vp, ctypes.POINTER(vp), vp, vp], i),
             "mol_bor_weights": ([i, i, i, dp], i),
+            "mol_time_weights": ([i, i, i, i, dp], i),
             "mol_restrict": ([vp, i, vp, vp, vp], i),
             "mol_rhs_adjoint": ([vp, i, vp, vp, vp, vp, vp], i),
             "mol_adjoint_workspace": ([vp, i], ctypes.c_int64),
             "mol_fill_ghosts_adjoint": ([vp, i, vp, vp], i),
             "mol_rk4_adjoint_step": ([vp, i, d, vp, vp, ctypes.POINTER(vp), vp, vp], i),
             "mol_norms": ([vp, i, vp, i, d, d, vp, vp], i),
+            "mol_box_norms": ([vp, i, vp, i, d, dp, dp, vp, vp], i),
             "mol_sphere_adjoint": ([vp, i, i, d, d, vp, vp], i),
             "mol_wave_gaussian": ([vp, i, dp, vp, vp], i),
             "mol_wave_gaussian_vjp": ([vp, i, dp, vp, vp, vp], i),
@@ -266,6 +270,12 @@ class Patchset:
     def norms(self, level, U, field, shift, radius, out_dev, stream=None):
         _check(lib().mol_norms(self._h, level, _ptr(U), field, shift, radius, _ptr(out_dev), _stream(stream)))
 
+    def box_norms(self, level, U, field, shift, lo, hi, out_dev, stream=None):
+        """norms() restricted to interior points with lo <= x <= hi."""
+        blo, bhi = (ctypes.c_double * 3)(*lo), (ctypes.c_double * 3)(*hi)
+        _check(lib().mol_box_norms(self._h, level, _ptr(U), field, shift, blo, bhi, _ptr(out_dev),
+                                   _stream(stream)))
+
     def sphere_adjoint(self, level, field, radius, scale, lam, stream=None):
         _check(lib().mol_sphere_adjoint(self._h, level, field, radius, scale, _ptr(lam), _stream(stream)))
 
@@ -298,6 +308,7 @@ class Patchset:
         return arr
 
     def advance(self, states, dt0, mode=MOL_BATCHED, stream=None):
+        """One level-0 step; mode = MOL_BATCHED or MOL_PLAIN | MOL_TIME_*."""
         _check(lib().mol_advance(self._h, self._states(states), dt0, mode, _stream(stream)))
 
     def graph_create(self, states, dt0):
@@ -332,6 +343,14 @@ class Graph:
 def bor_weights(R: int, r: int, stage: int) -> np.ndarray:
     w = (ctypes.c_double * 4)()
     _check(lib().mol_bor_weights(R, r, stage, w))
+    return np.array(list(w))
+
+
+def time_weights(tmode: int, R: int, r: int, stage: int) -> np.ndarray:
+    """Weights w_1..w_4 of the prolonged parent state U^n + sum_j w_j k_j
+    for fine step r, stage `stage`, under strategy `tmode` (MOL_TIME_*)."""
+    w = (ctypes.c_double * 4)()
+    _check(lib().mol_time_weights(tmode, R, r, stage, w))
     return np.array(list(w))
 
 

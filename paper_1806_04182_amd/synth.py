@@ -222,3 +222,12 @@ def amr_three_levels(seed: int = 0):
     l2 = tiled_boxes(start2, [composition(ext2[0], 6, 16, 48, rng), composition(ext2[1], 4, 16, 48, rng),
                               composition(ext2[2], 3, 16, 48, rng)])
     return [(1, l0), (2, l1), (3, l2)], (128, 128, 128), 2.0 / 128
+
+
+def wave_channel_pulse(x, t, L, width=0.173):
+    """Exact scalar field of the FMR wave test (Sec. IV.A): a Gaussian of
+    width `width` released at rest at x = 0 splits into halves moving left
+    and right, on a periodic line of length L (nearest images summed)."""
+    x = np.asarray(x, dtype=np.float64)
+    g = lambda s: np.exp(-(s ** 2) / width ** 2)
+    return sum(0.5 * (g(x - t + m * L) + g(x + t + m * L)) for m in (-1, 0, 1))

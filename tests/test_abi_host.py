@@ -68,3 +68,29 @@ def test_bor_weights_table_ratio2():
     assert np.allclose(M.bor_weights(2, 0, 3), [3 / 32, 1 / 8, 1 / 16, -1 / 32], atol=1e-16)
     with pytest.raises(M.MolError):
         M.bor_weights(2, 2, 1)
+
+
+@pytest.mark.parametrize("tmode,omode", [(M.MOL_TIME_BOR, O.TIME_BOR), (M.MOL_TIME_BO, O.TIME_BO),
+                                         (M.MOL_TIME_BO1, O.TIME_BO1), (M.MOL_TIME_NOSUB, O.TIME_NOSUB)])
+def test_time_weights_match_oracle_time_state(tmode, omode):
+    """The library's weights per time-refinement strategy against the oracle's
+    parent states built from the Sec. III.B definitions."""
+    rng = np.random.default_rng(11 + tmode)
+    Un = rng.standard_normal(9)
+    k = [rng.standard_normal(9) for _ in range(4)]
+    for R in ([1] if tmode == M.MOL_TIME_NOSUB else [1, 2, 3, 4]):
+        for r in range(R):
+            for s in range(1, 5):
+                w = M.time_weights(tmode, R, r, s)
+                ref = O.time_state(omode, R, r, s, 0.21, Un, k)
+                got = Un + sum(w[j] * k[j] for j in range(4))
+                assert np.max(np.abs(got - ref)) < 1e-14, (R, r, s)
+
+
+def test_time_weights_rejects_bad_arguments():
+    with pytest.raises(M.MolError):
+        M.time_weights(M.MOL_TIME_NOSUB, 2, 0, 1)
+    with pytest.raises(M.MolError):
+        M.time_weights(7, 2, 0, 1)
+    with pytest.raises(M.MolError):
+        M.time_weights(M.MOL_TIME_BO, 2, 0, 5)

@@ -105,6 +105,56 @@ def test_subcycled_step_parity_and_batching(system):
             assert np.array_equal(got[:, 3:-3, 3:-3, 3:-3], results["graph"][l][p][:, 3:-3, 3:-3, 3:-3])
 
 
+@pytest.mark.parametrize("system", [O.WAVE, O.CCZ4])
+@pytest.mark.parametrize("tmode,omode", [(M.MOL_TIME_BO, O.TIME_BO), (M.MOL_TIME_BO1, O.TIME_BO1),
+                                         (M.MOL_TIME_NOSUB, O.TIME_NOSUB)])
+def test_time_refinement_strategies_parity(system, tmode, omode):
+    """Berger-Oliger (dense output and linear) and the step without
+    sub-cycling, against the oracle's Sec. III.B strategies; batched and
+    per-patch launches agree bitwise."""
+    torch = _torch()
+    print("time refinement", system, tmode, flush=True)
+    ps, H, data, levels, dx0 = _setup(system)
+    H.set_time_mode(omode)
+    for l, arrs in enumerate(data):
+        for p, a in enumerate(arrs):
+            H.set(l, p, a)
+    for l in range(len(levels)):
+        H.fill_same(l)
+    # without sub-cycling every level takes the finest level's stable step
+    dt0 = 0.25 * dx0 / (6 if tmode == M.MOL_TIME_NOSUB else 1)
+    nsteps = 2
+    for _ in range(nsteps):
+        H.step(dt0, O.params(sigma=0.1))
+    results = {}
+    for launch in (M.MOL_BATCHED, M.MOL_PLAIN):
+        states = ps.alloc_states()
+        for l, arrs in enumerate(data):
+            states[l]["U"].copy_(torch.from_numpy(ps.pack(l, arrs)))
+        for _ in range(nsteps):
+            ps.advance(states, dt0, launch | tmode)
+        torch.cuda.synchronize()
+        results[launch] = [ps.unpack(l, states[l]["U"]) for l in range(len(levels))]
+    for l in range(len(levels)):
+        for p in range(len(levels[l][1])):
+            got = results[M.MOL_BATCHED][l][p][:, 3:-3, 3:-3, 3:-3]
+            ref = H.get(l, p)[:, 3:-3, 3:-3, 3:-3]
+            e = parity_err(got, ref)
+            assert np.all(e <= 1e-12), (l, p, e)
+            assert np.array_equal(got, results[M.MOL_PLAIN][l][p][:, 3:-3, 3:-3, 3:-3])
+
+
+def test_advance_rejects_unknown_mode():
+    torch = _torch()
+    ps, H, data, levels, dx0 = _setup(O.WAVE)
+    states = ps.alloc_states()
+    for bad in (2, 64, M.MOL_TIME_BO | 3):
+        with pytest.raises(M.MolError) as e:
+            ps.advance(states, 0.01, bad)
+        assert "mode" in str(e.value)
+    torch.cuda.synchronize()
+
+
 def test_fill_prolong_restrict_units():
     torch = _torch()
     ps, H, data, levels, dx0 = _setup(O.WAVE)

@@ -80,6 +80,39 @@ def test_norms_flag_non_finite_values():
     assert abs(o[0] - (10 * 9 * 8 - 2) * 1e-3) < 1e-12
 
 
+def test_box_norms_match_host_sums_over_the_box():
+    """Box-restricted reductions on a level cut into ragged patches against
+    plain sums over the points of the box (bounds on grid points included)."""
+    torch = _torch()
+    N, h = (20, 14, 9), 0.1
+    boxes = [((0, 0, 0), (6, 13, 8)), ((7, 0, 0), (19, 5, 8)), ((7, 6, 0), (19, 13, 8))]
+    ps = M.Patchset(M.Hierarchy(N, (-1.0, -0.7, 0.0), h, [(1, boxes)]), M.System(M.MOL_WAVE))
+    rng = np.random.default_rng(5)
+    full = rng.standard_normal((2, N[2], N[1], N[0]))
+    arrs = [synth.embed(full[:, lo[2]:hi[2] + 1, lo[1]:hi[1] + 1, lo[0]:hi[0] + 1]) for lo, hi in boxes]
+    U = torch.from_numpy(ps.pack(0, arrs)).cuda()
+    x = -1.0 + np.arange(N[0]) * h
+    y = -0.7 + np.arange(N[1]) * h
+    z = 0.0 + np.arange(N[2]) * h
+    for lo, hi in (((-0.5, -0.3, 0.2), (0.4, 0.6, 0.5)), ((-np.inf, 0.0, -np.inf), (np.inf, np.inf, 0.3)),
+                   ((5.0, 5.0, 5.0), (6.0, 6.0, 6.0))):
+        out = torch.zeros(5, dtype=torch.float64, device="cuda")
+        ps.box_norms(0, U, 1, 0.25, lo, hi, out)
+        torch.cuda.synchronize()
+        o = out.cpu().numpy()
+        m = ((z[:, None, None] >= lo[2]) & (z[:, None, None] <= hi[2]) & (y[None, :, None] >= lo[1]) &
+             (y[None, :, None] <= hi[1]) & (x[None, None, :] >= lo[0]) & (x[None, None, :] <= hi[0]))
+        v = (full[1] - 0.25)[m]
+        dV = h ** 3
+        assert abs(o[0] - np.sum(np.abs(v)) * dV) <= 1e-13 * max(1.0, np.sum(np.abs(v)) * dV)
+        assert abs(o[1] - np.sum(v * v) * dV) <= 1e-13 * max(1.0, np.sum(v * v) * dV)
+        assert o[2] == (np.max(np.abs(v)) if v.size else 0.0)
+        assert abs(o[3] - np.sum(v) * dV) <= 1e-13 * max(1.0, np.sum(np.abs(v)) * dV)
+        assert o[4] == 0.0
+    with pytest.raises(M.MolError, match="NaN"):
+        ps.box_norms(0, U, 0, 0.0, (np.nan, 0, 0), (1, 1, 1), out)
+
+
 def test_argument_errors_are_reported_before_launch():
     torch = _torch()
     n = (8, 8, 8)

@@ -144,6 +144,19 @@ def test_fmr_wave_reflections(mode, lo, hi):
     assert lo < orders[-1] < hi, (qs, orders)
 
 
+def test_fmr_wave_bo_reflections_first_order():
+    """Berger-Oliger with the dense output: at the paper's resolutions
+    (coarse dx = 1/80 and 1/160; pulse width 0.25 here, which makes BOR's
+    advantage show already at 1/80) the reflection integral Q falls only at
+    1st order, although the global error converges at 4th order, and BOR
+    reflections are several times smaller (Sec. IV.A, reflection figure)."""
+    qs = [_fmr_wave_run(n, 2, L=10.0, width=0.25, mode=O.TIME_BO, window=(3.2, 4.2)) for n in (80, 160)]
+    order = np.log2(qs[0] / qs[1])
+    assert 0.6 < order < 1.5, (qs, order)
+    q_bor = _fmr_wave_run(80, 2, L=10.0, width=0.25, mode=O.TIME_BOR, window=(3.2, 4.2))
+    assert q_bor < qs[0] / 3, (q_bor, qs[0])
+
+
 def test_time_refinement_states_reduce_to_known_values():
     """At the start of a parent step every strategy gives U^n for stage 1 of
     fine step 0; without sub-cycling the states are the parent's RK4 stages;
