@@ -1012,11 +1012,12 @@ int mol_rk4_adjoint_step(mol_patchset* ps, int level, double dt, const double* U
     const int64_t n = ps->L[level].nelems;
     hipStream_t s = S(stream);
     // Reverse of U' = U + sum_s c_s k_s, k_s = dt L(U_s), U_s = U + b_s k_{s-1}:
-    //   lk_s = c_s lam + b_{s+1} m_{s+1};  m_s = fill^T(dt L'(U_s)^T lk_s);
+    //   lk_s = c_s lam + b_{s+1} m_{s+1};  m_s = fill^T(L'(U_s)^T (dt lk_s));
     //   lam  <- lam + m_1 + m_2 + m_3 + m_4.
-    // w0 = lk, w1 = m (current), w2 = running sum of the m's; for a
-    // nonlinear system w3..w5 hold the stage states U_2..U_4, recomputed from
-    // U^n with the forward stage kernel (w2 serves as its accumulator).
+    // w0 = dt lk; w1 and w2 hold the current m and the running sum of the m's
+    // (the buffer that receives m_4 becomes the sum); for a nonlinear system
+    // w3..w5 hold the stage states U_2..U_4, recomputed from U^n with the
+    // forward stage kernel (w2 serves as its accumulator).
     static const double cw[4] = {1.0 / 6.0, 2.0 / 6.0, 2.0 / 6.0, 1.0 / 6.0};
     static const double bsub[4] = {0.0, 0.5, 0.5, 1.0};
     const double* Ust[4] = {Un, nullptr, nullptr, nullptr};
@@ -1029,20 +1030,28 @@ int mol_rk4_adjoint_step(mol_patchset* ps, int level, double dt, const double* U
         }
     }
     hipError_t e = hipSuccess;
+    double* wk = w[0];
+    double* wm = w[1];
+    double* wsum = w[2];
+    const double* prev = nullptr;  // m_{s+1}
     for (int st = 3; st >= 0; --st) {
         if (st == 3)
-            e = launch_axpby(n, cw[3], lam, 0.0, lam, w[0], s);
+            e = launch_axpby(n, dt * cw[3], lam, 0.0, lam, wk, s);
         else
-            e = launch_axpby(n, cw[st], lam, bsub[st + 1], w[1], w[0], s);
+            e = launch_axpby(n, dt * cw[st], lam, dt * bsub[st + 1], prev, wk, s);
         if (e != hipSuccess) return hip_fail(e, "axpby");
-        if ((rc = mol_rhs_adjoint(ps, level, Ust[st], w[0], w[1], work, stream))) return rc;
-        if ((rc = mol_fill_ghosts_adjoint(ps, level, w[1], stream))) return rc;
-        e = launch_axpby(n, dt, w[1], 0.0, w[1], w[1], s);
-        if (e != hipSuccess) return hip_fail(e, "axpby");
-        e = st == 3 ? launch_axpby(n, 1.0, w[1], 0.0, w[1], w[2], s) : launch_axpby(n, 1.0, w[2], 1.0, w[1], w[2], s);
-        if (e != hipSuccess) return hip_fail(e, "axpby");
+        if ((rc = mol_rhs_adjoint(ps, level, Ust[st], wk, wm, work, stream))) return rc;
+        if ((rc = mol_fill_ghosts_adjoint(ps, level, wm, stream))) return rc;
+        if (st == 3) {
+            std::swap(wm, wsum);
+            prev = wsum;
+        } else {
+            e = launch_axpby(n, 1.0, wsum, 1.0, wm, wsum, s);
+            if (e != hipSuccess) return hip_fail(e, "axpby");
+            prev = wm;
+        }
     }
-    e = launch_axpby(n, 1.0, lam, 1.0, w[2], lam, s);
+    e = launch_axpby(n, 1.0, lam, 1.0, wsum, lam, s);
     return e == hipSuccess ? MOL_OK : hip_fail(e, "axpby");
 }
 

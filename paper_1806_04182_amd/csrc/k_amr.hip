@@ -42,22 +42,23 @@ __global__ __launch_bounds__(BLK) void fill_kernel(const GhostCopy* __restrict__
     }
 }
 
-// transpose of the copy: source += its images, images <- 0
+// transpose of the copy: source += its images, images <- 0; one thread per
+// (source point, field), the field the slow index (every address is touched
+// by exactly one thread)
 __global__ __launch_bounds__(BLK) void fill_adjoint_kernel(const GhostSource* __restrict__ src, int64_t n,
                                                            const GhostImage* __restrict__ img, int nf,
                                                            double* __restrict__ A)
 {
-    for (int64_t t = blockIdx.x * (int64_t)BLK + threadIdx.x; t < n; t += (int64_t)gridDim.x * BLK) {
-        const GhostSource s = src[t];
-        for (int f = 0; f < nf; ++f) {
-            double acc = A[s.src + f * s.sfs];
-            for (int q = s.beg; q < s.end; ++q) {
-                const int64_t d = img[q].dst + f * img[q].dfs;
-                acc += A[d];
-                A[d] = 0.0;
-            }
-            A[s.src + f * s.sfs] = acc;
+    for (int64_t t = blockIdx.x * (int64_t)BLK + threadIdx.x; t < n * nf; t += (int64_t)gridDim.x * BLK) {
+        const int64_t f = t / n;
+        const GhostSource s = src[t - f * n];
+        double acc = A[s.src + f * s.sfs];
+        for (int q = s.beg; q < s.end; ++q) {
+            const int64_t d = img[q].dst + f * img[q].dfs;
+            acc += A[d];
+            A[d] = 0.0;
         }
+        A[s.src + f * s.sfs] = acc;
     }
 }
 
@@ -202,7 +203,7 @@ hipError_t launch_fill_adjoint(const GhostSource* src, int64_t n, const GhostIma
                                hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    fill_adjoint_kernel<<<grid_for(n), BLK, 0, s>>>(src, n, img, nf, A);
+    fill_adjoint_kernel<<<grid_for(n * nf), BLK, 0, s>>>(src, n, img, nf, A);
     return hipGetLastError();
 }
 

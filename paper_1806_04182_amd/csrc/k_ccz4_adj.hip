@@ -56,314 +56,415 @@ struct AdjConst {
     int upwind;
 };
 
-// ---------------------------------------------------------------- kernel 1
-__global__ __launch_bounds__(256) void ccz4_adj_point_kernel(const PatchDev* __restrict__ patches,
-                                                             const Tile* __restrict__ tiles, int ntiles,
-                                                             const double* __restrict__ Ug,
-                                                             const double* __restrict__ lamg,
-                                                             double* __restrict__ W,
-                                                             const int64_t* __restrict__ wofs, AdjConst C)
+// Further workspace slots, after the NW stencil-input adjoints: forward
+// intermediates stored by the first kernel, then adjoints of intermediates
+// handed from one kernel to the next.  Symmetric tensors are packed by SI;
+// an adjoint of a packed component is the derivative with respect to that one
+// variable (both orders of an off-diagonal pair together).
+constexpr int F_GU = NW;              // inverse conformal metric gt^{ij} (6)
+constexpr int F_GL = F_GU + 6;        // Gamma_{i jk}, packed in jk (18)
+constexpr int F_GUU = F_GL + 18;      // Gamma^i_{jk}, packed in jk (18)
+constexpr int F_Z = F_GUU + 18;       // Z^i (3)
+constexpr int F_RIC = F_Z + 3;        // R_ij = Rt_ij + R^chi_ij (6)
+constexpr int F_DDA = F_RIC + 6;      // D_i D_j alpha (6)
+constexpr int F_LNDET = F_DDA + 6;    // ln det gt (1)
+constexpr int F_DDG = F_LNDET + 1;    // d_m d_n gt_p, [p][mn packed] (36)
+constexpr int F_DGH = F_DDG + 36;     // d_j Ghat^k, [j][k] (9)
+constexpr int H_ARIC = F_DGH + 9;     // adjoint of R_ij (6)
+constexpr int H_ADDA = H_ARIC + 6;    // adjoint of D_i D_j alpha (6)
+constexpr int H_AGU = H_ADDA + 6;     // adjoint of gt^{ij} (6)
+constexpr int H_AGUU = H_AGU + 6;     // adjoint of Gamma^i_{jk} (18)
+constexpr int H_AZ = H_AGUU + 18;     // adjoint of Z^i (3)
+constexpr int H_AGL = H_AZ + 3;       // adjoint of Gamma_{i jk} (18)
+constexpr int NWX = H_AGL + 18;
+
+// multiplicity of a packed pair in a full double sum, and its indices
+__device__ constexpr double MU(int p) { return p == 0 || p == 3 || p == 5 ? 1.0 : 2.0; }
+__device__ constexpr int PI_(int p) { return p < 3 ? 0 : (p < 5 ? 1 : 2); }
+__device__ constexpr int PJ_(int p) { return p < 3 ? p : (p < 5 ? p - 2 : 2); }
+
+// One interior point of a tile and its views of U, lam and the workspace.
+struct Pt {
+    const double* u;
+    const double* lm;
+    double* w;
+    int64_t fs;
+    int S[3];
+    __device__ double U(int f) const { return u[(int64_t)f * fs]; }
+    __device__ double L(int f) const { return lm[(int64_t)f * fs]; }
+    __device__ double& Wq(int q) const { return w[(int64_t)q * fs]; }
+    __device__ double d1(const AdjConst& C, int f, int k) const { return C.i12h * fd1(u + (int64_t)f * fs, S[k]); }
+    __device__ double dd(const AdjConst& C, int f, int k, int l) const
+    {
+        const double* v = u + (int64_t)f * fs;
+        return k == l ? C.i12h2 * fd2(v, S[k]) : C.i144h2 * fmix(v, S[k], S[l]);
+    }
+};
+
+__device__ __forceinline__ bool pt_init(Pt& q, const PatchDev* __restrict__ patches, const Tile* __restrict__ tiles,
+                                        const double* Ug, const double* lamg, double* W,
+                                        const int64_t* __restrict__ wofs)
 {
-    const Tile t = tiles[blockIdx.x];
+    const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     const PatchDev P = patches[t.patch];
     const int ii = t.o[0] + threadIdx.x, jj = t.o[1] + threadIdx.y, kk = t.o[2] + threadIdx.z;
-    if (ii >= P.n[0] || jj >= P.n[1] || kk >= P.n[2]) return;
+    if (ii >= P.n[0] || jj >= P.n[1] || kk >= P.n[2]) return false;
     const int64_t loc = (int64_t)(kk + G) * P.pitch_z + (int64_t)(jj + G) * P.pitch_y + (ii + G);
-    const int64_t fs = P.fs;
-    const double* u = Ug + P.off + loc;
-    const double* lm = lamg + P.off + loc;
-    double* w = W + wofs[t.patch] + loc;
-    const int S[3] = {1, P.pitch_y, P.pitch_z};
-    auto F = [&](int f) { return u + (int64_t)f * fs; };
-    auto d1 = [&](int f, int k) { return C.i12h * fd1(F(f), S[k]); };
-    auto dd = [&](int f, int k, int l) {
-        return k == l ? C.i12h2 * fd2(F(f), S[k]) : C.i144h2 * fmix(F(f), S[k], S[l]);
-    };
+    q.fs = P.fs;
+    q.u = Ug + P.off + loc;
+    q.lm = lamg + P.off + loc;
+    q.w = W + wofs[t.patch] + loc;
+    q.S[0] = 1;
+    q.S[1] = P.pitch_y;
+    q.S[2] = P.pitch_z;
+    return true;
+}
 
-    // ---- forward recomputation (full symmetric tensors) ----
-    const double chi = F(CHI)[0], Kh = F(KH)[0], Th = F(TH)[0], alp = F(ALP)[0];
-    double g[3][3], A[3][3], Gh[3], be[3], Bv[3];
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-            g[i][j] = F(GT + SI(i, j))[0];
-            A[i][j] = F(AT + SI(i, j))[0];
-        }
+#define ADJ_KERNEL(name)                                                                                   \
+    __global__ __launch_bounds__(256) void name(const PatchDev* __restrict__ patches,                      \
+                                                const Tile* __restrict__ tiles, const double* __restrict__ Ug, \
+                                                const double* __restrict__ lamg, double* __restrict__ W,   \
+                                                const int64_t* __restrict__ wofs, AdjConst C)
+
+// inverse and ln det of the conformal metric (det expanded about the identity)
+__device__ __forceinline__ void metric_inverse(const double g[6], double gu[6], double& lndet)
+{
+    const double hx = g[0] - 1.0, hy = g[3] - 1.0, hz = g[5] - 1.0;
+    const double hxy = g[1], hxz = g[2], hyz = g[4];
+    const double m2 = hx * hy - hxy * hxy + hx * hz - hxz * hxz + hy * hz - hyz * hyz;
+    const double m3 = hx * (hy * hz - hyz * hyz) - hxy * (hxy * hz - hyz * hxz) + hxz * (hxy * hyz - hy * hxz);
+    const double dm = (hx + hy + hz) + m2 + m3;
+    lndet = log1p(dm);
+    const double idet = 1.0 / (1.0 + dm);
+    gu[0] = (g[3] * g[5] - g[4] * g[4]) * idet;
+    gu[1] = (g[2] * g[4] - g[1] * g[5]) * idet;
+    gu[2] = (g[1] * g[4] - g[2] * g[3]) * idet;
+    gu[3] = (g[0] * g[5] - g[2] * g[2]) * idet;
+    gu[4] = (g[2] * g[1] - g[0] * g[4]) * idet;
+    gu[5] = (g[0] * g[3] - g[1] * g[1]) * idet;
+}
+
+// ------------------------------------------------------------ kernel K1
+// Forward intermediates (stored).
+ADJ_KERNEL(ccz4_adj_forward_kernel)
+{
+    Pt q;
+    if (!pt_init(q, patches, tiles, Ug, lamg, W, wofs)) return;
+    double g[6], gu[6], lndet;
+    for (int p = 0; p < 6; ++p) g[p] = q.U(GT + p);
+    metric_inverse(g, gu, lndet);
+    const double chi = q.U(CHI), ic = 1.0 / chi;
+    double Gh[3], dchi[3], dalp[3];
     for (int i = 0; i < 3; ++i) {
-        Gh[i] = F(GH + i)[0];
-        be[i] = F(BETA + i)[0];
-        Bv[i] = F(BB + i)[0];
+        Gh[i] = q.U(GH + i);
+        dchi[i] = q.d1(C, CHI, i);
+        dalp[i] = q.d1(C, ALP, i);
     }
-    double dg[3][3][3], dchi[3], dalp[3], dGh[3][3], db[3][3], dKh[3], dTh[3];
-    for (int k = 0; k < 3; ++k) {
-        for (int i = 0; i < 3; ++i)
-            for (int j = i; j < 3; ++j) dg[k][i][j] = dg[k][j][i] = d1(GT + SI(i, j), k);
-        dchi[k] = d1(CHI, k);
-        dalp[k] = d1(ALP, k);
-        dKh[k] = d1(KH, k);
-        dTh[k] = d1(TH, k);
-        for (int i = 0; i < 3; ++i) {
-            dGh[k][i] = d1(GH + i, k);
-            db[k][i] = d1(BETA + i, k);
-        }
-    }
-    double ddc[3][3], dda[3][3], ddb[3][3][3];
-    for (int k = 0; k < 3; ++k)
-        for (int l = k; l < 3; ++l) {
-            ddc[k][l] = ddc[l][k] = dd(CHI, k, l);
-            dda[k][l] = dda[l][k] = dd(ALP, k, l);
-            for (int i = 0; i < 3; ++i) ddb[i][k][l] = ddb[i][l][k] = dd(BETA + i, k, l);
-        }
-    double gu[3][3], lndet;
+    double Gl[3][6], Gu[3][6];
     {
-        const double hx = g[0][0] - 1.0, hy = g[1][1] - 1.0, hz = g[2][2] - 1.0;
-        const double hxy = g[0][1], hxz = g[0][2], hyz = g[1][2];
-        const double m2 = hx * hy - hxy * hxy + hx * hz - hxz * hxz + hy * hz - hyz * hyz;
-        const double m3 = hx * (hy * hz - hyz * hyz) - hxy * (hxy * hz - hyz * hxz) + hxz * (hxy * hyz - hy * hxz);
-        const double dm = (hx + hy + hz) + m2 + m3;
-        lndet = log1p(dm);
-        const double idet = 1.0 / (1.0 + dm);
-        gu[0][0] = (g[1][1] * g[2][2] - g[1][2] * g[1][2]) * idet;
-        gu[0][1] = gu[1][0] = (g[0][2] * g[1][2] - g[0][1] * g[2][2]) * idet;
-        gu[0][2] = gu[2][0] = (g[0][1] * g[1][2] - g[0][2] * g[1][1]) * idet;
-        gu[1][1] = (g[0][0] * g[2][2] - g[0][2] * g[0][2]) * idet;
-        gu[1][2] = gu[2][1] = (g[0][2] * g[0][1] - g[0][0] * g[1][2]) * idet;
-        gu[2][2] = (g[0][0] * g[1][1] - g[0][1] * g[0][1]) * idet;
+        double dg[3][6];
+        for (int k = 0; k < 3; ++k)
+            for (int p = 0; p < 6; ++p) dg[k][p] = q.d1(C, GT + p, k);
+        for (int i = 0; i < 3; ++i)
+            for (int p = 0; p < 6; ++p) {
+                const int j = PI_(p), k = PJ_(p);
+                Gl[i][p] = 0.5 * (dg[j][SI(i, k)] + dg[k][SI(i, j)] - dg[i][p]);
+            }
     }
-    double Gl[3][3][3], Gu[3][3][3], Gc[3], Z[3];
     for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j)
-            for (int k = 0; k < 3; ++k) Gl[i][j][k] = 0.5 * (dg[j][i][k] + dg[k][i][j] - dg[i][j][k]);
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j)
-            for (int k = 0; k < 3; ++k) Gu[i][j][k] = gu[i][0] * Gl[0][j][k] + gu[i][1] * Gl[1][j][k] + gu[i][2] * Gl[2][j][k];
+        for (int p = 0; p < 6; ++p)
+            Gu[i][p] = gu[SI(i, 0)] * Gl[0][p] + gu[SI(i, 1)] * Gl[1][p] + gu[SI(i, 2)] * Gl[2][p];
+    double Z[3];
     for (int i = 0; i < 3; ++i) {
         double s = 0.0;
-        for (int j = 0; j < 3; ++j)
-            for (int k = 0; k < 3; ++k) s += gu[j][k] * Gu[i][j][k];
-        Gc[i] = s;
-        Z[i] = 0.5 * chi * (Gh[i] - Gc[i]);
+        for (int p = 0; p < 6; ++p) s += MU(p) * gu[p] * Gu[i][p];
+        Z[i] = 0.5 * chi * (Gh[i] - s);
     }
-    const double ic = 1.0 / chi;
-    double trc = 0.0, Ghd = 0.0;
-    for (int k = 0; k < 3; ++k) {
-        Ghd += Gh[k] * dchi[k];
-        for (int m = 0; m < 3; ++m) trc += gu[k][m] * (ddc[k][m] - 1.5 * ic * dchi[k] * dchi[m]);
+    double ddc[6], trc = 0.0, Ghd = 0.0;
+    for (int p = 0; p < 6; ++p) {
+        ddc[p] = q.dd(C, CHI, PI_(p), PJ_(p));
+        trc += MU(p) * gu[p] * (ddc[p] - 1.5 * ic * dchi[PI_(p)] * dchi[PJ_(p)]);
     }
-    // gt^{mn} d_m d_n gt_q, once per packed component q
-    double lapg[6];
-    for (int q = 0; q < 6; ++q) {
-        double t = 0.0;
-        for (int m = 0; m < 3; ++m)
-            for (int n = m; n < 3; ++n) t += (m == n ? 1.0 : 2.0) * gu[m][n] * dd(GT + q, m, n);
-        lapg[q] = t;
-    }
-    double Ric[3][3], Gd[3][3], zs[3][3];
+    for (int k = 0; k < 3; ++k) Ghd += Gh[k] * dchi[k];
+    // Gamma-Gamma terms through Q_i^{kn} = gt^{mn} Gamma^k_{mi}:
+    // sum_kn Q_i^{kn} (Gamma_jkn + Gamma_knj) + Q_j^{kn} Gamma_ikn
+    double Q[3][3][3];
     for (int i = 0; i < 3; ++i)
-        for (int j = i; j < 3; ++j) {
-            double gd = 0.0, z = 0.0;
-            for (int k = 0; k < 3; ++k) {
-                gd += Gu[k][i][j] * dchi[k];
-                z += Z[k] * 0.5 * (g[k][i] * dchi[j] + g[k][j] * dchi[i]);
-            }
-            Gd[i][j] = gd;
-            zs[i][j] = z;
-            double r = 0.5 * ic * ddc[i][j] - 0.5 * ic * gd - 0.25 * ic * ic * dchi[i] * dchi[j] + 2.0 * ic * ic * z +
-                       0.5 * ic * g[i][j] * (trc - Ghd);
-            r += -0.5 * lapg[SI(i, j)];
-            for (int k = 0; k < 3; ++k) {
-                r += 0.5 * (g[k][i] * dGh[j][k] + g[k][j] * dGh[i][k]);
-                r += Gh[k] * 0.5 * (Gl[i][j][k] + Gl[j][i][k]);
-            }
-            for (int m = 0; m < 3; ++m)
-                for (int n = 0; n < 3; ++n)
-                    for (int k = 0; k < 3; ++k)
-                        r += gu[m][n] * (Gu[k][m][i] * Gl[j][k][n] + Gu[k][m][j] * Gl[i][k][n] + Gu[k][m][i] * Gl[k][n][j]);
-            Ric[i][j] = Ric[j][i] = r;
-            Gd[j][i] = gd;
-            zs[j][i] = z;
+        for (int k = 0; k < 3; ++k)
+            for (int n = 0; n < 3; ++n)
+                Q[i][k][n] = gu[SI(0, n)] * Gu[k][SI(0, i)] + gu[SI(1, n)] * Gu[k][SI(1, i)] + gu[SI(2, n)] * Gu[k][SI(2, i)];
+    double dGh[3][3];  // [j][k] = d_j Ghat^k
+    for (int j = 0; j < 3; ++j)
+        for (int k = 0; k < 3; ++k) {
+            dGh[j][k] = q.d1(C, GH + k, j);
+            q.Wq(F_DGH + 3 * j + k) = dGh[j][k];
         }
-    double cr = 0.0;
-    for (int k = 0; k < 3; ++k)
-        for (int m = 0; m < 3; ++m) cr += gu[k][m] * dalp[k] * dchi[m];
-    const double hic = 0.5 * ic;
-    double DDa[3][3];
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j)
-            DDa[i][j] = dda[i][j] - (Gu[0][i][j] * dalp[0] + Gu[1][i][j] * dalp[1] + Gu[2][i][j] * dalp[2]) +
-                        hic * (dalp[i] * dchi[j] + dalp[j] * dchi[i] - g[i][j] * cr);
-    double Am[3][3], Au[3][3], trA = 0.0, AA = 0.0;
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) Am[i][j] = gu[i][0] * A[0][j] + gu[i][1] * A[1][j] + gu[i][2] * A[2][j];
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) Au[i][j] = Am[i][0] * gu[0][j] + Am[i][1] * gu[1][j] + Am[i][2] * gu[2][j];
-    for (int i = 0; i < 3; ++i) {
-        trA += Am[i][i];
-        for (int j = 0; j < 3; ++j) AA += A[i][j] * Au[i][j];
+    // Ricci tensor, one packed component at a time
+    for (int p = 0; p < 6; ++p) {
+        const int i = PI_(p), j = PJ_(p);
+        double gd = 0.0, zs = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            gd += Gu[k][p] * dchi[k];
+            zs += Z[k] * 0.5 * (g[SI(k, i)] * dchi[j] + g[SI(k, j)] * dchi[i]);
+        }
+        double lap = 0.0;
+        for (int m = 0; m < 6; ++m) {
+            const double v = q.dd(C, GT + p, PI_(m), PJ_(m));
+            q.Wq(F_DDG + 6 * p + m) = v;
+            lap += MU(m) * gu[m] * v;
+        }
+        double r = 0.5 * ic * ddc[p] - 0.5 * ic * gd - 0.25 * ic * ic * dchi[i] * dchi[j] + 2.0 * ic * ic * zs +
+                   0.5 * ic * g[p] * (trc - Ghd) - 0.5 * lap;
+        for (int k = 0; k < 3; ++k) {
+            r += 0.5 * (g[SI(k, i)] * dGh[j][k] + g[SI(k, j)] * dGh[i][k]);
+            r += Gh[k] * 0.5 * (Gl[i][SI(j, k)] + Gl[j][SI(i, k)]);
+        }
+        for (int k = 0; k < 3; ++k)
+            for (int n = 0; n < 3; ++n)
+                r += Q[i][k][n] * (Gl[j][SI(k, n)] + Gl[k][SI(n, j)]) + Q[j][k][n] * Gl[i][SI(k, n)];
+        q.Wq(F_RIC + p) = r;
     }
-    double X[3][3], trX = 0.0;
+    // D_i D_j alpha
+    {
+        double cr = 0.0;
+        for (int p = 0; p < 6; ++p)
+            cr += gu[p] * (p == 0 || p == 3 || p == 5 ? dalp[PI_(p)] * dchi[PJ_(p)]
+                                                      : dalp[PI_(p)] * dchi[PJ_(p)] + dalp[PJ_(p)] * dchi[PI_(p)]);
+        const double hic = 0.5 * ic;
+        for (int p = 0; p < 6; ++p) {
+            const int i = PI_(p), j = PJ_(p);
+            q.Wq(F_DDA + p) = q.dd(C, ALP, i, j) - (Gu[0][p] * dalp[0] + Gu[1][p] * dalp[1] + Gu[2][p] * dalp[2]) +
+                              hic * (dalp[i] * dchi[j] + dalp[j] * dchi[i] - g[p] * cr);
+        }
+    }
+    for (int p = 0; p < 6; ++p) q.Wq(F_GU + p) = gu[p];
     for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) X[i][j] = alp * Ric[i][j] - DDa[i][j];
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) trX += gu[i][j] * X[i][j];
+        for (int p = 0; p < 6; ++p) {
+            q.Wq(F_GL + 6 * i + p) = Gl[i][p];
+            q.Wq(F_GUU + 6 * i + p) = Gu[i][p];
+        }
+    for (int i = 0; i < 3; ++i) q.Wq(F_Z + i) = Z[i];
+    q.Wq(F_LNDET) = lndet;
+}
+
+// ------------------------------------------------------------ kernel K0
+// The derivative of the advection terms sum_f lam_f beta^k L_k u_f with
+// respect to beta^k (first writer of those three slots).
+ADJ_KERNEL(ccz4_adj_advection_kernel)
+{
+    Pt q;
+    if (!pt_init(q, patches, tiles, Ug, lamg, W, wofs)) return;
+    double be[3], a_be[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < 3; ++k) be[k] = q.U(BETA + k);
+    for (int f = 0; f < NF; ++f) {
+        const double lf = q.L(f);
+        const double* v = q.u + (int64_t)f * q.fs;
+        for (int k = 0; k < 3; ++k) a_be[k] += lf * (C.upwind ? fadv(v, q.S[k], be[k]) : fd1(v, q.S[k]));
+    }
+    for (int k = 0; k < 3; ++k) q.Wq(W_U + BETA + k) = C.i12h * a_be[k];
+}
+
+// ------------------------------------------------------------ kernel K2
+// Reverse of the gt_ij and At_ij equations, with X_ij = alpha R_ij - D_iD_j alpha,
+// its trace, Am = gt^{-1} At, tr At and ln det gt.
+ADJ_KERNEL(ccz4_adj_metric_kernel)
+{
+    Pt q;
+    if (!pt_init(q, patches, tiles, Ug, lamg, W, wofs)) return;
+    double g[6], A[6], gu[6], X[6];
+    for (int p = 0; p < 6; ++p) {
+        g[p] = q.U(GT + p);
+        A[p] = q.U(AT + p);
+        gu[p] = q.Wq(F_GU + p);
+    }
+    const double alp = q.U(ALP), Kh = q.U(KH), chi = q.U(CHI), lndet = q.Wq(F_LNDET);
+    double db[3][3];  // db[k][i] = d_k beta^i
+    for (int k = 0; k < 3; ++k)
+        for (int i = 0; i < 3; ++i) db[k][i] = q.d1(C, BETA + i, k);
     const double divb = db[0][0] + db[1][1] + db[2][2];
-    const double Kt = Kh + 2.0 * Th;
-    double gdiv[3];
-    for (int l = 0; l < 3; ++l) gdiv[l] = ddb[0][0][l] + ddb[1][1][l] + ddb[2][2][l];
-    double b1[3], rG[3], b2[3];
-    for (int i = 0; i < 3; ++i) {
-        double s = 0.0;
-        for (int j = 0; j < 3; ++j)
-            for (int k = 0; k < 3; ++k) s += Gu[i][j][k] * Au[j][k];
-        for (int j = 0; j < 3; ++j) s += -1.5 * ic * Au[i][j] * dchi[j];
-        b1[i] = s;
-        double r = 0.0;
-        for (int j = 0; j < 3; ++j) r += -(2.0 / 3.0) * gu[i][j] * dKh[j] - gu[i][j] * ((1.0 / 3.0) * dTh[j] + Th / alp * dalp[j]);
-        rG[i] = r;
-        b2[i] = -Z[i] * ic * (C.kz + (2.0 / 3.0) * Kt);
-    }
-
-    // ---- reverse sweep ----
-    double lGT[3][3], lAT[3][3], lGH[3], lBB[3], lBE[3];
+    double Am[3][3], trA = 0.0, trX = 0.0;
     for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-            lGT[i][j] = lm[(int64_t)(GT + SI(i, j)) * fs];
-            lAT[i][j] = lm[(int64_t)(AT + SI(i, j)) * fs];
-        }
-    for (int i = 0; i < 3; ++i) {
-        lGH[i] = lm[(int64_t)(GH + i) * fs];
-        lBB[i] = lm[(int64_t)(BB + i) * fs];
-        lBE[i] = lm[(int64_t)(BETA + i) * fs];
+        for (int j = 0; j < 3; ++j) Am[i][j] = gu[SI(i, 0)] * A[SI(0, j)] + gu[SI(i, 1)] * A[SI(1, j)] + gu[SI(i, 2)] * A[SI(2, j)];
+    for (int i = 0; i < 3; ++i) trA += Am[i][i];
+    for (int p = 0; p < 6; ++p) {
+        X[p] = alp * q.Wq(F_RIC + p) - q.Wq(F_DDA + p);
+        trX += MU(p) * gu[p] * X[p];
     }
-    const double lCHI = lm[(int64_t)CHI * fs], lKH = lm[(int64_t)KH * fs], lTH = lm[(int64_t)TH * fs],
-                 lALP = lm[(int64_t)ALP * fs];
-
-    double a_g[3][3] = {}, a_A[3][3] = {}, a_gu[3][3] = {}, a_Gl[3][3][3] = {}, a_Gu[3][3][3] = {};
-    double a_Ric[3][3] = {}, a_DDa[3][3] = {}, a_Am[3][3] = {}, a_Au[3][3] = {}, a_X[3][3] = {};
-    double a_dg[3][3][3] = {}, a_dGh[3][3] = {}, a_db[3][3] = {}, a_ddc[3][3] = {}, a_dda[3][3] = {}, a_ddb[3][3][3] = {};
-    double a_lapg[6] = {};
-    double a_chi = 0.0, a_Kh = 0.0, a_Th = 0.0, a_alp = 0.0, a_ic = 0.0, a_lndet = 0.0, a_trA = 0.0, a_AA = 0.0;
-    double a_divb = 0.0, a_Zda = 0.0, a_Kt = 0.0, a_trX = 0.0, a_trRic = 0.0, a_lapa = 0.0;
-    double a_Gh[3] = {}, a_Bv[3] = {}, a_Z[3] = {}, a_dchi[3] = {}, a_dalp[3] = {}, a_dKh[3] = {}, a_dTh[3] = {};
-    double a_gdiv[3] = {}, a_gddb[3] = {};
-
-    // (7) alpha: -(f0 alp^2 + f1 alp) Kh
-    a_alp += -(2.0 * C.f0 * alp + C.f1) * Kh * lALP;
-    a_Kh += -(C.f0 * alp * alp + C.f1 * alp) * lALP;
-    // (6) beta^i = g B^i; B^i = -eta B^i + S_i; Ghat^i = S_i
-    for (int i = 0; i < 3; ++i) {
-        a_Bv[i] += C.g * lBE[i] - C.eta * lBB[i];
-        const double aS = lGH[i] + lBB[i];
-        a_Gh[i] += (2.0 / 3.0) * divb * aS;
-        a_divb += (2.0 / 3.0) * Gh[i] * aS;
-        a_gddb[i] += aS;
-        for (int j = 0; j < 3; ++j) {
-            a_Gh[j] += -db[j][i] * aS;
-            a_db[j][i] += -Gh[j] * aS;
-            a_gu[i][j] += (1.0 / 3.0) * gdiv[j] * aS;
-            a_gdiv[j] += (1.0 / 3.0) * gu[i][j] * aS;
-            a_Au[i][j] += -2.0 * dalp[j] * aS;
-            a_dalp[j] += -2.0 * Au[i][j] * aS;
+    double a_A[6] = {}, a_g[6] = {}, a_X[6] = {}, a_gu[6] = {}, a_db[3][3] = {}, a_Am[3][3] = {};
+    double a_divb = 0.0, a_alp = 0.0, a_trA = 0.0, a_chi = 0.0, a_trX = 0.0, a_Kh = 0.0, a_lndet = 0.0;
+    for (int p = 0; p < 6; ++p) {
+        const int i = PI_(p), j = PJ_(p);
+        const double la = q.L(AT + p), lg = q.L(GT + p);
+        double AAm = 0.0;
+        for (int k = 0; k < 3; ++k) AAm += A[SI(i, k)] * Am[k][j];
+        for (int k = 0; k < 3; ++k) {
+            a_A[SI(i, k)] += db[j][k] * la;
+            a_db[j][k] += A[SI(i, k)] * la + g[SI(i, k)] * lg;
+            a_A[SI(k, j)] += db[i][k] * la;
+            a_db[i][k] += A[SI(k, j)] * la + g[SI(k, j)] * lg;
+            a_g[SI(i, k)] += db[j][k] * lg;
+            a_g[SI(k, j)] += db[i][k] * lg;
+            a_A[SI(i, k)] += -2.0 * alp * Am[k][j] * la;
+            a_Am[k][j] += -2.0 * alp * A[SI(i, k)] * la;
         }
-        a_alp += 2.0 * (b1[i] + rG[i] + b2[i]) * aS;
-        const double ab = 2.0 * alp * aS;  // adjoint of b1, rG and b2
-        // b1
+        a_A[p] += (-(2.0 / 3.0) * divb + alp * Kh) * la - 2.0 * alp * lg;
+        a_divb += -(2.0 / 3.0) * A[p] * la - (2.0 / 3.0) * g[p] * lg;
+        a_alp += -(C.kc / 3.0) * g[p] * trA * la + (Kh * A[p] - 2.0 * AAm) * la;
+        a_alp += -2.0 * (A[p] - (1.0 / 3.0) * g[p] * trA) * lg - (C.kc / 3.0) * g[p] * lndet * lg;
+        a_g[p] += -(C.kc / 3.0) * alp * trA * la - (1.0 / 3.0) * chi * trX * la;
+        a_g[p] += -(2.0 / 3.0) * divb * lg + (2.0 / 3.0) * alp * trA * lg - (C.kc / 3.0) * alp * lndet * lg;
+        a_trA += -(C.kc / 3.0) * alp * g[p] * la + (2.0 / 3.0) * alp * g[p] * lg;
+        a_chi += (X[p] - (1.0 / 3.0) * g[p] * trX) * la;
+        a_X[p] += chi * la;
+        a_trX += -(1.0 / 3.0) * chi * g[p] * la;
+        a_Kh += alp * A[p] * la;
+        a_lndet += -(C.kc / 3.0) * alp * g[p] * lg;
+    }
+    // trX = sum gt^{ij} X_ij; X = alpha R - DDa
+    for (int p = 0; p < 6; ++p) {
+        a_gu[p] += MU(p) * X[p] * a_trX;
+        a_X[p] += MU(p) * gu[p] * a_trX;
+        a_alp += q.Wq(F_RIC + p) * a_X[p];
+    }
+    // tr At = sum_i Am_ii; Am = gt^{-1} At
+    for (int i = 0; i < 3; ++i) a_Am[i][i] += a_trA;
+    for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j)
-            for (int k = 0; k < 3; ++k) {
-                a_Gu[i][j][k] += Au[j][k] * ab;
-                a_Au[j][k] += Gu[i][j][k] * ab;
+            for (int l = 0; l < 3; ++l) {
+                a_gu[SI(i, l)] += A[SI(l, j)] * a_Am[i][j];
+                a_A[SI(l, j)] += gu[SI(i, l)] * a_Am[i][j];
             }
-        for (int j = 0; j < 3; ++j) {
-            a_ic += -1.5 * Au[i][j] * dchi[j] * ab;
-            a_Au[i][j] += -1.5 * ic * dchi[j] * ab;
-            a_dchi[j] += -1.5 * ic * Au[i][j] * ab;
-        }
-        // rG
-        for (int j = 0; j < 3; ++j) {
-            a_gu[i][j] += (-(2.0 / 3.0) * dKh[j] - (1.0 / 3.0) * dTh[j] - Th / alp * dalp[j]) * ab;
-            a_dKh[j] += -(2.0 / 3.0) * gu[i][j] * ab;
-            a_dTh[j] += -(1.0 / 3.0) * gu[i][j] * ab;
-            a_dalp[j] += -gu[i][j] * Th / alp * ab;
-            a_Th += -gu[i][j] * dalp[j] / alp * ab;
-            a_alp += gu[i][j] * Th * dalp[j] / (alp * alp) * ab;
-        }
-        // b2
-        a_Z[i] += -ic * (C.kz + (2.0 / 3.0) * Kt) * ab;
-        a_ic += -Z[i] * (C.kz + (2.0 / 3.0) * Kt) * ab;
-        a_Kt += -Z[i] * ic * (2.0 / 3.0) * ab;
+    // ln det gt; div beta
+    for (int p = 0; p < 6; ++p) a_g[p] += MU(p) * gu[p] * a_lndet;
+    for (int i = 0; i < 3; ++i) a_db[i][i] += a_divb;
+    for (int p = 0; p < 6; ++p) {
+        q.Wq(W_U + AT + p) = a_A[p];
+        q.Wq(W_U + GT + p) = a_g[p];
+        q.Wq(H_ARIC + p) = alp * a_X[p];
+        q.Wq(H_ADDA + p) = -a_X[p];
+        q.Wq(H_AGU + p) = a_gu[p];
     }
-    // (5) Theta
+    for (int k = 0; k < 3; ++k)
+        for (int i = 0; i < 3; ++i) q.Wq(W_D1 + 3 * d1_slot(BETA + i) + k) = a_db[k][i];
+    q.Wq(W_U + CHI) = a_chi;
+    q.Wq(W_U + KH) = a_Kh;
+    q.Wq(W_U + ALP) = a_alp;
+}
+
+// ------------------------------------------------------------ kernel K3
+// Reverse of the chi, Khat, Theta, Ghat^i, B^i, beta^i and alpha equations.
+ADJ_KERNEL(ccz4_adj_gauge_kernel)
+{
+    Pt q;
+    if (!pt_init(q, patches, tiles, Ug, lamg, W, wofs)) return;
+    double A[6], gu[6];
+    for (int p = 0; p < 6; ++p) {
+        A[p] = q.U(AT + p);
+        gu[p] = q.Wq(F_GU + p);
+    }
+    const double chi = q.U(CHI), Kh = q.U(KH), Th = q.U(TH), alp = q.U(ALP), ic = 1.0 / chi;
+    const double Kt = Kh + 2.0 * Th;
+    double Gh[3], Z[3], dalp[3], dchi[3], dKh[3], dTh[3];
+    for (int i = 0; i < 3; ++i) {
+        Gh[i] = q.U(GH + i);
+        Z[i] = q.Wq(F_Z + i);
+        dalp[i] = q.d1(C, ALP, i);
+        dchi[i] = q.d1(C, CHI, i);
+        dKh[i] = q.d1(C, KH, i);
+        dTh[i] = q.d1(C, TH, i);
+    }
+    double db[3][3];
+    for (int k = 0; k < 3; ++k)
+        for (int i = 0; i < 3; ++i) db[k][i] = q.d1(C, BETA + i, k);
+    const double divb = db[0][0] + db[1][1] + db[2][2];
+    double Am[3][3], Au[6], AA = 0.0, trRic = 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Am[i][j] = gu[SI(i, 0)] * A[SI(0, j)] + gu[SI(i, 1)] * A[SI(1, j)] + gu[SI(i, 2)] * A[SI(2, j)];
+    for (int p = 0; p < 6; ++p) {
+        const int i = PI_(p), j = PJ_(p);
+        Au[p] = Am[i][0] * gu[SI(0, j)] + Am[i][1] * gu[SI(1, j)] + Am[i][2] * gu[SI(2, j)];
+        AA += MU(p) * A[p] * Au[p];
+        trRic += MU(p) * gu[p] * q.Wq(F_RIC + p);
+    }
+    trRic *= chi;
+
+    double a_alp = 0.0, a_Kh = 0.0, a_Th = 0.0, a_chi = 0.0, a_Kt = 0.0, a_AA = 0.0, a_trRic = 0.0, a_lapa = 0.0;
+    double a_Zda = 0.0, a_divb = 0.0, a_ic = 0.0;
+    double a_Au[6] = {}, a_gu[6] = {}, a_Gh[3] = {}, a_dalp[3] = {}, a_dchi[3] = {}, a_Z[3] = {}, a_db[3][3] = {};
     {
-        double trRic = 0.0;
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) trRic += chi * gu[i][j] * Ric[i][j];
-        const double Zda = Z[0] * dalp[0] + Z[1] * dalp[1] + Z[2] * dalp[2];
+        const double lALP = q.L(ALP), lKH = q.L(KH), lTH = q.L(TH), lCHI = q.L(CHI);
+        // alpha: -(f0 alpha^2 + f1 alpha) Khat
+        a_alp += -(2.0 * C.f0 * alp + C.f1) * Kh * lALP;
+        a_Kh += -(C.f0 * alp * alp + C.f1 * alp) * lALP;
+        // Theta
         a_alp += (0.5 * (trRic + (2.0 / 3.0) * Kh * Kh + (2.0 / 3.0) * Th * (Kh - 2.0 * Th) - AA) - 2.0 * C.kz * Th) * lTH;
         a_trRic += 0.5 * alp * lTH;
         a_Kh += 0.5 * alp * ((4.0 / 3.0) * Kh + (2.0 / 3.0) * Th) * lTH;
         a_Th += (0.5 * alp * (2.0 / 3.0) * (Kh - 4.0 * Th) - 2.0 * alp * C.kz) * lTH;
         a_AA += -0.5 * alp * lTH;
         a_Zda += -lTH;
-        // (4) Khat
+        // Khat
         a_lapa += -lKH;
         a_alp += ((1.0 / 3.0) * Kt * Kt + AA + C.kz * Th) * lKH;
         a_Kt += alp * (2.0 / 3.0) * Kt * lKH;
         a_AA += alp * lKH;
         a_Th += alp * C.kz * lKH;
         a_Zda += 2.0 * lKH;
-        (void)Zda;
+        // chi
+        a_chi += (2.0 / 3.0) * (alp * Kt - divb) * lCHI;
+        a_alp += (2.0 / 3.0) * chi * Kt * lCHI;
+        a_Kt += (2.0 / 3.0) * chi * alp * lCHI;
+        a_divb += -(2.0 / 3.0) * chi * lCHI;
     }
-    // (3) chi
-    a_chi += (2.0 / 3.0) * (alp * Kt - divb) * lCHI;
-    a_alp += (2.0 / 3.0) * chi * Kt * lCHI;
-    a_Kt += (2.0 / 3.0) * chi * alp * lCHI;
-    a_divb += -(2.0 / 3.0) * chi * lCHI;
-    // (2) At_ij and (1) gt_ij, i <= j
-    for (int i = 0; i < 3; ++i)
-        for (int j = i; j < 3; ++j) {
-            const double la = lAT[i][j], lg = lGT[i][j];
-            double AAm = 0.0;
-            for (int k = 0; k < 3; ++k) AAm += A[i][k] * Am[k][j];
-            for (int k = 0; k < 3; ++k) {
-                a_A[i][k] += db[j][k] * la;
-                a_db[j][k] += A[i][k] * la;
-                a_A[k][j] += db[i][k] * la;
-                a_db[i][k] += A[k][j] * la;
-                a_g[i][k] += db[j][k] * lg;
-                a_db[j][k] += g[i][k] * lg;
-                a_g[k][j] += db[i][k] * lg;
-                a_db[i][k] += g[k][j] * lg;
-                a_A[i][k] += -2.0 * alp * Am[k][j] * la;
-                a_Am[k][j] += -2.0 * alp * A[i][k] * la;
-            }
-            a_A[i][j] += -(2.0 / 3.0) * divb * la + alp * Kh * la;
-            a_divb += -(2.0 / 3.0) * A[i][j] * la - (2.0 / 3.0) * g[i][j] * lg;
-            a_alp += -(C.kc / 3.0) * g[i][j] * trA * la + (Kh * A[i][j] - 2.0 * AAm) * la;
-            a_g[i][j] += -(C.kc / 3.0) * alp * trA * la - (1.0 / 3.0) * chi * trX * la;
-            a_trA += -(C.kc / 3.0) * alp * g[i][j] * la;
-            a_chi += (X[i][j] - (1.0 / 3.0) * g[i][j] * trX) * la;
-            a_X[i][j] += chi * la;
-            a_trX += -(1.0 / 3.0) * chi * g[i][j] * la;
-            a_Kh += alp * A[i][j] * la;
-            // gt
-            a_g[i][j] += -(2.0 / 3.0) * divb * lg + (2.0 / 3.0) * alp * trA * lg - (C.kc / 3.0) * alp * lndet * lg;
-            a_alp += -2.0 * (A[i][j] - (1.0 / 3.0) * g[i][j] * trA) * lg - (C.kc / 3.0) * g[i][j] * lndet * lg;
-            a_A[i][j] += -2.0 * alp * lg;
-            a_trA += (2.0 / 3.0) * alp * g[i][j] * lg;
-            a_lndet += -(C.kc / 3.0) * alp * g[i][j] * lg;
-        }
-    // trX, X
-    for (int i = 0; i < 3; ++i)
+    // Ghat^i = S^i, B^i = S^i - eta B^i, beta^i = g B^i (the second
+    // derivatives of beta in S^i are reversed by the shift kernel)
+    double ab[3];
+    for (int i = 0; i < 3; ++i) {
+        q.Wq(W_U + BB + i) = C.g * q.L(BETA + i) - C.eta * q.L(BB + i);
+        const double aS = q.L(GH + i) + q.L(BB + i);
+        a_Gh[i] += (2.0 / 3.0) * divb * aS;
+        a_divb += (2.0 / 3.0) * Gh[i] * aS;
         for (int j = 0; j < 3; ++j) {
-            a_gu[i][j] += X[i][j] * a_trX;
-            a_X[i][j] += gu[i][j] * a_trX;
+            a_Gh[j] += -db[j][i] * aS;
+            a_db[j][i] += -Gh[j] * aS;
+            a_Au[SI(i, j)] += -2.0 * dalp[j] * aS;
+            a_dalp[j] += -2.0 * Au[SI(i, j)] * aS;
         }
-    for (int i = 0; i < 3; ++i)
+        ab[i] = 2.0 * alp * aS;
+    }
+    // 2 alpha (b1 + rG + b2)
+    for (int i = 0; i < 3; ++i) {
+        double b1 = 0.0, rG = 0.0;
+        for (int p = 0; p < 6; ++p) b1 += MU(p) * q.Wq(F_GUU + 6 * i + p) * Au[p];
         for (int j = 0; j < 3; ++j) {
-            a_alp += Ric[i][j] * a_X[i][j];
-            a_Ric[i][j] += alp * a_X[i][j];
-            a_DDa[i][j] += -a_X[i][j];
+            b1 += -1.5 * ic * Au[SI(i, j)] * dchi[j];
+            rG += -(2.0 / 3.0) * gu[SI(i, j)] * dKh[j] - gu[SI(i, j)] * ((1.0 / 3.0) * dTh[j] + Th / alp * dalp[j]);
         }
-    // Kt, Zda, divb, AA, trA, Au, Am
+        const double b2 = -Z[i] * ic * (C.kz + (2.0 / 3.0) * Kt);
+        a_alp += (b1 + rG + b2) * (q.L(GH + i) + q.L(BB + i)) * 2.0;
+    }
+    double a_dKh[3] = {}, a_dTh[3] = {};
+    for (int i = 0; i < 3; ++i) {
+        const double abi = ab[i];
+        for (int p = 0; p < 6; ++p) {
+            a_Au[p] += MU(p) * q.Wq(F_GUU + 6 * i + p) * abi;
+            q.Wq(H_AGUU + 6 * i + p) = MU(p) * Au[p] * abi;
+        }
+        for (int j = 0; j < 3; ++j) {
+            a_ic += -1.5 * Au[SI(i, j)] * dchi[j] * abi;
+            a_Au[SI(i, j)] += -1.5 * ic * dchi[j] * abi;
+            a_dchi[j] += -1.5 * ic * Au[SI(i, j)] * abi;
+            a_gu[SI(i, j)] += (-(2.0 / 3.0) * dKh[j] - (1.0 / 3.0) * dTh[j] - Th / alp * dalp[j]) * abi;
+            a_dKh[j] += -(2.0 / 3.0) * gu[SI(i, j)] * abi;
+            a_dTh[j] += -(1.0 / 3.0) * gu[SI(i, j)] * abi;
+            a_dalp[j] += -gu[SI(i, j)] * Th / alp * abi;
+            a_Th += -gu[SI(i, j)] * dalp[j] / alp * abi;
+            a_alp += gu[SI(i, j)] * Th * dalp[j] / (alp * alp) * abi;
+        }
+        a_Z[i] += -ic * (C.kz + (2.0 / 3.0) * Kt) * abi;
+        a_ic += -Z[i] * (C.kz + (2.0 / 3.0) * Kt) * abi;
+        a_Kt += -Z[i] * ic * (2.0 / 3.0) * abi;
+    }
     a_Kh += a_Kt;
     a_Th += 2.0 * a_Kt;
     for (int i = 0; i < 3; ++i) {
@@ -371,219 +472,340 @@ __global__ __launch_bounds__(256) void ccz4_adj_point_kernel(const PatchDev* __r
         a_dalp[i] += Z[i] * a_Zda;
         a_db[i][i] += a_divb;
     }
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-            a_A[i][j] += Au[i][j] * a_AA;
-            a_Au[i][j] += A[i][j] * a_AA;
+    // AA = At_ij At^ij; At^ij = Am gt^{-1}; Am = gt^{-1} At
+    double a_A[6];
+    for (int p = 0; p < 6; ++p) {
+        a_A[p] = MU(p) * Au[p] * a_AA;
+        a_Au[p] += MU(p) * A[p] * a_AA;
+    }
+    double a_Am[3][3] = {};
+    for (int p = 0; p < 6; ++p) {
+        const int i = PI_(p), j = PJ_(p);
+        for (int l = 0; l < 3; ++l) {
+            a_Am[i][l] += gu[SI(l, j)] * a_Au[p];
+            a_gu[SI(l, j)] += Am[i][l] * a_Au[p];
         }
-    for (int i = 0; i < 3; ++i) a_Am[i][i] += a_trA;
+    }
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j)
             for (int l = 0; l < 3; ++l) {
-                a_Am[i][l] += gu[l][j] * a_Au[i][j];
-                a_gu[l][j] += Am[i][l] * a_Au[i][j];
+                a_gu[SI(i, l)] += A[SI(l, j)] * a_Am[i][j];
+                a_A[SI(l, j)] += gu[SI(i, l)] * a_Am[i][j];
             }
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j)
-            for (int l = 0; l < 3; ++l) {
-                a_gu[i][l] += A[l][j] * a_Am[i][j];
-                a_A[l][j] += gu[i][l] * a_Am[i][j];
-            }
-    // lapa = chi gu.DDa, trRic = chi gu.Ric
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-            a_chi += gu[i][j] * (DDa[i][j] * a_lapa + Ric[i][j] * a_trRic);
-            a_gu[i][j] += chi * (DDa[i][j] * a_lapa + Ric[i][j] * a_trRic);
-            a_DDa[i][j] += chi * gu[i][j] * a_lapa;
-            a_Ric[i][j] += chi * gu[i][j] * a_trRic;
-        }
-    // gddb, gdiv
-    for (int i = 0; i < 3; ++i)
-        for (int k = 0; k < 3; ++k)
-            for (int l = 0; l < 3; ++l) {
-                a_gu[k][l] += ddb[i][k][l] * a_gddb[i];
-                a_ddb[i][k][l] += gu[k][l] * a_gddb[i];
-            }
-    for (int l = 0; l < 3; ++l)
-        for (int i = 0; i < 3; ++i) a_ddb[i][i][l] += a_gdiv[l];
-    // DDa
-    {
-        double a_cr = 0.0, a_hic = 0.0;
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) {
-                const double a = a_DDa[i][j];
-                a_dda[i][j] += a;
-                for (int k = 0; k < 3; ++k) {
-                    a_Gu[k][i][j] += -dalp[k] * a;
-                    a_dalp[k] += -Gu[k][i][j] * a;
-                }
-                a_hic += (dalp[i] * dchi[j] + dalp[j] * dchi[i] - g[i][j] * cr) * a;
-                a_dalp[i] += hic * dchi[j] * a;
-                a_dchi[j] += hic * dalp[i] * a;
-                a_dalp[j] += hic * dchi[i] * a;
-                a_dchi[i] += hic * dalp[j] * a;
-                a_g[i][j] += -hic * cr * a;
-                a_cr += -hic * g[i][j] * a;
-            }
-        for (int k = 0; k < 3; ++k)
-            for (int m = 0; m < 3; ++m) {
-                a_gu[k][m] += dalp[k] * dchi[m] * a_cr;
-                a_dalp[k] += gu[k][m] * dchi[m] * a_cr;
-                a_dchi[m] += gu[k][m] * dalp[k] * a_cr;
-            }
-        a_ic += 0.5 * a_hic;
+    // lapa = chi gt^{ij} D_iD_j alpha, trRic = chi gt^{ij} R_ij
+    for (int p = 0; p < 6; ++p) {
+        const double dda = q.Wq(F_DDA + p), ric = q.Wq(F_RIC + p);
+        a_chi += MU(p) * gu[p] * (dda * a_lapa + ric * a_trRic);
+        a_gu[p] += MU(p) * chi * (dda * a_lapa + ric * a_trRic);
+        q.Wq(H_ADDA + p) += MU(p) * chi * gu[p] * a_lapa;
+        q.Wq(H_ARIC + p) += MU(p) * chi * gu[p] * a_trRic;
+        q.Wq(H_AGU + p) += a_gu[p];
+        q.Wq(W_U + AT + p) += a_A[p];
     }
-    // Ric = Rh + Rchi (computed once per pair i <= j)
-    {
-        double a_trc = 0.0, a_Ghd = 0.0;
-        for (int i = 0; i < 3; ++i)
-            for (int j = i; j < 3; ++j) {
-                const double a = i == j ? a_Ric[i][i] : a_Ric[i][j] + a_Ric[j][i];
-                // Rchi
-                a_ic += (0.5 * ddc[i][j] - 0.5 * Gd[i][j] - 0.5 * ic * dchi[i] * dchi[j] + 4.0 * ic * zs[i][j] +
-                         0.5 * g[i][j] * (trc - Ghd)) * a;
-                a_ddc[i][j] += 0.5 * ic * a;
-                a_dchi[i] += -0.25 * ic * ic * dchi[j] * a;
-                a_dchi[j] += -0.25 * ic * ic * dchi[i] * a;
-                a_g[i][j] += 0.5 * ic * (trc - Ghd) * a;
-                a_trc += 0.5 * ic * g[i][j] * a;
-                a_Ghd += -0.5 * ic * g[i][j] * a;
-                const double aGd = -0.5 * ic * a, azs = 2.0 * ic * ic * a;
-                for (int k = 0; k < 3; ++k) {
-                    a_Gu[k][i][j] += dchi[k] * aGd;
-                    a_dchi[k] += Gu[k][i][j] * aGd;
-                    a_Z[k] += 0.5 * (g[k][i] * dchi[j] + g[k][j] * dchi[i]) * azs;
-                    a_g[k][i] += 0.5 * Z[k] * dchi[j] * azs;
-                    a_dchi[j] += 0.5 * Z[k] * g[k][i] * azs;
-                    a_g[k][j] += 0.5 * Z[k] * dchi[i] * azs;
-                    a_dchi[i] += 0.5 * Z[k] * g[k][j] * azs;
-                }
-                // Rh
-                a_lapg[SI(i, j)] += -0.5 * a;
-                for (int k = 0; k < 3; ++k) {
-                    a_g[k][i] += 0.5 * dGh[j][k] * a;
-                    a_dGh[j][k] += 0.5 * g[k][i] * a;
-                    a_g[k][j] += 0.5 * dGh[i][k] * a;
-                    a_dGh[i][k] += 0.5 * g[k][j] * a;
-                    a_Gh[k] += 0.5 * (Gl[i][j][k] + Gl[j][i][k]) * a;
-                    a_Gl[i][j][k] += 0.5 * Gh[k] * a;
-                    a_Gl[j][i][k] += 0.5 * Gh[k] * a;
-                }
-                for (int m = 0; m < 3; ++m)
-                    for (int n = 0; n < 3; ++n)
-                        for (int k = 0; k < 3; ++k) {
-                            a_gu[m][n] += (Gu[k][m][i] * Gl[j][k][n] + Gu[k][m][j] * Gl[i][k][n] + Gu[k][m][i] * Gl[k][n][j]) * a;
-                            a_Gu[k][m][i] += gu[m][n] * (Gl[j][k][n] + Gl[k][n][j]) * a;
-                            a_Gu[k][m][j] += gu[m][n] * Gl[i][k][n] * a;
-                            a_Gl[j][k][n] += gu[m][n] * Gu[k][m][i] * a;
-                            a_Gl[i][k][n] += gu[m][n] * Gu[k][m][j] * a;
-                            a_Gl[k][n][j] += gu[m][n] * Gu[k][m][i] * a;
-                        }
-            }
-        // lapg[q] = gt^{mn} d_m d_n gt_q: the second derivatives go to the
-        // workspace now (packed pairs), gt^{mn} collects the rest
-        for (int q = 0; q < 6; ++q)
-            for (int m = 0; m < 3; ++m)
-                for (int n = m; n < 3; ++n) {
-                    const double v = dd(GT + q, m, n);
-                    a_gu[m][n] += v * a_lapg[q];
-                    if (m != n) a_gu[n][m] += v * a_lapg[q];
-                    w[(int64_t)(W_D2 + 6 * d2_slot(GT + q) + SI(m, n)) * fs] = (m == n ? 1.0 : 2.0) * gu[m][n] * a_lapg[q];
-                }
-        for (int k = 0; k < 3; ++k)
-            for (int m = 0; m < 3; ++m) {
-                a_gu[k][m] += (ddc[k][m] - 1.5 * ic * dchi[k] * dchi[m]) * a_trc;
-                a_ddc[k][m] += gu[k][m] * a_trc;
-                a_ic += -1.5 * gu[k][m] * dchi[k] * dchi[m] * a_trc;
-                a_dchi[k] += -1.5 * ic * gu[k][m] * dchi[m] * a_trc;
-                a_dchi[m] += -1.5 * ic * gu[k][m] * dchi[k] * a_trc;
-            }
-        for (int k = 0; k < 3; ++k) {
-            a_Gh[k] += dchi[k] * a_Ghd;
-            a_dchi[k] += Gh[k] * a_Ghd;
-        }
-    }
-    // Z = chi (Ghat - Gc) / 2, Gc = gu.Gu
-    for (int i = 0; i < 3; ++i) {
-        a_chi += 0.5 * (Gh[i] - Gc[i]) * a_Z[i];
-        a_Gh[i] += 0.5 * chi * a_Z[i];
-        const double aGc = -0.5 * chi * a_Z[i];
-        for (int j = 0; j < 3; ++j)
-            for (int k = 0; k < 3; ++k) {
-                a_gu[j][k] += Gu[i][j][k] * aGc;
-                a_Gu[i][j][k] += gu[j][k] * aGc;
-            }
-    }
-    // Gu = gu Gl
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j)
-            for (int k = 0; k < 3; ++k)
-                for (int l = 0; l < 3; ++l) {
-                    a_gu[i][l] += Gl[l][j][k] * a_Gu[i][j][k];
-                    a_Gl[l][j][k] += gu[i][l] * a_Gu[i][j][k];
-                }
-    // Gl from dg
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j)
-            for (int k = 0; k < 3; ++k) {
-                a_dg[j][i][k] += 0.5 * a_Gl[i][j][k];
-                a_dg[k][i][j] += 0.5 * a_Gl[i][j][k];
-                a_dg[i][j][k] += -0.5 * a_Gl[i][j][k];
-            }
-    // lndet, gu = g^-1, ic = 1/chi
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-            double s = 0.0;
-            for (int a = 0; a < 3; ++a)
-                for (int b = 0; b < 3; ++b) s += gu[i][a] * a_gu[a][b] * gu[b][j];
-            a_g[i][j] += gu[i][j] * a_lndet - s;
-        }
     a_chi += -ic * ic * a_ic;
-
-    // advection: d/d beta^k of sum_f lam_f beta^k L_k u_f
-    double a_be[3] = {0.0, 0.0, 0.0};
-    for (int f = 0; f < NF; ++f) {
-        const double lf = lm[(int64_t)f * fs];
-        for (int k = 0; k < 3; ++k)
-            a_be[k] += lf * C.i12h * (C.upwind ? fadv(F(f), S[k], be[k]) : fd1(F(f), S[k]));
-    }
-
-    // ---- write Pbar(c) ----
-    auto put = [&](int q, double v) { w[(int64_t)q * fs] = v; };
-    auto sym = [&](const double (&a)[3][3], int i, int j) { return i == j ? a[i][i] : a[i][j] + a[j][i]; };
-    put(W_U + CHI, a_chi);
-    put(W_U + KH, a_Kh);
-    put(W_U + TH, a_Th);
-    put(W_U + ALP, a_alp);
-    for (int i = 0; i < 3; ++i)
-        for (int j = i; j < 3; ++j) {
-            put(W_U + GT + SI(i, j), sym(a_g, i, j));
-            put(W_U + AT + SI(i, j), sym(a_A, i, j));
-        }
+    q.Wq(W_U + CHI) += a_chi;
+    q.Wq(W_U + KH) += a_Kh;
+    q.Wq(W_U + ALP) += a_alp;
+    q.Wq(W_U + TH) = a_Th;
     for (int i = 0; i < 3; ++i) {
-        put(W_U + GH + i, a_Gh[i]);
-        put(W_U + BETA + i, a_be[i]);
-        put(W_U + BB + i, a_Bv[i]);
-    }
-    for (int k = 0; k < 3; ++k) {
-        for (int i = 0; i < 3; ++i)
-            for (int j = i; j < 3; ++j) put(W_D1 + 3 * d1_slot(GT + SI(i, j)) + k, sym(a_dg[k], i, j));
-        put(W_D1 + 3 * d1_slot(CHI) + k, a_dchi[k]);
-        put(W_D1 + 3 * d1_slot(ALP) + k, a_dalp[k]);
-        put(W_D1 + 3 * d1_slot(KH) + k, a_dKh[k]);
-        put(W_D1 + 3 * d1_slot(TH) + k, a_dTh[k]);
-        for (int i = 0; i < 3; ++i) {
-            put(W_D1 + 3 * d1_slot(GH + i) + k, a_dGh[k][i]);
-            put(W_D1 + 3 * d1_slot(BETA + i) + k, a_db[k][i]);
-        }
+        q.Wq(W_U + GH + i) = a_Gh[i];
+        q.Wq(H_AZ + i) = a_Z[i];
+        q.Wq(W_D1 + 3 * d1_slot(ALP) + i) = a_dalp[i];
+        q.Wq(W_D1 + 3 * d1_slot(CHI) + i) = a_dchi[i];
+        q.Wq(W_D1 + 3 * d1_slot(KH) + i) = a_dKh[i];
+        q.Wq(W_D1 + 3 * d1_slot(TH) + i) = a_dTh[i];
     }
     for (int k = 0; k < 3; ++k)
-        for (int l = k; l < 3; ++l) {
-            const int m = SI(k, l);
-            put(W_D2 + 6 * d2_slot(CHI) + m, sym(a_ddc, k, l));
-            put(W_D2 + 6 * d2_slot(ALP) + m, sym(a_dda, k, l));
-            for (int i = 0; i < 3; ++i) put(W_D2 + 6 * d2_slot(BETA + i) + m, sym(a_ddb[i], k, l));
+        for (int i = 0; i < 3; ++i) q.Wq(W_D1 + 3 * d1_slot(BETA + i) + k) += a_db[k][i];
+}
+
+// ------------------------------------------------------------ kernel K3b
+// Reverse of the second-derivative terms of the shift in S^i:
+// gt^{kl} d_k d_l beta^i + (1/3) gt^{ij} d_j d_k beta^k (first writer of the
+// second-derivative slots of beta).
+ADJ_KERNEL(ccz4_adj_shift_kernel)
+{
+    Pt q;
+    if (!pt_init(q, patches, tiles, Ug, lamg, W, wofs)) return;
+    double gu[6], aS[3], a_gu[6] = {};
+    for (int p = 0; p < 6; ++p) gu[p] = q.Wq(F_GU + p);
+    for (int i = 0; i < 3; ++i) aS[i] = q.L(GH + i) + q.L(BB + i);
+    for (int i = 0; i < 3; ++i)
+        for (int p = 0; p < 6; ++p) {
+            a_gu[p] += MU(p) * q.dd(C, BETA + i, PI_(p), PJ_(p)) * aS[i];
+            q.Wq(W_D2 + 6 * d2_slot(BETA + i) + p) = MU(p) * gu[p] * aS[i];
         }
+    // gdiv[l] = d_l d_m beta^m enters S^i as (1/3) gt^{il} gdiv[l]
+    for (int l = 0; l < 3; ++l) {
+        double gdiv = 0.0, a = 0.0;
+        for (int m = 0; m < 3; ++m) gdiv += q.dd(C, BETA + m, m, l);
+        for (int i = 0; i < 3; ++i) {
+            a_gu[SI(i, l)] += (1.0 / 3.0) * gdiv * aS[i];
+            a += (1.0 / 3.0) * gu[SI(i, l)] * aS[i];
+        }
+        for (int m = 0; m < 3; ++m) q.Wq(W_D2 + 6 * d2_slot(BETA + m) + SI(m, l)) += a;
+    }
+    for (int p = 0; p < 6; ++p) q.Wq(H_AGU + p) += a_gu[p];
+}
+
+// ------------------------------------------------------------ kernel K4
+// Reverse of D_iD_j alpha and of the chi part of the Ricci tensor
+// (R^chi_ij, with the traces trc and Ghd).
+ADJ_KERNEL(ccz4_adj_chi_kernel)
+{
+    Pt q;
+    if (!pt_init(q, patches, tiles, Ug, lamg, W, wofs)) return;
+    double g[6], gu[6], aR[6], aD[6];
+    for (int p = 0; p < 6; ++p) {
+        g[p] = q.U(GT + p);
+        gu[p] = q.Wq(F_GU + p);
+        aR[p] = q.Wq(H_ARIC + p);
+        aD[p] = q.Wq(H_ADDA + p);
+    }
+    const double chi = q.U(CHI), ic = 1.0 / chi, hic = 0.5 * ic;
+    double Gh[3], Z[3], dchi[3], dalp[3];
+    for (int i = 0; i < 3; ++i) {
+        Gh[i] = q.U(GH + i);
+        Z[i] = q.Wq(F_Z + i);
+        dchi[i] = q.d1(C, CHI, i);
+        dalp[i] = q.d1(C, ALP, i);
+    }
+    double ddc[6], trc = 0.0, Ghd = 0.0, cr = 0.0;
+    for (int p = 0; p < 6; ++p) {
+        const int i = PI_(p), j = PJ_(p);
+        ddc[p] = q.dd(C, CHI, i, j);
+        trc += MU(p) * gu[p] * (ddc[p] - 1.5 * ic * dchi[i] * dchi[j]);
+        cr += gu[p] * (i == j ? dalp[i] * dchi[j] : dalp[i] * dchi[j] + dalp[j] * dchi[i]);
+    }
+    for (int k = 0; k < 3; ++k) Ghd += Gh[k] * dchi[k];
+    double a_g[6] = {}, a_gu[6] = {}, a_dchi[3] = {}, a_dalp[3] = {}, a_Z[3] = {};
+    double a_ic = 0.0, a_hic = 0.0, a_cr = 0.0, a_trc = 0.0, a_Ghd = 0.0;
+    for (int p = 0; p < 6; ++p) {
+        const int i = PI_(p), j = PJ_(p);
+        // D_iD_j alpha = dd alpha - Gamma^k_ij d_k alpha + (1/2chi)(d_i alpha d_j chi + d_j alpha d_i chi - gt_ij cr)
+        const double a = aD[p];
+        q.Wq(W_D2 + 6 * d2_slot(ALP) + p) = a;
+        double Gd = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            const double Gkp = q.Wq(F_GUU + 6 * k + p);
+            Gd += Gkp * dchi[k];
+            a_dalp[k] += -Gkp * a;
+        }
+        a_hic += (dalp[i] * dchi[j] + dalp[j] * dchi[i] - g[p] * cr) * a;
+        a_dalp[i] += hic * dchi[j] * a;
+        a_dchi[j] += hic * dalp[i] * a;
+        a_dalp[j] += hic * dchi[i] * a;
+        a_dchi[i] += hic * dalp[j] * a;
+        a_g[p] += -hic * cr * a;
+        a_cr += -hic * g[p] * a;
+        // R^chi_ij
+        const double r = aR[p];
+        double zs = 0.0;
+        for (int k = 0; k < 3; ++k) zs += Z[k] * 0.5 * (g[SI(k, i)] * dchi[j] + g[SI(k, j)] * dchi[i]);
+        a_ic += (0.5 * ddc[p] - 0.5 * Gd - 0.5 * ic * dchi[i] * dchi[j] + 4.0 * ic * zs + 0.5 * g[p] * (trc - Ghd)) * r;
+        a_dchi[i] += -0.25 * ic * ic * dchi[j] * r;
+        a_dchi[j] += -0.25 * ic * ic * dchi[i] * r;
+        a_g[p] += 0.5 * ic * (trc - Ghd) * r;
+        a_trc += 0.5 * ic * g[p] * r;
+        a_Ghd += -0.5 * ic * g[p] * r;
+        const double aGd = -0.5 * ic * r, azs = 2.0 * ic * ic * r;
+        for (int k = 0; k < 3; ++k) {
+            const double Gkp = q.Wq(F_GUU + 6 * k + p);
+            // Gamma^k_ij enters D_iD_j alpha (-d_k alpha) and Gd (d_k chi)
+            q.Wq(H_AGUU + 6 * k + p) += -dalp[k] * a + dchi[k] * aGd;
+            a_dchi[k] += Gkp * aGd;
+            a_Z[k] += 0.5 * (g[SI(k, i)] * dchi[j] + g[SI(k, j)] * dchi[i]) * azs;
+            a_g[SI(k, i)] += 0.5 * Z[k] * dchi[j] * azs;
+            a_dchi[j] += 0.5 * Z[k] * g[SI(k, i)] * azs;
+            a_g[SI(k, j)] += 0.5 * Z[k] * dchi[i] * azs;
+            a_dchi[i] += 0.5 * Z[k] * g[SI(k, j)] * azs;
+        }
+    }
+    // cr = gt^{km} d_k alpha d_m chi
+    for (int p = 0; p < 6; ++p) {
+        const int k = PI_(p), m = PJ_(p);
+        a_gu[p] += (k == m ? dalp[k] * dchi[m] : dalp[k] * dchi[m] + dalp[m] * dchi[k]) * a_cr;
+    }
+    for (int k = 0; k < 3; ++k)
+        for (int m = 0; m < 3; ++m) {
+            a_dalp[k] += gu[SI(k, m)] * dchi[m] * a_cr;
+            a_dchi[m] += gu[SI(k, m)] * dalp[k] * a_cr;
+        }
+    a_ic += 0.5 * a_hic;
+    // trc = gt^{km} (dd chi_km - 3/2 d_k chi d_m chi / chi); Ghd = Ghat^k d_k chi
+    for (int p = 0; p < 6; ++p) {
+        const int k = PI_(p), m = PJ_(p);
+        a_gu[p] += MU(p) * (ddc[p] - 1.5 * ic * dchi[k] * dchi[m]) * a_trc;
+        q.Wq(W_D2 + 6 * d2_slot(CHI) + p) = 0.5 * ic * aR[p] + MU(p) * gu[p] * a_trc;
+        a_ic += -1.5 * MU(p) * gu[p] * dchi[k] * dchi[m] * a_trc;
+        a_dchi[k] += -1.5 * ic * MU(p) * gu[p] * dchi[m] * a_trc;
+        a_dchi[m] += -1.5 * ic * MU(p) * gu[p] * dchi[k] * a_trc;
+    }
+    for (int k = 0; k < 3; ++k) {
+        q.Wq(W_U + GH + k) += dchi[k] * a_Ghd;
+        a_dchi[k] += Gh[k] * a_Ghd;
+    }
+    for (int p = 0; p < 6; ++p) {
+        q.Wq(W_U + GT + p) += a_g[p];
+        q.Wq(H_AGU + p) += a_gu[p];
+    }
+    q.Wq(W_U + CHI) += -ic * ic * a_ic;
+    for (int i = 0; i < 3; ++i) {
+        q.Wq(W_D1 + 3 * d1_slot(ALP) + i) += a_dalp[i];
+        q.Wq(W_D1 + 3 * d1_slot(CHI) + i) += a_dchi[i];
+        q.Wq(H_AZ + i) += a_Z[i];
+    }
+}
+
+// ------------------------------------------------------------ kernel K5
+// Reverse of the conformal Ricci tensor Rt_ij: -1/2 gt^{mn} d_m d_n gt_ij,
+// gt_k(i d_j) Ghat^k, Ghat^k Gamma_(ij)k and the Gamma-Gamma products.
+ADJ_KERNEL(ccz4_adj_ricci_kernel)
+{
+    Pt q;
+    if (!pt_init(q, patches, tiles, Ug, lamg, W, wofs)) return;
+    double gu[6], aR[6], Gl[3][6], Gu[3][6];
+    for (int p = 0; p < 6; ++p) {
+        gu[p] = q.Wq(F_GU + p);
+        aR[p] = q.Wq(H_ARIC + p);
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int p = 0; p < 6; ++p) {
+            Gl[i][p] = q.Wq(F_GL + 6 * i + p);
+            Gu[i][p] = q.Wq(F_GUU + 6 * i + p);
+        }
+    double a_gu[6] = {}, a_Gl[3][6] = {}, a_Gu[3][6] = {};
+    {
+        // Q_i^{kn} = gt^{mn} Gamma^k_{mi}; T_ij = sum_kn Q_i^{kn} (Gamma_jkn + Gamma_knj) + Q_j^{kn} Gamma_ikn
+        double Q[3][3][3], aQ[3][3][3] = {};
+        for (int i = 0; i < 3; ++i)
+            for (int k = 0; k < 3; ++k)
+                for (int n = 0; n < 3; ++n)
+                    Q[i][k][n] = gu[SI(0, n)] * Gu[k][SI(0, i)] + gu[SI(1, n)] * Gu[k][SI(1, i)] + gu[SI(2, n)] * Gu[k][SI(2, i)];
+        for (int p = 0; p < 6; ++p) {
+            const int i = PI_(p), j = PJ_(p);
+            const double a = aR[p];
+            for (int k = 0; k < 3; ++k)
+                for (int n = 0; n < 3; ++n) {
+                    aQ[i][k][n] += (Gl[j][SI(k, n)] + Gl[k][SI(n, j)]) * a;
+                    aQ[j][k][n] += Gl[i][SI(k, n)] * a;
+                    a_Gl[j][SI(k, n)] += Q[i][k][n] * a;
+                    a_Gl[k][SI(n, j)] += Q[i][k][n] * a;
+                    a_Gl[i][SI(k, n)] += Q[j][k][n] * a;
+                }
+        }
+        for (int i = 0; i < 3; ++i)
+            for (int k = 0; k < 3; ++k)
+                for (int n = 0; n < 3; ++n)
+                    for (int m = 0; m < 3; ++m) {
+                        a_gu[SI(m, n)] += Gu[k][SI(m, i)] * aQ[i][k][n];
+                        a_Gu[k][SI(m, i)] += gu[SI(m, n)] * aQ[i][k][n];
+                    }
+    }
+    // Ghat^k Gamma_(ij)k; gt_k(i d_j) Ghat^k
+    double a_g[6] = {}, a_Gh[3] = {}, Gh[3], g[6];
+    for (int k = 0; k < 3; ++k) Gh[k] = q.U(GH + k);
+    for (int p = 0; p < 6; ++p) g[p] = q.U(GT + p);
+    double a_dGh[3][3] = {};  // [j][k] = adjoint of d_j Ghat^k
+    for (int p = 0; p < 6; ++p) {
+        const int i = PI_(p), j = PJ_(p);
+        const double a = aR[p];
+        for (int k = 0; k < 3; ++k) {
+            a_g[SI(k, i)] += 0.5 * q.Wq(F_DGH + 3 * j + k) * a;
+            a_dGh[j][k] += 0.5 * g[SI(k, i)] * a;
+            a_g[SI(k, j)] += 0.5 * q.Wq(F_DGH + 3 * i + k) * a;
+            a_dGh[i][k] += 0.5 * g[SI(k, j)] * a;
+            a_Gh[k] += 0.5 * (Gl[i][SI(j, k)] + Gl[j][SI(i, k)]) * a;
+            a_Gl[i][SI(j, k)] += 0.5 * Gh[k] * a;
+            a_Gl[j][SI(i, k)] += 0.5 * Gh[k] * a;
+        }
+    }
+    // -1/2 gt^{mn} d_m d_n gt_ij: the second derivatives of gt are written here
+    for (int p = 0; p < 6; ++p) {
+        const double al = -0.5 * aR[p];
+        for (int m = 0; m < 6; ++m) {
+            a_gu[m] += MU(m) * q.Wq(F_DDG + 6 * p + m) * al;
+            q.Wq(W_D2 + 6 * d2_slot(GT + p) + m) = MU(m) * gu[m] * al;
+        }
+    }
+    for (int p = 0; p < 6; ++p) {
+        q.Wq(W_U + GT + p) += a_g[p];
+        q.Wq(H_AGU + p) += a_gu[p];
+    }
+    for (int i = 0; i < 3; ++i) {
+        q.Wq(W_U + GH + i) += a_Gh[i];
+        for (int k = 0; k < 3; ++k) q.Wq(W_D1 + 3 * d1_slot(GH + k) + i) = a_dGh[i][k];
+        for (int p = 0; p < 6; ++p) {
+            q.Wq(H_AGUU + 6 * i + p) += a_Gu[i][p];
+            q.Wq(H_AGL + 6 * i + p) = a_Gl[i][p];
+        }
+    }
+}
+
+// ------------------------------------------------------------ kernel K6
+// Chain to the stencil inputs: Z = chi (Ghat - gt^{jk} Gamma^i_jk)/2,
+// Gamma^i_jk = gt^{il} Gamma_ljk, Gamma_ijk from d gt, gt^{ij} = inverse of gt_ij.
+ADJ_KERNEL(ccz4_adj_chain_kernel)
+{
+    Pt q;
+    if (!pt_init(q, patches, tiles, Ug, lamg, W, wofs)) return;
+    double gu[6], a_gu[6], a_Gu[3][6], a_Gl[3][6];
+    for (int p = 0; p < 6; ++p) {
+        gu[p] = q.Wq(F_GU + p);
+        a_gu[p] = q.Wq(H_AGU + p);
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int p = 0; p < 6; ++p) {
+            a_Gu[i][p] = q.Wq(H_AGUU + 6 * i + p);
+            a_Gl[i][p] = q.Wq(H_AGL + 6 * i + p);
+        }
+    const double chi = q.U(CHI);
+    double a_chi = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        const double aZ = q.Wq(H_AZ + i);
+        double Gc = 0.0;
+        for (int p = 0; p < 6; ++p) Gc += MU(p) * gu[p] * q.Wq(F_GUU + 6 * i + p);
+        a_chi += 0.5 * (q.U(GH + i) - Gc) * aZ;
+        q.Wq(W_U + GH + i) += 0.5 * chi * aZ;
+        const double aGc = -0.5 * chi * aZ;
+        for (int p = 0; p < 6; ++p) {
+            a_gu[p] += MU(p) * q.Wq(F_GUU + 6 * i + p) * aGc;
+            a_Gu[i][p] += MU(p) * gu[p] * aGc;
+        }
+    }
+    q.Wq(W_U + CHI) += a_chi;
+    // Gamma^i_p = sum_l gt^{il} Gamma_l p
+    for (int i = 0; i < 3; ++i)
+        for (int p = 0; p < 6; ++p)
+            for (int l = 0; l < 3; ++l) {
+                a_gu[SI(i, l)] += q.Wq(F_GL + 6 * l + p) * a_Gu[i][p];
+                a_Gl[l][p] += gu[SI(i, l)] * a_Gu[i][p];
+            }
+    // Gamma_i(jk) = (d_j gt_ik + d_k gt_ij - d_i gt_jk)/2
+    double a_dg[3][6] = {};
+    for (int i = 0; i < 3; ++i)
+        for (int p = 0; p < 6; ++p) {
+            const int j = PI_(p), k = PJ_(p);
+            const double a = 0.5 * a_Gl[i][p];
+            a_dg[j][SI(i, k)] += a;
+            a_dg[k][SI(i, j)] += a;
+            a_dg[i][p] -= a;
+        }
+    for (int k = 0; k < 3; ++k)
+        for (int p = 0; p < 6; ++p) q.Wq(W_D1 + 3 * d1_slot(GT + p) + k) = a_dg[k][p];
+    // gt^{-1}: a(gt) = -gt^{-1} a(gt^{-1}) gt^{-1} on the full symmetric adjoint
+    double Af[3][3];
+    for (int p = 0; p < 6; ++p) {
+        const double v = MU(p) == 1.0 ? a_gu[p] : 0.5 * a_gu[p];
+        Af[PI_(p)][PJ_(p)] = Af[PJ_(p)][PI_(p)] = v;
+    }
+    for (int p = 0; p < 6; ++p) {
+        const int i = PI_(p), j = PJ_(p);
+        double s = 0.0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) s += gu[SI(i, a)] * Af[a][b] * gu[SI(b, j)];
+        q.Wq(W_U + GT + p) += -MU(p) * s;
+    }
 }
 
 // ---------------------------------------------------------------- kernel 2
@@ -595,7 +817,7 @@ __global__ __launch_bounds__(256) void ccz4_adj_gather_kernel(const PatchDev* __
                                                               const int64_t* __restrict__ wofs, AdjConst C,
                                                               double* __restrict__ lamU)
 {
-    const Tile t = tiles[blockIdx.x];
+    const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     const PatchDev P = patches[t.patch];
     const int q[3] = {t.o[0] + (int)threadIdx.x, t.o[1] + (int)threadIdx.y, t.o[2] + (int)threadIdx.z};
     if (q[0] >= P.n[0] + G || q[1] >= P.n[1] + G || q[2] >= P.n[2] + G) return;
@@ -659,7 +881,7 @@ __global__ __launch_bounds__(256) void ccz4_adj_gather_kernel(const PatchDev* __
 
 }  // namespace
 
-int ccz4_adjoint_slots() { return NW; }
+int ccz4_adjoint_slots() { return NWX; }
 
 hipError_t launch_ccz4_adjoint(const SysParams& sp, const PatchDev* patches, const Tile* tiles, int ntiles,
                                const int td[3], const Tile* gtiles, int ngtiles, const int gtd[3],
@@ -679,7 +901,17 @@ hipError_t launch_ccz4_adjoint(const SysParams& sp, const PatchDev* patches, con
     C.eta = sp.gd_eta;
     C.upwind = sp.upwind;
     if (ntiles > 0) {
-        ccz4_adj_point_kernel<<<ntiles, dim3(td[0], td[1], td[2]), 0, s>>>(patches, tiles, ntiles, U, lam, W, wofs, C);
+        // every pointwise kernel covers the same interior points; each writes
+        // or accumulates only the workspace slots listed in its comment
+        const dim3 b(td[0], td[1], td[2]);
+        ccz4_adj_advection_kernel<<<ntiles, b, 0, s>>>(patches, tiles, U, lam, W, wofs, C);
+        ccz4_adj_forward_kernel<<<ntiles, b, 0, s>>>(patches, tiles, U, lam, W, wofs, C);
+        ccz4_adj_metric_kernel<<<ntiles, b, 0, s>>>(patches, tiles, U, lam, W, wofs, C);
+        ccz4_adj_gauge_kernel<<<ntiles, b, 0, s>>>(patches, tiles, U, lam, W, wofs, C);
+        ccz4_adj_shift_kernel<<<ntiles, b, 0, s>>>(patches, tiles, U, lam, W, wofs, C);
+        ccz4_adj_chi_kernel<<<ntiles, b, 0, s>>>(patches, tiles, U, lam, W, wofs, C);
+        ccz4_adj_ricci_kernel<<<ntiles, b, 0, s>>>(patches, tiles, U, lam, W, wofs, C);
+        ccz4_adj_chain_kernel<<<ntiles, b, 0, s>>>(patches, tiles, U, lam, W, wofs, C);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
