@@ -42,6 +42,9 @@ typedef struct {
     double gd_g;       /* Gamma-driver g */
     double gd_eta;     /* Gamma-driver eta */
     double upwind;     /* 1: lop-sided advection stencils; 0: centred */
+    /* MHD variants (Sec. II.B.2, App. A, App. B) */
+    double mhd_recon;  /* 0: WENO5-Z, 1: WENO5-JS, 2: WENO3 */
+    double mhd_riemann; /* 0: local Lax-Friedrichs (eq. LLF), 1: HLL */
 } orc_params;
 
 enum { ORC_WAVE = 0, ORC_MHD = 1, ORC_CCZ4 = 2 };
@@ -75,6 +78,14 @@ double orc_weno5z_left(const double* u, double eps, double q);
 double orc_weno5z_right(const double* u, double eps, double q);
 /* WENO5-JS variants (App. B, generic weights of Sec. II.B.2) */
 double orc_weno5js_left(const double* u, double eps);
+double orc_weno5js_right(const double* u, double eps);
+/* WENO3 (App. A): U^L_{i+1/2} from u[-1..1] and U^R_{i-1/2} from u[-1..1] */
+double orc_weno3_left(const double* u, double eps);
+double orc_weno3_right(const double* u, double eps);
+/* Interface flux between the reconstructed states UL, UR (8 fields) along
+ * axis d: LLF (riemann 0) or HLL (riemann 1) */
+void orc_mhd_interface_flux(const double UL[8], const double UR[8], int d, double gam, int riemann,
+                            double F[8]);
 
 /* ---- explicit Runge-Kutta (eq. eRK) on one periodic patch ---- */
 /* nsteps full steps with periodic ghost fill before every stage. */

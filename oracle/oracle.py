@@ -24,7 +24,12 @@ NFIELDS = {WAVE: 2, MHD: 8, CCZ4: 25}
 class Params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in (
         "sigma", "gamma_ad", "weno_eps", "weno_q", "kappa_z", "kappa_c",
-        "bm_f0", "bm_f1", "gd_g", "gd_eta", "upwind")]
+        "bm_f0", "bm_f1", "gd_g", "gd_eta", "upwind", "mhd_recon", "mhd_riemann")]
+
+
+# MHD variants: reconstruction (App. A/B) and interface flux (Sec. II.B.2)
+RECON_WENO5Z, RECON_WENO5JS, RECON_WENO3 = 0, 1, 2
+FLUX_LLF, FLUX_HLL = 0, 1
 
 
 # time refinement of the sub-cycled step (Sec. III.B)
@@ -34,7 +39,7 @@ TIME_BOR, TIME_BO, TIME_BO1, TIME_NOSUB = 0, 1, 2, 3
 def params(**kw) -> Params:
     d = dict(sigma=0.1, gamma_ad=5.0 / 3.0, weno_eps=-1.0, weno_q=2.0,
              kappa_z=0.1, kappa_c=0.1, bm_f0=0.0, bm_f1=2.0, gd_g=0.75,
-             gd_eta=2.0, upwind=1.0)
+             gd_eta=2.0, upwind=1.0, mhd_recon=0.0, mhd_riemann=0.0)
     d.update(kw)
     return Params(**d)
 
@@ -75,8 +80,10 @@ def lib():
         for name in ("orc_weno5z_left", "orc_weno5z_right"):
             getattr(L, name).argtypes = [dp, d, d]
             getattr(L, name).restype = d
-        L.orc_weno5js_left.argtypes = [dp, d]
-        L.orc_weno5js_left.restype = d
+        for name in ("orc_weno5js_left", "orc_weno5js_right", "orc_weno3_left", "orc_weno3_right"):
+            getattr(L, name).argtypes = [dp, d]
+            getattr(L, name).restype = d
+        L.orc_mhd_interface_flux.argtypes = [dp, dp, i, d, i, dp]
         L.orc_rk_run.argtypes = [i, i, dp, i, i, i, dp, d, i, P]
         L.orc_rk_scalar.argtypes = [i, d, d, dp, dp]
         L.orc_dense_rk4.argtypes = [i, i, d]
@@ -169,7 +176,22 @@ def weno(kind: str, u5: np.ndarray, eps: float, q: float = 2.0) -> float:
         return lib().orc_weno5z_left(ptr, eps, q)
     if kind == "zR":
         return lib().orc_weno5z_right(ptr, eps, q)
+    if kind == "jsR":
+        return lib().orc_weno5js_right(ptr, eps)
+    if kind == "3L":
+        return lib().orc_weno3_left(ptr, eps)
+    if kind == "3R":
+        return lib().orc_weno3_right(ptr, eps)
     return lib().orc_weno5js_left(ptr, eps)
+
+
+def mhd_interface_flux(UL, UR, d: int, gam: float, riemann: int) -> np.ndarray:
+    """Interface flux between reconstructed states (8 conserved fields)."""
+    UL = np.ascontiguousarray(UL, dtype=np.float64)
+    UR = np.ascontiguousarray(UR, dtype=np.float64)
+    F = np.zeros(8)
+    lib().orc_mhd_interface_flux(_p(UL), _p(UR), d, gam, riemann, _p(F))
+    return F
 
 
 def dense_rk4(j: int, m: int, theta: float) -> float:

@@ -1,8 +1,9 @@
 /*
  * Oracle: Newtonian ideal MHD right-hand side (Sec. IV.B) with the
  * conservative finite-difference form (eq. conservative_discretization),
- * WENO5-Z reconstruction of the evolved fields (Sec. II.B.2, App. B) and the
- * local Lax-Friedrichs flux (eq. LLF).  TEST INFRASTRUCTURE ONLY.
+ * reconstruction of the evolved fields by WENO5-Z (default), WENO5-JS
+ * (App. B) or WENO3 (App. A), and the local Lax-Friedrichs flux (eq. LLF,
+ * default) or the HLL flux (Sec. II.B.2).  TEST INFRASTRUCTURE ONLY.
  *
  * Conserved fields, in this order: rho, S_x, S_y, S_z, E, B^x, B^y, B^z
  * (the eight-field ideal core: the cleaning scalar psi is identically zero).
@@ -14,7 +15,14 @@
  *    the fast magnetosonic speed c_f^2 = ((a^2+b^2) + sqrt((a^2+b^2)^2 - 4 a^2 b_d^2))/2,
  *    a^2 = Gamma p / rho, b^2 = B^2/rho, b_d^2 = B_d^2/rho (units where the
  *    magnetic pressure is B^2/2, as in the paper's energy density);
- *  - S is taken per interface.
+ *  - S is taken per interface;
+ *  - HLL: the printed formula misses a "+" before S^R S^L (U^R - U^L); the
+ *    speeds are S^L = min(v_d - c_f) and S^R = max(v_d + c_f) over the two
+ *    states, clamped to S^L <= 0 <= S^R, which gives the textbook flux (F^L
+ *    when every wave moves right, F^R when every wave moves left) in one
+ *    formula;
+ *  - epsilon: dx^4 for the fifth-order reconstructions (App. B), dx^2 for
+ *    WENO3 (App. A), unless set.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -116,8 +124,40 @@ double orc_weno5js_left(const double* u, double eps)
     return out;
 }
 
-/* Physical flux along direction d and the largest signal speed |v_d| + c_f. */
-static void mhd_flux(const double U[8], int d, double gam, double F[8], double* speed)
+double orc_weno5js_right(const double* u, double eps)
+{
+    double v[3], b[3], a[3], sum = 0.0, out = 0.0;
+    double dt[3] = {D3[2], D3[1], D3[0]}; /* tilde d_r = d_{k-1-r} */
+    cand_right(u, v);
+    beta_right(u, b);
+    for (int r = 0; r < 3; ++r) { a[r] = dt[r] / sq(eps + b[r]); sum += a[r]; }
+    for (int r = 0; r < 3; ++r) out += (a[r] / sum) * v[r];
+    return out;
+}
+
+/* WENO3 (App. A): the two candidates, smoothness indicators and weights as
+ * printed, omega_r = alpha_r / sum_s alpha_s; u points at U_i. */
+double orc_weno3_left(const double* u, double eps)
+{
+    double v[2] = {0.5 * u[0] + 0.5 * u[1], -0.5 * u[-1] + 1.5 * u[0]};
+    double b[2] = {sq(u[1] - u[0]), sq(u[0] - u[-1])};
+    double a[2] = {(2.0 / 3.0) / sq(eps + b[0]), (1.0 / 3.0) / sq(eps + b[1])};
+    double sum = a[0] + a[1];
+    return (a[0] / sum) * v[0] + (a[1] / sum) * v[1];
+}
+
+double orc_weno3_right(const double* u, double eps)
+{
+    double v[2] = {-0.5 * u[1] + 1.5 * u[0], 0.5 * u[0] + 0.5 * u[-1]};
+    double b[2] = {sq(u[0] - u[1]), sq(u[-1] - u[0])};
+    double a[2] = {(1.0 / 3.0) / sq(eps + b[0]), (2.0 / 3.0) / sq(eps + b[1])};
+    double sum = a[0] + a[1];
+    return (a[0] / sum) * v[0] + (a[1] / sum) * v[1];
+}
+
+/* Physical flux along direction d, the normal velocity v_d and the fast
+ * magnetosonic speed c_f. */
+static void mhd_flux_vc(const double U[8], int d, double gam, double F[8], double* vd, double* cf)
 {
     double rho = U[0];
     double v[3] = {U[1] / rho, U[2] / rho, U[3] / rho};
@@ -136,7 +176,28 @@ static void mhd_flux(const double U[8], int d, double gam, double F[8], double* 
     double a2 = gam * p / rho, b2 = B2 / rho, bd2 = B[d] * B[d] / rho;
     double s = a2 + b2;
     double cf2 = 0.5 * (s + sqrt(s * s - 4.0 * a2 * bd2));
-    *speed = fabs(v[d]) + sqrt(cf2);
+    *vd = v[d];
+    *cf = sqrt(cf2);
+}
+
+void orc_mhd_interface_flux(const double UL[8], const double UR[8], int d, double gam, int riemann,
+                            double F[8])
+{
+    double FL[8], FR[8], vL, cL, vR, cR;
+    mhd_flux_vc(UL, d, gam, FL, &vL, &cL);
+    mhd_flux_vc(UR, d, gam, FR, &vR, &cR);
+    if (riemann == 1) {
+        /* HLL: F = (S^R F^L - S^L F^R + S^R S^L (U^R - U^L)) / (S^R - S^L) */
+        double SL = fmin(vL - cL, vR - cR), SR = fmax(vL + cL, vR + cR);
+        SL = fmin(SL, 0.0);
+        SR = fmax(SR, 0.0);
+        for (int f = 0; f < 8; ++f) F[f] = (SR * FL[f] - SL * FR[f] + SR * SL * (UR[f] - UL[f])) / (SR - SL);
+    } else {
+        /* LLF with S = max over the two states of |v_d| + c_f */
+        double sL = fabs(vL) + cL, sR = fabs(vR) + cR;
+        double S = sL > sR ? sL : sR;
+        for (int f = 0; f < 8; ++f) F[f] = 0.5 * (FL[f] + FR[f] - S * (UR[f] - UL[f]));
+    }
 }
 
 void orc_mhd_rhs(const double* U, double* R, int nx, int ny, int nz,
@@ -150,8 +211,9 @@ void orc_mhd_rhs(const double* U, double* R, int nx, int ny, int nz,
         for (int j = ORC_G; j < ny + ORC_G; ++j)
             for (int i = ORC_G; i < nx + ORC_G; ++i)
                 for (int f = 0; f < 8; ++f) R[f * vol + (k * NY + j) * NX + i] = 0.0;
+    const int recon = (int)p->mhd_recon, riemann = (int)p->mhd_riemann;
     for (int d = 0; d < 3; ++d) {
-        double eps = p->weno_eps > 0.0 ? p->weno_eps : h[d] * h[d] * h[d] * h[d];
+        double eps = p->weno_eps > 0.0 ? p->weno_eps : (recon == 2 ? h[d] * h[d] : h[d] * h[d] * h[d] * h[d]);
         /* every interface i+1/2 with i = -1 .. n_d - 1 along d (interior coords) */
         int lo[3] = {ORC_G, ORC_G, ORC_G}, hi[3] = {nx + ORC_G, ny + ORC_G, nz + ORC_G};
         lo[d] = ORC_G - 1;
@@ -160,20 +222,27 @@ void orc_mhd_rhs(const double* U, double* R, int nx, int ny, int nz,
             for (int j = lo[1]; j < hi[1]; ++j)
                 for (int i = lo[0]; i < hi[0]; ++i) {
                     long c = (k * NY + j) * NX + i;
-                    double UL[8], UR[8], FL[8], FR[8], sL, sR;
+                    double UL[8], UR[8], Fi[8];
                     for (int f = 0; f < 8; ++f) {
                         double line[6];
                         for (int m = 0; m < 6; ++m) line[m] = U[f * vol + c + (m - 2) * st[d]];
-                        /* line[2] is U_i; left state from cells i-2..i+2, right
-                         * state at i+1/2 is the right state at (i+1)-1/2 */
-                        UL[f] = orc_weno5z_left(line + 2, eps, p->weno_q);
-                        UR[f] = orc_weno5z_right(line + 3, eps, p->weno_q);
+                        /* line[2] is U_i; the left state at i+1/2 is
+                         * reconstructed around cell i, the right state at
+                         * i+1/2 is the right state at (i+1)-1/2 of cell i+1 */
+                        if (recon == 2) {
+                            UL[f] = orc_weno3_left(line + 2, eps);
+                            UR[f] = orc_weno3_right(line + 3, eps);
+                        } else if (recon == 1) {
+                            UL[f] = orc_weno5js_left(line + 2, eps);
+                            UR[f] = orc_weno5js_right(line + 3, eps);
+                        } else {
+                            UL[f] = orc_weno5z_left(line + 2, eps, p->weno_q);
+                            UR[f] = orc_weno5z_right(line + 3, eps, p->weno_q);
+                        }
                     }
-                    mhd_flux(UL, d, p->gamma_ad, FL, &sL);
-                    mhd_flux(UR, d, p->gamma_ad, FR, &sR);
-                    double S = sL > sR ? sL : sR;
+                    orc_mhd_interface_flux(UL, UR, d, p->gamma_ad, riemann, Fi);
                     for (int f = 0; f < 8; ++f) {
-                        double Fh = 0.5 * (FL[f] + FR[f] - S * (UR[f] - UL[f]));
+                        double Fh = Fi[f];
                         /* interface i+1/2 closes cell i (if interior) on the right
                          * and opens cell i+1 (if interior) on the left */
                         int ii[3] = {i, j, k};

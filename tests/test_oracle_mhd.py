@@ -1,5 +1,6 @@
-"""Pins of the oracle's WENO5-Z reconstruction (Sec. II.B.2, App. B), LLF
-flux (eq. LLF) and MHD right-hand side (Sec. IV.B)."""
+"""Pins of the oracle's reconstructions (WENO5-Z and WENO5-JS of App. B,
+WENO3 of App. A), interface fluxes (eq. LLF and HLL of Sec. II.B.2) and MHD
+right-hand side (Sec. IV.B)."""
 import numpy as np
 import pytest
 
@@ -28,6 +29,7 @@ def test_weno_exact_for_quadratic_cell_averages(seed):
         assert abs(O.weno("zL", u, eps) - p(x0 + h / 2)) < 1e-13
         assert abs(O.weno("zR", u, eps) - p(x0 - h / 2)) < 1e-13
         assert abs(O.weno("jsL", u, eps) - p(x0 + h / 2)) < 1e-13
+        assert abs(O.weno("jsR", u, eps) - p(x0 - h / 2)) < 1e-13
 
 
 def test_weno_linear_weights_when_tau_vanishes():
@@ -125,3 +127,95 @@ def test_conservation_sums_to_zero():
     scale = np.max(np.abs(R), axis=(1, 2, 3)) * R[0].size
     for f in range(8):
         assert abs(R[f].sum()) < 1e-13 * max(scale[f], 1.0)
+
+
+def test_weno3_exact_for_linear_data_and_ideal_weights():
+    """WENO3 (App. A): every candidate is exact for linear data, so both
+    states are; when the two smoothness indicators agree (data symmetric about
+    U_i) the weights are the ideal (2/3, 1/3) and the left state is
+    (-U_{i-1} + 5 U_i + 2 U_{i+1})/6, the right state its mirror."""
+    for a, b in ((0.3, -1.2), (2.0, 0.7)):
+        u = a + b * (np.arange(5) - 2.0)
+        for eps in (1e-12, 1e-2):
+            assert abs(O.weno("3L", u, eps) - (a + 0.5 * b)) < 1e-14
+            assert abs(O.weno("3R", u, eps) - (a - 0.5 * b)) < 1e-14
+    u = np.array([9.0, 0.4, -0.3, 0.4, 9.0])
+    assert abs(O.weno("3L", u, 1e-6) - (-0.4 + 5 * -0.3 + 2 * 0.4) / 6) < 1e-15
+    assert abs(O.weno("3R", u, 1e-6) - (2 * 0.4 + 5 * -0.3 - 0.4) / 6) < 1e-15
+
+
+def test_weno3_and_js_essentially_non_oscillatory_at_a_step():
+    u = np.array([0.0, 0.0, 0.0, 1.0, 1.0])
+    assert abs(O.weno("3L", u, 1e-6)) < 1e-10
+    assert abs(O.weno("jsL", u, 1e-6)) < 1e-10
+    u = np.array([0.0, 0.0, 1.0, 1.0, 1.0])
+    assert abs(O.weno("3R", u, 1e-6) - 1.0) < 1e-10
+    assert abs(O.weno("jsR", u, 1e-6) - 1.0) < 1e-10
+
+
+def _state(rho, v, p, B):
+    return synth.mhd_primitive_to_conserved(rho, v, p, B, 5.0 / 3.0).astype(np.float64)
+
+
+def test_hll_equals_llf_for_symmetric_speeds():
+    """With v_d = 0 on both sides and the same fast speed the HLL speeds are
+    S^L = -S^R, and HLL reduces to the LLF flux (Sec. II.B.2)."""
+    UL = _state(1.0, (0.0, 0.3, -0.1), 0.8, (0.4, 0.2, 0.1))
+    UR = _state(1.0, (0.0, -0.2, 0.2), 0.8, (0.4, 0.1, 0.2))
+    for d in (0,):
+        hll = O.mhd_interface_flux(UL, UR, d, 5.0 / 3.0, O.FLUX_HLL)
+        llf = O.mhd_interface_flux(UL, UR, d, 5.0 / 3.0, O.FLUX_LLF)
+        assert np.max(np.abs(hll - llf)) < 1e-14 * np.max(np.abs(llf))
+
+
+def test_hll_upwinds_supersonic_flow():
+    """Every wave moving right (v_x > c_f on both sides): the HLL flux is
+    F(U^L); every wave moving left: F(U^R)."""
+    UL = _state(1.0, (6.0, 0.1, 0.0), 0.5, (0.3, 0.2, 0.0))
+    UR = _state(0.8, (5.5, -0.1, 0.1), 0.4, (0.3, -0.1, 0.1))
+    F = lambda U: O.mhd_interface_flux(U, U, 0, 5.0 / 3.0, O.FLUX_LLF)
+    hll = O.mhd_interface_flux(UL, UR, 0, 5.0 / 3.0, O.FLUX_HLL)
+    assert np.max(np.abs(hll - F(UL))) < 1e-13 * np.max(np.abs(F(UL)))
+    UL[1:4] *= -1
+    UR[1:4] *= -1
+    hll = O.mhd_interface_flux(UL, UR, 0, 5.0 / 3.0, O.FLUX_HLL)
+    assert np.max(np.abs(hll - F(UR))) < 1e-13 * np.max(np.abs(F(UR)))
+
+
+VARIANTS = [(O.RECON_WENO5Z, O.FLUX_HLL), (O.RECON_WENO5JS, O.FLUX_LLF), (O.RECON_WENO3, O.FLUX_LLF),
+            (O.RECON_WENO3, O.FLUX_HLL)]
+
+
+@pytest.mark.parametrize("recon,flux", VARIANTS)
+def test_variants_free_stream_and_conservation(recon, flux):
+    prm = O.params(sigma=0.0, mhd_recon=float(recon), mhd_riemann=float(flux))
+    st = synth.mhd_primitive_to_conserved(1.3, (0.2, -0.1, 0.4), 0.7, (0.5, 0.3, -0.2), 5.0 / 3.0)
+    U = synth.embed(np.broadcast_to(st[:, None, None, None], (8, 4, 5, 6)).copy())
+    O.fill_periodic(U)
+    assert np.all(synth.interior(O.rhs(O.MHD, U, (0.1, 0.2, 0.3), prm)) == 0.0)
+    U = synth.embed(synth.mhd_ot_like((8, 6, 5), seed=3, N=(8, 8, 8)))
+    O.fill_periodic(U)
+    R = synth.interior(O.rhs(O.MHD, U, 1 / 8, prm))
+    scale = np.max(np.abs(R), axis=(1, 2, 3)) * R[0].size
+    for f in range(8):
+        assert abs(R[f].sum()) < 1e-13 * max(scale[f], 1.0)
+
+
+@pytest.mark.parametrize("recon,flux,lo,hi", [(O.RECON_WENO5JS, O.FLUX_LLF, 4.5, 6.0),
+                                              (O.RECON_WENO5Z, O.FLUX_HLL, 4.5, 6.0),
+                                              (O.RECON_WENO3, O.FLUX_LLF, 2.6, 3.6)])
+def test_alfven_orders_of_the_variants(recon, flux, lo, hi):
+    """CP Alfven wave (Sec. IV.B.1): WENO5-JS and WENO5-Z converge at 5th
+    order, WENO3 at 3rd (the paper's figure of the unigrid errors)."""
+    prm = O.params(sigma=0.0, mhd_recon=float(recon), mhd_riemann=float(flux))
+    errs = []
+    T = 0.05
+    for N in (16, 32, 64):
+        U = synth.embed(_alfven_1d(N, 0, 0.0))
+        dx = 1.0 / N
+        nsteps = int(round(T / (0.05 * dx)))
+        O.rk_run(O.MHD, O.RK4, U, (dx, dx, dx), T / nsteps, nsteps, prm)
+        ex = _alfven_1d(N, 0, T)
+        errs.append(np.sum(np.abs(synth.interior(U)[6] - ex[6])) / np.sum(np.abs(ex[6])))
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert lo < orders[-1] < hi, (errs, orders)
