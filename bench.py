@@ -255,7 +255,40 @@ def wave_mhd_bench(M):
     out["mhd_128^3"] = {"pt_stage_per_s": n ** 3 / (kms * 1e-3), "stage_kernel_ms": kms,
                         "stage_kernel_GBs_algorithmic": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
                         "bytes_per_pt_stage": 171.0}
+    # reconstruction and flux variants on the same data (App. A, B; Sec. II.B.2)
+    var = {}
+    for rname, rec in (("weno5z", M.MOL_RECON_WENO5Z), ("weno5js", M.MOL_RECON_WENO5JS), ("weno3", M.MOL_RECON_WENO3)):
+        for fname, fl in (("llf", M.MOL_FLUX_LLF), ("hll", M.MOL_FLUX_HLL)):
+            psv = M.Patchset(M.single_patch((n, n, n), (0, 0, 0), dx),
+                             M.System(M.MOL_MHD, sigma=0.0, mhd_recon=rec, mhd_flux=fl))
+            stv = psv.alloc_states()
+            stv[0]["U"].copy_(st[0]["U"])
+            var[f"{rname}_{fname}"] = {"stage_kernel_ms": stage_kernel_time(psv, M, stv, M.MOL_SSPRK3, 0.2 * dx)}
+            del psv, stv
+    out["mhd_variants_128^3"] = var
     return out
+
+
+def mhd_runs_bench(M):
+    """The MHD tests of Sec. IV.B on the GPU driver: relative L1 error of B_x
+    of the CP Alfven wave after three crossing times (N = 32, 64, 128) per
+    reconstruction, and of B_y of the Brio-Wu tube at t = 0.2 (N = 50 .. 400,
+    against WENO5-Z at N = 3200) unigrid and with FMR."""
+    import numpy as np
+    from paper_1806_04182_amd import mhd_runs as R
+    t0 = time.perf_counter()
+    res = {"alfven": {}, "brio_wu": {}}
+    for name, rec in (("weno5z", M.MOL_RECON_WENO5Z), ("weno5js", M.MOL_RECON_WENO5JS), ("weno3", M.MOL_RECON_WENO3)):
+        e = [R.alfven_error(N, rec) for N in (32, 64, 128)]
+        res["alfven"][name] = {"N": [32, 64, 128], "err_Bx": e, "orders": list(np.log2(np.array(e[:-1]) / np.array(e[1:])))}
+        log(f"bench: Alfven {name}: {e}")
+    ref = R.brio_wu(3200)
+    for fmr in (None, "2/2", "4"):
+        e = [R.brio_wu_error(R.brio_wu(N, fmr=fmr), ref, 3200) for N in (50, 100, 200, 400)]
+        res["brio_wu"][fmr or "unigrid"] = {"N": [50, 100, 200, 400], "err_By": e}
+        log(f"bench: Brio-Wu {fmr or 'unigrid'}: {e}")
+    res["wall_s"] = time.perf_counter() - t0
+    return res
 
 
 def main():
@@ -268,7 +301,7 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=96)
     ap.add_argument("--no-extras", action="store_true", help="skip the AMR and adjoint measurements")
     ap.add_argument("--no-fmr", action="store_true",
-                    help="skip the FMR reflection runs (many small launches; kept out of kernel traces)")
+                    help="skip the FMR reflection and MHD test runs (many small launches; kept out of kernel traces)")
     ap.add_argument("--paths-only", action="store_true",
                     help="measure only the wave and MHD paths and print their JSON (for profiling)")
     args = ap.parse_args()
@@ -375,6 +408,8 @@ def main():
         if not args.no_fmr:
             log("bench: FMR reflections")
             res["fmr_reflections"] = fmr_bench(M)
+            log("bench: MHD tests")
+            res["mhd_runs"] = mhd_runs_bench(M)
         log("bench: adjoint")
         res["adjoint"] = adjoint_bench(M)
         log("bench: wave and MHD paths")

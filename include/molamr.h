@@ -65,6 +65,15 @@ extern "C" {
 #define MOL_CCZ4 2 /* CCZ4, Sec. V: chi, gt_ij(6), trKhat, At_ij(6), Ghat^i(3), Theta,
                       alpha, beta^i(3), B^i(3); symmetric pairs ordered xx xy xz yy yz zz */
 
+/* MHD reconstruction of the evolved fields (App. A, App. B) and interface
+ * flux (Sec. II.B.2) */
+#define MOL_RECON_WENO5Z 0  /* WENO5-Z, q and epsilon as below (default) */
+#define MOL_RECON_WENO5JS 1 /* WENO5-JS, alpha_r = d_r / (eps + beta_r)^2 */
+#define MOL_RECON_WENO3 2   /* WENO3 (k = 2); epsilon defaults to dx^2 */
+#define MOL_FLUX_LLF 0      /* local Lax-Friedrichs, eq. LLF (default) */
+#define MOL_FLUX_HLL 1      /* HLL with S^L = min(v_d - c_f), S^R = max(v_d + c_f) over the two
+                               states, clamped to S^L <= 0 <= S^R */
+
 /* time integrators */
 #define MOL_RK4 0    /* Table RK44 */
 #define MOL_SSPRK3 1 /* SSP-RK(3,3) of App. D (stage 3 = U^n + k1/4 + k2/4, weights (1,1,4)/6) */
@@ -84,7 +93,7 @@ typedef struct {
     int upwind;           /* CCZ4: 1 = lop-sided advection stencils (Sec. II.B.1), 0 = centred */
     double sigma;         /* Kreiss-Oliger strength (Sec. II.B.1); wave and CCZ4 */
     double gamma_ad;      /* MHD ideal-gas index (Sec. IV.B) */
-    double weno_eps;      /* MHD WENO epsilon; <= 0 means dx^4 of the sweep axis (App. B) */
+    double weno_eps;      /* MHD WENO epsilon; <= 0 means dx^4 (dx^2 for WENO3) (App. A, B) */
     double weno_q;        /* MHD WENO-Z exponent q (App. B); 2 */
     double kappa_z;       /* CCZ4 damping (Sec. V) */
     double kappa_c;
@@ -92,6 +101,8 @@ typedef struct {
     double bm_f1;
     double gd_g;          /* CCZ4 Gamma-driver g and eta */
     double gd_eta;
+    int mhd_recon;        /* MOL_RECON_* */
+    int mhd_flux;         /* MOL_FLUX_* */
 } mol_system_desc;
 
 typedef struct mol_patchset mol_patchset;

@@ -86,6 +86,8 @@ double orc_weno3_right(const double* u, double eps);
  * axis d: LLF (riemann 0) or HLL (riemann 1) */
 void orc_mhd_interface_flux(const double UL[8], const double UR[8], int d, double gam, int riemann,
                             double F[8]);
+/* fast magnetosonic speed c_f of the state U along axis d */
+double orc_mhd_fast_speed(const double U[8], int d, double gam);
 
 /* ---- explicit Runge-Kutta (eq. eRK) on one periodic patch ---- */
 /* nsteps full steps with periodic ghost fill before every stage. */

@@ -84,6 +84,8 @@ def lib():
             getattr(L, name).argtypes = [dp, d]
             getattr(L, name).restype = d
         L.orc_mhd_interface_flux.argtypes = [dp, dp, i, d, i, dp]
+        L.orc_mhd_fast_speed.argtypes = [dp, i, d]
+        L.orc_mhd_fast_speed.restype = d
         L.orc_rk_run.argtypes = [i, i, dp, i, i, i, dp, d, i, P]
         L.orc_rk_scalar.argtypes = [i, d, d, dp, dp]
         L.orc_dense_rk4.argtypes = [i, i, d]
@@ -183,6 +185,11 @@ def weno(kind: str, u5: np.ndarray, eps: float, q: float = 2.0) -> float:
     if kind == "3R":
         return lib().orc_weno3_right(ptr, eps)
     return lib().orc_weno5js_left(ptr, eps)
+
+
+def mhd_fast_speed(U, d: int, gam: float) -> float:
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    return lib().orc_mhd_fast_speed(_p(U), d, gam)
 
 
 def mhd_interface_flux(UL, UR, d: int, gam: float, riemann: int) -> np.ndarray:

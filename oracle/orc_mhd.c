@@ -14,7 +14,11 @@
  *  - S in the LLF formula is max over the L and R states of |v_d| + c_f, with
  *    the fast magnetosonic speed c_f^2 = ((a^2+b^2) + sqrt((a^2+b^2)^2 - 4 a^2 b_d^2))/2,
  *    a^2 = Gamma p / rho, b^2 = B^2/rho, b_d^2 = B_d^2/rho (units where the
- *    magnetic pressure is B^2/2, as in the paper's energy density);
+ *    magnetic pressure is B^2/2, as in the paper's energy density); the
+ *    discriminant is evaluated as (a^2 - b^2)^2 + 4 a^2 b_t^2, b_t^2 the sum
+ *    of the two transverse components' squares over rho (the same number as
+ *    a sum of non-negative terms, which does not cancel where the sound and
+ *    Alfven speeds meet with B nearly along d);
  *  - S is taken per interface;
  *  - HLL: the printed formula misses a "+" before S^R S^L (U^R - U^L); the
  *    speeds are S^L = min(v_d - c_f) and S^R = max(v_d + c_f) over the two
@@ -173,11 +177,20 @@ static void mhd_flux_vc(const double U[8], int d, double gam, double F[8], doubl
         F[1 + i] = rho * v[d] * v[i] + (i == d ? ptot : 0.0) - B[d] * B[i];
     F[4] = (E + ptot) * v[d] - vB * B[d];
     for (int i = 0; i < 3; ++i) F[5 + i] = v[d] * B[i] - v[i] * B[d];
-    double a2 = gam * p / rho, b2 = B2 / rho, bd2 = B[d] * B[d] / rho;
-    double s = a2 + b2;
-    double cf2 = 0.5 * (s + sqrt(s * s - 4.0 * a2 * bd2));
+    double Bt2 = 0.0;
+    for (int i = 0; i < 3; ++i)
+        if (i != d) Bt2 += B[i] * B[i];
+    double a2 = gam * p / rho, b2 = B2 / rho, bt2 = Bt2 / rho;
+    double cf2 = 0.5 * (a2 + b2 + sqrt(sq(a2 - b2) + 4.0 * a2 * bt2));
     *vd = v[d];
     *cf = sqrt(cf2);
+}
+
+double orc_mhd_fast_speed(const double U[8], int d, double gam)
+{
+    double F[8], vd, cf;
+    mhd_flux_vc(U, d, gam, F, &vd, &cf);
+    return cf;
 }
 
 void orc_mhd_interface_flux(const double UL[8], const double UR[8], int d, double gam, int riemann,

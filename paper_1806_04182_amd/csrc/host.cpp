@@ -821,9 +821,16 @@ int mol_create_patchset(const mol_hierarchy_desc* h, const mol_system_desc* s, m
     ps->sp.bm_f1 = s->bm_f1;
     ps->sp.gd_g = s->gd_g;
     ps->sp.gd_eta = s->gd_eta;
+    ps->sp.mhd_recon = s->mhd_recon;
+    ps->sp.mhd_flux = s->mhd_flux;
     if (s->system == MOL_MHD && !(s->gamma_ad > 1.0)) {
         delete ps;
         return fail(MOL_EINVAL, "gamma_ad must exceed 1");
+    }
+    if (s->system == MOL_MHD && (s->mhd_recon < MOL_RECON_WENO5Z || s->mhd_recon > MOL_RECON_WENO3 ||
+                                 (s->mhd_flux != MOL_FLUX_LLF && s->mhd_flux != MOL_FLUX_HLL))) {
+        delete ps;
+        return fail(MOL_EINVAL, "unknown MHD reconstruction %d or flux %d", s->mhd_recon, s->mhd_flux);
     }
     ps->nlev = h->nlevels;
     for (int d = 0; d < 3; ++d) {

@@ -2,10 +2,13 @@
 // conservative finite-difference form (eq. conservative_discretization):
 //   L = - sum_d (F_{i+1/2} - F_{i-1/2}) / dx_d,
 // with the evolved fields reconstructed at every interface by WENO5-Z
-// (App. B; q = 2, eps = dx^4 unless set) and the local Lax-Friedrichs flux
-// (eq. LLF) F = (F(U^L) + F(U^R) - S (U^R - U^L)) / 2, where S is the larger
-// of |v_d| + c_f over the two states (fast magnetosonic speed c_f).  Fused with
-// the Runge-Kutta stage update.
+// (App. B; q = 2, eps = dx^4 unless set), WENO5-JS (App. B) or WENO3 (App. A,
+// eps = dx^2 unless set), and the local Lax-Friedrichs flux (eq. LLF)
+// F = (F(U^L) + F(U^R) - S (U^R - U^L)) / 2, S the larger of |v_d| + c_f over
+// the two states (fast magnetosonic speed c_f), or the HLL flux
+// F = (S^R F^L - S^L F^R + S^R S^L (U^R - U^L)) / (S^R - S^L) with
+// S^L = min(v_d - c_f, 0), S^R = max(v_d + c_f, 0) over the two states.  Fused
+// with the Runge-Kutta stage update.
 #include "k_common.h"
 
 namespace mol {
@@ -52,8 +55,52 @@ __device__ __forceinline__ double weno5z(double v0, double v1, double v2, double
     return (w0 * p0 + w1 * p1 + w2 * p2) / (w0 + w1 + w2);
 }
 
-// physical flux along d and the signal speed |v_d| + c_f
-__device__ __forceinline__ void flux(const double U[8], int d, double gam, double F[8], double& spd)
+// WENO5-JS value at the interface to the right of v[2] from the left:
+// alpha_r = d_r / e_r^2, e_r = eps + beta_r, scaled by e_0^2 e_1^2 e_2^2.
+__device__ __forceinline__ double weno5js(double v0, double v1, double v2, double v3, double v4, double eps)
+{
+    const double p0 = (2.0 * v2 + 5.0 * v3 - v4) * (1.0 / 6.0);
+    const double p1 = (-v1 + 5.0 * v2 + 2.0 * v3) * (1.0 / 6.0);
+    const double p2 = (2.0 * v0 - 7.0 * v1 + 11.0 * v2) * (1.0 / 6.0);
+    const double a0 = v2 - 2.0 * v3 + v4, b0 = 3.0 * v2 - 4.0 * v3 + v4;
+    const double a1 = v1 - 2.0 * v2 + v3, b1 = v1 - v3;
+    const double a2 = v0 - 2.0 * v1 + v2, b2 = v0 - 4.0 * v1 + 3.0 * v2;
+    const double e0 = eps + ((13.0 / 12.0) * a0 * a0 + 0.25 * b0 * b0);
+    const double e1 = eps + ((13.0 / 12.0) * a1 * a1 + 0.25 * b1 * b1);
+    const double e2 = eps + ((13.0 / 12.0) * a2 * a2 + 0.25 * b2 * b2);
+    const double s0 = e0 * e0, s1 = e1 * e1, s2 = e2 * e2;
+    const double w0 = 0.3 * (s1 * s2), w1 = 0.6 * (s0 * s2), w2 = 0.1 * (s0 * s1);
+    return (w0 * p0 + w1 * p1 + w2 * p2) / (w0 + w1 + w2);
+}
+
+// WENO3 value at the interface to the right of v2 from the left (cells v1,
+// v2, v3): alpha_0 = (2/3) / e_0^2, alpha_1 = (1/3) / e_1^2, scaled by e_0^2 e_1^2.
+__device__ __forceinline__ double weno3(double v1, double v2, double v3, double eps)
+{
+    const double p0 = 0.5 * (v2 + v3), p1 = 1.5 * v2 - 0.5 * v1;
+    const double d0 = v3 - v2, d1 = v2 - v1;
+    const double e0 = eps + d0 * d0, e1 = eps + d1 * d1;
+    const double w0 = (2.0 / 3.0) * (e1 * e1), w1 = (1.0 / 3.0) * (e0 * e0);
+    return (w0 * p0 + w1 * p1) / (w0 + w1);
+}
+
+enum { REC_W5Z = 0, REC_W5JS = 1, REC_W3 = 2 };
+enum { RS_LLF = 0, RS_HLL = 1 };
+
+// reconstructed value at the interface to the right of v2 from the left
+template <int REC, bool Q2>
+__device__ __forceinline__ double recon(double v0, double v1, double v2, double v3, double v4, double eps, double q)
+{
+    if constexpr (REC == REC_W3)
+        return weno3(v1, v2, v3, eps);
+    else if constexpr (REC == REC_W5JS)
+        return weno5js(v0, v1, v2, v3, v4, eps);
+    else
+        return weno5z<Q2>(v0, v1, v2, v3, v4, eps, q);
+}
+
+// physical flux along d, the normal velocity v_d and the fast speed c_f
+__device__ __forceinline__ void flux(const double U[8], int d, double gam, double F[8], double& vdo, double& cf)
 {
     const double rho = U[0], ir = 1.0 / rho;
     const double vx = U[1] * ir, vy = U[2] * ir, vz = U[3] * ir;
@@ -73,32 +120,43 @@ __device__ __forceinline__ void flux(const double U[8], int d, double gam, doubl
     F[5] = vd * Bx - vx * Bd;
     F[6] = vd * By - vy * Bd;
     F[7] = vd * Bz - vz * Bd;
-    const double a2 = gam * p * ir, b2 = B2 * ir, bd2 = Bd * Bd * ir;
-    const double sm = a2 + b2;
-    const double cf2 = 0.5 * (sm + sqrt(sm * sm - 4.0 * a2 * bd2));
-    spd = fabs(vd) + sqrt(cf2);
+    // (a^2 + b^2)^2 - 4 a^2 b_d^2 as (a^2 - b^2)^2 + 4 a^2 b_t^2: no cancellation
+    // where the sound and Alfven speeds meet with B nearly along d
+    const double Bt2 = d == 0 ? By * By + Bz * Bz : d == 1 ? Bx * Bx + Bz * Bz : Bx * Bx + By * By;
+    const double a2 = gam * p * ir, b2 = B2 * ir, bt2 = Bt2 * ir;
+    const double dab = a2 - b2;
+    const double cf2 = 0.5 * (a2 + b2 + sqrt(dab * dab + 4.0 * a2 * bt2));
+    vdo = vd;
+    cf = sqrt(cf2);
 }
 
-// LLF flux at the interface between cells 2 and 3 of a six-cell line; get(f, m)
-// returns cell m (0..5) of field f.  Left state reconstructed around cell 2,
-// right state around cell 3 (the left formula on mirrored cells).
-template <bool Q2, class Get>
-__device__ __forceinline__ void llf6(Get get, int d, const MhdConst& C, double Fh[8])
+// Interface flux between cells 2 and 3 of a six-cell line; get(f, m) returns
+// cell m (0..5) of field f.  Left state reconstructed around cell 2, right
+// state around cell 3 (the left formula on mirrored cells).
+template <int REC, int RS, bool Q2, class Get>
+__device__ __forceinline__ void riemann6(Get get, int d, const MhdConst& C, double Fh[8])
 {
     double UL[8], UR[8];
 #pragma unroll
     for (int f = 0; f < 8; ++f) {
         const double c0 = get(f, 0), c1 = get(f, 1), c2 = get(f, 2), c3 = get(f, 3), c4 = get(f, 4),
                      c5 = get(f, 5);
-        UL[f] = weno5z<Q2>(c0, c1, c2, c3, c4, C.eps[d], C.q);
-        UR[f] = weno5z<Q2>(c5, c4, c3, c2, c1, C.eps[d], C.q);
+        UL[f] = recon<REC, Q2>(c0, c1, c2, c3, c4, C.eps[d], C.q);
+        UR[f] = recon<REC, Q2>(c5, c4, c3, c2, c1, C.eps[d], C.q);
     }
-    double FL[8], FR[8], sL, sR;
-    flux(UL, d, C.gam, FL, sL);
-    flux(UR, d, C.gam, FR, sR);
-    const double S = fmax(sL, sR);
+    double FL[8], FR[8], vL, cL, vR, cR;
+    flux(UL, d, C.gam, FL, vL, cL);
+    flux(UR, d, C.gam, FR, vR, cR);
+    if constexpr (RS == RS_HLL) {
+        const double SL = fmin(fmin(vL - cL, vR - cR), 0.0), SR = fmax(fmax(vL + cL, vR + cR), 0.0);
+        const double id = 1.0 / (SR - SL), SRL = SR * SL;
 #pragma unroll
-    for (int f = 0; f < 8; ++f) Fh[f] = 0.5 * (FL[f] + FR[f] - S * (UR[f] - UL[f]));
+        for (int f = 0; f < 8; ++f) Fh[f] = (SR * FL[f] - SL * FR[f] + SRL * (UR[f] - UL[f])) * id;
+    } else {
+        const double S = fmax(fabs(vL) + cL, fabs(vR) + cR);
+#pragma unroll
+        for (int f = 0; f < 8; ++f) Fh[f] = 0.5 * (FL[f] + FR[f] - S * (UR[f] - UL[f]));
+    }
 }
 
 // One workgroup of 16 x 16 threads owns a tile of 15 x 15 columns and marches
@@ -115,7 +173,7 @@ constexpr int MB = MT + 1;       // threads per tile edge
 constexpr int MH = MT + 6;       // plane width with halo
 constexpr int MP = MH + 1;       // LDS row pitch
 
-template <bool Q2>
+template <int REC, int RS, bool Q2>
 __global__ __launch_bounds__(MB * MB) void mhd_stage_kernel(StageArgs a, MhdConst C, int zc)
 {
     __shared__ double pl[8][MH][MP];
@@ -145,7 +203,7 @@ __global__ __launch_bounds__(MB * MB) void mhd_stage_kernel(StageArgs a, MhdCons
         for (int f = 0; f < 8; ++f)
 #pragma unroll
             for (int m = 0; m < 6; ++m) w[f][m] = c7[f][m + 1];
-        llf6<Q2>([&](int f, int m) { return c7[f][m]; }, 2, C, Fm);
+        riemann6<REC, RS, Q2>([&](int f, int m) { return c7[f][m]; }, 2, C, Fm);
     }
     for (int k = z0; k < z1; ++k) {
         // stage plane k with its x/y halo
@@ -158,17 +216,17 @@ __global__ __launch_bounds__(MB * MB) void mhd_stage_kernel(StageArgs a, MhdCons
         __syncthreads();
         // x-interface to the left of column (tx, ty): cells tx-3 .. tx+2 of row ty
         double Fp[8];
-        if (col) llf6<Q2>([&](int f, int m) { return w[f][m]; }, 2, C, Fp);
+        if (col) riemann6<REC, RS, Q2>([&](int f, int m) { return w[f][m]; }, 2, C, Fp);
         if (ty < MT && x0 + tx <= P.n[0] && y0 + ty < P.n[1]) {
             double F[8];
-            llf6<Q2>([&](int f, int m) { return pl[f][ty + G][tx + m]; }, 0, C, F);
+            riemann6<REC, RS, Q2>([&](int f, int m) { return pl[f][ty + G][tx + m]; }, 0, C, F);
 #pragma unroll
             for (int f = 0; f < 8; ++f) fx[f][ty][tx] = F[f];
         }
         // y-interface below column (tx, ty)
         if (tx < MT && y0 + ty <= P.n[1] && x0 + tx < P.n[0]) {
             double F[8];
-            llf6<Q2>([&](int f, int m) { return pl[f][ty + m][tx + G]; }, 1, C, F);
+            riemann6<REC, RS, Q2>([&](int f, int m) { return pl[f][ty + m][tx + G]; }, 1, C, F);
 #pragma unroll
             for (int f = 0; f < 8; ++f) fy[f][ty][tx] = F[f];
         }
@@ -202,15 +260,32 @@ hipError_t launch_stage_mhd(const SysParams& sp, const StageArgs& a, const int t
     if (a.ntiles <= 0) return hipSuccess;
     MhdConst C;
     C.gam = sp.gamma_ad;
-    const double e = sp.weno_eps > 0.0 ? sp.weno_eps : sp.h * sp.h * sp.h * sp.h;
+    const double h2 = sp.h * sp.h;
+    const double e = sp.weno_eps > 0.0 ? sp.weno_eps : (sp.mhd_recon == MOL_RECON_WENO3 ? h2 : h2 * h2);
     C.eps[0] = C.eps[1] = C.eps[2] = e;
     C.q = sp.weno_q;
     C.ih = 1.0 / sp.h;
     if (td[0] != MT || td[1] != MT) return hipErrorInvalidConfiguration;
-    if (C.q == 2.0)
-        mhd_stage_kernel<true><<<a.ntiles, dim3(MB, MB, 1), 0, s>>>(a, C, td[2]);
-    else
-        mhd_stage_kernel<false><<<a.ntiles, dim3(MB, MB, 1), 0, s>>>(a, C, td[2]);
+    const dim3 g(a.ntiles), b(MB, MB, 1);
+    const bool hll = sp.mhd_flux == MOL_FLUX_HLL;
+    switch (sp.mhd_recon) {
+    case MOL_RECON_WENO3:
+        if (hll) mhd_stage_kernel<REC_W3, RS_HLL, true><<<g, b, 0, s>>>(a, C, td[2]);
+        else mhd_stage_kernel<REC_W3, RS_LLF, true><<<g, b, 0, s>>>(a, C, td[2]);
+        break;
+    case MOL_RECON_WENO5JS:
+        if (hll) mhd_stage_kernel<REC_W5JS, RS_HLL, true><<<g, b, 0, s>>>(a, C, td[2]);
+        else mhd_stage_kernel<REC_W5JS, RS_LLF, true><<<g, b, 0, s>>>(a, C, td[2]);
+        break;
+    default:
+        if (C.q == 2.0) {
+            if (hll) mhd_stage_kernel<REC_W5Z, RS_HLL, true><<<g, b, 0, s>>>(a, C, td[2]);
+            else mhd_stage_kernel<REC_W5Z, RS_LLF, true><<<g, b, 0, s>>>(a, C, td[2]);
+        } else {
+            if (hll) mhd_stage_kernel<REC_W5Z, RS_HLL, false><<<g, b, 0, s>>>(a, C, td[2]);
+            else mhd_stage_kernel<REC_W5Z, RS_LLF, false><<<g, b, 0, s>>>(a, C, td[2]);
+        }
+    }
     return hipGetLastError();
 }
 

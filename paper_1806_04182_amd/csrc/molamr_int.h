@@ -106,6 +106,7 @@ struct SysParams {
     int upwind;
     double h;  // grid spacing of the level (isotropic)
     double sigma, gamma_ad, weno_eps, weno_q, kappa_z, kappa_c, bm_f0, bm_f1, gd_g, gd_eta;
+    int mhd_recon, mhd_flux;
 };
 
 // What the fused stage kernels do after evaluating k = dt * rhs.

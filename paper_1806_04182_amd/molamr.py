@@ -20,6 +20,8 @@ LIB_PATH = os.environ.get("MOLAMR_LIB", os.path.join(HERE, "libmolamr.so"))
 MOL_WAVE, MOL_MHD, MOL_CCZ4 = 0, 1, 2
 MOL_RK4, MOL_SSPRK3 = 0, 1
 MOL_BATCHED, MOL_PLAIN = 0, 1
+MOL_RECON_WENO5Z, MOL_RECON_WENO5JS, MOL_RECON_WENO3 = 0, 1, 2
+MOL_FLUX_LLF, MOL_FLUX_HLL = 0, 1
 # time-refinement strategies (Sec. III.B), or-ed into the mode of advance()
 MOL_TIME_BOR, MOL_TIME_BO, MOL_TIME_BO1, MOL_TIME_NOSUB = 0, 16, 32, 48
 GHOST = 3
@@ -41,7 +43,8 @@ class _Hier(ctypes.Structure):
 class _Sys(ctypes.Structure):
     _fields_ = [("system", ctypes.c_int), ("upwind", ctypes.c_int)] + [
         (n, ctypes.c_double) for n in ("sigma", "gamma_ad", "weno_eps", "weno_q", "kappa_z", "kappa_c",
-                                       "bm_f0", "bm_f1", "gd_g", "gd_eta")]
+                                       "bm_f0", "bm_f1", "gd_g", "gd_eta")] + [
+        ("mhd_recon", ctypes.c_int), ("mhd_flux", ctypes.c_int)]
 
 
 class _LevelState(ctypes.Structure):
@@ -143,10 +146,13 @@ class System:
     gd_g: float = 0.75
     gd_eta: float = 2.0
     upwind: int = 1
+    mhd_recon: int = 0  # MOL_RECON_*
+    mhd_flux: int = 0   # MOL_FLUX_*
 
     def _c(self) -> _Sys:
         return _Sys(self.system, int(self.upwind), self.sigma, self.gamma_ad, self.weno_eps, self.weno_q,
-                    self.kappa_z, self.kappa_c, self.bm_f0, self.bm_f1, self.gd_g, self.gd_eta)
+                    self.kappa_z, self.kappa_c, self.bm_f0, self.bm_f1, self.gd_g, self.gd_eta,
+                    int(self.mhd_recon), int(self.mhd_flux))
 
 
 @dataclass

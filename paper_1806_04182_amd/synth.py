@@ -231,3 +231,37 @@ def wave_channel_pulse(x, t, L, width=0.173):
     x = np.asarray(x, dtype=np.float64)
     g = lambda s: np.exp(-(s ** 2) / width ** 2)
     return sum(0.5 * (g(x - t + m * L) + g(x + t + m * L)) for m in (-1, 0, 1))
+
+
+def mhd_cp_alfven(n, dx, lo=(0, 0, 0), L=2.0, gamma=5.0 / 3.0):
+    """Circularly polarised Alfven wave of the MHD tests (Sec. IV.B.1) on a
+    square periodic box of side L in x, y with alpha = pi/4: rho = 1, p = 0.1,
+    B_par = 1, B_perp = v_perp = 0.1 sin(phase), B_z = v_z = 0.1 cos(phase),
+    phase = 2 pi x_par / (L cos alpha) (one wavelength along k across the box),
+    B_perp = B_y cos alpha - B_x sin alpha.  Points at x = (lo + i) dx."""
+    ca = sa = np.sqrt(0.5)
+    x = (lo[0] + np.arange(n[0])) * dx
+    y = (lo[1] + np.arange(n[1])) * dx
+    X, Y = np.meshgrid(x, y)
+    ph = 2.0 * np.pi * (X * ca + Y * sa) / (L * ca)
+    bp, bz = 0.1 * np.sin(ph), 0.1 * np.cos(ph)
+    B = [ca - bp * sa, sa + bp * ca, bz]
+    v = [-bp * sa, bp * ca, bz]
+    shape = (n[2], n[1], n[0])
+    bc = lambda a: np.broadcast_to(np.asarray(a, dtype=np.float64), shape)
+    return mhd_primitive_to_conserved(bc(1.0), [bc(c) for c in v], bc(0.1), [bc(c) for c in B], gamma)
+
+
+def mhd_brio_wu(n, dx, lo=(0, 0, 0), jumps=(0.5, 2.5), gamma=2.0):
+    """Brio-Wu magnetic shock tube (Sec. IV.B.3) on a periodic line: the
+    left state (rho 1, p 1, B_y 1) for x <= jumps[0] and x > jumps[1], the
+    right state (rho 0.125, p 0.1, B_y -1) between; B_x = 0.75, v = B_z = 0."""
+    x = (lo[0] + np.arange(n[0])) * dx
+    left = (x <= jumps[0]) | (x > jumps[1])
+    shape = (n[2], n[1], n[0])
+    bc = lambda a: np.broadcast_to(np.asarray(a, dtype=np.float64), shape)
+    rho = bc(np.where(left, 1.0, 0.125))
+    p = bc(np.where(left, 1.0, 0.1))
+    By = bc(np.where(left, 1.0, -1.0))
+    zero = bc(0.0)
+    return mhd_primitive_to_conserved(rho, [zero, zero, zero], p, [bc(0.75), By, zero], gamma)

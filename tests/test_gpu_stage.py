@@ -77,6 +77,42 @@ def test_mhd_ssprk3_parity(n):
     assert np.all(e <= TOL), e
 
 
+def _jump_state(n, seed=0):
+    """Brio-Wu-type left/right states (Sec. IV.B.3) with a jump at both x
+    quarters, a uniform boost v_x = 2.5 (supersonic along x, so the HLL speeds
+    take both clamped branches) and 1e-3 noise; Gamma = 2."""
+    rng = np.random.default_rng(seed)
+    shape = (n[2], n[1], n[0])
+    x = (np.arange(n[0]) + 0.5) / n[0]
+    left = ((x < 0.25) | (x >= 0.75))[None, None, :] * np.ones(shape, bool)
+    rho = np.where(left, 1.0, 0.125) * (1 + 1e-3 * rng.uniform(-1, 1, shape))
+    p = np.where(left, 1.0, 0.1) * (1 + 1e-3 * rng.uniform(-1, 1, shape))
+    v = [2.5 + 1e-3 * rng.uniform(-1, 1, shape), 1e-3 * rng.uniform(-1, 1, shape), 1e-3 * rng.uniform(-1, 1, shape)]
+    B = [0.75 + 0 * rho, np.where(left, 1.0, -1.0) + 1e-3 * rng.uniform(-1, 1, shape), 1e-3 * rng.uniform(-1, 1, shape)]
+    return synth.mhd_primitive_to_conserved(rho, v, p, B, 2.0)
+
+
+@pytest.mark.parametrize("recon,flux", [(M.MOL_RECON_WENO5Z, M.MOL_FLUX_HLL), (M.MOL_RECON_WENO5JS, M.MOL_FLUX_LLF),
+                                        (M.MOL_RECON_WENO5JS, M.MOL_FLUX_HLL), (M.MOL_RECON_WENO3, M.MOL_FLUX_LLF),
+                                        (M.MOL_RECON_WENO3, M.MOL_FLUX_HLL)])
+@pytest.mark.parametrize("kind,n", [("smooth", (20, 17, 11)), ("jump", (46, 31, 17))])
+def test_mhd_variants_parity(recon, flux, kind, n):
+    """Reconstructions WENO5-JS, WENO3 (App. A, B) and the HLL flux against
+    the oracle's printed formulas, on smooth data and across jumps."""
+    print("mhd variant", recon, flux, kind, n, flush=True)
+    if kind == "smooth":
+        N = (max(n[0], 8),) * 3
+        U0, dx, gam = synth.embed(synth.mhd_ot_like(n, seed=1, N=N)), 1.0 / N[0], 5.0 / 3.0
+    else:
+        U0, dx, gam = synth.embed(_jump_state(n)), 1.0 / n[0], 2.0
+    sysd = M.System(M.MOL_MHD, sigma=0.0, gamma_ad=gam, mhd_recon=recon, mhd_flux=flux)
+    prm = O.params(sigma=0.0, gamma_ad=gam, mhd_recon=float(recon), mhd_riemann=float(flux))
+    got = _gpu_steps(O.MHD, M.MOL_SSPRK3, U0, dx, 0.1 * dx, 2, sysd)
+    ref = _oracle_steps(O.MHD, O.SSPRK3, U0, dx, 0.1 * dx, 2, prm)
+    e = parity_err(got[:, 3:-3, 3:-3, 3:-3], ref[:, 3:-3, 3:-3, 3:-3])
+    assert np.all(e <= TOL), e
+
+
 def _ccz4_state(n, kind, seed=0):
     dx = 2.0 / max(n)
     if kind == "noise":

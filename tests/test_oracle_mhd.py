@@ -219,3 +219,20 @@ def test_alfven_orders_of_the_variants(recon, flux, lo, hi):
         errs.append(np.sum(np.abs(synth.interior(U)[6] - ex[6])) / np.sum(np.abs(ex[6])))
     orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert lo < orders[-1] < hi, (errs, orders)
+
+
+def test_fast_speed_limits():
+    """Fast magnetosonic speed (textbook, units with magnetic pressure B^2/2):
+    B along d gives max(a, b); B across d gives sqrt(a^2 + b^2); B = 0 gives
+    the sound speed a; a^2 = b^2 with B along d (the double root) gives a."""
+    gam = 5.0 / 3.0
+    for rho, p, Bm in ((1.0, 0.6, 0.4), (0.3, 0.05, 1.2), (2.0, 1.5, 0.0)):
+        a2, b2 = gam * p / rho, Bm * Bm / rho
+        Upar = _state(rho, (0.1, 0.2, -0.3), p, (Bm, 0.0, 0.0))
+        Uperp = _state(rho, (0.1, 0.2, -0.3), p, (0.0, Bm * 0.6, Bm * 0.8))
+        assert abs(O.mhd_fast_speed(Upar, 0, gam) - np.sqrt(max(a2, b2))) < 1e-14
+        assert abs(O.mhd_fast_speed(Uperp, 0, gam) - np.sqrt(a2 + b2)) < 1e-14
+    rho, Bm = 1.0, 0.9
+    p = Bm * Bm / gam  # a^2 = b^2
+    U = _state(rho, (0.0, 0.0, 0.0), p, (0.0, Bm, 0.0))
+    assert abs(O.mhd_fast_speed(U, 1, gam) - Bm) < 1e-15
