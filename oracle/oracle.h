@@ -45,9 +45,11 @@ typedef struct {
     /* MHD variants (Sec. II.B.2, App. A, App. B) */
     double mhd_recon;  /* 0: WENO5-Z, 1: WENO5-JS, 2: WENO3 */
     double mhd_riemann; /* 0: local Lax-Friedrichs (eq. LLF), 1: HLL */
+    double mhd_ch;     /* divergence cleaning (Sec. IV.B, 9-field system): speed c_h */
+    double mhd_kpsi;   /* and damping kappa_psi */
 } orc_params;
 
-enum { ORC_WAVE = 0, ORC_MHD = 1, ORC_CCZ4 = 2 };
+enum { ORC_WAVE = 0, ORC_MHD = 1, ORC_CCZ4 = 2, ORC_MHD_GLM = 3 };
 enum { ORC_RK4 = 0, ORC_SSPRK3 = 1 };
 
 int orc_nfields(int system);
@@ -65,6 +67,9 @@ void orc_fill_periodic(double* U, int nf, int nx, int ny, int nz);
 /* ---- right-hand sides L(U) + Q_d(U) on the interior ---- */
 void orc_wave_rhs(const double* U, double* R, int nx, int ny, int nz,
                   const double h[3], const orc_params* p);
+/* nine fields (ORC_MHD_GLM): the cleaning scalar psi last */
+void orc_mhd_glm_rhs(const double* U, double* R, int nx, int ny, int nz,
+                     const double h[3], const orc_params* p);
 void orc_mhd_rhs(const double* U, double* R, int nx, int ny, int nz,
                  const double h[3], const orc_params* p);
 void orc_ccz4_rhs(const double* U, double* R, int nx, int ny, int nz,

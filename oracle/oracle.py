@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-WAVE, MHD, CCZ4 = 0, 1, 2
+WAVE, MHD, CCZ4, MHD_GLM = 0, 1, 2, 3
 RK4, SSPRK3 = 0, 1
 NFIELDS = {WAVE: 2, MHD: 8, CCZ4: 25}
 
@@ -24,7 +24,7 @@ NFIELDS = {WAVE: 2, MHD: 8, CCZ4: 25}
 class Params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in (
         "sigma", "gamma_ad", "weno_eps", "weno_q", "kappa_z", "kappa_c",
-        "bm_f0", "bm_f1", "gd_g", "gd_eta", "upwind", "mhd_recon", "mhd_riemann")]
+        "bm_f0", "bm_f1", "gd_g", "gd_eta", "upwind", "mhd_recon", "mhd_riemann", "mhd_ch", "mhd_kpsi")]
 
 
 # MHD variants: reconstruction (App. A/B) and interface flux (Sec. II.B.2)
@@ -39,7 +39,7 @@ TIME_BOR, TIME_BO, TIME_BO1, TIME_NOSUB = 0, 1, 2, 3
 def params(**kw) -> Params:
     d = dict(sigma=0.1, gamma_ad=5.0 / 3.0, weno_eps=-1.0, weno_q=2.0,
              kappa_z=0.1, kappa_c=0.1, bm_f0=0.0, bm_f1=2.0, gd_g=0.75,
-             gd_eta=2.0, upwind=1.0, mhd_recon=0.0, mhd_riemann=0.0)
+             gd_eta=2.0, upwind=1.0, mhd_recon=0.0, mhd_riemann=0.0, mhd_ch=1.0, mhd_kpsi=0.0)
     d.update(kw)
     return Params(**d)
 

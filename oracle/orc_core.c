@@ -13,6 +13,7 @@ int orc_nfields(int system)
     switch (system) {
     case ORC_WAVE: return 2;
     case ORC_MHD: return 8;
+    case ORC_MHD_GLM: return 9;
     case ORC_CCZ4: return 25;
     }
     return -1;
@@ -76,6 +77,7 @@ void orc_rhs(int system, const double* U, double* R, int nx, int ny, int nz,
     switch (system) {
     case ORC_WAVE: orc_wave_rhs(U, R, nx, ny, nz, h, p); break;
     case ORC_MHD: orc_mhd_rhs(U, R, nx, ny, nz, h, p); break;
+    case ORC_MHD_GLM: orc_mhd_glm_rhs(U, R, nx, ny, nz, h, p); break;
     case ORC_CCZ4: orc_ccz4_rhs(U, R, nx, ny, nz, h, p); break;
     }
 }

@@ -26,7 +26,11 @@
  *    when every wave moves right, F^R when every wave moves left) in one
  *    formula;
  *  - epsilon: dx^4 for the fifth-order reconstructions (App. B), dx^2 for
- *    WENO3 (App. A), unless set.
+ *    WENO3 (App. A), unless set;
+ *  - divergence cleaning (nine fields, psi last): the B^i flux along d gains
+ *    delta^{di} psi, psi has the flux c_h^2 B^d and the source -kappa_psi psi;
+ *    the cleaning waves move at -c_h and +c_h, so LLF takes S = max(..., c_h)
+ *    and HLL S^L = min(..., -c_h), S^R = max(..., c_h).
  */
 #include <math.h>
 #include <stdlib.h>
@@ -193,28 +197,46 @@ double orc_mhd_fast_speed(const double U[8], int d, double gam)
     return cf;
 }
 
-void orc_mhd_interface_flux(const double UL[8], const double UR[8], int d, double gam, int riemann,
-                            double F[8])
+/* interface flux of nf = 8 or 9 fields (9: with the cleaning scalar and speed ch) */
+static void interface_flux(const double* UL, const double* UR, int d, double gam, int riemann, int nf,
+                           double ch, double* F)
 {
-    double FL[8], FR[8], vL, cL, vR, cR;
+    double FL[9], FR[9], vL, cL, vR, cR;
     mhd_flux_vc(UL, d, gam, FL, &vL, &cL);
     mhd_flux_vc(UR, d, gam, FR, &vR, &cR);
+    if (nf == 9) {
+        FL[5 + d] += UL[8];
+        FR[5 + d] += UR[8];
+        FL[8] = ch * ch * UL[5 + d];
+        FR[8] = ch * ch * UR[5 + d];
+    }
     if (riemann == 1) {
         /* HLL: F = (S^R F^L - S^L F^R + S^R S^L (U^R - U^L)) / (S^R - S^L) */
         double SL = fmin(vL - cL, vR - cR), SR = fmax(vL + cL, vR + cR);
+        if (nf == 9) {
+            SL = fmin(SL, -ch);
+            SR = fmax(SR, ch);
+        }
         SL = fmin(SL, 0.0);
         SR = fmax(SR, 0.0);
-        for (int f = 0; f < 8; ++f) F[f] = (SR * FL[f] - SL * FR[f] + SR * SL * (UR[f] - UL[f])) / (SR - SL);
+        for (int f = 0; f < nf; ++f) F[f] = (SR * FL[f] - SL * FR[f] + SR * SL * (UR[f] - UL[f])) / (SR - SL);
     } else {
-        /* LLF with S = max over the two states of |v_d| + c_f */
+        /* LLF with S = max over the two states of |v_d| + c_f (and c_h) */
         double sL = fabs(vL) + cL, sR = fabs(vR) + cR;
         double S = sL > sR ? sL : sR;
-        for (int f = 0; f < 8; ++f) F[f] = 0.5 * (FL[f] + FR[f] - S * (UR[f] - UL[f]));
+        if (nf == 9 && ch > S) S = ch;
+        for (int f = 0; f < nf; ++f) F[f] = 0.5 * (FL[f] + FR[f] - S * (UR[f] - UL[f]));
     }
 }
 
-void orc_mhd_rhs(const double* U, double* R, int nx, int ny, int nz,
-                 const double h[3], const orc_params* p)
+void orc_mhd_interface_flux(const double UL[8], const double UR[8], int d, double gam, int riemann,
+                            double F[8])
+{
+    interface_flux(UL, UR, d, gam, riemann, 8, 0.0, F);
+}
+
+static void mhd_rhs_nf(const double* U, double* R, int nx, int ny, int nz, const double h[3],
+                       const orc_params* p, int nf)
 {
     long NX = nx + 2 * ORC_G, NY = ny + 2 * ORC_G, NZ = nz + 2 * ORC_G;
     long vol = NX * NY * NZ;
@@ -223,7 +245,7 @@ void orc_mhd_rhs(const double* U, double* R, int nx, int ny, int nz,
     for (int k = ORC_G; k < nz + ORC_G; ++k)
         for (int j = ORC_G; j < ny + ORC_G; ++j)
             for (int i = ORC_G; i < nx + ORC_G; ++i)
-                for (int f = 0; f < 8; ++f) R[f * vol + (k * NY + j) * NX + i] = 0.0;
+                for (int f = 0; f < nf; ++f) R[f * vol + (k * NY + j) * NX + i] = 0.0;
     const int recon = (int)p->mhd_recon, riemann = (int)p->mhd_riemann;
     for (int d = 0; d < 3; ++d) {
         double eps = p->weno_eps > 0.0 ? p->weno_eps : (recon == 2 ? h[d] * h[d] : h[d] * h[d] * h[d] * h[d]);
@@ -235,8 +257,8 @@ void orc_mhd_rhs(const double* U, double* R, int nx, int ny, int nz,
             for (int j = lo[1]; j < hi[1]; ++j)
                 for (int i = lo[0]; i < hi[0]; ++i) {
                     long c = (k * NY + j) * NX + i;
-                    double UL[8], UR[8], Fi[8];
-                    for (int f = 0; f < 8; ++f) {
+                    double UL[9], UR[9], Fi[9];
+                    for (int f = 0; f < nf; ++f) {
                         double line[6];
                         for (int m = 0; m < 6; ++m) line[m] = U[f * vol + c + (m - 2) * st[d]];
                         /* line[2] is U_i; the left state at i+1/2 is
@@ -253,8 +275,8 @@ void orc_mhd_rhs(const double* U, double* R, int nx, int ny, int nz,
                             UR[f] = orc_weno5z_right(line + 3, eps, p->weno_q);
                         }
                     }
-                    orc_mhd_interface_flux(UL, UR, d, p->gamma_ad, riemann, Fi);
-                    for (int f = 0; f < 8; ++f) {
+                    interface_flux(UL, UR, d, p->gamma_ad, riemann, nf, p->mhd_ch, Fi);
+                    for (int f = 0; f < nf; ++f) {
                         double Fh = Fi[f];
                         /* interface i+1/2 closes cell i (if interior) on the right
                          * and opens cell i+1 (if interior) on the left */
@@ -264,4 +286,23 @@ void orc_mhd_rhs(const double* U, double* R, int nx, int ny, int nz,
                     }
                 }
     }
+    if (nf == 9)
+        for (int k = ORC_G; k < nz + ORC_G; ++k)
+            for (int j = ORC_G; j < ny + ORC_G; ++j)
+                for (int i = ORC_G; i < nx + ORC_G; ++i) {
+                    long c = (k * NY + j) * NX + i;
+                    R[8 * vol + c] -= p->mhd_kpsi * U[8 * vol + c];
+                }
+}
+
+void orc_mhd_rhs(const double* U, double* R, int nx, int ny, int nz,
+                 const double h[3], const orc_params* p)
+{
+    mhd_rhs_nf(U, R, nx, ny, nz, h, p, 8);
+}
+
+void orc_mhd_glm_rhs(const double* U, double* R, int nx, int ny, int nz,
+                     const double h[3], const orc_params* p)
+{
+    mhd_rhs_nf(U, R, nx, ny, nz, h, p, 9);
 }

@@ -236,3 +236,87 @@ def test_fast_speed_limits():
     p = Bm * Bm / gam  # a^2 = b^2
     U = _state(rho, (0.0, 0.0, 0.0), p, (0.0, Bm, 0.0))
     assert abs(O.mhd_fast_speed(U, 1, gam) - Bm) < 1e-15
+
+
+def _glm_prm(**kw):
+    d = dict(sigma=0.0, gamma_ad=5.0 / 3.0, mhd_ch=0.05, mhd_kpsi=0.7)
+    d.update(kw)
+    return O.params(**d)
+
+
+@pytest.mark.parametrize("flux", [O.FLUX_LLF, O.FLUX_HLL])
+def test_glm_reduces_to_eight_fields_when_psi_vanishes(flux):
+    """With psi = 0 and c_h not among the extreme signal speeds (LLF: below
+    every |v_d| + c_f; HLL: below every c_f - |v_d|, here c_h = 0), the first
+    eight fields' right-hand side is the eight-field one exactly."""
+    n = (8, 6, 5)
+    U8 = synth.embed(synth.mhd_ot_like(n, seed=4, N=(8, 8, 8)))
+    O.fill_periodic(U8)
+    U9 = np.concatenate([U8, np.zeros((1,) + U8.shape[1:])])
+    ch = 0.05 if flux == O.FLUX_LLF else 0.0
+    R8 = O.rhs(O.MHD, U8, 1 / 8, _glm_prm(mhd_riemann=float(flux), mhd_ch=ch))
+    R9 = O.rhs(O.MHD_GLM, U9, 1 / 8, _glm_prm(mhd_riemann=float(flux), mhd_ch=ch))
+    assert np.array_equal(synth.interior(R8), synth.interior(R9)[:8])
+
+
+def test_glm_psi_budget_and_conservation():
+    """The flux parts of all nine fields sum to zero over a periodic box; psi
+    has in addition the source -kappa_psi psi."""
+    n = (8, 6, 5)
+    U8 = synth.embed(synth.mhd_ot_like(n, seed=5, N=(8, 8, 8)))
+    psi = 0.05 * np.random.default_rng(1).standard_normal((1,) + U8.shape[1:])
+    U = np.concatenate([U8, psi])
+    O.fill_periodic(U)
+    prm = _glm_prm(mhd_ch=1.5, mhd_kpsi=0.7)
+    R = synth.interior(O.rhs(O.MHD_GLM, U, 1 / 8, prm))
+    scale = np.max(np.abs(R), axis=(1, 2, 3)) * R[0].size
+    for f in range(8):
+        assert abs(R[f].sum()) < 1e-13 * max(scale[f], 1.0)
+    target = -0.7 * synth.interior(U)[8].sum()
+    assert abs(R[8].sum() - target) < 1e-13 * max(scale[8], 1.0)
+
+
+def _div_b_line(N, cleaning, T=3.0):
+    """1D: B_x = 1 + 0.1 sin(2 pi x) (a divergence error), rest uniform at rest."""
+    x = np.arange(N) / N
+    bx = 1.0 + 0.1 * np.sin(2 * np.pi * x)
+    zero = np.zeros(N)
+    st = synth.mhd_primitive_to_conserved(np.ones(N), [zero, zero, zero], np.ones(N), [bx, zero, zero], 5.0 / 3.0)
+    st = st.reshape((8, 1, 1, N))
+    if cleaning:
+        st = np.concatenate([st, np.zeros((1, 1, 1, N))])
+    U = synth.embed(st)
+    dx = 1.0 / N
+    nsteps = int(round(T / (0.2 * dx)))
+    system = O.MHD_GLM if cleaning else O.MHD
+    O.rk_run(system, O.RK4, U, (dx, dx, dx), T / nsteps, nsteps, _glm_prm(mhd_ch=1.0, mhd_kpsi=2.0))
+    b = synth.interior(U)[5, 0, 0]
+    return np.max(np.abs(b - b.mean()))
+
+
+def test_glm_cleans_a_divergence_error():
+    """Without cleaning the physical x-flux of B^x vanishes identically in 1D,
+    so the error only feels the LLF dissipation and stays within 1e-3 of its
+    size; with c_h = 1, kappa_psi = 2 the (div B, psi) pair is a damped wave
+    (decay rate kappa_psi / 2) and the error falls more than tenfold over t = 3."""
+    e0 = 0.1
+    assert abs(_div_b_line(32, False) - e0) < 1e-3 * e0
+    assert _div_b_line(32, True) < 0.1 * e0
+
+
+def test_glm_keeps_alfven_order_5():
+    """With cleaning on (c_h = 1, kappa_psi = 0.5) psi stays at truncation level
+    and the CP Alfven wave still converges at 5th order."""
+    prm = _glm_prm(mhd_ch=1.0, mhd_kpsi=0.5)
+    errs = []
+    T = 0.05
+    for N in (16, 32, 64):
+        st = _alfven_1d(N, 0, 0.0)
+        U = synth.embed(np.concatenate([st, np.zeros((1,) + st.shape[1:])]))
+        dx = 1.0 / N
+        nsteps = int(round(T / (0.05 * dx)))
+        O.rk_run(O.MHD_GLM, O.RK4, U, (dx, dx, dx), T / nsteps, nsteps, prm)
+        ex = _alfven_1d(N, 0, T)
+        errs.append(np.sum(np.abs(synth.interior(U)[6] - ex[6])) / np.sum(np.abs(ex[6])))
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert 4.5 < orders[-1] < 5.5, (errs, orders)
