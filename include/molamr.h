@@ -64,6 +64,9 @@ extern "C" {
 #define MOL_MHD 1  /* Newtonian ideal MHD, Sec. IV.B: rho, S_x, S_y, S_z, E, B^x, B^y, B^z */
 #define MOL_CCZ4 2 /* CCZ4, Sec. V: chi, gt_ij(6), trKhat, At_ij(6), Ghat^i(3), Theta,
                       alpha, beta^i(3), B^i(3); symmetric pairs ordered xx xy xz yy yz zz */
+#define MOL_MHD_GLM 3 /* MHD with the divergence-cleaning scalar (Sec. IV.B): the eight MHD
+                         fields and psi; B^i flux + delta^{di} psi, psi flux c_h^2 B^d, source
+                         -kappa_psi psi; the cleaning speeds -c_h, +c_h enter LLF and HLL */
 
 /* MHD reconstruction of the evolved fields (App. A, App. B) and interface
  * flux (Sec. II.B.2) */
@@ -103,6 +106,8 @@ typedef struct {
     double gd_eta;
     int mhd_recon;        /* MOL_RECON_* */
     int mhd_flux;         /* MOL_FLUX_* */
+    double mhd_ch;        /* MOL_MHD_GLM: cleaning speed c_h (>= 0) */
+    double mhd_kpsi;      /* MOL_MHD_GLM: damping kappa_psi (>= 0) */
 } mol_system_desc;
 
 typedef struct mol_patchset mol_patchset;

@@ -18,7 +18,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 WAVE, MHD, CCZ4, MHD_GLM = 0, 1, 2, 3
 RK4, SSPRK3 = 0, 1
-NFIELDS = {WAVE: 2, MHD: 8, CCZ4: 25}
+NFIELDS = {WAVE: 2, MHD: 8, CCZ4: 25, MHD_GLM: 9}
 
 
 class Params(ctypes.Structure):

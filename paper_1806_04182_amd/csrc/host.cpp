@@ -263,7 +263,8 @@ void default_tile(int system, int64_t level_points, int td[3])
             td[2] = 2;
         }
         break;
-    case MOL_MHD: td[0] = 15; td[1] = 15; td[2] = 8; break;  // 15 x 15 columns, 8 planes (z-marching)
+    case MOL_MHD:
+    case MOL_MHD_GLM: td[0] = 15; td[1] = 15; td[2] = 8; break;  // 15 x 15 columns, 8 planes (z-marching)
     default: td[0] = MOL_CCZ4_TX; td[1] = MOL_CCZ4_TY; td[2] = MOL_CCZ4_TZ; break;
     }
 }
@@ -804,12 +805,13 @@ int mol_create_patchset(const mol_hierarchy_desc* h, const mol_system_desc* s, m
     if (!(h->dx0 > 0.0)) return fail(MOL_EINVAL, "dx0 must be positive");
     for (int d = 0; d < 3; ++d)
         if (h->N0[d] < 1) return fail(MOL_EINVAL, "N0[%d] must be >= 1", d);
-    if (s->system != MOL_WAVE && s->system != MOL_MHD && s->system != MOL_CCZ4)
+    if (s->system != MOL_WAVE && s->system != MOL_MHD && s->system != MOL_CCZ4 && s->system != MOL_MHD_GLM)
         return fail(MOL_EINVAL, "unknown system %d", s->system);
+    const bool mhd = s->system == MOL_MHD || s->system == MOL_MHD_GLM;
     mol_patchset* ps = new (std::nothrow) mol_patchset();
     if (!ps) return fail(MOL_ENOMEM, "host allocation failed");
     ps->sp.system = s->system;
-    ps->sp.nf = s->system == MOL_WAVE ? 2 : s->system == MOL_MHD ? 8 : 25;
+    ps->sp.nf = s->system == MOL_WAVE ? 2 : s->system == MOL_MHD ? 8 : s->system == MOL_MHD_GLM ? 9 : 25;
     ps->sp.upwind = s->upwind;
     ps->sp.sigma = s->sigma;
     ps->sp.gamma_ad = s->gamma_ad;
@@ -823,11 +825,17 @@ int mol_create_patchset(const mol_hierarchy_desc* h, const mol_system_desc* s, m
     ps->sp.gd_eta = s->gd_eta;
     ps->sp.mhd_recon = s->mhd_recon;
     ps->sp.mhd_flux = s->mhd_flux;
-    if (s->system == MOL_MHD && !(s->gamma_ad > 1.0)) {
+    ps->sp.mhd_ch = s->mhd_ch;
+    ps->sp.mhd_kpsi = s->mhd_kpsi;
+    if (s->system == MOL_MHD_GLM && !(s->mhd_ch >= 0.0 && s->mhd_kpsi >= 0.0)) {
+        delete ps;
+        return fail(MOL_EINVAL, "c_h and kappa_psi must be non-negative");
+    }
+    if (mhd && !(s->gamma_ad > 1.0)) {
         delete ps;
         return fail(MOL_EINVAL, "gamma_ad must exceed 1");
     }
-    if (s->system == MOL_MHD && (s->mhd_recon < MOL_RECON_WENO5Z || s->mhd_recon > MOL_RECON_WENO3 ||
+    if (mhd && (s->mhd_recon < MOL_RECON_WENO5Z || s->mhd_recon > MOL_RECON_WENO3 ||
                                  (s->mhd_flux != MOL_FLUX_LLF && s->mhd_flux != MOL_FLUX_HLL))) {
         delete ps;
         return fail(MOL_EINVAL, "unknown MHD reconstruction %d or flux %d", s->mhd_recon, s->mhd_flux);
@@ -1167,7 +1175,8 @@ int mol_ccz4_lapse_pulse_vjp(mol_patchset* ps, int level, const double prm[5], c
 int mol_advance(mol_patchset* ps, const mol_level_state* states, double dt0, int mode, void* stream)
 {
     if (!ps) return fail(MOL_EINVAL, "null patchset");
-    if (ps->sp.system != MOL_WAVE && ps->sp.system != MOL_CCZ4 && ps->sp.system != MOL_MHD)
+    if (ps->sp.system != MOL_WAVE && ps->sp.system != MOL_CCZ4 && ps->sp.system != MOL_MHD &&
+        ps->sp.system != MOL_MHD_GLM)
         return fail(MOL_EINVAL, "unknown system");
     if (!std::isfinite(dt0) || dt0 <= 0.0) return fail(MOL_EINVAL, "dt must be positive and finite");
     const int launch = mode & 15, tmode = mode & ~15;

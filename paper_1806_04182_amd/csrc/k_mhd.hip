@@ -7,8 +7,11 @@
 // F = (F(U^L) + F(U^R) - S (U^R - U^L)) / 2, S the larger of |v_d| + c_f over
 // the two states (fast magnetosonic speed c_f), or the HLL flux
 // F = (S^R F^L - S^L F^R + S^R S^L (U^R - U^L)) / (S^R - S^L) with
-// S^L = min(v_d - c_f, 0), S^R = max(v_d + c_f, 0) over the two states.  Fused
-// with the Runge-Kutta stage update.
+// S^L = min(v_d - c_f, 0), S^R = max(v_d + c_f, 0) over the two states.  With
+// the divergence-cleaning scalar psi (nine fields) the B^i flux along d gains
+// delta^{di} psi, psi has the flux c_h^2 B^d and the source -kappa_psi psi, and
+// the cleaning speeds -c_h, +c_h join the signal speeds.  Fused with the
+// Runge-Kutta stage update.
 #include "k_common.h"
 
 namespace mol {
@@ -20,6 +23,7 @@ struct MhdConst {
     double eps[3];
     double q;
     double ih;  // 1 / dx
+    double ch2, ch, kpsi;  // cleaning: c_h^2, c_h, kappa_psi
 };
 
 // WENO5-Z value at the interface to the right of v[2] reconstructed from the
@@ -133,29 +137,42 @@ __device__ __forceinline__ void flux(const double U[8], int d, double gam, doubl
 // Interface flux between cells 2 and 3 of a six-cell line; get(f, m) returns
 // cell m (0..5) of field f.  Left state reconstructed around cell 2, right
 // state around cell 3 (the left formula on mirrored cells).
-template <int REC, int RS, bool Q2, class Get>
-__device__ __forceinline__ void riemann6(Get get, int d, const MhdConst& C, double Fh[8])
+template <int NF, int REC, int RS, bool Q2, class Get>
+__device__ __forceinline__ void riemann6(Get get, int d, const MhdConst& C, double Fh[NF])
 {
-    double UL[8], UR[8];
+    double UL[NF], UR[NF];
 #pragma unroll
-    for (int f = 0; f < 8; ++f) {
+    for (int f = 0; f < NF; ++f) {
         const double c0 = get(f, 0), c1 = get(f, 1), c2 = get(f, 2), c3 = get(f, 3), c4 = get(f, 4),
                      c5 = get(f, 5);
         UL[f] = recon<REC, Q2>(c0, c1, c2, c3, c4, C.eps[d], C.q);
         UR[f] = recon<REC, Q2>(c5, c4, c3, c2, c1, C.eps[d], C.q);
     }
-    double FL[8], FR[8], vL, cL, vR, cR;
+    double FL[NF], FR[NF], vL, cL, vR, cR;
     flux(UL, d, C.gam, FL, vL, cL);
     flux(UR, d, C.gam, FR, vR, cR);
+    if constexpr (NF == 9) {
+        FL[5 + d] += UL[8];
+        FR[5 + d] += UR[8];
+        FL[8] = C.ch2 * UL[5 + d];
+        FR[8] = C.ch2 * UR[5 + d];
+    }
     if constexpr (RS == RS_HLL) {
-        const double SL = fmin(fmin(vL - cL, vR - cR), 0.0), SR = fmax(fmax(vL + cL, vR + cR), 0.0);
+        double SL = fmin(vL - cL, vR - cR), SR = fmax(vL + cL, vR + cR);
+        if constexpr (NF == 9) {
+            SL = fmin(SL, -C.ch);
+            SR = fmax(SR, C.ch);
+        }
+        SL = fmin(SL, 0.0);
+        SR = fmax(SR, 0.0);
         const double id = 1.0 / (SR - SL), SRL = SR * SL;
 #pragma unroll
-        for (int f = 0; f < 8; ++f) Fh[f] = (SR * FL[f] - SL * FR[f] + SRL * (UR[f] - UL[f])) * id;
+        for (int f = 0; f < NF; ++f) Fh[f] = (SR * FL[f] - SL * FR[f] + SRL * (UR[f] - UL[f])) * id;
     } else {
-        const double S = fmax(fabs(vL) + cL, fabs(vR) + cR);
+        double S = fmax(fabs(vL) + cL, fabs(vR) + cR);
+        if constexpr (NF == 9) S = fmax(S, C.ch);
 #pragma unroll
-        for (int f = 0; f < 8; ++f) Fh[f] = 0.5 * (FL[f] + FR[f] - S * (UR[f] - UL[f]));
+        for (int f = 0; f < NF; ++f) Fh[f] = 0.5 * (FL[f] + FR[f] - S * (UR[f] - UL[f]));
     }
 }
 
@@ -173,12 +190,12 @@ constexpr int MB = MT + 1;       // threads per tile edge
 constexpr int MH = MT + 6;       // plane width with halo
 constexpr int MP = MH + 1;       // LDS row pitch
 
-template <int REC, int RS, bool Q2>
+template <int NF, int REC, int RS, bool Q2>
 __global__ __launch_bounds__(MB * MB) void mhd_stage_kernel(StageArgs a, MhdConst C, int zc)
 {
-    __shared__ double pl[8][MH][MP];
-    __shared__ double fx[8][MT][MB];
-    __shared__ double fy[8][MB][MT];
+    __shared__ double pl[NF][MH][MP];
+    __shared__ double fx[NF][MT][MB];
+    __shared__ double fy[NF][MB][MT];
     const Tile tile = a.tiles[xcd_tile(blockIdx.x, gridDim.x)];
     const PatchDev P = a.patches[tile.patch];
     const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + MB * ty;
@@ -191,57 +208,59 @@ __global__ __launch_bounds__(MB * MB) void mhd_stage_kernel(StageArgs a, MhdCons
     const int64_t colbase = P.off + (int64_t)(y0 + ty + G) * P.pitch_y + (x0 + tx + G);
     const double* __restrict__ Us = a.Us;
 
-    double w[8][6];  // cells k-2 .. k+3 of the own column
-    double Fm[8];    // z-flux below the current plane
+    double w[NF][6];  // cells k-2 .. k+3 of the own column
+    double Fm[NF];    // z-flux below the current plane
     if (col) {
-        double c7[8][7];
+        double c7[NF][7];
 #pragma unroll
-        for (int f = 0; f < 8; ++f)
+        for (int f = 0; f < NF; ++f)
 #pragma unroll
             for (int m = 0; m < 7; ++m) c7[f][m] = Us[colbase + f * fs + (int64_t)(z0 - 3 + m + G) * sz];
 #pragma unroll
-        for (int f = 0; f < 8; ++f)
+        for (int f = 0; f < NF; ++f)
 #pragma unroll
             for (int m = 0; m < 6; ++m) w[f][m] = c7[f][m + 1];
-        riemann6<REC, RS, Q2>([&](int f, int m) { return c7[f][m]; }, 2, C, Fm);
+        riemann6<NF, REC, RS, Q2>([&](int f, int m) { return c7[f][m]; }, 2, C, Fm);
     }
     for (int k = z0; k < z1; ++k) {
         // stage plane k with its x/y halo
         const int64_t pbase = P.off + (int64_t)(k + G) * sz + (int64_t)y0 * P.pitch_y + x0;
-        for (int e = tid; e < 8 * MH * MH; e += MB * MB) {
+        for (int e = tid; e < NF * MH * MH; e += MB * MB) {
             const int f = e / (MH * MH), r = e - f * MH * MH, hy = r / MH, hx = r - hy * MH;
             const bool ok = x0 + hx < P.n[0] + 2 * G && y0 + hy < P.n[1] + 2 * G;
             pl[f][hy][hx] = ok ? Us[pbase + f * fs + (int64_t)hy * P.pitch_y + hx] : 0.0;
         }
         __syncthreads();
         // x-interface to the left of column (tx, ty): cells tx-3 .. tx+2 of row ty
-        double Fp[8];
-        if (col) riemann6<REC, RS, Q2>([&](int f, int m) { return w[f][m]; }, 2, C, Fp);
+        double Fp[NF];
+        if (col) riemann6<NF, REC, RS, Q2>([&](int f, int m) { return w[f][m]; }, 2, C, Fp);
         if (ty < MT && x0 + tx <= P.n[0] && y0 + ty < P.n[1]) {
-            double F[8];
-            riemann6<REC, RS, Q2>([&](int f, int m) { return pl[f][ty + G][tx + m]; }, 0, C, F);
+            double F[NF];
+            riemann6<NF, REC, RS, Q2>([&](int f, int m) { return pl[f][ty + G][tx + m]; }, 0, C, F);
 #pragma unroll
-            for (int f = 0; f < 8; ++f) fx[f][ty][tx] = F[f];
+            for (int f = 0; f < NF; ++f) fx[f][ty][tx] = F[f];
         }
         // y-interface below column (tx, ty)
         if (tx < MT && y0 + ty <= P.n[1] && x0 + tx < P.n[0]) {
-            double F[8];
-            riemann6<REC, RS, Q2>([&](int f, int m) { return pl[f][ty + m][tx + G]; }, 1, C, F);
+            double F[NF];
+            riemann6<NF, REC, RS, Q2>([&](int f, int m) { return pl[f][ty + m][tx + G]; }, 1, C, F);
 #pragma unroll
-            for (int f = 0; f < 8; ++f) fy[f][ty][tx] = F[f];
+            for (int f = 0; f < NF; ++f) fy[f][ty][tx] = F[f];
         }
         __syncthreads();
         if (col) {
             const int64_t cidx = colbase + (int64_t)(k + G) * sz;
 #pragma unroll
-            for (int f = 0; f < 8; ++f) {
+            for (int f = 0; f < NF; ++f) {
                 const double div = (fx[f][ty][tx + 1] - fx[f][ty][tx]) + (fy[f][ty + 1][tx] - fy[f][ty][tx]) +
                                    (Fp[f] - Fm[f]);
-                stage_store(a, cidx + f * fs, -div * C.ih);
+                // psi: the damping source at the cell (w[8][2] is plane k of the column)
+                const double rhs = f == 8 ? -div * C.ih - C.kpsi * w[f][2] : -div * C.ih;
+                stage_store(a, cidx + f * fs, rhs);
             }
             if (k + 1 < z1) {
 #pragma unroll
-                for (int f = 0; f < 8; ++f) {
+                for (int f = 0; f < NF; ++f) {
 #pragma unroll
                     for (int m = 0; m < 5; ++m) w[f][m] = w[f][m + 1];
                     w[f][5] = Us[colbase + f * fs + (int64_t)(k + 4 + G) * sz];
@@ -251,6 +270,32 @@ __global__ __launch_bounds__(MB * MB) void mhd_stage_kernel(StageArgs a, MhdCons
         }
         __syncthreads();
     }
+}
+
+template <int NF>
+hipError_t dispatch(const SysParams& sp, const StageArgs& a, const MhdConst& C, int zc, hipStream_t s)
+{
+    const dim3 g(a.ntiles), b(MB, MB, 1);
+    const bool hll = sp.mhd_flux == MOL_FLUX_HLL;
+    switch (sp.mhd_recon) {
+    case MOL_RECON_WENO3:
+        if (hll) mhd_stage_kernel<NF, REC_W3, RS_HLL, true><<<g, b, 0, s>>>(a, C, zc);
+        else mhd_stage_kernel<NF, REC_W3, RS_LLF, true><<<g, b, 0, s>>>(a, C, zc);
+        break;
+    case MOL_RECON_WENO5JS:
+        if (hll) mhd_stage_kernel<NF, REC_W5JS, RS_HLL, true><<<g, b, 0, s>>>(a, C, zc);
+        else mhd_stage_kernel<NF, REC_W5JS, RS_LLF, true><<<g, b, 0, s>>>(a, C, zc);
+        break;
+    default:
+        if (C.q == 2.0) {
+            if (hll) mhd_stage_kernel<NF, REC_W5Z, RS_HLL, true><<<g, b, 0, s>>>(a, C, zc);
+            else mhd_stage_kernel<NF, REC_W5Z, RS_LLF, true><<<g, b, 0, s>>>(a, C, zc);
+        } else {
+            if (hll) mhd_stage_kernel<NF, REC_W5Z, RS_HLL, false><<<g, b, 0, s>>>(a, C, zc);
+            else mhd_stage_kernel<NF, REC_W5Z, RS_LLF, false><<<g, b, 0, s>>>(a, C, zc);
+        }
+    }
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -266,27 +311,11 @@ hipError_t launch_stage_mhd(const SysParams& sp, const StageArgs& a, const int t
     C.q = sp.weno_q;
     C.ih = 1.0 / sp.h;
     if (td[0] != MT || td[1] != MT) return hipErrorInvalidConfiguration;
-    const dim3 g(a.ntiles), b(MB, MB, 1);
-    const bool hll = sp.mhd_flux == MOL_FLUX_HLL;
-    switch (sp.mhd_recon) {
-    case MOL_RECON_WENO3:
-        if (hll) mhd_stage_kernel<REC_W3, RS_HLL, true><<<g, b, 0, s>>>(a, C, td[2]);
-        else mhd_stage_kernel<REC_W3, RS_LLF, true><<<g, b, 0, s>>>(a, C, td[2]);
-        break;
-    case MOL_RECON_WENO5JS:
-        if (hll) mhd_stage_kernel<REC_W5JS, RS_HLL, true><<<g, b, 0, s>>>(a, C, td[2]);
-        else mhd_stage_kernel<REC_W5JS, RS_LLF, true><<<g, b, 0, s>>>(a, C, td[2]);
-        break;
-    default:
-        if (C.q == 2.0) {
-            if (hll) mhd_stage_kernel<REC_W5Z, RS_HLL, true><<<g, b, 0, s>>>(a, C, td[2]);
-            else mhd_stage_kernel<REC_W5Z, RS_LLF, true><<<g, b, 0, s>>>(a, C, td[2]);
-        } else {
-            if (hll) mhd_stage_kernel<REC_W5Z, RS_HLL, false><<<g, b, 0, s>>>(a, C, td[2]);
-            else mhd_stage_kernel<REC_W5Z, RS_LLF, false><<<g, b, 0, s>>>(a, C, td[2]);
-        }
-    }
-    return hipGetLastError();
+    C.ch = sp.mhd_ch;
+    C.ch2 = sp.mhd_ch * sp.mhd_ch;
+    C.kpsi = sp.mhd_kpsi;
+    if (sp.system == MOL_MHD_GLM) return dispatch<9>(sp, a, C, td[2], s);
+    return dispatch<8>(sp, a, C, td[2], s);
 }
 
 }  // namespace mol

@@ -107,6 +107,7 @@ struct SysParams {
     double h;  // grid spacing of the level (isotropic)
     double sigma, gamma_ad, weno_eps, weno_q, kappa_z, kappa_c, bm_f0, bm_f1, gd_g, gd_eta;
     int mhd_recon, mhd_flux;
+    double mhd_ch, mhd_kpsi;
 };
 
 // What the fused stage kernels do after evaluating k = dt * rhs.
@@ -134,7 +135,8 @@ inline hipError_t launch_stage(const SysParams& sp, const StageArgs& a, const in
 {
     switch (sp.system) {
     case MOL_WAVE: return launch_stage_wave(sp, a, tdim, s);
-    case MOL_MHD: return launch_stage_mhd(sp, a, tdim, s);
+    case MOL_MHD:
+    case MOL_MHD_GLM: return launch_stage_mhd(sp, a, tdim, s);
     default: return launch_stage_ccz4(sp, a, tdim, s);
     }
 }

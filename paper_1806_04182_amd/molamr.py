@@ -17,7 +17,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("MOLAMR_LIB", os.path.join(HERE, "libmolamr.so"))
 
-MOL_WAVE, MOL_MHD, MOL_CCZ4 = 0, 1, 2
+MOL_WAVE, MOL_MHD, MOL_CCZ4, MOL_MHD_GLM = 0, 1, 2, 3
 MOL_RK4, MOL_SSPRK3 = 0, 1
 MOL_BATCHED, MOL_PLAIN = 0, 1
 MOL_RECON_WENO5Z, MOL_RECON_WENO5JS, MOL_RECON_WENO3 = 0, 1, 2
@@ -25,7 +25,7 @@ MOL_FLUX_LLF, MOL_FLUX_HLL = 0, 1
 # time-refinement strategies (Sec. III.B), or-ed into the mode of advance()
 MOL_TIME_BOR, MOL_TIME_BO, MOL_TIME_BO1, MOL_TIME_NOSUB = 0, 16, 32, 48
 GHOST = 3
-NFIELDS = {MOL_WAVE: 2, MOL_MHD: 8, MOL_CCZ4: 25}
+NFIELDS = {MOL_WAVE: 2, MOL_MHD: 8, MOL_CCZ4: 25, MOL_MHD_GLM: 9}
 
 
 class MolError(RuntimeError):
@@ -44,7 +44,8 @@ class _Sys(ctypes.Structure):
     _fields_ = [("system", ctypes.c_int), ("upwind", ctypes.c_int)] + [
         (n, ctypes.c_double) for n in ("sigma", "gamma_ad", "weno_eps", "weno_q", "kappa_z", "kappa_c",
                                        "bm_f0", "bm_f1", "gd_g", "gd_eta")] + [
-        ("mhd_recon", ctypes.c_int), ("mhd_flux", ctypes.c_int)]
+        ("mhd_recon", ctypes.c_int), ("mhd_flux", ctypes.c_int), ("mhd_ch", ctypes.c_double),
+        ("mhd_kpsi", ctypes.c_double)]
 
 
 class _LevelState(ctypes.Structure):
@@ -148,11 +149,13 @@ class System:
     upwind: int = 1
     mhd_recon: int = 0  # MOL_RECON_*
     mhd_flux: int = 0   # MOL_FLUX_*
+    mhd_ch: float = 1.0    # MOL_MHD_GLM cleaning speed
+    mhd_kpsi: float = 0.0  # MOL_MHD_GLM damping
 
     def _c(self) -> _Sys:
         return _Sys(self.system, int(self.upwind), self.sigma, self.gamma_ad, self.weno_eps, self.weno_q,
                     self.kappa_z, self.kappa_c, self.bm_f0, self.bm_f1, self.gd_g, self.gd_eta,
-                    int(self.mhd_recon), int(self.mhd_flux))
+                    int(self.mhd_recon), int(self.mhd_flux), self.mhd_ch, self.mhd_kpsi)
 
 
 @dataclass

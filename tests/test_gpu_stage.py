@@ -113,6 +113,30 @@ def test_mhd_variants_parity(recon, flux, kind, n):
     assert np.all(e <= TOL), e
 
 
+@pytest.mark.parametrize("recon,flux", [(M.MOL_RECON_WENO5Z, M.MOL_FLUX_LLF), (M.MOL_RECON_WENO5Z, M.MOL_FLUX_HLL),
+                                        (M.MOL_RECON_WENO3, M.MOL_FLUX_HLL)])
+@pytest.mark.parametrize("kind,n", [("smooth", (20, 17, 11)), ("jump", (46, 31, 17))])
+def test_mhd_glm_parity(recon, flux, kind, n):
+    """Nine fields with the cleaning scalar psi (random, O(0.05)): fluxes,
+    cleaning speeds and the -kappa_psi psi source against the oracle."""
+    print("mhd glm", recon, flux, kind, n, flush=True)
+    if kind == "smooth":
+        N = (max(n[0], 8),) * 3
+        st, dx, gam = synth.mhd_ot_like(n, seed=1, N=N), 1.0 / N[0], 5.0 / 3.0
+    else:
+        st, dx, gam = _jump_state(n), 1.0 / n[0], 2.0
+    psi = 0.05 * np.random.default_rng(3).standard_normal((1,) + st.shape[1:])
+    U0 = synth.embed(np.concatenate([st, psi]))
+    sysd = M.System(M.MOL_MHD_GLM, sigma=0.0, gamma_ad=gam, mhd_recon=recon, mhd_flux=flux, mhd_ch=1.7,
+                    mhd_kpsi=0.8)
+    prm = O.params(sigma=0.0, gamma_ad=gam, mhd_recon=float(recon), mhd_riemann=float(flux), mhd_ch=1.7,
+                   mhd_kpsi=0.8)
+    got = _gpu_steps(O.MHD_GLM, M.MOL_SSPRK3, U0, dx, 0.1 * dx, 2, sysd)
+    ref = _oracle_steps(O.MHD_GLM, O.SSPRK3, U0, dx, 0.1 * dx, 2, prm)
+    e = parity_err(got[:, 3:-3, 3:-3, 3:-3], ref[:, 3:-3, 3:-3, 3:-3])
+    assert np.all(e <= TOL), e
+
+
 def _ccz4_state(n, kind, seed=0):
     dx = 2.0 / max(n)
     if kind == "noise":
