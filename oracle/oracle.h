@@ -108,6 +108,11 @@ double orc_dense_rk4(int j, int m, double theta);
  * out[i] = state of fine step r (0..R-1), fine stage s (1..4) for i < n. */
 void orc_bor_rk4(int R, int r, int s, double dt, const double* Un,
                  const double* const* k, double* out, long n);
+/* the same for SSP-RK(3,3): its dense output (App. C, j = 0..2) and BOR
+ * (App. D) from U^n and k_1..k_3, fine stage s = 1..3 */
+double orc_dense_ssp3(int j, int m, double theta);
+void orc_bor_ssp3(int R, int r, int s, double dt, const double* Un,
+                  const double* const* k, double* out, long n);
 
 /* ---- Lagrange prolongation (Sec. III.A) ---- */
 /* weights of the 6-point Lagrange polynomial through nodes -2..3 at xi */
@@ -130,13 +135,17 @@ void orc_hier_get(const orc_hier* H, int l, int p, double* dst);
 /* ghost points of level l that have a same-level source (periodic images
  * included): copy it.  Acts on the current state. */
 void orc_hier_fill_same(orc_hier* H, int l);
-/* one sub-cycled RK4 coarse step with BOR prolongation and injection */
+/* one sub-cycled coarse step (RK4 or SSP-RK3) with prolongation and injection */
 void orc_hier_step(orc_hier* H, double dt0, const orc_params* p);
 /* time refinement of the sub-cycled step (Sec. III.B); BOR by default */
 enum { ORC_TIME_BOR = 0, ORC_TIME_BO = 1, ORC_TIME_BO1 = 2, ORC_TIME_NOSUB = 3 };
 void orc_hier_set_time_mode(orc_hier* H, int mode);
 void orc_time_state(int mode, int R, int r, int s, double dt, const double* Un,
                     const double* const* k, double* out, long n);
+void orc_time_state_ssp3(int mode, int R, int r, int s, double dt, const double* Un,
+                         const double* const* k, double* out, long n);
+/* integrator of the sub-cycled step: ORC_RK4 (default) or ORC_SSPRK3 */
+void orc_hier_set_scheme(orc_hier* H, int scheme);
 /* the pieces, for the unit checks: prolong into level l (>0) at fine step r,
  * stage s, from the parent's saved U^n and k's (set with orc_hier_set_parent) */
 void orc_hier_set_parent_data(orc_hier* H, int l, int p, const double* Un,

@@ -101,6 +101,10 @@ def lib():
         L.orc_hier_fill_same.argtypes = [vp, i]
         L.orc_hier_step.argtypes = [vp, d, P]
         L.orc_hier_set_time_mode.argtypes = [vp, i]
+        L.orc_hier_set_scheme.argtypes = [vp, i]
+        L.orc_time_state_ssp3.argtypes = [i, i, i, i, d, dp, ctypes.POINTER(dp), dp, lng]
+        L.orc_dense_ssp3.argtypes = [i, i, d]
+        L.orc_dense_ssp3.restype = d
         L.orc_time_state.argtypes = [i, i, i, i, d, dp, ctypes.POINTER(dp), dp, lng]
         L.orc_hier_set_parent_data.argtypes = [vp, i, i, dp, dp, dp, dp, dp]
         L.orc_hier_prolong.argtypes = [vp, i, i, i, d]
@@ -300,6 +304,10 @@ class Hierarchy:
     def set_time_mode(self, mode: int) -> None:
         lib().orc_hier_set_time_mode(self._h, mode)
 
+    def set_scheme(self, scheme: int) -> None:
+        """RK4 (default) or SSPRK3 for the sub-cycled step."""
+        lib().orc_hier_set_scheme(self._h, scheme)
+
     def set_parent_data(self, l: int, p: int, Un, k) -> None:
         arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in [Un] + list(k)]
         lib().orc_hier_set_parent_data(self._h, l, p, *[_p(a) for a in arrs])
@@ -346,10 +354,15 @@ def ccz4_rhs_vjp_periodic(U: np.ndarray, lam: np.ndarray, h, prm: Params | None 
     return out
 
 
-def time_state(mode: int, R: int, r: int, s: int, dt: float, Un: np.ndarray, k) -> np.ndarray:
+def time_state(mode: int, R: int, r: int, s: int, dt: float, Un: np.ndarray, k, scheme: int = 0) -> np.ndarray:
     """Parent state feeding fine step r, stage s for a time-refinement mode."""
     out = np.zeros_like(Un)
     arr = (ctypes.POINTER(ctypes.c_double) * 4)(*[_p(np.ascontiguousarray(kk)) for kk in k])
-    lib().orc_time_state(mode, R, r, s, dt, _p(Un), arr, _p(out), Un.size)
+    fn = lib().orc_time_state_ssp3 if scheme == SSPRK3 else lib().orc_time_state
+    fn(mode, R, r, s, dt, _p(Un), arr, _p(out), Un.size)
     return out
+
+
+def dense_ssp3(j: int, m: int, theta: float) -> float:
+    return lib().orc_dense_ssp3(j, m, theta)
 

@@ -83,6 +83,89 @@ void orc_bor_rk4(int R, int r, int s, double dt, const double* Un,
     }
 }
 
+/* App. C, SSP-RK(3,3) dense output b_j(theta), j = 0..2, and its derivatives. */
+double orc_dense_ssp3(int j, int m, double t)
+{
+    /* coefficients of theta, theta^2 */
+    static const double cf[3][2] = {{1.0, -5.0 / 6.0}, {0.0, 1.0 / 6.0}, {0.0, 4.0 / 6.0}};
+    const double* a = cf[j];
+    switch (m) {
+    case 0: return a[0] * t + a[1] * t * t;
+    case 1: return a[0] + 2.0 * a[1] * t;
+    case 2: return 2.0 * a[1];
+    }
+    return 0.0;
+}
+
+/* App. D, SSP-RK3 with ratio R, fine step r, fine stage s:
+ *  1. U_{n+r/R} from the dense output at theta = r/R;
+ *  2. U', U'' from its theta-derivatives;
+ *  3. the fine k_1 = dt_F U', k_2 = dt_F U' + dt_F^2 U'',
+ *     k_3 = dt_F U' + dt_F^2 U''/2, dt_F = dt / R;
+ *  4. the fine stage states U, U + k_1, U + (k_1 + k_2)/4 (the stage states
+ *     of the SSP-RK3 tableau). */
+void orc_bor_ssp3(int R, int r, int s, double dt, const double* Un,
+                  const double* const* k, double* out, long n)
+{
+    double th = (double)r / (double)R;
+    double dtF = dt / R;
+    double b[3][3];
+    for (int m = 0; m < 3; ++m)
+        for (int j = 0; j < 3; ++j) b[m][j] = orc_dense_ssp3(j, m, th);
+    for (long i = 0; i < n; ++i) {
+        double U = Un[i], U1 = 0.0, U2 = 0.0;
+        for (int j = 0; j < 3; ++j) {
+            U += b[0][j] * k[j][i];
+            U1 += b[1][j] * k[j][i];
+            U2 += b[2][j] * k[j][i];
+        }
+        U1 /= dt;
+        U2 /= dt * dt;
+        double k1 = dtF * U1;
+        double k2 = dtF * U1 + dtF * dtF * U2;
+        switch (s) {
+        case 1: out[i] = U; break;
+        case 2: out[i] = U + k1; break;
+        default: out[i] = U + 0.25 * k1 + 0.25 * k2; break;
+        }
+    }
+}
+
+/* Sec. III.B for SSP-RK3 (stage times c = (0, 1, 1/2), weights (1, 1, 4)/6):
+ * BOR (orc_bor_ssp3), BO (its dense output at the stage time), BO1 (linear
+ * between U^n and U^{n+1}) and no sub-cycling (the parent's stage states
+ * U^n, U^n + k_1, U^n + (k_1 + k_2)/4). */
+void orc_time_state_ssp3(int mode, int R, int r, int s, double dt, const double* Un,
+                         const double* const* k, double* out, long n)
+{
+    static const double cs[3] = {0.0, 1.0, 0.5};
+    static const double cw[3] = {1.0 / 6.0, 1.0 / 6.0, 4.0 / 6.0};
+    if (mode == ORC_TIME_BOR) {
+        orc_bor_ssp3(R, r, s, dt, Un, k, out, n);
+        return;
+    }
+    const double th = (r + cs[s - 1]) / (double)R;
+    for (long i = 0; i < n; ++i) {
+        double u = Un[i];
+        switch (mode) {
+        case ORC_TIME_BO:
+            for (int j = 0; j < 3; ++j) u += orc_dense_ssp3(j, 0, th) * k[j][i];
+            break;
+        case ORC_TIME_BO1: {
+            double inc = 0.0;
+            for (int j = 0; j < 3; ++j) inc += cw[j] * k[j][i];
+            u += th * inc;
+            break;
+        }
+        default: /* ORC_TIME_NOSUB */
+            if (s == 2) u += k[0][i];
+            if (s == 3) u += 0.25 * k[0][i] + 0.25 * k[1][i];
+            break;
+        }
+        out[i] = u;
+    }
+}
+
 /* Sec. III.B: the parent's state that feeds the ghost points of fine step r,
  * stage s, for each time-refinement strategy (the parent stepped from U^n
  * with increments k_1..k_4 over dt; the fine stage s of step r sits at
@@ -157,6 +240,7 @@ typedef struct {
 struct orc_hier {
     int system, nf, nlev;
     int tmode;  /* time refinement (ORC_TIME_*) */
+    int scheme; /* ORC_RK4 or ORC_SSPRK3 */
     int N0[3];
     double xlo[3], dx0;
     olevel L[MAXLEV];
@@ -346,7 +430,10 @@ static double parent_state(orc_hier* H, int lp, pro_ctx* c, const int gc[3], int
     if (!c->D[q][off]) {
         const double* kk[4] = {P->k[0][q] + off, P->k[1][q] + off, P->k[2][q] + off,
                                P->k[3][q] + off};
-        orc_time_state(H->tmode, c->R, c->r, c->s, c->dtp, P->Un[q] + off, kk, c->T[q] + off, 1);
+        if (H->scheme == ORC_SSPRK3)
+            orc_time_state_ssp3(H->tmode, c->R, c->r, c->s, c->dtp, P->Un[q] + off, kk, c->T[q] + off, 1);
+        else
+            orc_time_state(H->tmode, c->R, c->r, c->s, c->dtp, P->Un[q] + off, kk, c->T[q] + off, 1);
         c->D[q][off] = 1;
     }
     return c->T[q][off];
@@ -441,15 +528,21 @@ void orc_hier_restrict(orc_hier* H, int l)
     }
 }
 
-/* Sec. III skeleton with sub-cycling: level l takes one RK4 step of size dt;
- * its children then take R steps of dt/R using BOR ghost values built from
- * this step's U^n and k's; the children's result is injected back. */
+/* Sec. III skeleton with sub-cycling: level l takes one step of size dt (RK4
+ * or SSP-RK3, U^(s) = U^n + sum_j a_sj k_j); its children then take R steps of
+ * dt/R using ghost values built from this step's U^n and k's; the children's
+ * result is injected back. */
 static void advance(orc_hier* H, int l, double dt, const orc_params* prm)
 {
     olevel* L = &H->L[l];
     int nf = H->nf;
-    static const double bsub[4] = {0.0, 0.5, 0.5, 1.0};
-    static const double cw[4] = {1.0 / 6.0, 2.0 / 6.0, 2.0 / 6.0, 1.0 / 6.0};
+    static const double a4[4][3] = {{0, 0, 0}, {0.5, 0, 0}, {0, 0.5, 0}, {0, 0, 1.0}};
+    static const double w4[4] = {1.0 / 6.0, 2.0 / 6.0, 2.0 / 6.0, 1.0 / 6.0};
+    static const double a3[4][3] = {{0, 0, 0}, {1.0, 0, 0}, {0.25, 0.25, 0}, {0, 0, 0}};
+    static const double w3[4] = {1.0 / 6.0, 1.0 / 6.0, 4.0 / 6.0, 0.0};
+    const int ns = H->scheme == ORC_SSPRK3 ? 3 : 4;
+    const double (*a)[3] = H->scheme == ORC_SSPRK3 ? a3 : a4;
+    const double* cw = H->scheme == ORC_SSPRK3 ? w3 : w4;
     double hh[3];
     double dxl = H->dx0;
     for (int m = 1; m <= l; ++m) dxl /= H->L[m].ratio;
@@ -457,11 +550,14 @@ static void advance(orc_hier* H, int l, double dt, const orc_params* prm)
 
     for (int p = 0; p < L->np; ++p)
         memcpy(L->Un[p], L->U[p], sizeof(double) * pvol(L->box + 6 * p) * nf);
-    for (int s = 0; s < 4; ++s) {
+    for (int s = 0; s < ns; ++s) {
         for (int p = 0; p < L->np; ++p) {
             long n = pvol(L->box + 6 * p) * nf;
-            for (long i = 0; i < n; ++i)
-                L->Us[p][i] = L->Un[p][i] + (s > 0 ? bsub[s] * L->k[s - 1][p][i] : 0.0);
+            for (long i = 0; i < n; ++i) {
+                double u = L->Un[p][i];
+                for (int j = 0; j < s; ++j) u += a[s][j] * L->k[j][p][i];
+                L->Us[p][i] = u;
+            }
         }
         fill_same_set(H, l, L->Us);
         if (l > 0) {
@@ -480,7 +576,7 @@ static void advance(orc_hier* H, int l, double dt, const orc_params* prm)
         long n = pvol(L->box + 6 * p) * nf;
         for (long i = 0; i < n; ++i) {
             double acc = 0.0;
-            for (int s = 0; s < 4; ++s) acc += cw[s] * L->k[s][p][i];
+            for (int s = 0; s < ns; ++s) acc += cw[s] * L->k[s][p][i];
             L->U[p][i] = L->Un[p][i] + acc;
         }
     }
@@ -497,6 +593,7 @@ static void advance(orc_hier* H, int l, double dt, const orc_params* prm)
 }
 
 void orc_hier_set_time_mode(orc_hier* H, int mode) { H->tmode = mode; }
+void orc_hier_set_scheme(orc_hier* H, int scheme) { H->scheme = scheme; }
 
 void orc_hier_step(orc_hier* H, double dt0, const orc_params* p)
 {

@@ -76,7 +76,7 @@ def test_bor_fine_stages_are_consistent(R):
     assert 3.5 < np.log2(errs[0] / errs[1]) < 5.0
 
 
-def _fmr_wave_run(N_unit, R, T=2.5, L=6.0, width=0.25, mode=O.TIME_BOR, window=None):
+def _fmr_wave_run(N_unit, R, T=2.5, L=6.0, width=0.25, mode=O.TIME_BOR, window=None, scheme=O.RK4):
     """1D wave (Sec. IV.A set-up, shortened): periodic x in [-2, -2 + L), pulse
     at x = 0, one refined level over [1, 2] with ratio R, RK4 with the given
     time refinement (BOR by default).  Returns the L1 error at T, or with
@@ -89,6 +89,7 @@ def _fmr_wave_run(N_unit, R, T=2.5, L=6.0, width=0.25, mode=O.TIME_BOR, window=N
               (R, [((R * lo_c, 0, 0), (R * hi_c, R - 1, R - 1))])]
     H = O.Hierarchy(O.WAVE, (N0, 1, 1), (-2.0, 0.0, 0.0), dx0, levels)
     H.set_time_mode(mode)
+    H.set_scheme(scheme)
 
     def exact(x, t):
         g = lambda s: np.exp(-(s ** 2) / width ** 2)
@@ -200,3 +201,67 @@ def test_restriction_is_injection_and_fill_same_is_copy():
     assert np.array_equal(c0[:, 3 + 5, 3 + 5, 3 + 4], c1[:, 3 + 5, 3 + 5, 3 + 0])
     # periodic ghost: x = -1 of patch 0 is x = 7 of patch 1
     assert np.array_equal(c0[:, 3 + 1, 3 + 1, 2], c1[:, 3 + 1, 3 + 1, 3 + 3])
+
+
+
+def _ssp3_stages(lam, u0, dt):
+    k1 = dt * lam * u0
+    k2 = dt * lam * (u0 + k1)
+    k3 = dt * lam * (u0 + 0.25 * k1 + 0.25 * k2)
+    return [k1, k2, k3], [u0, u0 + k1, u0 + 0.25 * k1 + 0.25 * k2]
+
+
+def test_ssp3_dense_output_end_values():
+    """App. C: b(0) = 0 and b(1) = the SSP-RK3 weights (1, 1, 4)/6."""
+    for j, w in enumerate((1 / 6, 1 / 6, 4 / 6)):
+        assert O.dense_ssp3(j, 0, 0.0) == 0.0
+        assert abs(O.dense_ssp3(j, 0, 1.0) - w) < 1e-16
+
+
+@pytest.mark.parametrize("R", [2, 3])
+def test_bor_ssp3_fine_stages_are_consistent(R):
+    """App. D for SSP-RK3: for u' = lam u the fine stage states of step r
+    approximate the SSP-RK3 stages started from the exact solution at
+    t^{n+r/R} with error O(dt^3) (the dense output is of 2nd order)."""
+    lam, u0 = -1.1, np.array([1.0])
+    errs = []
+    for dt in (0.1, 0.05):
+        k, _ = _ssp3_stages(lam, u0, dt)
+        e = 0.0
+        for r in range(R):
+            ur = u0 * np.exp(lam * dt * r / R)
+            _, ref = _ssp3_stages(lam, ur, dt / R)
+            for st in range(1, 4):
+                got = O.time_state(O.TIME_BOR, R, r, st, dt, u0, k, scheme=O.SSPRK3)
+                e = max(e, abs(got[0] - ref[st - 1][0]))
+        errs.append(e)
+    assert 2.6 < np.log2(errs[0] / errs[1]) < 3.6, errs
+
+
+def test_ssp3_time_states_reduce_to_known_values():
+    """SSP-RK3: every strategy gives U^n at fine step 0, stage 1; without
+    sub-cycling the states are the parent's stage states; BO and BO1 at
+    theta = 1 (last fine step, stage 2 at c = 1) give U^{n+1}."""
+    rng = np.random.default_rng(3)
+    Un = rng.standard_normal(7)
+    k = [rng.standard_normal(7) for _ in range(3)]
+    un1 = Un + (k[0] + k[1] + 4 * k[2]) / 6
+    for mode in (O.TIME_BOR, O.TIME_BO, O.TIME_BO1, O.TIME_NOSUB):
+        assert np.array_equal(O.time_state(mode, 2, 0, 1, 0.1, Un, k, scheme=O.SSPRK3), Un)
+    for st, ref in ((2, Un + k[0]), (3, Un + 0.25 * k[0] + 0.25 * k[1])):
+        got = O.time_state(O.TIME_NOSUB, 1, 0, st, 0.1, Un, k, scheme=O.SSPRK3)
+        assert np.allclose(got, ref, rtol=0, atol=1e-15)
+    for mode in (O.TIME_BO, O.TIME_BO1):
+        got = O.time_state(mode, 3, 2, 2, 0.1, Un, k, scheme=O.SSPRK3)
+        assert np.allclose(got, un1, rtol=0, atol=1e-14)
+
+
+def test_fmr_wave_ssp3_bor_converges_order3():
+    """The FMR wave with SSP-RK3 and BOR (App. D): the global error falls at
+    3rd order (the integrator's), with BO1 at 1st."""
+    errs = [_fmr_wave_run(n, 2, width=0.3, scheme=O.SSPRK3) for n in (12, 24, 48)]
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert 2.6 < orders[-1] < 4.2, (errs, orders)
+    errs = [_fmr_wave_run(n, 2, width=0.3, scheme=O.SSPRK3, mode=O.TIME_BO1) for n in (12, 24, 48)]
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert 0.7 < orders[-1] < 1.6, (errs, orders)
