@@ -287,6 +287,9 @@ def mhd_runs_bench(M):
         e = [R.brio_wu_error(R.brio_wu(N, fmr=fmr), ref, 3200) for N in (50, 100, 200, 400)]
         res["brio_wu"][fmr or "unigrid"] = {"N": [50, 100, 200, 400], "err_By": e}
         log(f"bench: Brio-Wu {fmr or 'unigrid'}: {e}")
+    e = [R.brio_wu_error(R.brio_wu(N, fmr="2/2", ssp3=True), ref, 3200) for N in (50, 100, 200, 400)]
+    res["brio_wu"]["2/2_ssprk3_bor"] = {"N": [50, 100, 200, 400], "err_By": e}
+    log(f"bench: Brio-Wu 2/2 with SSP-RK3 and BOR: {e}")
     res["wall_s"] = time.perf_counter() - t0
     return res
 

@@ -201,8 +201,18 @@ int mol_bor_weights(int R, int r, int stage, double w[4]);
 #define MOL_TIME_BO 16
 #define MOL_TIME_BO1 32
 #define MOL_TIME_NOSUB 48
+/* Or-ed into the mode of mol_advance (and into tmode of mol_time_weights):
+ * SSP-RK3 steps (App. D scheme, three stages) instead of RK4; the parent state
+ * of fine step r, stage s (1..3) is then built from the SSP-RK3 increments
+ * k_1..k_3 with the SSP dense output of App. C: BOR as in App. D (fine
+ * k_1 = dt_F U', k_2 = dt_F U' + dt_F^2 U''; stage states U, U + k_1,
+ * U + (k_1 + k_2)/4), BO at the stage time theta = (r + c_s)/R with
+ * c = (0, 1, 1/2), BO1 theta (1, 1, 4)/6, no sub-cycling the parent's stage
+ * states. */
+#define MOL_ADV_SSPRK3 64
 
-/* Weights w_1..w_4 of strategy `tmode` (one of MOL_TIME_*), host query; for
+/* Weights w_1..w_4 of strategy `tmode` (one of MOL_TIME_*, optionally or-ed
+ * with MOL_ADV_SSPRK3: then stage <= 3 and w_4 = 0), host query; for
  * MOL_TIME_NOSUB only R = 1 is valid.  MOL_EINVAL on bad arguments. */
 int mol_time_weights(int tmode, int R, int r, int stage, double w[4]);
 
@@ -292,11 +302,12 @@ typedef struct {
 #define MOL_BATCHED 0 /* one launch per level and operation (work list over all patches) */
 #define MOL_PLAIN 1   /* one launch per patch and operation */
 
-/* One RK4 step of size dt0 on level 0 with sub-cycling of the finer levels
- * (each level steps with dt / R of its parent), prolongation of the parent
- * state into the fine ghosts at every stage and injection; states[nlevels].
- * mode = MOL_BATCHED or MOL_PLAIN, or-ed with one MOL_TIME_* strategy
- * (MOL_TIME_BOR when none is given).  MOL_EINVAL on an unknown mode. */
+/* One RK4 (or, with MOL_ADV_SSPRK3, SSP-RK3) step of size dt0 on level 0
+ * with sub-cycling of the finer levels (each level steps with dt / R of its
+ * parent), prolongation of the parent state into the fine ghosts at every
+ * stage and injection; states[nlevels].  mode = MOL_BATCHED or MOL_PLAIN,
+ * or-ed with one MOL_TIME_* strategy (MOL_TIME_BOR when none is given) and
+ * optionally MOL_ADV_SSPRK3.  MOL_EINVAL on an unknown mode. */
 int mol_advance(mol_patchset* ps, const mol_level_state* states, double dt0, int mode,
                 void* stream);
 

@@ -627,7 +627,7 @@ void bor_weights(int R, int r, int s, double w[4])
 // theta = (r + c_s)/R, c = (0, 1/2, 1/2, 1) (App. C); linear Berger-Oliger,
 // theta (1, 2, 2, 1)/6; no sub-cycling (R = 1 in time), the parent's own
 // stage states.
-void time_weights(int tmode, int R, int r, int s, double w[4])
+void time_weights_rk4(int tmode, int R, int r, int s, double w[4])
 {
     static const double cs[4] = {0.0, 0.5, 0.5, 1.0};
     static const double cw[4] = {1.0 / 6.0, 2.0 / 6.0, 2.0 / 6.0, 1.0 / 6.0};
@@ -644,6 +644,43 @@ void time_weights(int tmode, int R, int r, int s, double w[4])
         }
     }
     if (tmode == MOL_TIME_BOR) bor_weights(R, r, s, w);
+}
+
+// The same for SSP-RK3 (App. C dense output b(theta) = (theta - 5/6 theta^2,
+// theta^2/6, 4/6 theta^2), stage times c = (0, 1, 1/2), weights (1, 1, 4)/6):
+// BOR (App. D) with theta = r/R, fine k_1 = b'/R and k_2 = b'/R + b''/R^2 in
+// units of the parent k's, stage states b, b + k_1, b + (k_1 + k_2)/4.
+void time_weights_ssp3(int tmode, int R, int r, int s, double w[4])
+{
+    static const double cs[3] = {0.0, 1.0, 0.5};
+    static const double cw[3] = {1.0 / 6.0, 1.0 / 6.0, 4.0 / 6.0};
+    w[3] = 0.0;
+    if (tmode == MOL_TIME_BOR) {
+        const double th = (double)r / R, iR = 1.0 / R;
+        const double b[3] = {th - (5.0 / 6.0) * th * th, th * th / 6.0, (4.0 / 6.0) * th * th};
+        const double b1[3] = {1.0 - (5.0 / 3.0) * th, th / 3.0, (4.0 / 3.0) * th};
+        const double b2[3] = {-5.0 / 3.0, 1.0 / 3.0, 4.0 / 3.0};
+        for (int j = 0; j < 3; ++j)
+            w[j] = s == 1 ? b[j] : s == 2 ? b[j] + b1[j] * iR : b[j] + 0.5 * b1[j] * iR + 0.25 * b2[j] * iR * iR;
+        return;
+    }
+    const double th = (r + cs[s - 1]) / R;
+    for (int j = 0; j < 3; ++j) {
+        switch (tmode) {
+        case MOL_TIME_BO: w[j] = j == 0 ? th - (5.0 / 6.0) * th * th : j == 1 ? th * th / 6.0 : (4.0 / 6.0) * th * th; break;
+        case MOL_TIME_BO1: w[j] = th * cw[j]; break;
+        default: w[j] = s == 2 ? (j == 0 ? 1.0 : 0.0) : s == 3 ? (j < 2 ? 0.25 : 0.0) : 0.0; break;
+        }
+    }
+}
+
+// mode bits: MOL_TIME_* (48) and MOL_ADV_SSPRK3
+void time_weights(int mode, int R, int r, int s, double w[4])
+{
+    if (mode & MOL_ADV_SSPRK3)
+        time_weights_ssp3(mode & 48, R, r, s, w);
+    else
+        time_weights_rk4(mode & 48, R, r, s, w);
 }
 
 hipStream_t S(void* s) { return (hipStream_t)s; }
@@ -699,7 +736,7 @@ int prolong_impl(mol_patchset* ps, int fl, int r, int stage, const double* Unc,
 {
     Level& lev = ps->L[fl];
     double w[4];
-    time_weights(tmode, tmode == MOL_TIME_NOSUB ? 1 : lev.ratio, r, stage, w);
+    time_weights(tmode, (tmode & 48) == MOL_TIME_NOSUB ? 1 : lev.ratio, r, stage, w);
     const int nf = ps->sp.nf;
     // BOR stage state on the parent band, then Lagrange interpolation from it
     const int nl = plain ? (int)lev.pd.size() : 1;
@@ -737,16 +774,22 @@ int restrict_impl(mol_patchset* ps, int fl, const double* Uf, double* Uc, hipStr
 // Sec. III skeleton with BOR sub-cycling: level l takes one RK4 step of size
 // dt; its finer level then takes R steps of dt/R whose coarse-fine ghosts
 // come from this step's U^n and k_1..k_4; the fine result is injected.
+// tmode: MOL_TIME_* or-ed with MOL_ADV_SSPRK3 for SSP-RK3 steps
 int advance_level(mol_patchset* ps, const mol_level_state* st, int l, int r, double dt,
                   hipStream_t s, int plain, int tmode)
 {
     const mol_level_state& X = st[l];
     const bool kids = l + 1 < ps->nlev;
     const int nf = ps->sp.nf;
-    double* stage_in[4] = {X.U, X.S0, X.S1, X.S0};
-    double* stage_out[4] = {X.S0, X.S1, X.S0, kids ? X.S1 : X.U};
+    const bool ssp = tmode & MOL_ADV_SSPRK3;
+    // RK4 (accumulator form) or SSP-RK3 (Shu-Osher form); while the children
+    // step, U keeps U^n and the new state waits in S1 (RK4) or S0 (SSP-RK3)
+    double* const stage_in[4] = {X.U, X.S0, X.S1, X.S0};
+    double* const stage_out[4] = {X.S0, X.S1, ssp ? (kids ? X.S0 : X.U) : X.S0, kids ? X.S1 : X.U};
+    double* const next = ssp ? X.S0 : X.S1;
+    const int nst = ssp ? 3 : 4;
     int rc;
-    for (int sidx = 0; sidx < 4; ++sidx) {
+    for (int sidx = 0; sidx < nst; ++sidx) {
         double* Us = stage_in[sidx];
         if ((rc = fill_impl(ps, l, Us, nf, s, plain))) return rc;
         if (l > 0) {
@@ -754,17 +797,17 @@ int advance_level(mol_patchset* ps, const mol_level_state* st, int l, int r, dou
             const double* kc[4] = {P.k[0], P.k[1], P.k[2], P.k[3]};
             if ((rc = prolong_impl(ps, l, r, sidx + 1, P.U, kc, Us, s, plain, tmode))) return rc;
         }
-        if ((rc = stage_impl(ps, l, ST_RK4, sidx + 1, dt, X.U, Us, X.acc, stage_out[sidx],
+        if ((rc = stage_impl(ps, l, ssp ? ST_SSP3 : ST_RK4, sidx + 1, dt, X.U, Us, X.acc, stage_out[sidx],
                              kids ? X.k[sidx] : nullptr, s, plain)))
             return rc;
     }
     if (kids) {
         // sub-cycling: R fine steps of dt/R; without it, one step of dt
-        const int R = tmode == MOL_TIME_NOSUB ? 1 : ps->L[l + 1].ratio;
+        const int R = (tmode & 48) == MOL_TIME_NOSUB ? 1 : ps->L[l + 1].ratio;
         for (int rr = 0; rr < R; ++rr)
             if ((rc = advance_level(ps, st, l + 1, rr, dt / R, s, plain, tmode))) return rc;
-        if ((rc = restrict_impl(ps, l + 1, st[l + 1].U, X.S1, s, plain))) return rc;
-        hipError_t e = hipMemcpyAsync(X.U, X.S1, sizeof(double) * ps->L[l].nelems,
+        if ((rc = restrict_impl(ps, l + 1, st[l + 1].U, next, s, plain))) return rc;
+        hipError_t e = hipMemcpyAsync(X.U, next, sizeof(double) * ps->L[l].nelems,
                                       hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
     }
@@ -934,9 +977,9 @@ int mol_bor_weights(int R, int r, int stage, double w[4])
 
 int mol_time_weights(int tmode, int R, int r, int stage, double w[4])
 {
-    if (tmode != MOL_TIME_BOR && tmode != MOL_TIME_BO && tmode != MOL_TIME_BO1 && tmode != MOL_TIME_NOSUB)
-        return fail(MOL_EINVAL, "unknown time-refinement strategy %d", tmode);
-    if (R < 1 || r < 0 || r >= R || stage < 1 || stage > 4 || !w || (tmode == MOL_TIME_NOSUB && R != 1))
+    if (tmode & ~(48 | MOL_ADV_SSPRK3)) return fail(MOL_EINVAL, "unknown time-refinement strategy %d", tmode);
+    const int nst = (tmode & MOL_ADV_SSPRK3) ? 3 : 4;
+    if (R < 1 || r < 0 || r >= R || stage < 1 || stage > nst || !w || ((tmode & 48) == MOL_TIME_NOSUB && R != 1))
         return fail(MOL_EINVAL, "bad time-weight arguments");
     time_weights(tmode, R, r, stage, w);
     return MOL_OK;
@@ -1180,8 +1223,7 @@ int mol_advance(mol_patchset* ps, const mol_level_state* states, double dt0, int
         return fail(MOL_EINVAL, "unknown system");
     if (!std::isfinite(dt0) || dt0 <= 0.0) return fail(MOL_EINVAL, "dt must be positive and finite");
     const int launch = mode & 15, tmode = mode & ~15;
-    if ((launch != MOL_BATCHED && launch != MOL_PLAIN) ||
-        (tmode != MOL_TIME_BOR && tmode != MOL_TIME_BO && tmode != MOL_TIME_BO1 && tmode != MOL_TIME_NOSUB))
+    if ((launch != MOL_BATCHED && launch != MOL_PLAIN) || (tmode & ~(48 | MOL_ADV_SSPRK3)))
         return fail(MOL_EINVAL, "unknown mode %d", mode);
     int rc = check_states(ps, states);
     if (rc) return rc;

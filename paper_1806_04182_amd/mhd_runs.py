@@ -21,9 +21,10 @@ ALFVEN_L = 2.0
 BW_L = 4.0
 
 
-def _run(levels, N0, dx0, system, init, dt0, nsteps):
+def _run(levels, N0, dx0, system, init, dt0, nsteps, ssp3=False):
     """Build the patchset, set every patch from init(n, h, lo), run nsteps
-    coarse steps from a captured graph; return the patchset and states."""
+    coarse steps (RK4 from a captured graph, or SSP-RK3 with BOR for SSP-RK3);
+    return the patchset and states."""
     import torch
     ps = M.Patchset(M.Hierarchy(N0, (0.0, 0.0, 0.0), dx0, levels), system)
     st = ps.alloc_states()
@@ -36,11 +37,15 @@ def _run(levels, N0, dx0, system, init, dt0, nsteps):
             n = tuple(hi[d] - lo[d] + 1 for d in range(3))
             arrs.append(synth.embed(init(n, h, lo)))
         st[l]["U"].copy_(torch.from_numpy(ps.pack(l, arrs)))
-    g = ps.graph_create(st, dt0)
-    for _ in range(nsteps):
-        g.launch()
+    if ssp3:
+        for _ in range(nsteps):
+            ps.advance(st, dt0, M.MOL_BATCHED | M.MOL_ADV_SSPRK3)
+    else:
+        g = ps.graph_create(st, dt0)
+        for _ in range(nsteps):
+            g.launch()
+        del g
     torch.cuda.synchronize()
-    del g
     return ps, st
 
 
@@ -87,14 +92,14 @@ def brio_wu_levels(N, fmr=None):
     return levels
 
 
-def brio_wu(N, recon=M.MOL_RECON_WENO5Z, flux=M.MOL_FLUX_LLF, fmr=None, t_end=0.2):
+def brio_wu(N, recon=M.MOL_RECON_WENO5Z, flux=M.MOL_FLUX_LLF, fmr=None, t_end=0.2, ssp3=False):
     """Coarse-level state on [0, 1] (8 conserved fields x N + 1 points) at t_end."""
     dx0 = 1.0 / N
     dt0 = 0.2 * dx0
     nsteps = int(round(t_end / dt0))
     sysd = M.System(M.MOL_MHD, sigma=0.0, gamma_ad=2.0, mhd_recon=recon, mhd_flux=flux)
     init = lambda n, h, lo: synth.mhd_brio_wu(n, h, lo)
-    ps, st = _run(brio_wu_levels(N, fmr), (int(BW_L * N), 1, 1), dx0, sysd, init, dt0, nsteps)
+    ps, st = _run(brio_wu_levels(N, fmr), (int(BW_L * N), 1, 1), dx0, sysd, init, dt0, nsteps, ssp3)
     got = synth.interior(ps.unpack(0, st[0]["U"])[0])[:, 0, 0, :]
     return got[:, : N + 1]
 

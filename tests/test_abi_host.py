@@ -94,3 +94,23 @@ def test_time_weights_rejects_bad_arguments():
         M.time_weights(7, 2, 0, 1)
     with pytest.raises(M.MolError):
         M.time_weights(M.MOL_TIME_BO, 2, 0, 5)
+
+
+@pytest.mark.parametrize("tmode,omode", [(M.MOL_TIME_BOR, O.TIME_BOR), (M.MOL_TIME_BO, O.TIME_BO),
+                                         (M.MOL_TIME_BO1, O.TIME_BO1), (M.MOL_TIME_NOSUB, O.TIME_NOSUB)])
+def test_ssp3_time_weights_match_oracle_time_state(tmode, omode):
+    """SSP-RK3 (App. C dense output, App. D BOR) weights against the oracle's
+    parent states."""
+    rng = np.random.default_rng(21 + tmode)
+    Un = rng.standard_normal(9)
+    k = [rng.standard_normal(9) for _ in range(3)]
+    for R in ([1] if tmode == M.MOL_TIME_NOSUB else [1, 2, 3, 4]):
+        for r in range(R):
+            for s in range(1, 4):
+                w = M.time_weights(tmode | M.MOL_ADV_SSPRK3, R, r, s)
+                assert w[3] == 0.0
+                ref = O.time_state(omode, R, r, s, 0.21, Un, k, scheme=O.SSPRK3)
+                got = Un + sum(w[j] * k[j] for j in range(3))
+                assert np.max(np.abs(got - ref)) < 1e-14, (R, r, s)
+    with pytest.raises(M.MolError):
+        M.time_weights(tmode | M.MOL_ADV_SSPRK3, 1, 0, 4)

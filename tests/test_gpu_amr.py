@@ -144,11 +144,68 @@ def test_time_refinement_strategies_parity(system, tmode, omode):
             assert np.array_equal(got, results[M.MOL_PLAIN][l][p][:, 3:-3, 3:-3, 3:-3])
 
 
+@pytest.mark.parametrize("system", [O.WAVE, O.MHD])
+@pytest.mark.parametrize("tmode,omode", [(M.MOL_TIME_BOR, O.TIME_BOR), (M.MOL_TIME_BO1, O.TIME_BO1),
+                                         (M.MOL_TIME_NOSUB, O.TIME_NOSUB)])
+def test_ssp3_subcycled_step_parity(system, tmode, omode):
+    """SSP-RK3 steps in the sub-cycled driver (BOR for SSP-RK3 of App. D, and
+    the other strategies) against the oracle; batched and per-patch launches
+    agree bitwise."""
+    torch = _torch()
+    print("ssp3 subcycled", system, tmode, flush=True)
+    levels, N0 = hierarchy()
+    dx0 = 2.0 / N0[0]
+    if system == O.MHD:
+        sysd = M.System(M.MOL_MHD, sigma=0.0)
+        prm = O.params(sigma=0.0)
+        data = []
+        h = dx0
+        for l, (R, boxes) in enumerate(levels):
+            if l:
+                h /= R
+            data.append([synth.embed(synth.mhd_ot_like(tuple(hi[d] - lo[d] + 1 for d in range(3)), seed=2,
+                                                        N=tuple(int(round(2.0 / h)) for _ in range(3)), lo=lo))
+                         for lo, hi in boxes])
+    else:
+        sysd = M.System(M.MOL_WAVE, sigma=0.1)
+        prm = O.params(sigma=0.1)
+        data = _level_data(system, levels, dx0)
+    ps = M.Patchset(M.Hierarchy(N0, (-1, -1, -1), dx0, levels), sysd)
+    H = O.Hierarchy(system, N0, (-1, -1, -1), dx0, levels)
+    H.set_time_mode(omode)
+    H.set_scheme(O.SSPRK3)
+    for l, arrs in enumerate(data):
+        for p, a in enumerate(arrs):
+            H.set(l, p, a)
+    for l in range(len(levels)):
+        H.fill_same(l)
+    dt0 = 0.2 * dx0 / (6 if tmode == M.MOL_TIME_NOSUB else 1)
+    nsteps = 2
+    for _ in range(nsteps):
+        H.step(dt0, prm)
+    results = {}
+    for launch in (M.MOL_BATCHED, M.MOL_PLAIN):
+        states = ps.alloc_states()
+        for l, arrs in enumerate(data):
+            states[l]["U"].copy_(torch.from_numpy(ps.pack(l, arrs)))
+        for _ in range(nsteps):
+            ps.advance(states, dt0, launch | tmode | M.MOL_ADV_SSPRK3)
+        torch.cuda.synchronize()
+        results[launch] = [ps.unpack(l, states[l]["U"]) for l in range(len(levels))]
+    for l in range(len(levels)):
+        for p in range(len(levels[l][1])):
+            got = results[M.MOL_BATCHED][l][p][:, 3:-3, 3:-3, 3:-3]
+            ref = H.get(l, p)[:, 3:-3, 3:-3, 3:-3]
+            e = parity_err(got, ref)
+            assert np.all(e <= 1e-12), (l, p, e)
+            assert np.array_equal(got, results[M.MOL_PLAIN][l][p][:, 3:-3, 3:-3, 3:-3])
+
+
 def test_advance_rejects_unknown_mode():
     torch = _torch()
     ps, H, data, levels, dx0 = _setup(O.WAVE)
     states = ps.alloc_states()
-    for bad in (2, 64, M.MOL_TIME_BO | 3):
+    for bad in (2, 128, M.MOL_TIME_BO | 3):
         with pytest.raises(M.MolError) as e:
             ps.advance(states, 0.01, bad)
         assert "mode" in str(e.value)
