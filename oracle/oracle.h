@@ -44,7 +44,8 @@ typedef struct {
     double upwind;     /* 1: lop-sided advection stencils; 0: centred */
     /* MHD variants (Sec. II.B.2, App. A, App. B) */
     double mhd_recon;  /* 0: WENO5-Z, 1: WENO5-JS, 2: WENO3 */
-    double mhd_riemann; /* 0: local Lax-Friedrichs (eq. LLF), 1: HLL */
+    double mhd_riemann; /* 0: local Lax-Friedrichs (eq. LLF), 1: HLL, 2: LLF flux splitting
+                           (reading R2: reconstruct (F +- alpha U)/2) */
     double mhd_ch;     /* divergence cleaning (Sec. IV.B, 9-field system): speed c_h */
     double mhd_kpsi;   /* and damping kappa_psi */
 } orc_params;

@@ -29,7 +29,7 @@ class Params(ctypes.Structure):
 
 # MHD variants: reconstruction (App. A/B) and interface flux (Sec. II.B.2)
 RECON_WENO5Z, RECON_WENO5JS, RECON_WENO3 = 0, 1, 2
-FLUX_LLF, FLUX_HLL = 0, 1
+FLUX_LLF, FLUX_HLL, FLUX_SPLIT = 0, 1, 2
 
 
 # time refinement of the sub-cycled step (Sec. III.B)

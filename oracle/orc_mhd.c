@@ -27,6 +27,10 @@
  *    formula;
  *  - epsilon: dx^4 for the fifth-order reconstructions (App. B), dx^2 for
  *    WENO3 (App. A), unless set;
+ *  - reading R2 (mhd_riemann 2): the interface flux is the left-biased
+ *    reconstruction of F+ = (F + alpha U)/2 plus the right-biased one of
+ *    F- = (F - alpha U)/2, cell by cell from the physical fluxes, with alpha
+ *    the largest |v_d| + c_f (and c_h) over the six cells of the stencil;
  *  - divergence cleaning (nine fields, psi last): the B^i flux along d gains
  *    delta^{di} psi, psi has the flux c_h^2 B^d and the source -kappa_psi psi;
  *    the cleaning waves move at -c_h and +c_h, so LLF takes S = max(..., c_h)
@@ -235,6 +239,29 @@ void orc_mhd_interface_flux(const double UL[8], const double UR[8], int d, doubl
     interface_flux(UL, UR, d, gam, riemann, 8, 0.0, F);
 }
 
+/* physical flux of nf fields at one cell and its largest signal speed */
+static void cell_flux(const double* U, int d, double gam, int nf, double ch, double* F, double* speed)
+{
+    double vd, cf;
+    mhd_flux_vc(U, d, gam, F, &vd, &cf);
+    *speed = fabs(vd) + cf;
+    if (nf == 9) {
+        F[5 + d] += U[8];
+        F[8] = ch * ch * U[5 + d];
+        if (ch > *speed) *speed = ch;
+    }
+}
+
+static double recon_left(int recon, const double* u, double eps, double q)
+{
+    return recon == 2 ? orc_weno3_left(u, eps) : recon == 1 ? orc_weno5js_left(u, eps) : orc_weno5z_left(u, eps, q);
+}
+
+static double recon_right(int recon, const double* u, double eps, double q)
+{
+    return recon == 2 ? orc_weno3_right(u, eps) : recon == 1 ? orc_weno5js_right(u, eps) : orc_weno5z_right(u, eps, q);
+}
+
 static void mhd_rhs_nf(const double* U, double* R, int nx, int ny, int nz, const double h[3],
                        const orc_params* p, int nf)
 {
@@ -258,6 +285,23 @@ static void mhd_rhs_nf(const double* U, double* R, int nx, int ny, int nz, const
                 for (int i = lo[0]; i < hi[0]; ++i) {
                     long c = (k * NY + j) * NX + i;
                     double UL[9], UR[9], Fi[9];
+                    if (riemann == 2) {
+                        /* cells i-2 .. i+3: physical fluxes, alpha, split fluxes */
+                        double Uc[6][9], Fc[6][9], sp[6], alpha = 0.0;
+                        for (int m = 0; m < 6; ++m) {
+                            for (int f = 0; f < nf; ++f) Uc[m][f] = U[f * vol + c + (m - 2) * st[d]];
+                            cell_flux(Uc[m], d, p->gamma_ad, nf, p->mhd_ch, Fc[m], &sp[m]);
+                            if (sp[m] > alpha) alpha = sp[m];
+                        }
+                        for (int f = 0; f < nf; ++f) {
+                            double gp[6], gm[6];
+                            for (int m = 0; m < 6; ++m) {
+                                gp[m] = 0.5 * (Fc[m][f] + alpha * Uc[m][f]);
+                                gm[m] = 0.5 * (Fc[m][f] - alpha * Uc[m][f]);
+                            }
+                            Fi[f] = recon_left(recon, gp + 2, eps, p->weno_q) + recon_right(recon, gm + 3, eps, p->weno_q);
+                        }
+                    } else {
                     for (int f = 0; f < nf; ++f) {
                         double line[6];
                         for (int m = 0; m < 6; ++m) line[m] = U[f * vol + c + (m - 2) * st[d]];
@@ -276,6 +320,7 @@ static void mhd_rhs_nf(const double* U, double* R, int nx, int ny, int nz, const
                         }
                     }
                     interface_flux(UL, UR, d, p->gamma_ad, riemann, nf, p->mhd_ch, Fi);
+                    }
                     for (int f = 0; f < nf; ++f) {
                         double Fh = Fi[f];
                         /* interface i+1/2 closes cell i (if interior) on the right
