@@ -258,7 +258,7 @@ def wave_mhd_bench(M):
     # reconstruction and flux variants on the same data (App. A, B; Sec. II.B.2)
     var = {}
     for rname, rec in (("weno5z", M.MOL_RECON_WENO5Z), ("weno5js", M.MOL_RECON_WENO5JS), ("weno3", M.MOL_RECON_WENO3)):
-        for fname, fl in (("llf", M.MOL_FLUX_LLF), ("hll", M.MOL_FLUX_HLL)):
+        for fname, fl in (("llf", M.MOL_FLUX_LLF), ("hll", M.MOL_FLUX_HLL), ("split", M.MOL_FLUX_SPLIT)):
             psv = M.Patchset(M.single_patch((n, n, n), (0, 0, 0), dx),
                              M.System(M.MOL_MHD, sigma=0.0, mhd_recon=rec, mhd_flux=fl))
             stv = psv.alloc_states()

@@ -76,6 +76,8 @@ extern "C" {
 #define MOL_FLUX_LLF 0      /* local Lax-Friedrichs, eq. LLF (default) */
 #define MOL_FLUX_HLL 1      /* HLL with S^L = min(v_d - c_f), S^R = max(v_d + c_f) over the two
                                states, clamped to S^L <= 0 <= S^R */
+#define MOL_FLUX_SPLIT 2    /* LLF flux splitting: the reconstruction acts on (F +- alpha U)/2
+                               cell by cell, alpha the largest |v_d| + c_f over the stencil */
 
 /* time integrators */
 #define MOL_RK4 0    /* Table RK44 */

@@ -879,7 +879,8 @@ int mol_create_patchset(const mol_hierarchy_desc* h, const mol_system_desc* s, m
         return fail(MOL_EINVAL, "gamma_ad must exceed 1");
     }
     if (mhd && (s->mhd_recon < MOL_RECON_WENO5Z || s->mhd_recon > MOL_RECON_WENO3 ||
-                                 (s->mhd_flux != MOL_FLUX_LLF && s->mhd_flux != MOL_FLUX_HLL))) {
+                                 (s->mhd_flux != MOL_FLUX_LLF && s->mhd_flux != MOL_FLUX_HLL &&
+                                  s->mhd_flux != MOL_FLUX_SPLIT))) {
         delete ps;
         return fail(MOL_EINVAL, "unknown MHD reconstruction %d or flux %d", s->mhd_recon, s->mhd_flux);
     }

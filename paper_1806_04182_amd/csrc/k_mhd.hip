@@ -89,7 +89,7 @@ __device__ __forceinline__ double weno3(double v1, double v2, double v3, double 
 }
 
 enum { REC_W5Z = 0, REC_W5JS = 1, REC_W3 = 2 };
-enum { RS_LLF = 0, RS_HLL = 1 };
+enum { RS_LLF = 0, RS_HLL = 1, RS_SPLIT = 2 };
 
 // reconstructed value at the interface to the right of v2 from the left
 template <int REC, bool Q2>
@@ -140,6 +140,43 @@ __device__ __forceinline__ void flux(const double U[8], int d, double gam, doubl
 template <int NF, int REC, int RS, bool Q2, class Get>
 __device__ __forceinline__ void riemann6(Get get, int d, const MhdConst& C, double Fh[NF])
 {
+    if constexpr (RS == RS_SPLIT) {
+        // (F +- alpha U)/2 of the six cells, alpha the largest signal speed
+        // among them; left-biased reconstruction of the + part around cell 2,
+        // right-biased (mirrored) of the - part around cell 3
+        double gp[NF][6], gm[NF][6], alpha = 0.0;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+            double U[NF], F[NF], vd, cf;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) U[f] = get(f, m);
+            flux(U, d, C.gam, F, vd, cf);
+            double sp = fabs(vd) + cf;
+            if constexpr (NF == 9) {
+                F[5 + d] += U[8];
+                F[8] = C.ch2 * U[5 + d];
+                sp = fmax(sp, C.ch);
+            }
+            alpha = fmax(alpha, sp);
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                gp[f][m] = F[f];
+                gm[f][m] = U[f];
+            }
+        }
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            double p[6], q[6];
+#pragma unroll
+            for (int m = 0; m < 6; ++m) {
+                p[m] = 0.5 * (gp[f][m] + alpha * gm[f][m]);
+                q[m] = 0.5 * (gp[f][m] - alpha * gm[f][m]);
+            }
+            Fh[f] = recon<REC, Q2>(p[0], p[1], p[2], p[3], p[4], C.eps[d], C.q) +
+                    recon<REC, Q2>(q[5], q[4], q[3], q[2], q[1], C.eps[d], C.q);
+        }
+        return;
+    }
     double UL[NF], UR[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
@@ -277,6 +314,16 @@ hipError_t dispatch(const SysParams& sp, const StageArgs& a, const MhdConst& C, 
 {
     const dim3 g(a.ntiles), b(MB, MB, 1);
     const bool hll = sp.mhd_flux == MOL_FLUX_HLL;
+    if (sp.mhd_flux == MOL_FLUX_SPLIT) {
+        switch (sp.mhd_recon) {
+        case MOL_RECON_WENO3: mhd_stage_kernel<NF, REC_W3, RS_SPLIT, true><<<g, b, 0, s>>>(a, C, zc); break;
+        case MOL_RECON_WENO5JS: mhd_stage_kernel<NF, REC_W5JS, RS_SPLIT, true><<<g, b, 0, s>>>(a, C, zc); break;
+        default:
+            if (C.q == 2.0) mhd_stage_kernel<NF, REC_W5Z, RS_SPLIT, true><<<g, b, 0, s>>>(a, C, zc);
+            else mhd_stage_kernel<NF, REC_W5Z, RS_SPLIT, false><<<g, b, 0, s>>>(a, C, zc);
+        }
+        return hipGetLastError();
+    }
     switch (sp.mhd_recon) {
     case MOL_RECON_WENO3:
         if (hll) mhd_stage_kernel<NF, REC_W3, RS_HLL, true><<<g, b, 0, s>>>(a, C, zc);

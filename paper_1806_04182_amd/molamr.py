@@ -21,7 +21,7 @@ MOL_WAVE, MOL_MHD, MOL_CCZ4, MOL_MHD_GLM = 0, 1, 2, 3
 MOL_RK4, MOL_SSPRK3 = 0, 1
 MOL_BATCHED, MOL_PLAIN = 0, 1
 MOL_RECON_WENO5Z, MOL_RECON_WENO5JS, MOL_RECON_WENO3 = 0, 1, 2
-MOL_FLUX_LLF, MOL_FLUX_HLL = 0, 1
+MOL_FLUX_LLF, MOL_FLUX_HLL, MOL_FLUX_SPLIT = 0, 1, 2
 # time-refinement strategies (Sec. III.B), or-ed into the mode of advance()
 MOL_TIME_BOR, MOL_TIME_BO, MOL_TIME_BO1, MOL_TIME_NOSUB = 0, 16, 32, 48
 MOL_ADV_SSPRK3 = 64  # SSP-RK3 steps in advance() (or-ed into the mode)

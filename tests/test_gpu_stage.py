@@ -94,11 +94,12 @@ def _jump_state(n, seed=0):
 
 @pytest.mark.parametrize("recon,flux", [(M.MOL_RECON_WENO5Z, M.MOL_FLUX_HLL), (M.MOL_RECON_WENO5JS, M.MOL_FLUX_LLF),
                                         (M.MOL_RECON_WENO5JS, M.MOL_FLUX_HLL), (M.MOL_RECON_WENO3, M.MOL_FLUX_LLF),
-                                        (M.MOL_RECON_WENO3, M.MOL_FLUX_HLL)])
+                                        (M.MOL_RECON_WENO3, M.MOL_FLUX_HLL), (M.MOL_RECON_WENO5Z, M.MOL_FLUX_SPLIT),
+                                        (M.MOL_RECON_WENO3, M.MOL_FLUX_SPLIT)])
 @pytest.mark.parametrize("kind,n", [("smooth", (20, 17, 11)), ("jump", (46, 31, 17))])
 def test_mhd_variants_parity(recon, flux, kind, n):
-    """Reconstructions WENO5-JS, WENO3 (App. A, B) and the HLL flux against
-    the oracle's printed formulas, on smooth data and across jumps."""
+    """Reconstructions WENO5-JS, WENO3 (App. A, B), the HLL flux and the flux
+    splitting (reading R2) against the oracle, on smooth data and across jumps."""
     print("mhd variant", recon, flux, kind, n, flush=True)
     if kind == "smooth":
         N = (max(n[0], 8),) * 3
@@ -114,7 +115,7 @@ def test_mhd_variants_parity(recon, flux, kind, n):
 
 
 @pytest.mark.parametrize("recon,flux", [(M.MOL_RECON_WENO5Z, M.MOL_FLUX_LLF), (M.MOL_RECON_WENO5Z, M.MOL_FLUX_HLL),
-                                        (M.MOL_RECON_WENO3, M.MOL_FLUX_HLL)])
+                                        (M.MOL_RECON_WENO3, M.MOL_FLUX_HLL), (M.MOL_RECON_WENO5JS, M.MOL_FLUX_SPLIT)])
 @pytest.mark.parametrize("kind,n", [("smooth", (20, 17, 11)), ("jump", (46, 31, 17))])
 def test_mhd_glm_parity(recon, flux, kind, n):
     """Nine fields with the cleaning scalar psi (random, O(0.05)): fluxes,
