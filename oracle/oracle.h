@@ -147,6 +147,13 @@ void orc_time_state_ssp3(int mode, int R, int r, int s, double dt, const double*
                          const double* const* k, double* out, long n);
 /* integrator of the sub-cycled step: ORC_RK4 (default) or ORC_SSPRK3 */
 void orc_hier_set_scheme(orc_hier* H, int scheme);
+/* Open (non-periodic) domain with radiative boundaries (Sec. V): level 0 is a
+ * single patch and each of its ghost points evolves by
+ *   d_t U = -v (x^i / r) d_i U - v (U - U_inf) / r
+ * (v and U_inf per field, r the distance to the coordinate origin), d_i
+ * centred where both neighbours are in the ghosted array, one-sided (2nd
+ * order) at its edge. */
+void orc_hier_set_open(orc_hier* H, const double* v, const double* uinf);
 /* the pieces, for the unit checks: prolong into level l (>0) at fine step r,
  * stage s, from the parent's saved U^n and k's (set with orc_hier_set_parent) */
 void orc_hier_set_parent_data(orc_hier* H, int l, int p, const double* Un,

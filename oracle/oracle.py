@@ -102,6 +102,7 @@ def lib():
         L.orc_hier_step.argtypes = [vp, d, P]
         L.orc_hier_set_time_mode.argtypes = [vp, i]
         L.orc_hier_set_scheme.argtypes = [vp, i]
+        L.orc_hier_set_open.argtypes = [vp, dp, dp]
         L.orc_time_state_ssp3.argtypes = [i, i, i, i, d, dp, ctypes.POINTER(dp), dp, lng]
         L.orc_dense_ssp3.argtypes = [i, i, d]
         L.orc_dense_ssp3.restype = d
@@ -303,6 +304,11 @@ class Hierarchy:
 
     def set_time_mode(self, mode: int) -> None:
         lib().orc_hier_set_time_mode(self._h, mode)
+
+    def set_open(self, v, uinf) -> None:
+        """Radiative outer boundary (level 0 a single patch); v and U_inf per field."""
+        self._rad = (np.ascontiguousarray(v, dtype=np.float64), np.ascontiguousarray(uinf, dtype=np.float64))
+        lib().orc_hier_set_open(self._h, _p(self._rad[0]), _p(self._rad[1]))
 
     def set_scheme(self, scheme: int) -> None:
         """RK4 (default) or SSPRK3 for the sub-cycled step."""

@@ -241,10 +241,14 @@ struct orc_hier {
     int system, nf, nlev;
     int tmode;  /* time refinement (ORC_TIME_*) */
     int scheme; /* ORC_RK4 or ORC_SSPRK3 */
+    int open;   /* radiative outer boundary instead of periodic level 0 */
+    double rad_v[32], rad_uinf[32];
     int N0[3];
     double xlo[3], dx0;
     olevel L[MAXLEV];
 };
+
+static void radiative_rhs(orc_hier* H, const double* U, double* R, double h);
 
 static int wrapi(int a, int n)
 {
@@ -347,7 +351,7 @@ static int owner(const orc_hier* H, int l, const int g0[3], long* loc)
     for (int d = 0; d < 3; ++d) {
         int per = H->N0[d];
         for (int m = 1; m <= l; ++m) per *= H->L[m].ratio;
-        g[d] = wrapi(g[d], per);
+        if (!H->open) g[d] = wrapi(g[d], per);
     }
     for (int p = 0; p < L->np; ++p) {
         const int* b = L->box + 6 * p;
@@ -569,6 +573,7 @@ static void advance(orc_hier* H, int l, double dt, const orc_params* prm)
             long n = pvol(b) * nf;
             orc_rhs(H->system, L->Us[p], L->R[p], b[3] - b[0] + 1, b[4] - b[1] + 1,
                     b[5] - b[2] + 1, hh, prm);
+            if (l == 0 && H->open) radiative_rhs(H, L->Us[p], L->R[p], dxl);
             for (long i = 0; i < n; ++i) L->k[s][p][i] = dt * L->R[p][i];
         }
     }
@@ -594,6 +599,53 @@ static void advance(orc_hier* H, int l, double dt, const orc_params* prm)
 
 void orc_hier_set_time_mode(orc_hier* H, int mode) { H->tmode = mode; }
 void orc_hier_set_scheme(orc_hier* H, int scheme) { H->scheme = scheme; }
+
+void orc_hier_set_open(orc_hier* H, const double* v, const double* uinf)
+{
+    H->open = 1;
+    for (int f = 0; f < H->nf; ++f) {
+        H->rad_v[f] = v[f];
+        H->rad_uinf[f] = uinf[f];
+    }
+}
+
+/* derivative along d at local ghosted index a of a line of extent n (with
+ * stride st): centred where a-1 and a+1 exist, else one-sided inward */
+static double rad_d1(const double* u, long st, int a, int n, double h)
+{
+    if (a == 0) return (-3.0 * u[0] + 4.0 * u[st] - u[2 * st]) / (2.0 * h);
+    if (a == n - 1) return (3.0 * u[0] - 4.0 * u[-st] + u[-2 * st]) / (2.0 * h);
+    return (u[st] - u[-st]) / (2.0 * h);
+}
+
+/* radiative right-hand side at every ghost point of the level-0 patch */
+static void radiative_rhs(orc_hier* H, const double* U, double* R, double h)
+{
+    const int* b = H->L[0].box;
+    int NX = b[3] - b[0] + 1 + 2 * ORC_G, NY = b[4] - b[1] + 1 + 2 * ORC_G, NZ = b[5] - b[2] + 1 + 2 * ORC_G;
+    long vol = (long)NX * NY * NZ, st[3] = {1, NX, (long)NX * NY};
+    int N[3] = {NX, NY, NZ};
+    for (int k = 0; k < NZ; ++k)
+        for (int j = 0; j < NY; ++j)
+            for (int i = 0; i < NX; ++i) {
+                if (i >= ORC_G && i < NX - ORC_G && j >= ORC_G && j < NY - ORC_G && k >= ORC_G && k < NZ - ORC_G)
+                    continue;
+                int a[3] = {i, j, k};
+                double x[3], r2 = 0.0;
+                for (int d = 0; d < 3; ++d) {
+                    x[d] = H->xlo[d] + (b[d] + a[d] - ORC_G) * h;
+                    r2 += x[d] * x[d];
+                }
+                double r = sqrt(r2);
+                long c = ((long)k * NY + j) * NX + i;
+                for (int f = 0; f < H->nf; ++f) {
+                    const double* u = U + f * vol + c;
+                    double adv = 0.0;
+                    for (int d = 0; d < 3; ++d) adv += x[d] / r * rad_d1(u, st[d], a[d], N[d], h);
+                    R[f * vol + c] = -H->rad_v[f] * adv - H->rad_v[f] * (u[0] - H->rad_uinf[f]) / r;
+                }
+            }
+}
 
 void orc_hier_step(orc_hier* H, double dt0, const orc_params* p)
 {
