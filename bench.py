@@ -149,6 +149,38 @@ def fmr_bench(M):
     return res
 
 
+def single_bh_bench(M, nlev=8, N=64, L=128.0, t_end=20.0):
+    """A single spinning black hole (M = 1, a = 0.2; Sec. V) on nested
+    ratio-2 levels shaped like the paper's ratio-2 mesh (eight levels of N^3
+    points, outer radiative boundary at L, finest spacing 2L/N/2^7), RK4 with
+    BOR sub-cycling from a captured graph."""
+    import torch
+    from paper_1806_04182_amd.bh_runs import SingleBH
+    t0 = time.perf_counter()
+    bh = SingleBH(nlev=nlev, N=N, L=L)
+    setup = time.perf_counter() - t0
+    bh.run(1.0)  # warm-up
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    steps0 = bh.t
+    e0.record()
+    bh.run(t_end)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    nsteps = int(round((bh.t - steps0) / (0.25 * bh.dx0)))
+    pts = nlev * N ** 3
+    pt_stages = 4 * N ** 3 * sum(2 ** l for l in range(nlev)) * nsteps
+    s = bh.summary()
+    res = {"config": {"levels": nlev, "points_per_level": N ** 3, "outer_boundary": L,
+                      "finest_spacing": 2 * L / N / 2 ** (nlev - 1), "spin": 0.2},
+           "t_end": bh.t, "coarse_steps": nsteps, "ms_per_coarse_step": ms / nsteps,
+           "pt_stage_per_s": pt_stages / (ms * 1e-3), "total_points": pts, "setup_s": setup,
+           "finite": s["finite"], "alpha_r1": bh.field_at(18, 1.0), "alpha_r8": bh.field_at(18, 8.0)}
+    log(f"bench: single BH: {ms / nsteps:.1f} ms per coarse step, alpha(r=1) {res['alpha_r1']:.3f}")
+    return res
+
+
 def _time_objective(fn, p, *args):
     import torch
     torch.cuda.synchronize()
@@ -413,6 +445,8 @@ def main():
             res["fmr_reflections"] = fmr_bench(M)
             log("bench: MHD tests")
             res["mhd_runs"] = mhd_runs_bench(M)
+        log("bench: single black hole")
+        res["single_bh"] = single_bh_bench(M)
         log("bench: adjoint")
         res["adjoint"] = adjoint_bench(M)
         log("bench: wave and MHD paths")

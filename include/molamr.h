@@ -91,6 +91,8 @@ typedef struct {
     const int* ratio;     /* [nlevels]; ratio[l] = dx_{l-1}/dx_l in {2,3,4}; ratio[0] ignored */
     const int* npatch;    /* [nlevels] */
     const int* boxes;     /* 6 ints per patch (lo x y z, hi x y z), levels concatenated */
+    int open;             /* 0: periodic level 0; 1: open domain with radiative outer
+                             boundaries (level 0 one patch; see mol_set_radiative) */
 } mol_hierarchy_desc;
 
 typedef struct {
@@ -217,6 +219,17 @@ int mol_bor_weights(int R, int r, int stage, double w[4]);
  * with MOL_ADV_SSPRK3: then stage <= 3 and w_4 = 0), host query; for
  * MOL_TIME_NOSUB only R = 1 is valid.  MOL_EINVAL on bad arguments. */
 int mol_time_weights(int tmode, int R, int r, int stage, double w[4]);
+
+/* Radiative outer boundary of an open domain (Sec. V): every ghost point of
+ * the level-0 patch evolves, in the same Runge-Kutta stages as the interior,
+ * by d_t U = -v (x^i / r) d_i U - v (U - U_inf) / r, with r the distance to
+ * the coordinate origin and d_i the 2nd-order centred difference where both
+ * neighbours lie in the ghosted array, one-sided (2nd order, inward) at its
+ * edge.  v[nf] and uinf[nf] are host arrays (defaults: v = 1, U_inf = 0).
+ * MOL_EUNSUPPORTED for a periodic patchset.  The first refined level must
+ * keep 6 level-0 points from the outer boundary.  The ghost shell of level 0
+ * is then part of the evolved state: callers set it with the initial data. */
+int mol_set_radiative(mol_patchset* ps, const double* v, const double* uinf);
 
 /* Injection (Sec. III.A): every interior point of the parent level that
  * coincides with an interior point of `fine_level` takes the fine value. */

@@ -90,6 +90,9 @@ struct TileList {
 struct mol_patchset {
     SysParams sp{};
     int nlev = 0;
+    int open = 0;                  // radiative outer boundary (level 0 one patch)
+    RadParams rad{};               // per-field speed and value at infinity
+    DevArr<RadPt> rad_pts;         // the level-0 ghost points it evolves
     int N0[3] = {0, 0, 0};
     double xlo[3] = {0, 0, 0};
     double dx0 = 0;
@@ -147,6 +150,7 @@ struct mol_patchset {
             l.wofs.release();
             l.ntiles.dev.release();
         }
+        rad_pts.release();
         if (scratch) (void)hipFree(scratch);
         if (tband) (void)hipFree(tband);
         if (capture_stream) (void)hipStreamDestroy(capture_stream);
@@ -320,6 +324,12 @@ int build(mol_patchset* ps, const mol_hierarchy_desc* h)
         lev.nelems = off;
         if (l == 0 && vol != (int64_t)ps->N0[0] * ps->N0[1] * ps->N0[2])
             return fail(MOL_EINVAL, "level 0 boxes must tile the periodic domain exactly");
+        if (ps->open && l == 0 && np != 1) return fail(MOL_EINVAL, "an open domain needs one level-0 patch");
+        if (ps->open && l == 1)
+            for (const Box& b : lev.boxes)
+                for (int d = 0; d < 3; ++d)
+                    if (floor_div(b.lo[d], lev.ratio) < 6 || floor_div(b.hi[d], lev.ratio) > ps->N0[d] - 7)
+                        return fail(MOL_EINVAL, "level 1 patch must keep 6 level-0 points from the open boundary");
     }
 
     for (int l = 0; l < ps->nlev; ++l) {
@@ -329,6 +339,7 @@ int build(mol_patchset* ps, const mol_hierarchy_desc* h)
         // ---- same-level ghost copies and coarse-fine points ----
         auto cand = candidates(lev, G, lev, 1);
         std::vector<GhostCopy> fill;
+        std::vector<RadPt> rad;
         std::vector<ProlongPt> pro;
         std::vector<int64_t> pro_by_patch(lev.pd.size() + 1, 0);
         std::vector<ProlongCell> cells;
@@ -363,6 +374,10 @@ int build(mol_patchset* ps, const mol_hierarchy_desc* h)
                             continue;
                         int g[3] = {pd.lo[0] + i, pd.lo[1] + j, pd.lo[2] + k}, gw[3];
                         int64_t dst = pd.off + local_index(pd, i + G, j + G, k + G);
+                        if (l == 0 && ps->open) {  // evolved by the radiative condition
+                            rad.push_back(RadPt{{i + G, j + G, k + G, 0}});
+                            continue;
+                        }
                         int q = find_owner(lev, g, cand[p], gw);
                         if (q >= 0) {
                             const PatchDev& qd = lev.pd[q];
@@ -442,6 +457,7 @@ int build(mol_patchset* ps, const mol_hierarchy_desc* h)
         pro_by_patch[lev.pd.size()] = (int64_t)pro.size();
         lev.pcell_by_patch[lev.pd.size()] = (int64_t)cells.size();
         if ((rc = lev.fill.upload(fill))) return rc;
+        if (l == 0 && ps->open && (rc = ps->rad_pts.upload(rad))) return rc;
         if ((rc = lev.pcell.upload(cells))) return rc;
         if (par) {
             // every parent point that some stencil reads, once, grouped by the
@@ -704,13 +720,20 @@ int stage_impl(mol_patchset* ps, int level, int mode, int stage, double dt, cons
         a.tiles = lev.tiles.dev.p;
         a.ntiles = (int)lev.tiles.dev.n;
         hipError_t e = launch_stage(sp, a, lev.tiles.tdim, st);
-        return e == hipSuccess ? MOL_OK : hip_fail(e, "stage launch");
-    }
-    for (size_t p = 0; p < lev.pd.size(); ++p) {
-        a.tiles = lev.tiles.dev.p + lev.tiles.by_patch[p];
-        a.ntiles = lev.tiles.by_patch[p + 1] - lev.tiles.by_patch[p];
-        hipError_t e = launch_stage(sp, a, lev.tiles.tdim, st);
         if (e != hipSuccess) return hip_fail(e, "stage launch");
+    } else {
+        for (size_t p = 0; p < lev.pd.size(); ++p) {
+            a.tiles = lev.tiles.dev.p + lev.tiles.by_patch[p];
+            a.ntiles = lev.tiles.by_patch[p + 1] - lev.tiles.by_patch[p];
+            hipError_t e = launch_stage(sp, a, lev.tiles.tdim, st);
+            if (e != hipSuccess) return hip_fail(e, "stage launch");
+        }
+    }
+    if (level == 0 && ps->open) {
+        // the outer ghost points evolve in the same stage (they are not filled)
+        hipError_t e = launch_radiative(a, lev.pd[0], ps->rad_pts.p, ps->rad_pts.n, ps->sp.nf, ps->rad, ps->xlo,
+                                        lev.h, st);
+        if (e != hipSuccess) return hip_fail(e, "radiative boundary launch");
     }
     return MOL_OK;
 }
@@ -885,6 +908,11 @@ int mol_create_patchset(const mol_hierarchy_desc* h, const mol_system_desc* s, m
         return fail(MOL_EINVAL, "unknown MHD reconstruction %d or flux %d", s->mhd_recon, s->mhd_flux);
     }
     ps->nlev = h->nlevels;
+    ps->open = h->open ? 1 : 0;
+    for (int f = 0; f < 32; ++f) {
+        ps->rad.v[f] = 1.0;
+        ps->rad.uinf[f] = 0.0;
+    }
     for (int d = 0; d < 3; ++d) {
         ps->N0[d] = h->N0[d];
         ps->xlo[d] = h->xlo[d];
@@ -986,6 +1014,19 @@ int mol_time_weights(int tmode, int R, int r, int stage, double w[4])
     return MOL_OK;
 }
 
+int mol_set_radiative(mol_patchset* ps, const double* v, const double* uinf)
+{
+    if (!ps || !v || !uinf) return fail(MOL_EINVAL, "null argument");
+    if (!ps->open) return fail(MOL_EUNSUPPORTED, "the patchset has a periodic domain");
+    for (int f = 0; f < ps->sp.nf; ++f) {
+        if (!std::isfinite(v[f]) || !(v[f] >= 0.0) || !std::isfinite(uinf[f]))
+            return fail(MOL_EINVAL, "field %d: radiative speed must be finite and >= 0", f);
+        ps->rad.v[f] = v[f];
+        ps->rad.uinf[f] = uinf[f];
+    }
+    return MOL_OK;
+}
+
 int mol_prolong(mol_patchset* ps, int fine_level, int r, int stage, const double* Un_c,
                 const double* const* k_c, double* U_f, void* stream)
 {
@@ -1015,6 +1056,7 @@ int mol_rhs_adjoint(mol_patchset* ps, int level, const double* U, const double* 
 {
     int rc = check_level(ps, level);
     if (rc) return rc;
+    if (ps->open) return fail(MOL_EUNSUPPORTED, "the adjoint needs a periodic domain");
     if (ps->sp.system != MOL_WAVE && ps->sp.system != MOL_CCZ4)
         return fail(MOL_EUNSUPPORTED, "the right-hand-side adjoint exists for the wave and CCZ4 systems");
     if (!lam || !lamU) return fail(MOL_EINVAL, "null buffer");
@@ -1048,6 +1090,7 @@ int mol_fill_ghosts_adjoint(mol_patchset* ps, int level, double* lamU, void* str
 {
     int rc = check_level(ps, level);
     if (rc) return rc;
+    if (ps->open) return fail(MOL_EUNSUPPORTED, "the adjoint needs a periodic domain");
     if (!lamU) return fail(MOL_EINVAL, "null buffer");
     Level& lev = ps->L[level];
     hipError_t e = launch_fill_adjoint(lev.fill_src.p, lev.fill_src.n, lev.fill_img.p, ps->sp.nf,
@@ -1060,6 +1103,7 @@ int mol_rk4_adjoint_step(mol_patchset* ps, int level, double dt, const double* U
 {
     int rc = check_level(ps, level);
     if (rc) return rc;
+    if (ps->open) return fail(MOL_EUNSUPPORTED, "the adjoint needs a periodic domain");
     const bool nl = ps->sp.system == MOL_CCZ4;
     if (ps->sp.system != MOL_WAVE && !nl)
         return fail(MOL_EUNSUPPORTED, "the RK4 adjoint exists for the wave and CCZ4 systems");

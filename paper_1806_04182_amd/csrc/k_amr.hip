@@ -1,7 +1,7 @@
 // Ghost fill, its transpose, coarse-fine prolongation and injection kernels
 // (the data movement of the Sec. III skeleton), plus a vector update used
 // by the RK4 adjoint.
-#include "molamr_int.h"
+#include "k_common.h"
 
 namespace mol {
 
@@ -204,6 +204,53 @@ hipError_t launch_fill_adjoint(const GhostSource* src, int64_t n, const GhostIma
 {
     if (n <= 0) return hipSuccess;
     fill_adjoint_kernel<<<grid_for(n * nf), BLK, 0, s>>>(src, n, img, nf, A);
+    return hipGetLastError();
+}
+
+// Radiative outer boundary (open domain): one thread per (boundary point,
+// field); the right-hand side -v (x^i/r) d_i U - v (U - U_inf)/r with 2nd-order
+// differences (centred inside the ghosted array, one-sided at its edge), then
+// the same Runge-Kutta stage update as the interior.
+__global__ __launch_bounds__(BLK) void radiative_kernel(StageArgs a, PatchDev P, const RadPt* __restrict__ pts,
+                                                        int64_t n, int nf, RadParams rp, double x0, double y0,
+                                                        double z0, double h)
+{
+    const int N[3] = {P.n[0] + 2 * G, P.n[1] + 2 * G, P.n[2] + 2 * G};
+    const int64_t S[3] = {1, P.pitch_y, P.pitch_z};
+    const double xl[3] = {x0, y0, z0}, i2h = 0.5 / h;
+    for (int64_t t = blockIdx.x * (int64_t)BLK + threadIdx.x; t < n * nf; t += (int64_t)gridDim.x * BLK) {
+        const int f = (int)(t / n);
+        const RadPt q = pts[t - (int64_t)f * n];
+        const int64_t idx = P.off + f * P.fs + q.a[2] * S[2] + q.a[1] * S[1] + q.a[0];
+        const double* u = a.Us + idx;
+        double x[3], r2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            x[d] = xl[d] + (P.lo[d] + q.a[d] - G) * h;
+            r2 += x[d] * x[d];
+        }
+        const double ir = 1.0 / sqrt(r2);
+        double adv = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            const int64_t s = S[d];
+            double du;
+            if (q.a[d] == 0)
+                du = (-3.0 * u[0] + 4.0 * u[s] - u[2 * s]) * i2h;
+            else if (q.a[d] == N[d] - 1)
+                du = (3.0 * u[0] - 4.0 * u[-s] + u[-2 * s]) * i2h;
+            else
+                du = (u[s] - u[-s]) * i2h;
+            adv += x[d] * ir * du;
+        }
+        const double rhs = -rp.v[f] * adv - rp.v[f] * (u[0] - rp.uinf[f]) * ir;
+        stage_apply(a, idx, rhs, stage_load(a, idx));
+    }
+}
+
+hipError_t launch_radiative(const StageArgs& a, const PatchDev& P, const RadPt* pts, int64_t n, int nf,
+                            const RadParams& rp, const double xlo[3], double h, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    radiative_kernel<<<grid_for(n * nf), BLK, 0, s>>>(a, P, pts, n, nf, rp, xlo[0], xlo[1], xlo[2], h);
     return hipGetLastError();
 }
 

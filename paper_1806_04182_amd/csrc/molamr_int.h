@@ -141,6 +141,16 @@ inline hipError_t launch_stage(const SysParams& sp, const StageArgs& a, const in
     }
 }
 hipError_t launch_fill(const GhostCopy* e, int64_t n, int nf, double* U, hipStream_t s);
+// radiative outer boundary: ghosted-box coordinates of each boundary point of
+// the level-0 patch, and the per-field speed and value at infinity
+struct RadPt {
+    int32_t a[4];
+};
+struct RadParams {
+    double v[32], uinf[32];
+};
+hipError_t launch_radiative(const StageArgs& a, const PatchDev& P, const RadPt* pts, int64_t n, int nf,
+                            const RadParams& rp, const double xlo[3], double h, hipStream_t s);
 hipError_t launch_fill_adjoint(const GhostSource* src, int64_t nsrc, const GhostImage* img,
                                int nf, double* A, hipStream_t s);
 hipError_t launch_bor_band(const GhostCopy* band, int64_t n, int nf, const double w[4], const double* Un,

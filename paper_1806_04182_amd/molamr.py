@@ -38,7 +38,8 @@ class MolError(RuntimeError):
 class _Hier(ctypes.Structure):
     _fields_ = [("nlevels", ctypes.c_int), ("N0", ctypes.c_int * 3), ("xlo", ctypes.c_double * 3),
                 ("dx0", ctypes.c_double), ("ratio", ctypes.POINTER(ctypes.c_int)),
-                ("npatch", ctypes.POINTER(ctypes.c_int)), ("boxes", ctypes.POINTER(ctypes.c_int))]
+                ("npatch", ctypes.POINTER(ctypes.c_int)), ("boxes", ctypes.POINTER(ctypes.c_int)),
+                ("open", ctypes.c_int)]
 
 
 class _Sys(ctypes.Structure):
@@ -85,6 +86,7 @@ def lib():
             "mol_prolong": ([vp, i, i, i, vp, ctypes.POINTER(vp), vp, vp], i),
             "mol_bor_weights": ([i, i, i, dp], i),
             "mol_time_weights": ([i, i, i, i, dp], i),
+            "mol_set_radiative": ([vp, dp, dp], i),
             "mol_restrict": ([vp, i, vp, vp, vp], i),
             "mol_rhs_adjoint": ([vp, i, vp, vp, vp, vp, vp], i),
             "mol_adjoint_workspace": ([vp, i], ctypes.c_int64),
@@ -165,6 +167,7 @@ class Hierarchy:
     xlo: tuple
     dx0: float
     levels: list  # [(ratio, [((lo), (hi)), ...]), ...]
+    open: bool = False  # radiative outer boundary instead of a periodic level 0
 
     def _c(self):
         ratio = (ctypes.c_int * len(self.levels))(*[lv[0] for lv in self.levels])
@@ -172,7 +175,7 @@ class Hierarchy:
         flat = [v for _, boxes in self.levels for lo, hi in boxes for v in (*lo, *hi)]
         boxes = (ctypes.c_int * len(flat))(*flat)
         h = _Hier(len(self.levels), (ctypes.c_int * 3)(*self.N0), (ctypes.c_double * 3)(*self.xlo),
-                  self.dx0, ratio, npatch, boxes)
+                  self.dx0, ratio, npatch, boxes, int(bool(self.open)))
         return h, (ratio, npatch, boxes)
 
 
@@ -279,6 +282,12 @@ class Patchset:
 
     def norms(self, level, U, field, shift, radius, out_dev, stream=None):
         _check(lib().mol_norms(self._h, level, _ptr(U), field, shift, radius, _ptr(out_dev), _stream(stream)))
+
+    def set_radiative(self, v, uinf):
+        """Per-field speed and value at infinity of the radiative boundary."""
+        nf = self.nf
+        va, ua = (ctypes.c_double * nf)(*v), (ctypes.c_double * nf)(*uinf)
+        _check(lib().mol_set_radiative(self._h, va, ua))
 
     def box_norms(self, level, U, field, shift, lo, hi, out_dev, stream=None):
         """norms() restricted to interior points with lo <= x <= hi."""
