@@ -161,6 +161,13 @@ void orc_hier_set_parent_data(orc_hier* H, int l, int p, const double* Un,
                               const double* k3, const double* k4);
 void orc_hier_prolong(orc_hier* H, int l, int r, int s, double dt_parent);
 void orc_hier_restrict(orc_hier* H, int l);
+/* Regrid at a synchronised time (Sec. III.A): Hn has the same system, level-0
+ * boxes, level count and ratios as Ho.  Level 0 is copied; on each level
+ * l >= 1 (in increasing l) every interior point of Hn takes Ho's value where an
+ * Ho patch of that level holds it, and otherwise the tensor-product 6-point
+ * Lagrange interpolant of Hn's level l-1 (nodes i0-2..i0+3 on the axes where
+ * the point is between parent nodes).  Ghost points of Hn are not set. */
+void orc_hier_regrid(orc_hier* Hn, const orc_hier* Ho);
 
 /* ---- wave adjoint (vector-Jacobian product of the RHS, scatter form) ---- */
 void orc_wave_rhs_adjoint(const double* lam, double* lamU, int nx, int ny, int nz,

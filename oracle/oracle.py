@@ -110,6 +110,7 @@ def lib():
         L.orc_hier_set_parent_data.argtypes = [vp, i, i, dp, dp, dp, dp, dp]
         L.orc_hier_prolong.argtypes = [vp, i, i, i, d]
         L.orc_hier_restrict.argtypes = [vp, i]
+        L.orc_hier_regrid.argtypes = [vp, vp]
         L.orc_wave_rhs_adjoint.argtypes = [dp, dp, i, i, i, dp, P]
         L.orc_fill_periodic_adjoint.argtypes = [dp, i, i, i, i]
         L.orc_wave_adjoint_run.argtypes = [dp, i, i, i, dp, dp, d, i, d, P]
@@ -323,6 +324,57 @@ class Hierarchy:
 
     def restrict(self, l: int) -> None:
         lib().orc_hier_restrict(self._h, l)
+
+    def regrid_from(self, old: "Hierarchy") -> None:
+        """Take the state of `old` (same level 0, other fine boxes): copies
+        where old fine patches hold the point, Lagrange interpolation from the
+        new parent level elsewhere (orc_hier_regrid)."""
+        lib().orc_hier_regrid(self._h, old._h)
+
+
+def tag(u: np.ndarray, threshold: float) -> np.ndarray:
+    """Refinement criterion of the AMR wave test (Sec. IV.A): flag the points
+    where |phi| >= threshold (u: the level's interior values, any shape)."""
+    return (np.abs(u) >= threshold).astype(np.uint8)
+
+
+def cluster(flags: np.ndarray, buffer: int) -> list:
+    """Boxes covering the flagged points of a periodic (z, y, x) array: the
+    flags grown by `buffer` points along each axis with wrap-around, then the
+    face-connected components (no wrap: a region across a domain edge gives one
+    box on each side), the bounding box ((lo x, y, z), (hi x, y, z)) of each,
+    and boxes that overlap replaced by their common bounding box until none
+    overlap; sorted by lower corner (z, y, x).  Sec. III.A leaves the
+    clustering to SAMRAI; this is the reading used here."""
+    from scipy import ndimage
+
+    a = np.asarray(flags).astype(bool)
+    for ax in range(3):
+        reach = min(buffer, a.shape[ax] - 1)
+        grown = a.copy()
+        for o in range(1, reach + 1):
+            grown |= np.roll(a, o, axis=ax) | np.roll(a, -o, axis=ax)
+        a = grown
+    lab, n = ndimage.label(a)  # face connectivity by default
+    boxes = []
+    for sl in ndimage.find_objects(lab):
+        z, y, x = sl
+        boxes.append([x.start, y.start, z.start, x.stop - 1, y.stop - 1, z.stop - 1])
+    merged = True
+    while merged:
+        merged = False
+        for i in range(len(boxes)):
+            for j in range(i + 1, len(boxes)):
+                bi, bj = boxes[i], boxes[j]
+                if all(bi[3 + d] >= bj[d] and bj[3 + d] >= bi[d] for d in range(3)):
+                    boxes[i] = [min(bi[d], bj[d]) for d in range(3)] + [max(bi[3 + d], bj[3 + d]) for d in range(3)]
+                    del boxes[j]
+                    merged = True
+                    break
+            if merged:
+                break
+    boxes.sort(key=lambda b: (b[2], b[1], b[0]))
+    return [(tuple(b[:3]), tuple(b[3:])) for b in boxes]
 
 
 def ccz4_rhs_jvp(U: np.ndarray, V: np.ndarray, h, prm: Params | None = None):

@@ -532,6 +532,71 @@ void orc_hier_restrict(orc_hier* H, int l)
     }
 }
 
+/* Sec. III.A: when a level grows, the points it gains are set by prolongation
+ * from the next coarser level (here taken at the synchronised time, so the
+ * parent state is its current U); points that the old level already held keep
+ * their values. */
+void orc_hier_regrid(orc_hier* Hn, const orc_hier* Ho)
+{
+    for (int p = 0; p < Hn->L[0].np; ++p)
+        memcpy(Hn->L[0].U[p], Ho->L[0].U[p], sizeof(double) * pvol(Hn->L[0].box + 6 * p) * Hn->nf);
+    for (int l = 1; l < Hn->nlev; ++l) {
+        const olevel* F = &Hn->L[l];
+        const olevel* P = &Hn->L[l - 1];
+        const int R = F->ratio;
+        for (int p = 0; p < F->np; ++p) {
+            const int* b = F->box + 6 * p;
+            long NX = b[3] - b[0] + 1 + 2 * ORC_G, NY = b[4] - b[1] + 1 + 2 * ORC_G;
+            long vd = pvol(b);
+            for (int k = b[2]; k <= b[5]; ++k)
+                for (int j = b[1]; j <= b[4]; ++j)
+                    for (int i = b[0]; i <= b[3]; ++i) {
+                        int g[3] = {i, j, k};
+                        long dloc = ((long)(k - b[2] + ORC_G) * NY + (j - b[1] + ORC_G)) * NX + (i - b[0] + ORC_G);
+                        long sloc;
+                        int q = owner(Ho, l, g, &sloc);
+                        if (q >= 0) {
+                            long vs = pvol(Ho->L[l].box + 6 * q);
+                            for (int f = 0; f < Hn->nf; ++f) F->U[p][f * vd + dloc] = Ho->L[l].U[q][f * vs + sloc];
+                            continue;
+                        }
+                        int i0[3], cnt[3];
+                        double w[3][6];
+                        for (int d = 0; d < 3; ++d) {
+                            int m = wrapi(g[d], R);
+                            i0[d] = (g[d] - m) / R;
+                            if (m == 0) {
+                                cnt[d] = 1;
+                                w[d][0] = 1.0;
+                            } else {
+                                cnt[d] = 6;
+                                orc_lagrange6((double)m / R, w[d]);
+                            }
+                        }
+                        for (int f = 0; f < Hn->nf; ++f) {
+                            double v = 0.0;
+                            for (int a = 0; a < cnt[2]; ++a)
+                                for (int b2 = 0; b2 < cnt[1]; ++b2)
+                                    for (int e = 0; e < cnt[0]; ++e) {
+                                        int gc[3] = {i0[0] + (cnt[0] == 1 ? 0 : e - 2),
+                                                     i0[1] + (cnt[1] == 1 ? 0 : b2 - 2),
+                                                     i0[2] + (cnt[2] == 1 ? 0 : a - 2)};
+                                        long cloc;
+                                        int qc = owner(Hn, l - 1, gc, &cloc);
+                                        if (qc < 0) {
+                                            fprintf(stderr, "oracle: regrid stencil leaves the parent level\n");
+                                            abort();
+                                        }
+                                        v += w[0][e] * w[1][b2] * w[2][a]
+                                             * P->U[qc][f * pvol(P->box + 6 * qc) + cloc];
+                                    }
+                            F->U[p][f * vd + dloc] = v;
+                        }
+                    }
+        }
+    }
+}
+
 /* Sec. III skeleton with sub-cycling: level l takes one step of size dt (RK4
  * or SSP-RK3, U^(s) = U^n + sum_j a_sj k_j); its children then take R steps of
  * dt/R using ghost values built from this step's U^n and k's; the children's

@@ -1,0 +1,146 @@
+"""Pins of the oracle's adaptive-refinement pieces (Sec. III.A, Sec. IV.A):
+clustering of tags on hand-made fixtures and by brute-force properties, the
+regrid transfer (copies where the old level held a point, exact for
+polynomials of degree <= 5 elsewhere), and the AMR wave run converging to the
+exact solution at 4th order."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from oracle.amr_wave import AmrChannel, refine
+from paper_1806_04182_amd import synth
+
+
+def _grow(flags, buffer):
+    """brute-force periodic dilation: a point is set when a flagged point lies
+    within `buffer` along every axis (the per-axis growth makes a box shape)"""
+    nz, ny, nx = flags.shape
+    out = np.zeros_like(flags, dtype=bool)
+    for k, j, i in zip(*np.nonzero(flags)):
+        for dz in range(-min(buffer, nz - 1), min(buffer, nz - 1) + 1):
+            for dy in range(-min(buffer, ny - 1), min(buffer, ny - 1) + 1):
+                for dx in range(-min(buffer, nx - 1), min(buffer, nx - 1) + 1):
+                    out[(k + dz) % nz, (j + dy) % ny, (i + dx) % nx] = True
+    return out
+
+
+def _check_boxes(flags, buffer, boxes):
+    grown = _grow(flags, buffer)
+    cover = np.zeros_like(grown)
+    for lo, hi in boxes:
+        sl = (slice(lo[2], hi[2] + 1), slice(lo[1], hi[1] + 1), slice(lo[0], hi[0] + 1))
+        assert not cover[sl].any(), "boxes overlap"
+        cover[sl] = True
+        sub = grown[sl]
+        # tight: every face of the box touches a grown point
+        assert sub[0].any() and sub[-1].any() and sub[:, 0].any() and sub[:, -1].any()
+        assert sub[:, :, 0].any() and sub[:, :, -1].any()
+    assert np.all(cover[grown]), "a tagged point is not covered"
+
+
+def test_cluster_fixtures():
+    f = np.zeros((1, 1, 20), np.uint8)
+    f[0, 0, 7] = 1
+    assert O.cluster(f, 0) == [((7, 0, 0), (7, 0, 0))]
+    assert O.cluster(f, 2) == [((5, 0, 0), (9, 0, 0))]
+    f[0, 0, 13] = 1  # grown regions 5..9 and 11..15: apart
+    assert O.cluster(f, 2) == [((5, 0, 0), (9, 0, 0)), ((11, 0, 0), (15, 0, 0))]
+    assert O.cluster(f, 3) == [((4, 0, 0), (16, 0, 0))]  # they touch
+    # periodic growth across the domain edge: one box on each side
+    g = np.zeros((1, 1, 20), np.uint8)
+    g[0, 0, 0] = 1
+    assert O.cluster(g, 2) == [((0, 0, 0), (2, 0, 0)), ((18, 0, 0), (19, 0, 0))]
+    # an L-shaped region gives its bounding box
+    h = np.zeros((1, 8, 8), np.uint8)
+    h[0, 2, 2:6] = 1
+    h[0, 2:7, 5] = 1
+    assert O.cluster(h, 0) == [((2, 2, 0), (5, 6, 0))]
+    # two diagonal pieces that do not touch but whose boxes overlap are merged
+    d = np.zeros((1, 10, 10), np.uint8)
+    d[0, 1:6, 1] = 1
+    d[0, 1, 1:6] = 1  # an L at the top left
+    d[0, 3, 3] = 1    # inside its box, not connected to it
+    assert O.cluster(d, 0) == [((1, 1, 0), (5, 5, 0))]
+    assert O.cluster(np.zeros((2, 3, 4), np.uint8), 1) == []
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+@pytest.mark.parametrize("buffer", [0, 1, 2])
+def test_cluster_properties_random(seed, buffer):
+    rng = np.random.default_rng(seed)
+    f = (rng.random((5, 7, 9)) < 0.03).astype(np.uint8)
+    _check_boxes(f, buffer, O.cluster(f, buffer))
+
+
+def _poly(x, y, z):
+    return 0.3 + x - 0.5 * y ** 2 + 0.2 * z ** 3 + 0.01 * x ** 5 - 0.02 * (x * y * z) ** 1 + 0.03 * y ** 4 * z
+
+
+def test_regrid_copies_old_points_and_interpolates_polynomials_exactly():
+    """Level 0 holds a polynomial of degree <= 5 per axis; the old fine level
+    holds other values.  After the regrid, new points that the old level held
+    keep those values, the others equal the polynomial (6-point Lagrange
+    interpolation is exact for degree 5)."""
+    N0, dx0, R = (16, 16, 16), 0.5, 2
+    lvl0 = [((0, 0, 0), (15, 15, 15))]
+    old_boxes = [((16, 8, 10), (26, 18, 20))]
+    new_boxes = [((8, 10, 8), (20, 22, 18)), ((21, 10, 8), (24, 14, 12))]
+    Ho = O.Hierarchy(O.WAVE, N0, (0.0, 0.0, 0.0), dx0, [(1, lvl0), (R, old_boxes)])
+    Hn = O.Hierarchy(O.WAVE, N0, (0.0, 0.0, 0.0), dx0, [(1, lvl0), (R, new_boxes)])
+    g = np.arange(-3, 19)
+    Z, Y, X = np.meshgrid(g * dx0, g * dx0, g * dx0, indexing="ij")
+    Ho.set(0, 0, np.stack([_poly(X, Y, Z), -_poly(X, Y, Z)]))
+    marker = np.full(Ho.shape(1, 0), 7.5)
+    marker[1] = -2.5
+    Ho.set(1, 0, marker)
+    Hn.regrid_from(Ho)
+    np.testing.assert_array_equal(Hn.get(0, 0), Ho.get(0, 0))
+    h = dx0 / R
+    for p, (lo, hi) in enumerate(new_boxes):
+        u = synth.interior(Hn.get(1, p))
+        for k in range(lo[2], hi[2] + 1):
+            for j in range(lo[1], hi[1] + 1):
+                for i in range(lo[0], hi[0] + 1):
+                    v = u[:, k - lo[2], j - lo[1], i - lo[0]]
+                    ob = old_boxes[0]
+                    if all(ob[0][d] <= (i, j, k)[d] <= ob[1][d] for d in range(3)):
+                        assert tuple(v) == (7.5, -2.5)
+                    else:
+                        ref = _poly(i * h, j * h, k * h)
+                        assert abs(v[0] - ref) < 1e-11 and abs(v[1] + ref) < 1e-11, (i, j, k, v, ref)
+
+
+def test_refine_maps_level0_boxes():
+    assert refine([((3, 0, 0), (9, 0, 0))], 2, (20, 1, 1)) == [((6, 0, 0), (18, 1, 1))]
+    assert refine([((15, 0, 0), (19, 0, 0))], 3, (20, 1, 1)) == [((45, 0, 0), (59, 2, 2))]
+
+
+def _init(L=10.0, width=0.173):
+    def init(l, box, h):
+        lo, hi = box
+        n = tuple(hi[d] - lo[d] + 1 for d in range(3))
+        x = -2.0 + (lo[0] + np.arange(n[0])) * h
+        phi = np.broadcast_to(synth.wave_channel_pulse(x, 0.0, L, width), (n[2], n[1], n[0]))
+        return synth.embed(np.stack([phi, np.zeros_like(phi)]))
+    return init
+
+
+def test_amr_wave_run_follows_pulse_and_converges_at_fourth_order():
+    """The AMR wave test (Sec. IV.A) with BOR: the refined boxes follow the
+    two halves of the pulse, and the level-0 solution at t = 1.25 converges
+    to the exact one at about 4th order (dx = 1/20, 1/40, 1/80)."""
+    errs, t_end = [], 1.25
+    for n in (20, 40, 80):
+        dt0 = 0.25 / n
+        run = AmrChannel((10 * n, 1, 1), (-2.0, 0.0, 0.0), 1.0 / n, 2, 1e-3, round(0.1 * n), _init(), O.TIME_BOR,
+                         O.params(sigma=0.1))
+        run.run(dt0, int(round(t_end / dt0)), int(round(0.05 / dt0)))
+        phi = synth.interior(run.H.get(0, 0))[0, 0, 0]
+        x = -2.0 + np.arange(phi.size) / n
+        errs.append(np.abs(phi - synth.wave_channel_pulse(x, t_end, 10.0, 0.173)).sum() / n)
+        assert len(run.history) > 10
+        # two boxes centred on x = -t_end and x = +t_end
+        centres = sorted(-2.0 + 0.5 * (lo[0] + hi[0]) / (2 * n) for lo, hi in run.boxes)
+        assert np.allclose(centres, [-t_end, t_end], atol=0.1), centres
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert errs[-1] < 2e-6 and orders[-1] > 3.5, (errs, orders)
