@@ -149,6 +149,41 @@ def fmr_bench(M):
     return res
 
 
+def amr_wave_bench(M):
+    """The AMR wave experiment (Sec. IV.A) on the library: one refined level
+    (ratio 2) following the two halves of the pulse, regridded every 0.0125
+    from tags |phi| >= 1e-3 (mol_tag, mol_cluster, mol_regrid_*).  Convergence
+    factor n_c at t = 1.25, 2.5, 3.75, 5 for dx0 = 1/40, 1/80, 1/160 per
+    time-refinement strategy, and the cost of a regrid in the 1/160 BOR run."""
+    import numpy as np
+    from paper_1806_04182_amd import amr
+    times = (1.25, 2.5, 3.75, 5.0)
+    res = {"resolutions": [40, 80, 160], "times": list(times), "threshold": 1e-3, "buffer": 0.1,
+           "regrid_dt": 0.0125}
+    t0 = time.perf_counter()
+    for name, tm in (("BOR", M.MOL_TIME_BOR), ("BO", M.MOL_TIME_BO), ("NOSUB", M.MOL_TIME_NOSUB)):
+        phis = []
+        for n in (40, 80, 160):
+            run = amr.AmrChannelRun(n)
+            t1 = time.perf_counter()
+            phis.append(run.run(5.0, tm, checkpoints=times))
+            if n == 160 and name == "BOR":
+                wall = time.perf_counter() - t1
+                # the same run without regrids (first boxes kept) isolates their cost
+                still = amr.AmrChannelRun(n, regrid_dt=1e9)
+                t2 = time.perf_counter()
+                still.run(5.0, tm)
+                wall_still = time.perf_counter() - t2
+                res["run_1_160_BOR"] = {"wall_s": wall, "coarse_steps": int(round(5.0 / run.dt0(tm))),
+                                        "regrids": run.regrids, "wall_without_regrids_s": wall_still,
+                                        "ms_per_regrid": 1e3 * (wall - wall_still) / max(run.regrids, 1)}
+        nc = [amr.convergence_order([p[t] for p in phis]) for t in times]
+        res[name] = {"n_c": nc}
+        log(f"bench: AMR wave {name}: n_c {np.round(nc, 2).tolist()}")
+    res["wall_s"] = time.perf_counter() - t0
+    return res
+
+
 def single_bh_bench(M, nlev=8, N=64, L=128.0, t_end=20.0):
     """A single spinning black hole (M = 1, a = 0.2; Sec. V) on nested
     ratio-2 levels shaped like the paper's ratio-2 mesh (eight levels of N^3
@@ -336,7 +371,7 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=96)
     ap.add_argument("--no-extras", action="store_true", help="skip the AMR and adjoint measurements")
     ap.add_argument("--no-fmr", action="store_true",
-                    help="skip the FMR reflection and MHD test runs (many small launches; kept out of kernel traces)")
+                    help="skip the FMR reflection, MHD and AMR wave test runs (many small launches; kept out of kernel traces)")
     ap.add_argument("--paths-only", action="store_true",
                     help="measure only the wave and MHD paths and print their JSON (for profiling)")
     args = ap.parse_args()
@@ -445,6 +480,8 @@ def main():
             res["fmr_reflections"] = fmr_bench(M)
             log("bench: MHD tests")
             res["mhd_runs"] = mhd_runs_bench(M)
+            log("bench: AMR wave")
+            res["amr_wave"] = amr_wave_bench(M)
         log("bench: single black hole")
         res["single_bh"] = single_bh_bench(M)
         log("bench: adjoint")

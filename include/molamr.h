@@ -127,6 +127,7 @@ typedef struct mol_patchset mol_patchset;
  * failure. */
 int mol_create_patchset(const mol_hierarchy_desc* h, const mol_system_desc* s,
                         mol_patchset** out);
+/* Waits for the device to go idle, then frees the patchset. */
 void mol_destroy_patchset(mol_patchset* ps);
 const char* mol_last_error(void);
 
@@ -325,6 +326,41 @@ typedef struct {
  * optionally MOL_ADV_SSPRK3.  MOL_EINVAL on an unknown mode. */
 int mol_advance(mol_patchset* ps, const mol_level_state* states, double dt0, int mode,
                 void* stream);
+
+/* ---- adaptive refinement (Sec. III.A): tagging, boxes, regrid ---- */
+
+/* flags_dev[(gz * P_y + gy) * P_x + gx] = 1 at every interior point of
+ * `level` where |U[field]| >= threshold, P the level's index extent (the
+ * level-0 point counts times the ratios); other entries are not written (the
+ * caller clears the array).  MOL_EINVAL for a bad level or field. */
+int mol_tag(mol_patchset* ps, int level, const double* U, int field, double threshold,
+            uint8_t* flags_dev, void* stream);
+
+/* Boxes that cover the tagged points of a level: the host flags
+ * (dims[0] x dims[1] x dims[2], x fastest) are dilated by `buffer` points
+ * (periodically), grouped into face-connected components (not across the
+ * domain edges, so no box wraps), and each component's bounding box is taken;
+ * boxes that overlap are merged.  boxes_out: 6 ints per box (lo x y z, hi x y
+ * z), at most max_boxes; *nboxes receives the count (0 when nothing is
+ * tagged).  MOL_EINVAL when more than max_boxes boxes result. */
+int mol_cluster(const uint8_t* flags, const int dims[3], int buffer, int max_boxes, int* boxes_out,
+                int* nboxes);
+
+typedef struct mol_regrid mol_regrid;
+/* Transfer plan between two patchsets of the same system with the same level-0
+ * boxes, level count and ratios (a regrid at a synchronised time): level 0 is
+ * copied; on level l >= 1 each interior point takes the old level-l value
+ * where an old patch owned it, otherwise the quintic Lagrange interpolant
+ * (Sec. III.A) of the new level l-1.  Built once (host lists, device
+ * memory); MOL_EINVAL when the two patchsets do not match or a new point's
+ * stencil leaves the new parent level. */
+int mol_regrid_create(mol_patchset* ps_new, const mol_patchset* ps_old, mol_regrid** out);
+/* Apply the plan: U_old[l], U_new[l] are level buffers of the old and new
+ * patchsets; the ghosts of U_new[l-1] are filled before level l is
+ * interpolated.  Allocates nothing. */
+int mol_regrid_apply(mol_regrid* r, const double* const* U_old, double* const* U_new, void* stream);
+/* Waits for the device to go idle, then frees the plan. */
+void mol_regrid_destroy(mol_regrid* r);
 
 typedef struct mol_graph mol_graph;
 /* Capture mol_advance(ps, states, dt0, MOL_BATCHED) into a HIP graph and

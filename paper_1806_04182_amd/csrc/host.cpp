@@ -11,6 +11,7 @@
 #include <array>
 #include <limits>
 #include <map>
+#include <tuple>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -154,6 +155,20 @@ struct mol_patchset {
         if (scratch) (void)hipFree(scratch);
         if (tband) (void)hipFree(tband);
         if (capture_stream) (void)hipStreamDestroy(capture_stream);
+    }
+};
+
+struct mol_regrid {
+    mol_patchset* pn = nullptr;
+    const mol_patchset* po = nullptr;
+    DevArr<GhostCopy> copy[MOL_MAX_LEVELS];   // new <- old at the same level
+    DevArr<ProlongCell> cells[MOL_MAX_LEVELS];  // new points interpolated from the new parent
+    ~mol_regrid()
+    {
+        for (int l = 0; l < MOL_MAX_LEVELS; ++l) {
+            copy[l].release();
+            cells[l].release();
+        }
     }
 };
 
@@ -927,7 +942,12 @@ int mol_create_patchset(const mol_hierarchy_desc* h, const mol_system_desc* s, m
     return MOL_OK;
 }
 
-void mol_destroy_patchset(mol_patchset* ps) { delete ps; }
+void mol_destroy_patchset(mol_patchset* ps)
+{
+    if (!ps) return;
+    (void)hipDeviceSynchronize();  // device work may still read the schedules
+    delete ps;
+}
 
 int mol_nfields(const mol_patchset* ps) { return ps ? ps->sp.nf : fail(MOL_EINVAL, "null patchset"); }
 
@@ -1273,6 +1293,246 @@ int mol_advance(mol_patchset* ps, const mol_level_state* states, double dt0, int
     int rc = check_states(ps, states);
     if (rc) return rc;
     return advance_level(ps, states, 0, 0, dt0, S(stream), launch == MOL_PLAIN, tmode);
+}
+
+int mol_tag(mol_patchset* ps, int level, const double* U, int field, double threshold, uint8_t* flags_dev,
+            void* stream)
+{
+    int rc = check_level(ps, level);
+    if (rc) return rc;
+    if (!U || !flags_dev) return fail(MOL_EINVAL, "null buffer");
+    if (field < 0 || field >= ps->sp.nf) return fail(MOL_EINVAL, "field %d out of range", field);
+    Level& lev = ps->L[level];
+    hipError_t e = launch_tag(lev.d_pd.p, lev.ntiles.dev.p, (int)lev.ntiles.dev.n, lev.ntiles.tdim, U, field,
+                              threshold, lev.period, flags_dev, S(stream));
+    return e == hipSuccess ? MOL_OK : hip_fail(e, "tag launch");
+}
+
+int mol_cluster(const uint8_t* flags, const int dims[3], int buffer, int max_boxes, int* boxes_out, int* nboxes)
+{
+    if (!flags || !dims || !nboxes || (max_boxes > 0 && !boxes_out)) return fail(MOL_EINVAL, "null argument");
+    if (dims[0] < 1 || dims[1] < 1 || dims[2] < 1 || buffer < 0) return fail(MOL_EINVAL, "bad dimensions");
+    const int64_t n = (int64_t)dims[0] * dims[1] * dims[2];
+    auto at = [&](int i, int j, int k) { return ((int64_t)k * dims[1] + j) * dims[0] + i; };
+    // dilation by `buffer` along each axis in turn (periodic)
+    std::vector<uint8_t> a(flags, flags + n), b(n);
+    for (int d = 0; d < 3; ++d) {
+        std::fill(b.begin(), b.end(), 0);
+        for (int k = 0; k < dims[2]; ++k)
+            for (int j = 0; j < dims[1]; ++j)
+                for (int i = 0; i < dims[0]; ++i) {
+                    if (!a[at(i, j, k)]) continue;
+                    const int reach = std::min(buffer, dims[d] - 1);
+                    for (int o = -reach; o <= reach; ++o) {
+                        int c[3] = {i, j, k};
+                        c[d] = wrapi(c[d] + o, dims[d]);
+                        b[at(c[0], c[1], c[2])] = 1;
+                    }
+                }
+        a.swap(b);
+    }
+    // face-connected components (no wrap), bounding boxes
+    std::vector<int> comp(n, -1);
+    std::vector<std::array<int, 6>> bb;
+    std::vector<int64_t> stack;
+    for (int64_t s0 = 0; s0 < n; ++s0) {
+        if (!a[s0] || comp[s0] >= 0) continue;
+        const int id = (int)bb.size();
+        std::array<int, 6> box = {dims[0], dims[1], dims[2], -1, -1, -1};
+        comp[s0] = id;
+        stack.assign(1, s0);
+        while (!stack.empty()) {
+            const int64_t q = stack.back();
+            stack.pop_back();
+            const int c[3] = {(int)(q % dims[0]), (int)((q / dims[0]) % dims[1]), (int)(q / ((int64_t)dims[0] * dims[1]))};
+            for (int d = 0; d < 3; ++d) {
+                box[d] = std::min(box[d], c[d]);
+                box[3 + d] = std::max(box[3 + d], c[d]);
+            }
+            for (int d = 0; d < 3; ++d)
+                for (int o = -1; o <= 1; o += 2) {
+                    int e[3] = {c[0], c[1], c[2]};
+                    e[d] += o;
+                    if (e[d] < 0 || e[d] >= dims[d]) continue;
+                    const int64_t r = at(e[0], e[1], e[2]);
+                    if (a[r] && comp[r] < 0) {
+                        comp[r] = id;
+                        stack.push_back(r);
+                    }
+                }
+        }
+        bb.push_back(box);
+    }
+    // merge overlapping boxes until none overlap
+    for (bool merged = true; merged;) {
+        merged = false;
+        for (size_t i = 0; i < bb.size() && !merged; ++i)
+            for (size_t j = i + 1; j < bb.size() && !merged; ++j) {
+                bool ov = true;
+                for (int d = 0; d < 3; ++d)
+                    if (bb[i][3 + d] < bb[j][d] || bb[j][3 + d] < bb[i][d]) ov = false;
+                if (ov) {
+                    for (int d = 0; d < 3; ++d) {
+                        bb[i][d] = std::min(bb[i][d], bb[j][d]);
+                        bb[i][3 + d] = std::max(bb[i][3 + d], bb[j][3 + d]);
+                    }
+                    bb.erase(bb.begin() + (std::ptrdiff_t)j);
+                    merged = true;
+                }
+            }
+    }
+    *nboxes = (int)bb.size();
+    if ((int)bb.size() > max_boxes) return fail(MOL_EINVAL, "%zu boxes needed, room for %d", bb.size(), max_boxes);
+    // deterministic order: by lower corner (z, y, x)
+    std::sort(bb.begin(), bb.end(), [](const std::array<int, 6>& x, const std::array<int, 6>& y) {
+        return std::make_tuple(x[2], x[1], x[0]) < std::make_tuple(y[2], y[1], y[0]);
+    });
+    for (size_t i = 0; i < bb.size(); ++i)
+        for (int q = 0; q < 6; ++q) boxes_out[6 * i + q] = bb[i][q];
+    return MOL_OK;
+}
+
+int mol_regrid_create(mol_patchset* pn, const mol_patchset* po, mol_regrid** out)
+{
+    if (!pn || !po || !out) return fail(MOL_EINVAL, "null argument");
+    *out = nullptr;
+    if (pn->sp.system != po->sp.system || pn->nlev != po->nlev || pn->open != po->open)
+        return fail(MOL_EINVAL, "the patchsets differ in system, level count or boundary");
+    for (int l = 0; l < pn->nlev; ++l)
+        if (pn->L[l].ratio != po->L[l].ratio) return fail(MOL_EINVAL, "level %d: ratios differ", l);
+    const Level& n0 = pn->L[0];
+    const Level& o0 = po->L[0];
+    if (n0.boxes.size() != o0.boxes.size() || n0.nelems != o0.nelems)
+        return fail(MOL_EINVAL, "level 0 differs");
+    for (size_t q = 0; q < n0.boxes.size(); ++q)
+        for (int d = 0; d < 3; ++d)
+            if (n0.boxes[q].lo[d] != o0.boxes[q].lo[d] || n0.boxes[q].hi[d] != o0.boxes[q].hi[d])
+                return fail(MOL_EINVAL, "level 0 boxes differ");
+    mol_regrid* r = new (std::nothrow) mol_regrid();
+    if (!r) return fail(MOL_ENOMEM, "host allocation failed");
+    r->pn = pn;
+    r->po = po;
+    for (int l = 1; l < pn->nlev; ++l) {
+        const Level& lev = pn->L[l];
+        const Level& old = po->L[l];
+        const Level& par = pn->L[l - 1];
+        const int R = lev.ratio;
+        std::vector<int> allold, allpar;
+        for (size_t q = 0; q < old.boxes.size(); ++q) allold.push_back((int)q);
+        for (size_t q = 0; q < par.boxes.size(); ++q) allpar.push_back((int)q);
+        std::vector<GhostCopy> copy;
+        std::vector<ProlongCell> cells;
+        for (size_t p = 0; p < lev.pd.size(); ++p) {
+            const PatchDev& pd = lev.pd[p];
+            struct CellTmp {
+                int key[3], q0, cw[3];
+                uint64_t mask;
+                int frac;
+            };
+            std::vector<CellTmp> ct;
+            std::map<std::array<int, 3>, size_t> cidx;
+            for (int k = 0; k < pd.n[2]; ++k)
+                for (int j = 0; j < pd.n[1]; ++j)
+                    for (int i = 0; i < pd.n[0]; ++i) {
+                        int g[3] = {pd.lo[0] + i, pd.lo[1] + j, pd.lo[2] + k}, gw[3];
+                        const int64_t dst = pd.off + local_index(pd, i + G, j + G, k + G);
+                        const int q = find_owner(old, g, allold, gw);
+                        if (q >= 0) {
+                            const PatchDev& qd = old.pd[q];
+                            const int64_t src = qd.off + local_index(qd, gw[0] - qd.lo[0] + G, gw[1] - qd.lo[1] + G,
+                                                                     gw[2] - qd.lo[2] + G);
+                            copy.push_back(GhostCopy{dst, src, pd.fs, qd.fs});
+                            continue;
+                        }
+                        int i0[3], m[3], cw[3];
+                        for (int d = 0; d < 3; ++d) {
+                            gw[d] = wrapi(g[d], lev.period[d]);
+                            m[d] = gw[d] % R;
+                            i0[d] = gw[d] / R;
+                        }
+                        const int q0 = find_owner(par, i0, allpar, cw);
+                        if (q0 < 0) {
+                            delete r;
+                            return fail(MOL_EINVAL, "level %d: new point outside the new parent level", l);
+                        }
+                        for (int c = (m[2] ? -2 : 0); c <= (m[2] ? 3 : 0); ++c)
+                            for (int b = (m[1] ? -2 : 0); b <= (m[1] ? 3 : 0); ++b)
+                                for (int a = (m[0] ? -2 : 0); a <= (m[0] ? 3 : 0); ++a) {
+                                    int nd[3] = {i0[0] + a, i0[1] + b, i0[2] + c}, tmp[3];
+                                    if (find_owner(par, nd, allpar, tmp) < 0) {
+                                        delete r;
+                                        return fail(MOL_EINVAL, "level %d: interpolation stencil leaves the new "
+                                                    "parent level", l);
+                                    }
+                                }
+                        const std::array<int, 3> key = {floor_div(g[0], R), floor_div(g[1], R), floor_div(g[2], R)};
+                        auto it = cidx.find(key);
+                        if (it == cidx.end()) {
+                            it = cidx.emplace(key, ct.size()).first;
+                            ct.push_back(CellTmp{{key[0], key[1], key[2]}, q0, {cw[0], cw[1], cw[2]}, 0, 0});
+                        }
+                        CellTmp& c = ct[it->second];
+                        c.mask |= uint64_t(1) << ((m[2] * R + m[1]) * R + m[0]);
+                        for (int d = 0; d < 3; ++d)
+                            if (m[d]) c.frac |= 1 << d;
+                    }
+            std::stable_sort(ct.begin(), ct.end(), [](const CellTmp& a, const CellTmp& b) { return a.frac < b.frac; });
+            for (const CellTmp& c : ct) {
+                const PatchDev& qd = par.pd[c.q0];
+                int c0[3];
+                for (int d = 0; d < 3; ++d) c0[d] = c.cw[d] - qd.lo[d] + G - ((c.frac >> d & 1) ? 2 : 0);
+                ProlongCell e{};
+                e.dbase = pd.off + local_index(pd, R * c.key[0] - pd.lo[0] + G, R * c.key[1] - pd.lo[1] + G,
+                                               R * c.key[2] - pd.lo[2] + G);
+                e.cbase = qd.off + local_index(qd, c0[0], c0[1], c0[2]);
+                e.dfs = pd.fs;
+                e.cfs = qd.fs;
+                e.dpy = pd.pitch_y;
+                e.dpz = pd.pitch_z;
+                e.cpy = qd.pitch_y;
+                e.cpz = qd.pitch_z;
+                e.mask = c.mask;
+                e.frac = c.frac;
+                cells.push_back(e);
+            }
+        }
+        int rc;
+        if ((rc = r->copy[l].upload(copy)) || (rc = r->cells[l].upload(cells))) {
+            delete r;
+            return rc;
+        }
+    }
+    *out = r;
+    return MOL_OK;
+}
+
+int mol_regrid_apply(mol_regrid* r, const double* const* U_old, double* const* U_new, void* stream)
+{
+    if (!r || !U_old || !U_new) return fail(MOL_EINVAL, "null argument");
+    mol_patchset* pn = r->pn;
+    for (int l = 0; l < pn->nlev; ++l)
+        if (!U_old[l] || !U_new[l]) return fail(MOL_EINVAL, "level %d: null buffer", l);
+    hipStream_t s = S(stream);
+    hipError_t e = hipMemcpyAsync(U_new[0], U_old[0], sizeof(double) * pn->L[0].nelems, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    const int nf = pn->sp.nf;
+    for (int l = 1; l < pn->nlev; ++l) {
+        int rc = fill_impl(pn, l - 1, U_new[l - 1], nf, s, 0);
+        if (rc) return rc;
+        if ((e = launch_copy2(r->copy[l].p, r->copy[l].n, nf, U_old[l], U_new[l], s)) != hipSuccess)
+            return hip_fail(e, "regrid copy launch");
+        if ((e = launch_prolong(r->cells[l].p, r->cells[l].n, nf, pn->L[l].ratio, pn->L[l].lagw.data(), U_new[l - 1],
+                                U_new[l], s)) != hipSuccess)
+            return hip_fail(e, "regrid interpolation launch");
+    }
+    return MOL_OK;
+}
+
+void mol_regrid_destroy(mol_regrid* r)
+{
+    if (!r) return;
+    (void)hipDeviceSynchronize();  // device work may still read the plan's lists
+    delete r;
 }
 
 int mol_graph_create(mol_patchset* ps, const mol_level_state* states, double dt0, mol_graph** out)

@@ -246,6 +246,24 @@ __global__ __launch_bounds__(BLK) void radiative_kernel(StageArgs a, PatchDev P,
     }
 }
 
+// copy between two level buffers (regrid): dst[e.dst + f dfs] = src[e.src + f sfs]
+__global__ __launch_bounds__(BLK) void copy2_kernel(const GhostCopy* __restrict__ e, int64_t n, int nf,
+                                                    const double* __restrict__ src, double* __restrict__ dst)
+{
+    for (int64_t t = blockIdx.x * (int64_t)BLK + threadIdx.x; t < n * nf; t += (int64_t)gridDim.x * BLK) {
+        const int64_t f = t / n;
+        const GhostCopy c = e[t - f * n];
+        dst[c.dst + f * c.dfs] = src[c.src + f * c.sfs];
+    }
+}
+
+hipError_t launch_copy2(const GhostCopy* e, int64_t n, int nf, const double* src, double* dst, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    copy2_kernel<<<grid_for(n * nf), BLK, 0, s>>>(e, n, nf, src, dst);
+    return hipGetLastError();
+}
+
 hipError_t launch_radiative(const StageArgs& a, const PatchDev& P, const RadPt* pts, int64_t n, int nf,
                             const RadParams& rp, const double xlo[3], double h, hipStream_t s)
 {

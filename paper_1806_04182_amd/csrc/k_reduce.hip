@@ -165,6 +165,31 @@ hipError_t launch_sphere_adjoint(const PatchDev* patches, const Tile* tiles, int
     return hipGetLastError();
 }
 
+namespace {
+// refinement tagging: flags[(gz * py + gy) * px + gx] = 1 where |U[field]| >= thr
+__global__ __launch_bounds__(RB) void tag_kernel(const PatchDev* __restrict__ patches, const Tile* __restrict__ tiles,
+                                                 const double* __restrict__ U, int field, double thr, int px, int py,
+                                                 uint8_t* __restrict__ flags)
+{
+    const Tile t = tiles[blockIdx.x];
+    const PatchDev P = patches[t.patch];
+    const int i = t.o[0] + threadIdx.x, j = t.o[1] + threadIdx.y, k = t.o[2] + threadIdx.z;
+    if (i >= P.n[0] || j >= P.n[1] || k >= P.n[2]) return;
+    const double v =
+        U[P.off + (int64_t)field * P.fs + (int64_t)(k + G) * P.pitch_z + (int64_t)(j + G) * P.pitch_y + i + G];
+    if (fabs(v) >= thr)
+        flags[((int64_t)(P.lo[2] + k) * py + (P.lo[1] + j)) * px + (P.lo[0] + i)] = 1;
+}
+}  // namespace
+
+hipError_t launch_tag(const PatchDev* patches, const Tile* tiles, int ntiles, const int td[3], const double* U,
+                      int field, double thr, const int period[3], uint8_t* flags, hipStream_t s)
+{
+    if (ntiles <= 0) return hipSuccess;
+    tag_kernel<<<ntiles, dim3(td[0], td[1], td[2]), 0, s>>>(patches, tiles, U, field, thr, period[0], period[1], flags);
+    return hipGetLastError();
+}
+
 hipError_t launch_norms(const PatchDev* patches, const Tile* tiles, int ntiles, const int td[3], const double* U,
                         int field, double shift, double radius, double h, const double xlo[3], const CoordBox& box,
                         double* partial, int nblocks, double* out, hipStream_t s)

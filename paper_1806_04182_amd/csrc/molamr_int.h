@@ -141,6 +141,9 @@ inline hipError_t launch_stage(const SysParams& sp, const StageArgs& a, const in
     }
 }
 hipError_t launch_fill(const GhostCopy* e, int64_t n, int nf, double* U, hipStream_t s);
+hipError_t launch_copy2(const GhostCopy* e, int64_t n, int nf, const double* src, double* dst, hipStream_t s);
+hipError_t launch_tag(const PatchDev* patches, const Tile* tiles, int ntiles, const int td[3], const double* U,
+                      int field, double thr, const int period[3], uint8_t* flags, hipStream_t s);
 // radiative outer boundary: ghosted-box coordinates of each boundary point of
 // the level-0 patch, and the per-field speed and value at infinity
 struct RadPt {

@@ -103,6 +103,12 @@ def lib():
             "mol_graph_create": ([vp, ctypes.POINTER(_LevelState), d, ctypes.POINTER(vp)], i),
             "mol_graph_launch": ([vp, vp], i),
             "mol_graph_destroy": ([vp], None),
+            "mol_tag": ([vp, i, vp, i, d, vp, vp], i),
+            "mol_cluster": ([ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int), i, i,
+                             ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)], i),
+            "mol_regrid_create": ([vp, vp, ctypes.POINTER(vp)], i),
+            "mol_regrid_apply": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp], i),
+            "mol_regrid_destroy": ([vp], None),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -335,6 +341,18 @@ class Patchset:
         _check(lib().mol_graph_create(self._h, self._states(states), dt0, ctypes.byref(g)))
         return Graph(g)
 
+    def period(self, level: int) -> tuple:
+        """Index extent of a level: N0 times the ratios up to it."""
+        f = 1
+        for l in range(1, level + 1):
+            f *= self.hier.levels[l][0]
+        return tuple(n * f for n in self.hier.N0)
+
+    def tag(self, level, U, field, threshold, flags_dev, stream=None):
+        """Set flags_dev (uint8, index extent of the level, x fastest) to 1
+        where |U[field]| >= threshold on the level's interior points."""
+        _check(lib().mol_tag(self._h, level, _ptr(U), field, threshold, _ptr(flags_dev), _stream(stream)))
+
     def alloc_states(self, device="cuda"):
         """Device buffers for mol_advance: U, S0, S1, acc and (when a finer
         level exists) k[4] per level."""
@@ -344,6 +362,39 @@ class Patchset:
             st["k"] = [self.alloc(l, device) for _ in range(4)] if l + 1 < self.nlev else None
             out.append(st)
         return out
+
+
+def cluster(flags: np.ndarray, buffer: int, max_boxes: int = 4096) -> list:
+    """Boxes ((lo), (hi)) covering the tagged points of a (z, y, x) uint8 array
+    after a periodic dilation by `buffer` points (mol_cluster)."""
+    f = np.ascontiguousarray(flags, dtype=np.uint8)
+    dims = (ctypes.c_int * 3)(f.shape[2], f.shape[1], f.shape[0])
+    out = (ctypes.c_int * (6 * max_boxes))()
+    nb = ctypes.c_int()
+    _check(lib().mol_cluster(f.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), dims, int(buffer), max_boxes, out,
+                             ctypes.byref(nb)))
+    return [(tuple(out[6 * q:6 * q + 3]), tuple(out[6 * q + 3:6 * q + 6])) for q in range(nb.value)]
+
+
+class Regrid:
+    """Transfer plan from an old patchset to a new one (mol_regrid_create)."""
+
+    def __init__(self, ps_new: "Patchset", ps_old: "Patchset"):
+        g = ctypes.c_void_p()
+        _check(lib().mol_regrid_create(ps_new._h, ps_old._h, ctypes.byref(g)))
+        self._r = g
+        self._keep = (ps_new, ps_old)
+        self.nlev = ps_new.nlev
+
+    def apply(self, U_old, U_new, stream=None):
+        a = (ctypes.c_void_p * self.nlev)(*[_ptr(x) for x in U_old])
+        b = (ctypes.c_void_p * self.nlev)(*[_ptr(x) for x in U_new])
+        _check(lib().mol_regrid_apply(self._r, a, b, _stream(stream)))
+
+    def __del__(self):
+        if getattr(self, "_r", None) and _lib is not None:
+            _lib.mol_regrid_destroy(self._r)
+            self._r = None
 
 
 class Graph:

@@ -114,3 +114,22 @@ def test_ssp3_time_weights_match_oracle_time_state(tmode, omode):
                 assert np.max(np.abs(got - ref)) < 1e-14, (R, r, s)
     with pytest.raises(M.MolError):
         M.time_weights(tmode | M.MOL_ADV_SSPRK3, 1, 0, 4)
+
+
+# host clustering of refinement tags (mol_cluster) against the oracle's
+@pytest.mark.parametrize("seed", [4, 5, 6, 7])
+@pytest.mark.parametrize("buffer", [0, 1, 3])
+def test_library_cluster_matches_oracle(seed, buffer):
+    rng = np.random.default_rng(seed)
+    f = (rng.random((6, 11, 13)) < 0.02).astype(np.uint8)
+    assert M.cluster(f, buffer) == O.cluster(f, buffer)
+    line = np.zeros((1, 1, 64), np.uint8)
+    line[0, 0, [0, 5, 30, 63]] = 1
+    assert M.cluster(line, buffer) == O.cluster(line, buffer)
+
+
+def test_library_cluster_rejects_too_many_boxes():
+    f = np.zeros((1, 1, 40), np.uint8)
+    f[0, 0, ::4] = 1
+    with pytest.raises(M.MolError):
+        M.cluster(f, 0, max_boxes=3)
