@@ -127,6 +127,14 @@ typedef struct mol_patchset mol_patchset;
  * failure. */
 int mol_create_patchset(const mol_hierarchy_desc* h, const mol_system_desc* s,
                         mol_patchset** out);
+/* As mol_create_patchset, for a hierarchy that shares its leading levels
+ * with `prev` (a regrid, Sec. III.A): the levels 0..k-1 that have the same
+ * ratios and boxes (in the same order) as prev's, for the same system, domain
+ * and boundary, take prev's schedules (copied on the device) instead of being
+ * built again; the others are built.  prev is only read and may be destroyed
+ * afterwards.  Errors as mol_create_patchset; MOL_EINVAL for a null prev. */
+int mol_create_patchset_from(const mol_hierarchy_desc* h, const mol_system_desc* s, const mol_patchset* prev,
+                             mol_patchset** out);
 /* Waits for the device to go idle, then frees the patchset. */
 void mol_destroy_patchset(mol_patchset* ps);
 const char* mol_last_error(void);

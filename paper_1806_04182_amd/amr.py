@@ -94,7 +94,7 @@ class AmrChannelRun:
         boxes = self._boxes(self.ps, self.states[0]["U"])
         if boxes == self.ps.hier.levels[1][1]:
             return False
-        ps = M.Patchset(self._hier(boxes), self.system)
+        ps = M.Patchset(self._hier(boxes), self.system, prev=self.ps)  # level 0 taken over
         states = ps.alloc_states()
         M.Regrid(ps, self.ps).apply([s["U"] for s in self.states], [s["U"] for s in states])
         self.ps, self.states = ps, states

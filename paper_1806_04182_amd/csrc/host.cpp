@@ -57,15 +57,84 @@ int wrapi(int a, int n)
 
 int64_t round_up(int64_t a, int64_t m) { return (a + m - 1) / m * m; }
 
-// device array helper: owns one hipMalloc'd block
+// Device tables of one object in one allocation: each table is appended to a
+// host staging buffer (256-byte aligned), device-only regions are reserved
+// after them, and commit() makes one hipMalloc and one copy, then points
+// every registered slot at its place.  Slots must not move before commit.
+struct Arena {
+    std::vector<unsigned char> host;
+    std::vector<std::pair<void**, size_t>> tables;    // slot, offset
+    std::vector<std::pair<void**, size_t>> reserved;  // slot, bytes
+    struct Adopt {
+        void** slot;
+        const void* src;
+        size_t bytes;
+    };
+    std::vector<Adopt> adopted;  // device tables copied from elsewhere
+    void* dev = nullptr;
+    void stage(const void* src, size_t bytes, void** slot)
+    {
+        const size_t off = (host.size() + 255) / 256 * 256;
+        host.resize(off + bytes);
+        std::memcpy(host.data() + off, src, bytes);
+        tables.emplace_back(slot, off);
+    }
+    void reserve(size_t bytes, void** slot) { reserved.emplace_back(slot, bytes); }
+    void adopt(const void* src, size_t bytes, void** slot) { adopted.push_back(Adopt{slot, src, bytes}); }
+    int commit()
+    {
+        size_t total = (host.size() + 255) / 256 * 256;
+        std::vector<size_t> roff, aoff;
+        for (auto& r : reserved) {
+            roff.push_back(total);
+            total += (r.second + 255) / 256 * 256;
+        }
+        for (auto& a : adopted) {
+            aoff.push_back(total);
+            total += (a.bytes + 255) / 256 * 256;
+        }
+        if (total == 0) return MOL_OK;
+        hipError_t e = hipMalloc(&dev, total);
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+        unsigned char* d = static_cast<unsigned char*>(dev);
+        if (!host.empty() && (e = hipMemcpy(dev, host.data(), host.size(), hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(e, "hipMemcpy");
+        for (size_t i = 0; i < adopted.size(); ++i)
+            if ((e = hipMemcpy(d + aoff[i], adopted[i].src, adopted[i].bytes, hipMemcpyDeviceToDevice)) != hipSuccess)
+                return hip_fail(e, "hipMemcpy");
+        for (auto& t : tables) *t.first = d + t.second;
+        for (size_t i = 0; i < reserved.size(); ++i) *reserved[i].first = d + roff[i];
+        for (size_t i = 0; i < adopted.size(); ++i) *adopted[i].slot = d + aoff[i];
+        host.clear();
+        host.shrink_to_fit();
+        tables.clear();
+        reserved.clear();
+        adopted.clear();
+        return MOL_OK;
+    }
+    void release()
+    {
+        if (dev) (void)hipFree(dev);
+        dev = nullptr;
+    }
+};
+
+// device array helper: a block of its own (hipMalloc'd), or a table in an
+// arena (placed by the arena's commit, freed with it)
 template <class T>
 struct DevArr {
     T* p = nullptr;
     int64_t n = 0;
-    int upload(const std::vector<T>& v)
+    bool in_arena = false;
+    int upload(const std::vector<T>& v, Arena* A = nullptr)
     {
         n = (int64_t)v.size();
         if (n == 0) return MOL_OK;
+        if (A) {
+            in_arena = true;
+            A->stage(v.data(), sizeof(T) * n, reinterpret_cast<void**>(&p));
+            return MOL_OK;
+        }
         hipError_t e = hipMalloc(&p, sizeof(T) * n);
         if (e != hipSuccess) return hip_fail(e, "hipMalloc");
         e = hipMemcpy(p, v.data(), sizeof(T) * n, hipMemcpyHostToDevice);
@@ -74,9 +143,18 @@ struct DevArr {
     }
     void release()
     {
-        if (p) (void)hipFree(p);
+        if (p && !in_arena) (void)hipFree(p);
         p = nullptr;
         n = 0;
+        in_arena = false;
+    }
+    // the same table as `o` (a device copy made by A's commit)
+    void adopt(const DevArr& o, Arena* A)
+    {
+        n = o.n;
+        if (n == 0) return;
+        in_arena = true;
+        A->adopt(o.p, sizeof(T) * n, reinterpret_cast<void**>(&p));
     }
 };
 
@@ -131,6 +209,7 @@ struct mol_patchset {
         int64_t wsize = 0;
     };
     Level L[MOL_MAX_LEVELS];
+    Arena arena;                // every device table and buffer below
     double* scratch = nullptr;  // reduction partials
     double* tband = nullptr;    // parent-level BOR stage state used by the prolongation
     int red_blocks = 256;
@@ -152,8 +231,7 @@ struct mol_patchset {
             l.ntiles.dev.release();
         }
         rad_pts.release();
-        if (scratch) (void)hipFree(scratch);
-        if (tband) (void)hipFree(tband);
+        arena.release();
         if (capture_stream) (void)hipStreamDestroy(capture_stream);
     }
 };
@@ -245,7 +323,7 @@ struct ProlongPt {
 
 int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 
-void build_tiles(const Level& lev, const int td[3], int margin, TileList& tl)
+void build_tiles(const Level& lev, const int td[3], int margin, TileList& tl, Arena* A)
 {
     tl.tdim[0] = td[0];
     tl.tdim[1] = td[1];
@@ -261,7 +339,7 @@ void build_tiles(const Level& lev, const int td[3], int margin, TileList& tl)
                     v.push_back(Tile{(int)p, {i, j, k}});
     }
     tl.by_patch[lev.pd.size()] = (int)v.size();
-    tl.dev.upload(v);
+    tl.dev.upload(v, A);
 }
 
 // Tile of the stage kernels.  Wave: levels of at least 2^21 points march
@@ -295,7 +373,62 @@ bool overlap(const Box& a, const Box& b)
     return true;
 }
 
-int build(mol_patchset* ps, const mol_hierarchy_desc* h)
+// level l of ps takes over level l of prev (whose levels 0..l match): the
+// host lists are copied and the device tables copied into ps's arena
+void reuse_level(mol_patchset* ps, const mol_patchset* prev, int l)
+{
+    Level& lev = ps->L[l];
+    const Level& o = prev->L[l];
+    Arena* A = &ps->arena;
+    lev.d_pd.adopt(o.d_pd, A);
+    lev.fill.adopt(o.fill, A);
+    lev.fill_by_patch = o.fill_by_patch;
+    lev.fill_src.adopt(o.fill_src, A);
+    lev.fill_img.adopt(o.fill_img, A);
+    lev.pcell.adopt(o.pcell, A);
+    lev.pcell_by_patch = o.pcell_by_patch;
+    lev.lagw = o.lagw;
+    lev.band.adopt(o.band, A);
+    lev.band_by_patch = o.band_by_patch;
+    lev.rst.adopt(o.rst, A);
+    lev.rst_by_patch = o.rst_by_patch;
+    TileList* mine[3] = {&lev.tiles, &lev.gtiles, &lev.ntiles};
+    const TileList* theirs[3] = {&o.tiles, &o.gtiles, &o.ntiles};
+    for (int i = 0; i < 3; ++i) {
+        for (int d = 0; d < 3; ++d) mine[i]->tdim[d] = theirs[i]->tdim[d];
+        mine[i]->by_patch = theirs[i]->by_patch;
+        mine[i]->dev.adopt(theirs[i]->dev, A);
+    }
+    lev.wofs.adopt(o.wofs, A);
+    lev.wsize = o.wsize;
+    if (l == 0 && ps->open) {
+        ps->rad_pts.adopt(prev->rad_pts, A);
+        ps->rad = prev->rad;
+    }
+}
+
+// number of leading levels of prev that ps can take over: same system and
+// boundary, and levels 0..l with the same ratios and boxes (in order)
+int same_levels(const mol_patchset* ps, const mol_patchset* prev)
+{
+    if (!prev || prev->sp.system != ps->sp.system || prev->open != ps->open) return 0;
+    for (int d = 0; d < 3; ++d)
+        if (prev->N0[d] != ps->N0[d]) return 0;
+    int n = 0;
+    for (; n < std::min(ps->nlev, prev->nlev); ++n) {
+        const Level& a = ps->L[n];
+        const Level& b = prev->L[n];
+        if (a.ratio != b.ratio || a.boxes.size() != b.boxes.size() || a.nelems != b.nelems) break;
+        bool same = true;
+        for (size_t q = 0; q < a.boxes.size() && same; ++q)
+            for (int d = 0; d < 3; ++d)
+                if (a.boxes[q].lo[d] != b.boxes[q].lo[d] || a.boxes[q].hi[d] != b.boxes[q].hi[d]) same = false;
+        if (!same) break;
+    }
+    return n;
+}
+
+int build(mol_patchset* ps, const mol_hierarchy_desc* h, const mol_patchset* prev = nullptr)
 {
     const int* bx = h->boxes;
     for (int l = 0; l < ps->nlev; ++l) {
@@ -347,9 +480,14 @@ int build(mol_patchset* ps, const mol_hierarchy_desc* h)
                         return fail(MOL_EINVAL, "level 1 patch must keep 6 level-0 points from the open boundary");
     }
 
+    const int nsame = same_levels(ps, prev);
     for (int l = 0; l < ps->nlev; ++l) {
         Level& lev = ps->L[l];
-        int rc = lev.d_pd.upload(lev.pd);
+        if (l < nsame) {
+            reuse_level(ps, prev, l);
+            continue;
+        }
+        int rc = lev.d_pd.upload(lev.pd, &ps->arena);
         if (rc) return rc;
         // ---- same-level ghost copies and coarse-fine points ----
         auto cand = candidates(lev, G, lev, 1);
@@ -471,9 +609,9 @@ int build(mol_patchset* ps, const mol_hierarchy_desc* h)
         lev.fill_by_patch[lev.pd.size()] = (int64_t)fill.size();
         pro_by_patch[lev.pd.size()] = (int64_t)pro.size();
         lev.pcell_by_patch[lev.pd.size()] = (int64_t)cells.size();
-        if ((rc = lev.fill.upload(fill))) return rc;
-        if (l == 0 && ps->open && (rc = ps->rad_pts.upload(rad))) return rc;
-        if ((rc = lev.pcell.upload(cells))) return rc;
+        if ((rc = lev.fill.upload(fill, &ps->arena))) return rc;
+        if (l == 0 && ps->open && (rc = ps->rad_pts.upload(rad, &ps->arena))) return rc;
+        if ((rc = lev.pcell.upload(cells, &ps->arena))) return rc;
         if (par) {
             // every parent point that some stencil reads, once, grouped by the
             // fine patch that first needs it (so per-patch launches cover it)
@@ -517,7 +655,7 @@ int build(mol_patchset* ps, const mol_hierarchy_desc* h)
                 }
             }
             lev.band_by_patch[lev.pd.size()] = (int64_t)band.size();
-            if ((rc = lev.band.upload(band))) return rc;
+            if ((rc = lev.band.upload(band, &ps->arena))) return rc;
         }
         // owner-gather form of the fill (for the adjoint)
         {
@@ -534,8 +672,8 @@ int build(mol_patchset* ps, const mol_hierarchy_desc* h)
                 imgs.push_back(GhostImage{e.dst, e.dfs});
                 srcs.back().end = (int32_t)imgs.size();
             }
-            if ((rc = lev.fill_src.upload(srcs))) return rc;
-            if ((rc = lev.fill_img.upload(imgs))) return rc;
+            if ((rc = lev.fill_src.upload(srcs, &ps->arena))) return rc;
+            if ((rc = lev.fill_img.upload(imgs, &ps->arena))) return rc;
         }
         if (par) {
             // Lagrange weights at xi = m/R through nodes -2..3 (Sec. III.A)
@@ -580,15 +718,15 @@ int build(mol_patchset* ps, const mol_hierarchy_desc* h)
                 rst.insert(rst.end(), per[p].begin(), per[p].end());
             }
             lev.rst_by_patch[lev.pd.size()] = (int64_t)rst.size();
-            if ((rc = lev.rst.upload(rst))) return rc;
+            if ((rc = lev.rst.upload(rst, &ps->arena))) return rc;
         }
         int td[3];
         int64_t npts = 0;
         for (const PatchDev& pd : lev.pd) npts += (int64_t)pd.n[0] * pd.n[1] * pd.n[2];
         default_tile(ps->sp.system, npts, td);
-        build_tiles(lev, td, 0, lev.tiles);
+        build_tiles(lev, td, 0, lev.tiles, &ps->arena);
         int tg[3] = {16, 4, 4};
-        build_tiles(lev, tg, G, lev.gtiles);
+        build_tiles(lev, tg, G, lev.gtiles, &ps->arena);
         if (ps->sp.system == MOL_CCZ4) {
             std::vector<int64_t> wo(lev.pd.size());
             int64_t w = 0;
@@ -597,20 +735,16 @@ int build(mol_patchset* ps, const mol_hierarchy_desc* h)
                 w += (int64_t)ccz4_adjoint_slots() * lev.pd[p].fs;
             }
             lev.wsize = w;
-            if ((rc = lev.wofs.upload(wo))) return rc;
+            if ((rc = lev.wofs.upload(wo, &ps->arena))) return rc;
         }
         int tn[3] = {32, 4, 2};
-        build_tiles(lev, tn, 0, lev.ntiles);
+        build_tiles(lev, tn, 0, lev.ntiles, &ps->arena);
     }
-    hipError_t e = hipMalloc(&ps->scratch, sizeof(double) * 8 * ps->red_blocks);
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+    ps->arena.reserve(sizeof(double) * 8 * ps->red_blocks, reinterpret_cast<void**>(&ps->scratch));
     int64_t tmax = 0;
     for (int l = 0; l + 1 < ps->nlev; ++l) tmax = std::max(tmax, ps->L[l].nelems);
-    if (tmax > 0) {
-        e = hipMalloc(&ps->tband, sizeof(double) * tmax);
-        if (e != hipSuccess) return hip_fail(e, "hipMalloc");
-    }
-    return MOL_OK;
+    if (tmax > 0) ps->arena.reserve(sizeof(double) * tmax, reinterpret_cast<void**>(&ps->tband));
+    return ps->arena.commit();
 }
 
 int check_level(const mol_patchset* ps, int level)
@@ -875,7 +1009,8 @@ extern "C" {
 
 const char* mol_last_error(void) { return g_err.c_str(); }
 
-int mol_create_patchset(const mol_hierarchy_desc* h, const mol_system_desc* s, mol_patchset** out)
+namespace {
+int create_impl(const mol_hierarchy_desc* h, const mol_system_desc* s, const mol_patchset* prev, mol_patchset** out)
 {
     if (!h || !s || !out) return fail(MOL_EINVAL, "null argument");
     *out = nullptr;
@@ -933,13 +1068,26 @@ int mol_create_patchset(const mol_hierarchy_desc* h, const mol_system_desc* s, m
         ps->xlo[d] = h->xlo[d];
     }
     ps->dx0 = h->dx0;
-    int rc = build(ps, h);
+    int rc = build(ps, h, prev);
     if (rc) {
         delete ps;
         return rc;
     }
     *out = ps;
     return MOL_OK;
+}
+}  // namespace
+
+int mol_create_patchset(const mol_hierarchy_desc* h, const mol_system_desc* s, mol_patchset** out)
+{
+    return create_impl(h, s, nullptr, out);
+}
+
+int mol_create_patchset_from(const mol_hierarchy_desc* h, const mol_system_desc* s, const mol_patchset* prev,
+                             mol_patchset** out)
+{
+    if (!prev) return fail(MOL_EINVAL, "null previous patchset");
+    return create_impl(h, s, prev, out);
 }
 
 void mol_destroy_patchset(mol_patchset* ps)

@@ -75,6 +75,7 @@ def lib():
         dp = ctypes.POINTER(ctypes.c_double)
         sig = {
             "mol_create_patchset": ([ctypes.POINTER(_Hier), ctypes.POINTER(_Sys), ctypes.POINTER(vp)], i),
+            "mol_create_patchset_from": ([ctypes.POINTER(_Hier), ctypes.POINTER(_Sys), vp, ctypes.POINTER(vp)], i),
             "mol_destroy_patchset": ([vp], None),
             "mol_last_error": ([], ctypes.c_char_p),
             "mol_nfields": ([vp], i),
@@ -186,13 +187,18 @@ class Hierarchy:
 
 
 class Patchset:
-    """A hierarchy of patches with its device schedules (mol_create_patchset)."""
+    """A hierarchy of patches with its device schedules (mol_create_patchset;
+    with `prev`, mol_create_patchset_from: the leading levels that match
+    prev's take its schedules)."""
 
-    def __init__(self, hier: Hierarchy, system: System):
+    def __init__(self, hier: Hierarchy, system: System, prev: "Patchset | None" = None):
         h, keep = hier._c()
         s = system._c()
         out = ctypes.c_void_p()
-        _check(lib().mol_create_patchset(ctypes.byref(h), ctypes.byref(s), ctypes.byref(out)))
+        if prev is None:
+            _check(lib().mol_create_patchset(ctypes.byref(h), ctypes.byref(s), ctypes.byref(out)))
+        else:
+            _check(lib().mol_create_patchset_from(ctypes.byref(h), ctypes.byref(s), prev._h, ctypes.byref(out)))
         self._h = out
         self.hier = hier
         self.system = system

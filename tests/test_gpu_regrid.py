@@ -60,22 +60,24 @@ def test_tag_matches_oracle_criterion():
         assert ref.sum() > 10
 
 
-def test_regrid_matches_oracle():
+@pytest.mark.parametrize("system,osys", [(M.MOL_WAVE, O.WAVE), (M.MOL_MHD, O.MHD), (M.MOL_CCZ4, O.CCZ4),
+                                         (M.MOL_MHD_GLM, O.MHD_GLM)])
+def test_regrid_matches_oracle(system, osys):
     torch = _torch()
-    po = M.Patchset(M.Hierarchy(N0, (0.0, 0.0, 0.0), 1.0, OLD), M.System(M.MOL_WAVE))
-    pn = M.Patchset(M.Hierarchy(N0, (0.0, 0.0, 0.0), 1.0, NEW), M.System(M.MOL_WAVE))
-    data = _random(OLD, 5)
+    po = M.Patchset(M.Hierarchy(N0, (0.0, 0.0, 0.0), 1.0, OLD), M.System(system))
+    pn = M.Patchset(M.Hierarchy(N0, (0.0, 0.0, 0.0), 1.0, NEW), M.System(system))
+    data = _random(OLD, 5, nf=po.nf)
     Uo = [po.alloc(l) for l in range(3)]
     for l in range(3):
         Uo[l].copy_(torch.from_numpy(po.pack(l, data[l])))
     Un = [pn.alloc(l) for l in range(3)]
     M.Regrid(pn, po).apply(Uo, Un)
     torch.cuda.synchronize()
-    Ho = O.Hierarchy(O.WAVE, N0, (0.0, 0.0, 0.0), 1.0, OLD)
+    Ho = O.Hierarchy(osys, N0, (0.0, 0.0, 0.0), 1.0, OLD)
     for l in range(3):
         for p, a in enumerate(data[l]):
             Ho.set(l, p, a)
-    Hn = O.Hierarchy(O.WAVE, N0, (0.0, 0.0, 0.0), 1.0, NEW)
+    Hn = O.Hierarchy(osys, N0, (0.0, 0.0, 0.0), 1.0, NEW)
     Hn.regrid_from(Ho)
     for l in range(3):
         got = pn.unpack(l, Un[l])
@@ -172,3 +174,28 @@ def test_amr_bo_loses_order_at_the_moving_interface():
     print("AMR n_c threshold 1e-2 BOR", np.round(bor2, 2), "BO", np.round(bo2, 2), flush=True)
     assert min(bor2) > 3.6
     assert max(bo2) < 3.0
+
+
+@pytest.mark.parametrize("system", [M.MOL_WAVE, M.MOL_CCZ4])
+def test_patchset_from_previous_matches_fresh_build(system):
+    """mol_create_patchset_from takes over the leading levels that match: a
+    sub-cycled step on it equals the same step on a patchset built from
+    scratch, bit for bit, whether it reuses one level, two, or none."""
+    torch = _torch()
+    sysd = M.System(system)
+    prev = M.Patchset(M.Hierarchy(N0, (0.0, 0.0, 0.0), 1.0 / 16, OLD), sysd)
+    for levels in (NEW, OLD[:2] + [(2, [((26, 26, 26), (35, 35, 35))])], OLD):
+        fresh = M.Patchset(M.Hierarchy(N0, (0.0, 0.0, 0.0), 1.0 / 16, levels), sysd)
+        reuse = M.Patchset(M.Hierarchy(N0, (0.0, 0.0, 0.0), 1.0 / 16, levels), sysd, prev=prev)
+        data = _random(levels, 9, nf=fresh.nf)
+        outs = []
+        for ps in (fresh, reuse):
+            st = ps.alloc_states()
+            for l in range(3):
+                base = synth.CCZ4_FLAT[:, None, None, None] if system == M.MOL_CCZ4 else 0.0
+                st[l]["U"].copy_(torch.from_numpy(ps.pack(l, [base + 1e-3 * a for a in data[l]])))
+            ps.advance(st, 0.25 / 64, M.MOL_BATCHED)
+            torch.cuda.synchronize()
+            outs.append([st[l]["U"].cpu().numpy() for l in range(3)])
+        for l in range(3):
+            np.testing.assert_array_equal(outs[0][l], outs[1][l])
