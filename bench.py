@@ -99,6 +99,29 @@ def amr_bench(M, steps=2):
         res[mode] = {"ms_per_coarse_step": ms, "pt_stage_per_s": stages / (ms * 1e-3),
                      "wall_ms_per_coarse_step": (time.perf_counter() - t0) * 1e3 / steps}
         log(f"bench: AMR {mode}: {ms:.1f} ms per coarse step")
+    # the same graph after autotuning every level's stage launch (patch order;
+    # the CCZ4 tile is fixed)
+    tilings, dtl = [], dt0
+    for l in range(len(levels)):
+        dtl = dtl / levels[l][0] if l else dtl
+        tilings.append(ps.autotune(l, st[l], dtl, reps=3))
+    for l in range(len(levels)):
+        fill_minkowski_noise(ps, l, st[l]["U"], 100 + l)
+    gt = ps.graph_create(st, dt0)
+    gt.launch(stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        gt.launch(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    res["batched_autotuned"] = {"ms_per_coarse_step": ms, "pt_stage_per_s": stages / (ms * 1e-3),
+                                "tilings": tilings}
+    log(f"bench: AMR batched, autotuned: {ms:.1f} ms per coarse step")
+    del gt
     # time-refinement strategies (batched launches, no graph): the cost of
     # advancing the hierarchy by dt0; without sub-cycling every level takes
     # the finest level's step, dt0 / 6
@@ -310,6 +333,10 @@ def wave_mhd_bench(M):
         out[f"wave_{n}^3"] = {"pt_stage_per_s": n ** 3 * 4 / (ms * 1e-3), "ms_per_step": ms,
                                "stage_kernel_ms": kms, "stage_kernel_GBs_algorithmic": gbs,
                                "hbm_frac": gbs / HBM_PEAK_GBS, "bytes_per_pt_stage": 68.0}
+        tuned = ps.autotune(0, st[0], 0.25 * dx, reps=3)
+        tkms = stage_kernel_time(ps, M, st, M.MOL_RK4, 0.25 * dx)
+        out[f"wave_{n}^3"]["autotuned"] = {"tiling": tuned, "stage_kernel_ms": tkms,
+                                           "hbm_frac": 68.0 * n ** 3 / (tkms * 1e-3) / 1e9 / HBM_PEAK_GBS}
         del g
     n = 128
     log(f"bench: MHD {n}^3")
@@ -322,6 +349,10 @@ def wave_mhd_bench(M):
     out["mhd_128^3"] = {"pt_stage_per_s": n ** 3 / (kms * 1e-3), "stage_kernel_ms": kms,
                         "stage_kernel_GBs_algorithmic": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
                         "bytes_per_pt_stage": 171.0}
+    tuned = ps.autotune(0, st[0], 0.2 * dx, reps=3)
+    st[0]["U"].copy_(torch.from_numpy(ps.pack(0, [synth.embed(synth.mhd_ot_like((n, n, n), seed=0))])))
+    out["mhd_128^3"]["autotuned"] = {"tiling": tuned,
+                                     "stage_kernel_ms": stage_kernel_time(ps, M, st, M.MOL_SSPRK3, 0.2 * dx)}
     # reconstruction and flux variants on the same data (App. A, B; Sec. II.B.2)
     var = {}
     for rname, rec in (("weno5z", M.MOL_RECON_WENO5Z), ("weno5js", M.MOL_RECON_WENO5JS), ("weno3", M.MOL_RECON_WENO3)):

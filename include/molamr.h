@@ -370,6 +370,26 @@ int mol_regrid_apply(mol_regrid* r, const double* const* U_old, double* const* U
 /* Waits for the device to go idle, then frees the plan. */
 void mol_regrid_destroy(mol_regrid* r);
 
+/* ---- autotuning of the stage launches ---- */
+typedef struct {
+    int tdim[3]; /* launch shape: thread tile, or 64 x 8 (wave) / 15 x 15 (MHD) columns and a z-chunk length */
+    int order;   /* patches in the launch: 0 as listed, 1 largest interior first */
+    double ms;   /* measured time of one stage launch (mol_autotune) */
+} mol_tiling;
+/* Time the batched stage kernel of `level` under every candidate launch shape
+ * of the system (wave: z-chunks 4..64 of the z-marching kernel and five
+ * thread tiles of the point-wise one; MHD: z-chunks 4..32; CCZ4: its fixed
+ * tile) and both patch orders, `reps` launches each (RK4 stage 2 with U as
+ * U^n, S0 as stage state, acc and S1 overwritten), and keep the fastest for
+ * the level's later stage launches; *best (nullable) receives it.  The
+ * results of a stage do not depend on the tiling.  Synchronises the stream;
+ * graphs created before keep the tiling they captured. */
+int mol_autotune(mol_patchset* ps, int level, const mol_level_state* st, double dt, int reps, mol_tiling* best,
+                 void* stream);
+/* Use a known tiling (one mol_autotune found earlier); MOL_EINVAL when tdim
+ * is not a launch shape of the system's stage kernel or order is not 0/1. */
+int mol_set_tiling(mol_patchset* ps, int level, const mol_tiling* t);
+
 typedef struct mol_graph mol_graph;
 /* Capture mol_advance(ps, states, dt0, MOL_BATCHED) into a HIP graph and
  * instantiate it (the states' buffers are baked in). */

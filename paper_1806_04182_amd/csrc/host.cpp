@@ -161,7 +161,9 @@ struct DevArr {
 struct TileList {
     int tdim[3] = {1, 1, 1};
     DevArr<Tile> dev;
-    std::vector<int> by_patch;  // np + 1 offsets
+    std::vector<int> by_patch;  // start of each patch's tiles, then the total
+    std::vector<int> count;     // tiles of each patch
+    int order = 0;              // patch order in the launch: 0 as given, 1 largest first
 };
 
 }  // namespace
@@ -210,6 +212,7 @@ struct mol_patchset {
     };
     Level L[MOL_MAX_LEVELS];
     Arena arena;                // every device table and buffer below
+    std::vector<DevArr<Tile>> retired;  // tile lists replaced by the autotuner (graphs may still use them)
     double* scratch = nullptr;  // reduction partials
     double* tband = nullptr;    // parent-level BOR stage state used by the prolongation
     int red_blocks = 256;
@@ -231,6 +234,7 @@ struct mol_patchset {
             l.ntiles.dev.release();
         }
         rad_pts.release();
+        for (auto& t : retired) t.release();
         arena.release();
         if (capture_stream) (void)hipStreamDestroy(capture_stream);
     }
@@ -323,23 +327,35 @@ struct ProlongPt {
 
 int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 
-void build_tiles(const Level& lev, const int td[3], int margin, TileList& tl, Arena* A)
+// tiles of td[0] x td[1] x td[2] points over every patch (grown by margin),
+// each patch's tiles contiguous; patches in the given order (0: as listed,
+// 1: largest interior first, so that the small patches fill the tail of the
+// launch)
+int build_tiles(const Level& lev, const int td[3], int margin, TileList& tl, Arena* A, int order = 0)
 {
     tl.tdim[0] = td[0];
     tl.tdim[1] = td[1];
     tl.tdim[2] = td[2];
+    tl.order = order;
+    const size_t np = lev.pd.size();
+    std::vector<int> perm(np);
+    for (size_t p = 0; p < np; ++p) perm[p] = (int)p;
+    auto vol = [&](int p) { return (int64_t)lev.pd[p].n[0] * lev.pd[p].n[1] * lev.pd[p].n[2]; };
+    if (order == 1) std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return vol(a) > vol(b); });
     std::vector<Tile> v;
-    tl.by_patch.assign(lev.pd.size() + 1, 0);
-    for (size_t p = 0; p < lev.pd.size(); ++p) {
+    tl.by_patch.assign(np + 1, 0);
+    tl.count.assign(np, 0);
+    for (int p : perm) {
         const PatchDev& pd = lev.pd[p];
         tl.by_patch[p] = (int)v.size();
         for (int k = -margin; k < pd.n[2] + margin; k += td[2])
             for (int j = -margin; j < pd.n[1] + margin; j += td[1])
                 for (int i = -margin; i < pd.n[0] + margin; i += td[0])
-                    v.push_back(Tile{(int)p, {i, j, k}});
+                    v.push_back(Tile{p, {i, j, k}});
+        tl.count[p] = (int)v.size() - tl.by_patch[p];
     }
-    tl.by_patch[lev.pd.size()] = (int)v.size();
-    tl.dev.upload(v, A);
+    tl.by_patch[np] = (int)v.size();
+    return tl.dev.upload(v, A);
 }
 
 // Tile of the stage kernels.  Wave: levels of at least 2^21 points march
@@ -397,6 +413,8 @@ void reuse_level(mol_patchset* ps, const mol_patchset* prev, int l)
     for (int i = 0; i < 3; ++i) {
         for (int d = 0; d < 3; ++d) mine[i]->tdim[d] = theirs[i]->tdim[d];
         mine[i]->by_patch = theirs[i]->by_patch;
+        mine[i]->count = theirs[i]->count;
+        mine[i]->order = theirs[i]->order;
         mine[i]->dev.adopt(theirs[i]->dev, A);
     }
     lev.wofs.adopt(o.wofs, A);
@@ -873,7 +891,7 @@ int stage_impl(mol_patchset* ps, int level, int mode, int stage, double dt, cons
     } else {
         for (size_t p = 0; p < lev.pd.size(); ++p) {
             a.tiles = lev.tiles.dev.p + lev.tiles.by_patch[p];
-            a.ntiles = lev.tiles.by_patch[p + 1] - lev.tiles.by_patch[p];
+            a.ntiles = lev.tiles.count[p];
             hipError_t e = launch_stage(sp, a, lev.tiles.tdim, st);
             if (e != hipSuccess) return hip_fail(e, "stage launch");
         }
@@ -1681,6 +1699,128 @@ void mol_regrid_destroy(mol_regrid* r)
     if (!r) return;
     (void)hipDeviceSynchronize();  // device work may still read the plan's lists
     delete r;
+}
+
+namespace {
+// launch shapes of a level's stage kernel worth timing: the z-chunk length of
+// the z-marching kernels, the thread tile of the point-wise wave kernel
+std::vector<std::array<int, 3>> tiling_candidates(int system)
+{
+    std::vector<std::array<int, 3>> c;
+    switch (system) {
+    case MOL_WAVE:
+        for (int z : {4, 8, 16, 32, 64}) c.push_back({MOL_WAVE_WX, MOL_WAVE_WY, z});
+        c.push_back({32, 4, 2});
+        c.push_back({64, 4, 1});
+        c.push_back({16, 8, 2});
+        c.push_back({16, 4, 4});
+        c.push_back({8, 8, 4});
+        break;
+    case MOL_MHD:
+    case MOL_MHD_GLM:
+        for (int z : {4, 8, 16, 32}) c.push_back({15, 15, z});
+        break;
+    default: c.push_back({MOL_CCZ4_TX, MOL_CCZ4_TY, MOL_CCZ4_TZ}); break;
+    }
+    return c;
+}
+
+bool tiling_valid(int system, const int td[3])
+{
+    if (td[0] < 1 || td[1] < 1 || td[2] < 1) return false;
+    switch (system) {
+    case MOL_WAVE:
+        if (td[0] == MOL_WAVE_WX && td[1] == MOL_WAVE_WY) return td[2] > 1 && td[2] <= 1024;  // z-marching
+        return td[0] * td[1] * td[2] <= 256;                                                 // point-wise
+    case MOL_MHD:
+    case MOL_MHD_GLM: return td[0] == 15 && td[1] == 15 && td[2] <= 1024;
+    default: return td[0] == MOL_CCZ4_TX && td[1] == MOL_CCZ4_TY && td[2] == MOL_CCZ4_TZ;
+    }
+}
+
+// replace the level's stage tile list (the old one is kept until the
+// patchset is destroyed: graphs captured earlier still read it)
+int set_tiles(mol_patchset* ps, int level, const int td[3], int order)
+{
+    Level& lev = ps->L[level];
+    TileList tl;
+    int rc = build_tiles(lev, td, 0, tl, nullptr, order);
+    if (rc) {
+        tl.dev.release();
+        return rc;
+    }
+    ps->retired.push_back(lev.tiles.dev);
+    lev.tiles = tl;
+    return MOL_OK;
+}
+}  // namespace
+
+int mol_set_tiling(mol_patchset* ps, int level, const mol_tiling* t)
+{
+    int rc = check_level(ps, level);
+    if (rc) return rc;
+    if (!t) return fail(MOL_EINVAL, "null tiling");
+    if (t->order < 0 || t->order > 1) return fail(MOL_EINVAL, "patch order %d not in {0, 1}", t->order);
+    if (!tiling_valid(ps->sp.system, t->tdim))
+        return fail(MOL_EINVAL, "tile %d x %d x %d is not a launch shape of this system's stage kernel", t->tdim[0],
+                    t->tdim[1], t->tdim[2]);
+    return set_tiles(ps, level, t->tdim, t->order);
+}
+
+int mol_autotune(mol_patchset* ps, int level, const mol_level_state* st, double dt, int reps, mol_tiling* best,
+                 void* stream)
+{
+    int rc = check_level(ps, level);
+    if (rc) return rc;
+    if (!st || !st->U || !st->S0 || !st->S1 || !st->acc) return fail(MOL_EINVAL, "null state buffer");
+    if (!std::isfinite(dt) || dt <= 0.0) return fail(MOL_EINVAL, "dt must be positive and finite");
+    if (reps < 1 || reps > 1000) return fail(MOL_EINVAL, "reps %d not in [1, 1000]", reps);
+    Level& lev = ps->L[level];
+    hipStream_t s = S(stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return hip_fail(e, "hipEventCreate");
+    }
+    mol_tiling win{};
+    win.ms = -1.0;
+    const TileList keep = lev.tiles;
+    rc = MOL_OK;
+    for (const auto& td : tiling_candidates(ps->sp.system)) {
+        for (int order = 0; order <= 1 && rc == MOL_OK; ++order) {
+            TileList tl;
+            if ((rc = build_tiles(lev, td.data(), 0, tl, nullptr, order))) break;
+            lev.tiles = tl;
+            // RK4 stage 2: reads U, S0 and acc, writes acc and S1
+            rc = stage_impl(ps, level, ST_RK4, 2, dt, st->U, st->S0, st->acc, st->S1, nullptr, s, 0);
+            if (rc == MOL_OK && (e = hipEventRecord(e0, s)) != hipSuccess) rc = hip_fail(e, "hipEventRecord");
+            for (int r = 0; r < reps && rc == MOL_OK; ++r)
+                rc = stage_impl(ps, level, ST_RK4, 2, dt, st->U, st->S0, st->acc, st->S1, nullptr, s, 0);
+            float ms = 0.0f;
+            if (rc == MOL_OK && (e = hipEventRecord(e1, s)) != hipSuccess) rc = hip_fail(e, "hipEventRecord");
+            if (rc == MOL_OK && (e = hipEventSynchronize(e1)) != hipSuccess) rc = hip_fail(e, "hipEventSynchronize");
+            if (rc == MOL_OK && (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess)
+                rc = hip_fail(e, "hipEventElapsedTime");
+            lev.tiles = keep;
+            tl.dev.release();
+            if (rc) break;
+            const double per = ms / reps;
+            if (win.ms < 0.0 || per < win.ms) {
+                for (int d = 0; d < 3; ++d) win.tdim[d] = td[d];
+                win.order = order;
+                win.ms = per;
+            }
+        }
+        if (rc) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    if ((rc = set_tiles(ps, level, win.tdim, win.order))) return rc;
+    if (best) *best = win;
+    return MOL_OK;
 }
 
 int mol_graph_create(mol_patchset* ps, const mol_level_state* states, double dt0, mol_graph** out)

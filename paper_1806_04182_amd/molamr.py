@@ -50,6 +50,10 @@ class _Sys(ctypes.Structure):
         ("mhd_kpsi", ctypes.c_double)]
 
 
+class _Tiling(ctypes.Structure):
+    _fields_ = [("tdim", ctypes.c_int * 3), ("order", ctypes.c_int), ("ms", ctypes.c_double)]
+
+
 class _LevelState(ctypes.Structure):
     _fields_ = [("U", ctypes.c_void_p), ("S0", ctypes.c_void_p), ("S1", ctypes.c_void_p),
                 ("acc", ctypes.c_void_p), ("k", ctypes.c_void_p * 4)]
@@ -105,6 +109,8 @@ def lib():
             "mol_graph_launch": ([vp, vp], i),
             "mol_graph_destroy": ([vp], None),
             "mol_tag": ([vp, i, vp, i, d, vp, vp], i),
+            "mol_autotune": ([vp, i, ctypes.POINTER(_LevelState), d, i, ctypes.POINTER(_Tiling), vp], i),
+            "mol_set_tiling": ([vp, i, ctypes.POINTER(_Tiling)], i),
             "mol_cluster": ([ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int), i, i,
                              ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)], i),
             "mol_regrid_create": ([vp, vp, ctypes.POINTER(vp)], i),
@@ -358,6 +364,19 @@ class Patchset:
         """Set flags_dev (uint8, index extent of the level, x fastest) to 1
         where |U[field]| >= threshold on the level's interior points."""
         _check(lib().mol_tag(self._h, level, _ptr(U), field, threshold, _ptr(flags_dev), _stream(stream)))
+
+    def autotune(self, level, state, dt, reps=5, stream=None) -> dict:
+        """Time the level's stage launch shapes and patch orders and keep the
+        fastest (mol_autotune); state: the level's dict from alloc_states
+        (U read, S0/S1/acc overwritten)."""
+        arr = self._states([state])  # the entry point reads the first record
+        t = _Tiling()
+        _check(lib().mol_autotune(self._h, level, arr, dt, reps, ctypes.byref(t), _stream(stream)))
+        return {"tdim": tuple(t.tdim), "order": t.order, "ms": t.ms}
+
+    def set_tiling(self, level, tdim, order=0):
+        t = _Tiling((ctypes.c_int * 3)(*tdim), order, 0.0)
+        _check(lib().mol_set_tiling(self._h, level, ctypes.byref(t)))
 
     def alloc_states(self, device="cuda"):
         """Device buffers for mol_advance: U, S0, S1, acc and (when a finer

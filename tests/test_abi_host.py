@@ -133,3 +133,11 @@ def test_library_cluster_rejects_too_many_boxes():
     f[0, 0, ::4] = 1
     with pytest.raises(M.MolError):
         M.cluster(f, 0, max_boxes=3)
+
+
+def test_set_tiling_rejects_bad_launch_shapes():
+    """mol_set_tiling validates before touching the device (null patchset and
+    bad shapes are argument errors)."""
+    import ctypes
+    t = M._Tiling((ctypes.c_int * 3)(64, 8, 4), 0, 0.0)
+    assert M.lib().mol_set_tiling(None, 0, ctypes.byref(t)) == -1  # MOL_EINVAL

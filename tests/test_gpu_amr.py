@@ -277,3 +277,46 @@ def test_fill_ghosts_multipatch_matches_oracle():
                 # the oracle leaves coarse-fine ghosts untouched (zero in the input)
                 same = np.any(ref[:, mask] != data[l][p][:, mask], axis=0)
                 assert np.array_equal(got[p][:, mask][:, same], ref[:, mask][:, same])
+
+
+@pytest.mark.parametrize("system", [M.MOL_WAVE, M.MOL_CCZ4, M.MOL_MHD])
+def test_autotuned_tiling_gives_identical_steps(system):
+    """mol_autotune picks a launch shape and patch order per level; a
+    sub-cycled step (batched and per patch) is then bit for bit the step of
+    the untuned patchset, and mol_set_tiling reproduces a choice."""
+    torch = _torch()
+    levels, N0 = hierarchy()
+    sysd = M.System(system, sigma=0.05 if system == M.MOL_MHD else 0.1)
+    ref, tuned = (M.Patchset(M.Hierarchy(N0, (-1, -1, -1), 2.0 / N0[0], levels), sysd) for _ in range(2))
+    def noise(l, lo, hi):
+        gk, gj, gi = np.meshgrid(*[np.arange(lo[d], hi[d] + 1) for d in (2, 1, 0)], indexing="ij")
+        return synth.embed(np.stack([synth.uniform(7, l, f, gi, gj, gk) for f in range(ref.nf)]))
+    base = 0.0
+    if system == M.MOL_CCZ4:
+        base = synth.CCZ4_FLAT[:, None, None, None]
+    elif system == M.MOL_MHD:
+        base = np.array([1.0, 0, 0, 0, 2.0, 0.5, 0.5, 0.5])[:, None, None, None]
+    data = [[base + 1e-3 * noise(l, lo, hi) for lo, hi in boxes] for l, (_, boxes) in enumerate(levels)]
+    dt0 = 0.05 * 2.0 / N0[0]
+    choices = []
+    for l in range(len(levels)):
+        st = tuned.alloc_states()[l]
+        st["U"].copy_(torch.from_numpy(tuned.pack(l, data[l])))
+        choices.append(tuned.autotune(l, st, dt0, reps=2))
+    print("tilings", choices, flush=True)
+    for mode in (M.MOL_BATCHED, M.MOL_PLAIN):
+        outs = []
+        for ps in (ref, tuned):
+            st = ps.alloc_states()
+            for l in range(len(levels)):
+                st[l]["U"].copy_(torch.from_numpy(ps.pack(l, data[l])))
+            ps.advance(st, dt0, mode)
+            torch.cuda.synchronize()
+            outs.append([st[l]["U"].cpu().numpy() for l in range(len(levels))])
+        for l in range(len(levels)):
+            np.testing.assert_array_equal(outs[0][l], outs[1][l])
+    again = M.Patchset(M.Hierarchy(N0, (-1, -1, -1), 2.0 / N0[0], levels), sysd)
+    for l, c in enumerate(choices):
+        again.set_tiling(l, c["tdim"], c["order"])
+    with pytest.raises(M.MolError):
+        again.set_tiling(0, (7, 7, 7), 0)
