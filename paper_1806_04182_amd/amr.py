@@ -2,12 +2,15 @@
 
 A 1D pulse (Gaussian of width 0.173 at rest at x = 0) on a periodic channel
 x in [-2, 8) (one point thick in y and z on level 0) splits into two halves
-that travel in opposite directions.  One refined level of ratio R follows
-them: every `regrid_dt` time units the level-0 state is tagged where
-|phi| >= threshold (`mol_tag`), the tags are grown by `buffer` (a length) and
-clustered into boxes (`mol_cluster`), a patchset with the new fine boxes is
-built, and the state moves over (`mol_regrid_*`: copies where the old fine
-level held a point, quintic Lagrange interpolation from level 0 elsewhere).
+that travel in opposite directions.  Refined levels of ratio R follow them:
+every `regrid_dt` time units each level l but the finest is tagged where
+|phi| >= thresholds[l] (`mol_tag`), the tags are grown by `buffer` (a length)
+and clustered into boxes (`mol_cluster`) for level l+1, which is kept inside
+level l with room for the prolongation stencils; a patchset with the new
+boxes is built (taking over the unchanged levels), and the state moves over
+(`mol_regrid_*`: copies where the old level held a point, quintic Lagrange
+interpolation from the new parent elsewhere).  The paper's experiment has one
+refined level; more levels repeat the tagging on the new levels (Sec. III.A).
 Between regrids the hierarchy advances with the sub-cycled driver under the
 chosen time refinement (MOL_TIME_*).
 
@@ -36,30 +39,61 @@ def fine_boxes(coarse_boxes, R: int, dims) -> list:
     return out
 
 
+def nest(boxes, parent_boxes, R: int, dims, margin: int = 6) -> list:
+    """The parts of `boxes` (level l+1 index space) that lie inside the parent
+    level's boxes shrunk by `margin` parent points on every axis the parent box
+    does not span whole (dims: the parent level's extent), so that the
+    prolongation stencils of the new level's ghost points stay on the parent
+    level."""
+    out = []
+    for plo, phi in parent_boxes:
+        lo, hi = [], []
+        for d in range(3):
+            if plo[d] == 0 and phi[d] == dims[d] - 1:
+                lo.append(0)
+                hi.append(R * dims[d] - 1)
+            else:
+                lo.append(R * (plo[d] + margin))
+                hi.append(R * (phi[d] - margin))
+        for blo, bhi in boxes:
+            c_lo = tuple(max(blo[d], lo[d]) for d in range(3))
+            c_hi = tuple(min(bhi[d], hi[d]) for d in range(3))
+            if all(c_lo[d] <= c_hi[d] for d in range(3)):
+                out.append((c_lo, c_hi))
+    return sorted(out, key=lambda b: (b[0][2], b[0][1], b[0][0]))
+
+
 class AmrChannelRun:
-    """Device state and driver of one AMR channel run."""
+    """Device state and driver of one AMR channel run with `len(thresholds)`
+    adaptive levels: level l+1 refines where |phi| >= thresholds[l] on level
+    l, nested inside level l."""
 
     def __init__(self, n_unit: int, R: int = 2, L: float = 10.0, width: float = 0.173, threshold: float = 1e-3,
-                 buffer: float = 0.1, regrid_dt: float = 0.0125, sigma: float = 0.1):
+                 buffer: float = 0.1, regrid_dt: float = 0.0125, sigma: float = 0.1, thresholds=None):
         import torch
         self.n_unit, self.R, self.L, self.width = n_unit, R, L, width
         self.dx0 = 1.0 / n_unit
         self.N0 = (int(round(L * n_unit)), 1, 1)
         self.xlo = (-2.0, 0.0, 0.0)
-        self.threshold = threshold
+        self.thresholds = tuple(thresholds) if thresholds is not None else (threshold,)
+        self.threshold = self.thresholds[0]
+        self.buffer = buffer
         self.buffer_pts = int(round(buffer * n_unit))
         self.regrid_dt = regrid_dt
         self.system = M.System(M.MOL_WAVE, sigma=sigma)
         self.level0 = [((0, 0, 0), (self.N0[0] - 1, 0, 0))]
-        self.flags = torch.zeros(self.N0[::-1], dtype=torch.uint8, device="cuda")
-        # initial hierarchy: tag the exact data on level 0 alone
-        ps0 = M.Patchset(self._hier([]), self.system)
-        U0 = ps0.alloc(0)
-        U0.copy_(torch.from_numpy(ps0.pack(0, [self._exact(0, b) for b in self.level0])))
-        boxes = self._boxes(ps0, U0)
+        self.nlev = len(self.thresholds) + 1
+        # initial hierarchy, level by level: tag the exact data of the finest
+        # level built so far
+        boxes = []
+        for l in range(self.nlev - 1):
+            ps = M.Patchset(self._hier(boxes), self.system)
+            U = ps.alloc(l)
+            U.copy_(torch.from_numpy(ps.pack(l, [self._exact(l, b) for b in ps.hier.levels[l][1]])))
+            boxes = boxes + [self._boxes(ps, l, U)]
         self.ps = M.Patchset(self._hier(boxes), self.system)
         self.states = self.ps.alloc_states()
-        for l in range(2):
+        for l in range(self.nlev):
             self.states[l]["U"].copy_(torch.from_numpy(
                 self.ps.pack(l, [self._exact(l, b) for b in self.ps.hier.levels[l][1]])))
         self.t = 0.0
@@ -67,43 +101,57 @@ class AmrChannelRun:
         self.regrids = 0
 
     def _hier(self, boxes):
-        levels = [(1, self.level0)]
-        if boxes:
-            levels.append((self.R, boxes))
+        levels = [(1, self.level0)] + [(self.R, b) for b in boxes]
         return M.Hierarchy(self.N0, self.xlo, self.dx0, levels)
+
+    def _h(self, l: int) -> float:
+        return self.dx0 / self.R ** l
+
+    def _period(self, l: int):
+        return tuple(n * self.R ** l for n in self.N0)
 
     def _exact(self, l: int, box):
         lo, hi = box
-        h = self.dx0 / (self.R if l else 1)
+        h = self._h(l)
         n = tuple(hi[d] - lo[d] + 1 for d in range(3))
         x = self.xlo[0] + (lo[0] + np.arange(n[0])) * h
         phi = np.broadcast_to(synth.wave_channel_pulse(x, 0.0, self.L, self.width), (n[2], n[1], n[0]))
         return synth.embed(np.stack([phi, np.zeros_like(phi)]))
 
-    def _boxes(self, ps, U0):
-        self.flags.zero_()
-        ps.tag(0, U0, 0, self.threshold, self.flags)
-        coarse = M.cluster(self.flags.cpu().numpy(), self.buffer_pts)
-        if not coarse:
-            raise RuntimeError("nothing is tagged: the refined level would be empty")
-        return fine_boxes(coarse, self.R, self.N0)
+    def _boxes(self, ps, l: int, U, parent_boxes=None):
+        """Boxes of level l+1 from the tags of level l of `ps`."""
+        import torch
+        per = self._period(l)
+        flags = torch.zeros(per[::-1], dtype=torch.uint8, device="cuda")
+        ps.tag(l, U, 0, self.thresholds[l], flags)
+        coarse = M.cluster(flags.cpu().numpy(), int(round(self.buffer / self._h(l))))
+        boxes = fine_boxes(coarse, self.R, per)
+        if l > 0:
+            parent = parent_boxes if parent_boxes is not None else ps.hier.levels[l][1]
+            boxes = nest(boxes, parent, self.R, per)
+        if not boxes:
+            raise RuntimeError(f"nothing is tagged on level {l}: level {l + 1} would be empty")
+        return boxes
 
     def regrid(self) -> bool:
-        """Re-tag level 0 and move to the new fine boxes; False when they
-        are unchanged."""
-        boxes = self._boxes(self.ps, self.states[0]["U"])
-        if boxes == self.ps.hier.levels[1][1]:
+        """Re-tag every level but the finest (level l's tags on its current
+        data give level l+1, nested in the new level l) and move to the new
+        boxes; False when nothing changes."""
+        new = []
+        for l in range(self.nlev - 1):
+            new.append(self._boxes(self.ps, l, self.states[l]["U"], new[-1] if l else None))
+        if new == [self.ps.hier.levels[l][1] for l in range(1, self.nlev)]:
             return False
-        ps = M.Patchset(self._hier(boxes), self.system, prev=self.ps)  # level 0 taken over
+        ps = M.Patchset(self._hier(new), self.system, prev=self.ps)  # unchanged levels taken over
         states = ps.alloc_states()
         M.Regrid(ps, self.ps).apply([s["U"] for s in self.states], [s["U"] for s in states])
         self.ps, self.states = ps, states
-        self.history.append((self.t, boxes))
+        self.history.append((self.t, new))
         self.regrids += 1
         return True
 
     def dt0(self, tmode: int, courant: float = 0.25) -> float:
-        return courant * self.dx0 / (self.R if tmode == M.MOL_TIME_NOSUB else 1)
+        return courant * (self._h(self.nlev - 1) if tmode == M.MOL_TIME_NOSUB else self.dx0)
 
     def run(self, t_end: float, tmode: int = M.MOL_TIME_BOR, courant: float = 0.25, checkpoints=()):
         """Advance to t_end, regridding every regrid_dt; returns the level-0

@@ -358,9 +358,10 @@ int build_tiles(const Level& lev, const int td[3], int margin, TileList& tl, Are
     return tl.dev.upload(v, A);
 }
 
-// Tile of the stage kernels.  Wave: levels of at least 2^21 points march
-// along z (64 x 8 columns, chunk length chosen so that the launch still has
-// about 2048 workgroups); smaller levels use one thread per point.
+// Tile of the stage kernels (the autotuner can replace it).  Wave: levels of
+// at least 2^21 points march along z (64 x 8 columns, chunk length chosen so
+// that the launch has about 512 workgroups, the fastest measured at 256^3);
+// smaller levels use one thread per point.  MHD: 15 x 15 columns, 4 planes.
 void default_tile(int system, int64_t level_points, int td[3])
 {
     switch (system) {
@@ -369,7 +370,7 @@ void default_tile(int system, int64_t level_points, int td[3])
             td[0] = MOL_WAVE_WX;
             td[1] = MOL_WAVE_WY;
             td[2] = (int)std::max<int64_t>(
-                4, std::min<int64_t>(MOL_WAVE_ZMAX, level_points / (MOL_WAVE_WX * MOL_WAVE_WY * 2048)));
+                4, std::min<int64_t>(MOL_WAVE_ZMAX, level_points / (MOL_WAVE_WX * MOL_WAVE_WY * 512)));
         } else {
             td[0] = 32;
             td[1] = 4;
@@ -377,7 +378,7 @@ void default_tile(int system, int64_t level_points, int td[3])
         }
         break;
     case MOL_MHD:
-    case MOL_MHD_GLM: td[0] = 15; td[1] = 15; td[2] = 8; break;  // 15 x 15 columns, 8 planes (z-marching)
+    case MOL_MHD_GLM: td[0] = 15; td[1] = 15; td[2] = 4; break;  // 15 x 15 columns, 4 planes (z-marching)
     default: td[0] = MOL_CCZ4_TX; td[1] = MOL_CCZ4_TY; td[2] = MOL_CCZ4_TZ; break;
     }
 }

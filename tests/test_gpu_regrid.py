@@ -105,16 +105,19 @@ def _oracle_twin(run, tmode):
     def init(l, box, h):
         return run._exact(l, box)
     return AmrChannel(run.N0, run.xlo, run.dx0, run.R, run.threshold, run.buffer_pts, init, MODES[tmode],
-                      O.params(sigma=0.1))
+                      O.params(sigma=0.1), thresholds=run.thresholds)
 
 
-@pytest.mark.parametrize("tmode", [M.MOL_TIME_BOR, M.MOL_TIME_BO, M.MOL_TIME_NOSUB])
-def test_amr_wave_run_matches_oracle(tmode):
+@pytest.mark.parametrize("tmode,thresholds", [(M.MOL_TIME_BOR, (1e-3,)), (M.MOL_TIME_BO, (1e-3,)),
+                                              (M.MOL_TIME_NOSUB, (1e-3,)), (M.MOL_TIME_BOR, (1e-3, 1e-2)),
+                                              (M.MOL_TIME_NOSUB, (1e-3, 1e-2))])
+def test_amr_wave_run_matches_oracle(tmode, thresholds):
     """dx0 = 1/20 to t = 2.5: the left half of the pulse crosses the periodic
     edge, so the run covers boxes split at the edge, regrids that copy and
-    interpolate, and the sub-cycled steps in between."""
+    interpolate, and the sub-cycled steps in between; with one refined level
+    (the paper's) and with a second one nested in it."""
     _torch()
-    run = amr.AmrChannelRun(20)
+    run = amr.AmrChannelRun(20, thresholds=thresholds)
     ref = _oracle_twin(run, tmode)
     t_end = 2.5
     dt0 = run.dt0(tmode)
@@ -123,8 +126,8 @@ def test_amr_wave_run_matches_oracle(tmode):
     ref.run(dt0, int(round(t_end / dt0)), every)
     assert [b for _, b in run.history] == [b for _, b in ref.history]
     assert len(run.history) > 20
-    assert any(len(b) == 3 for _, b in run.history)  # a box cut at the edge
-    for l in range(2):
+    assert any(len(b[0]) == 3 for _, b in run.history)  # a box cut at the edge
+    for l in range(run.nlev):
         got = run.level_state(l)
         want = ref.level(l)
         assert len(got) == len(want)
@@ -199,3 +202,23 @@ def test_patchset_from_previous_matches_fresh_build(system):
             outs.append([st[l]["U"].cpu().numpy() for l in range(3)])
         for l in range(3):
             np.testing.assert_array_equal(outs[0][l], outs[1][l])
+
+
+def test_two_adaptive_levels_convergence():
+    """A second refined level (|phi| >= 1e-2 on level 1) on top of the paper's
+    one: n_c at dx0 = 1/40, 1/80, 1/160 with BOR stays near 4 (3.2 rising to
+    3.9), and the error against the exact solution is of the one-level run's
+    size (the level-2 boundary sits where |phi| is ten times larger, so its
+    interface error offsets the finer grid)."""
+    _torch()
+    times = (1.25, 2.5, 3.75, 5.0)
+    phis = [amr.AmrChannelRun(n, thresholds=(1e-3, 1e-2)).run(5.0, M.MOL_TIME_BOR, checkpoints=times)
+            for n in (40, 80, 160)]
+    nc = [amr.convergence_order([p[t] for p in phis]) for t in times]
+    one = amr.AmrChannelRun(160).run(5.0, M.MOL_TIME_BOR, checkpoints=(5.0,))[5.0]
+    x = -2.0 + np.arange(one.size) / 160
+    ex = synth.wave_channel_pulse(x, 5.0, 10.0, 0.173)
+    e1, e2 = np.abs(one - ex).sum(), np.abs(phis[-1][5.0] - ex).sum()
+    print("AMR two levels n_c", np.round(nc, 2), "error one level", e1 / 160, "two levels", e2 / 160, flush=True)
+    assert min(nc) > 3.0
+    assert 0.2 < e2 / e1 < 5.0

@@ -140,7 +140,38 @@ def test_amr_wave_run_follows_pulse_and_converges_at_fourth_order():
         errs.append(np.abs(phi - synth.wave_channel_pulse(x, t_end, 10.0, 0.173)).sum() / n)
         assert len(run.history) > 10
         # two boxes centred on x = -t_end and x = +t_end
-        centres = sorted(-2.0 + 0.5 * (lo[0] + hi[0]) / (2 * n) for lo, hi in run.boxes)
+        centres = sorted(-2.0 + 0.5 * (lo[0] + hi[0]) / (2 * n) for lo, hi in run.boxes[0])
         assert np.allclose(centres, [-t_end, t_end], atol=0.1), centres
     orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert errs[-1] < 2e-6 and orders[-1] > 3.5, (errs, orders)
+
+
+def test_inside_parent_clips_to_shrunk_parent():
+    from oracle.amr_wave import inside_parent
+    # a level-1 box [10, 40] (full in y and z) on a level of extent (64, 2, 2):
+    # level-2 boxes are cut to [2 (10 + 6), 2 (40 - 6)] = [32, 68] in x
+    parent = [((10, 0, 0), (40, 1, 1))]
+    got = inside_parent([((20, 0, 0), (90, 3, 3)), ((0, 0, 0), (40, 3, 3))], parent, 2, (64, 2, 2))
+    assert got == [((32, 0, 0), (68, 3, 3)), ((32, 0, 0), (40, 3, 3))]
+    assert inside_parent([((0, 0, 0), (20, 3, 3))], parent, 2, (64, 2, 2)) == []
+
+
+def test_two_adaptive_levels_nest_and_converge():
+    """Repeating the tagging on the new level (Sec. III.A): level 2 refines
+    where |phi| >= 1e-2 on level 1 and stays six level-1 points inside it; the
+    run is more accurate than with one refined level and converges at about
+    4th order (dx0 = 1/20, 1/40, t = 1.25)."""
+    errs, t_end = [], 1.25
+    for n in (20, 40):
+        dt0 = 0.25 / n
+        run = AmrChannel((10 * n, 1, 1), (-2.0, 0.0, 0.0), 1.0 / n, 2, 1e-3, round(0.1 * n), _init(), O.TIME_BOR,
+                         O.params(sigma=0.1), thresholds=(1e-3, 1e-2))
+        run.run(dt0, int(round(t_end / dt0)), max(int(round(0.0125 / dt0)), 1))
+        for _, (b1, b2) in run.history:
+            for lo, hi in b2:
+                assert any(2 * (plo[0] + 6) <= lo[0] and hi[0] <= 2 * (phi_[0] - 6) for plo, phi_ in b1), (lo, hi)
+                assert (lo[1], lo[2], hi[1], hi[2]) == (0, 0, 3, 3)
+        phi = synth.interior(run.H.get(0, 0))[0, 0, 0]
+        x = -2.0 + np.arange(phi.size) / n
+        errs.append(np.abs(phi - synth.wave_channel_pulse(x, t_end, 10.0, 0.173)).sum() / n)
+    assert errs[1] < 1.0e-5 and np.log2(errs[0] / errs[1]) > 3.5, errs
