@@ -24,6 +24,24 @@
 
 using namespace mol;
 
+// workgroup tiles of the adjoint (at most 256 threads each): over the
+// ghosted box for the transposed stencils (wave adjoint, CCZ4 gather), over
+// the interior for the CCZ4 point-wise kernels.  Measured on the 48^3 CCZ4
+// adjoint: the gather takes 185 us with 32 x 4 x 2 against 223 us with
+// 16 x 4 x 4 (rows of whole cache lines, fewer workgroups than resident
+// slots); the eight point-wise kernels 562 - 185 = 377 us with 16 x 16 x 1
+// against 411 us with the stage kernel's 8 x 8 x 4
+#ifndef MOL_ADJ_GTX
+#define MOL_ADJ_GTX 32
+#define MOL_ADJ_GTY 4
+#define MOL_ADJ_GTZ 2
+#endif
+#ifndef MOL_ADJ_PTX
+#define MOL_ADJ_PTX 16
+#define MOL_ADJ_PTY 16
+#define MOL_ADJ_PTZ 1
+#endif
+
 namespace {
 
 thread_local std::string g_err;
@@ -205,6 +223,7 @@ struct mol_patchset {
         std::vector<int64_t> rst_by_patch;
         TileList tiles;   // interior tiles for the stage kernels
         TileList gtiles;  // ghosted-box tiles for the adjoint
+        TileList ptiles;  // interior tiles for the CCZ4 adjoint's point-wise kernels
         TileList ntiles;  // interior tiles for reductions / initial data
         // CCZ4 adjoint workspace: start of each patch's block (slots x fs)
         DevArr<int64_t> wofs;
@@ -230,6 +249,7 @@ struct mol_patchset {
             l.rst.release();
             l.tiles.dev.release();
             l.gtiles.dev.release();
+            l.ptiles.dev.release();
             l.wofs.release();
             l.ntiles.dev.release();
         }
@@ -409,9 +429,9 @@ void reuse_level(mol_patchset* ps, const mol_patchset* prev, int l)
     lev.band_by_patch = o.band_by_patch;
     lev.rst.adopt(o.rst, A);
     lev.rst_by_patch = o.rst_by_patch;
-    TileList* mine[3] = {&lev.tiles, &lev.gtiles, &lev.ntiles};
-    const TileList* theirs[3] = {&o.tiles, &o.gtiles, &o.ntiles};
-    for (int i = 0; i < 3; ++i) {
+    TileList* mine[4] = {&lev.tiles, &lev.gtiles, &lev.ntiles, &lev.ptiles};
+    const TileList* theirs[4] = {&o.tiles, &o.gtiles, &o.ntiles, &o.ptiles};
+    for (int i = 0; i < 4; ++i) {
         for (int d = 0; d < 3; ++d) mine[i]->tdim[d] = theirs[i]->tdim[d];
         mine[i]->by_patch = theirs[i]->by_patch;
         mine[i]->count = theirs[i]->count;
@@ -744,8 +764,12 @@ int build(mol_patchset* ps, const mol_hierarchy_desc* h, const mol_patchset* pre
         for (const PatchDev& pd : lev.pd) npts += (int64_t)pd.n[0] * pd.n[1] * pd.n[2];
         default_tile(ps->sp.system, npts, td);
         build_tiles(lev, td, 0, lev.tiles, &ps->arena);
-        int tg[3] = {16, 4, 4};
+        int tg[3] = {MOL_ADJ_GTX, MOL_ADJ_GTY, MOL_ADJ_GTZ};
         build_tiles(lev, tg, G, lev.gtiles, &ps->arena);
+        if (ps->sp.system == MOL_CCZ4) {
+            int tp[3] = {MOL_ADJ_PTX, MOL_ADJ_PTY, MOL_ADJ_PTZ};
+            build_tiles(lev, tp, 0, lev.ptiles, &ps->arena);
+        }
         if (ps->sp.system == MOL_CCZ4) {
             std::vector<int64_t> wo(lev.pd.size());
             int64_t w = 0;
@@ -1259,7 +1283,7 @@ int mol_rhs_adjoint(mol_patchset* ps, int level, const double* U, const double* 
         if (!U || !work) return fail(MOL_EINVAL, "the CCZ4 adjoint needs U and the workspace");
         if (U == lamU || work == lamU || work == U || work == lam)
             return fail(MOL_EINVAL, "U, lamU and work must not alias");
-        e = launch_ccz4_adjoint(sp, lev.d_pd.p, lev.tiles.dev.p, (int)lev.tiles.dev.n, lev.tiles.tdim,
+        e = launch_ccz4_adjoint(sp, lev.d_pd.p, lev.ptiles.dev.p, (int)lev.ptiles.dev.n, lev.ptiles.tdim,
                                 lev.gtiles.dev.p, (int)lev.gtiles.dev.n, lev.gtiles.tdim, U, lam, work, lev.wofs.p,
                                 lamU, S(stream));
     }

@@ -809,6 +809,10 @@ ADJ_KERNEL(ccz4_adj_chain_kernel)
 }
 
 // ---------------------------------------------------------------- kernel 2
+#ifndef MOL_ADJ_GATHER_GROUP
+#define MOL_ADJ_GATHER_GROUP 9
+#endif
+
 __global__ __launch_bounds__(256) void ccz4_adj_gather_kernel(const PatchDev* __restrict__ patches,
                                                               const Tile* __restrict__ tiles,
                                                               const double* __restrict__ Ug,
@@ -840,43 +844,65 @@ __global__ __launch_bounds__(256) void ccz4_adj_gather_kernel(const PatchDev* __
     const double wko[7] = {1.0, -6.0, 15.0, -20.0, 15.0, -6.0, 1.0};
     const double wlp[7] = {0.0, 0.0, -3.0, -10.0, 18.0, -6.0, 1.0};  // beta >= 0: o = -3..3
     const double wlm[7] = {-1.0, 6.0, -18.0, 10.0, 3.0, 0.0, 0.0};   // beta < 0
-    double acc[NF];
+    // fields in groups of MOL_ADJ_GATHER_GROUP (9: the 25 fields in three
+    // sweeps, 5% faster than one sweep with 25 accumulators, at 160 instead
+    // of 247 VGPRs), one accumulator per field of the group; the taps are
+    // swept once per group (rolled loops keep the code small) and the terms
+    // of each field are summed in the same order whatever the grouping
 #pragma unroll
-    for (int f = 0; f < NF; ++f) acc[f] = self ? wp[(int64_t)(W_U + f) * fs] : 0.0;
-    // u(p) enters the stencils of the interior points c = p - o e_k
-    for (int k = 0; k < 3; ++k)
-        for (int o = -3; o <= 3; ++o) {
-            if (!inside(k, -o)) continue;
-            const int64_t cof = -(int64_t)o * S[k];
-            const double bk = bp[(int64_t)k * fs + cof];
-            const double wa = C.upwind ? (bk >= 0.0 ? wlp[o + 3] : wlm[o + 3]) : (o >= -2 && o <= 2 ? w1[o + 2] : 0.0);
-            // KO and advection act on lam of every field
-            const double wl = C.ko * wko[o + 3] + C.i12h * wa * bk;
+    for (int f0 = 0; f0 < NF; f0 += MOL_ADJ_GATHER_GROUP) {
+        constexpr int GF = MOL_ADJ_GATHER_GROUP;
+        double acc[GF];
 #pragma unroll
-            for (int f = 0; f < NF; ++f) acc[f] += wl * lp[(int64_t)f * fs + cof];
-            if (o < -2 || o > 2) continue;
+        for (int g = 0; g < GF; ++g)
+            if (f0 + g < NF) acc[g] = self ? wp[(int64_t)(W_U + f0 + g) * fs] : 0.0;
+        // u(p) enters the stencils of the interior points c = p - o e_k
+#pragma unroll 1
+        for (int k = 0; k < 3; ++k)
+#pragma unroll 1
+            for (int o = -3; o <= 3; ++o) {
+                if (!inside(k, -o)) continue;
+                const int64_t cof = -(int64_t)o * S[k];
+                const double bk = bp[(int64_t)k * fs + cof];
+                const double wa = C.upwind ? (bk >= 0.0 ? wlp[o + 3] : wlm[o + 3]) : (o >= -2 && o <= 2 ? w1[o + 2] : 0.0);
+                // KO and advection act on lam of every field
+                const double wl = C.ko * wko[o + 3] + C.i12h * wa * bk;
 #pragma unroll
-            for (int f = 0; f < NF; ++f) {
-                const int s1 = d1_slot(f), s2 = d2_slot(f);
-                if (s1 >= 0) acc[f] += C.i12h * w1[o + 2] * wp[(int64_t)(W_D1 + 3 * s1 + k) * fs + cof];
-                if (s2 >= 0) acc[f] += C.i12h2 * w2[o + 2] * wp[(int64_t)(W_D2 + 6 * s2 + SI(k, k)) * fs + cof];
-            }
-        }
-    for (int k = 0; k < 3; ++k)
-        for (int l = k + 1; l < 3; ++l)
-            for (int a = -2; a <= 2; ++a)
-                for (int b = -2; b <= 2; ++b) {
-                    if (a == 0 || b == 0 || !inside(k, -a, l, -b)) continue;
-                    const int64_t cof = -(int64_t)a * S[k] - (int64_t)b * S[l];
-                    const double wm = C.i144h2 * w1[a + 2] * w1[b + 2];
+                for (int g = 0; g < GF; ++g)
+                    if (f0 + g < NF) acc[g] += wl * lp[(int64_t)(f0 + g) * fs + cof];
+                if (o < -2 || o > 2) continue;
 #pragma unroll
-                    for (int f = 0; f < NF; ++f) {
-                        const int s2 = d2_slot(f);
-                        if (s2 >= 0) acc[f] += wm * wp[(int64_t)(W_D2 + 6 * s2 + SI(k, l)) * fs + cof];
-                    }
+                for (int g = 0; g < GF; ++g) {
+                    const int f = f0 + g;
+                    if (f >= NF) continue;
+                    const int s1 = d1_slot(f), s2 = d2_slot(f);
+                    if (s1 >= 0) acc[g] += C.i12h * w1[o + 2] * wp[(int64_t)(W_D1 + 3 * s1 + k) * fs + cof];
+                    if (s2 >= 0) acc[g] += C.i12h2 * w2[o + 2] * wp[(int64_t)(W_D2 + 6 * s2 + SI(k, k)) * fs + cof];
                 }
+            }
+#pragma unroll 1
+        for (int k = 0; k < 3; ++k)
+#pragma unroll 1
+            for (int l = k + 1; l < 3; ++l)
+#pragma unroll 1
+                for (int a = -2; a <= 2; ++a)
+#pragma unroll 1
+                    for (int b = -2; b <= 2; ++b) {
+                        if (a == 0 || b == 0 || !inside(k, -a, l, -b)) continue;
+                        const int64_t cof = -(int64_t)a * S[k] - (int64_t)b * S[l];
+                        const double wm = C.i144h2 * w1[a + 2] * w1[b + 2];
 #pragma unroll
-    for (int f = 0; f < NF; ++f) lamU[P.off + loc + (int64_t)f * fs] = acc[f];
+                        for (int g = 0; g < GF; ++g) {
+                            const int f = f0 + g;
+                            if (f >= NF) continue;
+                            const int s2 = d2_slot(f);
+                            if (s2 >= 0) acc[g] += wm * wp[(int64_t)(W_D2 + 6 * s2 + SI(k, l)) * fs + cof];
+                        }
+                    }
+#pragma unroll
+        for (int g = 0; g < GF; ++g)
+            if (f0 + g < NF) lamU[P.off + loc + (int64_t)(f0 + g) * fs] = acc[g];
+    }
 }
 
 }  // namespace
