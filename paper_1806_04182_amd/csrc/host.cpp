@@ -908,6 +908,7 @@ int stage_impl(mol_patchset* ps, int level, int mode, int stage, double dt, cons
     a.acc = acc;
     a.out = out;
     a.kst = kst;
+    a.stream = lev.nelems * (int64_t)sizeof(double) >= (int64_t(128) << 20);
     if (!plain) {
         a.tiles = lev.tiles.dev.p;
         a.ntiles = (int)lev.tiles.dev.n;

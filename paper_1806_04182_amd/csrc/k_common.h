@@ -43,59 +43,80 @@ __device__ __forceinline__ bool tile_point(const StageArgs& a, int tile, PointRe
     return true;
 }
 
+// Point loads and stores of the stage update; NT = true marks them
+// non-temporal (streamed past the caches), for levels whose arrays are far
+// larger than the caches.
+template <bool NT>
+__device__ __forceinline__ double mem_ld(const double* p)
+{
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+template <bool NT>
+__device__ __forceinline__ void mem_st(double* p, double v)
+{
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
 // Values the stage update reads at a point besides the right-hand side
 // (loaded separately so that kernels can fetch them ahead of use).
 struct StageIn {
     double un, ac, us;
 };
+template <bool NT = false>
 __device__ __forceinline__ StageIn stage_load(const StageArgs& a, int64_t idx)
 {
     StageIn v{0.0, 0.0, 0.0};
     if (a.mode == ST_RHS) return v;
-    v.un = a.Un[idx];
+    v.un = mem_ld<NT>(&a.Un[idx]);
     if (a.stage >= 2) {
         if (a.mode == ST_RK4)
-            v.ac = a.acc[idx];
+            v.ac = mem_ld<NT>(&a.acc[idx]);
         else
-            v.us = a.Us[idx];
+            v.us = mem_ld<NT>(&a.Us[idx]);
     }
     return v;
 }
 
 // k = dt * rhs, then the RK4 (Table RK44, accumulator form) or SSP-RK3
 // (Shu-Osher form of the App. D scheme) stage update, or plain rhs output.
+template <bool NT = false>
 __device__ __forceinline__ void stage_apply(const StageArgs& a, int64_t idx, double rhs, const StageIn& v)
 {
     if (a.mode == ST_RHS) {
-        a.out[idx] = rhs;
+        mem_st<NT>(&a.out[idx], rhs);
         return;
     }
     const double k = a.dt * rhs;
-    if (a.kst) a.kst[idx] = k;
+    if (a.kst) mem_st<NT>(&a.kst[idx], k);
     const double un = v.un;
     if (a.mode == ST_RK4) {
         switch (a.stage) {
         case 1:
-            a.acc[idx] = k * (1.0 / 6.0);
-            a.out[idx] = un + 0.5 * k;
+            mem_st<NT>(&a.acc[idx], k * (1.0 / 6.0));
+            mem_st<NT>(&a.out[idx], un + 0.5 * k);
             break;
         case 2:
-            a.acc[idx] = v.ac + k * (1.0 / 3.0);
-            a.out[idx] = un + 0.5 * k;
+            mem_st<NT>(&a.acc[idx], v.ac + k * (1.0 / 3.0));
+            mem_st<NT>(&a.out[idx], un + 0.5 * k);
             break;
         case 3:
-            a.acc[idx] = v.ac + k * (1.0 / 3.0);
-            a.out[idx] = un + k;
+            mem_st<NT>(&a.acc[idx], v.ac + k * (1.0 / 3.0));
+            mem_st<NT>(&a.out[idx], un + k);
             break;
         default:
-            a.out[idx] = un + (v.ac + k * (1.0 / 6.0));
+            mem_st<NT>(&a.out[idx], un + (v.ac + k * (1.0 / 6.0)));
             break;
         }
     } else {
         switch (a.stage) {
-        case 1: a.out[idx] = un + k; break;
-        case 2: a.out[idx] = 0.75 * un + 0.25 * (v.us + k); break;
-        default: a.out[idx] = (1.0 / 3.0) * un + (2.0 / 3.0) * (v.us + k); break;
+        case 1: mem_st<NT>(&a.out[idx], un + k); break;
+        case 2: mem_st<NT>(&a.out[idx], 0.75 * un + 0.25 * (v.us + k)); break;
+        default: mem_st<NT>(&a.out[idx], (1.0 / 3.0) * un + (2.0 / 3.0) * (v.us + k)); break;
         }
     }
 }

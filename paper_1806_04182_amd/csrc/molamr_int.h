@@ -125,6 +125,10 @@ struct StageArgs {
     double* acc;
     double* out;
     double* kst;
+    // 1 when one array of the level exceeds 128 MiB: the z-marching wave
+    // kernel then streams its point loads and stores past the caches (the
+    // other stage kernels measured slower with that and ignore it)
+    int stream;
 };
 
 // kernel launchers (each returns hipGetLastError() of its launch)
