@@ -83,7 +83,7 @@ def kernel_trace_md(folder, cmd):
         grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
         acc[(_short(r["Kernel_Name"]), grid)].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
     total = sum(sum(v) for v in acc.values())
-    out = ["# rocprofv3 kernel-trace summary of the benchmark", "", "Command (repository root on the GPU box):",
+    out = ["# rocprofv3 kernel-trace summary of the benchmark", "", "Command (run from the repository root):",
            "", "    " + cmd, "",
            "Kernels of this library with at least 0.1% of the GPU time, by grid size (work-items).", "",
            "| kernel | grid | calls | avg (us) | min (us) | max (us) | share |", "|---|---|---|---|---|---|---|"]
