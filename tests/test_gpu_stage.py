@@ -65,6 +65,24 @@ def test_wave_rk4_parity(n):
     assert np.all(e <= TOL), e
 
 
+def test_wave_rk4_parity_streamed_level():
+    """256^3 (a level array of 290 MB): the z-marching kernel takes its
+    non-temporal variant for the stage-update loads and stores; one full RK4
+    step against the oracle, element by element."""
+    print("wave rk4 256^3 streamed", flush=True)
+    n = (256, 256, 256)
+    dx = 2.0 / n[0]
+    ps = M.Patchset(M.single_patch(n, (0, 0, 0), dx), M.System(M.MOL_WAVE, sigma=0.1))
+    assert ps.level_layout(0)["nelems"] * 8 >= 128 << 20
+    del ps
+    U0 = synth.embed(synth.wave_gaussian(n, (-1, -1, -1), dx, centre=synth.wave_centre(3),
+                                         period=(n[0] * dx, n[1] * dx, n[2] * dx)))
+    got = _gpu_steps(O.WAVE, M.MOL_RK4, U0, dx, 0.25 * dx, 1, M.System(M.MOL_WAVE, sigma=0.1))
+    ref = _oracle_steps(O.WAVE, O.RK4, U0, dx, 0.25 * dx, 1, O.params(sigma=0.1))
+    e = parity_err(got[:, 3:-3, 3:-3, 3:-3], ref[:, 3:-3, 3:-3, 3:-3])
+    assert np.all(e <= TOL), e
+
+
 @pytest.mark.parametrize("n", [(20, 17, 11), (1, 24, 5), (46, 31, 17)])
 def test_mhd_ssprk3_parity(n):
     print("mhd ssprk3", n, flush=True)
