@@ -23,6 +23,8 @@
 // done; then the RK stage update writes the results.
 #include <utility>
 
+#include <algorithm>
+
 #include "k_common.h"
 
 namespace mol {
@@ -75,24 +77,37 @@ constexpr int ORDER[NF] = {GT + 0, GT + 1, GT + 2,   GT + 3,   GT + 4,   GT + 5,
                            AT + 1, AT + 2, AT + 3,   AT + 4,   AT + 5,   GH + 0, GH + 1, GH + 2,
                            BETA + 0, BETA + 1, BETA + 2, KH,     TH,     BB + 0, BB + 1, BB + 2};
 
-template <int TX, int TY, int TZ, bool UPWIND>
-__global__ __launch_bounds__(TX * TY * TZ, MOL_CCZ4_WAVES) void ccz4_stage_kernel(StageArgs a, CczConst C)
-{
-    // halo tile in LDS: rows padded to a pitch of PX doubles.  A wave reads
-    // 8 rows of 8 doubles; with PX = 24 (= 8 mod 16 doubles) every group of
-    // rows served in one LDS cycle starts on distinct banks
-    constexpr int HX = TX + 2 * G, HY = TY + 2 * G, HZ = TZ + 2 * G;
-    constexpr int PX = TX == 8 ? 24 : HX;
-    constexpr int NT = TX * TY * TZ;
-    // halo loads: 16 lanes per row (x), NT / 16 rows per pass covering PP
-    // whole planes, NR passes; the offset between passes is a constant
-    constexpr int LW = 16, PP = (NT / LW) / HY, NR = (HZ + PP - 1) / PP;
-    static_assert(HX <= LW && PP >= 1 && HZ % PP == 0, "halo tile does not fit the load pattern");
-    constexpr int LV = PX * HY * HZ;
-    __shared__ double buf[LV];
-    __shared__ double akx[NF][NT];  // advection + dissipation of every field
+// LDS geometry of the stage kernel for a TX x TY x TZ tile.  The halo tile's
+// rows are padded to a pitch of PX doubles: a wave reads 8 rows of 8 doubles;
+// with PX = 24 (= 8 mod 16 doubles) every group of rows served in one LDS
+// cycle starts on distinct banks.  Halo loads: 16 lanes per row (x), NT / 16
+// rows per pass covering PP whole planes, NR passes; the offset between
+// passes is a constant.
+#ifndef MOL_CCZ4_PERSISTENT
+#define MOL_CCZ4_PERSISTENT 0
+#endif
 
-    const Tile tile = a.tiles[xcd_tile(blockIdx.x, gridDim.x)];
+template <int TX, int TY, int TZ>
+struct CczLds {
+    static constexpr int HX = TX + 2 * G, HY = TY + 2 * G, HZ = TZ + 2 * G;
+    static constexpr int PX = TX == 8 ? 24 : HX;
+    static constexpr int NT = TX * TY * TZ;
+    static constexpr int LW = 16, PP = (NT / LW) / HY, NR = (HZ + PP - 1) / PP;
+    static_assert(HX <= LW && PP >= 1 && HZ % PP == 0, "halo tile does not fit the load pattern");
+    static constexpr int LV = PX * HY * HZ;
+};
+
+// One tile of the stage: the right-hand side of every interior point of tile
+// tidx and its stage update.  buf: the halo tile of the field passing
+// through LDS; akx: advection + dissipation of every field.
+template <int TX, int TY, int TZ, bool UPWIND>
+__device__ __forceinline__ void ccz4_tile(const StageArgs& a, const CczConst& C, int tidx, double* __restrict__ buf,
+                                          double (*__restrict__ akx)[TX * TY * TZ])
+{
+    using L = CczLds<TX, TY, TZ>;
+    constexpr int HX = L::HX, HY = L::HY, HZ = L::HZ, PX = L::PX, NT = L::NT, LW = L::LW, PP = L::PP, NR = L::NR;
+
+    const Tile tile = a.tiles[tidx];
     const PatchDev P = a.patches[tile.patch];
     const int tx = threadIdx.x, ty = threadIdx.y, tz = threadIdx.z;
     const int tid = tx + TX * (ty + TY * tz);
@@ -483,6 +498,37 @@ __global__ __launch_bounds__(TX * TY * TZ, MOL_CCZ4_WAVES) void ccz4_stage_kerne
     out(ALP, -alp * alp * (C.f0 + C.f1 / alp) * Kh);
 }
 
+template <int TX, int TY, int TZ, bool UPWIND>
+__global__ __launch_bounds__(TX * TY * TZ, MOL_CCZ4_WAVES) void ccz4_stage_kernel(StageArgs a, CczConst C)
+{
+    using L = CczLds<TX, TY, TZ>;
+    __shared__ double buf[L::LV];
+    __shared__ double akx[NF][L::NT];
+    ccz4_tile<TX, TY, TZ, UPWIND>(a, C, xcd_tile(blockIdx.x, gridDim.x), buf, akx);
+}
+
+// Persistent form: a grid of at most as many workgroups as are resident at
+// once; the workgroups of XCD x (x = blockIdx mod 8) take the tiles of that
+// XCD's contiguous range of the tile list in turn, so that concurrently
+// running tiles of an XCD stay spatial neighbours, and every workgroup exits
+// after its last tile.
+template <int TX, int TY, int TZ, bool UPWIND>
+__global__ __launch_bounds__(TX * TY * TZ, MOL_CCZ4_WAVES) void ccz4_stage_persistent_kernel(StageArgs a, CczConst C)
+{
+    using L = CczLds<TX, TY, TZ>;
+    __shared__ double buf[L::LV];
+    __shared__ double akx[NF][L::NT];
+    constexpr int NXCD = 8;
+    const int n = a.ntiles, x = blockIdx.x % NXCD, slot = blockIdx.x / NXCD;
+    const int per = n / NXCD, rem = n % NXCD;
+    const int lo = x * per + (x < rem ? x : rem), hi = lo + per + (x < rem ? 1 : 0);
+    const int nwg = ((int)gridDim.x - x + NXCD - 1) / NXCD;  // workgroups of this XCD
+    for (int t = lo + slot; t < hi; t += nwg) {
+        ccz4_tile<TX, TY, TZ, UPWIND>(a, C, t, buf, akx);
+        __syncthreads();  // the next tile overwrites buf and akx
+    }
+}
+
 }  // namespace
 
 hipError_t launch_stage_ccz4(const SysParams& sp, const StageArgs& a, const int td[3], hipStream_t s)
@@ -501,10 +547,28 @@ hipError_t launch_stage_ccz4(const SysParams& sp, const StageArgs& a, const int 
     C.g = sp.gd_g;
     C.eta = sp.gd_eta;
     dim3 blk(MOL_CCZ4_TX, MOL_CCZ4_TY, MOL_CCZ4_TZ);
+#if MOL_CCZ4_PERSISTENT
+    // as many workgroups as are resident at once: MOL_CCZ4_WAVES waves per
+    // SIMD, four SIMDs per compute unit
+    static int cus[64] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    if (!cus[dev] && (e = hipDeviceGetAttribute(&cus[dev], hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+        return e;
+    constexpr int wg_per_cu = MOL_CCZ4_WAVES * 4 / (MOL_CCZ4_TX * MOL_CCZ4_TY * MOL_CCZ4_TZ / 64);
+    const int grid = std::min(a.ntiles, cus[dev] * std::max(wg_per_cu, 1));
+    if (sp.upwind)
+        ccz4_stage_persistent_kernel<MOL_CCZ4_TX, MOL_CCZ4_TY, MOL_CCZ4_TZ, true><<<grid, blk, 0, s>>>(a, C);
+    else
+        ccz4_stage_persistent_kernel<MOL_CCZ4_TX, MOL_CCZ4_TY, MOL_CCZ4_TZ, false><<<grid, blk, 0, s>>>(a, C);
+#else
     if (sp.upwind)
         ccz4_stage_kernel<MOL_CCZ4_TX, MOL_CCZ4_TY, MOL_CCZ4_TZ, true><<<a.ntiles, blk, 0, s>>>(a, C);
     else
         ccz4_stage_kernel<MOL_CCZ4_TX, MOL_CCZ4_TY, MOL_CCZ4_TZ, false><<<a.ntiles, blk, 0, s>>>(a, C);
+#endif
     return hipGetLastError();
 }
 
