@@ -32,13 +32,20 @@ __device__ __forceinline__ void copy_fields(const double* __restrict__ src, int6
     }
 }
 
-// same-level / periodic copy: ghost <- interior point of the owning patch
+// same-level / periodic copy: ghost <- interior point of the owning patch.
+// One thread per (ghost point, group of FC fields), the group the slow index,
+// so that a launch has ceil(nf / FC) times as many threads, each with one
+// batch of loads in flight, and consecutive threads still copy consecutive
+// points.
 __global__ __launch_bounds__(BLK) void fill_kernel(const GhostCopy* __restrict__ e, int64_t n, int nf,
                                                    double* __restrict__ U)
 {
-    for (int64_t t = blockIdx.x * (int64_t)BLK + threadIdx.x; t < n; t += (int64_t)gridDim.x * BLK) {
-        const GhostCopy c = e[t];
-        copy_fields(U + c.src, c.sfs, U + c.dst, c.dfs, nf);
+    const int ng = (nf + FC - 1) / FC;
+    for (int64_t t = blockIdx.x * (int64_t)BLK + threadIdx.x; t < n * ng; t += (int64_t)gridDim.x * BLK) {
+        const int64_t gi = t / n;
+        const GhostCopy c = e[t - gi * n];
+        const int f0 = (int)gi * FC;
+        copy_fields(U + c.src + f0 * c.sfs, c.sfs, U + c.dst + f0 * c.dfs, c.dfs, min(FC, nf - f0));
     }
 }
 
@@ -195,7 +202,7 @@ __global__ __launch_bounds__(BLK) void axpby_kernel(int64_t n, double a, const d
 hipError_t launch_fill(const GhostCopy* e, int64_t n, int nf, double* U, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    fill_kernel<<<grid_for(n), BLK, 0, s>>>(e, n, nf, U);
+    fill_kernel<<<grid_for(n * ((nf + FC - 1) / FC)), BLK, 0, s>>>(e, n, nf, U);
     return hipGetLastError();
 }
 
