@@ -272,6 +272,17 @@ int mol_fill_ghosts_adjoint(mol_patchset* ps, int level, double* lamU, void* str
  * ignored and left unchanged. */
 int mol_rk4_adjoint_step(mol_patchset* ps, int level, double dt, const double* Un, double* lam,
                          double* const w[6], double* work, void* stream);
+/* The same reverse RK4 step from stage states the caller kept (project
+ * addition): Ust[0..3] = U_1 = U^n, U_2 = U^n + k_1/2, U_3 = U^n + k_2/2,
+ * U_4 = U^n + k_3 with k_s = dt L(U_s), ghosts filled, exactly as the forward
+ * stages of mol_rk_stage produce them; read by the CCZ4 system (Ust may be
+ * NULL for the wave).  Needs no forward recomputation, so a caller that
+ * stores the stage states while it recomputes a checkpoint segment saves
+ * three stage launches per reverse step.  w[0..2]: work buffers of the
+ * level's size; work: as for mol_rhs_adjoint.  The stage states must not
+ * alias lam, w or work (MOL_EINVAL). */
+int mol_rk4_adjoint_step_stages(mol_patchset* ps, int level, double dt, const double* const Ust[4], double* lam,
+                                double* const w[3], double* work, void* stream);
 
 /* Reductions over the interior of every patch of the level, for
  * v = U[field] - shift: out_dev[0] = sum |v| dV, [1] = sum v^2 dV,

@@ -16,9 +16,10 @@ segments are not recomputed.
 CCZ4.  Forward: flat data with alpha = 1 + A exp(-|x - c|^2 / w^2)
 (mol_ccz4_lapse_pulse); nsteps RK4 steps; J = sum_{|x| < R} (alpha - 1) dV.
 Backward: the operator is nonlinear, so each segment is recomputed forward
-from its checkpoint (its states kept), then the reverse RK4 steps
-(mol_rk4_adjoint_step with the state at the start of each step) run from the
-last state of the segment back to its checkpoint; dJ/dp through
+from its checkpoint with the stage kernels, keeping the four stage states of
+every step, then the reverse RK4 steps (mol_rk4_adjoint_step_stages, which
+needs no further recomputation) run from the last step of the segment back
+to its checkpoint; dJ/dp through
 mol_ccz4_lapse_pulse_vjp.  All arithmetic runs in libmolamr.
 """
 from __future__ import annotations
@@ -92,21 +93,29 @@ class Ccz4LapseObjective(torch.autograd.Function):
     def backward(ctx, gJ):
         ps = ctx.ps
         lam = ps.alloc(0)
-        w = [ps.alloc(0) for _ in range(6)]
+        w = [ps.alloc(0) for _ in range(3)]
         work = ps.alloc_work(0)
         ps.sphere_adjoint(0, ALPHA, ctx.radius, float(gJ), lam)
-        st = ps.alloc_states()
+        U = ps.alloc(0)
+        acc = ps.alloc(0)
         nseg = (ctx.nsteps + ctx.every - 1) // ctx.every
         for k in reversed(range(nseg)):
             steps = min(ctx.every, ctx.nsteps - k * ctx.every)
-            # states at the start of each step of the segment
-            st[0]["U"].copy_(ctx.ckpts[k])
-            states = []
+            # the segment recomputed from its checkpoint with the forward
+            # stages (the kernels and order of mol_advance), keeping the four
+            # stage states of every step (ghosts filled) for the reverse steps
+            U.copy_(ctx.ckpts[k])
+            kept = []
             for _ in range(steps):
-                states.append(st[0]["U"].clone())
-                ps.advance(st, ctx.dt)
-            for Un in reversed(states):
-                ps.rk4_adjoint_step(0, ctx.dt, lam, w, Un=Un, work=work)
+                stages = [U.clone()] + [ps.alloc(0) for _ in range(3)]
+                for s in range(1, 5):
+                    out = stages[s] if s < 4 else U
+                    ps.rk_stage(0, M.MOL_RK4, s, ctx.dt, stages[0], stages[s - 1], acc, out)
+                    ps.fill_ghosts(0, out)
+                kept.append(stages)
+            for stages in reversed(kept):
+                ps.rk4_adjoint_step_stages(0, ctx.dt, lam, w, stages=stages, work=work)
+            del kept
         g = torch.zeros(5, dtype=torch.float64, device=lam.device)
         ps.ccz4_lapse_pulse_vjp(0, ctx.p, lam, g)
         return g.cpu(), None, None, None, None, None

@@ -1310,44 +1310,25 @@ int mol_fill_ghosts_adjoint(mol_patchset* ps, int level, double* lamU, void* str
     return e == hipSuccess ? MOL_OK : hip_fail(e, "fill adjoint launch");
 }
 
-int mol_rk4_adjoint_step(mol_patchset* ps, int level, double dt, const double* Un, double* lam,
-                         double* const w[6], double* work, void* stream)
+namespace {
+// Reverse of U' = U + sum_s c_s k_s, k_s = dt L(U_s), U_s = U + b_s k_{s-1}:
+//   lk_s = c_s lam + b_{s+1} m_{s+1};  m_s = fill^T(L'(U_s)^T (dt lk_s));
+//   lam  <- lam + m_1 + m_2 + m_3 + m_4.
+// Ust: the stage states U_1 = U^n .. U_4 (ghosts filled; unused by the
+// wave).  w0 = dt lk; w1 and w2 hold the current m and the running sum of the
+// m's (the buffer that receives m_4 becomes the sum).
+int rk4_adjoint_core(mol_patchset* ps, int level, double dt, const double* const Ust[4], double* lam, double* w0,
+                     double* w1, double* w2, double* work, void* stream)
 {
-    int rc = check_level(ps, level);
-    if (rc) return rc;
-    if (ps->open) return fail(MOL_EUNSUPPORTED, "the adjoint needs a periodic domain");
-    const bool nl = ps->sp.system == MOL_CCZ4;
-    if (ps->sp.system != MOL_WAVE && !nl)
-        return fail(MOL_EUNSUPPORTED, "the RK4 adjoint exists for the wave and CCZ4 systems");
-    if (!lam || !w || !w[0] || !w[1] || !w[2]) return fail(MOL_EINVAL, "null buffer");
-    if (nl && (!Un || !w[3] || !w[4] || !w[5] || !work))
-        return fail(MOL_EINVAL, "the CCZ4 RK4 adjoint needs U^n, six work buffers and the workspace");
-    if (ps->nlev != 1) return fail(MOL_EUNSUPPORTED, "the RK4 adjoint handles one periodic level");
-    if (!std::isfinite(dt) || dt <= 0.0) return fail(MOL_EINVAL, "dt must be positive and finite");
     const int64_t n = ps->L[level].nelems;
     hipStream_t s = S(stream);
-    // Reverse of U' = U + sum_s c_s k_s, k_s = dt L(U_s), U_s = U + b_s k_{s-1}:
-    //   lk_s = c_s lam + b_{s+1} m_{s+1};  m_s = fill^T(L'(U_s)^T (dt lk_s));
-    //   lam  <- lam + m_1 + m_2 + m_3 + m_4.
-    // w0 = dt lk; w1 and w2 hold the current m and the running sum of the m's
-    // (the buffer that receives m_4 becomes the sum); for a nonlinear system
-    // w3..w5 hold the stage states U_2..U_4, recomputed from U^n with the
-    // forward stage kernel (w2 serves as its accumulator).
     static const double cw[4] = {1.0 / 6.0, 2.0 / 6.0, 2.0 / 6.0, 1.0 / 6.0};
     static const double bsub[4] = {0.0, 0.5, 0.5, 1.0};
-    const double* Ust[4] = {Un, nullptr, nullptr, nullptr};
-    if (nl) {
-        const double* in[3] = {Un, w[3], w[4]};
-        for (int st = 0; st < 3; ++st) {
-            if ((rc = stage_impl(ps, level, ST_RK4, st + 1, dt, Un, in[st], w[2], w[3 + st], nullptr, s, 0))) return rc;
-            if ((rc = fill_impl(ps, level, w[3 + st], ps->sp.nf, s, 0))) return rc;
-            Ust[st + 1] = w[3 + st];
-        }
-    }
     hipError_t e = hipSuccess;
-    double* wk = w[0];
-    double* wm = w[1];
-    double* wsum = w[2];
+    int rc;
+    double* wk = w0;
+    double* wm = w1;
+    double* wsum = w2;
     const double* prev = nullptr;  // m_{s+1}
     for (int st = 3; st >= 0; --st) {
         if (st == 3)
@@ -1368,6 +1349,63 @@ int mol_rk4_adjoint_step(mol_patchset* ps, int level, double dt, const double* U
     }
     e = launch_axpby(n, 1.0, lam, 1.0, wsum, lam, s);
     return e == hipSuccess ? MOL_OK : hip_fail(e, "axpby");
+}
+
+int rk4_adjoint_check(mol_patchset* ps, int level, double dt)
+{
+    int rc = check_level(ps, level);
+    if (rc) return rc;
+    if (ps->open) return fail(MOL_EUNSUPPORTED, "the adjoint needs a periodic domain");
+    if (ps->sp.system != MOL_WAVE && ps->sp.system != MOL_CCZ4)
+        return fail(MOL_EUNSUPPORTED, "the RK4 adjoint exists for the wave and CCZ4 systems");
+    if (ps->nlev != 1) return fail(MOL_EUNSUPPORTED, "the RK4 adjoint handles one periodic level");
+    if (!std::isfinite(dt) || dt <= 0.0) return fail(MOL_EINVAL, "dt must be positive and finite");
+    return MOL_OK;
+}
+}  // namespace
+
+int mol_rk4_adjoint_step(mol_patchset* ps, int level, double dt, const double* Un, double* lam,
+                         double* const w[6], double* work, void* stream)
+{
+    int rc = rk4_adjoint_check(ps, level, dt);
+    if (rc) return rc;
+    const bool nl = ps->sp.system == MOL_CCZ4;
+    if (!lam || !w || !w[0] || !w[1] || !w[2]) return fail(MOL_EINVAL, "null buffer");
+    if (nl && (!Un || !w[3] || !w[4] || !w[5] || !work))
+        return fail(MOL_EINVAL, "the CCZ4 RK4 adjoint needs U^n, six work buffers and the workspace");
+    hipStream_t s = S(stream);
+    // for a nonlinear system w3..w5 hold the stage states U_2..U_4,
+    // recomputed from U^n with the forward stage kernel (w2 serves as its
+    // accumulator)
+    const double* Ust[4] = {Un, nullptr, nullptr, nullptr};
+    if (nl) {
+        const double* in[3] = {Un, w[3], w[4]};
+        for (int st = 0; st < 3; ++st) {
+            if ((rc = stage_impl(ps, level, ST_RK4, st + 1, dt, Un, in[st], w[2], w[3 + st], nullptr, s, 0))) return rc;
+            if ((rc = fill_impl(ps, level, w[3 + st], ps->sp.nf, s, 0))) return rc;
+            Ust[st + 1] = w[3 + st];
+        }
+    }
+    return rk4_adjoint_core(ps, level, dt, Ust, lam, w[0], w[1], w[2], work, stream);
+}
+
+int mol_rk4_adjoint_step_stages(mol_patchset* ps, int level, double dt, const double* const Ust[4], double* lam,
+                                double* const w[3], double* work, void* stream)
+{
+    int rc = rk4_adjoint_check(ps, level, dt);
+    if (rc) return rc;
+    const bool nl = ps->sp.system == MOL_CCZ4;
+    if (!lam || !w || !w[0] || !w[1] || !w[2]) return fail(MOL_EINVAL, "null buffer");
+    if (nl && (!Ust || !Ust[0] || !Ust[1] || !Ust[2] || !Ust[3] || !work))
+        return fail(MOL_EINVAL, "the CCZ4 RK4 adjoint needs the four stage states and the workspace");
+    const double* none[4] = {nullptr, nullptr, nullptr, nullptr};
+    const double* const* st = Ust ? Ust : none;
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 3; ++j)
+            if (st[i] && (st[i] == lam || st[i] == w[j] || st[i] == work))
+                return fail(MOL_EINVAL, "a stage state aliases lam, a work buffer or the workspace");
+    const double* U4[4] = {st[0], st[1], st[2], st[3]};
+    return rk4_adjoint_core(ps, level, dt, U4, lam, w[0], w[1], w[2], work, stream);
 }
 
 namespace {

@@ -97,6 +97,7 @@ def lib():
             "mol_adjoint_workspace": ([vp, i], ctypes.c_int64),
             "mol_fill_ghosts_adjoint": ([vp, i, vp, vp], i),
             "mol_rk4_adjoint_step": ([vp, i, d, vp, vp, ctypes.POINTER(vp), vp, vp], i),
+            "mol_rk4_adjoint_step_stages": ([vp, i, d, ctypes.POINTER(vp), vp, ctypes.POINTER(vp), vp, vp], i),
             "mol_norms": ([vp, i, vp, i, d, d, vp, vp], i),
             "mol_box_norms": ([vp, i, vp, i, d, dp, dp, vp, vp], i),
             "mol_sphere_adjoint": ([vp, i, i, d, d, vp, vp], i),
@@ -297,6 +298,14 @@ class Patchset:
         ws = list(w) + [None] * (6 - len(w))
         arr = (ctypes.c_void_p * 6)(*[_ptr(x) for x in ws])
         _check(lib().mol_rk4_adjoint_step(self._h, level, dt, _ptr(Un), _ptr(lam), arr, _ptr(work), _stream(stream)))
+
+    def rk4_adjoint_step_stages(self, level, dt, lam, w, stages=None, work=None, stream=None):
+        """Reverse RK4 step from kept stage states: stages = [U_1 = U^n, U_2,
+        U_3, U_4] (ghosts filled; None for the wave); w: 3 level-size work
+        buffers."""
+        st = (ctypes.c_void_p * 4)(*[_ptr(x) for x in stages]) if stages is not None else None
+        arr = (ctypes.c_void_p * 3)(*[_ptr(x) for x in w])
+        _check(lib().mol_rk4_adjoint_step_stages(self._h, level, dt, st, _ptr(lam), arr, _ptr(work), _stream(stream)))
 
     def norms(self, level, U, field, shift, radius, out_dev, stream=None):
         _check(lib().mol_norms(self._h, level, _ptr(U), field, shift, radius, _ptr(out_dev), _stream(stream)))

@@ -141,3 +141,14 @@ def test_set_tiling_rejects_bad_launch_shapes():
     import ctypes
     t = M._Tiling((ctypes.c_int * 3)(64, 8, 4), 0, 0.0)
     assert M.lib().mol_set_tiling(None, 0, ctypes.byref(t)) == -1  # MOL_EINVAL
+
+
+def test_adjoint_steps_reject_null_patchset():
+    """Both reverse RK4 entry points validate their handle on the host."""
+    import ctypes
+    L = M.lib()
+    w = (ctypes.c_void_p * 6)()
+    st = (ctypes.c_void_p * 4)()
+    assert L.mol_rk4_adjoint_step(None, 0, 0.1, None, None, w, None, None) == -1  # MOL_EINVAL
+    assert L.mol_rk4_adjoint_step_stages(None, 0, 0.1, st, None, w, None, None) == -1
+    assert "null patchset" in M.lib().mol_last_error().decode()

@@ -111,6 +111,45 @@ def test_rk4_adjoint_step_dot_product_with_oracle_jvp():
     assert abs(got - ref) <= 1e-12 * abs(ref), (got, ref)
 
 
+def test_rk4_adjoint_step_from_kept_stages_equals_recomputing_step():
+    """mol_rk4_adjoint_step_stages with the stage states produced by the
+    forward stage launches gives the same lam, bit for bit, as
+    mol_rk4_adjoint_step, which recomputes them (the same kernels in the same
+    order); the wave form with no stage states too."""
+    torch = _torch()
+    n = (12, 9, 7)
+    dx = 2.0 / 12
+    dt = 0.25 * dx
+    print("kept-stage reverse step", n, flush=True)
+    ps = M.Patchset(M.single_patch(n, (-1, -1, -1), dx), M.System(M.MOL_CCZ4))
+    Un = torch.from_numpy(ps.pack(0, [_state(n, dx, 6)])).cuda()
+    rng = np.random.default_rng(7)
+    lam0 = torch.from_numpy(ps.pack(0, [synth.embed(rng.standard_normal((25,) + tuple(reversed(n))))])).cuda()
+    work = ps.alloc_work(0)
+    L1 = lam0.clone()
+    ps.rk4_adjoint_step(0, dt, L1, [ps.alloc(0) for _ in range(6)], Un=Un, work=work)
+    stages = [Un] + [ps.alloc(0) for _ in range(3)]
+    acc, Unext = ps.alloc(0), ps.alloc(0)
+    for s in range(1, 5):
+        out = stages[s] if s < 4 else Unext
+        ps.rk_stage(0, M.MOL_RK4, s, dt, Un, stages[s - 1], acc, out)
+        ps.fill_ghosts(0, out)
+    L2 = lam0.clone()
+    ps.rk4_adjoint_step_stages(0, dt, L2, [ps.alloc(0) for _ in range(3)], stages=stages, work=work)
+    torch.cuda.synchronize()
+    assert torch.equal(L1, L2)
+    with pytest.raises(M.MolError):
+        ps.rk4_adjoint_step_stages(0, dt, L2, [ps.alloc(0) for _ in range(3)], stages=stages[:3] + [L2], work=work)
+    # wave: linear, no stage states
+    pw = M.Patchset(M.single_patch(n, (-1, -1, -1), dx), M.System(M.MOL_WAVE, sigma=0.1))
+    lw = torch.from_numpy(pw.pack(0, [synth.embed(rng.standard_normal((2,) + tuple(reversed(n))))])).cuda()
+    a, b = lw.clone(), lw.clone()
+    pw.rk4_adjoint_step(0, dt, a, [pw.alloc(0) for _ in range(3)])
+    pw.rk4_adjoint_step_stages(0, dt, b, [pw.alloc(0) for _ in range(3)])
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
 def test_lapse_objective_gradient_matches_central_differences():
     torch = _torch()
     from paper_1806_04182_amd.adjoint import ccz4_lapse_objective
