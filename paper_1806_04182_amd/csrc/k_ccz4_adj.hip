@@ -120,6 +120,13 @@ __device__ __forceinline__ bool pt_init(Pt& q, const PatchDev* __restrict__ patc
     return true;
 }
 
+#ifndef MOL_ADJ_GAUGE_WAVES
+#define MOL_ADJ_GAUGE_WAVES 2
+#endif
+#define ADJ_KERNEL2(name, waves)                                                                           \
+    __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves))) void name(                \
+        const PatchDev* __restrict__ patches, const Tile* __restrict__ tiles, const double* __restrict__ Ug,  \
+        const double* __restrict__ lamg, double* __restrict__ W, const int64_t* __restrict__ wofs, AdjConst C)
 #define ADJ_KERNEL(name)                                                                                   \
     __global__ __launch_bounds__(256) void name(const PatchDev* __restrict__ patches,                      \
                                                 const Tile* __restrict__ tiles, const double* __restrict__ Ug, \
@@ -145,7 +152,8 @@ __device__ __forceinline__ void metric_inverse(const double g[6], double gu[6], 
 }
 
 // ------------------------------------------------------------ kernel K1
-// Forward intermediates (stored).
+// Forward intermediates (stored): inverse metric, Christoffel symbols, Z^i,
+// ln det, d Ghat, D_iD_j alpha.  The Ricci tensor follows in K1b.
 ADJ_KERNEL(ccz4_adj_forward_kernel)
 {
     Pt q;
@@ -180,50 +188,8 @@ ADJ_KERNEL(ccz4_adj_forward_kernel)
         for (int p = 0; p < 6; ++p) s += MU(p) * gu[p] * Gu[i][p];
         Z[i] = 0.5 * chi * (Gh[i] - s);
     }
-    double ddc[6], trc = 0.0, Ghd = 0.0;
-    for (int p = 0; p < 6; ++p) {
-        ddc[p] = q.dd(C, CHI, PI_(p), PJ_(p));
-        trc += MU(p) * gu[p] * (ddc[p] - 1.5 * ic * dchi[PI_(p)] * dchi[PJ_(p)]);
-    }
-    for (int k = 0; k < 3; ++k) Ghd += Gh[k] * dchi[k];
-    // Gamma-Gamma terms through Q_i^{kn} = gt^{mn} Gamma^k_{mi}:
-    // sum_kn Q_i^{kn} (Gamma_jkn + Gamma_knj) + Q_j^{kn} Gamma_ikn
-    double Q[3][3][3];
-    for (int i = 0; i < 3; ++i)
-        for (int k = 0; k < 3; ++k)
-            for (int n = 0; n < 3; ++n)
-                Q[i][k][n] = gu[SI(0, n)] * Gu[k][SI(0, i)] + gu[SI(1, n)] * Gu[k][SI(1, i)] + gu[SI(2, n)] * Gu[k][SI(2, i)];
-    double dGh[3][3];  // [j][k] = d_j Ghat^k
     for (int j = 0; j < 3; ++j)
-        for (int k = 0; k < 3; ++k) {
-            dGh[j][k] = q.d1(C, GH + k, j);
-            q.Wq(F_DGH + 3 * j + k) = dGh[j][k];
-        }
-    // Ricci tensor, one packed component at a time
-    for (int p = 0; p < 6; ++p) {
-        const int i = PI_(p), j = PJ_(p);
-        double gd = 0.0, zs = 0.0;
-        for (int k = 0; k < 3; ++k) {
-            gd += Gu[k][p] * dchi[k];
-            zs += Z[k] * 0.5 * (g[SI(k, i)] * dchi[j] + g[SI(k, j)] * dchi[i]);
-        }
-        double lap = 0.0;
-        for (int m = 0; m < 6; ++m) {
-            const double v = q.dd(C, GT + p, PI_(m), PJ_(m));
-            q.Wq(F_DDG + 6 * p + m) = v;
-            lap += MU(m) * gu[m] * v;
-        }
-        double r = 0.5 * ic * ddc[p] - 0.5 * ic * gd - 0.25 * ic * ic * dchi[i] * dchi[j] + 2.0 * ic * ic * zs +
-                   0.5 * ic * g[p] * (trc - Ghd) - 0.5 * lap;
-        for (int k = 0; k < 3; ++k) {
-            r += 0.5 * (g[SI(k, i)] * dGh[j][k] + g[SI(k, j)] * dGh[i][k]);
-            r += Gh[k] * 0.5 * (Gl[i][SI(j, k)] + Gl[j][SI(i, k)]);
-        }
-        for (int k = 0; k < 3; ++k)
-            for (int n = 0; n < 3; ++n)
-                r += Q[i][k][n] * (Gl[j][SI(k, n)] + Gl[k][SI(n, j)]) + Q[j][k][n] * Gl[i][SI(k, n)];
-        q.Wq(F_RIC + p) = r;
-    }
+        for (int k = 0; k < 3; ++k) q.Wq(F_DGH + 3 * j + k) = q.d1(C, GH + k, j);
     // D_i D_j alpha
     {
         double cr = 0.0;
@@ -245,6 +211,82 @@ ADJ_KERNEL(ccz4_adj_forward_kernel)
         }
     for (int i = 0; i < 3; ++i) q.Wq(F_Z + i) = Z[i];
     q.Wq(F_LNDET) = lndet;
+}
+
+// ------------------------------------------------------------ kernel K1b
+// Forward intermediates (stored): the Ricci tensor R_ij = Rt_ij + R^chi_ij
+// and the second derivatives of gt_ij, from the stored gt^{ij}, Gamma_ijk,
+// Gamma^i_jk, Z^i and d Ghat (split from K1 so that each half holds two
+// waves per SIMD).
+ADJ_KERNEL(ccz4_adj_ricci_fwd_kernel)
+{
+    Pt q;
+    if (!pt_init(q, patches, tiles, Ug, lamg, W, wofs)) return;
+    double g[6], gu[6];
+    for (int p = 0; p < 6; ++p) {
+        g[p] = q.U(GT + p);
+        gu[p] = q.Wq(F_GU + p);
+    }
+    const double chi = q.U(CHI), ic = 1.0 / chi;
+    double Gh[3], dchi[3], Z[3];
+    for (int i = 0; i < 3; ++i) {
+        Gh[i] = q.U(GH + i);
+        dchi[i] = q.d1(C, CHI, i);
+        Z[i] = q.Wq(F_Z + i);
+    }
+    double Gl[3][6];
+    for (int i = 0; i < 3; ++i)
+        for (int p = 0; p < 6; ++p) Gl[i][p] = q.Wq(F_GL + 6 * i + p);
+    double ddc[6], trc = 0.0, Ghd = 0.0;
+    for (int p = 0; p < 6; ++p) {
+        ddc[p] = q.dd(C, CHI, PI_(p), PJ_(p));
+        trc += MU(p) * gu[p] * (ddc[p] - 1.5 * ic * dchi[PI_(p)] * dchi[PJ_(p)]);
+    }
+    for (int k = 0; k < 3; ++k) Ghd += Gh[k] * dchi[k];
+    // Gamma-Gamma terms through Q_i^{kn} = gt^{mn} Gamma^k_{mi}:
+    // sum_kn Q_i^{kn} (Gamma_jkn + Gamma_knj) + Q_j^{kn} Gamma_ikn; and
+    // gd_ij = Gamma^k_ij d_k chi.  Gamma^i_jk is needed for these only.
+    double Q[3][3][3], gdv[6];
+    {
+        double Gu[3][6];
+        for (int i = 0; i < 3; ++i)
+            for (int p = 0; p < 6; ++p) Gu[i][p] = q.Wq(F_GUU + 6 * i + p);
+        for (int i = 0; i < 3; ++i)
+            for (int k = 0; k < 3; ++k)
+                for (int n = 0; n < 3; ++n)
+                    Q[i][k][n] = gu[SI(0, n)] * Gu[k][SI(0, i)] + gu[SI(1, n)] * Gu[k][SI(1, i)] + gu[SI(2, n)] * Gu[k][SI(2, i)];
+        for (int p = 0; p < 6; ++p) {
+            double gd = 0.0;
+            for (int k = 0; k < 3; ++k) gd += Gu[k][p] * dchi[k];
+            gdv[p] = gd;
+        }
+    }
+    double dGh[3][3];  // [j][k] = d_j Ghat^k
+    for (int j = 0; j < 3; ++j)
+        for (int k = 0; k < 3; ++k) dGh[j][k] = q.Wq(F_DGH + 3 * j + k);
+    // Ricci tensor, one packed component at a time
+    for (int p = 0; p < 6; ++p) {
+        const int i = PI_(p), j = PJ_(p);
+        const double gd = gdv[p];
+        double zs = 0.0;
+        for (int k = 0; k < 3; ++k) zs += Z[k] * 0.5 * (g[SI(k, i)] * dchi[j] + g[SI(k, j)] * dchi[i]);
+        double lap = 0.0;
+        for (int m = 0; m < 6; ++m) {
+            const double v = q.dd(C, GT + p, PI_(m), PJ_(m));
+            q.Wq(F_DDG + 6 * p + m) = v;
+            lap += MU(m) * gu[m] * v;
+        }
+        double r = 0.5 * ic * ddc[p] - 0.5 * ic * gd - 0.25 * ic * ic * dchi[i] * dchi[j] + 2.0 * ic * ic * zs +
+                   0.5 * ic * g[p] * (trc - Ghd) - 0.5 * lap;
+        for (int k = 0; k < 3; ++k) {
+            r += 0.5 * (g[SI(k, i)] * dGh[j][k] + g[SI(k, j)] * dGh[i][k]);
+            r += Gh[k] * 0.5 * (Gl[i][SI(j, k)] + Gl[j][SI(i, k)]);
+        }
+        for (int k = 0; k < 3; ++k)
+            for (int n = 0; n < 3; ++n)
+                r += Q[i][k][n] * (Gl[j][SI(k, n)] + Gl[k][SI(n, j)]) + Q[j][k][n] * Gl[i][SI(k, n)];
+        q.Wq(F_RIC + p) = r;
+    }
 }
 
 // ------------------------------------------------------------ kernel K0
@@ -353,7 +395,7 @@ ADJ_KERNEL(ccz4_adj_metric_kernel)
 
 // ------------------------------------------------------------ kernel K3
 // Reverse of the chi, Khat, Theta, Ghat^i, B^i, beta^i and alpha equations.
-ADJ_KERNEL(ccz4_adj_gauge_kernel)
+ADJ_KERNEL2(ccz4_adj_gauge_kernel, MOL_ADJ_GAUGE_WAVES)
 {
     Pt q;
     if (!pt_init(q, patches, tiles, Ug, lamg, W, wofs)) return;
@@ -932,6 +974,7 @@ hipError_t launch_ccz4_adjoint(const SysParams& sp, const PatchDev* patches, con
         const dim3 b(td[0], td[1], td[2]);
         ccz4_adj_advection_kernel<<<ntiles, b, 0, s>>>(patches, tiles, U, lam, W, wofs, C);
         ccz4_adj_forward_kernel<<<ntiles, b, 0, s>>>(patches, tiles, U, lam, W, wofs, C);
+        ccz4_adj_ricci_fwd_kernel<<<ntiles, b, 0, s>>>(patches, tiles, U, lam, W, wofs, C);
         ccz4_adj_metric_kernel<<<ntiles, b, 0, s>>>(patches, tiles, U, lam, W, wofs, C);
         ccz4_adj_gauge_kernel<<<ntiles, b, 0, s>>>(patches, tiles, U, lam, W, wofs, C);
         ccz4_adj_shift_kernel<<<ntiles, b, 0, s>>>(patches, tiles, U, lam, W, wofs, C);
