@@ -152,10 +152,13 @@ __device__ __forceinline__ double fko(const double* __restrict__ u, int s)
 // i-1..i+3, b < 0 reads i-3..i+1)
 __device__ __forceinline__ double fadv(const double* __restrict__ u, int s, double b)
 {
+    // the b < 0 stencil is the b >= 0 one mirrored and negated: the lanes of
+    // a wave read mirrored addresses instead of taking different branches
+    // (negation is exact, so the value is the same bit for bit)
+    const int m = b >= 0.0 ? s : -s;
     const double c = u[0];
-    if (b >= 0.0)
-        return (u[3 * s] - c) - 6.0 * (u[2 * s] - c) + 18.0 * (u[s] - c) - 3.0 * (u[-s] - c);
-    return -(u[-3 * s] - c) + 6.0 * (u[-2 * s] - c) - 18.0 * (u[-s] - c) + 3.0 * (u[s] - c);
+    const double r = (u[3 * m] - c) - 6.0 * (u[2 * m] - c) + 18.0 * (u[m] - c) - 3.0 * (u[-m] - c);
+    return b >= 0.0 ? r : -r;
 }
 // (12 h)^2 * D_b(D_a U)
 __device__ __forceinline__ double fmix(const double* __restrict__ u, int sa, int sb)
