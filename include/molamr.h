@@ -258,7 +258,9 @@ int mol_restrict(mol_patchset* ps, int fine_level, const double* U_f, double* U_
 int mol_rhs_adjoint(mol_patchset* ps, int level, const double* U, const double* lam,
                     double* lamU, double* work, void* stream);
 /* Doubles of workspace mol_rhs_adjoint needs on `level` (0 for the wave;
- * CCZ4: 139 per point of the padded ghosted boxes); negative on error. */
+ * CCZ4: 299 per point of the padded ghosted boxes: 139 stencil-input
+ * adjoints, 103 stored forward values, 57 adjoints handed between its
+ * kernels); negative on error. */
 int64_t mol_adjoint_workspace(const mol_patchset* ps, int level);
 /* Transpose of mol_fill_ghosts: every source point adds the ghost entries
  * that copy it, then those ghost entries are zeroed (owner gather, no atomics). */
