@@ -894,7 +894,8 @@ void time_weights(int mode, int R, int r, int s, double w[4])
 hipStream_t S(void* s) { return (hipStream_t)s; }
 
 int stage_impl(mol_patchset* ps, int level, int mode, int stage, double dt, const double* Un,
-               const double* Us, double* acc, double* out, double* kst, hipStream_t st, int plain)
+               const double* Us, double* acc, double* out, double* kst, hipStream_t st, int plain,
+               bool wrap = false)
 {
     Level& lev = ps->L[level];
     SysParams sp = level_params(ps, level);
@@ -909,6 +910,7 @@ int stage_impl(mol_patchset* ps, int level, int mode, int stage, double dt, cons
     a.out = out;
     a.kst = kst;
     a.stream = lev.nelems * (int64_t)sizeof(double) >= (int64_t(128) << 20);
+    a.wrap = wrap ? 1 : 0;
     if (!plain) {
         a.tiles = lev.tiles.dev.p;
         a.ntiles = (int)lev.tiles.dev.n;
@@ -1004,17 +1006,27 @@ int advance_level(mol_patchset* ps, const mol_level_state* st, int l, int r, dou
     double* const stage_out[4] = {X.S0, X.S1, ssp ? (kids ? X.S0 : X.U) : X.S0, kids ? X.S1 : X.U};
     double* const next = ssp ? X.S0 : X.S1;
     const int nst = ssp ? 3 : 4;
+    // a wave level that is one periodic patch (the whole domain, no finer
+    // level, at least 4 points per axis) stepped with the point-wise stage
+    // kernel reads its neighbours at the periodic images: no ghost fill
+    // before its stages (small levels, where each launch costs more than its
+    // work)
+    const Level& lev = ps->L[l];
+    const int* td = lev.tiles.tdim;
+    const bool wrap = ps->sp.system == MOL_WAVE && l == 0 && ps->nlev == 1 && !ps->open && lev.pd.size() == 1 &&
+                      lev.pd[0].n[0] >= 4 && lev.pd[0].n[1] >= 4 && lev.pd[0].n[2] >= 4 &&
+                      !(td[0] == MOL_WAVE_WX && td[1] == MOL_WAVE_WY && td[2] > 1);
     int rc;
     for (int sidx = 0; sidx < nst; ++sidx) {
         double* Us = stage_in[sidx];
-        if ((rc = fill_impl(ps, l, Us, nf, s, plain))) return rc;
+        if (!wrap && (rc = fill_impl(ps, l, Us, nf, s, plain))) return rc;
         if (l > 0) {
             const mol_level_state& P = st[l - 1];
             const double* kc[4] = {P.k[0], P.k[1], P.k[2], P.k[3]};
             if ((rc = prolong_impl(ps, l, r, sidx + 1, P.U, kc, Us, s, plain, tmode))) return rc;
         }
         if ((rc = stage_impl(ps, l, ssp ? ST_SSP3 : ST_RK4, sidx + 1, dt, X.U, Us, X.acc, stage_out[sidx],
-                             kids ? X.k[sidx] : nullptr, s, plain)))
+                             kids ? X.k[sidx] : nullptr, s, plain, wrap)))
             return rc;
     }
     if (kids) {

@@ -9,6 +9,10 @@ namespace mol {
 
 namespace {
 
+// WRAP: the patch is the whole periodic domain (at least 4 points per axis)
+// and the neighbours are read at the periodic images of interior points, so
+// that the stage needs no ghost fill; the stencils see the same values.
+template <bool WRAP>
 __global__ __launch_bounds__(256) void wave_stage_kernel(StageArgs a, double ih2, double ko)
 {
     PointRef pr;
@@ -18,11 +22,31 @@ __global__ __launch_bounds__(256) void wave_stage_kernel(StageArgs a, double ih2
     const double* pi = phi + pr.fs;
     const int s[3] = {1, pr.sy, pr.sz};
     double lap = 0.0, qphi = 0.0, qpi = 0.0;
+    if constexpr (WRAP) {
+        const int q[3] = {i, j, k};
+        const int* n = a.patches[p].n;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        lap += fd2(phi, s[d]);
-        qphi += fko(phi, s[d]);
-        qpi += fko(pi, s[d]);
+        for (int d = 0; d < 3; ++d) {
+            double vp[7], vq[7];
+#pragma unroll
+            for (int o = -3; o <= 3; ++o) {
+                int c = q[d] + o;
+                c = c < 0 ? c + n[d] : (c >= n[d] ? c - n[d] : c);
+                const int64_t off = (int64_t)(c - q[d]) * s[d];
+                vp[o + 3] = phi[off];
+                vq[o + 3] = pi[off];
+            }
+            lap += fd2(vp + 3, 1);
+            qphi += fko(vp + 3, 1);
+            qpi += fko(vq + 3, 1);
+        }
+    } else {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            lap += fd2(phi, s[d]);
+            qphi += fko(phi, s[d]);
+            qpi += fko(pi, s[d]);
+        }
     }
     stage_store(a, pr.c, -pi[0] + ko * qphi);
     stage_store(a, pr.c + pr.fs, -ih2 * lap + ko * qpi);
@@ -201,6 +225,7 @@ hipError_t launch_stage_wave(const SysParams& sp, const StageArgs& a, const int 
     const double ih2 = 1.0 / (12.0 * sp.h * sp.h);
     const double ko = sp.sigma / (64.0 * sp.h);
     if (td[0] == WX && td[1] == WY && td[2] > 1) {
+        if (a.wrap) return hipErrorInvalidValue;  // the z-marching kernel reads ghost cells
         // levels larger than the caches: the point loads and stores of the
         // stage update are non-temporal (6-7% faster at 256^3 and 512^3,
         // 18% slower at 128^3, where the arrays stay in the caches)
@@ -208,8 +233,10 @@ hipError_t launch_stage_wave(const SysParams& sp, const StageArgs& a, const int 
             wave_zmarch_kernel<true><<<a.ntiles, dim3(WX, WY, 1), 0, s>>>(a, ih2, ko, td[2]);
         else
             wave_zmarch_kernel<false><<<a.ntiles, dim3(WX, WY, 1), 0, s>>>(a, ih2, ko, td[2]);
+    } else if (a.wrap) {
+        wave_stage_kernel<true><<<a.ntiles, dim3(td[0], td[1], td[2]), 0, s>>>(a, ih2, ko);
     } else {
-        wave_stage_kernel<<<a.ntiles, dim3(td[0], td[1], td[2]), 0, s>>>(a, ih2, ko);
+        wave_stage_kernel<false><<<a.ntiles, dim3(td[0], td[1], td[2]), 0, s>>>(a, ih2, ko);
     }
     return hipGetLastError();
 }
