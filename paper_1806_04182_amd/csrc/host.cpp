@@ -1007,15 +1007,11 @@ int advance_level(mol_patchset* ps, const mol_level_state* st, int l, int r, dou
     double* const next = ssp ? X.S0 : X.S1;
     const int nst = ssp ? 3 : 4;
     // a wave level that is one periodic patch (the whole domain, no finer
-    // level, at least 4 points per axis) stepped with the point-wise stage
-    // kernel reads its neighbours at the periodic images: no ghost fill
-    // before its stages (small levels, where each launch costs more than its
-    // work)
+    // level, at least 4 points per axis) reads its stencil neighbours at the
+    // periodic images: no ghost fill before its stages
     const Level& lev = ps->L[l];
-    const int* td = lev.tiles.tdim;
     const bool wrap = ps->sp.system == MOL_WAVE && l == 0 && ps->nlev == 1 && !ps->open && lev.pd.size() == 1 &&
-                      lev.pd[0].n[0] >= 4 && lev.pd[0].n[1] >= 4 && lev.pd[0].n[2] >= 4 &&
-                      !(td[0] == MOL_WAVE_WX && td[1] == MOL_WAVE_WY && td[2] > 1);
+                      lev.pd[0].n[0] >= 4 && lev.pd[0].n[1] >= 4 && lev.pd[0].n[2] >= 4;
     int rc;
     for (int sidx = 0; sidx < nst; ++sidx) {
         double* Us = stage_in[sidx];

@@ -64,7 +64,10 @@ constexpr int WX = MOL_WAVE_WX, WY = MOL_WAVE_WY, WHX = WX + 6, WHY = WY + 6, WP
 constexpr int WNH = 6 * WHX + 6 * WY;                   // halo cells per plane
 constexpr int WT = WX * WY, NH = (WNH + WT - 1) / WT;  // halo cells per thread
 
-template <bool NT>
+// WRAP: the patch is the whole periodic domain; every cell outside the
+// interior (halo cells, the column queue's planes, ragged-tail cells) is read
+// at its periodic image, so the stage needs no ghost fill.
+template <bool NT, bool WRAP>
 __global__ __launch_bounds__(WT) void wave_zmarch_kernel(StageArgs a, double ih2, double ko, int zc)
 {
     __shared__ double pl[2][WHY][WPX];
@@ -79,6 +82,15 @@ __global__ __launch_bounds__(WT) void wave_zmarch_kernel(StageArgs a, double ih2
     const bool cin = x0 + tx < P.n[0] + G && y0 + ty < P.n[1] + G;
     const int64_t cb = P.off + (int64_t)(y0 + ty + G) * P.pitch_y + (x0 + tx + G);
     const double* __restrict__ U = a.Us;
+    // periodic image of interior coordinate v in [-3, n + 3)
+    auto wrapc = [](int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); };
+    // plane offset of interior plane z (its image when WRAP)
+    auto plane = [&](int z) -> int64_t { return (int64_t)((WRAP ? wrapc(z, P.n[2]) : z) + G) * sz; };
+    // in-plane offset (from the patch start) of a ragged-tail column's own
+    // cell: its image when WRAP (-1: beyond the reach of the stencils)
+    const int64_t cwo = !WRAP ? cb - P.off
+                        : cin ? (int64_t)(wrapc(y0 + ty, P.n[1]) + G) * P.pitch_y + wrapc(x0 + tx, P.n[0]) + G
+                              : -1;
     // this thread's halo cells: LDS slot (-1: none) and offset in the plane
     // (-1: outside the ghosted box)
     int hl[NH], hg[NH];
@@ -97,20 +109,23 @@ __global__ __launch_bounds__(WT) void wave_zmarch_kernel(StageArgs a, double ih2
         }
         const bool ok = e < WNH && x0 + hx < P.n[0] + 2 * G && y0 + hy < P.n[1] + 2 * G;
         hl[r] = e < WNH ? hy * WPX + hx : -1;
-        hg[r] = ok ? hy * P.pitch_y + hx : -1;
+        if constexpr (WRAP)  // offset from the patch start, at the image
+            hg[r] = ok ? (wrapc(y0 + hy - G, P.n[1]) + G) * P.pitch_y + wrapc(x0 + hx - G, P.n[0]) + G : -1;
+        else                 // offset from the tile's ghosted-box corner
+            hg[r] = ok ? hy * P.pitch_y + hx : -1;
     }
     double qp[7], qq[7];  // phi and Pi at z = k-3 .. k+3
     if (col)
 #pragma unroll
         for (int m = 0; m < 6; ++m) {
-            qp[m] = U[cb + (int64_t)(z0 - 3 + m + G) * sz];
-            qq[m] = U[cb + P.fs + (int64_t)(z0 - 3 + m + G) * sz];
+            qp[m] = U[cb + plane(z0 - 3 + m)];
+            qq[m] = U[cb + P.fs + plane(z0 - 3 + m)];
         }
     // halo cells and stage-update inputs are fetched one plane ahead
     double hp[NH], hq[NH];
     StageIn sp, sq;
     auto fetch = [&](int k, double* np, double* nq, StageIn& s0, StageIn& s1) __attribute__((always_inline)) {
-        const int64_t hb = P.off + (int64_t)(k + G) * sz + (int64_t)y0 * P.pitch_y + x0;
+        const int64_t hb = P.off + (int64_t)(k + G) * sz + (WRAP ? 0 : (int64_t)y0 * P.pitch_y + x0);
 #pragma unroll
         for (int r = 0; r < NH; ++r) {
             const bool ok = hg[r] >= 0;
@@ -127,13 +142,13 @@ __global__ __launch_bounds__(WT) void wave_zmarch_kernel(StageArgs a, double ih2
     for (int k = z0; k < z1; ++k) {
         const int64_t pc = (int64_t)(k + G) * sz;
         if (col) {
-            qp[6] = U[cb + pc + 3 * (int64_t)sz];
-            qq[6] = U[cb + P.fs + pc + 3 * (int64_t)sz];
+            qp[6] = U[cb + plane(k + 3)];
+            qq[6] = U[cb + P.fs + plane(k + 3)];
             pl[0][ty + G][tx + G] = qp[3];
             pl[1][ty + G][tx + G] = qq[3];
         } else {
-            pl[0][ty + G][tx + G] = cin ? U[cb + pc] : 0.0;
-            pl[1][ty + G][tx + G] = cin ? U[cb + P.fs + pc] : 0.0;
+            pl[0][ty + G][tx + G] = cwo >= 0 && cin ? U[P.off + pc + cwo] : 0.0;
+            pl[1][ty + G][tx + G] = cwo >= 0 && cin ? U[P.off + P.fs + pc + cwo] : 0.0;
         }
 #pragma unroll
         for (int r = 0; r < NH; ++r)
@@ -225,14 +240,16 @@ hipError_t launch_stage_wave(const SysParams& sp, const StageArgs& a, const int 
     const double ih2 = 1.0 / (12.0 * sp.h * sp.h);
     const double ko = sp.sigma / (64.0 * sp.h);
     if (td[0] == WX && td[1] == WY && td[2] > 1) {
-        if (a.wrap) return hipErrorInvalidValue;  // the z-marching kernel reads ghost cells
         // levels larger than the caches: the point loads and stores of the
         // stage update are non-temporal (6-7% faster at 256^3 and 512^3,
         // 18% slower at 128^3, where the arrays stay in the caches)
+        const dim3 g(a.ntiles), b(WX, WY, 1);
         if (a.stream)
-            wave_zmarch_kernel<true><<<a.ntiles, dim3(WX, WY, 1), 0, s>>>(a, ih2, ko, td[2]);
+            a.wrap ? wave_zmarch_kernel<true, true><<<g, b, 0, s>>>(a, ih2, ko, td[2])
+                   : wave_zmarch_kernel<true, false><<<g, b, 0, s>>>(a, ih2, ko, td[2]);
         else
-            wave_zmarch_kernel<false><<<a.ntiles, dim3(WX, WY, 1), 0, s>>>(a, ih2, ko, td[2]);
+            a.wrap ? wave_zmarch_kernel<false, true><<<g, b, 0, s>>>(a, ih2, ko, td[2])
+                   : wave_zmarch_kernel<false, false><<<g, b, 0, s>>>(a, ih2, ko, td[2]);
     } else if (a.wrap) {
         wave_stage_kernel<true><<<a.ntiles, dim3(td[0], td[1], td[2]), 0, s>>>(a, ih2, ko);
     } else {

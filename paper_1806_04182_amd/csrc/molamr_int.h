@@ -129,10 +129,9 @@ struct StageArgs {
     // kernel then streams its point loads and stores past the caches (the
     // other stage kernels measured slower with that and ignore it)
     int stream;
-    // 1 when the driver steps a wave level that is one periodic patch with
-    // the point-wise stage kernel: that kernel then reads its neighbours at
-    // the periodic images of interior points and the ghost fill before the
-    // stage is skipped
+    // 1 when the driver steps a wave level that is one periodic patch: the
+    // wave stage kernels then read stencil neighbours at the periodic images
+    // of interior points and the ghost fill before the stage is skipped
     int wrap;
 };
 
