@@ -235,6 +235,8 @@ typedef struct {
     double** k[4];  /* stage increments of the level's current step */
     double** R;     /* rhs scratch */
     int step_r;     /* index of the level's step inside its parent's step */
+    int hint;       /* patch that answered the last owner query (search starts there) */
+    int per[3];     /* period in level index space: N0 * R_1 * .. * R_l per axis */
 } olevel;
 
 struct orc_hier {
@@ -284,6 +286,7 @@ orc_hier* orc_hier_create(int system, int nlev, const int* ratio, const int N0[3
         olevel* L = &H->L[l];
         L->ratio = l == 0 ? 1 : ratio[l];
         L->np = npatch[l];
+        for (int d = 0; d < 3; ++d) L->per[d] = (l == 0 ? N0[d] : H->L[l - 1].per[d] * L->ratio);
         L->box = (int*)malloc(sizeof(int) * 6 * L->np);
         memcpy(L->box, b, sizeof(int) * 6 * L->np);
         b += 6 * L->np;
@@ -348,17 +351,21 @@ static int owner(const orc_hier* H, int l, const int g0[3], long* loc)
 {
     const olevel* L = &H->L[l];
     int g[3] = {g0[0], g0[1], g0[2]};
-    for (int d = 0; d < 3; ++d) {
-        int per = H->N0[d];
-        for (int m = 1; m <= l; ++m) per *= H->L[m].ratio;
-        if (!H->open) g[d] = wrapi(g[d], per);
-    }
-    for (int p = 0; p < L->np; ++p) {
+    if (!H->open)
+        for (int d = 0; d < 3; ++d)
+            if (g[d] < 0 || g[d] >= L->per[d]) g[d] = wrapi(g[d], L->per[d]);
+    /* patches are disjoint, so at most one holds g: start the search at the
+     * patch that answered the previous query (consecutive queries are
+     * usually neighbours) and go round the list once */
+    int* hint = (int*)&L->hint;
+    for (int t = 0; t < L->np; ++t) {
+        int p = (*hint + t) % L->np;
         const int* b = L->box + 6 * p;
         if (g[0] < b[0] || g[0] > b[3] || g[1] < b[1] || g[1] > b[4] || g[2] < b[2] || g[2] > b[5])
             continue;
         long NX = b[3] - b[0] + 1 + 2 * ORC_G, NY = b[4] - b[1] + 1 + 2 * ORC_G;
         *loc = ((long)(g[2] - b[2] + ORC_G) * NY + (g[1] - b[1] + ORC_G)) * NX + (g[0] - b[0] + ORC_G);
+        *hint = p;
         return p;
     }
     return -1;
@@ -419,18 +426,11 @@ typedef struct {
     double dtp;
 } pro_ctx;
 
-/* value of the parent's BOR stage state at coarse global index gc, field f
+/* value of the parent's BOR stage state at entry `off` of parent patch q
  * (App. D applied at that coarse point, computed once per call) */
-static double parent_state(orc_hier* H, int lp, pro_ctx* c, const int gc[3], int f)
+static double parent_state(orc_hier* H, int lp, pro_ctx* c, int q, long off)
 {
-    long loc;
-    int q = owner(H, lp, gc, &loc);
-    if (q < 0) {
-        fprintf(stderr, "oracle: prolongation stencil leaves the parent level\n");
-        abort();
-    }
     const olevel* P = &H->L[lp];
-    long off = f * pvol(P->box + 6 * q) + loc;
     if (!c->D[q][off]) {
         const double* kk[4] = {P->k[0][q] + off, P->k[1][q] + off, P->k[2][q] + off,
                                P->k[3][q] + off};
@@ -463,18 +463,27 @@ static void prolong_one(orc_hier* H, int l, int p, long loc, const int g[3], voi
         }
     }
     long vd = pvol(H->L[l].box + 6 * p);
-    for (int f = 0; f < H->nf; ++f) {
-        double v = 0.0;
-        for (int a = 0; a < cnt[2]; ++a)
-            for (int b2 = 0; b2 < cnt[1]; ++b2)
-                for (int e = 0; e < cnt[0]; ++e) {
-                    int gc[3] = {i0[0] + (cnt[0] == 1 ? 0 : e - 2),
-                                 i0[1] + (cnt[1] == 1 ? 0 : b2 - 2),
-                                 i0[2] + (cnt[2] == 1 ? 0 : a - 2)};
-                    v += w[0][e] * w[1][b2] * w[2][a] * parent_state(H, l - 1, c, gc, f);
+    double v[64];
+    for (int f = 0; f < H->nf; ++f) v[f] = 0.0;
+    /* every field sums the same stencil in the same (z, y, x) order */
+    for (int a = 0; a < cnt[2]; ++a)
+        for (int b2 = 0; b2 < cnt[1]; ++b2)
+            for (int e = 0; e < cnt[0]; ++e) {
+                int gc[3] = {i0[0] + (cnt[0] == 1 ? 0 : e - 2),
+                             i0[1] + (cnt[1] == 1 ? 0 : b2 - 2),
+                             i0[2] + (cnt[2] == 1 ? 0 : a - 2)};
+                long ploc;
+                int q = owner(H, l - 1, gc, &ploc);
+                if (q < 0) {
+                    fprintf(stderr, "oracle: prolongation stencil leaves the parent level\n");
+                    abort();
                 }
-        c->A[p][f * vd + loc] = v;
-    }
+                long pv = pvol(H->L[l - 1].box + 6 * q);
+                double wt = w[0][e] * w[1][b2] * w[2][a];
+                for (int f = 0; f < H->nf; ++f)
+                    v[f] += wt * parent_state(H, l - 1, c, q, f * pv + ploc);
+            }
+    for (int f = 0; f < H->nf; ++f) c->A[p][f * vd + loc] = v[f];
 }
 
 static void prolong_set(orc_hier* H, int l, double** A, int r, int s, double dtp)
