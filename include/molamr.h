@@ -262,6 +262,23 @@ int mol_rhs_adjoint(mol_patchset* ps, int level, const double* U, const double* 
  * adjoints, 103 stored forward values, 57 adjoints handed between its
  * kernels); negative on error. */
 int64_t mol_adjoint_workspace(const mol_patchset* ps, int level);
+/* mol_rhs_adjoint without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The CCZ4 workspace lives in a static
+ * device array of MOL_ADJOINT_SCRATCH_BYTES that each GPU the library runs
+ * on holds until the process ends; the wave needs none.  The call allocates
+ * nothing (no hipMalloc, hipFree or allocating library routine); its device
+ * address is looked up once per device on the first call made with that
+ * device current.  Levels whose workspace (mol_adjoint_workspace) exceeds
+ * the array are rejected with MOL_EINVAL (use mol_rhs_adjoint there): a CCZ4
+ * patch of up to about 24^3 interior points fits.  Every call on one GPU
+ * shares that GPU's array: calls that overlap in time on one GPU (other
+ * streams, other threads) race; calls ordered on one stream do not.  No
+ * slot has to start at zero: every slot a call reads was written by that
+ * call.  Same arguments, results and errors as mol_rhs_adjoint otherwise. */
+#define MOL_ADJOINT_SCRATCH_BYTES (64ll << 20)
+int mol_rhs_adjoint_noalloc(mol_patchset* ps, int level, const double* U, const double* lam,
+                            double* lamU, void* stream);
 /* Transpose of mol_fill_ghosts: every source point adds the ghost entries
  * that copy it, then those ghost entries are zeroed (owner gather, no atomics). */
 int mol_fill_ghosts_adjoint(mol_patchset* ps, int level, double* lamU, void* stream);

@@ -11,6 +11,7 @@
 #include <array>
 #include <limits>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <cmath>
 #include <cstdarg>
@@ -1297,6 +1298,54 @@ int mol_rhs_adjoint(mol_patchset* ps, int level, const double* U, const double* 
                                 lamU, S(stream));
     }
     return e == hipSuccess ? MOL_OK : hip_fail(e, "adjoint launch");
+}
+
+// Workspace of mol_rhs_adjoint_noalloc: one file-scope device array per GPU.
+// In host code `scratch` is a host-side stand-in, not a device address; the
+// device address of the current device's copy comes from
+// hipGetSymbolAddress, taken once per device and kept in g_scratch_dev.
+static __device__ __align__(256) double scratch[MOL_ADJOINT_SCRATCH_BYTES / sizeof(double)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+std::array<double*, kMaxDevices> g_scratch_dev{};
+
+int scratch_address(double** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(MOL_EUNSUPPORTED, "device %d beyond the %d supported", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(MOL_EHIP, "hipGetSymbolAddress(scratch) returned no address");
+        g_scratch_dev[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return MOL_OK;
+}
+}  // namespace
+
+int mol_rhs_adjoint_noalloc(mol_patchset* ps, int level, const double* U, const double* lam, double* lamU,
+                            void* stream)
+{
+    int rc = check_level(ps, level);
+    if (rc) return rc;
+    const int64_t need = ps->L[level].wsize;
+    const int64_t have = MOL_ADJOINT_SCRATCH_BYTES / (int64_t)sizeof(double);
+    if (need > have)
+        return fail(MOL_EINVAL,
+                    "level %d needs %lld doubles of adjoint workspace (%.1f MiB); the static scratch holds %lld "
+                    "(%lld MiB): use mol_rhs_adjoint with a workspace",
+                    level, (long long)need, need * 8.0 / (1 << 20), (long long)have,
+                    (long long)(MOL_ADJOINT_SCRATCH_BYTES >> 20));
+    double* w = nullptr;
+    if (need > 0 && (rc = scratch_address(&w))) return rc;
+    return mol_rhs_adjoint(ps, level, U, lam, lamU, w, stream);
 }
 
 int64_t mol_adjoint_workspace(const mol_patchset* ps, int level)

@@ -25,6 +25,7 @@ MOL_FLUX_LLF, MOL_FLUX_HLL, MOL_FLUX_SPLIT = 0, 1, 2
 # time-refinement strategies (Sec. III.B), or-ed into the mode of advance()
 MOL_TIME_BOR, MOL_TIME_BO, MOL_TIME_BO1, MOL_TIME_NOSUB = 0, 16, 32, 48
 MOL_ADV_SSPRK3 = 64  # SSP-RK3 steps in advance() (or-ed into the mode)
+MOL_ADJOINT_SCRATCH_BYTES = 64 << 20  # static workspace of mol_rhs_adjoint_noalloc
 GHOST = 3
 NFIELDS = {MOL_WAVE: 2, MOL_MHD: 8, MOL_CCZ4: 25, MOL_MHD_GLM: 9}
 
@@ -94,6 +95,7 @@ def lib():
             "mol_set_radiative": ([vp, dp, dp], i),
             "mol_restrict": ([vp, i, vp, vp, vp], i),
             "mol_rhs_adjoint": ([vp, i, vp, vp, vp, vp, vp], i),
+            "mol_rhs_adjoint_noalloc": ([vp, i, vp, vp, vp, vp], i),
             "mol_adjoint_workspace": ([vp, i], ctypes.c_int64),
             "mol_fill_ghosts_adjoint": ([vp, i, vp, vp], i),
             "mol_rk4_adjoint_step": ([vp, i, d, vp, vp, ctypes.POINTER(vp), vp, vp], i),
@@ -277,6 +279,10 @@ class Patchset:
 
     def rhs_adjoint(self, level, U, lam, lamU, work=None, stream=None):
         _check(lib().mol_rhs_adjoint(self._h, level, _ptr(U), _ptr(lam), _ptr(lamU), _ptr(work), _stream(stream)))
+
+    def rhs_adjoint_noalloc(self, level, U, lam, lamU, stream=None):
+        """rhs_adjoint with the library's static workspace (allocates nothing)."""
+        _check(lib().mol_rhs_adjoint_noalloc(self._h, level, _ptr(U), _ptr(lam), _ptr(lamU), _stream(stream)))
 
     def adjoint_workspace(self, level) -> int:
         n = lib().mol_adjoint_workspace(self._h, level)
