@@ -320,6 +320,42 @@ int mol_norms(mol_patchset* ps, int level, const double* U, int field, double sh
 int mol_box_norms(mol_patchset* ps, int level, const double* U, int field, double shift,
                   const double lo[3], const double hi[3], double* out_dev, void* stream);
 
+/* Constraint and dissipation monitors (Sec. V, Sec. II.B.1) over the
+ * interior of every patch of the level; U needs filled ghosts.  Bits of
+ * `which`, and the quantity v evaluated at each interior point:
+ *   MOL_MON_THETA  Theta (CCZ4)
+ *   MOL_MON_Z      |Z| = sqrt(gamma_ij Z^i Z^j), Z^i = chi (Ghat^i - Gt^i)/2,
+ *                  gamma_ij = gt_ij / chi (CCZ4)
+ *   MOL_MON_HZ     H_Z = R + 2 nabla_i Z^i + 2/3 trKhat^2
+ *                  + 2/3 Theta (trKhat - 2 Theta) - At_ij At^ij, the bracket
+ *                  of the Theta equation (with Theta = Z = 0 the Hamiltonian
+ *                  constraint); R + 2 nabla_i Z^i is the trace
+ *                  chi gt^ij (Rhat_ij + Rhat^chi_ij) (CCZ4)
+ *   MOL_MON_LNDET  ln det gt, the first conformal constraint (CCZ4)
+ *   MOL_MON_TRA    tr At = gt^ij At_ij, the second (CCZ4)
+ *   MOL_MON_KO     sqrt(sum_f (Q_d U_f)^2), the size of the KO term of the
+ *                  right-hand side over all fields (every system)
+ * out_dev (device memory, MOL_MON_OUT doubles): for monitor q (bit q),
+ * out_dev[3q] = sum |v| dV, [3q+1] = sum v^2 dV, [3q+2] = max |v|, over the
+ * points where v is finite (0 for monitors not requested);
+ * out_dev[3 MOL_MON_COUNT] = number of non-finite values among all fields of
+ * U at interior points.  The summation order is fixed (deterministic).
+ * pointwise (device memory in the level layout, or NULL): the k-th
+ * requested monitor (in bit order) is written to field k at every interior
+ * point.  MOL_EINVAL for an empty or unknown mask, MOL_EUNSUPPORTED for a
+ * CCZ4 monitor on another system. */
+#define MOL_MON_THETA (1u << 0)
+#define MOL_MON_Z (1u << 1)
+#define MOL_MON_HZ (1u << 2)
+#define MOL_MON_LNDET (1u << 3)
+#define MOL_MON_TRA (1u << 4)
+#define MOL_MON_KO (1u << 5)
+#define MOL_MON_COUNT 6
+#define MOL_MON_ALL 0x3fu
+#define MOL_MON_OUT (3 * MOL_MON_COUNT + 1)
+int mol_monitor(mol_patchset* ps, int level, const double* U, uint32_t which, double* pointwise,
+                double* out_dev, void* stream);
+
 /* Transpose of the sphere integral of mol_norms (out_dev[3]): lam[field] =
  * scale * dV at interior points with |x| < radius, 0 at the other interior
  * points; the other fields are set to 0 on interior points; ghost entries

@@ -78,6 +78,17 @@ void orc_ccz4_rhs(const double* U, double* R, int nx, int ny, int nz,
 void orc_rhs(int system, const double* U, double* R, int nx, int ny, int nz,
              const double h[3], const orc_params* p);
 
+/* ---- constraint and dissipation monitors (Sec. V; Sec. II.B.1) ---- */
+/* CCZ4, at every interior point, into five fields of M (patch-array layout):
+ * Theta, gamma_ij Z^i Z^j, H_Z (the bracket of the Theta equation), ln det gt,
+ * tr At, each as the right-hand side evaluates it. */
+void orc_ccz4_monitor(const double* U, double* M, int nx, int ny, int nz,
+                      const double h[3], const orc_params* p);
+/* any system: M[c] = sum_f (sum_d KO_d U_f)^2 at every interior point, the
+ * square of the dissipation term's magnitude over all nf fields */
+void orc_ko_monitor(int system, const double* U, double* M, int nx, int ny, int nz,
+                    const double h[3], const orc_params* p);
+
 /* WENO5-Z reconstruction of the left state at i+1/2 from u[-2..2] and the right
  * state at i-1/2 from u[-2..2] (App. B); exposed for the pins. */
 double orc_weno5z_left(const double* u, double eps, double q);

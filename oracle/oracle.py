@@ -117,6 +117,8 @@ def lib():
         L.orc_sphere_integral.argtypes = [dp, i, i, i, i, dp, dp, d, d]
         L.orc_sphere_integral.restype = d
         L.orc_ccz4_rhs_jvp.argtypes = [dp, dp, dp, dp, i, i, i, dp, P]
+        L.orc_ccz4_monitor.argtypes = [dp, dp, i, i, i, dp, P]
+        L.orc_ko_monitor.argtypes = [i, dp, dp, i, i, i, dp, P]
         _lib = L
     return _lib
 
@@ -148,6 +150,48 @@ def rhs(system: int, U: np.ndarray, h, prm: Params | None = None) -> np.ndarray:
     hh = _h3(h)
     lib().orc_rhs(system, _p(U), _p(R), nx, ny, nz, _p(hh), ctypes.byref(prm))
     return R
+
+
+MONITORS = ("theta", "z", "hz", "lndet", "tra", "ko")
+
+
+def monitor(system: int, U: np.ndarray, h, prm: Params | None = None) -> dict:
+    """Constraint and dissipation monitors at every interior point (arrays of
+    the interior shape): CCZ4 (Sec. V) Theta, |Z| = sqrt(gamma_ij Z^i Z^j),
+    H_Z (the bracket of the Theta equation), ln det gt, tr At; every system:
+    ko = sqrt(sum_f (Q_d U_f)^2), the magnitude of the dissipation term."""
+    prm = prm or params()
+    nf, nx, ny, nz = dims(U)
+    hh = _h3(h)
+    I = (slice(3, -3), slice(3, -3), slice(3, -3))
+    out = {}
+    if system == CCZ4:
+        Mc = np.zeros((5,) + U.shape[1:])
+        lib().orc_ccz4_monitor(_p(U), _p(Mc), nx, ny, nz, _p(hh), ctypes.byref(prm))
+        out["theta"] = Mc[0][I].copy()
+        out["z"] = np.sqrt(Mc[1][I])
+        out["hz"] = Mc[2][I].copy()
+        out["lndet"] = Mc[3][I].copy()
+        out["tra"] = Mc[4][I].copy()
+    Mk = np.zeros(U.shape[1:])
+    lib().orc_ko_monitor(system, _p(U), _p(Mk), nx, ny, nz, _p(hh), ctypes.byref(prm))
+    out["ko"] = np.sqrt(Mk[I])
+    return out
+
+
+def monitor_norms(system: int, U: np.ndarray, h, prm: Params | None = None) -> dict:
+    """Per monitor: (sum |v| dV, sum v^2 dV, max |v|) over the interior
+    points where v is finite, and the number of non-finite values of U at
+    interior points ("nonfinite")."""
+    hh = _h3(h)
+    dV = hh[0] * hh[1] * hh[2]
+    res = {}
+    for k, v in monitor(system, U, h, prm).items():
+        v = v[np.isfinite(v)]
+        res[k] = (float(np.sum(np.abs(v)) * dV), float(np.sum(v * v) * dV),
+                  float(np.max(np.abs(v))) if v.size else 0.0)
+    res["nonfinite"] = int(np.sum(~np.isfinite(U[:, 3:-3, 3:-3, 3:-3])))
+    return res
 
 
 def rk_run(system: int, scheme: int, U: np.ndarray, h, dt: float, nsteps: int,

@@ -39,18 +39,20 @@ enum {
 /* symmetric index pair (i,j) -> 0..5 for xx xy xz yy yz zz */
 static const int SYM[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
 
-void orc_ccz4_rhs(const double* U, double* R, int nx, int ny, int nz,
-                  const double h[3], const orc_params* p)
+/* The right-hand side at point c of the patch array U (field stride vol,
+ * axis strides st): out[f] = rhs of field f + its KO term.  When mon is not
+ * NULL it also receives the constraint monitors of Sec. V at that point:
+ * mon[0] = Theta, mon[1] = gamma_ij Z^i Z^j = gt_ij Z^i Z^j / chi, mon[2] =
+ * H_Z, the bracket of the Theta equation (R + 2 nabla_i Z^i + 2/3 trKhat^2 +
+ * 2/3 Theta (trKhat - 2 Theta) - At_ij At^ij), mon[3] = ln det gt, mon[4] =
+ * tr At = gt^ij At_ij; each is the value the right-hand side itself uses. */
+static void ccz4_point(const double* U, long vol, long c, const long st[3], const double h[3],
+                       const orc_params* p, double out[NF_CCZ4], double* mon)
 {
-    long NX = nx + 2 * ORC_G, NY = ny + 2 * ORC_G, NZ = nz + 2 * ORC_G;
-    long vol = NX * NY * NZ;
-    long st[3] = {1, NX, NX * NY};
     const double kz = p->kappa_z, kc = p->kappa_c;
-
-    for (int kk = ORC_G; kk < nz + ORC_G; ++kk)
-        for (int jj = ORC_G; jj < ny + ORC_G; ++jj)
-            for (int ii = ORC_G; ii < nx + ORC_G; ++ii) {
-                long c = (kk * NY + jj) * NX + ii;
+    {
+        {
+            {
 #define FLD(f) (U + (long)(f) * vol + c)
                 /* ---- point values ---- */
                 double chi = *FLD(F_CHI), Kh = *FLD(F_KH), Th = *FLD(F_TH), alp = *FLD(F_ALP);
@@ -329,7 +331,52 @@ void orc_ccz4_rhs(const double* U, double* R, int nx, int ny, int nz,
                     rhs[F_BETA + i] = adv[F_BETA + i] + p->gd_g * Bv[i];
                     rhs[F_B + i] = adv[F_B + i] - p->gd_eta * Bv[i] + dtG_noadv[i];
                 }
-                for (int fld = 0; fld < NF_CCZ4; ++fld)
-                    R[(long)fld * vol + c] = rhs[fld] + ko[fld];
+                for (int fld = 0; fld < NF_CCZ4; ++fld) out[fld] = rhs[fld] + ko[fld];
+                if (mon) {
+                    double zz = 0.0;
+                    for (int i = 0; i < 3; ++i)
+                        for (int j = 0; j < 3; ++j) zz += gt[i][j] * Z[i] * Z[j];
+                    mon[0] = Th;
+                    mon[1] = zz / chi;
+                    mon[2] = trRic + 2.0 / 3.0 * Kh * Kh + 2.0 / 3.0 * Th * (Kh - 2.0 * Th) - AA;
+                    mon[3] = lndet;
+                    mon[4] = trA;
+                }
+            }
+        }
+    }
+}
+
+void orc_ccz4_rhs(const double* U, double* R, int nx, int ny, int nz,
+                  const double h[3], const orc_params* p)
+{
+    long NX = nx + 2 * ORC_G, NY = ny + 2 * ORC_G, NZ = nz + 2 * ORC_G;
+    long vol = NX * NY * NZ;
+    long st[3] = {1, NX, NX * NY};
+    double out[NF_CCZ4];
+    for (int kk = ORC_G; kk < nz + ORC_G; ++kk)
+        for (int jj = ORC_G; jj < ny + ORC_G; ++jj)
+            for (int ii = ORC_G; ii < nx + ORC_G; ++ii) {
+                long c = (kk * NY + jj) * NX + ii;
+                ccz4_point(U, vol, c, st, h, p, out, 0);
+                for (int fld = 0; fld < NF_CCZ4; ++fld) R[(long)fld * vol + c] = out[fld];
+            }
+}
+
+/* Constraint monitors (see ccz4_point) at every interior point: M holds
+ * five fields in the patch-array layout. */
+void orc_ccz4_monitor(const double* U, double* M, int nx, int ny, int nz,
+                      const double h[3], const orc_params* p)
+{
+    long NX = nx + 2 * ORC_G, NY = ny + 2 * ORC_G, NZ = nz + 2 * ORC_G;
+    long vol = NX * NY * NZ;
+    long st[3] = {1, NX, NX * NY};
+    double out[NF_CCZ4], mon[5];
+    for (int kk = ORC_G; kk < nz + ORC_G; ++kk)
+        for (int jj = ORC_G; jj < ny + ORC_G; ++jj)
+            for (int ii = ORC_G; ii < nx + ORC_G; ++ii) {
+                long c = (kk * NY + jj) * NX + ii;
+                ccz4_point(U, vol, c, st, h, p, out, mon);
+                for (int q = 0; q < 5; ++q) M[(long)q * vol + c] = mon[q];
             }
 }

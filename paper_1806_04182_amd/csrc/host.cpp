@@ -784,7 +784,9 @@ int build(mol_patchset* ps, const mol_hierarchy_desc* h, const mol_patchset* pre
         int tn[3] = {32, 4, 2};
         build_tiles(lev, tn, 0, lev.ntiles, &ps->arena);
     }
-    ps->arena.reserve(sizeof(double) * 8 * ps->red_blocks, reinterpret_cast<void**>(&ps->scratch));
+    // reduction partials: the norms' 5 (8 reserved) or the monitors' per block
+    ps->arena.reserve(sizeof(double) * std::max(8, monitor_partials()) * ps->red_blocks,
+                      reinterpret_cast<void**>(&ps->scratch));
     int64_t tmax = 0;
     for (int l = 0; l + 1 < ps->nlev; ++l) tmax = std::max(tmax, ps->L[l].nelems);
     if (tmax > 0) ps->arena.reserve(sizeof(double) * tmax, reinterpret_cast<void**>(&ps->tband));
@@ -1501,6 +1503,25 @@ int mol_box_norms(mol_patchset* ps, int level, const double* U, int field, doubl
     }
     const double inf = std::numeric_limits<double>::infinity();
     return norms_impl(ps, level, U, field, shift, inf, b, out_dev, stream);
+}
+
+int mol_monitor(mol_patchset* ps, int level, const double* U, uint32_t which, double* pointwise, double* out_dev,
+                void* stream)
+{
+    int rc = check_level(ps, level);
+    if (rc) return rc;
+    if (!U || !out_dev) return fail(MOL_EINVAL, "null buffer");
+    if (which == 0 || (which & ~MOL_MON_ALL)) return fail(MOL_EINVAL, "monitor mask 0x%x is empty or unknown", which);
+    const bool ccz4 = ps->sp.system == MOL_CCZ4;
+    if (!ccz4 && (which & ~MOL_MON_KO))
+        return fail(MOL_EUNSUPPORTED, "only MOL_MON_KO exists for this system (the others are CCZ4 monitors)");
+    if (pointwise && (pointwise == U)) return fail(MOL_EINVAL, "pointwise must not alias U");
+    Level& lev = ps->L[level];
+    SysParams sp = level_params(ps, level);
+    hipError_t e = launch_monitor(lev.d_pd.p, lev.ntiles.dev.p, (int)lev.ntiles.dev.n, lev.ntiles.tdim, ps->sp.nf,
+                                  ccz4 ? 1 : 0, which, lev.h, sp.sigma, U, pointwise, ps->scratch, ps->red_blocks,
+                                  out_dev, S(stream));
+    return e == hipSuccess ? MOL_OK : hip_fail(e, "monitor launch");
 }
 
 int mol_sphere_adjoint(mol_patchset* ps, int level, int field, double radius, double scale, double* lam,

@@ -189,6 +189,10 @@ hipError_t launch_norms(const PatchDev* patches, const Tile* tiles, int ntiles, 
                         const double* U, int field, double shift, double radius, double h,
                         const double xlo[3], const CoordBox& box, double* partial, int nblocks, double* out,
                         hipStream_t s);
+int monitor_partials();  // doubles per reduction block of launch_monitor
+hipError_t launch_monitor(const PatchDev* patches, const Tile* tiles, int ntiles, const int td[3], int nf, int ccz4,
+                          unsigned which, double h, double sigma, const double* U, double* point, double* partial,
+                          int nblocks, double* out, hipStream_t s);
 hipError_t launch_sphere_adjoint(const PatchDev* patches, const Tile* tiles, int ntiles, const int tdim[3],
                                 int nf, int field, double radius, double scale, double h, const double xlo[3],
                                 double* lam, hipStream_t s);

@@ -26,6 +26,10 @@ MOL_FLUX_LLF, MOL_FLUX_HLL, MOL_FLUX_SPLIT = 0, 1, 2
 MOL_TIME_BOR, MOL_TIME_BO, MOL_TIME_BO1, MOL_TIME_NOSUB = 0, 16, 32, 48
 MOL_ADV_SSPRK3 = 64  # SSP-RK3 steps in advance() (or-ed into the mode)
 MOL_ADJOINT_SCRATCH_BYTES = 64 << 20  # static workspace of mol_rhs_adjoint_noalloc
+MOL_MON_THETA, MOL_MON_Z, MOL_MON_HZ, MOL_MON_LNDET, MOL_MON_TRA, MOL_MON_KO = (1 << q for q in range(6))
+MOL_MON_ALL, MOL_MON_COUNT = 0x3F, 6
+MOL_MON_OUT = 3 * MOL_MON_COUNT + 1
+MONITORS = ("theta", "z", "hz", "lndet", "tra", "ko")
 GHOST = 3
 NFIELDS = {MOL_WAVE: 2, MOL_MHD: 8, MOL_CCZ4: 25, MOL_MHD_GLM: 9}
 
@@ -103,6 +107,7 @@ def lib():
             "mol_norms": ([vp, i, vp, i, d, d, vp, vp], i),
             "mol_box_norms": ([vp, i, vp, i, d, dp, dp, vp, vp], i),
             "mol_sphere_adjoint": ([vp, i, i, d, d, vp, vp], i),
+            "mol_monitor": ([vp, i, vp, ctypes.c_uint32, vp, vp, vp], i),
             "mol_wave_gaussian": ([vp, i, dp, vp, vp], i),
             "mol_wave_gaussian_vjp": ([vp, i, dp, vp, vp, vp], i),
             "mol_ccz4_lapse_pulse": ([vp, i, dp, vp, vp], i),
@@ -315,6 +320,12 @@ class Patchset:
 
     def norms(self, level, U, field, shift, radius, out_dev, stream=None):
         _check(lib().mol_norms(self._h, level, _ptr(U), field, shift, radius, _ptr(out_dev), _stream(stream)))
+
+    def monitor(self, level, U, which, out_dev, pointwise=None, stream=None):
+        """Constraint / dissipation monitors (mol_monitor): out_dev holds
+        MOL_MON_OUT doubles (L1, sum of squares and max per monitor, then
+        the count of non-finite values)."""
+        _check(lib().mol_monitor(self._h, level, _ptr(U), which, _ptr(pointwise), _ptr(out_dev), _stream(stream)))
 
     def set_radiative(self, v, uinf):
         """Per-field speed and value at infinity of the radiative boundary."""

@@ -140,7 +140,9 @@ def test_ccz4_noisy_minkowski_stays_bounded(n):
     """Robust stability on the GPU path at the benchmark sizes: Minkowski plus
     1e-10 noise, 50 RK4 steps.  The first steps amplify the grid-scale noise by
     a bounded factor that grows with the resolution (about 150x at 48^3);
-    after that the deviation from flat space must not grow."""
+    after that the deviation from flat space must not grow.  The L2 norm of
+    H_Z (mol_monitor) stays within 10x its initial value and does not grow
+    over the second half of the run."""
     torch = _torch()
     dx = 2.0 / n
     ps = M.Patchset(M.single_patch((n, n, n), (-1, -1, -1), dx), M.System(M.MOL_CCZ4))
@@ -157,11 +159,24 @@ def test_ccz4_noisy_minkowski_stays_bounded(n):
             d = max(d, float(o[2]))
         return d
 
-    dev0 = deviation()
-    devs = []
+    mon = torch.zeros(M.MOL_MON_OUT, dtype=torch.float64, device="cuda")
+
+    def hz_l2():
+        ps.monitor(0, st[0]["U"], M.MOL_MON_HZ, mon)
+        m = mon.cpu().numpy()
+        assert m[-1] == 0.0
+        return float(np.sqrt(m[3 * 2 + 1]))
+
+    ps.fill_ghosts(0, st[0]["U"])
+    dev0, hz0 = deviation(), hz_l2()
+    devs, hzs = [], []
     for _ in range(10):
         for _ in range(5):
             ps.advance(st, 0.25 * dx)
         devs.append(deviation())
+        hzs.append(hz_l2())
+    print("noisy minkowski", n, dev0, devs, hz0, hzs, flush=True)
     assert max(devs) <= 1e4 * dev0, (dev0, devs)
     assert max(devs[5:]) <= max(devs[:5]), devs
+    # the Hamiltonian-type constraint (L2 of the Theta bracket H_Z) does not grow
+    assert max(hzs) <= 10 * hz0 and max(hzs[5:]) <= max(hzs[:5]), (hz0, hzs)
