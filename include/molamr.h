@@ -356,6 +356,22 @@ int mol_box_norms(mol_patchset* ps, int level, const double* U, int field, doubl
 int mol_monitor(mol_patchset* ps, int level, const double* U, uint32_t which, double* pointwise,
                 double* out_dev, void* stream);
 
+/* Puncture initial data of Sec. V for the CCZ4 system on every patch of
+ * `level`: the conformal factor psi = 1 + sum_A m_A / (2 r_A)
+ * (eq. conformal_factor; Brill-Lindquist), chi = psi^-4, gt_ij = delta_ij,
+ * alpha = psi^-2, At_ij = psi^-6 times the sum over the holes of the
+ * Bowen-York solution for the hole's momentum P and spin S, and zero for
+ * trKhat, Theta, Ghat^i, beta^i, B^i.  holes: nholes (1..MOL_MAX_HOLES)
+ * records of 10 doubles on the host, (m, c_x, c_y, c_z, P_x, P_y, P_z, S_x,
+ * S_y, S_z), with m > 0.  whole = 0 writes the interior points, 1 the whole
+ * ghosted boxes (for the outer shell of an open level 0, which is evolved
+ * state).  U: device level buffer.  No grid point may coincide with a
+ * puncture (the data are infinite there; not checked).  MOL_EUNSUPPORTED
+ * for other systems, MOL_EINVAL for bad arguments. */
+#define MOL_MAX_HOLES 8
+int mol_ccz4_puncture(mol_patchset* ps, int level, int nholes, const double* holes, int whole, double* U,
+                      void* stream);
+
 /* Transpose of the sphere integral of mol_norms (out_dev[3]): lam[field] =
  * scale * dV at interior points with |x| < radius, 0 at the other interior
  * points; the other fields are set to 0 on interior points; ghost entries
@@ -439,13 +455,16 @@ void mol_regrid_destroy(mol_regrid* r);
 /* ---- autotuning of the stage launches ---- */
 typedef struct {
     int tdim[3]; /* launch shape: thread tile, or 64 x 8 (wave) / 15 x 15 (MHD) columns and a z-chunk length */
-    int order;   /* patches in the launch: 0 as listed, 1 largest interior first */
+    int order;   /* tiles in the launch: 0 patches as listed, x fastest within a patch;
+                    1 largest interior first; 2 as 0 with the tiles of each patch in
+                    columns along z (z fastest); 3 as 2 with columns in blocks of 2 x 2 */
     double ms;   /* measured time of one stage launch (mol_autotune) */
 } mol_tiling;
 /* Time the batched stage kernel of `level` under every candidate launch shape
  * of the system (wave: z-chunks 4..64 of the z-marching kernel and five
- * thread tiles of the point-wise one; MHD: z-chunks 4..32; CCZ4: its fixed
- * tile) and both patch orders, `reps` launches each (RK4 stage 2 with U as
+ * thread tiles of the point-wise one; MHD: z-chunks 4..32; CCZ4: tiles
+ * 8 x 8 x 4, 8 x 8 x 8 and 8 x 4 x 8) and tile orders (0 and 1; CCZ4 also 2
+ * and 3), `reps` launches each (RK4 stage 2 with U as
  * U^n, S0 as stage state, acc and S1 overwritten), and keep the fastest for
  * the level's later stage launches; *best (nullable) receives it.  The
  * results of a stage do not depend on the tiling.  Synchronises the stream;
@@ -453,7 +472,7 @@ typedef struct {
 int mol_autotune(mol_patchset* ps, int level, const mol_level_state* st, double dt, int reps, mol_tiling* best,
                  void* stream);
 /* Use a known tiling (one mol_autotune found earlier); MOL_EINVAL when tdim
- * is not a launch shape of the system's stage kernel or order is not 0/1. */
+ * is not a launch shape of the system's stage kernel or order is not 0..3. */
 int mol_set_tiling(mol_patchset* ps, int level, const mol_tiling* t);
 
 typedef struct mol_graph mol_graph;

@@ -468,3 +468,53 @@ def time_state(mode: int, R: int, r: int, s: int, dt: float, Un: np.ndarray, k, 
 def dense_ssp3(j: int, m: int, theta: float) -> float:
     return lib().orc_dense_ssp3(j, m, theta)
 
+
+
+def ccz4_puncture_at(x, y, z, holes) -> np.ndarray:
+    """Puncture initial data of Sec. V at the points (x, y, z) (arrays of one
+    shape), for holes [(m, centre(3), P(3), S(3)), ...]: the 25 CCZ4 fields.
+    Conformal factor psi = 1 + sum_A m_A / (2 r_A) (eq. conformal_factor,
+    Brill-Lindquist); chi = psi^-4, gt_ij = delta_ij, trKhat = Theta = 0,
+    Ghat^i = beta^i = B^i = 0, alpha = psi^-2 (the paper's initial lapse);
+    At_ij = psi^-6 times the sum over holes of the Bowen-York solution
+      3/(2 r^2) [P_i n_j + P_j n_i - (delta_ij - n_i n_j) P^k n_k]
+      + 3/r^3 [eps_kil S^l n^k n_j + eps_kjl S^l n^k n_i],
+    n = (x - c)/r.  No point may coincide with a puncture."""
+    x = [np.asarray(x, dtype=np.float64), np.asarray(y, dtype=np.float64), np.asarray(z, dtype=np.float64)]
+    psi = np.ones_like(x[0])
+    for m, c, _, _ in holes:
+        r = np.sqrt((x[0] - c[0]) ** 2 + (x[1] - c[1]) ** 2 + (x[2] - c[2]) ** 2)
+        psi = psi + m / (2.0 * r)
+    eps = np.zeros((3, 3, 3))
+    eps[0, 1, 2] = eps[1, 2, 0] = eps[2, 0, 1] = 1.0
+    eps[0, 2, 1] = eps[2, 1, 0] = eps[1, 0, 2] = -1.0
+    A = np.zeros((3, 3) + x[0].shape)
+    for m, c, P, S in holes:
+        r = np.sqrt((x[0] - c[0]) ** 2 + (x[1] - c[1]) ** 2 + (x[2] - c[2]) ** 2)
+        n = [(x[d] - c[d]) / r for d in range(3)]
+        Pn = P[0] * n[0] + P[1] * n[1] + P[2] * n[2]
+        for i in range(3):
+            for j in range(3):
+                dij = 1.0 if i == j else 0.0
+                mom = 1.5 / r ** 2 * (P[i] * n[j] + P[j] * n[i] - (dij - n[i] * n[j]) * Pn)
+                spin = 0.0
+                for k in range(3):
+                    for l in range(3):
+                        spin = spin + (eps[k, i, l] * n[j] + eps[k, j, l] * n[i]) * S[l] * n[k]
+                A[i, j] = A[i, j] + mom + 3.0 / r ** 3 * spin
+    A = A / psi ** 6
+    out = np.zeros((25,) + x[0].shape)
+    out[0] = psi ** -4
+    for q, (i, j) in enumerate(((0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2))):
+        out[1 + q] = 1.0 if i == j else 0.0
+        out[8 + q] = A[i, j]
+    out[18] = psi ** -2
+    return out
+
+
+def ccz4_puncture(n, h, lo, xlo, holes) -> np.ndarray:
+    """ccz4_puncture_at on the points x_d = xlo_d + (lo_d + i) h of an
+    n[0] x n[1] x n[2] block, as a (25, n[2], n[1], n[0]) array."""
+    ax = [xlo[d] + (lo[d] + np.arange(n[d])) * h for d in range(3)]
+    Z, Y, X = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    return ccz4_puncture_at(X, Y, Z, holes)

@@ -8,7 +8,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import molamr as M
-from . import synth
+from . import synth  # noqa: F401  (flat values of the radiative boundary)
 
 
 def nested_levels(nlev: int, N: int):
@@ -34,17 +34,11 @@ class SingleBH:
         self.ps.set_radiative([1.0] * 25, list(synth.CCZ4_FLAT))
         self.holes = [(mass, (0.0, 0.0, 0.0), (0.0, 0.0, 0.0), (0.0, 0.0, spin * mass * mass))]
         self.st = self.ps.alloc_states()
-        h = self.dx0
-        for l, (R, boxes) in enumerate(self.levels):
-            if l:
-                h /= R
-            arrs = []
-            for lo, hi in boxes:
-                # data on the whole ghosted box: on level 0 the ghost shell is
-                # evolved state (radiative boundary), not filled
-                n = tuple(hi[d] - lo[d] + 1 + 6 for d in range(3))
-                arrs.append(synth.ccz4_puncture(n, h, tuple(x - 3 for x in lo), self.xlo, self.holes))
-            self.st[l]["U"].copy_(torch.from_numpy(self.ps.pack(l, arrs)))
+        for l in range(len(self.levels)):
+            # data on the whole ghosted box: on level 0 the ghost shell is
+            # evolved state (radiative boundary), not filled
+            self.ps.ccz4_puncture(l, self.holes, self.st[l]["U"], whole=True)
+        torch.cuda.synchronize()
         self.t = 0.0
         self.graph = self.ps.graph_create(self.st, 0.25 * self.dx0)
 
@@ -68,10 +62,11 @@ class SingleBH:
             lo = self.levels[l][1][0][0]
             i = int(round((x - self.xlo[0]) / h)) - lo[0]
             j = int(round((0.0 - self.xlo[1]) / h)) - lo[1]
+            k = int(round((0.0 - self.xlo[2]) / h)) - lo[2]
             u = self.level(l)
-            if 0 <= i < u.shape[3]:
-                return float(u[f][j, j, i])
-        raise ValueError("x outside the domain")
+            if 0 <= i < u.shape[3] and 0 <= j < u.shape[2] and 0 <= k < u.shape[1]:
+                return float(u[f][k, j, i])
+        raise ValueError("(x, 0, 0) outside every level")
 
     def summary(self):
         """Lapse and conformal factor at the finest level, and finiteness."""

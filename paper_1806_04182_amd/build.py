@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libmolamr.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("MOLAMR_ARCH", "gfx950")
 
-SOURCES = ["host.cpp", "k_wave.hip", "k_mhd.hip", "k_ccz4.hip", "k_ccz4_adj.hip", "k_amr.hip", "k_reduce.hip", "k_monitor.hip"]
+SOURCES = ["host.cpp", "k_wave.hip", "k_mhd.hip", "k_ccz4.hip", "k_ccz4_adj.hip", "k_amr.hip", "k_reduce.hip", "k_monitor.hip", "k_init.hip"]
 FLAGS = ["-O3", "-std=c++20", "-fPIC", f"--offload-arch={ARCH}", "-I", os.path.join(ROOT, "include"),
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-function",
          "-Wno-unused-command-line-argument"]

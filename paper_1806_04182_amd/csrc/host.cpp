@@ -369,10 +369,22 @@ int build_tiles(const Level& lev, const int td[3], int margin, TileList& tl, Are
     for (int p : perm) {
         const PatchDev& pd = lev.pd[p];
         tl.by_patch[p] = (int)v.size();
-        for (int k = -margin; k < pd.n[2] + margin; k += td[2])
-            for (int j = -margin; j < pd.n[1] + margin; j += td[1])
-                for (int i = -margin; i < pd.n[0] + margin; i += td[0])
-                    v.push_back(Tile{p, {i, j, k}});
+        if (order == 2 || order == 3) {
+            // columns of tiles along z, z fastest (order 2), or grouped in
+            // blocks of 2 x 2 columns (order 3): tiles that share z halos run
+            // together on one XCD
+            const int bw = order == 3 ? 2 : 1;
+            for (int jb = -margin; jb < pd.n[1] + margin; jb += bw * td[1])
+                for (int ib = -margin; ib < pd.n[0] + margin; ib += bw * td[0])
+                    for (int jj = jb; jj < std::min(jb + bw * td[1], pd.n[1] + margin); jj += td[1])
+                        for (int ii = ib; ii < std::min(ib + bw * td[0], pd.n[0] + margin); ii += td[0])
+                            for (int k = -margin; k < pd.n[2] + margin; k += td[2]) v.push_back(Tile{p, {ii, jj, k}});
+        } else {
+            for (int k = -margin; k < pd.n[2] + margin; k += td[2])
+                for (int j = -margin; j < pd.n[1] + margin; j += td[1])
+                    for (int i = -margin; i < pd.n[0] + margin; i += td[0])
+                        v.push_back(Tile{p, {i, j, k}});
+        }
         tl.count[p] = (int)v.size() - tl.by_patch[p];
     }
     tl.by_patch[np] = (int)v.size();
@@ -896,6 +908,16 @@ void time_weights(int mode, int R, int r, int s, double w[4])
 
 hipStream_t S(void* s) { return (hipStream_t)s; }
 
+// a wave level that is one periodic patch (the whole domain, no finer level,
+// at least 4 points per axis): the wave stage kernels read stencil
+// neighbours at the periodic images, and the driver skips the ghost fill
+bool level_wraps(const mol_patchset* ps, int l)
+{
+    const auto& lev = ps->L[l];
+    return ps->sp.system == MOL_WAVE && l == 0 && ps->nlev == 1 && !ps->open && lev.pd.size() == 1 &&
+           lev.pd[0].n[0] >= 4 && lev.pd[0].n[1] >= 4 && lev.pd[0].n[2] >= 4;
+}
+
 int stage_impl(mol_patchset* ps, int level, int mode, int stage, double dt, const double* Un,
                const double* Us, double* acc, double* out, double* kst, hipStream_t st, int plain,
                bool wrap = false)
@@ -1012,9 +1034,7 @@ int advance_level(mol_patchset* ps, const mol_level_state* st, int l, int r, dou
     // a wave level that is one periodic patch (the whole domain, no finer
     // level, at least 4 points per axis) reads its stencil neighbours at the
     // periodic images: no ghost fill before its stages
-    const Level& lev = ps->L[l];
-    const bool wrap = ps->sp.system == MOL_WAVE && l == 0 && ps->nlev == 1 && !ps->open && lev.pd.size() == 1 &&
-                      lev.pd[0].n[0] >= 4 && lev.pd[0].n[1] >= 4 && lev.pd[0].n[2] >= 4;
+    const bool wrap = level_wraps(ps, l);
     int rc;
     for (int sidx = 0; sidx < nst; ++sidx) {
         double* Us = stage_in[sidx];
@@ -1524,6 +1544,27 @@ int mol_monitor(mol_patchset* ps, int level, const double* U, uint32_t which, do
     return e == hipSuccess ? MOL_OK : hip_fail(e, "monitor launch");
 }
 
+int mol_ccz4_puncture(mol_patchset* ps, int level, int nholes, const double* holes, int whole, double* U,
+                      void* stream)
+{
+    int rc = check_level(ps, level);
+    if (rc) return rc;
+    if (ps->sp.system != MOL_CCZ4) return fail(MOL_EUNSUPPORTED, "CCZ4 system only");
+    if (!holes || !U) return fail(MOL_EINVAL, "null argument");
+    if (nholes < 1 || nholes > MOL_MAX_HOLES) return fail(MOL_EINVAL, "nholes %d not in [1, %d]", nholes, MOL_MAX_HOLES);
+    if (whole != 0 && whole != 1) return fail(MOL_EINVAL, "whole must be 0 or 1");
+    for (int a = 0; a < nholes; ++a) {
+        if (!(holes[10 * a] > 0.0)) return fail(MOL_EINVAL, "hole %d: mass must be positive", a);
+        for (int q = 0; q < 10; ++q)
+            if (!std::isfinite(holes[10 * a + q])) return fail(MOL_EINVAL, "hole %d: non-finite parameter", a);
+    }
+    Level& lev = ps->L[level];
+    const TileList& tl = whole ? lev.gtiles : lev.ntiles;
+    hipError_t e = launch_puncture(lev.d_pd.p, tl.dev.p, (int)tl.dev.n, tl.tdim, nholes, holes, lev.h, ps->xlo, whole,
+                                   U, S(stream));
+    return e == hipSuccess ? MOL_OK : hip_fail(e, "puncture launch");
+}
+
 int mol_sphere_adjoint(mol_patchset* ps, int level, int field, double radius, double scale, double* lam,
                        void* stream)
 {
@@ -1862,7 +1903,11 @@ std::vector<std::array<int, 3>> tiling_candidates(int system)
     case MOL_MHD_GLM:
         for (int z : {4, 8, 16, 32}) c.push_back({15, 15, z});
         break;
-    default: c.push_back({MOL_CCZ4_TX, MOL_CCZ4_TY, MOL_CCZ4_TZ}); break;
+    default:
+        c.push_back({MOL_CCZ4_TX, MOL_CCZ4_TY, MOL_CCZ4_TZ});
+        c.push_back({8, 8, 8});
+        c.push_back({8, 4, 8});
+        break;
     }
     return c;
 }
@@ -1876,7 +1921,9 @@ bool tiling_valid(int system, const int td[3])
         return td[0] * td[1] * td[2] <= 256;                                                 // point-wise
     case MOL_MHD:
     case MOL_MHD_GLM: return td[0] == 15 && td[1] == 15 && td[2] <= 1024;
-    default: return td[0] == MOL_CCZ4_TX && td[1] == MOL_CCZ4_TY && td[2] == MOL_CCZ4_TZ;
+    default:
+        return (td[0] == MOL_CCZ4_TX && td[1] == MOL_CCZ4_TY && td[2] == MOL_CCZ4_TZ) ||
+               (td[0] == 8 && td[1] == 8 && td[2] == 8) || (td[0] == 8 && td[1] == 4 && td[2] == 8);
     }
 }
 
@@ -1902,7 +1949,7 @@ int mol_set_tiling(mol_patchset* ps, int level, const mol_tiling* t)
     int rc = check_level(ps, level);
     if (rc) return rc;
     if (!t) return fail(MOL_EINVAL, "null tiling");
-    if (t->order < 0 || t->order > 1) return fail(MOL_EINVAL, "patch order %d not in {0, 1}", t->order);
+    if (t->order < 0 || t->order > 3) return fail(MOL_EINVAL, "tile order %d not in 0..3", t->order);
     if (!tiling_valid(ps->sp.system, t->tdim))
         return fail(MOL_EINVAL, "tile %d x %d x %d is not a launch shape of this system's stage kernel", t->tdim[0],
                     t->tdim[1], t->tdim[2]);
@@ -1930,16 +1977,20 @@ int mol_autotune(mol_patchset* ps, int level, const mol_level_state* st, double 
     win.ms = -1.0;
     const TileList keep = lev.tiles;
     rc = MOL_OK;
+    const bool wrap = level_wraps(ps, level);
+    // tile orders: patches as listed or largest first; for CCZ4 also the
+    // column orders (the wave and MHD kernels march along z already)
+    const int last_order = ps->sp.system == MOL_CCZ4 ? 3 : 1;
     for (const auto& td : tiling_candidates(ps->sp.system)) {
-        for (int order = 0; order <= 1 && rc == MOL_OK; ++order) {
+        for (int order = 0; order <= last_order && rc == MOL_OK; ++order) {
             TileList tl;
             if ((rc = build_tiles(lev, td.data(), 0, tl, nullptr, order))) break;
             lev.tiles = tl;
             // RK4 stage 2: reads U, S0 and acc, writes acc and S1
-            rc = stage_impl(ps, level, ST_RK4, 2, dt, st->U, st->S0, st->acc, st->S1, nullptr, s, 0);
+            rc = stage_impl(ps, level, ST_RK4, 2, dt, st->U, st->S0, st->acc, st->S1, nullptr, s, 0, wrap);
             if (rc == MOL_OK && (e = hipEventRecord(e0, s)) != hipSuccess) rc = hip_fail(e, "hipEventRecord");
             for (int r = 0; r < reps && rc == MOL_OK; ++r)
-                rc = stage_impl(ps, level, ST_RK4, 2, dt, st->U, st->S0, st->acc, st->S1, nullptr, s, 0);
+                rc = stage_impl(ps, level, ST_RK4, 2, dt, st->U, st->S0, st->acc, st->S1, nullptr, s, 0, wrap);
             float ms = 0.0f;
             if (rc == MOL_OK && (e = hipEventRecord(e1, s)) != hipSuccess) rc = hip_fail(e, "hipEventRecord");
             if (rc == MOL_OK && (e = hipEventSynchronize(e1)) != hipSuccess) rc = hip_fail(e, "hipEventSynchronize");

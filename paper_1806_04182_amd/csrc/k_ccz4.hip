@@ -531,10 +531,26 @@ __global__ __launch_bounds__(TX * TY * TZ, MOL_CCZ4_WAVES) void ccz4_stage_persi
 
 }  // namespace
 
+namespace {
+// the tile shapes compiled besides the default (the autotuner picks one per level)
+template <int TX, int TY, int TZ>
+hipError_t launch_ccz4_tile(const SysParams& sp, const StageArgs& a, const CczConst& C, hipStream_t s)
+{
+    const dim3 blk(TX, TY, TZ);
+    if (sp.upwind)
+        ccz4_stage_kernel<TX, TY, TZ, true><<<a.ntiles, blk, 0, s>>>(a, C);
+    else
+        ccz4_stage_kernel<TX, TY, TZ, false><<<a.ntiles, blk, 0, s>>>(a, C);
+    return hipGetLastError();
+}
+}  // namespace
+
 hipError_t launch_stage_ccz4(const SysParams& sp, const StageArgs& a, const int td[3], hipStream_t s)
 {
     if (a.ntiles <= 0) return hipSuccess;
-    if (td[0] != MOL_CCZ4_TX || td[1] != MOL_CCZ4_TY || td[2] != MOL_CCZ4_TZ) return hipErrorInvalidConfiguration;
+    const bool dflt = td[0] == MOL_CCZ4_TX && td[1] == MOL_CCZ4_TY && td[2] == MOL_CCZ4_TZ;
+    const bool t888 = td[0] == 8 && td[1] == 8 && td[2] == 8, t848 = td[0] == 8 && td[1] == 4 && td[2] == 8;
+    if (!dflt && !t888 && !t848) return hipErrorInvalidConfiguration;
     CczConst C;
     C.i12h = 1.0 / (12.0 * sp.h);
     C.i12h2 = 1.0 / (12.0 * sp.h * sp.h);
@@ -546,6 +562,7 @@ hipError_t launch_stage_ccz4(const SysParams& sp, const StageArgs& a, const int 
     C.f1 = sp.bm_f1;
     C.g = sp.gd_g;
     C.eta = sp.gd_eta;
+    if (!dflt) return t888 ? launch_ccz4_tile<8, 8, 8>(sp, a, C, s) : launch_ccz4_tile<8, 4, 8>(sp, a, C, s);
     dim3 blk(MOL_CCZ4_TX, MOL_CCZ4_TY, MOL_CCZ4_TZ);
 #if MOL_CCZ4_PERSISTENT
     // as many workgroups as are resident at once: MOL_CCZ4_WAVES waves per

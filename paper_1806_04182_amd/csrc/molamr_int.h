@@ -193,6 +193,8 @@ int monitor_partials();  // doubles per reduction block of launch_monitor
 hipError_t launch_monitor(const PatchDev* patches, const Tile* tiles, int ntiles, const int td[3], int nf, int ccz4,
                           unsigned which, double h, double sigma, const double* U, double* point, double* partial,
                           int nblocks, double* out, hipStream_t s);
+hipError_t launch_puncture(const PatchDev* patches, const Tile* tiles, int ntiles, const int td[3], int nholes,
+                           const double* holes, double h, const double xlo[3], int whole, double* U, hipStream_t s);
 hipError_t launch_sphere_adjoint(const PatchDev* patches, const Tile* tiles, int ntiles, const int tdim[3],
                                 int nf, int field, double radius, double scale, double h, const double xlo[3],
                                 double* lam, hipStream_t s);

@@ -108,6 +108,7 @@ def lib():
             "mol_box_norms": ([vp, i, vp, i, d, dp, dp, vp, vp], i),
             "mol_sphere_adjoint": ([vp, i, i, d, d, vp, vp], i),
             "mol_monitor": ([vp, i, vp, ctypes.c_uint32, vp, vp, vp], i),
+            "mol_ccz4_puncture": ([vp, i, i, dp, i, vp, vp], i),
             "mol_wave_gaussian": ([vp, i, dp, vp, vp], i),
             "mol_wave_gaussian_vjp": ([vp, i, dp, vp, vp, vp], i),
             "mol_ccz4_lapse_pulse": ([vp, i, dp, vp, vp], i),
@@ -326,6 +327,13 @@ class Patchset:
         MOL_MON_OUT doubles (L1, sum of squares and max per monitor, then
         the count of non-finite values)."""
         _check(lib().mol_monitor(self._h, level, _ptr(U), which, _ptr(pointwise), _ptr(out_dev), _stream(stream)))
+
+    def ccz4_puncture(self, level, holes, U, whole=False, stream=None):
+        """Puncture initial data (mol_ccz4_puncture); holes: [(m, centre(3),
+        P(3), S(3)), ...]; whole: also the ghost points."""
+        flat = [float(v) for m, c, P, S in holes for v in (m, *c, *P, *S)]
+        arr = (ctypes.c_double * len(flat))(*flat)
+        _check(lib().mol_ccz4_puncture(self._h, level, len(holes), arr, 1 if whole else 0, _ptr(U), _stream(stream)))
 
     def set_radiative(self, v, uinf):
         """Per-field speed and value at infinity of the radiative boundary."""

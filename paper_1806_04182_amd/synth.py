@@ -265,46 +265,3 @@ def mhd_brio_wu(n, dx, lo=(0, 0, 0), jumps=(0.5, 2.5), gamma=2.0):
     By = bc(np.where(left, 1.0, -1.0))
     zero = bc(0.0)
     return mhd_primitive_to_conserved(rho, [zero, zero, zero], p, [bc(0.75), By, zero], gamma)
-
-
-def ccz4_puncture(n, h, lo, xlo, holes):
-    """Puncture initial data of Sec. V on one patch: conformal factor
-    psi = 1 + sum_A m_A / (2 r_A), chi = psi^-4, alpha = psi^-2, gt_ij = delta_ij,
-    Khat = Theta = Ghat^i = beta^i = B^i = 0 and the Bowen-York At_ij of each
-    hole's momentum P and spin S, each term scaled by psi^-6:
-      3/(2 r^2) [P_i n_j + P_j n_i - (delta_ij - n_i n_j) P.n]
-      + 3/r^3 [eps_kil S^l n^k n_j + eps_kjl S^l n^k n_i].
-    holes: [(m, centre(3), P(3), S(3)), ...]; points at x = xlo + (lo + i) h
-    (the grid must not contain a puncture)."""
-    ax = [xlo[d] + (lo[d] + np.arange(n[d])) * h for d in range(3)]
-    Z, Y, X = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
-    x = [X, Y, Z]
-    psi = np.ones_like(X)
-    for m, c, _, _ in holes:
-        r = np.sqrt(sum((x[d] - c[d]) ** 2 for d in range(3)))
-        psi = psi + m / (2.0 * r)
-    eps = np.zeros((3, 3, 3))
-    eps[0, 1, 2] = eps[1, 2, 0] = eps[2, 0, 1] = 1.0
-    eps[0, 2, 1] = eps[2, 1, 0] = eps[1, 0, 2] = -1.0
-    A = np.zeros((3, 3) + X.shape)
-    for m, c, P, S in holes:
-        r = np.sqrt(sum((x[d] - c[d]) ** 2 for d in range(3)))
-        nv = [(x[d] - c[d]) / r for d in range(3)]
-        Pn = sum(P[d] * nv[d] for d in range(3))
-        for i in range(3):
-            for j in range(3):
-                dij = 1.0 if i == j else 0.0
-                a = 1.5 / r ** 2 * (P[i] * nv[j] + P[j] * nv[i] - (dij - nv[i] * nv[j]) * Pn)
-                s = 0.0
-                for k in range(3):
-                    for l in range(3):
-                        s = s + (eps[k, i, l] * nv[j] + eps[k, j, l] * nv[i]) * S[l] * nv[k]
-                A[i, j] += a + 3.0 / r ** 3 * s
-    A = A / psi ** 6
-    out = np.zeros((25,) + X.shape)
-    out[0] = psi ** -4
-    for p, (i, j) in enumerate(((0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2))):
-        out[1 + p] = 1.0 if i == j else 0.0
-        out[8 + p] = A[i, j]
-    out[18] = psi ** -2
-    return out

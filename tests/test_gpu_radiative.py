@@ -1,6 +1,7 @@
 """Open domains with radiative outer boundaries (Sec. V) on the GPU driver
-against the oracle (wave pulse, one and two levels; CCZ4 puncture data), and
-a single spinning black hole smoke run."""
+against the oracle (wave pulse, one and two levels; CCZ4 puncture data, the
+initial data written by the library's kernel), the puncture initial data
+itself, and a single spinning black hole smoke run."""
 import numpy as np
 import pytest
 
@@ -26,13 +27,17 @@ def _pulse(n, h, lo, xlo, w=0.4, r0=1.0):
     return np.stack([g / r, -2 * (r - r0) / w ** 2 * g / r])
 
 
-def _compare(system, levels, N0, xlo, dx0, init, sysd, prm, v, uinf, dt0, nsteps):
+def _compare(system, levels, N0, xlo, dx0, init, sysd, prm, v, uinf, dt0, nsteps, gpu_init=None):
+    """init: the oracle's (and, without gpu_init, the GPU's) data on each
+    level's ghosted box; gpu_init(ps, st): the GPU's own initial data."""
     torch = _torch()
     ps = M.Patchset(M.Hierarchy(N0, xlo, dx0, levels, open=True), sysd)
     ps.set_radiative(v, uinf)
     H = O.Hierarchy(system, N0, xlo, dx0, levels)
     H.set_open(v, uinf)
     st = ps.alloc_states()
+    if gpu_init is not None:
+        gpu_init(ps, st)
     h = dx0
     for l, (R, boxes) in enumerate(levels):
         if l:
@@ -41,7 +46,13 @@ def _compare(system, levels, N0, xlo, dx0, init, sysd, prm, v, uinf, dt0, nsteps
         # the data on the whole ghosted box: the outer shell is evolved state
         n = tuple(hi[d] - lo[d] + 1 + 6 for d in range(3))
         a = init(n, h, tuple(lo[d] - 3 for d in range(3)))
-        st[l]["U"].copy_(torch.from_numpy(ps.pack(l, [a])))
+        if gpu_init is None:
+            st[l]["U"].copy_(torch.from_numpy(ps.pack(l, [a])))
+        else:
+            torch.cuda.synchronize()
+            got = ps.unpack(l, st[l]["U"])[0]
+            e = parity_err(got, a)
+            assert np.all(e <= 1e-13), ("initial data", l, e)
         H.set(l, 0, a)
         H.fill_same(l)
     for _ in range(nsteps):
@@ -82,9 +93,43 @@ def test_ccz4_puncture_open_two_levels_matches_oracle():
     xlo = (-L + 0.25 * h,) * 3
     holes = [(1.0, (0.0, 0.0, 0.0), (0.0, 0.0, 0.0), (0.0, 0.0, 0.2))]
     levels = [(1, [((0, 0, 0), (N - 1,) * 3)]), (2, [((12, 12, 12), (35, 35, 35))])]
-    _compare(O.CCZ4, levels, (N, N, N), xlo, h, lambda n, hh, lo: synth.ccz4_puncture(n, hh, lo, xlo, holes),
+    def gpu_init(ps, st):
+        for l in range(len(levels)):
+            ps.ccz4_puncture(l, holes, st[l]["U"], whole=True)
+
+    _compare(O.CCZ4, levels, (N, N, N), xlo, h, lambda n, hh, lo: O.ccz4_puncture(n, hh, lo, xlo, holes),
              M.System(M.MOL_CCZ4, gd_eta=2.0), O.params(gd_eta=2.0), [1.0] * 25, list(synth.CCZ4_FLAT),
-             0.25 * h, 2)
+             0.25 * h, 2, gpu_init=gpu_init)
+
+
+@pytest.mark.parametrize("whole", [False, True])
+def test_puncture_initial_data_matches_oracle(whole):
+    """mol_ccz4_puncture on a level of ragged patches, two boosted spinning
+    holes, against the oracle's puncture data element by element (interior
+    points, or the whole ghosted boxes); untouched entries stay as they were."""
+    torch = _torch()
+    h, xlo = 0.13, (-1.9, -1.7, -1.55)
+    levels = [(1, [((0, 0, 0), (13, 29, 24)), ((14, 0, 0), (29, 29, 24))])]
+    holes = [(0.8, (-0.4, 0.3, 0.1), (0.05, -0.2, 0.1), (0.1, 0.3, -0.25)),
+             (0.5, (0.7, -0.2, -0.3), (-0.1, 0.15, 0.0), (0.0, -0.1, 0.2))]
+    ps = M.Patchset(M.Hierarchy((30, 30, 25), xlo, h, levels), M.System(M.MOL_CCZ4))
+    U = ps.alloc(0)
+    U.fill_(7.0)
+    ps.ccz4_puncture(0, holes, U, whole=whole)
+    torch.cuda.synchronize()
+    got = ps.unpack(0, U)
+    for p, (lo, hi) in enumerate(levels[0][1]):
+        n = tuple(hi[d] - lo[d] + 1 + 6 for d in range(3))
+        ref = O.ccz4_puncture(n, h, tuple(lo[d] - 3 for d in range(3)), xlo, holes)
+        sl = slice(None) if whole else slice(3, -3)
+        e = parity_err(got[p][:, sl, sl, sl], ref[:, sl, sl, sl])
+        assert np.all(e <= 1e-14), (p, e)
+        if not whole:
+            assert np.all(got[p][:, :3] == 7.0)
+    with pytest.raises(M.MolError, match="mass must be positive"):
+        ps.ccz4_puncture(0, [(0.0, (0, 0, 0), (0, 0, 0), (0, 0, 0))], U)
+    with pytest.raises(M.MolError, match="CCZ4 system only"):
+        M.Patchset(M.Hierarchy((30, 30, 25), xlo, h, levels), M.System(M.MOL_WAVE)).ccz4_puncture(0, holes, U)
 
 
 def test_open_domain_rules():

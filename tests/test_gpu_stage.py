@@ -83,26 +83,32 @@ def test_wave_rk4_parity_streamed_level():
     assert np.all(e <= TOL), e
 
 
+@pytest.mark.parametrize("scheme,launch", [("rk4", M.MOL_BATCHED), ("rk4", M.MOL_PLAIN), ("ssp3", M.MOL_BATCHED),
+                                           ("ssp3", M.MOL_PLAIN)])
 @pytest.mark.parametrize("n", [(32, 32, 32), (20, 17, 11)])
-def test_wave_driver_periodic_patch_without_ghost_fill(n):
+def test_wave_driver_periodic_patch_without_ghost_fill(n, scheme, launch):
     """The driver on a wave level that is one periodic patch, stepped with the
     point-wise stage kernel, reads neighbours at the periodic images and
-    skips the ghost fill before each stage: three steps, eager and replayed
-    from a graph, equal the fill + stage sequence through the ABI bit for bit
-    (ghost cells of the end state included) and the oracle within the parity
-    bar; with a z-marching tiling set on the same level (its own periodic
-    image reads, ragged tails included) the state agrees within the bar."""
+    skips the ghost fill before each stage: three steps (RK4 or SSP-RK3,
+    batched or per-patch launches; RK4 batched also replayed from a graph)
+    equal the fill + stage sequence through the ABI bit for bit (ghost cells
+    of the end state included) and the oracle within the parity bar; with a
+    z-marching tiling set on the same level (its own periodic image reads,
+    ragged tails included) the state agrees within the bar."""
     torch = _torch()
-    print("wave periodic driver", n, flush=True)
+    print("wave periodic driver", n, scheme, launch, flush=True)
     dx = 2.0 / n[0]
     dt = 0.25 * dx
     U0 = synth.embed(synth.wave_gaussian(n, (-1, -1, -1), dx, centre=synth.wave_centre(1),
                                          period=(n[0] * dx, n[1] * dx, n[2] * dx)))
     sysd = M.System(M.MOL_WAVE, sigma=0.1)
-    ref_abi = _gpu_steps(O.WAVE, M.MOL_RK4, U0, dx, dt, 3, sysd)
+    ssp = scheme == "ssp3"
+    ref_abi = _gpu_steps(O.WAVE, M.MOL_SSPRK3 if ssp else M.MOL_RK4, U0, dx, dt, 3, sysd)
+    mode_bits = launch | (M.MOL_ADV_SSPRK3 if ssp else 0)
     ps = M.Patchset(M.single_patch(n, (-1, -1, -1), dx), sysd)
     got = []
-    for mode in ("eager", "graph", "zmarch"):
+    modes = ("eager", "graph", "zmarch") if (not ssp and launch == M.MOL_BATCHED) else ("eager", "zmarch")
+    for mode in modes:
         if mode == "zmarch":
             ps.set_tiling(0, (64, 8, 4))
         st = ps.alloc_states()
@@ -114,13 +120,13 @@ def test_wave_driver_periodic_patch_without_ghost_fill(n):
                 g.launch()
         else:
             for _ in range(3):
-                ps.advance(st, dt)
+                ps.advance(st, dt, mode_bits)
         torch.cuda.synchronize()
         got.append(ps.unpack(0, st[0]["U"])[0])
-    for G in got[:2]:
+    for G in got[:-1]:
         assert np.array_equal(G, ref_abi)
-    assert parity_err(got[2], ref_abi).max() <= TOL
-    ref = _oracle_steps(O.WAVE, O.RK4, U0, dx, dt, 3, O.params(sigma=0.1))
+    assert parity_err(got[-1], ref_abi).max() <= TOL
+    ref = _oracle_steps(O.WAVE, O.SSPRK3 if ssp else O.RK4, U0, dx, dt, 3, O.params(sigma=0.1))
     e = parity_err(got[0][:, 3:-3, 3:-3, 3:-3], ref[:, 3:-3, 3:-3, 3:-3])
     assert np.all(e <= TOL), e
 
