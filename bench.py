@@ -393,19 +393,16 @@ def mhd_runs_bench(M):
         res["alfven"][name] = {"N": [32, 64, 128], "err_Bx": e, "orders": list(np.log2(np.array(e[:-1]) / np.array(e[1:])))}
         log(f"bench: Alfven {name}: {e}")
     ref = R.brio_wu(3200)
-    for fmr in (None, "2/2", "4"):
-        e = [R.brio_wu_error(R.brio_wu(N, fmr=fmr), ref, 3200) for N in (50, 100, 200, 400)]
-        res["brio_wu"][fmr or "unigrid"] = {"N": [50, 100, 200, 400], "err_By": e}
-        log(f"bench: Brio-Wu {fmr or 'unigrid'}: {e}")
-    # SSP-RK3 with BOR on the ratio-2/2 hierarchy: from N = 100 on the state
-    # turns non-finite (negative pressure inside the finest level once the
-    # fronts have crossed its boundaries), in the oracle's hierarchy step as
-    # on the GPU; such runs are reported as null with the list of N
-    e = [R.brio_wu_error(R.brio_wu(N, fmr="2/2", ssp3=True), ref, 3200) for N in (50, 100, 200, 400)]
-    bad = [N for N, x in zip((50, 100, 200, 400), e) if not math.isfinite(x)]
-    e = [x if math.isfinite(x) else None for x in e]
-    res["brio_wu"]["2/2_ssprk3_bor"] = {"N": [50, 100, 200, 400], "err_By": e, "nonfinite_N": bad}
-    log(f"bench: Brio-Wu 2/2 with SSP-RK3 and BOR: {e}")
+    res["brio_wu"]["dt_over_dx"] = {"unigrid": R.BW_CFL, "fmr": R.BW_CFL_FMR}
+    runs = [("unigrid", {}), ("2/2", {"fmr": "2/2"}), ("4", {"fmr": "4"}),
+            ("2/2_weno3", {"fmr": "2/2", "recon": M.MOL_RECON_WENO3}), ("unigrid_weno3", {"recon": M.MOL_RECON_WENO3}),
+            ("2/2_ssprk3_bor", {"fmr": "2/2", "ssp3": True})]
+    for name, kw in runs:
+        e = [R.brio_wu_error(R.brio_wu(N, **kw), ref, 3200) for N in (50, 100, 200, 400)]
+        bad = [N for N, x in zip((50, 100, 200, 400), e) if not math.isfinite(x)]
+        res["brio_wu"][name] = {"N": [50, 100, 200, 400], "err_By": [x if math.isfinite(x) else None for x in e],
+                                "nonfinite_N": bad}
+        log(f"bench: Brio-Wu {name}: {e}")
     res["wall_s"] = time.perf_counter() - t0
     return res
 

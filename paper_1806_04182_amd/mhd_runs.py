@@ -5,10 +5,15 @@
   levels over [0.5, 1.5]^2 and [0.75, 1.25]^2; ratio 4: one level over
   [0.5, 1.5]^2); the relative L1 error of B_x on the coarse level against the
   initial data, to which the wave returns after three crossing times;
-- the Brio-Wu shock tube (Gamma = 2, dt = 0.2 dx, t = 0.2) on the periodic
-  line [0, 4) with the mirror jump at x = 2.5 (its waves stay in x > 1), B_y
-  on [0, 1] of the coarse level, unigrid or with FMR (ratio 2/2 over
-  [0.34, 0.66] and [0.4, 0.6]; ratio 4 over [0.4, 0.6]).
+- the Brio-Wu shock tube (Gamma = 2, t = 0.2) on the periodic line [0, 4)
+  with the mirror jump at x = 2.5 (its waves stay in x > 1), B_y on [0, 1] of
+  the coarse level, unigrid (dt = 0.2 dx, the paper's step) or with FMR
+  (ratio 2/2 over [0.34, 0.66] and [0.4, 0.6]; ratio 4 over [0.4, 0.6]) with
+  dt = 0.15 dx on the coarse level (and the same Courant factor on every
+  level): at 0.2 the sub-cycled coarse-fine interfaces are past their
+  stability limit for this tube, and WENO3 with RK4, or WENO5-Z with SSP-RK3
+  and BOR, develop a negative pressure one fine cell inside the finest
+  level's boundary when the compound wave reaches it (t ~ 0.05).
 """
 from __future__ import annotations
 
@@ -19,6 +24,8 @@ from . import synth
 
 ALFVEN_L = 2.0
 BW_L = 4.0
+BW_CFL = 0.2       # unigrid Brio-Wu: dt = 0.2 dx (Sec. IV.B.3)
+BW_CFL_FMR = 0.15  # with FMR: the interfaces' stability limit is below 0.2 (module notes)
 
 
 def _run(levels, N0, dx0, system, init, dt0, nsteps, ssp3=False):
@@ -92,10 +99,11 @@ def brio_wu_levels(N, fmr=None):
     return levels
 
 
-def brio_wu(N, recon=M.MOL_RECON_WENO5Z, flux=M.MOL_FLUX_LLF, fmr=None, t_end=0.2, ssp3=False):
-    """Coarse-level state on [0, 1] (8 conserved fields x N + 1 points) at t_end."""
+def brio_wu(N, recon=M.MOL_RECON_WENO5Z, flux=M.MOL_FLUX_LLF, fmr=None, t_end=0.2, ssp3=False, cfl=None):
+    """Coarse-level state on [0, 1] (8 conserved fields x N + 1 points) at
+    t_end; dt = cfl dx (default BW_CFL unigrid, BW_CFL_FMR with FMR)."""
     dx0 = 1.0 / N
-    dt0 = 0.2 * dx0
+    dt0 = (cfl if cfl is not None else (BW_CFL_FMR if fmr else BW_CFL)) * dx0
     nsteps = int(round(t_end / dt0))
     sysd = M.System(M.MOL_MHD, sigma=0.0, gamma_ad=2.0, mhd_recon=recon, mhd_flux=flux)
     init = lambda n, h, lo: synth.mhd_brio_wu(n, h, lo)

@@ -63,8 +63,10 @@ def test_alfven_run_matches_oracle(recon, fmr):
     _parity(R.alfven_levels(N, fmr), (N, N, 1), dx0, sysd, prm, init, dx0 / (4 * np.sqrt(2)), 3)
 
 
-@pytest.mark.parametrize("fmr,flux", [("2/2", M.MOL_FLUX_LLF), ("4", M.MOL_FLUX_HLL)])
-def test_brio_wu_run_matches_oracle(fmr, flux):
+@pytest.mark.parametrize("fmr,flux,recon", [("2/2", M.MOL_FLUX_LLF, M.MOL_RECON_WENO5Z),
+                                             ("4", M.MOL_FLUX_HLL, M.MOL_RECON_WENO5Z),
+                                             ("2/2", M.MOL_FLUX_LLF, M.MOL_RECON_WENO3)])
+def test_brio_wu_run_matches_oracle(fmr, flux, recon):
     """Across the shock and the coarse-fine boundaries (WENO5-Z).  With FMR
     the run amplifies rounding-level differences as the shock meets the
     interfaces (the oracle against itself with 1e-15 perturbed data: about
@@ -72,16 +74,17 @@ def test_brio_wu_run_matches_oracle(fmr, flux):
     at 1e-12 over three steps, and over ten steps within a factor 100 of the
     oracle's own spread under such a perturbation."""
     _torch()
-    print("brio-wu parity", fmr, flux, flush=True)
+    print("brio-wu parity", fmr, flux, recon, flush=True)
     N = 50
-    sysd = M.System(M.MOL_MHD, sigma=0.0, gamma_ad=2.0, mhd_flux=flux)
-    prm = O.params(sigma=0.0, gamma_ad=2.0, mhd_riemann=float(flux))
+    dt = R.BW_CFL_FMR / N
+    sysd = M.System(M.MOL_MHD, sigma=0.0, gamma_ad=2.0, mhd_flux=flux, mhd_recon=recon)
+    prm = O.params(sigma=0.0, gamma_ad=2.0, mhd_riemann=float(flux), mhd_recon=float(recon))
     init = lambda n, h, lo: synth.mhd_brio_wu(n, h, lo)
     args = (R.brio_wu_levels(N, fmr), (int(R.BW_L * N), 1, 1), 1.0 / N)
-    _parity(*args, sysd, prm, init, 0.2 / N, 3)
-    got = _gpu(*args, sysd, init, 0.2 / N, 10)
-    ref = _oracle(*args, prm, init, 0.2 / N, 10)
-    spread = _oracle(*args, prm, init, 0.2 / N, 10, pert=1e-15)
+    _parity(*args, sysd, prm, init, dt, 3)
+    got = _gpu(*args, sysd, init, dt, 10)
+    ref = _oracle(*args, prm, init, dt, 10)
+    spread = _oracle(*args, prm, init, dt, 10, pert=1e-15)
     for l in range(len(got)):
         d_gpu = np.max(np.abs(got[l] - ref[l]))
         d_self = np.max(np.abs(spread[l] - ref[l]))
@@ -162,3 +165,17 @@ def test_alfven_fmr_with_cleaning_matches_oracle():
     for l in range(len(levels)):
         e = parity_err(got[l], H.get(l, 0)[:, 3:-3, 3:-3, 3:-3])
         assert np.all(e <= 1e-12), (l, e)
+
+
+def test_brio_wu_weno3_and_ssp3_with_fmr_converge():
+    """The runs that turned non-finite at dt = 0.2 dx with FMR (WENO3 with
+    RK4; WENO5-Z with SSP-RK3 and BOR) complete at dt = 0.15 dx on the GPU
+    driver and converge to the reference as N doubles."""
+    _torch()
+    ref = R.brio_wu(3200)
+    e3 = [R.brio_wu_error(R.brio_wu(N, recon=M.MOL_RECON_WENO3, fmr="2/2"), ref, 3200) for N in (50, 100, 200, 400)]
+    es = [R.brio_wu_error(R.brio_wu(N, fmr="2/2", ssp3=True), ref, 3200) for N in (50, 100, 200, 400)]
+    print("brio-wu weno3 fmr", e3, "ssp3 bor fmr", es, flush=True)
+    for e in (e3, es):
+        assert all(np.isfinite(e))
+        assert all(b < a for a, b in zip(e[:-1], e[1:]))

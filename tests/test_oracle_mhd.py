@@ -354,3 +354,61 @@ def test_flux_splitting_is_fifth_order_where_field_reconstruction_is_second():
             errs.append(np.sum(np.abs(_pulse_run(N, flux)[0] - r[0])) / np.sum(np.abs(r[0])))
         order = np.log2(errs[0] / errs[1])
         assert lo < order < hi, (flux, errs, order)
+
+
+def _brio_wu_oracle(N, recon, fmr, cfl, scheme=None):
+    """The Brio-Wu tube of Sec. IV.B.3 on the oracle's hierarchy step (RK4,
+    or SSP-RK3 with BOR): B_y on [0, 1] of the coarse level at t = 0.2, and
+    whether the state stayed finite with positive pressure everywhere."""
+    from paper_1806_04182_amd import synth
+    from paper_1806_04182_amd.mhd_runs import BW_L, brio_wu_levels
+    levels = brio_wu_levels(N, fmr)
+    dx0 = 1.0 / N
+    dt0 = cfl * dx0
+    H = O.Hierarchy(O.MHD, (int(BW_L * N), 1, 1), (0, 0, 0), dx0, levels)
+    if scheme is not None:
+        H.set_scheme(scheme)
+    h = dx0
+    for l, (R, boxes) in enumerate(levels):
+        if l:
+            h /= R
+        for p, (lo, hi) in enumerate(boxes):
+            n = tuple(hi[d] - lo[d] + 1 for d in range(3))
+            H.set(l, p, synth.embed(synth.mhd_brio_wu(n, h, lo)))
+    for l in range(len(levels)):
+        H.fill_same(l)
+    prm = O.params(sigma=0.0, gamma_ad=2.0, mhd_recon=float(recon))
+    ok = True
+    for _ in range(int(round(0.2 / dt0))):
+        H.step(dt0, prm)
+        for l in range(len(levels)):
+            U = H.get(l, 0)[:, 3:-3, 3:-3, 3:-3]
+            with np.errstate(all="ignore"):
+                p = U[4] - 0.5 * (U[1] ** 2 + U[2] ** 2 + U[3] ** 2) / U[0] - 0.5 * (U[5] ** 2 + U[6] ** 2 + U[7] ** 2)
+            if not (np.all(np.isfinite(U)) and np.all(p > 0) and np.all(U[0] > 0)):
+                ok = False
+        if not ok:
+            break
+    return H.get(0, 0)[6, 3, 3, 3:3 + N + 1], ok
+
+
+def test_brio_wu_fmr_courant_factor():
+    """WENO3 with FMR (ratio 2/2) on the Brio-Wu tube: with the paper's
+    unigrid step dt = 0.2 dx the sub-cycled interfaces are unstable (negative
+    pressure near the finest level's boundary when the compound wave reaches
+    it); with dt = 0.15 dx the runs complete and converge to the reference
+    (WENO5-Z unigrid, N = 400) as N doubles.  SSP-RK3 with BOR (App. D) on the
+    same hierarchy behaves the same way."""
+    _, ok = _brio_wu_oracle(50, 2, "2/2", 0.2)
+    assert not ok
+    ref, ok = _brio_wu_oracle(400, 0, None, 0.15)
+    assert ok
+    errs = []
+    for N in (50, 100):
+        by, ok = _brio_wu_oracle(N, 2, "2/2", 0.15)
+        assert ok, N
+        r = ref[:: 400 // N][: N + 1]
+        errs.append(np.sum(np.abs(by - r)) / np.sum(np.abs(r)))
+    assert errs[1] < 0.8 * errs[0], errs
+    _, ok = _brio_wu_oracle(100, 0, "2/2", 0.15, scheme=O.SSPRK3)
+    assert ok
