@@ -304,6 +304,75 @@ def stage_kernel_time(ps, M, st, scheme, dt, reps=10):
     return e0.elapsed_time(e1) / (reps * len(seq))
 
 
+# Workloads whose stage kernel is profiled alone (rocprofv3 counters): system,
+# points per axis, scheme, the data the benchmark gives them
+PROFILE_CASES = {"ccz4_96": ("ccz4", 96), "wave_256": ("wave", 256), "wave_512": ("wave", 512),
+                 "mhd_128": ("mhd", 128)}
+
+
+def _single_patch_case(M, system, n):
+    """Patchset, states, scheme and dt of the benchmark's single-patch
+    workloads, with their data in place."""
+    import torch
+    from paper_1806_04182_amd import synth
+    if system == "ccz4":
+        dx = 2.0 / n
+        ps = M.Patchset(M.single_patch((n, n, n), (-1, -1, -1), dx), M.System(M.MOL_CCZ4))
+        st = ps.alloc_states()
+        st[0]["U"].copy_(torch.from_numpy(ps.pack(0, [synth.embed(
+            synth.ccz4_minkowski_noise((n, n, n), amp=1e-10, seed=0))])))
+        return ps, st, M.MOL_RK4, 0.25 * dx
+    if system == "wave":
+        dx = 2.0 / n
+        ps = M.Patchset(M.single_patch((n, n, n), (-1, -1, -1), dx), M.System(M.MOL_WAVE, sigma=0.1))
+        st = ps.alloc_states()
+        ps.wave_gaussian(0, [1.0, 0.2, *synth.wave_centre(0)], st[0]["U"])
+        return ps, st, M.MOL_RK4, 0.25 * dx
+    dx = 1.0 / n
+    ps = M.Patchset(M.single_patch((n, n, n), (0, 0, 0), dx), M.System(M.MOL_MHD, sigma=0.0))
+    st = ps.alloc_states()
+    st[0]["U"].copy_(torch.from_numpy(ps.pack(0, [synth.embed(synth.mhd_ot_like((n, n, n), seed=0))])))
+    return ps, st, M.MOL_SSPRK3, 0.2 * dx
+
+
+def profile_case(M, name):
+    system, n = PROFILE_CASES[name]
+    ps, st, scheme, dt = _single_patch_case(M, system, n)
+    kms = stage_kernel_time(ps, M, st, scheme, dt, reps=5)
+    return {"case": name, "points": n ** 3, "stage_kernel_ms": kms}
+
+
+def profile_record(case, pts):
+    """The committed rocprofv3 counter record of one workload's stage kernel
+    (HBM bytes per launch, FP64 FLOP per point-stage), or None when the
+    kernel sources changed since it was taken or the workload differs."""
+    from paper_1806_04182_amd import profsum
+    path = os.path.join(ROOT, "profiles", profsum.CASES[case]["file"])
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != profsum.source_hash(profsum.CASES[case]["sources"]) or rec.get("points") != pts:
+        return None
+    return rec
+
+
+def _counter_fields(case, pts, kms, alg_bytes_per_pt):
+    """Counter-based HBM traffic and FP64 rate of a stage kernel beside its
+    algorithmic bytes, from the committed record (None entries when stale)."""
+    from paper_1806_04182_amd import profsum
+    rec = profile_record(case, pts)
+    if rec is None:
+        return {"counter_record": None}
+    tf = rec["fp64_flop_per_pt_stage"] * pts / (kms * 1e-3) / 1e12
+    return {"counter_record": "profiles/" + profsum.CASES[case]["file"],
+            "counter_bytes_per_pt_stage": rec["hbm_bytes_per_launch"] / pts,
+            "traffic_over_algorithmic": rec["hbm_bytes_per_launch"] / (alg_bytes_per_pt * pts),
+            "roofline_fp64": {"bound": "alu", "achieved": tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                              "frac": tf / FP64_PEAK_TFLOPS, "flop_per_pt_stage": rec["fp64_flop_per_pt_stage"],
+                              "flop_count": "executed (SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes)"}}
+
+
 def wave_mhd_bench(M):
     """Secondary paths: the scalar wave (32^3, 20 steps; and 256^3, where the
     state is far larger than the caches) and MHD (128^3, SSP-RK3)."""
@@ -334,6 +403,8 @@ def wave_mhd_bench(M):
         out[f"wave_{n}^3"] = {"pt_stage_per_s": n ** 3 * 4 / (ms * 1e-3), "ms_per_step": ms,
                                "stage_kernel_ms": kms, "stage_kernel_GBs_algorithmic": gbs,
                                "hbm_frac": gbs / HBM_PEAK_GBS, "bytes_per_pt_stage": 68.0}
+        if f"wave_{n}" in PROFILE_CASES:
+            out[f"wave_{n}^3"].update(_counter_fields(f"wave_{n}", n ** 3, kms, 68.0))
         tuned = ps.autotune(0, st[0], 0.25 * dx, reps=3)
         tkms = stage_kernel_time(ps, M, st, M.MOL_RK4, 0.25 * dx)
         out[f"wave_{n}^3"]["autotuned"] = {"tiling": tuned, "stage_kernel_ms": tkms,
@@ -361,6 +432,7 @@ def wave_mhd_bench(M):
     out["mhd_128^3"] = {"pt_stage_per_s": n ** 3 / (kms * 1e-3), "stage_kernel_ms": kms,
                         "stage_kernel_GBs_algorithmic": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
                         "bytes_per_pt_stage": 171.0}
+    out["mhd_128^3"].update(_counter_fields("mhd_128", n ** 3, kms, 171.0))
     tuned = ps.autotune(0, st[0], 0.2 * dx, reps=3)
     st[0]["U"].copy_(torch.from_numpy(ps.pack(0, [synth.embed(synth.mhd_ot_like((n, n, n), seed=0))])))
     out["mhd_128^3"]["autotuned"] = {"tiling": tuned,
@@ -419,7 +491,9 @@ def main():
     ap.add_argument("--no-fmr", action="store_true",
                     help="skip the FMR reflection, MHD and AMR wave test runs (many small launches; kept out of kernel traces)")
     ap.add_argument("--paths-only", action="store_true",
-                    help="measure only the wave and MHD paths and print their JSON (for profiling)")
+                    help="measure only the wave and MHD paths and print their JSON")
+    ap.add_argument("--profile-case", choices=sorted(PROFILE_CASES),
+                    help="run only the stage-kernel timing of one workload (for counter collection)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
@@ -435,6 +509,9 @@ def main():
     assert torch.cuda.is_available(), "no GPU"
     if args.paths_only:
         print(json.dumps(wave_mhd_bench(M)), flush=True)
+        return
+    if args.profile_case:
+        print(json.dumps(profile_case(M, args.profile_case)), flush=True)
         return
     n = args.n
     dx = 2.0 / n
@@ -514,7 +591,7 @@ def main():
                      "kernel": "ccz4_stage_kernel", "kernel_ms": kms,
                      "bytes_per_pt_stage": CCZ4_BYTES_PER_PT_STAGE},
     }
-    rec = ccz4_profile_record(pts)
+    rec = profile_record("ccz4_96", pts)
     if rec is not None:
         res["roofline"]["traffic"] = rec["hbm_bytes_per_launch"]
         # the same kernel against the FP64 vector peak, with the executed FP64
@@ -545,21 +622,6 @@ def main():
         res["cpu_baseline"]["host_cpu"] = _cpu_name()
         res["cpu_baseline"]["nproc"] = os.cpu_count()
     print(json.dumps(res), flush=True)
-
-
-def ccz4_profile_record(pts):
-    """The committed rocprofv3 counter record of the CCZ4 stage kernel (HBM
-    bytes per launch, FP64 FLOP per point-stage), or None when the kernel
-    sources changed since it was taken or the workload differs."""
-    from paper_1806_04182_amd import profsum
-    path = os.path.join(ROOT, "profiles", "ccz4_stage_96cube_traffic.json")
-    try:
-        rec = json.load(open(path))
-    except (OSError, ValueError):
-        return None
-    if rec.get("source_sha256") != profsum.ccz4_source_hash() or rec.get("points") != pts:
-        return None
-    return rec
 
 
 def _cpu_name():

@@ -1,22 +1,22 @@
 """Summaries of rocprofv3 output for the measurement record.
 
-`python -m paper_1806_04182_amd.profsum <outdir>` reads the rocprofv3 CSV
-folders written by the profiling commands listed in the generated files
-(under <outdir>: ktrace; pmc_FETCH_SIZE, pmc_WRITE_SIZE, pmc_FLOPS for the
-CCZ4 benchmark and the same with suffix _paths for the wave and MHD paths;
-copy_FETCH_SIZE, copy_WRITE_SIZE) and writes, under profiles/:
+`python -m paper_1806_04182_amd.profsum <outdir> [<dest>]` reads the rocprofv3 CSV
+folders written by the profiling commands listed in <outdir>/commands.json
+(ktrace: the kernel trace of the benchmark; pmc_<COUNTER>_<case>: one counter
+over `bench.py --profile-case <case>`, which runs only one workload's stage
+kernel; copy_FETCH_SIZE, copy_WRITE_SIZE: a plain 1 GiB device copy) and
+writes, under <dest> (default profiles/):
 
   stage_kernels_kernel_trace.md   per-kernel duration statistics
-  stage_kernels_counters.md       HBM bytes and FP64 FLOP per dispatch,
-                                  grouped by kernel and grid size
-  ccz4_stage_96cube_traffic.json  the record bench.py reads for the CCZ4
-                                  stage kernel (tied to the kernel sources
-                                  by a hash)
+  stage_kernels_counters.md       HBM bytes and FP64 FLOP per dispatch of
+                                  every workload's stage kernel
+  <case record>.json              the record bench.py reads per workload
+                                  (tied to the kernel sources by a hash)
 
 HBM bytes: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by the ratio
-of the known size of a plain 1 GiB device copy to what the same counter
-reads for it.  FP64 FLOP: SQ_INSTS_VALU_FLOPS_FP64 counts per wave
-instruction, so it is multiplied by the 64 lanes of a wave.
+of the known size of the 1 GiB copy to what the same counter reads for it.
+FP64 FLOP: SQ_INSTS_VALU_FLOPS_FP64 counts per wave instruction, so it is
+multiplied by the 64 lanes of a wave.
 """
 from __future__ import annotations
 
@@ -29,18 +29,37 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-CCZ4_SOURCES = ("k_ccz4.hip", "k_common.h", "molamr_int.h")
+COMMON = ("k_common.h", "molamr_int.h")
+CCZ4_SOURCES = ("k_ccz4.hip",) + COMMON
 COPY_BYTES = 1 << 30
-CCZ4_POINTS = 96 ** 3
+COUNTERS = ("FETCH_SIZE", "WRITE_SIZE", "SQ_INSTS_VALU_FLOPS_FP64")
+
+# per workload: the stage kernel's name prefix, its points, the sources that
+# determine it, the record file and a description
+CASES = {
+    "ccz4_96": {"prefix": "mol::ccz4_stage_kernel", "points": 96 ** 3, "sources": CCZ4_SOURCES,
+                "file": "ccz4_stage_96cube_traffic.json", "workload": "ccz4 96^3 periodic patch, RK4 stages 1-4"},
+    "wave_256": {"prefix": "mol::wave_", "points": 256 ** 3, "sources": ("k_wave.hip",) + COMMON,
+                 "file": "wave_stage_256cube_traffic.json", "workload": "wave 256^3 periodic patch, RK4 stages 1-4"},
+    "wave_512": {"prefix": "mol::wave_", "points": 512 ** 3, "sources": ("k_wave.hip",) + COMMON,
+                 "file": "wave_stage_512cube_traffic.json", "workload": "wave 512^3 periodic patch, RK4 stages 1-4"},
+    "mhd_128": {"prefix": "mol::mhd_stage_kernel", "points": 128 ** 3, "sources": ("k_mhd.hip",) + COMMON,
+                "file": "mhd_stage_128cube_traffic.json",
+                "workload": "mhd 128^3 periodic patch (WENO5-Z, LLF), SSP-RK3 stages 1-3"},
+}
 
 
-def ccz4_source_hash() -> str:
-    """Hash of the sources that determine the CCZ4 stage kernel."""
+def source_hash(files) -> str:
+    """Hash of the sources that determine a stage kernel."""
     h = hashlib.sha256()
-    for f in CCZ4_SOURCES:
+    for f in files:
         with open(os.path.join(HERE, "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def ccz4_source_hash() -> str:
+    return source_hash(CCZ4_SOURCES)
 
 
 def _rows(folder):
@@ -95,50 +114,54 @@ def kernel_trace_md(folder, cmd):
     return "\n".join(out) + "\n"
 
 
-def main(outdir):
-    prof = os.path.join(ROOT, "profiles")
+def main(outdir, prof=os.path.join(ROOT, "profiles")):
+    os.makedirs(prof, exist_ok=True)
     cmds = json.load(open(os.path.join(outdir, "commands.json")))
     with open(os.path.join(prof, "stage_kernels_kernel_trace.md"), "w") as fh:
         fh.write(kernel_trace_md(os.path.join(outdir, "ktrace"), cmds["ktrace"]))
     fscale = copy_scale(os.path.join(outdir, "copy_FETCH_SIZE"), "FETCH_SIZE", COPY_BYTES / 1024)
     wscale = copy_scale(os.path.join(outdir, "copy_WRITE_SIZE"), "WRITE_SIZE", COPY_BYTES / 1024)
-    fetch, write, flops = {}, {}, {}
-    for tag in ("", "_paths"):
-        fetch.update(counter_means(os.path.join(outdir, "pmc_FETCH_SIZE" + tag), "FETCH_SIZE"))
-        write.update(counter_means(os.path.join(outdir, "pmc_WRITE_SIZE" + tag), "WRITE_SIZE"))
-        flops.update(counter_means(os.path.join(outdir, "pmc_FLOPS" + tag), "SQ_INSTS_VALU_FLOPS_FP64"))
-    lines = ["# HBM bytes and FP64 FLOP per dispatch (rocprofv3 counters)", "", "Commands (one counter per run):", ""]
-    lines += ["    " + cmds[k] for k in ("fetch", "write", "flops", "fetch_paths", "write_paths", "flops_paths",
-                                          "copy_fetch", "copy_write")]
-    lines += ["", f"Copy calibration (1 GiB device copy): FETCH_SIZE scale {fscale:.3f}, WRITE_SIZE scale {wscale:.3f}.",
-              "", "| kernel | grid | dispatches | HBM read (MB) | HBM write (MB) | FP64 GFLOP |", "|---|---|---|---|---|---|"]
-    for key in sorted(set(fetch) | set(write) | set(flops)):
-        if key[0].startswith("at::") or "rocclr" in key[0]:
+    lines = ["# HBM bytes and FP64 FLOP per dispatch of the stage kernels (rocprofv3 counters)", "",
+             "Commands (one counter per run, each over `bench.py --profile-case <case>`, which times only that",
+             "workload's stage kernel, 5 cycles of the scheme's stages after one warm-up cycle):", ""]
+    lines += ["    " + cmds[k] for k in sorted(cmds) if k != "ktrace"]
+    lines += ["", f"Copy calibration (1 GiB device copy): FETCH_SIZE scale {fscale:.3f}, "
+                  f"WRITE_SIZE scale {wscale:.3f}.", "",
+              "| case | kernel | grid | dispatches | HBM read (MB) | HBM write (MB) | B per point | FP64 FLOP per point |",
+              "|---|---|---|---|---|---|---|---|"]
+    records = {}
+    for case, c in CASES.items():
+        got = {}
+        for ctr in COUNTERS:
+            folder = os.path.join(outdir, f"pmc_{ctr}_{case}")
+            if not os.path.isdir(folder):
+                break
+            got[ctr] = {k: v for k, v in counter_means(folder, ctr).items() if k[0].startswith(c["prefix"])}
+        if len(got) != len(COUNTERS):
             continue
-        n = fetch.get(key, (0, 0))[0]
-        rd = fetch.get(key, (0, float("nan")))[1] * 1024 * fscale / 1e6
-        wr = write.get(key, (0, float("nan")))[1] * 1024 * wscale / 1e6
-        fl = flops.get(key, (0, float("nan")))[1] * 64 / 1e9
-        lines.append(f"| {key[0]} | {key[1]} | {n} | {rd:.1f} | {wr:.1f} | {fl:.3f} |")
+        # the stage kernel is the one dispatched most often in the case's run
+        key = max(got["FETCH_SIZE"], key=lambda k: got["FETCH_SIZE"][k][0])
+        n, fr = got["FETCH_SIZE"][key]
+        wr = got["WRITE_SIZE"][key][1]
+        fl = got["SQ_INSTS_VALU_FLOPS_FP64"][key][1] * 64
+        rd_b, wr_b = fr * 1024 * fscale, wr * 1024 * wscale
+        pts = c["points"]
+        lines.append(f"| {case} | {key[0]} | {key[1]} | {n} | {rd_b / 1e6:.1f} | {wr_b / 1e6:.1f} | "
+                     f"{(rd_b + wr_b) / pts:.1f} | {fl / pts:.1f} |")
+        rec = {"kernel": key[0], "grid": key[1], "workload": c["workload"], "points": pts,
+               "source_sha256": source_hash(c["sources"]), "dispatches": n,
+               "fetch_kib_per_dispatch_raw": fr, "write_kib_per_dispatch_raw": wr,
+               "fetch_scale": fscale, "write_scale": wscale,
+               "hbm_bytes_per_launch": rd_b + wr_b,
+               "fp64_flop_per_launch": fl, "fp64_flop_per_pt_stage": fl / pts,
+               "command": cmds.get(f"FETCH_SIZE_{case}", "")}
+        with open(os.path.join(prof, c["file"]), "w") as fh:
+            json.dump(rec, fh, indent=1)
+        records[case] = rec
     with open(os.path.join(prof, "stage_kernels_counters.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
-    # the CCZ4 96^3 stage kernel: its grid is the tile count of one 96^3 patch
-    ck = [k for k in fetch if k[0].startswith("mol::ccz4_stage_kernel") and k[1] == CCZ4_POINTS]
-    assert len(ck) == 1, ck
-    k = ck[0]
-    rec = {
-        "kernel": k[0], "workload": "ccz4 96^3 periodic patch, RK4 stages 1-4", "points": CCZ4_POINTS,
-        "source_sha256": ccz4_source_hash(), "dispatches": fetch[k][0],
-        "fetch_kib_per_dispatch_raw": fetch[k][1], "write_kib_per_dispatch_raw": write[k][1],
-        "fetch_scale": fscale, "write_scale": wscale,
-        "hbm_bytes_per_launch": fetch[k][1] * 1024 * fscale + write[k][1] * 1024 * wscale,
-        "fp64_flop_per_launch": flops[k][1] * 64,
-        "fp64_flop_per_pt_stage": flops[k][1] * 64 / CCZ4_POINTS,
-    }
-    with open(os.path.join(prof, "ccz4_stage_96cube_traffic.json"), "w") as fh:
-        json.dump(rec, fh, indent=1)
-    print(json.dumps(rec, indent=1))
+    print(json.dumps(records, indent=1))
 
 
 if __name__ == "__main__":
-    main(sys.argv[1])
+    main(*sys.argv[1:3])
