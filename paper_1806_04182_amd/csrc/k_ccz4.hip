@@ -95,7 +95,20 @@ struct CczLds {
     static constexpr int LW = 16, PP = (NT / LW) / HY, NR = (HZ + PP - 1) / PP;
     static_assert(HX <= LW && PP >= 1 && HZ % PP == 0, "halo tile does not fit the load pattern");
     static constexpr int LV = PX * HY * HZ;
+    // Cross of a single-axis field: the tile's columns over all HZ planes
+    // (z slab, NT / (TX TY) planes per pass) and, on the tile's own planes,
+    // the three points beyond each x face and each y face (wings)
+    static constexpr int ZS = TX * TY * HZ, NZ = (ZS + NT - 1) / NT, ZPP = NT / (TX * TY);
+    static constexpr int XW = 2 * G * TY * TZ, YW = 2 * G * TX * TZ, NW = (XW + YW + NT - 1) / NT;
+    static_assert(NT % (TX * TY) == 0 && NZ + NW <= NR, "cross does not fit the load pattern");
 };
+
+// fields whose stencils read only along the axes through the point (first
+// derivatives, advection, dissipation): their halo corners are never read
+__device__ constexpr bool single_axis(int f)
+{
+    return (f >= KH && f < GH + 3) || f == TH || (f >= BB && f < BB + 3);
+}
 
 // One tile of the stage: the right-hand side of every interior point of tile
 // tidx and its stage update.  buf: the halo tile of the field passing
@@ -140,6 +153,58 @@ __device__ __forceinline__ void ccz4_tile(const StageArgs& a, const CczConst& C,
 #pragma unroll
         for (int r = 0; r < NR; ++r)
             if (lane) buf[ll + r * PP * HY * PX] = stg[r];
+    };
+    // the cross of a single-axis field (fewer loads than the box): z-slab
+    // element tid + r NT is column (zx, zy) of plane zz + r ZPP; wing element
+    // e = tid + r NT is decoded per pass.  Elements outside the ghosted box
+    // load from the tile origin and are never read.
+    constexpr int ZS = L::ZS, NZ = L::NZ, ZPP = L::ZPP, XW = L::XW, YW = L::YW, NW = L::NW;
+    const int zx = tid % TX + G, zy = (tid / TX) % TY + G, zz = tid / (TX * TY);
+    const bool zin = tile.o[0] + zx < P.n[0] + 2 * G && tile.o[1] + zy < P.n[1] + 2 * G;
+    auto wing = [&](int e, int& hx, int& hy, int& hz) __attribute__((always_inline)) {
+        if (e < XW) {
+            const int w = e % (2 * G), r = e / (2 * G);
+            hx = w < G ? w : w + TX;
+            hy = r % TY + G;
+            hz = r / TY + G;
+        } else {
+            const int e2 = e - XW, r = e2 / TX, w = r % (2 * G);
+            hx = e2 % TX + G;
+            hy = w < G ? w : w + TY;
+            hz = r / (2 * G) + G;
+        }
+    };
+    auto gload_x = [&](int f) __attribute__((always_inline)) {
+        const double* src = a.Us + hbase + (int64_t)f * fs;
+#pragma unroll
+        for (int r = 0; r < NZ; ++r) {
+            const int hz = zz + r * ZPP;
+            const bool ok = zin && hz < HZ && hz < hzmax;
+            stg[r] = src[ok ? hz * P.pitch_z + zy * P.pitch_y + zx : 0];
+        }
+#pragma unroll
+        for (int r = 0; r < NW; ++r) {
+            const int e = tid + r * NT;
+            int hx, hy, hz;
+            wing(e, hx, hy, hz);
+            const bool ok = e < XW + YW && tile.o[0] + hx < P.n[0] + 2 * G && tile.o[1] + hy < P.n[1] + 2 * G &&
+                            hz < hzmax;
+            stg[NZ + r] = src[ok ? hz * P.pitch_z + hy * P.pitch_y + hx : 0];
+        }
+    };
+    auto lstore_x = [&]() __attribute__((always_inline)) {
+#pragma unroll
+        for (int r = 0; r < NZ; ++r) {
+            const int hz = zz + r * ZPP;
+            if (ZS % NT == 0 || hz < HZ) buf[(hz * HY + zy) * PX + zx] = stg[r];
+        }
+#pragma unroll
+        for (int r = 0; r < NW; ++r) {
+            const int e = tid + r * NT;
+            int hx, hy, hz;
+            wing(e, hx, hy, hz);
+            if ((XW + YW) % NT == 0 || e < XW + YW) buf[(hz * HY + hy) * PX + hx] = stg[NZ + r];
+        }
     };
 
     // ---- point values needed from the first pass on (global loads) ----
@@ -188,7 +253,12 @@ __device__ __forceinline__ void ccz4_tile(const StageArgs& a, const CczConst& C,
     auto pass = [&](auto qc) __attribute__((always_inline)) {
         constexpr int q = decltype(qc)::value;
         constexpr int f = ORDER[q];
-        if constexpr (q + 1 < NF) gload(ORDER[q + 1]);
+        if constexpr (q + 1 < NF) {
+            if constexpr (single_axis(ORDER[q + 1]))
+                gload_x(ORDER[q + 1]);
+            else
+                gload(ORDER[q + 1]);
+        }
         if (valid) {
             const double* t = &buf[((tz + G) * HY + ty + G) * PX + tx + G];
             // advection beta^k d_k and KO dissipation of every field; first
@@ -410,7 +480,10 @@ __device__ __forceinline__ void ccz4_tile(const StageArgs& a, const CczConst& C,
         }
         __syncthreads();
         if constexpr (q + 1 < NF) {
-            lstore();
+            if constexpr (single_axis(ORDER[q + 1]))
+                lstore_x();
+            else
+                lstore();
             __syncthreads();
         }
     };
