@@ -918,9 +918,20 @@ bool level_wraps(const mol_patchset* ps, int l)
            lev.pd[0].n[0] >= 4 && lev.pd[0].n[1] >= 4 && lev.pd[0].n[2] >= 4;
 }
 
+// a CCZ4 level that is one periodic patch (the whole domain, no finer level,
+// at least 2G points per axis): its stage kernel writes the periodic ghost
+// images of its output, so the driver fills ghosts only before the first
+// stage of a step (the caller's U)
+bool level_images(const mol_patchset* ps, int l)
+{
+    const auto& lev = ps->L[l];
+    return ps->sp.system == MOL_CCZ4 && l == 0 && ps->nlev == 1 && !ps->open && lev.pd.size() == 1 &&
+           lev.pd[0].n[0] >= 2 * G && lev.pd[0].n[1] >= 2 * G && lev.pd[0].n[2] >= 2 * G;
+}
+
 int stage_impl(mol_patchset* ps, int level, int mode, int stage, double dt, const double* Un,
                const double* Us, double* acc, double* out, double* kst, hipStream_t st, int plain,
-               bool wrap = false)
+               bool wrap = false, bool images = false)
 {
     Level& lev = ps->L[level];
     SysParams sp = level_params(ps, level);
@@ -936,6 +947,7 @@ int stage_impl(mol_patchset* ps, int level, int mode, int stage, double dt, cons
     a.kst = kst;
     a.stream = lev.nelems * (int64_t)sizeof(double) >= (int64_t(128) << 20);
     a.wrap = wrap ? 1 : 0;
+    a.images = images ? 1 : 0;
     if (!plain) {
         a.tiles = lev.tiles.dev.p;
         a.ntiles = (int)lev.tiles.dev.n;
@@ -1035,17 +1047,20 @@ int advance_level(mol_patchset* ps, const mol_level_state* st, int l, int r, dou
     // level, at least 4 points per axis) reads its stencil neighbours at the
     // periodic images: no ghost fill before its stages
     const bool wrap = level_wraps(ps, l);
+    // a CCZ4 level that is one periodic patch: every stage writes the ghost
+    // images of its output, so only the caller's U is filled (first stage)
+    const bool images = level_images(ps, l);
     int rc;
     for (int sidx = 0; sidx < nst; ++sidx) {
         double* Us = stage_in[sidx];
-        if (!wrap && (rc = fill_impl(ps, l, Us, nf, s, plain))) return rc;
+        if (!wrap && !(images && sidx > 0) && (rc = fill_impl(ps, l, Us, nf, s, plain))) return rc;
         if (l > 0) {
             const mol_level_state& P = st[l - 1];
             const double* kc[4] = {P.k[0], P.k[1], P.k[2], P.k[3]};
             if ((rc = prolong_impl(ps, l, r, sidx + 1, P.U, kc, Us, s, plain, tmode))) return rc;
         }
         if ((rc = stage_impl(ps, l, ssp ? ST_SSP3 : ST_RK4, sidx + 1, dt, X.U, Us, X.acc, stage_out[sidx],
-                             kids ? X.k[sidx] : nullptr, s, plain, wrap)))
+                             kids ? X.k[sidx] : nullptr, s, plain, wrap, images)))
             return rc;
     }
     if (kids) {
@@ -1058,7 +1073,7 @@ int advance_level(mol_patchset* ps, const mol_level_state* st, int l, int r, dou
                                       hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
     }
-    return fill_impl(ps, l, X.U, nf, s, plain);
+    return images ? MOL_OK : fill_impl(ps, l, X.U, nf, s, plain);
 }
 
 int check_states(const mol_patchset* ps, const mol_level_state* st)

@@ -514,7 +514,27 @@ __device__ __forceinline__ void ccz4_tile(const StageArgs& a, const CczConst& C,
     const double divb = db[0][0] + db[1][1] + db[2][2];
     const double Zda = Z[0] * dalp[0] + Z[1] * dalp[1] + Z[2] * dalp[2];
     const double Kt = Kh + 2.0 * Th;
-    auto out = [&](int f, double phys) __attribute__((always_inline)) { stage_store(a, c + (int64_t)f * fs, phys + akx[f][tid]); };
+    // periodic ghost images of this point in the output (a.images): per axis
+    // the offset to the image, 0 when the point is not within G of a face
+    int64_t im[3] = {0, 0, 0};
+    if (a.images) {
+        const int q[3] = {tile.o[0] + tx, tile.o[1] + ty, tile.o[2] + tz};
+        const int64_t sd[3] = {1, P.pitch_y, P.pitch_z};
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            im[d] = q[d] < G ? (int64_t)P.n[d] * sd[d] : (q[d] >= P.n[d] - G ? -(int64_t)P.n[d] * sd[d] : 0);
+    }
+    const bool img = (im[0] | im[1] | im[2]) != 0;
+    auto out = [&](int f, double phys) __attribute__((always_inline)) {
+        const int64_t idx = c + (int64_t)f * fs;
+        const double v = stage_value(a, idx, phys + akx[f][tid], stage_load(a, idx));
+        a.out[idx] = v;
+        if (img)
+#pragma unroll
+            for (int m = 1; m < 8; ++m)
+                if (((m & 1) == 0 || im[0]) && ((m & 2) == 0 || im[1]) && ((m & 4) == 0 || im[2]))
+                    a.out[idx + ((m & 1) ? im[0] : 0) + ((m & 2) ? im[1] : 0) + ((m & 4) ? im[2] : 0)] = v;
+    };
 
     // d_t gt_ij
 #pragma unroll

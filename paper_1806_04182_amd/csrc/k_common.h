@@ -83,42 +83,34 @@ __device__ __forceinline__ StageIn stage_load(const StageArgs& a, int64_t idx)
 }
 
 // k = dt * rhs, then the RK4 (Table RK44, accumulator form) or SSP-RK3
-// (Shu-Osher form of the App. D scheme) stage update, or plain rhs output.
+// (Shu-Osher form of the App. D scheme) stage update, or plain rhs output:
+// writes acc (and k) at idx and returns the value of the output at idx.
 template <bool NT = false>
-__device__ __forceinline__ void stage_apply(const StageArgs& a, int64_t idx, double rhs, const StageIn& v)
+__device__ __forceinline__ double stage_value(const StageArgs& a, int64_t idx, double rhs, const StageIn& v)
 {
-    if (a.mode == ST_RHS) {
-        mem_st<NT>(&a.out[idx], rhs);
-        return;
-    }
+    if (a.mode == ST_RHS) return rhs;
     const double k = a.dt * rhs;
     if (a.kst) mem_st<NT>(&a.kst[idx], k);
     const double un = v.un;
     if (a.mode == ST_RK4) {
         switch (a.stage) {
-        case 1:
-            mem_st<NT>(&a.acc[idx], k * (1.0 / 6.0));
-            mem_st<NT>(&a.out[idx], un + 0.5 * k);
-            break;
-        case 2:
-            mem_st<NT>(&a.acc[idx], v.ac + k * (1.0 / 3.0));
-            mem_st<NT>(&a.out[idx], un + 0.5 * k);
-            break;
-        case 3:
-            mem_st<NT>(&a.acc[idx], v.ac + k * (1.0 / 3.0));
-            mem_st<NT>(&a.out[idx], un + k);
-            break;
-        default:
-            mem_st<NT>(&a.out[idx], un + (v.ac + k * (1.0 / 6.0)));
-            break;
-        }
-    } else {
-        switch (a.stage) {
-        case 1: mem_st<NT>(&a.out[idx], un + k); break;
-        case 2: mem_st<NT>(&a.out[idx], 0.75 * un + 0.25 * (v.us + k)); break;
-        default: mem_st<NT>(&a.out[idx], (1.0 / 3.0) * un + (2.0 / 3.0) * (v.us + k)); break;
+        case 1: mem_st<NT>(&a.acc[idx], k * (1.0 / 6.0)); return un + 0.5 * k;
+        case 2: mem_st<NT>(&a.acc[idx], v.ac + k * (1.0 / 3.0)); return un + 0.5 * k;
+        case 3: mem_st<NT>(&a.acc[idx], v.ac + k * (1.0 / 3.0)); return un + k;
+        default: return un + (v.ac + k * (1.0 / 6.0));
         }
     }
+    switch (a.stage) {
+    case 1: return un + k;
+    case 2: return 0.75 * un + 0.25 * (v.us + k);
+    default: return (1.0 / 3.0) * un + (2.0 / 3.0) * (v.us + k);
+    }
+}
+
+template <bool NT = false>
+__device__ __forceinline__ void stage_apply(const StageArgs& a, int64_t idx, double rhs, const StageIn& v)
+{
+    mem_st<NT>(&a.out[idx], stage_value<NT>(a, idx, rhs, v));
 }
 
 __device__ __forceinline__ void stage_store(const StageArgs& a, int64_t idx, double rhs)

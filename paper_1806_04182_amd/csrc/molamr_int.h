@@ -133,6 +133,12 @@ struct StageArgs {
     // wave stage kernels then read stencil neighbours at the periodic images
     // of interior points and the ghost fill before the stage is skipped
     int wrap;
+    // 1 when the driver steps a CCZ4 level that is one periodic patch of at
+    // least 2G points per axis: the stage kernel also writes its output at
+    // the periodic ghost images of every point within G of a face (faces,
+    // edges, corners), which is what the ghost fill would copy there, and
+    // the fill after the stage is skipped
+    int images;
 };
 
 // kernel launchers (each returns hipGetLastError() of its launch)

@@ -249,6 +249,47 @@ def test_ccz4_rk4_parity(n, kind, upwind):
     assert np.all(e <= TOL), e
 
 
+@pytest.mark.parametrize("scheme,launch", [("rk4", M.MOL_BATCHED), ("rk4", M.MOL_PLAIN), ("ssp3", M.MOL_BATCHED)])
+@pytest.mark.parametrize("n,tdim", [((18, 13, 9), (8, 8, 4)), ((6, 7, 11), (8, 8, 4)), ((18, 13, 9), (8, 8, 8)),
+                                    ((18, 13, 9), (8, 4, 8))])
+def test_ccz4_driver_periodic_patch_writes_ghost_images(n, tdim, scheme, launch):
+    """On a CCZ4 level that is one periodic patch the stage kernel writes the
+    periodic ghost images of its output and the driver fills ghosts only
+    before the first stage: two steps (RK4 or SSP-RK3, batched or per-patch;
+    RK4 batched also from a graph; every CCZ4 tile) equal the fill + stage
+    sequence through the ABI bit for bit, ghost cells of the end state
+    included, and the oracle within the parity bar.  Sizes down to 2G = 6
+    points per axis (a point may then be both a low and a high image)."""
+    torch = _torch()
+    print("ccz4 periodic driver", n, tdim, scheme, launch, flush=True)
+    st0, dx = _ccz4_state(n, "strong")
+    U0 = synth.embed(st0)
+    dt = 0.25 * dx
+    sysd = M.System(M.MOL_CCZ4)
+    ssp = scheme == "ssp3"
+    ref_abi = _gpu_steps(O.CCZ4, M.MOL_SSPRK3 if ssp else M.MOL_RK4, U0, dx, dt, 2, sysd)
+    mode_bits = launch | (M.MOL_ADV_SSPRK3 if ssp else 0)
+    ps = M.Patchset(M.single_patch(n, (0, 0, 0), dx), sysd)
+    ps.set_tiling(0, tdim)
+    modes = ("eager", "graph") if (not ssp and launch == M.MOL_BATCHED) else ("eager",)
+    for mode in modes:
+        st = ps.alloc_states()
+        st[0]["U"].copy_(torch.from_numpy(ps.pack(0, [U0])))
+        if mode == "graph":
+            g = ps.graph_create(st, dt)
+            for _ in range(2):
+                g.launch()
+        else:
+            for _ in range(2):
+                ps.advance(st, dt, mode_bits)
+        torch.cuda.synchronize()
+        got = ps.unpack(0, st[0]["U"])[0]
+        assert np.array_equal(got, ref_abi), mode
+    ref = _oracle_steps(O.CCZ4, O.SSPRK3 if ssp else O.RK4, U0, dx, dt, 2, O.params())
+    e = parity_err(got[:, 3:-3, 3:-3, 3:-3], ref[:, 3:-3, 3:-3, 3:-3])
+    assert np.all(e <= TOL), e
+
+
 def test_rhs_entry_point_matches_oracle():
     torch = _torch()
     n = (12, 9, 7)
