@@ -1053,7 +1053,9 @@ int advance_level(mol_patchset* ps, const mol_level_state* st, int l, int r, dou
     int rc;
     for (int sidx = 0; sidx < nst; ++sidx) {
         double* Us = stage_in[sidx];
-        if (!wrap && !(images && sidx > 0) && (rc = fill_impl(ps, l, Us, nf, s, plain))) return rc;
+        // U of a later sub-step (r > 0) was filled at the end of the previous one
+        const bool filled = (images && sidx > 0) || (sidx == 0 && r > 0);
+        if (!wrap && !filled && (rc = fill_impl(ps, l, Us, nf, s, plain))) return rc;
         if (l > 0) {
             const mol_level_state& P = st[l - 1];
             const double* kc[4] = {P.k[0], P.k[1], P.k[2], P.k[3]};

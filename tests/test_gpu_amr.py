@@ -105,6 +105,47 @@ def test_subcycled_step_parity_and_batching(system):
             assert np.array_equal(got[:, 3:-3, 3:-3, 3:-3], results["graph"][l][p][:, 3:-3, 3:-3, 3:-3])
 
 
+@pytest.mark.parametrize("mode", [M.MOL_BATCHED, M.MOL_PLAIN, M.MOL_BATCHED | M.MOL_ADV_SSPRK3,
+                                  M.MOL_BATCHED | M.MOL_TIME_NOSUB])
+def test_ccz4_driver_leaves_same_level_ghosts_filled(mode):
+    """The driver fills a level's U before the first stage only on its first
+    sub-step of a parent step (later sub-steps start from the U that the
+    previous one left filled): after two coarse steps of the three-level
+    hierarchy every level's state is unchanged by a ghost fill, and the
+    interiors match the oracle's hierarchy step (which fills before every
+    stage) within the parity bar."""
+    torch = _torch()
+    print("ccz4 driver fills", mode, flush=True)
+    ps, H, data, levels, dx0 = _setup(O.CCZ4)
+    nosub = mode & M.MOL_TIME_NOSUB == M.MOL_TIME_NOSUB
+    if mode & M.MOL_ADV_SSPRK3:
+        H.set_scheme(O.SSPRK3)
+    if nosub:
+        H.set_time_mode(O.TIME_NOSUB)
+    for l, arrs in enumerate(data):
+        for p, a in enumerate(arrs):
+            H.set(l, p, a)
+    for l in range(len(levels)):
+        H.fill_same(l)
+    dt0 = 0.25 * dx0 / (6 if nosub else 1)
+    states = ps.alloc_states()
+    for l, arrs in enumerate(data):
+        states[l]["U"].copy_(torch.from_numpy(ps.pack(l, arrs)))
+    for _ in range(2):
+        H.step(dt0, O.params(sigma=0.1))
+        ps.advance(states, dt0, mode)
+    torch.cuda.synchronize()
+    for l in range(len(levels)):
+        U = states[l]["U"]
+        V = U.clone()
+        ps.fill_ghosts(l, V)
+        torch.cuda.synchronize()
+        assert torch.equal(U, V), l
+        for p, got in enumerate(ps.unpack(l, U)):
+            e = parity_err(got[:, 3:-3, 3:-3, 3:-3], H.get(l, p)[:, 3:-3, 3:-3, 3:-3])
+            assert np.all(e <= 1e-12), (l, p, e)
+
+
 @pytest.mark.parametrize("system", [O.WAVE, O.CCZ4])
 @pytest.mark.parametrize("tmode,omode", [(M.MOL_TIME_BO, O.TIME_BO), (M.MOL_TIME_BO1, O.TIME_BO1),
                                          (M.MOL_TIME_NOSUB, O.TIME_NOSUB)])
