@@ -1901,6 +1901,7 @@ void mol_regrid_destroy(mol_regrid* r)
     delete r;
 }
 
+extern "C++" {  // helpers below are C++ (they return std::vector)
 namespace {
 // launch shapes of a level's stage kernel worth timing: the z-chunk length of
 // the z-marching kernels, the thread tile of the point-wise wave kernel
@@ -1960,6 +1961,7 @@ int set_tiles(mol_patchset* ps, int level, const int td[3], int order)
     return MOL_OK;
 }
 }  // namespace
+}  // extern "C++"
 
 int mol_set_tiling(mol_patchset* ps, int level, const mol_tiling* t)
 {
