@@ -176,7 +176,11 @@ int mol_rhs(mol_patchset* ps, int level, const double* U, double* dUdt, void* st
  *    s = 3: Uout = 1/3 Un + 2/3 (Us + k)
  * k_store (nullable) receives k on the interior.  Us must have filled
  * ghosts and must not alias Uout; Un may alias Us; Uout may alias Un only for
- * the last stage.  Ghosts of Uout are not written. */
+ * the last stage.  Ghosts of Uout are not written, except on a CCZ4 level
+ * that is one periodic patch of at least 6 points per axis: there every
+ * ghost point of Uout receives the value of the interior point it is the
+ * periodic image of (what mol_fill_ghosts would write), so the next stage
+ * needs no fill. */
 int mol_rk_stage(mol_patchset* ps, int level, int scheme, int stage, double dt,
                  const double* Un, const double* Us, double* Acc, double* Uout,
                  double* k_store, void* stream);

@@ -1245,13 +1245,15 @@ int mol_rk_stage(mol_patchset* ps, int level, int scheme, int stage, double dt, 
         if (!Acc) return fail(MOL_EINVAL, "RK4 needs the accumulator");
         if ((const double*)Uout == Un && stage != 4)
             return fail(MOL_EINVAL, "Uout may alias Un only at the last stage");
-        return stage_impl(ps, level, ST_RK4, stage, dt, Un, Us, Acc, Uout, k_store, S(stream), 0);
+        return stage_impl(ps, level, ST_RK4, stage, dt, Un, Us, Acc, Uout, k_store, S(stream), 0, false,
+                          level_images(ps, level));
     }
     if (scheme == MOL_SSPRK3) {
         if (stage < 1 || stage > 3) return fail(MOL_EINVAL, "SSP-RK3 stage %d not in 1..3", stage);
         if ((const double*)Uout == Un && stage != 3)
             return fail(MOL_EINVAL, "Uout may alias Un only at the last stage");
-        return stage_impl(ps, level, ST_SSP3, stage, dt, Un, Us, Acc, Uout, k_store, S(stream), 0);
+        return stage_impl(ps, level, ST_SSP3, stage, dt, Un, Us, Acc, Uout, k_store, S(stream), 0, false,
+                          level_images(ps, level));
     }
     return fail(MOL_EINVAL, "unknown scheme %d", scheme);
 }
