@@ -99,23 +99,24 @@ class Ccz4LapseObjective(torch.autograd.Function):
         U = ps.alloc(0)
         acc = ps.alloc(0)
         nseg = (ctx.nsteps + ctx.every - 1) // ctx.every
+        # the four stage states of every step of one segment, allocated once
+        # and reused by every segment
+        kept = [[ps.alloc(0) for _ in range(4)] for _ in range(min(ctx.every, ctx.nsteps))]
         for k in reversed(range(nseg)):
             steps = min(ctx.every, ctx.nsteps - k * ctx.every)
             # the segment recomputed from its checkpoint with the forward
             # stages (the kernels and order of mol_advance), keeping the four
             # stage states of every step (ghosts filled) for the reverse steps
             U.copy_(ctx.ckpts[k])
-            kept = []
-            for _ in range(steps):
-                stages = [U.clone()] + [ps.alloc(0) for _ in range(3)]
+            for stages in kept[:steps]:
+                stages[0].copy_(U)
                 for s in range(1, 5):
                     out = stages[s] if s < 4 else U
                     ps.rk_stage(0, M.MOL_RK4, s, ctx.dt, stages[0], stages[s - 1], acc, out)
                     ps.fill_ghosts(0, out)
-                kept.append(stages)
-            for stages in reversed(kept):
+            for stages in reversed(kept[:steps]):
                 ps.rk4_adjoint_step_stages(0, ctx.dt, lam, w, stages=stages, work=work)
-            del kept
+        del kept
         g = torch.zeros(5, dtype=torch.float64, device=lam.device)
         ps.ccz4_lapse_pulse_vjp(0, ctx.p, lam, g)
         return g.cpu(), None, None, None, None, None

@@ -32,6 +32,12 @@ using namespace mol;
 // 16 x 4 x 4 (rows of whole cache lines, fewer workgroups than resident
 // slots); the eight point-wise kernels 562 - 185 = 377 us with 16 x 16 x 1
 // against 411 us with the stage kernel's 8 x 8 x 4
+// tile of the CCZ4 adjoint's periodic gather (interior points)
+#ifndef MOL_ADJ_WTX
+#define MOL_ADJ_WTX 16
+#define MOL_ADJ_WTY 8
+#define MOL_ADJ_WTZ 2
+#endif
 #ifndef MOL_ADJ_GTX
 #define MOL_ADJ_GTX 32
 #define MOL_ADJ_GTY 4
@@ -226,6 +232,7 @@ struct mol_patchset {
         TileList gtiles;  // ghosted-box tiles for the adjoint
         TileList ptiles;  // interior tiles for the CCZ4 adjoint's point-wise kernels
         TileList ntiles;  // interior tiles for reductions / initial data
+        TileList wtiles;  // interior tiles for the CCZ4 adjoint's periodic gather
         // CCZ4 adjoint workspace: start of each patch's block (slots x fs)
         DevArr<int64_t> wofs;
         int64_t wsize = 0;
@@ -253,6 +260,7 @@ struct mol_patchset {
             l.ptiles.dev.release();
             l.wofs.release();
             l.ntiles.dev.release();
+            l.wtiles.dev.release();
         }
         rad_pts.release();
         for (auto& t : retired) t.release();
@@ -442,9 +450,9 @@ void reuse_level(mol_patchset* ps, const mol_patchset* prev, int l)
     lev.band_by_patch = o.band_by_patch;
     lev.rst.adopt(o.rst, A);
     lev.rst_by_patch = o.rst_by_patch;
-    TileList* mine[4] = {&lev.tiles, &lev.gtiles, &lev.ntiles, &lev.ptiles};
-    const TileList* theirs[4] = {&o.tiles, &o.gtiles, &o.ntiles, &o.ptiles};
-    for (int i = 0; i < 4; ++i) {
+    TileList* mine[5] = {&lev.tiles, &lev.gtiles, &lev.ntiles, &lev.ptiles, &lev.wtiles};
+    const TileList* theirs[5] = {&o.tiles, &o.gtiles, &o.ntiles, &o.ptiles, &o.wtiles};
+    for (int i = 0; i < 5; ++i) {
         for (int d = 0; d < 3; ++d) mine[i]->tdim[d] = theirs[i]->tdim[d];
         mine[i]->by_patch = theirs[i]->by_patch;
         mine[i]->count = theirs[i]->count;
@@ -782,6 +790,8 @@ int build(mol_patchset* ps, const mol_hierarchy_desc* h, const mol_patchset* pre
         if (ps->sp.system == MOL_CCZ4) {
             int tp[3] = {MOL_ADJ_PTX, MOL_ADJ_PTY, MOL_ADJ_PTZ};
             build_tiles(lev, tp, 0, lev.ptiles, &ps->arena);
+            int tw[3] = {MOL_ADJ_WTX, MOL_ADJ_WTY, MOL_ADJ_WTZ};
+            build_tiles(lev, tw, 0, lev.wtiles, &ps->arena);
         }
         if (ps->sp.system == MOL_CCZ4) {
             std::vector<int64_t> wo(lev.pd.size());
@@ -1427,6 +1437,28 @@ int rk4_adjoint_core(mol_patchset* ps, int level, double dt, const double* const
     double* wk = w0;
     double* wm = w1;
     double* wsum = w2;
+    const Level& lev = ps->L[level];
+    if (ps->sp.system == MOL_CCZ4 && lev.pd.size() == 1 && lev.pd[0].n[0] >= 7 && lev.pd[0].n[1] >= 7 &&
+        lev.pd[0].n[2] >= 7) {
+        // one periodic patch: each stage's gather takes its stencil points at
+        // their periodic images (no ghost entries, no fill transpose) and
+        // forms wsum and the next stage's input (or the new lam) itself
+        const SysParams sp = level_params(ps, level);
+        double* win = w0;
+        double* wnext = w1;
+        e = launch_axpby(n, dt * cw[3], lam, 0.0, lam, win, s);
+        if (e != hipSuccess) return hip_fail(e, "axpby");
+        for (int st = 3; st >= 0; --st) {
+            const double a = st > 0 ? dt * cw[st - 1] : 0.0, b = st > 0 ? dt * bsub[st] : 0.0;
+            e = launch_ccz4_adjoint_stage(sp, lev.d_pd.p, lev.ptiles.dev.p, (int)lev.ptiles.dev.n, lev.ptiles.tdim,
+                                          lev.wtiles.dev.p, (int)lev.wtiles.dev.n, lev.wtiles.tdim, Ust[st], win,
+                                          work, lev.wofs.p, lam, lam, w2, st > 0 ? wnext : nullptr, a, b, st == 3,
+                                          st == 0, s);
+            if (e != hipSuccess) return hip_fail(e, "adjoint stage launch");
+            std::swap(win, wnext);
+        }
+        return MOL_OK;
+    }
     const double* prev = nullptr;  // m_{s+1}
     for (int st = 3; st >= 0; --st) {
         if (st == 3)

@@ -855,18 +855,39 @@ ADJ_KERNEL(ccz4_adj_chain_kernel)
 #define MOL_ADJ_GATHER_GROUP 9
 #endif
 
+// Epilogue of the periodic (WRAP) gather inside a reverse RK4 step: with v the
+// transposed value at p, wsum = v (first) or wsum + v; then either
+// wnext = a lam + b v (the next stage's input), or lam += wsum (last).
+struct GatherEpi {
+    const double* lam0;  // lam of the step (read)
+    double* lam;         // lam of the step, updated in place by the last stage
+    double* wsum;
+    double* wnext;
+    double a, b;
+    int first, last;
+};
+
+// WRAP = false: every point p of the ghosted box, interior stencil points c
+// only; the ghost entries of lamU are then folded into their owners by the
+// fill transpose.  WRAP = true (one periodic patch of at least 7 points per
+// axis): every interior point p, with the stencil points c taken at their
+// periodic images, so no ghost entry arises; the result goes through the
+// epilogue instead of lamU.
+template <bool WRAP>
 __global__ __launch_bounds__(256) void ccz4_adj_gather_kernel(const PatchDev* __restrict__ patches,
                                                               const Tile* __restrict__ tiles,
                                                               const double* __restrict__ Ug,
                                                               const double* __restrict__ lamg,
                                                               const double* __restrict__ W,
                                                               const int64_t* __restrict__ wofs, AdjConst C,
-                                                              double* __restrict__ lamU)
+                                                              double* __restrict__ lamU, GatherEpi E)
 {
     const Tile t = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     const PatchDev P = patches[t.patch];
     const int q[3] = {t.o[0] + (int)threadIdx.x, t.o[1] + (int)threadIdx.y, t.o[2] + (int)threadIdx.z};
-    if (q[0] >= P.n[0] + G || q[1] >= P.n[1] + G || q[2] >= P.n[2] + G) return;
+    if (WRAP ? (q[0] >= P.n[0] || q[1] >= P.n[1] || q[2] >= P.n[2])
+             : (q[0] >= P.n[0] + G || q[1] >= P.n[1] + G || q[2] >= P.n[2] + G))
+        return;
     const int64_t loc = (int64_t)(q[2] + G) * P.pitch_z + (int64_t)(q[1] + G) * P.pitch_y + (q[0] + G);
     const int64_t fs = P.fs;
     const int S[3] = {1, P.pitch_y, P.pitch_z};
@@ -874,11 +895,22 @@ __global__ __launch_bounds__(256) void ccz4_adj_gather_kernel(const PatchDev* __
     const double* bp = Ug + P.off + loc + (int64_t)BETA * fs;
     const double* wp = W + wofs[t.patch] + loc;
     // c = p + off along axis d (and e along axis d2) is an interior point
+    // (always, at its periodic image, when WRAP)
     auto inside = [&](int d, int off, int d2 = 0, int e = 0) {
+        if constexpr (WRAP) return true;
         int c[3] = {q[0], q[1], q[2]};
         c[d] += off;
         c[d2] += e;
         return c[0] >= 0 && c[0] < P.n[0] && c[1] >= 0 && c[1] < P.n[1] && c[2] >= 0 && c[2] < P.n[2];
+    };
+    // offset of p + off along axis d from p (at the periodic image when WRAP)
+    auto shift = [&](int d, int off) -> int64_t {
+        int v = off;
+        if constexpr (WRAP) {
+            const int c = q[d] + off;
+            v = c < 0 ? off + P.n[d] : (c >= P.n[d] ? off - P.n[d] : off);
+        }
+        return (int64_t)v * S[d];
     };
     const bool self = inside(0, 0);
     const double w1[5] = {1.0, -8.0, 0.0, 8.0, -1.0};   // D1: coefficient of u(c+o), o = -2..2
@@ -904,7 +936,7 @@ __global__ __launch_bounds__(256) void ccz4_adj_gather_kernel(const PatchDev* __
 #pragma unroll 1
             for (int o = -3; o <= 3; ++o) {
                 if (!inside(k, -o)) continue;
-                const int64_t cof = -(int64_t)o * S[k];
+                const int64_t cof = shift(k, -o);
                 const double bk = bp[(int64_t)k * fs + cof];
                 const double wa = C.upwind ? (bk >= 0.0 ? wlp[o + 3] : wlm[o + 3]) : (o >= -2 && o <= 2 ? w1[o + 2] : 0.0);
                 // KO and advection act on lam of every field
@@ -931,7 +963,7 @@ __global__ __launch_bounds__(256) void ccz4_adj_gather_kernel(const PatchDev* __
 #pragma unroll 1
                     for (int b = -2; b <= 2; ++b) {
                         if (a == 0 || b == 0 || !inside(k, -a, l, -b)) continue;
-                        const int64_t cof = -(int64_t)a * S[k] - (int64_t)b * S[l];
+                        const int64_t cof = shift(k, -a) + shift(l, -b);
                         const double wm = C.i144h2 * w1[a + 2] * w1[b + 2];
 #pragma unroll
                         for (int g = 0; g < GF; ++g) {
@@ -942,19 +974,25 @@ __global__ __launch_bounds__(256) void ccz4_adj_gather_kernel(const PatchDev* __
                         }
                     }
 #pragma unroll
-        for (int g = 0; g < GF; ++g)
-            if (f0 + g < NF) lamU[P.off + loc + (int64_t)(f0 + g) * fs] = acc[g];
+        for (int g = 0; g < GF; ++g) {
+            if (f0 + g >= NF) continue;
+            const int64_t idx = P.off + loc + (int64_t)(f0 + g) * fs;
+            if constexpr (!WRAP) {
+                lamU[idx] = acc[g];
+            } else {
+                const double s = E.first ? acc[g] : E.wsum[idx] + acc[g];
+                if (E.last) {
+                    E.lam[idx] = E.lam0[idx] + s;
+                } else {
+                    E.wsum[idx] = s;
+                    E.wnext[idx] = E.a * E.lam0[idx] + E.b * acc[g];
+                }
+            }
+        }
     }
 }
 
-}  // namespace
-
-int ccz4_adjoint_slots() { return NWX; }
-
-hipError_t launch_ccz4_adjoint(const SysParams& sp, const PatchDev* patches, const Tile* tiles, int ntiles,
-                               const int td[3], const Tile* gtiles, int ngtiles, const int gtd[3],
-                               const double* U, const double* lam, double* W, const int64_t* wofs, double* lamU,
-                               hipStream_t s)
+AdjConst adj_const(const SysParams& sp)
 {
     AdjConst C;
     C.i12h = 1.0 / (12.0 * sp.h);
@@ -968,6 +1006,19 @@ hipError_t launch_ccz4_adjoint(const SysParams& sp, const PatchDev* patches, con
     C.g = sp.gd_g;
     C.eta = sp.gd_eta;
     C.upwind = sp.upwind;
+    return C;
+}
+
+}  // namespace
+
+int ccz4_adjoint_slots() { return NWX; }
+
+hipError_t launch_ccz4_adjoint(const SysParams& sp, const PatchDev* patches, const Tile* tiles, int ntiles,
+                               const int td[3], const Tile* gtiles, int ngtiles, const int gtd[3],
+                               const double* U, const double* lam, double* W, const int64_t* wofs, double* lamU,
+                               hipStream_t s)
+{
+    const AdjConst C = adj_const(sp);
     if (ntiles > 0) {
         // every pointwise kernel covers the same interior points; each writes
         // or accumulates only the workspace slots listed in its comment
@@ -985,7 +1036,25 @@ hipError_t launch_ccz4_adjoint(const SysParams& sp, const PatchDev* patches, con
         if (e != hipSuccess) return e;
     }
     if (ngtiles > 0)
-        ccz4_adj_gather_kernel<<<ngtiles, dim3(gtd[0], gtd[1], gtd[2]), 0, s>>>(patches, gtiles, U, lam, W, wofs, C, lamU);
+        ccz4_adj_gather_kernel<false>
+            <<<ngtiles, dim3(gtd[0], gtd[1], gtd[2]), 0, s>>>(patches, gtiles, U, lam, W, wofs, C, lamU, GatherEpi{});
+    return hipGetLastError();
+}
+
+hipError_t launch_ccz4_adjoint_stage(const SysParams& sp, const PatchDev* patches, const Tile* tiles, int ntiles,
+                                     const int td[3], const Tile* itiles, int nitiles, const int itd[3],
+                                     const double* U, const double* lam_in, double* W, const int64_t* wofs,
+                                     const double* lam0, double* lam, double* wsum, double* wnext, double a,
+                                     double b, int first, int last, hipStream_t s)
+{
+    // the point-wise kernels as in launch_ccz4_adjoint (no gather), then the
+    // periodic gather with the reverse-RK4 epilogue
+    hipError_t e = launch_ccz4_adjoint(sp, patches, tiles, ntiles, td, nullptr, 0, itd, U, lam_in, W, wofs, nullptr, s);
+    if (e != hipSuccess || nitiles <= 0) return e;
+    AdjConst C = adj_const(sp);
+    GatherEpi E{lam0, lam, wsum, wnext, a, b, first, last};
+    ccz4_adj_gather_kernel<true>
+        <<<nitiles, dim3(itd[0], itd[1], itd[2]), 0, s>>>(patches, itiles, U, lam_in, W, wofs, C, nullptr, E);
     return hipGetLastError();
 }
 

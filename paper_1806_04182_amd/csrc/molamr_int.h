@@ -182,6 +182,16 @@ hipError_t launch_ccz4_adjoint(const SysParams& sp, const PatchDev* patches, con
                                const int td[3], const Tile* gtiles, int ngtiles, const int gtd[3],
                                const double* U, const double* lam, double* W, const int64_t* wofs, double* lamU,
                                hipStream_t s);
+// One stage of the reverse RK4 step on a level that is one periodic patch of
+// at least 7 points per axis: the point-wise kernels at Ust, then the gather
+// over interior points with periodic stencil images and the epilogue
+// wsum = (first ? 0 : wsum) + v, then wnext = a lam0 + b v, or on the last
+// stage lam = lam0 + wsum (interior points only; ghost entries untouched).
+hipError_t launch_ccz4_adjoint_stage(const SysParams& sp, const PatchDev* patches, const Tile* tiles, int ntiles,
+                                     const int td[3], const Tile* itiles, int nitiles, const int itd[3],
+                                     const double* U, const double* lam_in, double* W, const int64_t* wofs,
+                                     const double* lam0, double* lam, double* wsum, double* wnext, double a,
+                                     double b, int first, int last, hipStream_t s);
 hipError_t launch_wave_adjoint(const SysParams& sp, const PatchDev* patches, const Tile* tiles,
                                int ntiles, const int tdim[3], const double* lam, double* lamU,
                                hipStream_t s);

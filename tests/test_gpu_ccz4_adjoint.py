@@ -72,11 +72,14 @@ def test_rhs_adjoint_dot_product_with_oracle_jvp(n):
     assert abs(a - b) <= 1e-12 * np.sum(np.abs(got * v)), (a, b)
 
 
-def test_rk4_adjoint_step_dot_product_with_oracle_jvp():
+@pytest.mark.parametrize("n", [(10, 8, 6), (10, 8, 7)])
+def test_rk4_adjoint_step_dot_product_with_oracle_jvp(n):
     """One reverse RK4 step against the tangent of one forward step built from
-    the oracle's right-hand side and its exact JVP, stage by stage."""
+    the oracle's right-hand side and its exact JVP, stage by stage.  With
+    fewer than 7 points on an axis the step gathers over the ghosted box and
+    folds the ghost entries back (fill transpose); from 7 on, over the
+    interior with periodic stencil images and a fused stage epilogue."""
     torch = _torch()
-    n = (10, 8, 6)
     dx = 2.0 / 10
     dt = 0.25 * dx
     U = _state(n, dx, 5)
