@@ -80,9 +80,9 @@ constexpr int ORDER[NF] = {GT + 0, GT + 1, GT + 2,   GT + 3,   GT + 4,   GT + 5,
 // LDS geometry of the stage kernel for a TX x TY x TZ tile.  The halo tile's
 // rows are padded to a pitch of PX doubles: a wave reads 8 rows of 8 doubles;
 // with PX = 24 (= 8 mod 16 doubles) every group of rows served in one LDS
-// cycle starts on distinct banks.  Halo loads: 16 lanes per row (x), NT / 16
-// rows per pass covering PP whole planes, NR passes; the offset between
-// passes is a constant.
+// cycle starts on distinct banks.  Only the halo points a field's stencils
+// read are loaded (below); NR, the passes of a whole-box load with 16 lanes
+// per row, bounds the loads per thread and sizes the staging registers.
 #ifndef MOL_CCZ4_PERSISTENT
 #define MOL_CCZ4_PERSISTENT 0
 #endif
@@ -101,6 +101,15 @@ struct CczLds {
     static constexpr int ZS = TX * TY * HZ, NZ = (ZS + NT - 1) / NT, ZPP = NT / (TX * TY);
     static constexpr int XW = 2 * G * TY * TZ, YW = 2 * G * TX * TZ, NW = (XW + YW + NT - 1) / NT;
     static_assert(NT % (TX * TY) == 0 && NZ + NW <= NR, "cross does not fit the load pattern");
+    // The rest of the halo that a field with second derivatives reads: its
+    // cross plus the reach-2 squares of the mixed derivatives, i.e. the z slab
+    // and, on each of the tile's planes, the wings and the four 2 x 2 corners
+    // (TPE points), and on the two planes below and above the tile, reach-2
+    // strips beyond the x faces and beyond the y faces (OPE points).  The
+    // reach-3 edges and the corners off the tile's planes are never read.
+    static constexpr int TPE = 6 * TY + 6 * TX + 16, OPE = 4 * TY + 4 * TX;
+    static constexpr int BE = TZ * TPE + 4 * OPE, NB = (BE + NT - 1) / NT;
+    static_assert(NZ + NB <= NR, "reduced box does not fit the load pattern");
 };
 
 // fields whose stencils read only along the axes through the point (first
@@ -130,30 +139,8 @@ __device__ __forceinline__ void ccz4_tile(const StageArgs& a, const CczConst& C,
     const int64_t c = hbase + (int64_t)(tz + G) * P.pitch_z + (int64_t)(ty + G) * P.pitch_y + (tx + G);
     const int64_t fs = P.fs;
 
-    // this thread's halo element in the first pass; pass r adds PP planes.
-    // Lanes outside the ghosted box load from the tile origin instead (no
-    // branch around the load; such halo values are read only by threads
-    // outside the patch, which compute nothing).
-    const int lx = tid % LW, ly = tid / LW, hy = ly % HY, hz0 = ly / HY;
-    const bool lane = lx < HX && ly < PP * HY;
-    const bool inxy = lane && tile.o[0] + lx < P.n[0] + 2 * G && tile.o[1] + hy < P.n[1] + 2 * G;
-    const int gl = hz0 * P.pitch_z + hy * P.pitch_y + lx;
-    const int ll = (hz0 * HY + hy) * PX + lx;
     const int hzmax = P.n[2] + 2 * G - tile.o[2];  // halo planes inside the ghosted box
     double stg[NR];
-    auto gload = [&](int f) __attribute__((always_inline)) {
-        const double* src = a.Us + hbase + (int64_t)f * fs;
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            const bool ok = inxy && hz0 + r * PP < hzmax;
-            stg[r] = src[ok ? gl + r * PP * P.pitch_z : 0];
-        }
-    };
-    auto lstore = [&]() __attribute__((always_inline)) {
-#pragma unroll
-        for (int r = 0; r < NR; ++r)
-            if (lane) buf[ll + r * PP * HY * PX] = stg[r];
-    };
     // the cross of a single-axis field (fewer loads than the box): z-slab
     // element tid + r NT is column (zx, zy) of plane zz + r ZPP; wing element
     // e = tid + r NT is decoded per pass.  Elements outside the ghosted box
@@ -190,6 +177,73 @@ __device__ __forceinline__ void ccz4_tile(const StageArgs& a, const CczConst& C,
             const bool ok = e < XW + YW && tile.o[0] + hx < P.n[0] + 2 * G && tile.o[1] + hy < P.n[1] + 2 * G &&
                             hz < hzmax;
             stg[NZ + r] = src[ok ? hz * P.pitch_z + hy * P.pitch_y + hx : 0];
+        }
+    };
+    // the reduced box of a field with second derivatives: the z slab as for
+    // the cross, then the extra points decoded per pass
+    constexpr int TPE = L::TPE, OPE = L::OPE, BE = L::BE, NB = L::NB;
+    auto bextra = [&](int e, int& hx, int& hy, int& hz) __attribute__((always_inline)) {
+        // reach-2 positions beyond a face: G - 2, G - 1, G + T, G + T + 1
+        auto r2 = [](int c, int T) { return c < 2 ? G - 2 + c : G + T + c - 2; };
+        if (e < TZ * TPE) {
+            const int pl = e / TPE, w = e - pl * TPE;
+            hz = G + pl;
+            if (w < 6 * TY) {
+                const int c = w % 6;
+                hx = c < 3 ? c : c + TX;
+                hy = G + w / 6;
+            } else if (w < 6 * TY + 6 * TX) {
+                const int w2 = w - 6 * TY, r = w2 / TX;
+                hx = G + w2 % TX;
+                hy = r < 3 ? r : r + TY;
+            } else {
+                const int w3 = w - 6 * TY - 6 * TX;
+                hx = r2(w3 % 4, TX);
+                hy = r2(w3 / 4, TY);
+            }
+        } else {
+            const int e2 = e - TZ * TPE, pl = e2 / OPE, w = e2 - pl * OPE;
+            hz = r2(pl, TZ);
+            if (w < 4 * TY) {
+                hx = r2(w % 4, TX);
+                hy = G + w / 4;
+            } else {
+                const int w2 = w - 4 * TY;
+                hx = G + w2 % TX;
+                hy = r2(w2 / TX, TY);
+            }
+        }
+    };
+    auto gload = [&](int f) __attribute__((always_inline)) {
+        const double* src = a.Us + hbase + (int64_t)f * fs;
+#pragma unroll
+        for (int r = 0; r < NZ; ++r) {
+            const int hz = zz + r * ZPP;
+            const bool ok = zin && hz < HZ && hz < hzmax;
+            stg[r] = src[ok ? hz * P.pitch_z + zy * P.pitch_y + zx : 0];
+        }
+#pragma unroll
+        for (int r = 0; r < NB; ++r) {
+            const int e = tid + r * NT;
+            int hx, hy, hz;
+            bextra(e, hx, hy, hz);
+            const bool ok = e < BE && tile.o[0] + hx < P.n[0] + 2 * G && tile.o[1] + hy < P.n[1] + 2 * G &&
+                            hz < hzmax;
+            stg[NZ + r] = src[ok ? hz * P.pitch_z + hy * P.pitch_y + hx : 0];
+        }
+    };
+    auto lstore = [&]() __attribute__((always_inline)) {
+#pragma unroll
+        for (int r = 0; r < NZ; ++r) {
+            const int hz = zz + r * ZPP;
+            if (ZS % NT == 0 || hz < HZ) buf[(hz * HY + zy) * PX + zx] = stg[r];
+        }
+#pragma unroll
+        for (int r = 0; r < NB; ++r) {
+            const int e = tid + r * NT;
+            int hx, hy, hz;
+            bextra(e, hx, hy, hz);
+            if (BE % NT == 0 || e < BE) buf[(hz * HY + hy) * PX + hx] = stg[NZ + r];
         }
     };
     auto lstore_x = [&]() __attribute__((always_inline)) {
