@@ -127,7 +127,7 @@ __device__ __forceinline__ void ccz4_tile(const StageArgs& a, const CczConst& C,
                                           double (*__restrict__ akx)[TX * TY * TZ])
 {
     using L = CczLds<TX, TY, TZ>;
-    constexpr int HX = L::HX, HY = L::HY, HZ = L::HZ, PX = L::PX, NT = L::NT, LW = L::LW, PP = L::PP, NR = L::NR;
+    constexpr int HY = L::HY, HZ = L::HZ, PX = L::PX, NT = L::NT, NR = L::NR;
 
     const Tile tile = a.tiles[tidx];
     const PatchDev P = a.patches[tile.patch];

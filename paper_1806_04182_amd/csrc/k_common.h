@@ -118,6 +118,22 @@ __device__ __forceinline__ void stage_store(const StageArgs& a, int64_t idx, dou
     stage_apply(a, idx, rhs, stage_load(a, idx));
 }
 
+// ---- wavefront reductions: a fixed butterfly of lane exchanges over the 64
+// lanes of a wave (the same pairs and order on every run; a + b and b + a are
+// the same double, so every lane ends with the same value)
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
 // ---- 4th-order finite differences, evaluated as differences of symmetric
 // neighbours / differences from the centre so that a small signal on an
 // O(1) background keeps its digits.  Scale factors are applied by callers.

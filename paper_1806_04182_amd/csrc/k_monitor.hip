@@ -14,7 +14,7 @@
 // the traces of the printed Rhat_ij and Rhat^chi_ij with
 // Z^k = chi (Ghat^k - Gt^k)/2 substituted; R + 2 nabla_i Z^i is chi times
 // their sum.
-#include "molamr_int.h"
+#include "k_common.h"
 
 namespace mol {
 
@@ -29,20 +29,24 @@ struct MonRed {
 
 __device__ __forceinline__ bool is_max(int q) { return q < 3 * MOL_MON_COUNT && q % 3 == 2; }
 
+// Block reduction: each wave reduces its 64 lanes (wave_sum / wave_max), lane
+// 0 of each wave parks the result in LDS, then the RB / 64 wave results are
+// folded in wave order.  Fixed order throughout: the same bits on every run.
+constexpr int NWV = RB / 64;
 __device__ __forceinline__ void block_reduce(MonRed& r, double* sh)
 {
     const int t = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
-    for (int q = 0; q < NQ; ++q) sh[q * RB + t] = r.v[q];
-    __syncthreads();
-    for (int w = RB / 2; w > 0; w >>= 1) {
-        if (t < w)
-            for (int q = 0; q < NQ; ++q) {
-                const double a = sh[q * RB + t], b = sh[q * RB + t + w];
-                sh[q * RB + t] = is_max(q) ? fmax(a, b) : a + b;
-            }
-        __syncthreads();
+    const int lane = t & 63, wv = t >> 6;
+    for (int q = 0; q < NQ; ++q) {
+        const double v = is_max(q) ? wave_max(r.v[q]) : wave_sum(r.v[q]);
+        if (lane == 0) sh[q * NWV + wv] = v;
     }
-    for (int q = 0; q < NQ; ++q) r.v[q] = sh[q * RB];
+    __syncthreads();
+    for (int q = 0; q < NQ; ++q) {
+        double v = sh[q * NWV];
+        for (int w = 1; w < NWV; ++w) v = is_max(q) ? fmax(v, sh[q * NWV + w]) : v + sh[q * NWV + w];
+        r.v[q] = v;
+    }
 }
 
 // 4th-order stencils of Sec. II.B.1 along stride s (weighted differences)
@@ -92,7 +96,7 @@ struct MonArgs {
 
 __global__ __launch_bounds__(RB) void monitor_kernel(MonArgs a)
 {
-    __shared__ double sh[NQ * RB];
+    __shared__ double sh[NQ * NWV];
     MonRed r;
     for (int q = 0; q < NQ; ++q) r.v[q] = 0.0;
     const double h = a.h, dV = h * h * h;
@@ -256,7 +260,7 @@ __global__ __launch_bounds__(RB) void monitor_kernel(MonArgs a)
 __global__ __launch_bounds__(RB) void monitor_final_kernel(const double* __restrict__ partial, int nb,
                                                            double* __restrict__ out)
 {
-    __shared__ double sh[NQ * RB];
+    __shared__ double sh[NQ * NWV];
     MonRed r;
     for (int q = 0; q < NQ; ++q) r.v[q] = 0.0;
     const int t = threadIdx.x;

@@ -3,7 +3,7 @@
 // product).  Order of summation is fixed: each thread walks a fixed set of
 // tiles, blocks reduce with a fixed tree in LDS, and one final block reduces
 // the per-block partials with the same tree.
-#include "molamr_int.h"
+#include "k_common.h"
 
 // Sphere membership |x| < R decides which points enter the objective: the
 // coordinates and x^2 + y^2 + z^2 are evaluated without FMA contraction so
@@ -23,20 +23,25 @@ struct Red {
 };
 
 // q < 2, 3: sums; q == 2: max
+// Block reduction: each wave reduces its 64 lanes (wave_sum, or wave_max for
+// entry nmaxq), lane 0 of each wave parks the result in LDS, then the RB / 64
+// wave results are folded in wave order.  Fixed order throughout: the same
+// bits on every run.
+constexpr int NWV = RB / 64;
 __device__ __forceinline__ void block_reduce(Red& r, double* sh, int nmaxq)
 {
     const int t = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
-    for (int q = 0; q < NQ; ++q) sh[q * RB + t] = r.v[q];
-    __syncthreads();
-    for (int w = RB / 2; w > 0; w >>= 1) {
-        if (t < w)
-            for (int q = 0; q < NQ; ++q) {
-                const double a = sh[q * RB + t], b = sh[q * RB + t + w];
-                sh[q * RB + t] = q == nmaxq ? fmax(a, b) : a + b;
-            }
-        __syncthreads();
+    const int lane = t & 63, wv = t >> 6;
+    for (int q = 0; q < NQ; ++q) {
+        const double v = q == nmaxq ? wave_max(r.v[q]) : wave_sum(r.v[q]);
+        if (lane == 0) sh[q * NWV + wv] = v;
     }
-    for (int q = 0; q < NQ; ++q) r.v[q] = sh[q * RB];
+    __syncthreads();
+    for (int q = 0; q < NQ; ++q) {
+        double v = sh[q * NWV];
+        for (int w = 1; w < NWV; ++w) v = q == nmaxq ? fmax(v, sh[q * NWV + w]) : v + sh[q * NWV + w];
+        r.v[q] = v;
+    }
 }
 
 __global__ __launch_bounds__(RB) void norms_kernel(const PatchDev* __restrict__ patches,
@@ -45,7 +50,7 @@ __global__ __launch_bounds__(RB) void norms_kernel(const PatchDev* __restrict__ 
                                                    double r2max, double h, double x0, double y0, double z0,
                                                    CoordBox box, double* __restrict__ partial)
 {
-    __shared__ double sh[NQ * RB];
+    __shared__ double sh[NQ * NWV];
     Red r;
     for (int q = 0; q < NQ; ++q) r.v[q] = 0.0;
     const double dV = h * h * h;
@@ -78,7 +83,7 @@ __global__ __launch_bounds__(RB) void norms_kernel(const PatchDev* __restrict__ 
 __global__ __launch_bounds__(RB) void final_kernel(const double* __restrict__ partial, int nb, int nmaxq,
                                                    double* __restrict__ out)
 {
-    __shared__ double sh[NQ * RB];
+    __shared__ double sh[NQ * NWV];
     Red r;
     for (int q = 0; q < NQ; ++q) r.v[q] = 0.0;
     const int t = threadIdx.x;
@@ -103,7 +108,7 @@ __global__ __launch_bounds__(RB) void gaussian_kernel(const PatchDev* __restrict
                                                       double* __restrict__ U, const double* __restrict__ lam,
                                                       double* __restrict__ partial)
 {
-    __shared__ double sh[NQ * RB];
+    __shared__ double sh[NQ * NWV];
     Red r;
     for (int q = 0; q < NQ; ++q) r.v[q] = 0.0;
     const double A = prm.v[0], w = prm.v[1];

@@ -8,6 +8,7 @@ importing this module on a machine without it raises instead of falling back.
 from __future__ import annotations
 
 import ctypes
+import dataclasses
 import os
 from dataclasses import dataclass, field
 from typing import Sequence
@@ -412,6 +413,43 @@ class Patchset:
         t = _Tiling((ctypes.c_int * 3)(*tdim), order, 0.0)
         _check(lib().mol_set_tiling(self._h, level, ctypes.byref(t)))
 
+    def tiling_key(self, level) -> str:
+        """Key of a level's stage launches in an autotuning cache: the device,
+        the library build (hash of the shared object), the system and the
+        level's ratio and boxes (in order: the tile orders depend on it)."""
+        import hashlib
+        import json
+        import torch
+        desc = {"device": torch.cuda.get_device_name(), "system": dataclasses.asdict(self.system),
+                "ratio": self.hier.levels[level][0], "boxes": [[list(lo), list(hi)] for lo, hi in
+                                                               self.hier.levels[level][1]],
+                "lib": _lib_digest()}
+        return hashlib.sha256(json.dumps(desc, sort_keys=True).encode()).hexdigest()
+
+    def autotune_cached(self, level, state, dt, cache, reps=5, stream=None) -> dict:
+        """autotune with a JSON cache file: a level seen before (same key)
+        takes its recorded tiling without timing anything; otherwise the
+        level is tuned and the result recorded.  Returns the tiling and
+        whether it came from the cache."""
+        import json
+        key = self.tiling_key(level)
+        try:
+            with open(cache) as fh:
+                table = json.load(fh)
+        except (OSError, ValueError):
+            table = {}
+        if key in table:
+            rec = table[key]
+            self.set_tiling(level, rec["tdim"], rec["order"])
+            return {"tdim": tuple(rec["tdim"]), "order": rec["order"], "ms": rec["ms"], "cached": True}
+        res = self.autotune(level, state, dt, reps, stream)
+        table[key] = {"tdim": list(res["tdim"]), "order": res["order"], "ms": res["ms"]}
+        tmp = f"{cache}.{os.getpid()}.tmp"
+        with open(tmp, "w") as fh:
+            json.dump(table, fh, indent=1, sort_keys=True)
+        os.replace(tmp, cache)
+        return dict(res, cached=False)
+
     def alloc_states(self, device="cuda"):
         """Device buffers for mol_advance: U, S0, S1, acc and (when a finer
         level exists) k[4] per level."""
@@ -421,6 +459,20 @@ class Patchset:
             st["k"] = [self.alloc(l, device) for _ in range(4)] if l + 1 < self.nlev else None
             out.append(st)
         return out
+
+
+_LIB_DIGEST = None
+
+
+def _lib_digest() -> str:
+    """sha256 of the loaded library file (an autotuning cache entry holds only
+    for the build that measured it)."""
+    global _LIB_DIGEST
+    if _LIB_DIGEST is None:
+        import hashlib
+        with open(LIB_PATH, "rb") as fh:
+            _LIB_DIGEST = hashlib.sha256(fh.read()).hexdigest()
+    return _LIB_DIGEST
 
 
 def cluster(flags: np.ndarray, buffer: int, max_boxes: int = 4096) -> list:

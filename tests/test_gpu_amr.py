@@ -379,3 +379,36 @@ def test_autotuned_tiling_gives_identical_steps(system):
                 torch.cuda.synchronize()
                 for l in range(len(levels)):
                     np.testing.assert_array_equal(st[l]["U"].cpu().numpy(), want[l], err_msg=f"{tdim} {order} {l}")
+
+
+def test_autotune_cache_records_and_reuses_tilings(tmp_path):
+    """autotune_cached: the first patchset tunes every level and records the
+    choices in a JSON file keyed by device, library build, system and level
+    geometry; a second patchset of the same hierarchy takes them from the
+    file without timing, and a hierarchy with other boxes gets its own
+    entries."""
+    torch = _torch()
+    import json
+    levels, N0 = hierarchy()
+    sysd = M.System(M.MOL_CCZ4, sigma=0.1)
+    cache = tmp_path / "tilings.json"
+    dt0 = 0.05 * 2.0 / N0[0]
+    first = M.Patchset(M.Hierarchy(N0, (-1, -1, -1), 2.0 / N0[0], levels), sysd)
+    got = []
+    for l in range(len(levels)):
+        st = first.alloc_states()[l]
+        ps_data = _level_data(O.CCZ4, levels, 2.0 / N0[0])[l]
+        st["U"].copy_(torch.from_numpy(first.pack(l, ps_data)))
+        got.append(first.autotune_cached(l, st, dt0, cache, reps=2))
+    assert not any(g["cached"] for g in got)
+    table = json.loads(cache.read_text())
+    assert len(table) == len(levels)
+    second = M.Patchset(M.Hierarchy(N0, (-1, -1, -1), 2.0 / N0[0], levels), sysd)
+    for l in range(len(levels)):
+        st = second.alloc_states()[l]
+        again = second.autotune_cached(l, st, dt0, cache)
+        assert again["cached"] and again["tdim"] == got[l]["tdim"] and again["order"] == got[l]["order"]
+    other = [(1, levels[0][1]), (2, levels[1][1][:2])]
+    third = M.Patchset(M.Hierarchy(N0, (-1, -1, -1), 2.0 / N0[0], other), sysd)
+    assert third.tiling_key(0) == first.tiling_key(0)
+    assert third.tiling_key(1) != first.tiling_key(1)
