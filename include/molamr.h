@@ -420,6 +420,12 @@ typedef struct {
  * optionally MOL_ADV_SSPRK3.  MOL_EINVAL on an unknown mode. */
 int mol_advance(mol_patchset* ps, const mol_level_state* states, double dt0, int mode,
                 void* stream);
+/* nsteps >= 1 consecutive mol_advance steps.  Every step leaves level 0's U
+ * with filled ghosts, so the steps after the first skip the ghost fill of U
+ * before their first stage; the results are those of nsteps mol_advance
+ * calls bit for bit.  MOL_EINVAL when nsteps < 1. */
+int mol_advance_steps(mol_patchset* ps, const mol_level_state* states, double dt0, int nsteps, int mode,
+                      void* stream);
 
 /* ---- adaptive refinement (Sec. III.A): tagging, boxes, regrid ---- */
 
@@ -484,6 +490,10 @@ typedef struct mol_graph mol_graph;
  * instantiate it (the states' buffers are baked in). */
 int mol_graph_create(mol_patchset* ps, const mol_level_state* states, double dt0,
                      mol_graph** out);
+/* The same for mol_advance_steps(ps, states, dt0, nsteps, MOL_BATCHED): one
+ * graph whose launch takes nsteps steps. */
+int mol_graph_create_steps(mol_patchset* ps, const mol_level_state* states, double dt0, int nsteps,
+                           mol_graph** out);
 int mol_graph_launch(mol_graph* g, void* stream);
 void mol_graph_destroy(mol_graph* g);
 

@@ -1041,8 +1041,10 @@ int restrict_impl(mol_patchset* ps, int fl, const double* Uf, double* Uc, hipStr
 // dt; its finer level then takes R steps of dt/R whose coarse-fine ghosts
 // come from this step's U^n and k_1..k_4; the fine result is injected.
 // tmode: MOL_TIME_* or-ed with MOL_ADV_SSPRK3 for SSP-RK3 steps
+// u_filled: the level's U already has its same-level ghosts (a later step
+// of a multi-step call: every step leaves U filled)
 int advance_level(mol_patchset* ps, const mol_level_state* st, int l, int r, double dt,
-                  hipStream_t s, int plain, int tmode)
+                  hipStream_t s, int plain, int tmode, bool u_filled = false)
 {
     const mol_level_state& X = st[l];
     const bool kids = l + 1 < ps->nlev;
@@ -1064,8 +1066,9 @@ int advance_level(mol_patchset* ps, const mol_level_state* st, int l, int r, dou
     int rc;
     for (int sidx = 0; sidx < nst; ++sidx) {
         double* Us = stage_in[sidx];
-        // U of a later sub-step (r > 0) was filled at the end of the previous one
-        const bool filled = (images && sidx > 0) || (sidx == 0 && r > 0);
+        // U of a later sub-step (r > 0), or of a later step of a multi-step
+        // call, was filled at the end of the previous one
+        const bool filled = (images && sidx > 0) || (sidx == 0 && (r > 0 || u_filled));
         if (!wrap && !filled && (rc = fill_impl(ps, l, Us, nf, s, plain))) return rc;
         if (l > 0) {
             const mol_level_state& P = st[l - 1];
@@ -1683,7 +1686,14 @@ int mol_ccz4_lapse_pulse_vjp(mol_patchset* ps, int level, const double prm[5], c
 
 int mol_advance(mol_patchset* ps, const mol_level_state* states, double dt0, int mode, void* stream)
 {
+    return mol_advance_steps(ps, states, dt0, 1, mode, stream);
+}
+
+int mol_advance_steps(mol_patchset* ps, const mol_level_state* states, double dt0, int nsteps, int mode,
+                      void* stream)
+{
     if (!ps) return fail(MOL_EINVAL, "null patchset");
+    if (nsteps < 1) return fail(MOL_EINVAL, "nsteps must be at least 1");
     if (ps->sp.system != MOL_WAVE && ps->sp.system != MOL_CCZ4 && ps->sp.system != MOL_MHD &&
         ps->sp.system != MOL_MHD_GLM)
         return fail(MOL_EINVAL, "unknown system");
@@ -1693,7 +1703,9 @@ int mol_advance(mol_patchset* ps, const mol_level_state* states, double dt0, int
         return fail(MOL_EINVAL, "unknown mode %d", mode);
     int rc = check_states(ps, states);
     if (rc) return rc;
-    return advance_level(ps, states, 0, 0, dt0, S(stream), launch == MOL_PLAIN, tmode);
+    for (int k = 0; k < nsteps; ++k)
+        if ((rc = advance_level(ps, states, 0, 0, dt0, S(stream), launch == MOL_PLAIN, tmode, k > 0))) return rc;
+    return MOL_OK;
 }
 
 int mol_tag(mol_patchset* ps, int level, const double* U, int field, double threshold, uint8_t* flags_dev,
@@ -2072,8 +2084,15 @@ int mol_autotune(mol_patchset* ps, int level, const mol_level_state* st, double 
 
 int mol_graph_create(mol_patchset* ps, const mol_level_state* states, double dt0, mol_graph** out)
 {
+    return mol_graph_create_steps(ps, states, dt0, 1, out);
+}
+
+int mol_graph_create_steps(mol_patchset* ps, const mol_level_state* states, double dt0, int nsteps,
+                           mol_graph** out)
+{
     if (!ps || !out) return fail(MOL_EINVAL, "null argument");
     *out = nullptr;
+    if (nsteps < 1) return fail(MOL_EINVAL, "nsteps must be at least 1");
     if (!std::isfinite(dt0) || dt0 <= 0.0) return fail(MOL_EINVAL, "dt must be positive and finite");
     int rc = check_states(ps, states);
     if (rc) return rc;
@@ -2089,7 +2108,8 @@ int mol_graph_create(mol_patchset* ps, const mol_level_state* states, double dt0
         delete g;
         return hip_fail(e, "hipStreamBeginCapture");
     }
-    rc = advance_level(ps, states, 0, 0, dt0, ps->capture_stream, 0, MOL_TIME_BOR);
+    for (int k = 0; k < nsteps && !rc; ++k)
+        rc = advance_level(ps, states, 0, 0, dt0, ps->capture_stream, 0, MOL_TIME_BOR, k > 0);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(ps->capture_stream, &graph);
     if (rc || e != hipSuccess) {

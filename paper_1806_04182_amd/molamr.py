@@ -115,7 +115,9 @@ def lib():
             "mol_ccz4_lapse_pulse": ([vp, i, dp, vp, vp], i),
             "mol_ccz4_lapse_pulse_vjp": ([vp, i, dp, vp, vp, vp], i),
             "mol_advance": ([vp, ctypes.POINTER(_LevelState), d, i, vp], i),
+            "mol_advance_steps": ([vp, ctypes.POINTER(_LevelState), d, i, i, vp], i),
             "mol_graph_create": ([vp, ctypes.POINTER(_LevelState), d, ctypes.POINTER(vp)], i),
+            "mol_graph_create_steps": ([vp, ctypes.POINTER(_LevelState), d, i, ctypes.POINTER(vp)], i),
             "mol_graph_launch": ([vp, vp], i),
             "mol_graph_destroy": ([vp], None),
             "mol_tag": ([vp, i, vp, i, d, vp, vp], i),
@@ -383,9 +385,14 @@ class Patchset:
         """One level-0 step; mode = MOL_BATCHED or MOL_PLAIN | MOL_TIME_*."""
         _check(lib().mol_advance(self._h, self._states(states), dt0, mode, _stream(stream)))
 
-    def graph_create(self, states, dt0):
+    def advance_steps(self, states, dt0, nsteps, mode=MOL_BATCHED, stream=None):
+        """nsteps level-0 steps in one call (mol_advance_steps)."""
+        _check(lib().mol_advance_steps(self._h, self._states(states), dt0, nsteps, mode, _stream(stream)))
+
+    def graph_create(self, states, dt0, nsteps=1):
+        """A HIP graph of nsteps level-0 steps (mol_graph_create_steps)."""
         g = ctypes.c_void_p()
-        _check(lib().mol_graph_create(self._h, self._states(states), dt0, ctypes.byref(g)))
+        _check(lib().mol_graph_create_steps(self._h, self._states(states), dt0, nsteps, ctypes.byref(g)))
         return Graph(g)
 
     def period(self, level: int) -> tuple:

@@ -412,3 +412,53 @@ def test_autotune_cache_records_and_reuses_tilings(tmp_path):
     third = M.Patchset(M.Hierarchy(N0, (-1, -1, -1), 2.0 / N0[0], other), sysd)
     assert third.tiling_key(0) == first.tiling_key(0)
     assert third.tiling_key(1) != first.tiling_key(1)
+
+
+@pytest.mark.parametrize("case", ["ccz4_patch", "ccz4_hierarchy", "wave_hierarchy", "mhd_patch_ssp3"])
+def test_multi_step_calls_equal_repeated_steps(case):
+    """mol_advance_steps and mol_graph_create_steps skip the ghost fill of
+    level 0's U before the first stage of every step after the first (the
+    previous step left it filled): three steps in one call, and in one graph
+    launch, equal three single steps bit for bit over whole level buffers."""
+    torch = _torch()
+    print("multi-step", case, flush=True)
+    mode = M.MOL_BATCHED
+    if case.endswith("hierarchy"):
+        system = O.CCZ4 if case.startswith("ccz4") else O.WAVE
+        ps, H, data, levels, dx0 = _setup(system)
+    else:
+        n = (14, 11, 9)
+        dx0 = 2.0 / n[0]
+        if case == "ccz4_patch":
+            st0 = synth.ccz4_lapse_pulse(n, (-1, -1, -1), dx0, amp=0.2, width=0.4)
+            st0 = st0 + synth.ccz4_minkowski_noise(n, amp=1e-2, seed=3) - synth.CCZ4_FLAT[:, None, None, None]
+            sysd = M.System(M.MOL_CCZ4)
+        else:
+            st0 = synth.mhd_ot_like(n, seed=2)
+            sysd = M.System(M.MOL_MHD, sigma=0.0)
+            mode |= M.MOL_ADV_SSPRK3
+        ps = M.Patchset(M.single_patch(n, (-1, -1, -1), dx0), sysd)
+        data = [[synth.embed(st0)]]
+    dt0 = 0.1 * dx0
+    results = []
+    for how in ("single", "multi", "graph"):
+        st = ps.alloc_states()
+        for l, arrs in enumerate(data):
+            st[l]["U"].copy_(torch.from_numpy(ps.pack(l, arrs)))
+        if how == "single":
+            for _ in range(3):
+                ps.advance(st, dt0, mode)
+        elif how == "multi":
+            ps.advance_steps(st, dt0, 3, mode)
+        elif not mode & M.MOL_ADV_SSPRK3:
+            g = ps.graph_create(st, dt0, nsteps=3)
+            g.launch()
+            torch.cuda.synchronize()
+            del g
+        else:
+            continue
+        torch.cuda.synchronize()
+        results.append([s["U"].cpu().numpy() for s in st])
+    for other in results[1:]:
+        for a, b in zip(results[0], other):
+            assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
