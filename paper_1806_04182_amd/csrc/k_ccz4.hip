@@ -12,8 +12,9 @@
 //
 // Kernel organisation (gfx950): one workgroup of 256 threads owns a tile of
 // TX x TY x TZ points.  The 25 fields are streamed through LDS one at a time
-// (tile plus a 3-point halo; the next field's global loads are in flight
-// while the current one is differentiated).  Each field's derivatives are
+// (tile plus a 3-point halo, brought in by 16-byte LDS-DMA loads that write
+// LDS without passing through registers; the next field's halo lands in a
+// second buffer while the current one is differentiated).  Each field's derivatives are
 // consumed as soon as they arrive (Christoffel symbols after the six metric
 // components, Ricci terms after chi and Ghat, the lapse Hessian after alpha,
 // ...), and point values that are needed only late are taken from LDS when
@@ -77,15 +78,34 @@ constexpr int ORDER[NF] = {GT + 0, GT + 1, GT + 2,   GT + 3,   GT + 4,   GT + 5,
                            AT + 1, AT + 2, AT + 3,   AT + 4,   AT + 5,   GH + 0, GH + 1, GH + 2,
                            BETA + 0, BETA + 1, BETA + 2, KH,     TH,     BB + 0, BB + 1, BB + 2};
 
-// LDS geometry of the stage kernel for a TX x TY x TZ tile.  The halo tile's
-// rows are padded to a pitch of PX doubles: a wave reads 8 rows of 8 doubles;
-// with PX = 24 (= 8 mod 16 doubles) every group of rows served in one LDS
-// cycle starts on distinct banks.  Only the halo points a field's stencils
-// read are loaded (below); NR, the passes of a whole-box load with 16 lanes
-// per row, bounds the loads per thread and sizes the staging registers.
+// LDS geometry of the stage kernel for a TX x TY x TZ tile.  Two load paths
+// are compiled: LDS-DMA (the default, MOL_CCZ4_DMA = 1, described below
+// DMA) and loads staged through registers (MOL_CCZ4_DMA = 0), in which the
+// halo tile's rows are padded to a pitch of PX doubles: a wave reads 8 rows
+// of 8 doubles; with PX = 24 (= 8 mod 16 doubles) every group of rows served
+// in one LDS cycle starts on distinct banks.  There only the halo points a
+// field's stencils read are loaded (below); NR, the passes of a whole-box
+// load with 16 lanes per row, bounds the loads per thread and sizes the
+// staging registers.
 #ifndef MOL_CCZ4_PERSISTENT
 #define MOL_CCZ4_PERSISTENT 0
 #endif
+#ifndef MOL_CCZ4_DMA
+#define MOL_CCZ4_DMA 1
+#endif
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// s_waitcnt immediate that waits until at most n vector-memory loads of this
+// wave are outstanding (expcnt and lgkmcnt left unconstrained)
+__device__ constexpr int vm_wait(int n) { return 0x0F70 | n; }
+
+// Workgroup barrier after this wave's LDS accesses have completed.  Unlike
+// __syncthreads() it does not wait for the wave's outstanding vector-memory
+// loads, so LDS-DMA loads of later passes stay in flight across it (the
+// caller waits for the ones the next pass reads); the memory clobber keeps the
+// compiler from moving memory accesses across it.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 template <int TX, int TY, int TZ>
 struct CczLds {
@@ -110,11 +130,27 @@ struct CczLds {
     static constexpr int TPE = 6 * TY + 6 * TX + 16, OPE = 4 * TY + 4 * TX;
     static constexpr int BE = TZ * TPE + 4 * OPE, NB = (BE + NT - 1) / NT;
     static_assert(NZ + NB <= NR, "reduced box does not fit the load pattern");
+    // Direct loads into LDS: the halo box in two buffers of rows of HX
+    // doubles at pitch HX, written by 16-byte LDS-DMA loads (a wave's load
+    // fills 64 consecutive 16-byte chunks, lane l the l-th) while the other
+    // buffer is read.  Each buffer holds the window from row G of the first
+    // plane to row G + TY - 1 of the last, the two planes being read only in
+    // the tile's columns: NCH chunks, NI loads per thread.
+    static constexpr bool DMA = MOL_CCZ4_DMA;
+    static constexpr int CPR = HX / 2, C0 = G * CPR, NCH = ((HZ - 1) * HY + TY) * CPR;
+    static constexpr int NI = (NCH + NT - 1) / NT;
+    // loads per thread that every wave issues (the waves past the end of the
+    // window skip the last one)
+    static constexpr int NIW = (NI - 1) * NT + (NT - 64) < NCH ? NI : NI - 1;
+    static constexpr int NBUF = DMA ? MOL_CCZ4_NBUF : 1;
+    static_assert(NBUF >= 1 && NBUF <= 3 && (DMA || NBUF == 1), "one to three halo buffers");
+    static_assert(HX % 2 == 0, "halo rows must be whole 16-byte chunks");
+    static constexpr int LB = DMA ? 2 * NCH : LV;  // doubles per halo buffer
 };
 
 // fields whose stencils read only along the axes through the point (first
 // derivatives, advection, dissipation): their halo corners are never read
-__device__ constexpr bool single_axis(int f)
+[[maybe_unused]] __device__ constexpr bool single_axis(int f)
 {
     return (f >= KH && f < GH + 3) || f == TH || (f >= BB && f < BB + 3);
 }
@@ -124,15 +160,21 @@ __device__ constexpr bool single_axis(int f)
 // through LDS; akx: advection + dissipation of every field.
 template <int TX, int TY, int TZ, bool UPWIND>
 __device__ __forceinline__ void ccz4_tile(const StageArgs& a, const CczConst& C, int tidx, double* __restrict__ buf,
+                                          double* __restrict__ buf2, double* __restrict__ buf3,
                                           double (*__restrict__ akx)[TX * TY * TZ])
 {
     using L = CczLds<TX, TY, TZ>;
-    constexpr int HY = L::HY, HZ = L::HZ, PX = L::PX, NT = L::NT, NR = L::NR;
+    constexpr bool DMA = L::DMA;
+    constexpr int HY = L::HY, HZ = L::HZ, PX = DMA ? L::HX : L::PX, NT = L::NT, NR = L::NR;
 
     const Tile tile = a.tiles[tidx];
     const PatchDev P = a.patches[tile.patch];
-    const int tx = threadIdx.x, ty = threadIdx.y, tz = threadIdx.z;
-    const int tid = tx + TX * (ty + TY * tz);
+    const int tx = threadIdx.x, tz = threadIdx.z;
+    const int tid = tx + TX * ((int)threadIdx.y + TY * tz);
+    // With the halo rows at a pitch of 14 doubles, the two rows that one LDS
+    // cycle serves for a wave's 8 x 8 reads (lanes 16 m .. 16 m + 15) are
+    // rows y and y + 4, whose 64-byte segments fall on disjoint banks
+    const int ty = (DMA && TY == 8) ? (((int)threadIdx.y >> 1) | (((int)threadIdx.y & 1) << 2)) : (int)threadIdx.y;
     const bool valid = tile.o[0] + tx < P.n[0] && tile.o[1] + ty < P.n[1] && tile.o[2] + tz < P.n[2];
     // halo tile origin = tile origin - 3 in interior coordinates = tile origin in ghosted coordinates
     const int64_t hbase = P.off + (int64_t)tile.o[2] * P.pitch_z + (int64_t)tile.o[1] * P.pitch_y + tile.o[0];
@@ -261,6 +303,30 @@ __device__ __forceinline__ void ccz4_tile(const StageArgs& a, const CczConst& C,
         }
     };
 
+    // LDS-DMA loads of the halo window: chunk j = r NT + tid, offsets from the
+    // tile's halo origin (0, the origin itself, for chunks outside the
+    // ghosted box, which only the stencils of points outside the patch read)
+    int doff[DMA ? L::NI : 1];
+    if constexpr (DMA) {
+#pragma unroll
+        for (int r = 0; r < L::NI; ++r) {
+            const int j = r * NT + tid, ac = j + L::C0, row = ac / L::CPR, cc = ac - row * L::CPR;
+            const int hz = row / HY, hy = row - hz * HY;
+            const bool ok = j < L::NCH && tile.o[0] + 2 * cc < P.n[0] + 2 * G &&
+                            tile.o[1] + hy < P.n[1] + 2 * G && hz < hzmax;
+            doff[r] = ok ? hz * P.pitch_z + hy * P.pitch_y + 2 * cc : 0;
+        }
+    }
+    auto dma = [&](int f, double* dst) __attribute__((always_inline)) {
+        const double* src = a.Us + hbase + (int64_t)f * fs;
+        const int wbase = tid & ~63;  // first chunk of this wave's window of 64
+#pragma unroll
+        for (int r = 0; r < L::NI; ++r)
+            if ((r + 1) * NT <= L::NCH || r * NT + tid < L::NCH)
+                __builtin_amdgcn_global_load_lds((const void*)(src + doff[r]), (lds_void*)(dst + 2 * (r * NT + wbase)),
+                                                 16, 0, 0);
+    };
+
     // ---- point values needed from the first pass on (global loads) ----
     const double* __restrict__ u = a.Us + c;
     const double chi = u[CHI * fs];
@@ -298,23 +364,38 @@ __device__ __forceinline__ void ccz4_tile(const StageArgs& a, const CczConst& C,
     double rG[3];                       // Ghat^i terms with d Khat and d Theta
     double alp, A[6], Au[6], Kh, Th, Bv[3];  // point values taken from LDS, At^{ij}
     const int S[3] = {1, PX, PX * HY};
+    // this point in the halo buffer
+    const int ctr = ((tz + G) * HY + ty + G) * PX + tx + G - (DMA ? 2 * L::C0 : 0);
 
-    gload(ORDER[0]);
-    lstore();
+    // halo buffer of pass q
+    constexpr int NBUF = L::NBUF;
+    auto hbuf = [&](int q) __attribute__((always_inline)) {
+        return q % NBUF == 0 ? buf : (q % NBUF == 1 ? buf2 : buf3);
+    };
+    if constexpr (DMA) {
+#pragma unroll
+        for (int q = 0; q + 1 < NBUF; ++q) dma(ORDER[q], hbuf(q));
+        __builtin_amdgcn_s_waitcnt(vm_wait(NBUF == 3 ? L::NIW : 0));
+    } else {
+        gload(ORDER[0]);
+        lstore();
+    }
     __syncthreads();
     // one pass per field, expanded at compile time so that every branch and
     // array index below is a constant
     auto pass = [&](auto qc) __attribute__((always_inline)) {
         constexpr int q = decltype(qc)::value;
         constexpr int f = ORDER[q];
-        if constexpr (q + 1 < NF) {
+        if constexpr (DMA) {
+            if constexpr (q + NBUF - 1 < NF) dma(ORDER[q + NBUF - 1], hbuf(q + NBUF - 1));
+        } else if constexpr (q + 1 < NF) {
             if constexpr (single_axis(ORDER[q + 1]))
                 gload_x(ORDER[q + 1]);
             else
                 gload(ORDER[q + 1]);
         }
         if (valid) {
-            const double* t = &buf[((tz + G) * HY + ty + G) * PX + tx + G];
+            const double* t = hbuf(q) + ctr;
             // advection beta^k d_k and KO dissipation of every field; first
             // and pure second derivatives from the same combinations
             constexpr bool second = (f >= GT && f < GT + 6) || f == CHI || f == ALP || (f >= BETA && f < BETA + 3);
@@ -532,13 +613,21 @@ __device__ __forceinline__ void ccz4_tile(const StageArgs& a, const CczConst& C,
                 Bv[f - BB] = t[0];
             }
         }
-        __syncthreads();
-        if constexpr (q + 1 < NF) {
-            if constexpr (single_axis(ORDER[q + 1]))
-                lstore_x();
-            else
-                lstore();
+        if constexpr (DMA) {
+            // the next field's halo has arrived (the loads of the field after
+            // it may still be in flight), and every wave is done with this
+            // buffer before the load issued in the pass NBUF - 1 ahead refills it
+            if constexpr (q + 1 < NF) __builtin_amdgcn_s_waitcnt(vm_wait(NBUF == 3 && q + 2 < NF ? L::NIW : 0));
+            lds_barrier();
+        } else {
             __syncthreads();
+            if constexpr (q + 1 < NF) {
+                if constexpr (single_axis(ORDER[q + 1]))
+                    lstore_x();
+                else
+                    lstore();
+                __syncthreads();
+            }
         }
     };
     [&]<int... Q>(std::integer_sequence<int, Q...>) {
@@ -649,9 +738,11 @@ template <int TX, int TY, int TZ, bool UPWIND>
 __global__ __launch_bounds__(TX * TY * TZ, MOL_CCZ4_WAVES) void ccz4_stage_kernel(StageArgs a, CczConst C)
 {
     using L = CczLds<TX, TY, TZ>;
-    __shared__ double buf[L::LV];
+    __shared__ double buf[L::LB];
+    __shared__ double buf2[L::NBUF >= 2 ? L::LB : 1];
+    __shared__ double buf3[L::NBUF >= 3 ? L::LB : 1];
     __shared__ double akx[NF][L::NT];
-    ccz4_tile<TX, TY, TZ, UPWIND>(a, C, xcd_tile(blockIdx.x, gridDim.x), buf, akx);
+    ccz4_tile<TX, TY, TZ, UPWIND>(a, C, xcd_tile(blockIdx.x, gridDim.x), buf, buf2, buf3, akx);
 }
 
 // Persistent form: a grid of at most as many workgroups as are resident at
@@ -663,7 +754,9 @@ template <int TX, int TY, int TZ, bool UPWIND>
 __global__ __launch_bounds__(TX * TY * TZ, MOL_CCZ4_WAVES) void ccz4_stage_persistent_kernel(StageArgs a, CczConst C)
 {
     using L = CczLds<TX, TY, TZ>;
-    __shared__ double buf[L::LV];
+    __shared__ double buf[L::LB];
+    __shared__ double buf2[L::NBUF >= 2 ? L::LB : 1];
+    __shared__ double buf3[L::NBUF >= 3 ? L::LB : 1];
     __shared__ double akx[NF][L::NT];
     constexpr int NXCD = 8;
     const int n = a.ntiles, x = blockIdx.x % NXCD, slot = blockIdx.x / NXCD;
@@ -671,7 +764,7 @@ __global__ __launch_bounds__(TX * TY * TZ, MOL_CCZ4_WAVES) void ccz4_stage_persi
     const int lo = x * per + (x < rem ? x : rem), hi = lo + per + (x < rem ? 1 : 0);
     const int nwg = ((int)gridDim.x - x + NXCD - 1) / NXCD;  // workgroups of this XCD
     for (int t = lo + slot; t < hi; t += nwg) {
-        ccz4_tile<TX, TY, TZ, UPWIND>(a, C, t, buf, akx);
+        ccz4_tile<TX, TY, TZ, UPWIND>(a, C, t, buf, buf2, buf3, akx);
         __syncthreads();  // the next tile overwrites buf and akx
     }
 }

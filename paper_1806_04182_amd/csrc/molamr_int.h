@@ -26,9 +26,11 @@ constexpr int G = MOL_GHOST;
 #define MOL_CCZ4_TY 8
 #define MOL_CCZ4_TZ 4
 #endif
-// LDS halo buffers of the CCZ4 kernel and its minimum waves per SIMD
+// LDS halo buffers of the CCZ4 kernel (the halo of the field NBUF - 1 passes
+// ahead is requested while a field is differentiated) and its minimum waves
+// per SIMD
 #ifndef MOL_CCZ4_NBUF
-#define MOL_CCZ4_NBUF 1
+#define MOL_CCZ4_NBUF 2
 #endif
 #ifndef MOL_CCZ4_WAVES
 #define MOL_CCZ4_WAVES 2
