@@ -422,8 +422,10 @@ int mol_advance(mol_patchset* ps, const mol_level_state* states, double dt0, int
                 void* stream);
 /* nsteps >= 1 consecutive mol_advance steps.  Every step leaves level 0's U
  * with filled ghosts, so the steps after the first skip the ghost fill of U
- * before their first stage; the results are those of nsteps mol_advance
- * calls bit for bit.  MOL_EINVAL when nsteps < 1. */
+ * before their first stage; on a wave level that is one periodic patch, whose
+ * stages read periodic images instead of ghosts, only the last step fills
+ * U's ghosts.  The results are those of nsteps mol_advance calls bit for bit
+ * (ghost cells of the end state included).  MOL_EINVAL when nsteps < 1. */
 int mol_advance_steps(mol_patchset* ps, const mol_level_state* states, double dt0, int nsteps, int mode,
                       void* stream);
 
@@ -475,7 +477,9 @@ typedef struct {
  * thread tiles of the point-wise one; MHD: z-chunks 4..32; CCZ4: tiles
  * 8 x 8 x 4, 8 x 8 x 8 and 8 x 4 x 8) and tile orders (0 and 1; CCZ4 also 2
  * and 3), `reps` launches each (RK4 stage 2 with U as
- * U^n, S0 as stage state, acc and S1 overwritten), and keep the fastest for
+ * U^n, S0 as stage state, acc and S1 overwritten; the kernel variant the
+ * driver launches on the level: periodic stencil reads on a wave level that is
+ * one periodic patch, ghost-image stores on such a CCZ4 level), and keep the fastest for
  * the level's later stage launches; *best (nullable) receives it.  The
  * results of a stage do not depend on the tiling.  Synchronises the stream;
  * graphs created before keep the tiling they captured. */

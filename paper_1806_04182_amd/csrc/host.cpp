@@ -1043,8 +1043,11 @@ int restrict_impl(mol_patchset* ps, int fl, const double* Uf, double* Uc, hipStr
 // tmode: MOL_TIME_* or-ed with MOL_ADV_SSPRK3 for SSP-RK3 steps
 // u_filled: the level's U already has its same-level ghosts (a later step
 // of a multi-step call: every step leaves U filled)
+// last: the last step of the call; on a level whose stages read periodic
+// images (wrap) the fill of the new U is needed only for the caller, so the
+// earlier steps of a multi-step call skip it
 int advance_level(mol_patchset* ps, const mol_level_state* st, int l, int r, double dt,
-                  hipStream_t s, int plain, int tmode, bool u_filled = false)
+                  hipStream_t s, int plain, int tmode, bool u_filled = false, bool last = true)
 {
     const mol_level_state& X = st[l];
     const bool kids = l + 1 < ps->nlev;
@@ -1089,7 +1092,7 @@ int advance_level(mol_patchset* ps, const mol_level_state* st, int l, int r, dou
                                       hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
     }
-    return images ? MOL_OK : fill_impl(ps, l, X.U, nf, s, plain);
+    return (images || (wrap && !last)) ? MOL_OK : fill_impl(ps, l, X.U, nf, s, plain);
 }
 
 int check_states(const mol_patchset* ps, const mol_level_state* st)
@@ -1704,7 +1707,8 @@ int mol_advance_steps(mol_patchset* ps, const mol_level_state* states, double dt
     int rc = check_states(ps, states);
     if (rc) return rc;
     for (int k = 0; k < nsteps; ++k)
-        if ((rc = advance_level(ps, states, 0, 0, dt0, S(stream), launch == MOL_PLAIN, tmode, k > 0))) return rc;
+        if ((rc = advance_level(ps, states, 0, 0, dt0, S(stream), launch == MOL_PLAIN, tmode, k > 0, k + 1 == nsteps)))
+            return rc;
     return MOL_OK;
 }
 
@@ -2043,7 +2047,8 @@ int mol_autotune(mol_patchset* ps, int level, const mol_level_state* st, double 
     win.ms = -1.0;
     const TileList keep = lev.tiles;
     rc = MOL_OK;
-    const bool wrap = level_wraps(ps, level);
+    // the kernel variant the driver launches on this level
+    const bool wrap = level_wraps(ps, level), images = level_images(ps, level);
     // tile orders: patches as listed or largest first; for CCZ4 also the
     // column orders (the wave and MHD kernels march along z already)
     const int last_order = ps->sp.system == MOL_CCZ4 ? 3 : 1;
@@ -2053,10 +2058,11 @@ int mol_autotune(mol_patchset* ps, int level, const mol_level_state* st, double 
             if ((rc = build_tiles(lev, td.data(), 0, tl, nullptr, order))) break;
             lev.tiles = tl;
             // RK4 stage 2: reads U, S0 and acc, writes acc and S1
-            rc = stage_impl(ps, level, ST_RK4, 2, dt, st->U, st->S0, st->acc, st->S1, nullptr, s, 0, wrap);
+            rc = stage_impl(ps, level, ST_RK4, 2, dt, st->U, st->S0, st->acc, st->S1, nullptr, s, 0, wrap, images);
             if (rc == MOL_OK && (e = hipEventRecord(e0, s)) != hipSuccess) rc = hip_fail(e, "hipEventRecord");
             for (int r = 0; r < reps && rc == MOL_OK; ++r)
-                rc = stage_impl(ps, level, ST_RK4, 2, dt, st->U, st->S0, st->acc, st->S1, nullptr, s, 0, wrap);
+                rc = stage_impl(ps, level, ST_RK4, 2, dt, st->U, st->S0, st->acc, st->S1, nullptr, s, 0, wrap,
+                                images);
             float ms = 0.0f;
             if (rc == MOL_OK && (e = hipEventRecord(e1, s)) != hipSuccess) rc = hip_fail(e, "hipEventRecord");
             if (rc == MOL_OK && (e = hipEventSynchronize(e1)) != hipSuccess) rc = hip_fail(e, "hipEventSynchronize");
@@ -2109,7 +2115,7 @@ int mol_graph_create_steps(mol_patchset* ps, const mol_level_state* states, doub
         return hip_fail(e, "hipStreamBeginCapture");
     }
     for (int k = 0; k < nsteps && !rc; ++k)
-        rc = advance_level(ps, states, 0, 0, dt0, ps->capture_stream, 0, MOL_TIME_BOR, k > 0);
+        rc = advance_level(ps, states, 0, 0, dt0, ps->capture_stream, 0, MOL_TIME_BOR, k > 0, k + 1 == nsteps);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(ps->capture_stream, &graph);
     if (rc || e != hipSuccess) {

@@ -414,12 +414,15 @@ def test_autotune_cache_records_and_reuses_tilings(tmp_path):
     assert third.tiling_key(1) != first.tiling_key(1)
 
 
-@pytest.mark.parametrize("case", ["ccz4_patch", "ccz4_hierarchy", "wave_hierarchy", "mhd_patch_ssp3"])
+@pytest.mark.parametrize("case", ["ccz4_patch", "ccz4_hierarchy", "wave_hierarchy", "mhd_patch_ssp3", "wave_patch",
+                                  "wave_patch_ssp3"])
 def test_multi_step_calls_equal_repeated_steps(case):
     """mol_advance_steps and mol_graph_create_steps skip the ghost fill of
     level 0's U before the first stage of every step after the first (the
-    previous step left it filled): three steps in one call, and in one graph
-    launch, equal three single steps bit for bit over whole level buffers."""
+    previous step left it filled), and on a periodic wave patch, whose stages
+    read periodic images, the fill after every step but the last: three steps
+    in one call, and in one graph launch, equal three single steps bit for
+    bit over whole level buffers."""
     torch = _torch()
     print("multi-step", case, flush=True)
     mode = M.MOL_BATCHED
@@ -433,6 +436,11 @@ def test_multi_step_calls_equal_repeated_steps(case):
             st0 = synth.ccz4_lapse_pulse(n, (-1, -1, -1), dx0, amp=0.2, width=0.4)
             st0 = st0 + synth.ccz4_minkowski_noise(n, amp=1e-2, seed=3) - synth.CCZ4_FLAT[:, None, None, None]
             sysd = M.System(M.MOL_CCZ4)
+        elif case.startswith("wave"):
+            st0 = np.random.default_rng(4).standard_normal((2,) + n[::-1])
+            sysd = M.System(M.MOL_WAVE, sigma=0.1)
+            if case.endswith("ssp3"):
+                mode |= M.MOL_ADV_SSPRK3
         else:
             st0 = synth.mhd_ot_like(n, seed=2)
             sysd = M.System(M.MOL_MHD, sigma=0.0)
