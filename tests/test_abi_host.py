@@ -152,3 +152,19 @@ def test_adjoint_steps_reject_null_patchset():
     assert L.mol_rk4_adjoint_step(None, 0, 0.1, None, None, w, None, None) == -1  # MOL_EINVAL
     assert L.mol_rk4_adjoint_step_stages(None, 0, 0.1, st, None, w, None, None) == -1
     assert "null patchset" in M.lib().mol_last_error().decode()
+
+
+def test_register_staged_ccz4_loads_still_compile(tmp_path):
+    """The CCZ4 stage kernel's alternative load path (halo loads staged
+    through registers, -DMOL_CCZ4_DMA=0; the default path uses LDS-DMA loads)
+    cross-compiles for the GPU without warnings, so the comparison build
+    stays available."""
+    import subprocess
+    from paper_1806_04182_amd import build as B
+    src = os.path.join(B.CSRC, "k_ccz4.hip")
+    cmd = [B.HIPCC, *B.FLAGS, "-DMOL_CCZ4_DMA=0", "--cuda-device-only", "-x", "hip", "-c", src,
+           "-o", str(tmp_path / "k_ccz4_staged.o")]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    warnings = [l for l in r.stderr.splitlines() if "warning:" in l and "packed-fp32-ops" not in l]
+    assert not warnings, warnings
