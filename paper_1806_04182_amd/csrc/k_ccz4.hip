@@ -668,15 +668,39 @@ __device__ __forceinline__ void ccz4_tile(const StageArgs& a, const CczConst& C,
             im[d] = q[d] < G ? (int64_t)P.n[d] * sd[d] : (q[d] >= P.n[d] - G ? -(int64_t)P.n[d] * sd[d] : 0);
     }
     const bool img = (im[0] | im[1] | im[2]) != 0;
+    // the stage update of every field as straight-line code (stage_update)
+    const StageCoef sc = stage_coef(a);
+    double* pout = a.out;
+    // Fields in the order of the out() calls below; the stage inputs of the
+    // field PD calls ahead are requested before a field's update is stored,
+    // so that their memory latency overlaps the algebra in between.
+    constexpr int OUTORD[NF] = {GT,     GT + 1, GT + 2, GT + 3, GT + 4,   GT + 5, AT,     AT + 1, AT + 2,
+                                AT + 3, AT + 4, AT + 5, CHI,    KH,       TH,     GH,     BB,     BETA,
+                                GH + 1, BB + 1, BETA + 1, GH + 2, BB + 2, BETA + 2, ALP};
+    constexpr int PD = 3;
+    double pu[PD], pv[PD];
+    auto pref = [&](int p) __attribute__((always_inline)) {
+        if (p < NF) {
+            const int64_t i = c + (int64_t)OUTORD[p] * fs;
+            pu[p % PD] = sc.pun[i];
+            pv[p % PD] = sc.pw[i];
+        }
+    };
+#pragma unroll
+    for (int p = 0; p < PD; ++p) pref(p);
+    int pos = 0;
     auto out = [&](int f, double phys) __attribute__((always_inline)) {
         const int64_t idx = c + (int64_t)f * fs;
-        const double v = stage_value(a, idx, phys + akx[f][tid], stage_load(a, idx));
-        a.out[idx] = v;
+        const double un = pu[pos % PD], w = pv[pos % PD];
+        pref(pos + PD);
+        ++pos;
+        const double v = stage_update(a, sc, idx, phys + akx[f][tid], un, w);
+        pout[idx] = v;
         if (img)
 #pragma unroll
             for (int m = 1; m < 8; ++m)
                 if (((m & 1) == 0 || im[0]) && ((m & 2) == 0 || im[1]) && ((m & 4) == 0 || im[2]))
-                    a.out[idx + ((m & 1) ? im[0] : 0) + ((m & 2) ? im[1] : 0) + ((m & 4) ? im[2] : 0)] = v;
+                    pout[idx + ((m & 1) ? im[0] : 0) + ((m & 2) ? im[1] : 0) + ((m & 4) ? im[2] : 0)] = v;
     };
 
     // d_t gt_ij

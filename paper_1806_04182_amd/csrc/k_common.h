@@ -107,6 +107,51 @@ __device__ __forceinline__ double stage_value(const StageArgs& a, int64_t idx, d
     }
 }
 
+// The same updates as straight-line code, for kernels that request a point's
+// stage inputs ahead of its right-hand side: with k = dt rhs,
+// v = al un + bt (w2 + de k), w2 the accumulator (RK4 stage 4) or the stage
+// state (SSP-RK3 stages 2, 3), else 0; the new accumulator of RK4 stages 1-3
+// is w3 + ep k, w3 the accumulator (stages 2, 3) or 0.  The coefficients and
+// the two arrays read (un from pun, w from pw) are uniform per launch; a read
+// that a stage does not use is discarded (w then repeats the read of un, un in
+// a right-hand-side launch reads the output array), so that the loads need no
+// branch and add no traffic.
+struct StageCoef {
+    bool rhs_only, use_w2, use_w3, st_acc;
+    double al, bt, de, ep;
+    const double* pun;
+    const double* pw;
+};
+__device__ __forceinline__ StageCoef stage_coef(const StageArgs& a)
+{
+    StageCoef s;
+    const bool rk4 = a.mode == ST_RK4;
+    const int n = a.stage;
+    s.rhs_only = a.mode == ST_RHS;
+    s.al = rk4 ? 1.0 : (n == 1 ? 1.0 : (n == 2 ? 0.75 : 1.0 / 3.0));
+    s.bt = rk4 ? 1.0 : (n == 1 ? 1.0 : (n == 2 ? 0.25 : 2.0 / 3.0));
+    s.de = rk4 ? (n <= 2 ? 0.5 : (n == 3 ? 1.0 : 1.0 / 6.0)) : 1.0;
+    s.ep = n == 1 ? 1.0 / 6.0 : 1.0 / 3.0;
+    s.use_w2 = !s.rhs_only && (rk4 ? n == 4 : n >= 2);
+    s.use_w3 = rk4 && (n == 2 || n == 3);
+    s.st_acc = rk4 && n <= 3;
+    s.pun = s.rhs_only ? a.out : a.Un;
+    s.pw = s.use_w2 ? (rk4 ? a.acc : a.Us) : (s.use_w3 ? a.acc : s.pun);
+    return s;
+}
+// stage value at idx from the right-hand side and the inputs un = pun[idx],
+// w = pw[idx]; writes k and the accumulator where the stage has them
+__device__ __forceinline__ double stage_update(const StageArgs& a, const StageCoef& s, int64_t idx, double rhs,
+                                               double un, double w)
+{
+    const double k = a.dt * rhs;
+    const double w2 = s.use_w2 ? w : 0.0, w3 = s.use_w3 ? w : 0.0;
+    const double v = s.rhs_only ? rhs : s.al * un + s.bt * (w2 + s.de * k);
+    if (a.kst && !s.rhs_only) a.kst[idx] = k;
+    if (s.st_acc) a.acc[idx] = w3 + s.ep * k;
+    return v;
+}
+
 template <bool NT = false>
 __device__ __forceinline__ void stage_apply(const StageArgs& a, int64_t idx, double rhs, const StageIn& v)
 {
