@@ -22,8 +22,11 @@
  *    dissipation (dissipation is added to every field separately);
  *  - ln det gt is evaluated as log1p(d) with d = det(I+h) - 1 expanded in
  *    h = gt - I, which is the same number written without cancellation.
- *  The terms proportional to Theta or Z vanish on the constraint surface and
- *  have no independent pin: parity unpinned beyond this oracle.
+ *  The terms proportional to Theta or Z vanish on the constraint surface;
+ *  they are pinned off it by the covariant Z4 equation of Sec. V on a
+ *  time-symmetric slice (Z^i from Ghat != Gt, the kappa_z, Theta-gradient and
+ *  Z.grad(alpha) terms) and on a homogeneous, spatially flat metric (the terms
+ *  quadratic in trK and Theta), and the shift terms by the Lie derivative.
  */
 #include <math.h>
 #include <stdlib.h>
