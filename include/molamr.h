@@ -33,11 +33,12 @@
  * Field layout of a level buffer: patch p starts at patch_offsets[p]; from
  * there, field f starts at f * fstride_p, and point (i, j, k) of the ghosted
  * box (0 <= i < nx+6, ...) is at (k * (ny+6) + j) * px_p + i, where the row
- * pitch px_p = nx+6 rounded up to a multiple of 8 doubles and fstride_p =
- * px_p (ny+6)(nz+6) rounded up to a multiple of 32 doubles.  Patch offsets
- * are 5 more than a multiple of 32 doubles, so that every interior row
- * (i = 3) starts on a 64-byte boundary; the doubles between rows are padding
- * that no call reads as data.
+ * pitch px_p = nx+6 rounded up to a multiple of 8 doubles (of 16 when
+ * nx+6 >= 256) and fstride_p = px_p (ny+6)(nz+6) rounded up to a multiple of
+ * 32 doubles.  Patch offsets are 5 (13 when px_p is rounded to 16) more than
+ * a multiple of 32 doubles, so that every interior row (i = 3) starts on a
+ * 64-byte (128-byte) boundary, for a buffer that itself starts on one; the
+ * doubles between rows are padding that no call reads as data.
  */
 #ifndef MOLAMR_H
 #define MOLAMR_H
