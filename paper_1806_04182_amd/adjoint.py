@@ -96,24 +96,32 @@ class Ccz4LapseObjective(torch.autograd.Function):
         w = [ps.alloc(0) for _ in range(3)]
         work = ps.alloc_work(0)
         ps.sphere_adjoint(0, ALPHA, ctx.radius, float(gJ), lam)
-        U = ps.alloc(0)
         acc = ps.alloc(0)
         nseg = (ctx.nsteps + ctx.every - 1) // ctx.every
         # the four stage states of every step of one segment, allocated once
         # and reused by every segment
         kept = [[ps.alloc(0) for _ in range(4)] for _ in range(min(ctx.every, ctx.nsteps))]
+        # on a level that is one periodic patch of at least 6 points per axis
+        # the stage kernel writes the periodic ghost images of its output
+        # (the values the ghost fill would copy), so no fill is needed there
+        dims = ps.layouts[0]["dims"]
+        images = ps.nlev == 1 and len(dims) == 1 and min(dims[0]) >= 6 and not ps.hier.open
         for k in reversed(range(nseg)):
             steps = min(ctx.every, ctx.nsteps - k * ctx.every)
             # the segment recomputed from its checkpoint with the forward
             # stages (the kernels and order of mol_advance), keeping the four
-            # stage states of every step (ghosts filled) for the reverse steps
-            U.copy_(ctx.ckpts[k])
-            for stages in kept[:steps]:
-                stages[0].copy_(U)
+            # stage states of every step (ghosts filled) for the reverse
+            # steps; each step's last stage writes the next step's U^n, and
+            # the segment's last step stops after its fourth stage state
+            kept[0][0].copy_(ctx.ckpts[k])
+            for j, stages in enumerate(kept[:steps]):
                 for s in range(1, 5):
-                    out = stages[s] if s < 4 else U
+                    if s == 4 and j + 1 == steps:
+                        break
+                    out = stages[s] if s < 4 else kept[j + 1][0]
                     ps.rk_stage(0, M.MOL_RK4, s, ctx.dt, stages[0], stages[s - 1], acc, out)
-                    ps.fill_ghosts(0, out)
+                    if not images:
+                        ps.fill_ghosts(0, out)
             for stages in reversed(kept[:steps]):
                 ps.rk4_adjoint_step_stages(0, ctx.dt, lam, w, stages=stages, work=work)
         del kept

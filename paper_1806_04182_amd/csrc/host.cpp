@@ -401,8 +401,8 @@ int build_tiles(const Level& lev, const int td[3], int margin, TileList& tl, Are
 
 // Tile of the stage kernels (the autotuner can replace it).  Wave: levels of
 // at least 2^21 points march along z (64 x 8 columns; chunk length for about
-// 512 workgroups, at most 128 planes: the fastest measured at 256^3 (64
-// planes) and 512^3 (128 planes));
+// 512 workgroups, two per compute unit: the fastest measured at 256^3 (64
+// planes) and 512^3 (whole 512-plane columns, no chunk-boundary re-reads));
 // smaller levels use one thread per point.  MHD: 15 x 15 columns, 4 planes.
 void default_tile(int system, int64_t level_points, int td[3])
 {
@@ -1968,7 +1968,7 @@ std::vector<std::array<int, 3>> tiling_candidates(int system)
     std::vector<std::array<int, 3>> c;
     switch (system) {
     case MOL_WAVE:
-        for (int z : {4, 8, 16, 32, 64, 128}) c.push_back({MOL_WAVE_WX, MOL_WAVE_WY, z});
+        for (int z : {4, 8, 16, 32, 64, 128, 256, 512}) c.push_back({MOL_WAVE_WX, MOL_WAVE_WY, z});
         c.push_back({32, 4, 2});
         c.push_back({64, 4, 1});
         c.push_back({16, 8, 2});

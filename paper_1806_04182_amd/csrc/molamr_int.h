@@ -18,7 +18,7 @@ constexpr int G = MOL_GHOST;
 #define MOL_WAVE_WY 8
 #endif
 #ifndef MOL_WAVE_ZMAX
-#define MOL_WAVE_ZMAX 128
+#define MOL_WAVE_ZMAX 1024
 #endif
 // tile of the CCZ4 stage kernel (threads per workgroup = product)
 #ifndef MOL_CCZ4_TX
