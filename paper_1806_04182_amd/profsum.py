@@ -29,7 +29,9 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-COMMON = ("k_common.h", "molamr_int.h")
+# host.cpp fixes the level layout (row pitches, alignment) and the default
+# launch shapes, which change the bytes a stage kernel moves
+COMMON = ("k_common.h", "molamr_int.h", "host.cpp")
 CCZ4_SOURCES = ("k_ccz4.hip",) + COMMON
 COPY_BYTES = 1 << 30
 COUNTERS = ("FETCH_SIZE", "WRITE_SIZE", "SQ_INSTS_VALU_FLOPS_FP64")
