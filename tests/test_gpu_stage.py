@@ -19,12 +19,15 @@ def _torch():
     return torch
 
 
-def _gpu_steps(system, scheme, U0, h, dt, nsteps, sysd):
-    """nsteps full steps on one periodic patch: fill + fused stages."""
+def _gpu_steps(system, scheme, U0, h, dt, nsteps, sysd, tiling=None):
+    """nsteps full steps on one periodic patch: fill + fused stages (with
+    `tiling`, that launch shape instead of the default)."""
     torch = _torch()
     nf, NZ, NY, NX = U0.shape
     n = (NX - 6, NY - 6, NZ - 6)
     ps = M.Patchset(M.single_patch(n, (0, 0, 0), h), sysd)
+    if tiling is not None:
+        ps.set_tiling(0, tiling)
     dev = lambda a: torch.from_numpy(ps.pack(0, [a])).cuda()
     U = dev(U0)
     S0, S1, acc = ps.alloc(0), ps.alloc(0), ps.alloc(0)
@@ -61,6 +64,23 @@ def test_wave_rk4_parity(n):
     nsteps = 20 if n == (32, 32, 32) else (1 if n[0] > 100 else 3)
     got = _gpu_steps(O.WAVE, M.MOL_RK4, U0, dx, 0.25 * dx, nsteps, M.System(M.MOL_WAVE, sigma=0.1))
     ref = _oracle_steps(O.WAVE, O.RK4, U0, dx, 0.25 * dx, nsteps, O.params(sigma=0.1))
+    e = parity_err(got[:, 3:-3, 3:-3, 3:-3], ref[:, 3:-3, 3:-3, 3:-3])
+    assert np.all(e <= TOL), e
+
+
+@pytest.mark.parametrize("zc", [125, 1024, 7])
+def test_wave_zmarch_chunk_lengths(zc):
+    """The z-marching kernel with chunks of the whole column (125 planes, the
+    default shape of large levels), longer than the column, and a ragged
+    7-plane chunking: one RK4 step against the oracle, element by element."""
+    print("wave rk4 zmarch chunk", zc, flush=True)
+    n = (131, 130, 125)
+    dx = 2.0 / n[0]
+    U0 = synth.embed(synth.wave_gaussian(n, (-1, -1, -1), dx, centre=synth.wave_centre(1),
+                                         period=(n[0] * dx, n[1] * dx, n[2] * dx)))
+    got = _gpu_steps(O.WAVE, M.MOL_RK4, U0, dx, 0.25 * dx, 1, M.System(M.MOL_WAVE, sigma=0.1),
+                     tiling=(64, 8, zc))
+    ref = _oracle_steps(O.WAVE, O.RK4, U0, dx, 0.25 * dx, 1, O.params(sigma=0.1))
     e = parity_err(got[:, 3:-3, 3:-3, 3:-3], ref[:, 3:-3, 3:-3, 3:-3])
     assert np.all(e <= TOL), e
 
@@ -346,3 +366,24 @@ def test_fill_ghosts_periodic_parity():
         ref = a.copy()
         O.fill_periodic(ref)
         assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("n", [(40, 9, 8), (249, 8, 8), (250, 8, 8), (262, 7, 9)])
+def test_level_layout_row_alignment(n):
+    """Interior rows (ghosted x index 3) start on 64-byte boundaries, and on
+    128-byte boundaries when a ghosted row holds at least 256 doubles; the
+    field stride is a multiple of 32 doubles and a level buffer from the
+    caching allocator starts on a 256-byte boundary."""
+    torch = _torch()
+    ps = M.Patchset(M.single_patch(n, (-1, -1, -1), 2.0 / n[0]), M.System(M.MOL_WAVE))
+    L = ps.layouts[0]
+    px, fs, off = L["pitches"][0], L["fstrides"][0], L["offsets"][0]
+    align = 16 if n[0] + 6 >= 256 else 8
+    assert px >= n[0] + 6 and px % align == 0 and fs % 32 == 0
+    assert fs >= px * (n[1] + 6) * (n[2] + 6)
+    for f in range(ps.nf):
+        for k in range(n[2]):
+            for j in range(n[1]):
+                row = off + f * fs + ((k + 3) * (n[1] + 6) + j + 3) * px + 3
+                assert row % align == 0, (f, j, k)
+    assert ps.alloc(0).data_ptr() % 256 == 0
