@@ -474,7 +474,7 @@ typedef struct {
     double ms;   /* measured time of one stage launch (mol_autotune) */
 } mol_tiling;
 /* Time the batched stage kernel of `level` under every candidate launch shape
- * of the system (wave: z-chunks 4..128 of the z-marching kernel and five
+ * of the system (wave: z-chunks 4..512 of the z-marching kernel and five
  * thread tiles of the point-wise one; MHD: z-chunks 4..32; CCZ4: tiles
  * 8 x 8 x 4, 8 x 8 x 8 and 8 x 4 x 8) and tile orders (0 and 1; CCZ4 also 2
  * and 3), `reps` launches each (RK4 stage 2 with U as
