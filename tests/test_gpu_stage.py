@@ -257,7 +257,11 @@ def _ccz4_state(n, kind, seed=0):
 
 
 @pytest.mark.parametrize("n,kind,upwind", [((18, 13, 9), "noise", 1), ((18, 13, 9), "strong", 1),
-                                           ((16, 10, 7), "strong", 0)])
+                                           ((16, 10, 7), "strong", 0),
+                                           # fewer than 6 points along z (ghosts from the fill, not
+                                           # written by the stage kernel; a ragged z tile), and a
+                                           # single plane (every z neighbour is an image of it)
+                                           ((12, 9, 5), "strong", 1), ((9, 7, 1), "strong", 1)])
 def test_ccz4_rk4_parity(n, kind, upwind):
     print("ccz4 rk4", n, kind, upwind, flush=True)
     st, dx = _ccz4_state(n, kind)
