@@ -959,10 +959,12 @@ __global__ __launch_bounds__(256) void ccz4_adj_gather_kernel(const PatchDev* __
 #pragma unroll 1
             for (int l = k + 1; l < 3; ++l)
 #pragma unroll 1
-                for (int a = -2; a <= 2; ++a)
+                for (int ia = 0; ia < 4; ++ia)
 #pragma unroll 1
-                    for (int b = -2; b <= 2; ++b) {
-                        if (a == 0 || b == 0 || !inside(k, -a, l, -b)) continue;
+                    for (int ib = 0; ib < 4; ++ib) {
+                        // the mixed stencil's taps: offsets -2, -1, 1, 2 on both axes
+                        const int a = ia < 2 ? ia - 2 : ia - 1, b = ib < 2 ? ib - 2 : ib - 1;
+                        if (!inside(k, -a, l, -b)) continue;
                         const int64_t cof = shift(k, -a) + shift(l, -b);
                         const double wm = C.i144h2 * w1[a + 2] * w1[b + 2];
 #pragma unroll
