@@ -263,9 +263,9 @@ int mol_restrict(mol_patchset* ps, int fine_level, const double* U_f, double* U_
 int mol_rhs_adjoint(mol_patchset* ps, int level, const double* U, const double* lam,
                     double* lamU, double* work, void* stream);
 /* Doubles of workspace mol_rhs_adjoint needs on `level` (0 for the wave;
- * CCZ4: 299 per point of the padded ghosted boxes: 139 stencil-input
- * adjoints, 103 stored forward values, 57 adjoints handed between its
- * kernels); negative on error. */
+ * CCZ4: 299 per interior point, rows padded to 16 doubles: 139
+ * stencil-input adjoints, 103 stored forward values, 57 adjoints handed
+ * between its kernels); negative on error. */
 int64_t mol_adjoint_workspace(const mol_patchset* ps, int level);
 /* mol_rhs_adjoint without a workspace argument, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving loops,
@@ -276,7 +276,7 @@ int64_t mol_adjoint_workspace(const mol_patchset* ps, int level);
  * address is looked up once per device on the first call made with that
  * device current.  Levels whose workspace (mol_adjoint_workspace) exceeds
  * the array are rejected with MOL_EINVAL (use mol_rhs_adjoint there): a CCZ4
- * patch of up to about 24^3 interior points fits.  Every call on one GPU
+ * patch of up to about 29^3 interior points fits.  Every call on one GPU
  * shares that GPU's array: calls that overlap in time on one GPU (other
  * streams, other threads) race; calls ordered on one stream do not.  No
  * slot has to start at zero: every slot a call reads was written by that

@@ -806,7 +806,7 @@ int build(mol_patchset* ps, const mol_hierarchy_desc* h, const mol_patchset* pre
             int64_t w = 0;
             for (size_t p = 0; p < lev.pd.size(); ++p) {
                 wo[p] = w;
-                w += (int64_t)ccz4_adjoint_slots() * lev.pd[p].fs;
+                w += (int64_t)ccz4_adjoint_slots() * adj_wfs(lev.pd[p].n);
             }
             lev.wsize = w;
             if ((rc = lev.wofs.upload(wo, &ps->arena))) return rc;

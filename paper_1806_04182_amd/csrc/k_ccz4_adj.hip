@@ -89,10 +89,11 @@ struct Pt {
     const double* lm;
     double* w;
     int64_t fs;
+    int64_t wfs;  // slot stride of the workspace (interior-only layout)
     int S[3];
     __device__ double U(int f) const { return u[(int64_t)f * fs]; }
     __device__ double L(int f) const { return lm[(int64_t)f * fs]; }
-    __device__ double& Wq(int q) const { return w[(int64_t)q * fs]; }
+    __device__ double& Wq(int q) const { return w[(int64_t)q * wfs]; }
     __device__ double d1(const AdjConst& C, int f, int k) const { return C.i12h * fd1(u + (int64_t)f * fs, S[k]); }
     __device__ double dd(const AdjConst& C, int f, int k, int l) const
     {
@@ -113,7 +114,8 @@ __device__ __forceinline__ bool pt_init(Pt& q, const PatchDev* __restrict__ patc
     q.fs = P.fs;
     q.u = Ug + P.off + loc;
     q.lm = lamg + P.off + loc;
-    q.w = W + wofs[t.patch] + loc;
+    q.wfs = adj_wfs(P.n);
+    q.w = W + wofs[t.patch] + ((int64_t)kk * P.n[1] + jj) * adj_wpitch(P.n[0]) + ii;
     q.S[0] = 1;
     q.S[1] = P.pitch_y;
     q.S[2] = P.pitch_z;
@@ -893,7 +895,12 @@ __global__ __launch_bounds__(256) void ccz4_adj_gather_kernel(const PatchDev* __
     const int S[3] = {1, P.pitch_y, P.pitch_z};
     const double* lp = lamg + P.off + loc;
     const double* bp = Ug + P.off + loc + (int64_t)BETA * fs;
-    const double* wp = W + wofs[t.patch] + loc;
+    // the workspace holds interior points only (its own row and plane
+    // pitches): wb is p's index there, which for a ghost point p lies outside
+    // the patch's block; only wb plus the offset of an interior c is read
+    const int64_t wpy = adj_wpitch(P.n[0]), wfs = adj_wfs(P.n);
+    const int64_t SW[3] = {1, wpy, wpy * P.n[1]};
+    const int64_t wb = wofs[t.patch] + ((int64_t)q[2] * P.n[1] + q[1]) * wpy + q[0];
     // c = p + off along axis d (and e along axis d2) is an interior point
     // (always, at its periodic image, when WRAP)
     auto inside = [&](int d, int off, int d2 = 0, int e = 0) {
@@ -903,15 +910,18 @@ __global__ __launch_bounds__(256) void ccz4_adj_gather_kernel(const PatchDev* __
         c[d2] += e;
         return c[0] >= 0 && c[0] < P.n[0] && c[1] >= 0 && c[1] < P.n[1] && c[2] >= 0 && c[2] < P.n[2];
     };
-    // offset of p + off along axis d from p (at the periodic image when WRAP)
-    auto shift = [&](int d, int off) -> int64_t {
+    // offset of p + off along axis d from p (at the periodic image when WRAP),
+    // in points; then in the level buffer and in the workspace
+    auto tapv = [&](int d, int off) -> int {
         int v = off;
         if constexpr (WRAP) {
             const int c = q[d] + off;
             v = c < 0 ? off + P.n[d] : (c >= P.n[d] ? off - P.n[d] : off);
         }
-        return (int64_t)v * S[d];
+        return v;
     };
+    auto shift = [&](int d, int off) -> int64_t { return (int64_t)tapv(d, off) * S[d]; };
+    auto shiftw = [&](int d, int off) -> int64_t { return (int64_t)tapv(d, off) * SW[d]; };
     const bool self = inside(0, 0);
     const double w1[5] = {1.0, -8.0, 0.0, 8.0, -1.0};   // D1: coefficient of u(c+o), o = -2..2
     const double w2[5] = {-1.0, 16.0, -30.0, 16.0, -1.0};
@@ -929,7 +939,7 @@ __global__ __launch_bounds__(256) void ccz4_adj_gather_kernel(const PatchDev* __
         double acc[GF];
 #pragma unroll
         for (int g = 0; g < GF; ++g)
-            if (f0 + g < NF) acc[g] = self ? wp[(int64_t)(W_U + f0 + g) * fs] : 0.0;
+            if (f0 + g < NF) acc[g] = self ? W[wb + (int64_t)(W_U + f0 + g) * wfs] : 0.0;
         // u(p) enters the stencils of the interior points c = p - o e_k
 #pragma unroll 1
         for (int k = 0; k < 3; ++k)
@@ -945,13 +955,14 @@ __global__ __launch_bounds__(256) void ccz4_adj_gather_kernel(const PatchDev* __
                 for (int g = 0; g < GF; ++g)
                     if (f0 + g < NF) acc[g] += wl * lp[(int64_t)(f0 + g) * fs + cof];
                 if (o < -2 || o > 2) continue;
+                const int64_t cofw = wb + shiftw(k, -o);
 #pragma unroll
                 for (int g = 0; g < GF; ++g) {
                     const int f = f0 + g;
                     if (f >= NF) continue;
                     const int s1 = d1_slot(f), s2 = d2_slot(f);
-                    if (s1 >= 0) acc[g] += C.i12h * w1[o + 2] * wp[(int64_t)(W_D1 + 3 * s1 + k) * fs + cof];
-                    if (s2 >= 0) acc[g] += C.i12h2 * w2[o + 2] * wp[(int64_t)(W_D2 + 6 * s2 + SI(k, k)) * fs + cof];
+                    if (s1 >= 0) acc[g] += C.i12h * w1[o + 2] * W[(int64_t)(W_D1 + 3 * s1 + k) * wfs + cofw];
+                    if (s2 >= 0) acc[g] += C.i12h2 * w2[o + 2] * W[(int64_t)(W_D2 + 6 * s2 + SI(k, k)) * wfs + cofw];
                 }
             }
 #pragma unroll 1
@@ -965,14 +976,14 @@ __global__ __launch_bounds__(256) void ccz4_adj_gather_kernel(const PatchDev* __
                         // the mixed stencil's taps: offsets -2, -1, 1, 2 on both axes
                         const int a = ia < 2 ? ia - 2 : ia - 1, b = ib < 2 ? ib - 2 : ib - 1;
                         if (!inside(k, -a, l, -b)) continue;
-                        const int64_t cof = shift(k, -a) + shift(l, -b);
+                        const int64_t cofw = wb + shiftw(k, -a) + shiftw(l, -b);
                         const double wm = C.i144h2 * w1[a + 2] * w1[b + 2];
 #pragma unroll
                         for (int g = 0; g < GF; ++g) {
                             const int f = f0 + g;
                             if (f >= NF) continue;
                             const int s2 = d2_slot(f);
-                            if (s2 >= 0) acc[g] += wm * wp[(int64_t)(W_D2 + 6 * s2 + SI(k, l)) * fs + cof];
+                            if (s2 >= 0) acc[g] += wm * W[(int64_t)(W_D2 + 6 * s2 + SI(k, l)) * wfs + cofw];
                         }
                     }
 #pragma unroll

@@ -47,6 +47,15 @@ struct PatchDev {
     int pad;
 };
 
+// Layout of a patch's block in the CCZ4 adjoint workspace: interior points
+// only (no ghost layer), rows of nx rounded up to 16 doubles so that every
+// row starts on a 128-byte line, slot stride a multiple of 32 doubles.
+__host__ __device__ inline int64_t adj_wpitch(int nx) { return ((int64_t)nx + 15) & ~int64_t(15); }
+__host__ __device__ inline int64_t adj_wfs(const int n[3])
+{
+    return (adj_wpitch(n[0]) * n[1] * n[2] + 31) & ~int64_t(31);
+}
+
 // A tile of a patch's interior (or of its ghosted box for the adjoint):
 // origin in interior coordinates (may be negative for ghosted-box tiles).
 struct Tile {

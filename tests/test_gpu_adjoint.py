@@ -73,7 +73,7 @@ def test_autograd_gradient_matches_central_differences():
     J = sphere_objective(p0, ps, nsteps, dt, rad, every=10)
     J.backward()
     g = p0.grad.numpy()
-    Jv = float(J)
+    Jv = float(J.detach())
     assert abs(g[0] - Jv) < 1e-12 * abs(Jv)  # dJ/dA = J/A with A = 1
     base = p0.detach().numpy()
     for i in range(5):
