@@ -854,7 +854,7 @@ ADJ_KERNEL(ccz4_adj_chain_kernel)
 
 // ---------------------------------------------------------------- kernel 2
 #ifndef MOL_ADJ_GATHER_GROUP
-#define MOL_ADJ_GATHER_GROUP 9
+#define MOL_ADJ_GATHER_GROUP 13
 #endif
 
 // Epilogue of the periodic (WRAP) gather inside a reverse RK4 step: with v the
@@ -928,11 +928,12 @@ __global__ __launch_bounds__(256) void ccz4_adj_gather_kernel(const PatchDev* __
     const double wko[7] = {1.0, -6.0, 15.0, -20.0, 15.0, -6.0, 1.0};
     const double wlp[7] = {0.0, 0.0, -3.0, -10.0, 18.0, -6.0, 1.0};  // beta >= 0: o = -3..3
     const double wlm[7] = {-1.0, 6.0, -18.0, 10.0, 3.0, 0.0, 0.0};   // beta < 0
-    // fields in groups of MOL_ADJ_GATHER_GROUP (9: the 25 fields in three
-    // sweeps, 5% faster than one sweep with 25 accumulators, at 160 instead
-    // of 247 VGPRs), one accumulator per field of the group; the taps are
-    // swept once per group (rolled loops keep the code small) and the terms
-    // of each field are summed in the same order whatever the grouping
+    // fields in groups of MOL_ADJ_GATHER_GROUP (13: the 25 fields in two
+    // sweeps, at about 150 VGPRs; three sweeps of 9 and one of 25, at 240
+    // VGPRs, measured slower), one accumulator per field of the group; the
+    // taps are swept once per group (rolled loops keep the code small) and
+    // the terms of each field are summed in the same order whatever the
+    // grouping
 #pragma unroll
     for (int f0 = 0; f0 < NF; f0 += MOL_ADJ_GATHER_GROUP) {
         constexpr int GF = MOL_ADJ_GATHER_GROUP;
