@@ -122,8 +122,12 @@ __device__ __forceinline__ bool pt_init(Pt& q, const PatchDev* __restrict__ patc
     return true;
 }
 
+// waves per SIMD the gauge reverse is held to: two cost it 116 bytes per
+// lane of scratch; with the interior-only workspace one wave without
+// scratch measured slightly faster (reverse RK4 step at 48^3 1.961 against
+// 1.975 ms)
 #ifndef MOL_ADJ_GAUGE_WAVES
-#define MOL_ADJ_GAUGE_WAVES 2
+#define MOL_ADJ_GAUGE_WAVES 1
 #endif
 #define ADJ_KERNEL2(name, waves)                                                                           \
     __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(waves))) void name(                \
