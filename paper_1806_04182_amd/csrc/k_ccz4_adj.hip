@@ -224,7 +224,10 @@ ADJ_KERNEL(ccz4_adj_forward_kernel)
 // and the second derivatives of gt_ij, from the stored gt^{ij}, Gamma_ijk,
 // Gamma^i_jk, Z^i and d Ghat (split from K1 so that each half holds two
 // waves per SIMD).
-ADJ_KERNEL(ccz4_adj_ricci_fwd_kernel)
+// held to two waves per SIMD (20 bytes per lane of scratch): left alone the
+// compiler takes 4 registers more than half the file and runs one wave
+// (reverse RK4 step at 48^3 1.954 -> 1.926 ms)
+ADJ_KERNEL2(ccz4_adj_ricci_fwd_kernel, 2)
 {
     Pt q;
     if (!pt_init(q, patches, tiles, Ug, lamg, W, wofs)) return;
