@@ -157,6 +157,34 @@ __device__ __forceinline__ void metric_inverse(const double g[6], double gu[6], 
     gu[5] = (g[0] * g[3] - g[1] * g[1]) * idet;
 }
 
+// ------------------------------------------------------------ kernel K0
+// The derivative of the advection terms sum_f lam_f beta^k L_k u_f with
+// respect to beta^k (first writer of those three slots).
+__device__ __forceinline__ void advection_body(const Pt& q, const AdjConst& C)
+{
+    double be[3], a_be[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < 3; ++k) be[k] = q.U(BETA + k);
+    for (int f = 0; f < NF; ++f) {
+        const double lf = q.L(f);
+        const double* v = q.u + (int64_t)f * q.fs;
+        for (int k = 0; k < 3; ++k) a_be[k] += lf * (C.upwind ? fadv(v, q.S[k], be[k]) : fd1(v, q.S[k]));
+    }
+    for (int k = 0; k < 3; ++k) q.Wq(W_U + BETA + k) = C.i12h * a_be[k];
+}
+ADJ_KERNEL(ccz4_adj_advection_kernel)
+{
+    Pt q;
+    if (!pt_init(q, patches, tiles, Ug, lamg, W, wofs)) return;
+    advection_body(q, C);
+}
+
+// The advection reverse runs inside the forward-intermediates kernel (after
+// its stores) instead of as a launch of its own: 1 saves a launch and a
+// pass over the points' stencil neighbourhoods of U.
+#ifndef MOL_ADJ_FUSE_ADV
+#define MOL_ADJ_FUSE_ADV 1
+#endif
+
 // ------------------------------------------------------------ kernel K1
 // Forward intermediates (stored): inverse metric, Christoffel symbols, Z^i,
 // ln det, d Ghat, D_iD_j alpha.  The Ricci tensor follows in K1b.
@@ -217,6 +245,9 @@ ADJ_KERNEL(ccz4_adj_forward_kernel)
         }
     for (int i = 0; i < 3; ++i) q.Wq(F_Z + i) = Z[i];
     q.Wq(F_LNDET) = lndet;
+#if MOL_ADJ_FUSE_ADV
+    advection_body(q, C);
+#endif
 }
 
 // ------------------------------------------------------------ kernel K1b
@@ -296,23 +327,6 @@ ADJ_KERNEL2(ccz4_adj_ricci_fwd_kernel, 2)
                 r += Q[i][k][n] * (Gl[j][SI(k, n)] + Gl[k][SI(n, j)]) + Q[j][k][n] * Gl[i][SI(k, n)];
         q.Wq(F_RIC + p) = r;
     }
-}
-
-// ------------------------------------------------------------ kernel K0
-// The derivative of the advection terms sum_f lam_f beta^k L_k u_f with
-// respect to beta^k (first writer of those three slots).
-ADJ_KERNEL(ccz4_adj_advection_kernel)
-{
-    Pt q;
-    if (!pt_init(q, patches, tiles, Ug, lamg, W, wofs)) return;
-    double be[3], a_be[3] = {0.0, 0.0, 0.0};
-    for (int k = 0; k < 3; ++k) be[k] = q.U(BETA + k);
-    for (int f = 0; f < NF; ++f) {
-        const double lf = q.L(f);
-        const double* v = q.u + (int64_t)f * q.fs;
-        for (int k = 0; k < 3; ++k) a_be[k] += lf * (C.upwind ? fadv(v, q.S[k], be[k]) : fd1(v, q.S[k]));
-    }
-    for (int k = 0; k < 3; ++k) q.Wq(W_U + BETA + k) = C.i12h * a_be[k];
 }
 
 // ------------------------------------------------------------ kernel K2
@@ -1044,7 +1058,7 @@ hipError_t launch_ccz4_adjoint(const SysParams& sp, const PatchDev* patches, con
         // every pointwise kernel covers the same interior points; each writes
         // or accumulates only the workspace slots listed in its comment
         const dim3 b(td[0], td[1], td[2]);
-        ccz4_adj_advection_kernel<<<ntiles, b, 0, s>>>(patches, tiles, U, lam, W, wofs, C);
+        if (!MOL_ADJ_FUSE_ADV) ccz4_adj_advection_kernel<<<ntiles, b, 0, s>>>(patches, tiles, U, lam, W, wofs, C);
         ccz4_adj_forward_kernel<<<ntiles, b, 0, s>>>(patches, tiles, U, lam, W, wofs, C);
         ccz4_adj_ricci_fwd_kernel<<<ntiles, b, 0, s>>>(patches, tiles, U, lam, W, wofs, C);
         ccz4_adj_metric_kernel<<<ntiles, b, 0, s>>>(patches, tiles, U, lam, W, wofs, C);
