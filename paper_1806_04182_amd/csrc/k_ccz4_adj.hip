@@ -588,10 +588,8 @@ ADJ_KERNEL2(ccz4_adj_gauge_kernel, MOL_ADJ_GAUGE_WAVES)
 // Reverse of the second-derivative terms of the shift in S^i:
 // gt^{kl} d_k d_l beta^i + (1/3) gt^{ij} d_j d_k beta^k (first writer of the
 // second-derivative slots of beta).
-ADJ_KERNEL(ccz4_adj_shift_kernel)
+__device__ __forceinline__ void shift_body(const Pt& q, const AdjConst& C)
 {
-    Pt q;
-    if (!pt_init(q, patches, tiles, Ug, lamg, W, wofs)) return;
     double gu[6], aS[3], a_gu[6] = {};
     for (int p = 0; p < 6; ++p) gu[p] = q.Wq(F_GU + p);
     for (int i = 0; i < 3; ++i) aS[i] = q.L(GH + i) + q.L(BB + i);
@@ -612,14 +610,18 @@ ADJ_KERNEL(ccz4_adj_shift_kernel)
     }
     for (int p = 0; p < 6; ++p) q.Wq(H_AGU + p) += a_gu[p];
 }
+ADJ_KERNEL(ccz4_adj_shift_kernel)
+{
+    Pt q;
+    if (!pt_init(q, patches, tiles, Ug, lamg, W, wofs)) return;
+    shift_body(q, C);
+}
 
 // ------------------------------------------------------------ kernel K4
 // Reverse of D_iD_j alpha and of the chi part of the Ricci tensor
 // (R^chi_ij, with the traces trc and Ghd).
-ADJ_KERNEL(ccz4_adj_chi_kernel)
+__device__ __forceinline__ void chi_body(const Pt& q, const AdjConst& C)
 {
-    Pt q;
-    if (!pt_init(q, patches, tiles, Ug, lamg, W, wofs)) return;
     double g[6], gu[6], aR[6], aD[6];
     for (int p = 0; p < 6; ++p) {
         g[p] = q.U(GT + p);
@@ -721,14 +723,18 @@ ADJ_KERNEL(ccz4_adj_chi_kernel)
         q.Wq(H_AZ + i) += a_Z[i];
     }
 }
+ADJ_KERNEL(ccz4_adj_chi_kernel)
+{
+    Pt q;
+    if (!pt_init(q, patches, tiles, Ug, lamg, W, wofs)) return;
+    chi_body(q, C);
+}
 
 // ------------------------------------------------------------ kernel K5
 // Reverse of the conformal Ricci tensor Rt_ij: -1/2 gt^{mn} d_m d_n gt_ij,
 // gt_k(i d_j) Ghat^k, Ghat^k Gamma_(ij)k and the Gamma-Gamma products.
-ADJ_KERNEL(ccz4_adj_ricci_kernel)
+__device__ __forceinline__ void ricci_body(const Pt& q, const AdjConst& C)
 {
-    Pt q;
-    if (!pt_init(q, patches, tiles, Ug, lamg, W, wofs)) return;
     double gu[6], aR[6], Gl[3][6], Gu[3][6];
     for (int p = 0; p < 6; ++p) {
         gu[p] = q.Wq(F_GU + p);
@@ -805,6 +811,36 @@ ADJ_KERNEL(ccz4_adj_ricci_kernel)
             q.Wq(H_AGL + 6 * i + p) = a_Gl[i][p];
         }
     }
+}
+ADJ_KERNEL(ccz4_adj_ricci_kernel)
+{
+    Pt q;
+    if (!pt_init(q, patches, tiles, Ug, lamg, W, wofs)) return;
+    ricci_body(q, C);
+}
+
+// The reverses of the shift Hessian, of D_iD_j alpha with the chi part of
+// the Ricci tensor, and of the conformal Ricci tensor run one after the other
+// in one launch: one launch and one point set-up instead of three.  Alone
+// each fits two waves per SIMD; together the kernel takes more than half the
+// register file and runs one wave without scratch (held to two waves it
+// spills 560 bytes per lane), and is still slightly faster than the three
+// (reverse RK4 step at 48^3 1.886 against 1.897 ms).
+#ifndef MOL_ADJ_FUSE_SCR
+#define MOL_ADJ_FUSE_SCR 1
+#endif
+ADJ_KERNEL(ccz4_adj_shift_chi_ricci_kernel)
+{
+    Pt q;
+    if (!pt_init(q, patches, tiles, Ug, lamg, W, wofs)) return;
+    // the bodies pass their results through the workspace; the fences keep
+    // the compiler from hoisting one body's loads into the one before it,
+    // which would hold both bodies' values live at once
+    shift_body(q, C);
+    asm volatile("" ::: "memory");
+    chi_body(q, C);
+    asm volatile("" ::: "memory");
+    ricci_body(q, C);
 }
 
 // ------------------------------------------------------------ kernel K6
@@ -1063,9 +1099,13 @@ hipError_t launch_ccz4_adjoint(const SysParams& sp, const PatchDev* patches, con
         ccz4_adj_ricci_fwd_kernel<<<ntiles, b, 0, s>>>(patches, tiles, U, lam, W, wofs, C);
         ccz4_adj_metric_kernel<<<ntiles, b, 0, s>>>(patches, tiles, U, lam, W, wofs, C);
         ccz4_adj_gauge_kernel<<<ntiles, b, 0, s>>>(patches, tiles, U, lam, W, wofs, C);
-        ccz4_adj_shift_kernel<<<ntiles, b, 0, s>>>(patches, tiles, U, lam, W, wofs, C);
-        ccz4_adj_chi_kernel<<<ntiles, b, 0, s>>>(patches, tiles, U, lam, W, wofs, C);
-        ccz4_adj_ricci_kernel<<<ntiles, b, 0, s>>>(patches, tiles, U, lam, W, wofs, C);
+        if (MOL_ADJ_FUSE_SCR) {
+            ccz4_adj_shift_chi_ricci_kernel<<<ntiles, b, 0, s>>>(patches, tiles, U, lam, W, wofs, C);
+        } else {
+            ccz4_adj_shift_kernel<<<ntiles, b, 0, s>>>(patches, tiles, U, lam, W, wofs, C);
+            ccz4_adj_chi_kernel<<<ntiles, b, 0, s>>>(patches, tiles, U, lam, W, wofs, C);
+            ccz4_adj_ricci_kernel<<<ntiles, b, 0, s>>>(patches, tiles, U, lam, W, wofs, C);
+        }
         ccz4_adj_chain_kernel<<<ntiles, b, 0, s>>>(patches, tiles, U, lam, W, wofs, C);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
