@@ -176,3 +176,37 @@ def test_lapse_objective_gradient_matches_central_differences():
         fd[i] = (Jp - Jm) / (2 * h)
     err = np.abs(g - fd) / np.maximum(np.abs(fd), 1e-3 * np.max(np.abs(fd)))
     assert np.all(err < 1e-6), (g, fd, err)
+
+
+def test_rhs_adjoint_on_a_level_of_ragged_patches_matches_oracle():
+    """A periodic level tiled by four patches of different sizes (each its own
+    offset and interior-only slot layout in the workspace; ghost entries
+    folded across patch faces by the fill transpose): element by element
+    against the oracle's exact derivative on the whole periodic box."""
+    torch = _torch()
+    n, dx = (7, 6, 3), 0.15
+    U = _state(n, dx, 11)
+    lam = np.random.default_rng(5).standard_normal((25,) + tuple(reversed(n)))
+    ref = O.ccz4_rhs_vjp_periodic(U, lam, dx, O.params(upwind=1.0))
+    # x split 3 + 4, y split 3 + 3 (inclusive boxes in level index space)
+    boxes = [((0, 0, 0), (2, 2, 2)), ((3, 0, 0), (6, 2, 2)), ((0, 3, 0), (2, 5, 2)), ((3, 3, 0), (6, 5, 2))]
+    ps = M.Patchset(M.Hierarchy(n, (-1, -1, -1), dx, [(1, boxes)]), M.System(M.MOL_CCZ4, upwind=1))
+    G = 3
+    Up, Lp = [], []
+    for lo, hi in boxes:
+        sl = (slice(None), slice(lo[2], hi[2] + 1 + 2 * G), slice(lo[1], hi[1] + 1 + 2 * G),
+              slice(lo[0], hi[0] + 1 + 2 * G))
+        Up.append(U[sl].copy())  # U is ghosted and periodic: the patch with its ghosts
+        Lp.append(synth.embed(lam[:, lo[2]:hi[2] + 1, lo[1]:hi[1] + 1, lo[0]:hi[0] + 1]))
+    Ud = torch.from_numpy(ps.pack(0, Up)).cuda()
+    Ld = torch.from_numpy(ps.pack(0, Lp)).cuda()
+    out = ps.alloc(0)
+    ps.rhs_adjoint(0, Ud, Ld, out, ps.alloc_work(0))
+    ps.fill_ghosts_adjoint(0, out)
+    torch.cuda.synchronize()
+    got = np.zeros_like(ref)
+    for (lo, hi), a in zip(boxes, ps.unpack(0, out)):
+        got[:, lo[2]:hi[2] + 1, lo[1]:hi[1] + 1, lo[0]:hi[0] + 1] = synth.interior(a)
+    sc = np.maximum(np.max(np.abs(ref), axis=(1, 2, 3)), 1.0)
+    err = np.max(np.abs(got - ref), axis=(1, 2, 3)) / sc
+    assert np.all(err < 1e-12), err
